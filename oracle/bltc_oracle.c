@@ -1,0 +1,656 @@
+/*
+ * bltc_oracle.c -- CPU oracle for the barycentric Lagrange treecode (BLTC).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain, FP64 reference that
+ * the GPU library is checked against.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no code, header,
+ * table or helper with the GPU library, and it never reads anything the GPU
+ * library produced.
+ *
+ * What it computes (Vaughn, Wilson, Krasny, "A GPU-Accelerated Barycentric
+ * Lagrange Treecode", 2020):
+ *   - the direct sum phi_i = sum_j G(x_i, y_j) q_j                 (Sec. II, eq. 1)
+ *     with G = 1/r (Coulomb) or exp(-kappa r)/r (Yukawa)             (eq. 2);
+ *   - the BLTC of Alg. 1: source-cluster tree and target batches
+ *     (Sec. II-D), modified charges on each cluster's tensor grid of
+ *     Chebyshev points of the 2nd kind (eqs. 4-7, 12) with the
+ *     removable-singularity rule (eq. 5, Sec. II-C), and the recursive
+ *     ComputePotential with the two-part MAC (eq. 13): the approximation
+ *     (eq. 11) when it holds, the direct particle sum (eq. 9) when it fails.
+ *
+ * Readings where the paper is silent (each one is listed in the design notes):
+ *   R1  pairs at exactly zero distance are skipped (self term, duplicates);
+ *   R2  cluster/batch center = midpoint of its minimal bounding box,
+ *       radius = half the box diagonal;
+ *   R3  MAC evaluated as r_B + r_C < theta * R (false when R = 0), strict "<"
+ *       in both parts, R = sqrt(dx*dx + dy*dy + dz*dz) summed x, y, z;
+ *   R4  branch order of Alg. 1 as printed: a geometric failure recurses into
+ *       the children of a non-leaf cluster even when the size test also fails;
+ *       a size-only failure is a direct sum over the whole cluster;
+ *   R5  a coordinate on the split plane (y_l >= c_l) goes to the upper child;
+ *   R6  aspect-ratio rule (Sec. III-A) applied to every node: dimension l is
+ *       split iff 2 L_l^2 >= L_max^2, L_l = hi_l - lo_l;
+ *   R7  every node shrinks to the minimal box of its own particles;
+ *   R8  leaf iff N_C <= N_L, or L_max = 0, or the split leaves every particle
+ *       in one child (possible only for boxes a few ulps wide);
+ *   R9  a source coordinate coincides with a node when |y - s| < DBL_MIN
+ *       (the smallest positive normal double); the lowest such k wins;
+ *   R10 nodes s_k = c + h cos(pi k / n), h = (hi - lo)/2, k = 0..n (k = 0 at
+ *       the upper end), weights w_k = (-1)^k delta_k;
+ *   R11 modified charges are formed for every cluster that appears in some
+ *       approximation list (the same values Alg. 1 forms for all clusters).
+ *
+ * Floating point: plain FP64, compiled without contraction so that the tree
+ * and MAC decisions follow the formulas above operation by operation.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_COULOMB 0
+#define ORACLE_YUKAWA 1
+
+static double wall_seconds(void)
+{
+#ifdef _OPENMP
+    return omp_get_wtime();
+#else
+    return 0.0;
+#endif
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* Kernel G(x, y), eq. (2).                                                   */
+/* ------------------------------------------------------------------------- */
+static double kernel_of_distance(double r, int kernel, double kappa)
+{
+    if (kernel == ORACLE_YUKAWA)
+        return exp(-kappa * r) / r;
+    return 1.0 / r;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Direct sum, eq. (1): phi[m*phi_ld + i] = sum_j G(x_i, y_j) q[m*q_ld + j],  */
+/* skipping pairs at exactly zero distance (reading R1).                      */
+/* ------------------------------------------------------------------------- */
+void oracle_direct(int64_t nt, const double *tx, const double *ty, const double *tz,
+                   int64_t ns, const double *sx, const double *sy, const double *sz,
+                   const double *q, int32_t m, int64_t q_ld,
+                   int32_t kernel, double kappa, double *phi, int64_t phi_ld)
+{
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (i = 0; i < nt; ++i) {
+        for (int32_t c = 0; c < m; ++c) {
+            double sum = 0.0;
+            for (int64_t j = 0; j < ns; ++j) {
+                double dx = tx[i] - sx[j];
+                double dy = ty[i] - sy[j];
+                double dz = tz[i] - sz[j];
+                double r = sqrt(dx * dx + dy * dy + dz * dz);
+                if (r == 0.0)
+                    continue;
+                sum += kernel_of_distance(r, kernel, kappa) * q[(int64_t)c * q_ld + j];
+            }
+            phi[(int64_t)c * phi_ld + i] = sum;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* 1-D Chebyshev points of the 2nd kind on [a, b] and their barycentric       */
+/* weights, eqs. (6)-(7) with the linear map of Sec. II-A (reading R10).      */
+/* ------------------------------------------------------------------------- */
+void oracle_chebyshev(int32_t n, double a, double b, double *s, double *w)
+{
+    double c = (a + b) / 2.0;
+    double h = (b - a) / 2.0;
+    for (int32_t k = 0; k <= n; ++k) {
+        s[k] = c + h * cos(M_PI * (double)k / (double)n);
+        double delta = (k == 0 || k == n) ? 0.5 : 1.0;
+        w[k] = ((k % 2) ? -1.0 : 1.0) * delta;
+    }
+}
+
+/* L_k(x), k = 0..n, by the barycentric formula eq. (4), with the removable
+ * singularity eq. (5) enforced when |x - s_k'| < DBL_MIN (reading R9). */
+void oracle_lagrange(int32_t n, const double *s, const double *w, double x, double *L)
+{
+    for (int32_t k = 0; k <= n; ++k) {
+        if (fabs(x - s[k]) < DBL_MIN) {
+            for (int32_t kk = 0; kk <= n; ++kk)
+                L[kk] = (kk == k) ? 1.0 : 0.0;
+            return;
+        }
+    }
+    double denom = 0.0;
+    for (int32_t k = 0; k <= n; ++k)
+        denom += w[k] / (x - s[k]);
+    for (int32_t k = 0; k <= n; ++k)
+        L[k] = (w[k] / (x - s[k])) / denom;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Trees (Sec. II-D, Sec. III-A), readings R2, R5-R8.                         */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double lo[3], hi[3], center[3], radius;
+    int64_t begin, count;   /* range in the tree's permuted index array */
+    int32_t child[8];
+    int32_t nchild;
+    int32_t level;
+} onode;
+
+typedef struct {
+    onode *nodes;
+    int64_t n_nodes, cap_nodes;
+    int64_t *idx;           /* idx[p] = original index of the particle at tree position p */
+    int64_t n;
+} otree;
+
+static int32_t tree_new_node(otree *t)
+{
+    if (t->n_nodes == t->cap_nodes) {
+        t->cap_nodes = t->cap_nodes ? 2 * t->cap_nodes : 64;
+        t->nodes = (onode *)realloc(t->nodes, (size_t)t->cap_nodes * sizeof(onode));
+    }
+    memset(&t->nodes[t->n_nodes], 0, sizeof(onode));
+    return (int32_t)t->n_nodes++;
+}
+
+static void tree_split(otree *t, const double *const p[3], int32_t id, int64_t cap,
+                       int64_t *scratch)
+{
+    onode *nd = &t->nodes[id];
+    int64_t begin = nd->begin, count = nd->count;
+
+    /* minimal bounding box of this node's particles (R7) */
+    for (int l = 0; l < 3; ++l) {
+        nd->lo[l] = INFINITY;
+        nd->hi[l] = -INFINITY;
+    }
+    for (int64_t a = begin; a < begin + count; ++a) {
+        int64_t i = t->idx[a];
+        for (int l = 0; l < 3; ++l) {
+            double v = p[l][i];
+            if (v < nd->lo[l]) nd->lo[l] = v;
+            if (v > nd->hi[l]) nd->hi[l] = v;
+        }
+    }
+    double L[3];
+    for (int l = 0; l < 3; ++l) {
+        nd->center[l] = (nd->lo[l] + nd->hi[l]) / 2.0;
+        L[l] = nd->hi[l] - nd->lo[l];
+    }
+    nd->radius = 0.5 * sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
+    nd->nchild = 0;
+    double Lmax = L[0];
+    if (L[1] > Lmax) Lmax = L[1];
+    if (L[2] > Lmax) Lmax = L[2];
+    if (count <= cap || Lmax == 0.0)
+        return;
+
+    int split[3];
+    for (int l = 0; l < 3; ++l)
+        split[l] = (2.0 * L[l] * L[l] >= Lmax * Lmax);
+
+    /* child code: bit l set iff dimension l is split and y_l >= c_l (R5) */
+    int64_t nb[8] = {0};
+    for (int64_t a = begin; a < begin + count; ++a) {
+        int64_t i = t->idx[a];
+        int code = 0;
+        for (int l = 0; l < 3; ++l)
+            if (split[l] && p[l][i] >= nd->center[l])
+                code |= 1 << l;
+        scratch[a - begin] = code;
+        nb[code]++;
+    }
+    int nonempty = 0;
+    for (int c = 0; c < 8; ++c)
+        nonempty += nb[c] > 0;
+    if (nonempty <= 1)
+        return; /* degenerate split: leaf (R8) */
+
+    /* stable partition of this node's range by child code */
+    int64_t off[8], pos = 0;
+    for (int c = 0; c < 8; ++c) {
+        off[c] = pos;
+        pos += nb[c];
+    }
+    int64_t *tmp = (int64_t *)malloc((size_t)count * sizeof(int64_t));
+    for (int64_t a = 0; a < count; ++a)
+        tmp[off[scratch[a]]++] = t->idx[begin + a];
+    memcpy(t->idx + begin, tmp, (size_t)count * sizeof(int64_t));
+    free(tmp);
+
+    int64_t start = begin;
+    int32_t kids[8];
+    int nk = 0;
+    int32_t level = nd->level;
+    for (int c = 0; c < 8; ++c) {
+        if (nb[c] == 0)
+            continue;
+        int32_t cid = tree_new_node(t);     /* may move t->nodes */
+        t->nodes[cid].begin = start;
+        t->nodes[cid].count = nb[c];
+        t->nodes[cid].level = level + 1;
+        kids[nk++] = cid;
+        start += nb[c];
+    }
+    nd = &t->nodes[id];
+    nd->nchild = nk;
+    for (int c = 0; c < nk; ++c)
+        nd->child[c] = kids[c];
+    for (int c = 0; c < nk; ++c)
+        tree_split(t, p, kids[c], cap, scratch);
+}
+
+static void tree_build(otree *t, int64_t n, const double *x, const double *y, const double *z,
+                       int64_t cap)
+{
+    memset(t, 0, sizeof(*t));
+    t->n = n;
+    t->idx = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i)
+        t->idx[i] = i;
+    if (n == 0)
+        return;
+    const double *p[3] = {x, y, z};
+    int64_t *scratch = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int32_t root = tree_new_node(t);
+    t->nodes[root].begin = 0;
+    t->nodes[root].count = n;
+    t->nodes[root].level = 0;
+    tree_split(t, p, root, cap, scratch);
+    free(scratch);
+}
+
+static void tree_free(otree *t)
+{
+    free(t->nodes);
+    free(t->idx);
+    memset(t, 0, sizeof(*t));
+}
+
+/* ------------------------------------------------------------------------- */
+/* The treecode object: source tree, target batches, interaction lists,      */
+/* and modified charges formed on demand.                                     */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t cluster;
+    int32_t kind;   /* 0 = approximation (eq. 11), 1 = direct sum (eq. 9) */
+} oitem;
+
+typedef struct {
+    /* caller data (not owned) */
+    int64_t nt, ns;
+    const double *tx, *ty, *tz, *sx, *sy, *sz;
+    double theta;
+    int32_t n;       /* interpolation degree */
+    int64_t leaf, batch;
+    otree src, tgt;
+    int32_t *batch_node;     /* target-tree node id of each batch (leaves, DFS order) */
+    int64_t n_batches;
+    int64_t *batch_of_pos;   /* batch id of each target tree position */
+    int64_t *target_pos;     /* target tree position of each original target index */
+    oitem **items;           /* per batch */
+    int64_t *n_items, *cap_items;
+    double t_setup;
+} otc;
+
+static void push_item(otc *tc, int64_t b, int32_t cluster, int32_t kind)
+{
+    if (tc->n_items[b] == tc->cap_items[b]) {
+        tc->cap_items[b] = tc->cap_items[b] ? 2 * tc->cap_items[b] : 16;
+        tc->items[b] = (oitem *)realloc(tc->items[b], (size_t)tc->cap_items[b] * sizeof(oitem));
+    }
+    tc->items[b][tc->n_items[b]].cluster = cluster;
+    tc->items[b][tc->n_items[b]].kind = kind;
+    tc->n_items[b]++;
+}
+
+/* ComputePotential of Alg. 1, recording what it would compute (R3, R4). */
+static void compute_potential(otc *tc, int64_t b, const onode *B, int32_t cid)
+{
+    const onode *C = &tc->src.nodes[cid];
+    double dx = B->center[0] - C->center[0];
+    double dy = B->center[1] - C->center[1];
+    double dz = B->center[2] - C->center[2];
+    double R = sqrt(dx * dx + dy * dy + dz * dz);
+    int64_t P = (int64_t)(tc->n + 1) * (tc->n + 1) * (tc->n + 1);
+    int geometric = (B->radius + C->radius < tc->theta * R);
+    int size = (P < C->count);
+    if (geometric && size) {
+        push_item(tc, b, cid, 0);
+    } else if (!geometric) {
+        if (C->nchild == 0) {
+            push_item(tc, b, cid, 1);
+        } else {
+            int32_t nk = C->nchild;
+            int32_t kids[8];
+            memcpy(kids, C->child, sizeof(kids));
+            for (int32_t c = 0; c < nk; ++c)
+                compute_potential(tc, b, B, kids[c]);
+        }
+    } else {
+        push_item(tc, b, cid, 1);
+    }
+}
+
+otc *oracle_tc_create(int64_t nt, const double *tx, const double *ty, const double *tz,
+                      int64_t ns, const double *sx, const double *sy, const double *sz,
+                      double theta, int32_t degree, int64_t leaf, int64_t batch)
+{
+    double t0 = wall_seconds();
+    otc *tc = (otc *)calloc(1, sizeof(otc));
+    tc->nt = nt; tc->ns = ns;
+    tc->tx = tx; tc->ty = ty; tc->tz = tz;
+    tc->sx = sx; tc->sy = sy; tc->sz = sz;
+    tc->theta = theta; tc->n = degree; tc->leaf = leaf; tc->batch = batch;
+
+    tree_build(&tc->src, ns, sx, sy, sz, leaf);
+    tree_build(&tc->tgt, nt, tx, ty, tz, batch);
+
+    /* batches = leaves of the target tree, in depth-first order */
+    int64_t nb = 0;
+    for (int64_t i = 0; i < tc->tgt.n_nodes; ++i)
+        nb += tc->tgt.nodes[i].nchild == 0;
+    tc->n_batches = nb;
+    tc->batch_node = (int32_t *)malloc((size_t)(nb > 0 ? nb : 1) * sizeof(int32_t));
+    {
+        /* depth-first walk with an explicit stack */
+        int64_t sp = 0, k = 0;
+        int32_t *stack = (int32_t *)malloc((size_t)(tc->tgt.n_nodes + 1) * sizeof(int32_t));
+        if (tc->tgt.n_nodes > 0)
+            stack[sp++] = 0;
+        while (sp > 0) {
+            int32_t id = stack[--sp];
+            const onode *nd = &tc->tgt.nodes[id];
+            if (nd->nchild == 0) {
+                tc->batch_node[k++] = id;
+            } else {
+                for (int32_t c = nd->nchild - 1; c >= 0; --c)
+                    stack[sp++] = nd->child[c];
+            }
+        }
+        free(stack);
+    }
+    tc->batch_of_pos = (int64_t *)malloc((size_t)(nt > 0 ? nt : 1) * sizeof(int64_t));
+    tc->target_pos = (int64_t *)malloc((size_t)(nt > 0 ? nt : 1) * sizeof(int64_t));
+    for (int64_t b = 0; b < nb; ++b) {
+        const onode *B = &tc->tgt.nodes[tc->batch_node[b]];
+        for (int64_t a = B->begin; a < B->begin + B->count; ++a)
+            tc->batch_of_pos[a] = b;
+    }
+    for (int64_t a = 0; a < nt; ++a)
+        tc->target_pos[tc->tgt.idx[a]] = a;
+
+    tc->items = (oitem **)calloc((size_t)(nb > 0 ? nb : 1), sizeof(oitem *));
+    tc->n_items = (int64_t *)calloc((size_t)(nb > 0 ? nb : 1), sizeof(int64_t));
+    tc->cap_items = (int64_t *)calloc((size_t)(nb > 0 ? nb : 1), sizeof(int64_t));
+    if (ns > 0) {
+        int64_t b;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (b = 0; b < nb; ++b)
+            compute_potential(tc, b, &tc->tgt.nodes[tc->batch_node[b]], 0);
+    }
+    tc->t_setup = wall_seconds() - t0;
+    return tc;
+}
+
+void oracle_tc_destroy(otc *tc)
+{
+    if (!tc)
+        return;
+    for (int64_t b = 0; b < tc->n_batches; ++b)
+        free(tc->items[b]);
+    free(tc->items);
+    free(tc->n_items);
+    free(tc->cap_items);
+    free(tc->batch_node);
+    free(tc->batch_of_pos);
+    free(tc->target_pos);
+    tree_free(&tc->src);
+    tree_free(&tc->tgt);
+    free(tc);
+}
+
+/* ---- structure export (for structural comparisons in tests) ------------ */
+void oracle_tc_sizes(const otc *tc, int64_t *out /* [5] */)
+{
+    int64_t total = 0;
+    for (int64_t b = 0; b < tc->n_batches; ++b)
+        total += tc->n_items[b];
+    out[0] = tc->src.n_nodes;
+    out[1] = tc->n_batches;
+    out[2] = total;
+    out[3] = tc->tgt.n_nodes;
+    out[4] = (int64_t)(tc->t_setup * 1e9);
+}
+
+/* node i of the source tree: lo[3], hi[3], begin, count, nchild, child[8], level */
+void oracle_tc_source_node(const otc *tc, int64_t i, double *lo, double *hi,
+                           int64_t *begin_count, int32_t *nchild_children_level)
+{
+    const onode *nd = &tc->src.nodes[i];
+    for (int l = 0; l < 3; ++l) {
+        lo[l] = nd->lo[l];
+        hi[l] = nd->hi[l];
+    }
+    begin_count[0] = nd->begin;
+    begin_count[1] = nd->count;
+    nchild_children_level[0] = nd->nchild;
+    for (int c = 0; c < 8; ++c)
+        nchild_children_level[1 + c] = c < nd->nchild ? nd->child[c] : -1;
+    nchild_children_level[9] = nd->level;
+}
+
+void oracle_tc_source_order(const otc *tc, int64_t *out)
+{
+    memcpy(out, tc->src.idx, (size_t)tc->ns * sizeof(int64_t));
+}
+
+void oracle_tc_target_order(const otc *tc, int64_t *out)
+{
+    memcpy(out, tc->tgt.idx, (size_t)tc->nt * sizeof(int64_t));
+}
+
+/* batch b: lo[3], hi[3], begin/count in target tree order */
+void oracle_tc_batch(const otc *tc, int64_t b, double *lo, double *hi, int64_t *begin_count)
+{
+    const onode *nd = &tc->tgt.nodes[tc->batch_node[b]];
+    for (int l = 0; l < 3; ++l) {
+        lo[l] = nd->lo[l];
+        hi[l] = nd->hi[l];
+    }
+    begin_count[0] = nd->begin;
+    begin_count[1] = nd->count;
+}
+
+/* all items, batch-major: batch id, cluster (source node id), kind */
+void oracle_tc_items(const otc *tc, int64_t *batch, int32_t *cluster, int32_t *kind)
+{
+    int64_t k = 0;
+    for (int64_t b = 0; b < tc->n_batches; ++b)
+        for (int64_t t = 0; t < tc->n_items[b]; ++t) {
+            batch[k] = b;
+            cluster[k] = tc->items[b][t].cluster;
+            kind[k] = tc->items[b][t].kind;
+            ++k;
+        }
+}
+
+/* Chebyshev nodes of source cluster c: out[l*(n+1) + k] = s_{l,k} (R10) */
+void oracle_tc_cluster_nodes(const otc *tc, int32_t c, double *out)
+{
+    const onode *nd = &tc->src.nodes[c];
+    double w[64];
+    for (int l = 0; l < 3; ++l)
+        oracle_chebyshev(tc->n, nd->lo[l], nd->hi[l], out + l * (tc->n + 1), w);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Modified charges of one cluster, eq. (12):                                  */
+/*   qhat[k*m_count + m] = sum_{j in C} L_k1(y_j1) L_k2(y_j2) L_k3(y_j3) q_jm, */
+/*   k = (k1*(n+1) + k2)*(n+1) + k3, L from eq. (4) with the rule of eq. (5).  */
+/* ------------------------------------------------------------------------- */
+void oracle_tc_modified_charges(const otc *tc, int32_t c, const double *q, int32_t m,
+                                int64_t q_ld, double *qhat)
+{
+    const onode *nd = &tc->src.nodes[c];
+    int32_t n = tc->n, np = n + 1;
+    int64_t P = (int64_t)np * np * np;
+    double s[3][64], w[64], L[3][64];
+    for (int l = 0; l < 3; ++l)
+        oracle_chebyshev(n, nd->lo[l], nd->hi[l], s[l], w);
+    memset(qhat, 0, (size_t)(P * m) * sizeof(double));
+    const double *p[3] = {tc->sx, tc->sy, tc->sz};
+    for (int64_t a = nd->begin; a < nd->begin + nd->count; ++a) {
+        int64_t j = tc->src.idx[a];
+        for (int l = 0; l < 3; ++l)
+            oracle_lagrange(n, s[l], w, p[l][j], L[l]);
+        for (int32_t k1 = 0; k1 < np; ++k1)
+            for (int32_t k2 = 0; k2 < np; ++k2)
+                for (int32_t k3 = 0; k3 < np; ++k3) {
+                    double L123 = L[0][k1] * L[1][k2] * L[2][k3];
+                    int64_t k = ((int64_t)k1 * np + k2) * np + k3;
+                    for (int32_t mm = 0; mm < m; ++mm)
+                        qhat[k * m + mm] += L123 * q[(int64_t)mm * q_ld + j];
+                }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Evaluation (Alg. 1): phi at the targets listed in `sample` (original      */
+/* indices; all targets when sample == NULL), each through its own batch's   */
+/* interaction list:                                                          */
+/*   phi = sum_{C approx} sum_k G(x, s_k) qhat_k  (eq. 11)                    */
+/*       + sum_{C direct} sum_{j in C, r != 0} G(x, y_j) q_j  (eq. 9).        */
+/* phi[mm*phi_ld + s] for charge vector mm and sample s.                      */
+/* times[0] = modified-charge seconds, times[1] = evaluation seconds.         */
+/* ------------------------------------------------------------------------- */
+int oracle_tc_potential(const otc *tc, const double *q, int32_t m, int64_t q_ld,
+                        int32_t kernel, double kappa, int64_t n_sample, const int64_t *sample,
+                        double *phi, int64_t phi_ld, double *times)
+{
+    int32_t n = tc->n, np = n + 1;
+    int64_t P = (int64_t)np * np * np;
+    int64_t n_eval = sample ? n_sample : tc->nt;
+    double t0 = wall_seconds();
+
+    /* which batches are touched, then which clusters need modified charges */
+    char *batch_used = (char *)calloc((size_t)(tc->n_batches > 0 ? tc->n_batches : 1), 1);
+    for (int64_t s = 0; s < n_eval; ++s) {
+        int64_t i = sample ? sample[s] : s;
+        if (i < 0 || i >= tc->nt) {
+            free(batch_used);
+            return -1;
+        }
+        batch_used[tc->batch_of_pos[tc->target_pos[i]]] = 1;
+    }
+    int64_t nn = tc->src.n_nodes;
+    int32_t *need = (int32_t *)calloc((size_t)(nn > 0 ? nn : 1), sizeof(int32_t));
+    for (int64_t b = 0; b < tc->n_batches; ++b)
+        if (batch_used[b])
+            for (int64_t t = 0; t < tc->n_items[b]; ++t)
+                if (tc->items[b][t].kind == 0)
+                    need[tc->items[b][t].cluster] = 1;
+    int64_t n_need = 0;
+    for (int64_t c = 0; c < nn; ++c)
+        n_need += need[c];
+    int32_t *need_list = (int32_t *)malloc((size_t)(n_need > 0 ? n_need : 1) * sizeof(int32_t));
+    double **qhat = (double **)calloc((size_t)(nn > 0 ? nn : 1), sizeof(double *));
+    {
+        int64_t k = 0;
+        for (int64_t c = 0; c < nn; ++c)
+            if (need[c])
+                need_list[k++] = (int32_t)c;
+    }
+    {
+        int64_t u;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (u = 0; u < n_need; ++u) {
+            int32_t c = need_list[u];
+            double *buf = (double *)malloc((size_t)(P * m) * sizeof(double));
+            oracle_tc_modified_charges(tc, c, q, m, q_ld, buf);
+            qhat[c] = buf;
+        }
+    }
+    double t1 = wall_seconds();
+
+    {
+        int64_t s;
+#pragma omp parallel for schedule(dynamic, 8)
+        for (s = 0; s < n_eval; ++s) {
+            int64_t i = sample ? sample[s] : s;
+            int64_t b = tc->batch_of_pos[tc->target_pos[i]];
+            double x = tc->tx[i], y = tc->ty[i], z = tc->tz[i];
+            double acc[64];
+            double nodes[3][64], w[64];
+            for (int32_t mm = 0; mm < m; ++mm)
+                acc[mm] = 0.0;
+            for (int64_t t = 0; t < tc->n_items[b]; ++t) {
+                const oitem *it = &tc->items[b][t];
+                const onode *C = &tc->src.nodes[it->cluster];
+                if (it->kind == 0) {
+                    for (int l = 0; l < 3; ++l)
+                        oracle_chebyshev(n, C->lo[l], C->hi[l], nodes[l], w);
+                    const double *qh = qhat[it->cluster];
+                    for (int32_t k1 = 0; k1 < np; ++k1)
+                        for (int32_t k2 = 0; k2 < np; ++k2)
+                            for (int32_t k3 = 0; k3 < np; ++k3) {
+                                double dx = x - nodes[0][k1];
+                                double dy = y - nodes[1][k2];
+                                double dz = z - nodes[2][k3];
+                                double r = sqrt(dx * dx + dy * dy + dz * dz);
+                                double g = kernel_of_distance(r, kernel, kappa);
+                                int64_t k = ((int64_t)k1 * np + k2) * np + k3;
+                                for (int32_t mm = 0; mm < m; ++mm)
+                                    acc[mm] += g * qh[k * m + mm];
+                            }
+                } else {
+                    for (int64_t a = C->begin; a < C->begin + C->count; ++a) {
+                        int64_t j = tc->src.idx[a];
+                        double dx = x - tc->sx[j];
+                        double dy = y - tc->sy[j];
+                        double dz = z - tc->sz[j];
+                        double r = sqrt(dx * dx + dy * dy + dz * dz);
+                        if (r == 0.0)
+                            continue;
+                        double g = kernel_of_distance(r, kernel, kappa);
+                        for (int32_t mm = 0; mm < m; ++mm)
+                            acc[mm] += g * q[(int64_t)mm * q_ld + j];
+                    }
+                }
+            }
+            for (int32_t mm = 0; mm < m; ++mm)
+                phi[(int64_t)mm * phi_ld + s] = acc[mm];
+        }
+    }
+    double t2 = wall_seconds();
+    if (times) {
+        times[0] = t1 - t0;
+        times[1] = t2 - t1;
+    }
+    for (int64_t c = 0; c < nn; ++c)
+        free(qhat[c]);
+    free(qhat);
+    free(need_list);
+    free(need);
+    free(batch_used);
+    return 0;
+}
