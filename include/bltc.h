@@ -1,0 +1,195 @@
+/*
+ * bltc.h -- C ABI of the MI355X (gfx950) barycentric Lagrange treecode library.
+ *
+ * The library evaluates potentials
+ *     phi(x_i) = sum_j G(x_i, y_j) q_j,  G = 1/r (Coulomb) or exp(-kappa r)/r (Yukawa)
+ * (Vaughn, Wilson, Krasny 2020, Sec. II, eqs. 1-2) with the barycentric Lagrange
+ * treecode of Alg. 1: a tree of source clusters and a set of target batches
+ * (Sec. II-D), modified charges on each cluster's (n+1)^3 tensor grid of
+ * Chebyshev points of the 2nd kind (eqs. 6-7, 12; computed in the two-step form
+ * of eqs. 14-15 with the removable-singularity rule of eq. 5), then for every
+ * batch/cluster pair either the approximation of eq. 11 (MAC of eq. 13 holds)
+ * or the direct sum of eq. 9 (it fails).
+ *
+ * Conventions shared by every entry point:
+ *  - Counts are int64_t.  Coordinates are structure-of-arrays FP64: x, y, z are
+ *    three separate arrays of length n.
+ *  - Charge vectors: q[m * q_ld + j] is charge j of vector m (q_ld >= ns).
+ *    Potentials: phi[m * phi_ld + i] is the potential at target i for charge
+ *    vector m (phi_ld >= nt).
+ *  - Unless an entry point says otherwise, every array pointer is a DEVICE
+ *    pointer (HIP device memory, e.g. a ROCm torch tensor) on the current
+ *    HIP device, and `stream` is a hipStream_t passed as void* (NULL = the
+ *    default stream).  Work is enqueued on `stream`; results are ready when the
+ *    stream is synchronised.
+ *  - Ownership: the caller owns every input and output buffer.  Inputs are
+ *    never modified.  Outputs are overwritten (not accumulated).  The library
+ *    keeps no pointer to a caller buffer after a call returns.
+ *  - Errors: a negative bltc_status is returned and a message is stored for
+ *    the calling thread (bltc_last_error).  No C++ exception crosses this ABI.
+ *    Faults of kernels already enqueued surface as BLTC_EHIP on a later call
+ *    that synchronises.
+ */
+#ifndef BLTC_H
+#define BLTC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BLTC_OK = 0,
+    BLTC_EINVAL = -1,        /* invalid argument (message says which)              */
+    BLTC_ENOMEM = -2,        /* host or device allocation failed                     */
+    BLTC_EHIP = -3,          /* a HIP runtime call failed                            */
+    BLTC_EUNSUPPORTED = -4,  /* valid request this build does not support            */
+    BLTC_EINTERNAL = -5      /* internal consistency check failed                    */
+} bltc_status;
+
+typedef enum { BLTC_COULOMB = 0, BLTC_YUKAWA = 1 } bltc_kernel;
+
+/* Arithmetic of the evaluation.
+ *  BLTC_FP64        every step in FP64.
+ *  BLTC_FP32_MIXED  kernel evaluations in FP32 on local coordinates, partial
+ *                   sums over at most one cluster in FP32, accumulated per target
+ *                   in FP64; barycentric factors, the coincidence branch and
+ *                   pairs closer than a fixed cut-off stay FP64. */
+typedef enum { BLTC_FP64 = 0, BLTC_FP32_MIXED = 1 } bltc_precision;
+
+typedef struct {
+    int32_t kernel;              /* bltc_kernel                                         */
+    int32_t precision;           /* bltc_precision                                      */
+    double kappa;                /* Yukawa inverse Debye length, >= 0 (eq. 2)           */
+    double theta;                /* MAC parameter, 0 <= theta < 1 (eq. 13); 0 = direct  */
+    int32_t degree;              /* interpolation degree n, 1..16 (eqs. 6-8)            */
+    int32_t leaf_size;           /* N_L >= 1: clusters with <= N_L sources are leaves  */
+    int32_t batch_size;          /* N_B >= 1: batches hold <= N_B targets              */
+    int32_t threads_per_target;  /* 0 or 1 (reserved for split target evaluation)      */
+} bltc_params;
+
+/* Fills *p with the defaults: Coulomb, FP64, theta 0.7, degree 8, N_L = N_B = 2000. */
+void bltc_params_default(bltc_params* p);
+
+/* One-shot evaluation (Alg. 1): builds the tree, batches and interaction lists
+ * on the host (coordinates are copied device->host), then computes
+ * phi[m*phi_ld + i], m < num_q, on the GPU.  Synchronises `stream`.
+ * nt == 0 is a no-op; ns == 0 writes zeros.  Coordinates must be finite
+ * (BLTC_EINVAL otherwise). */
+int bltc_potential(const bltc_params* p,
+                   int64_t nt, const double* tx, const double* ty, const double* tz,
+                   int64_t ns, const double* sx, const double* sy, const double* sz,
+                   const double* q, int32_t num_q, int64_t q_ld,
+                   double* phi, int64_t phi_ld, void* stream);
+
+/* A plan fixes the geometry (trees, batches, lists, device copies of the
+ * coordinates in tree order) so that charges can vary between executions. */
+typedef struct bltc_plan bltc_plan;
+
+/* Creates a plan from DEVICE coordinates (copied device->host for planning,
+ * then uploaded in tree order on `stream`; synchronises `stream`).
+ * max_q >= 1 bounds num_q of later executions. */
+int bltc_plan_create(bltc_plan** out, const bltc_params* p,
+                     int64_t nt, const double* tx, const double* ty, const double* tz,
+                     int64_t ns, const double* sx, const double* sy, const double* sz,
+                     int32_t max_q, void* stream);
+
+/* Same as bltc_plan_create but the coordinates are HOST pointers and no HIP
+ * call is made: the plan holds only its host side (trees, batches, lists) and
+ * uploads its device side on its first execution.  Usable without a GPU for
+ * inspection (bltc_plan_view, bltc_plan_stats). */
+int bltc_plan_create_host(bltc_plan** out, const bltc_params* p,
+                          int64_t nt, const double* tx, const double* ty, const double* tz,
+                          int64_t ns, const double* sx, const double* sy, const double* sz,
+                          int32_t max_q);
+
+/* Evaluates the upward pass (eqs. 14-15) and all batch/cluster interactions
+ * (eqs. 9 and 11) for num_q <= max_q charge vectors q (device, caller order),
+ * writing phi (device, caller order).  Enqueued on `stream`; does not
+ * synchronise. */
+int bltc_plan_execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld,
+                      double* phi, int64_t phi_ld, void* stream);
+
+/* Copies the modified charges (eq. 12) that the last execution formed for
+ * source cluster `cluster` (an index into the cluster arrays of
+ * bltc_plan_view) and charge vector `qi` into the HOST buffer out[(n+1)^3],
+ * ordered k = (k1*(n+1) + k2)*(n+1) + k3.  Synchronises `stream`.
+ * BLTC_EINVAL if the cluster is in no approximation list (no charges formed). */
+int bltc_plan_modified_charges(bltc_plan* plan, int64_t cluster, int32_t qi,
+                               double* out, void* stream);
+
+typedef struct {
+    int64_t clusters;        /* source clusters in the tree                         */
+    int64_t leaves;          /* leaf clusters                                       */
+    int64_t batches;         /* target batches                                      */
+    int64_t approx_pairs;    /* batch/cluster pairs evaluated with eq. 11           */
+    int64_t direct_pairs;    /* batch/cluster pairs evaluated with eq. 9            */
+    int64_t approx_clusters; /* clusters that need modified charges                 */
+    int64_t far_evals;       /* sum over approx pairs of N_B * (n+1)^3               */
+    int64_t near_evals;      /* sum over direct pairs of N_B * N_C                   */
+    int64_t upward_terms;    /* sum over approx clusters of N_C * (n+1)^3            */
+    int32_t depth;           /* deepest source-tree level (root = 0)                */
+    int32_t degree;
+    int32_t leaf_size;
+    int32_t batch_size;
+    double setup_seconds;    /* host planning time                                  */
+} bltc_stats;
+
+int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out);
+
+/* Phase timing of executions (the paper's precompute / compute split,
+ * Sec. IV).  With timing enabled, bltc_plan_execute records HIP events on its
+ * stream around each phase; bltc_plan_phase_times waits for the last
+ * execution's events and writes its device milliseconds:
+ *   ms[0] charges gathered into tree order, ms[1] upward pass (eqs. 14-15),
+ *   ms[2] batch/cluster interactions (eqs. 9, 11), ms[3] total.
+ * BLTC_EINVAL if timing is off or nothing was executed since it was enabled. */
+int bltc_plan_set_timing(bltc_plan* plan, int32_t enable);
+int bltc_plan_phase_times(bltc_plan* plan, double* ms /* [4] */);
+
+/* Read-only HOST view of a plan's structure (valid until the plan is
+ * destroyed).  Cluster ids index the cluster arrays; the children of cluster c
+ * are cluster_first_child[c] .. + cluster_nchild[c] - 1. */
+typedef struct {
+    int64_t nt, ns, n_clusters, n_batches, n_items;
+    const int64_t* source_order;        /* [ns] original index at tree position    */
+    const int64_t* target_order;        /* [nt] original index at batch position   */
+    const int64_t* cluster_begin;       /* [n_clusters] first tree position        */
+    const int64_t* cluster_count;       /* [n_clusters]                           */
+    const double* cluster_lo;           /* [3*n_clusters] minimal box, x,y,z      */
+    const double* cluster_hi;           /* [3*n_clusters]                         */
+    const int32_t* cluster_first_child; /* [n_clusters] -1 for leaves             */
+    const int32_t* cluster_nchild;      /* [n_clusters]                           */
+    const int32_t* cluster_level;       /* [n_clusters]                           */
+    const int64_t* batch_begin;         /* [n_batches] first batch position       */
+    const int64_t* batch_count;         /* [n_batches]                            */
+    const double* batch_lo;             /* [3*n_batches]                          */
+    const double* batch_hi;             /* [3*n_batches]                          */
+    const int32_t* item_batch;          /* [n_items]                              */
+    const int32_t* item_cluster;        /* [n_items]                              */
+    const int32_t* item_kind;           /* [n_items] 0 = approximation, 1 = direct */
+} bltc_plan_view;
+
+int bltc_plan_view_get(const bltc_plan* plan, bltc_plan_view* out);
+
+void bltc_plan_destroy(bltc_plan* plan);
+
+/* GPU direct sum of eq. 1 (all pairs, pairs at zero distance skipped), FP64:
+ * phi[m*phi_ld + i] for m < num_q.  Diagnostic / baseline path.  Enqueued on
+ * `stream`. */
+int bltc_direct(const bltc_params* p,
+                int64_t nt, const double* tx, const double* ty, const double* tz,
+                int64_t ns, const double* sx, const double* sy, const double* sz,
+                const double* q, int32_t num_q, int64_t q_ld,
+                double* phi, int64_t phi_ld, void* stream);
+
+const char* bltc_status_string(int code);
+const char* bltc_last_error(void);     /* message of the calling thread's last failure */
+const char* bltc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLTC_H */

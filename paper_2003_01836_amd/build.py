@@ -1,0 +1,86 @@
+"""Builds the gfx950 shared library libbltc.so in-tree.
+
+    python -m paper_2003_01836_amd.build
+
+Host planning code is compiled by g++ without floating-point contraction (its
+geometric decisions follow their formulas operation by operation); the HIP
+sources are compiled by hipcc for gfx950 only.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(PKG, "libbltc.so")
+
+ARCH = "gfx950"
+HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+             # no packed-FP32 instructions anywhere in device code
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I" + INCLUDE, "-I" + CSRC, "-Wno-unused-command-line-argument"]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
+              "-I" + INCLUDE, "-I" + CSRC, "-Wall"]
+
+
+def _hipcc():
+    for cand in (shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def _run_all(cmds):
+    procs = [(c, subprocess.Popen(c, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)) for c in cmds]
+    failed = []
+    for c, p in procs:
+        out, _ = p.communicate()
+        text = out.decode(errors="replace")
+        # the host pass of hipcc does not know the packed-FP32 feature; that note is harmless
+        lines = [ln for ln in text.splitlines() if "packed-fp32-ops" not in ln]
+        if p.returncode != 0:
+            failed.append((c, "\n".join(lines)))
+        elif any(ln.strip() for ln in lines):
+            sys.stderr.write("\n".join(lines) + "\n")
+    if failed:
+        msg = "\n\n".join(" ".join(c) + "\n" + t for c, t in failed)
+        raise RuntimeError("build failed:\n" + msg)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    hipcc = _hipcc()
+    objs = {
+        "planner": os.path.join(BUILD, "planner.o"),
+        "kernels": os.path.join(BUILD, "kernels.o"),
+        "mixed": os.path.join(BUILD, "kernels_mixed.o"),
+        "capi": os.path.join(BUILD, "capi.o"),
+    }
+    cmds = [
+        ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
+        [hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", objs["kernels"]],
+        [hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, "kernels_mixed.hip"), "-o", objs["mixed"]],
+        [hipcc] + HIP_FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, "capi.cpp"), "-o", objs["capi"]],
+    ]
+    if not os.path.exists(os.path.join(CSRC, "kernels_mixed.hip")):
+        cmds.pop(2)
+        objs.pop("mixed")
+    if verbose:
+        for c in cmds:
+            print(" ".join(c))
+    _run_all(cmds)
+    tmp = LIB + ".tmp"
+    link = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + list(objs.values()) + ["-lpthread"]
+    _run_all([link])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

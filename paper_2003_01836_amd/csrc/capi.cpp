@@ -1,0 +1,634 @@
+// capi.cpp -- the C ABI declared in include/bltc.h: argument checks, plans
+// (host planning + device tables), execution on the caller's HIP stream.
+#include "bltc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "planner.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(BLTC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess)                           \
+            return hip_fail(e_, #call);                 \
+    } while (0)
+
+int check_params(const bltc_params* p)
+{
+    if (!p)
+        return fail(BLTC_EINVAL, "params is NULL");
+    if (p->kernel != BLTC_COULOMB && p->kernel != BLTC_YUKAWA)
+        return fail(BLTC_EINVAL, "kernel must be BLTC_COULOMB or BLTC_YUKAWA");
+    if (p->precision != BLTC_FP64 && p->precision != BLTC_FP32_MIXED)
+        return fail(BLTC_EINVAL, "precision must be BLTC_FP64 or BLTC_FP32_MIXED");
+    if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa))
+        return fail(BLTC_EINVAL, "kappa must be finite and >= 0");
+    if (!(p->theta >= 0.0 && p->theta < 1.0))
+        return fail(BLTC_EINVAL, "theta must satisfy 0 <= theta < 1");
+    if (p->degree < 1 || p->degree > bltc::kMaxDegree)
+        return fail(BLTC_EINVAL, "degree must be in 1..%d", bltc::kMaxDegree);
+    if (p->leaf_size < 1 || p->batch_size < 1)
+        return fail(BLTC_EINVAL, "leaf_size and batch_size must be >= 1");
+    if (p->precision == BLTC_FP32_MIXED)
+        return fail(BLTC_EUNSUPPORTED, "FP32-mixed precision is not available in this build");
+    if (p->threads_per_target < 0 || p->threads_per_target > 1)
+        return fail(BLTC_EUNSUPPORTED, "threads_per_target must be 0 or 1");
+    return BLTC_OK;
+}
+
+int check_coords(int64_t n, const double* x, const double* y, const double* z, const char* what)
+{
+    if (n < 0)
+        return fail(BLTC_EINVAL, "%s count is negative", what);
+    if (n > 0 && (!x || !y || !z))
+        return fail(BLTC_EINVAL, "%s coordinate pointer is NULL", what);
+    return BLTC_OK;
+}
+
+int check_finite(int64_t n, const double* x, const double* y, const double* z, const char* what)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(x[i]) || !std::isfinite(y[i]) || !std::isfinite(z[i]))
+            return fail(BLTC_EINVAL, "%s coordinate %lld is not finite", what,
+                        static_cast<long long>(i));
+    return BLTC_OK;
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s)
+{
+    const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), bytes);
+    if (e != hipSuccess)
+        return e;
+    if (!v.empty())
+        e = hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    return e;
+}
+
+}  // namespace
+
+struct bltc_plan {
+    bltc_params prm{};
+    int32_t max_q = 1;
+    bltc::HostPlan hp;
+    bool uploaded = false;
+    int device = -1;
+    bltc::DevicePlan d;
+    std::vector<void*> allocations;
+    bool timing = false;
+    int32_t timed_q = 0;                 // charge vectors covered by the recorded events
+    std::vector<hipEvent_t> events;      // 4 per charge vector
+
+    ~bltc_plan()
+    {
+        for (hipEvent_t e : events)
+            (void)hipEventDestroy(e);
+        for (void* p : allocations)
+            (void)hipFree(p);
+    }
+
+    template <class T>
+    hipError_t put(T** dst, const std::vector<T>& v, hipStream_t s)
+    {
+        hipError_t e = upload(dst, v, s);
+        if (e == hipSuccess)
+            allocations.push_back(*dst);
+        return e;
+    }
+
+    template <class T>
+    hipError_t alloc(T** dst, size_t count)
+    {
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(1, count) * sizeof(T));
+        if (e == hipSuccess)
+            allocations.push_back(*dst);
+        return e;
+    }
+};
+
+namespace {
+
+int make_host_plan(bltc_plan* plan, const bltc_params* p, int64_t nt, const double* tx,
+                   const double* ty, const double* tz, int64_t ns, const double* sx,
+                   const double* sy, const double* sz)
+{
+    bltc::PlanParams pp;
+    pp.theta = p->theta;
+    pp.degree = p->degree;
+    pp.leaf_size = p->leaf_size;
+    pp.batch_size = p->batch_size;
+    pp.group_size = bltc::kGroupSize;
+    std::string err = bltc::make_plan(plan->hp, pp, nt, tx, ty, tz, ns, sx, sy, sz);
+    if (!err.empty())
+        return fail(BLTC_EINTERNAL, "%s", err.c_str());
+    return BLTC_OK;
+}
+
+int upload_plan(bltc_plan* plan, hipStream_t s)
+{
+    if (plan->uploaded)
+        return BLTC_OK;
+    const bltc::HostPlan& hp = plan->hp;
+    bltc::DevicePlan& d = plan->d;
+    HIP_TRY(hipGetDevice(&plan->device));
+    d.degree = plan->prm.degree;
+    d.nt = hp.tgt.n;
+    d.ns = hp.src.n;
+    d.nslots = static_cast<int64_t>(hp.slot_cluster.size());
+    d.nchunks = static_cast<int64_t>(hp.chunk_slot.size());
+    d.ngroups = static_cast<int64_t>(hp.group_batch.size());
+    d.nbatches = static_cast<int64_t>(hp.batch_begin.size());
+
+    std::vector<double4> src(d.ns), tgt(d.nt);
+    for (int64_t j = 0; j < d.ns; ++j)
+        src[j] = make_double4(hp.src.x[j], hp.src.y[j], hp.src.z[j], 0.0);
+    for (int64_t i = 0; i < d.nt; ++i)
+        tgt[i] = make_double4(hp.tgt.x[i], hp.tgt.y[i], hp.tgt.z[i], 0.0);
+    std::vector<int64_t> batch_end(d.nbatches);
+    for (int64_t b = 0; b < d.nbatches; ++b)
+        batch_end[b] = hp.batch_begin[b] + hp.batch_count[b];
+
+    HIP_TRY(plan->put(&d.src, src, s));
+    HIP_TRY(plan->put(&d.tgt, tgt, s));
+    HIP_TRY(plan->put(&d.tgt_orig, hp.tgt.order, s));
+    int64_t* src_order = nullptr;
+    HIP_TRY(plan->put(&src_order, hp.src.order, s));
+    d.src_order = src_order;
+    HIP_TRY(plan->put(&d.group_batch, hp.group_batch, s));
+    HIP_TRY(plan->put(&d.group_first, hp.group_first, s));
+    HIP_TRY(plan->put(&d.batch_end, batch_end, s));
+    HIP_TRY(plan->put(&d.far_off, hp.far_off, s));
+    HIP_TRY(plan->put(&d.far_slot, hp.far_slot, s));
+    HIP_TRY(plan->put(&d.near_off, hp.near_off, s));
+    HIP_TRY(plan->put(&d.near_begin, hp.near_begin, s));
+    HIP_TRY(plan->put(&d.near_count, hp.near_count, s));
+    HIP_TRY(plan->put(&d.near_leaf, hp.near_leaf, s));
+    HIP_TRY(plan->put(&d.slot_nodes, hp.slot_nodes, s));
+    HIP_TRY(plan->put(&d.chunk_slot, hp.chunk_slot, s));
+    HIP_TRY(plan->put(&d.chunk_begin, hp.chunk_begin, s));
+    HIP_TRY(plan->put(&d.chunk_count, hp.chunk_count, s));
+    HIP_TRY(plan->put(&d.slot_chunk_off, hp.slot_chunk_off, s));
+    HIP_TRY(plan->alloc(&d.partial, static_cast<size_t>(d.nchunks) * hp.P));
+    HIP_TRY(plan->alloc(&d.qhat, static_cast<size_t>(d.nslots) * hp.P * plan->max_q));
+    // host staging vectors die at return: finish the copies first
+    HIP_TRY(hipStreamSynchronize(s));
+    plan->uploaded = true;
+    return BLTC_OK;
+}
+
+int zero_phi(int64_t nt, int32_t num_q, double* phi, int64_t phi_ld, hipStream_t s)
+{
+    for (int32_t m = 0; m < num_q; ++m)
+        HIP_TRY(hipMemsetAsync(phi + static_cast<int64_t>(m) * phi_ld, 0, nt * sizeof(double), s));
+    return BLTC_OK;
+}
+
+int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, double* phi,
+            int64_t phi_ld, hipStream_t s)
+{
+    const bltc::HostPlan& hp = plan->hp;
+    const int64_t nt = hp.tgt.n, ns = hp.src.n;
+    if (num_q < 1 || num_q > plan->max_q)
+        return fail(BLTC_EINVAL, "num_q must be in 1..max_q (%d)", plan->max_q);
+    if (nt == 0)
+        return BLTC_OK;
+    if (!phi)
+        return fail(BLTC_EINVAL, "phi is NULL");
+    if (phi_ld < nt && num_q > 1)
+        return fail(BLTC_EINVAL, "phi_ld must be >= nt");
+    if (ns == 0)
+        return zero_phi(nt, num_q, phi, phi_ld, s);
+    if (!q)
+        return fail(BLTC_EINVAL, "q is NULL");
+    if (q_ld < ns && num_q > 1)
+        return fail(BLTC_EINVAL, "q_ld must be >= ns");
+    int rc = upload_plan(plan, s);
+    if (rc != BLTC_OK)
+        return rc;
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != plan->device)
+        return fail(BLTC_EINVAL, "plan was uploaded on device %d, current device is %d",
+                    plan->device, dev);
+    bltc::KernelParams kp;
+    kp.kernel = plan->prm.kernel;
+    kp.precision = plan->prm.precision;
+    kp.kappa = plan->prm.kappa;
+    bltc::DevicePlan d = plan->d;
+    if (plan->timing) {
+        while (static_cast<int32_t>(plan->events.size()) < 4 * num_q) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            plan->events.push_back(e);
+        }
+    }
+    plan->timed_q = 0;
+    auto mark = [&](int32_t m, int k) -> hipError_t {
+        return plan->timing ? hipEventRecord(plan->events[4 * m + k], s) : hipSuccess;
+    };
+    for (int32_t m = 0; m < num_q; ++m) {
+        d.qhat = plan->d.qhat + static_cast<int64_t>(m) * d.nslots * hp.P;
+        HIP_TRY(mark(m, 0));
+        HIP_TRY(bltc::launch_gather_charges(d, q + static_cast<int64_t>(m) * q_ld, s));
+        HIP_TRY(mark(m, 1));
+        HIP_TRY(bltc::launch_upward(d, s));
+        HIP_TRY(mark(m, 2));
+        HIP_TRY(bltc::launch_interact(d, kp, phi + static_cast<int64_t>(m) * phi_ld, s));
+        HIP_TRY(mark(m, 3));
+    }
+    plan->timed_q = plan->timing ? num_q : 0;
+    return BLTC_OK;
+}
+
+int create_common(bltc_plan** out, const bltc_params* p, int64_t nt, const double* tx,
+                  const double* ty, const double* tz, int64_t ns, const double* sx,
+                  const double* sy, const double* sz, int32_t max_q)
+{
+    if (!out)
+        return fail(BLTC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_params(p);
+    if (rc != BLTC_OK)
+        return rc;
+    if ((rc = check_coords(nt, tx, ty, tz, "target")) != BLTC_OK)
+        return rc;
+    if ((rc = check_coords(ns, sx, sy, sz, "source")) != BLTC_OK)
+        return rc;
+    if (max_q < 1)
+        return fail(BLTC_EINVAL, "max_q must be >= 1");
+    return BLTC_OK;
+}
+
+int create_from_host(bltc_plan** out, const bltc_params* p, int64_t nt, const double* tx,
+                     const double* ty, const double* tz, int64_t ns, const double* sx,
+                     const double* sy, const double* sz, int32_t max_q)
+{
+    int rc;
+    if ((rc = check_finite(nt, tx, ty, tz, "target")) != BLTC_OK)
+        return rc;
+    if ((rc = check_finite(ns, sx, sy, sz, "source")) != BLTC_OK)
+        return rc;
+    bltc_plan* plan = new (std::nothrow) bltc_plan();
+    if (!plan)
+        return fail(BLTC_ENOMEM, "cannot allocate plan");
+    plan->prm = *p;
+    plan->max_q = max_q;
+    try {
+        rc = make_host_plan(plan, p, nt, tx, ty, tz, ns, sx, sy, sz);
+    } catch (const std::bad_alloc&) {
+        rc = fail(BLTC_ENOMEM, "host allocation failed while planning");
+    } catch (const std::exception& ex) {
+        rc = fail(BLTC_EINTERNAL, "planning failed: %s", ex.what());
+    }
+    if (rc != BLTC_OK) {
+        delete plan;
+        return rc;
+    }
+    *out = plan;
+    return BLTC_OK;
+}
+
+// device -> host copies of coordinates; identical pointers stay identical
+int download_coords(int64_t nt, const double* tx, const double* ty, const double* tz, int64_t ns,
+                    const double* sx, const double* sy, const double* sz, std::vector<double>& h,
+                    const double* hp[6], hipStream_t s)
+{
+    const double* dev[6] = {tx, ty, tz, sx, sy, sz};
+    const int64_t cnt[6] = {nt, nt, nt, ns, ns, ns};
+    int64_t total = 0;
+    int64_t off[6];
+    for (int k = 0; k < 6; ++k) {
+        off[k] = -1;
+        for (int j = 0; j < k; ++j)
+            if (dev[j] == dev[k] && cnt[j] == cnt[k])
+                off[k] = off[j];
+        if (off[k] < 0) {
+            off[k] = total;
+            total += cnt[k];
+        }
+    }
+    h.resize(std::max<int64_t>(1, total));
+    for (int k = 0; k < 6; ++k) {
+        bool first = true;
+        for (int j = 0; j < k; ++j)
+            if (off[j] == off[k])
+                first = false;
+        if (first && cnt[k] > 0)
+            HIP_TRY(hipMemcpyAsync(h.data() + off[k], dev[k], cnt[k] * sizeof(double),
+                                   hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < 6; ++k)
+        hp[k] = h.data() + off[k];
+    return BLTC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bltc_params_default(bltc_params* p)
+{
+    if (!p)
+        return;
+    std::memset(p, 0, sizeof(*p));
+    p->kernel = BLTC_COULOMB;
+    p->precision = BLTC_FP64;
+    p->kappa = 0.0;
+    p->theta = 0.7;
+    p->degree = 8;
+    p->leaf_size = 2000;
+    p->batch_size = 2000;
+    p->threads_per_target = 0;
+}
+
+int bltc_plan_create_host(bltc_plan** out, const bltc_params* p, int64_t nt, const double* tx,
+                          const double* ty, const double* tz, int64_t ns, const double* sx,
+                          const double* sy, const double* sz, int32_t max_q)
+{
+    int rc = create_common(out, p, nt, tx, ty, tz, ns, sx, sy, sz, max_q);
+    if (rc != BLTC_OK)
+        return rc;
+    return create_from_host(out, p, nt, tx, ty, tz, ns, sx, sy, sz, max_q);
+}
+
+int bltc_plan_create(bltc_plan** out, const bltc_params* p, int64_t nt, const double* tx,
+                     const double* ty, const double* tz, int64_t ns, const double* sx,
+                     const double* sy, const double* sz, int32_t max_q, void* stream)
+{
+    int rc = create_common(out, p, nt, tx, ty, tz, ns, sx, sy, sz, max_q);
+    if (rc != BLTC_OK)
+        return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<double> h;
+    const double* hp[6];
+    try {
+        rc = download_coords(nt, tx, ty, tz, ns, sx, sy, sz, h, hp, s);
+    } catch (const std::bad_alloc&) {
+        rc = fail(BLTC_ENOMEM, "host allocation failed");
+    }
+    if (rc != BLTC_OK)
+        return rc;
+    rc = create_from_host(out, p, nt, hp[0], hp[1], hp[2], ns, hp[3], hp[4], hp[5], max_q);
+    if (rc != BLTC_OK)
+        return rc;
+    try {
+        rc = upload_plan(*out, s);
+    } catch (const std::bad_alloc&) {
+        rc = fail(BLTC_ENOMEM, "host allocation failed while uploading");
+    }
+    if (rc != BLTC_OK) {
+        delete *out;
+        *out = nullptr;
+    }
+    return rc;
+}
+
+int bltc_plan_execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, double* phi,
+                      int64_t phi_ld, void* stream)
+{
+    if (!plan)
+        return fail(BLTC_EINVAL, "plan is NULL");
+    try {
+        return execute(plan, q, num_q, q_ld, phi, phi_ld, static_cast<hipStream_t>(stream));
+    } catch (const std::bad_alloc&) {
+        return fail(BLTC_ENOMEM, "host allocation failed");
+    } catch (const std::exception& ex) {
+        return fail(BLTC_EINTERNAL, "%s", ex.what());
+    }
+}
+
+int bltc_potential(const bltc_params* p, int64_t nt, const double* tx, const double* ty,
+                   const double* tz, int64_t ns, const double* sx, const double* sy,
+                   const double* sz, const double* q, int32_t num_q, int64_t q_ld, double* phi,
+                   int64_t phi_ld, void* stream)
+{
+    if (nt == 0) {
+        int rc = check_params(p);
+        return rc != BLTC_OK ? rc : BLTC_OK;
+    }
+    if (num_q < 1)
+        return fail(BLTC_EINVAL, "num_q must be >= 1");
+    bltc_plan* plan = nullptr;
+    int rc = bltc_plan_create(&plan, p, nt, tx, ty, tz, ns, sx, sy, sz, num_q, stream);
+    if (rc != BLTC_OK)
+        return rc;
+    rc = bltc_plan_execute(plan, q, num_q, q_ld, phi, phi_ld, stream);
+    if (rc == BLTC_OK) {
+        hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (e != hipSuccess)
+            rc = hip_fail(e, "hipStreamSynchronize");
+    }
+    bltc_plan_destroy(plan);
+    return rc;
+}
+
+int bltc_plan_modified_charges(bltc_plan* plan, int64_t cluster, int32_t qi, double* out,
+                               void* stream)
+{
+    if (!plan || !out)
+        return fail(BLTC_EINVAL, "NULL argument");
+    const bltc::HostPlan& hp = plan->hp;
+    if (cluster < 0 || cluster >= hp.src.nodes())
+        return fail(BLTC_EINVAL, "cluster index out of range");
+    if (qi < 0 || qi >= plan->max_q)
+        return fail(BLTC_EINVAL, "charge-vector index out of range");
+    const int32_t slot = hp.cluster_slot[cluster];
+    if (slot < 0)
+        return fail(BLTC_EINVAL, "cluster %lld has no modified charges",
+                    static_cast<long long>(cluster));
+    if (!plan->uploaded)
+        return fail(BLTC_EINVAL, "plan has not been executed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double* src = plan->d.qhat + (static_cast<int64_t>(qi) * plan->d.nslots + slot) * hp.P;
+    HIP_TRY(hipMemcpyAsync(out, src, hp.P * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return BLTC_OK;
+}
+
+int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out)
+{
+    if (!plan || !out)
+        return fail(BLTC_EINVAL, "NULL argument");
+    const bltc::HostPlan& hp = plan->hp;
+    std::memset(out, 0, sizeof(*out));
+    out->clusters = hp.src.nodes();
+    out->leaves = hp.leaves;
+    out->batches = static_cast<int64_t>(hp.batch_begin.size());
+    out->approx_pairs = hp.approx_pairs;
+    out->direct_pairs = hp.direct_pairs;
+    out->approx_clusters = static_cast<int64_t>(hp.slot_cluster.size());
+    out->far_evals = hp.far_evals;
+    out->near_evals = hp.near_evals;
+    out->upward_terms = hp.upward_terms;
+    out->depth = hp.src.depth;
+    out->degree = plan->prm.degree;
+    out->leaf_size = plan->prm.leaf_size;
+    out->batch_size = plan->prm.batch_size;
+    out->setup_seconds = hp.setup_seconds;
+    return BLTC_OK;
+}
+
+int bltc_plan_view_get(const bltc_plan* plan, bltc_plan_view* out)
+{
+    if (!plan || !out)
+        return fail(BLTC_EINVAL, "NULL argument");
+    const bltc::HostPlan& hp = plan->hp;
+    std::memset(out, 0, sizeof(*out));
+    out->nt = hp.tgt.n;
+    out->ns = hp.src.n;
+    out->n_clusters = hp.src.nodes();
+    out->n_batches = static_cast<int64_t>(hp.batch_begin.size());
+    out->n_items = static_cast<int64_t>(hp.item_batch.size());
+    out->source_order = hp.src.order.data();
+    out->target_order = hp.tgt.order.data();
+    out->cluster_begin = hp.src.begin.data();
+    out->cluster_count = hp.src.count.data();
+    out->cluster_lo = hp.src.lo.data();
+    out->cluster_hi = hp.src.hi.data();
+    out->cluster_first_child = hp.src.first_child.data();
+    out->cluster_nchild = hp.src.nchild.data();
+    out->cluster_level = hp.src.level.data();
+    out->batch_begin = hp.batch_begin.data();
+    out->batch_count = hp.batch_count.data();
+    out->batch_lo = hp.batch_lo.data();
+    out->batch_hi = hp.batch_hi.data();
+    out->item_batch = hp.item_batch.data();
+    out->item_cluster = hp.item_cluster.data();
+    out->item_kind = hp.item_kind.data();
+    return BLTC_OK;
+}
+
+int bltc_plan_set_timing(bltc_plan* plan, int32_t enable)
+{
+    if (!plan)
+        return fail(BLTC_EINVAL, "plan is NULL");
+    plan->timing = enable != 0;
+    plan->timed_q = 0;
+    return BLTC_OK;
+}
+
+int bltc_plan_phase_times(bltc_plan* plan, double* ms)
+{
+    if (!plan || !ms)
+        return fail(BLTC_EINVAL, "NULL argument");
+    if (!plan->timing || plan->timed_q == 0)
+        return fail(BLTC_EINVAL, "no timed execution (enable timing, then execute)");
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int32_t m = 0; m < plan->timed_q; ++m) {
+        HIP_TRY(hipEventSynchronize(plan->events[4 * m + 3]));
+        for (int k = 0; k < 3; ++k) {
+            float t = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&t, plan->events[4 * m + k], plan->events[4 * m + k + 1]));
+            acc[k] += t;
+        }
+    }
+    for (int k = 0; k < 3; ++k)
+        ms[k] = acc[k];
+    ms[3] = acc[0] + acc[1] + acc[2];
+    return BLTC_OK;
+}
+
+void bltc_plan_destroy(bltc_plan* plan)
+{
+    delete plan;
+}
+
+int bltc_direct(const bltc_params* p, int64_t nt, const double* tx, const double* ty,
+                const double* tz, int64_t ns, const double* sx, const double* sy, const double* sz,
+                const double* q, int32_t num_q, int64_t q_ld, double* phi, int64_t phi_ld,
+                void* stream)
+{
+    int rc = check_params(p);
+    if (rc != BLTC_OK)
+        return rc;
+    if ((rc = check_coords(nt, tx, ty, tz, "target")) != BLTC_OK)
+        return rc;
+    if ((rc = check_coords(ns, sx, sy, sz, "source")) != BLTC_OK)
+        return rc;
+    if (num_q < 1)
+        return fail(BLTC_EINVAL, "num_q must be >= 1");
+    if (nt == 0)
+        return BLTC_OK;
+    if (!phi)
+        return fail(BLTC_EINVAL, "phi is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ns == 0)
+        return zero_phi(nt, num_q, phi, phi_ld, s);
+    if (!q)
+        return fail(BLTC_EINVAL, "q is NULL");
+    double4* packed = nullptr;
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&packed), ns * sizeof(double4), s));
+    bltc::KernelParams kp;
+    kp.kernel = p->kernel;
+    kp.kappa = p->kappa;
+    hipError_t e = hipSuccess;
+    for (int32_t m = 0; m < num_q && e == hipSuccess; ++m) {
+        e = bltc::launch_pack_sources(ns, sx, sy, sz, q + static_cast<int64_t>(m) * q_ld, packed, s);
+        if (e == hipSuccess)
+            e = bltc::launch_direct(nt, tx, ty, tz, ns, packed, kp,
+                                    phi + static_cast<int64_t>(m) * phi_ld, s);
+    }
+    hipError_t f = hipFreeAsync(packed, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "direct-sum launch");
+    if (f != hipSuccess)
+        return hip_fail(f, "hipFreeAsync");
+    return BLTC_OK;
+}
+
+const char* bltc_status_string(int code)
+{
+    switch (code) {
+    case BLTC_OK: return "ok";
+    case BLTC_EINVAL: return "invalid argument";
+    case BLTC_ENOMEM: return "out of memory";
+    case BLTC_EHIP: return "HIP runtime error";
+    case BLTC_EUNSUPPORTED: return "unsupported";
+    case BLTC_EINTERNAL: return "internal error";
+    default: return "unknown status";
+    }
+}
+
+const char* bltc_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+const char* bltc_version(void)
+{
+    return "bltc-mi355x 0.1 (gfx950)";
+}
+
+}  // extern "C"

@@ -1,0 +1,436 @@
+// kernels.hip -- gfx950 kernels of the barycentric Lagrange treecode.
+//
+// Mapping (CDNA4, wave64):
+//  * interactions: one target per lane, 256 targets of one batch per
+//    workgroup; every lane of a wave walks the same interaction list (the MAC
+//    is applied per batch, Sec. III-B), so source particles, Chebyshev points
+//    and modified charges are wave-uniform and are read through the scalar
+//    data cache into SGPRs -- no LDS staging and no barriers.  Each lane owns
+//    its target's accumulator, so phi is written exactly once, in caller
+//    order, without atomics.
+//  * upward pass: one workgroup per chunk of a cluster's sources; lanes over
+//    sources form the 1-D barycentric factors of eq. 14 in LDS, then lanes
+//    over grid points accumulate eq. 15; a second kernel sums the chunks of
+//    each cluster in a fixed order (deterministic).
+#include "kernels.hpp"
+
+#include <cfloat>
+
+namespace bltc {
+namespace {
+
+// ---------------------------------------------------------------------------
+// FP64 reciprocal square root: the hardware estimate (v_rsq_f64) refined by
+// one third-order Householder step for x^{-1/2}: with e = 1 - r2*y0^2,
+// y = y0 * (1 + e/2 + 3e^2/8).  The truncation term is 5e^3/16, far below the
+// FP64 rounding unit for the estimate's accuracy.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rsqrt_f64(double r2)
+{
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double t = r2 * y;
+    const double e = __fma_rn(-t, y, 1.0);
+    const double p = __fma_rn(0.375, e, 0.5);
+    const double s = y * e;
+    return __fma_rn(s, p, y);
+}
+
+// G as a function of r^2 and 1/r (eq. 2).
+template <int KER>
+__device__ __forceinline__ double green_f64(double r2, double rinv, double kappa)
+{
+    if constexpr (KER == 0) {
+        return rinv;
+    } else {
+        return exp(-kappa * (r2 * rinv)) * rinv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Direct batch/cluster sum over a contiguous source range (eq. 9), pairs at
+// zero distance skipped.  `s` is wave-uniform.
+// ---------------------------------------------------------------------------
+template <int KER>
+__device__ __forceinline__ double near_term_f64(double x, double y, double z, const double4 p,
+                                                double kappa)
+{
+    const double dx = x - p.x;
+    const double dy = y - p.y;
+    const double dz = z - p.z;
+    const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+    const double g = green_f64<KER>(r2, rsqrt_f64(r2), kappa);
+    return (r2 > 0.0 ? g : 0.0) * p.w;
+}
+
+template <int KER>
+__device__ __forceinline__ double near_sum_f64(double x, double y, double z,
+                                               const double4* __restrict__ s, int64_t cnt,
+                                               double kappa)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t j = 0;
+    for (; j + 4 <= cnt; j += 4) {
+        a0 += near_term_f64<KER>(x, y, z, s[j], kappa);
+        a1 += near_term_f64<KER>(x, y, z, s[j + 1], kappa);
+        a2 += near_term_f64<KER>(x, y, z, s[j + 2], kappa);
+        a3 += near_term_f64<KER>(x, y, z, s[j + 3], kappa);
+    }
+    for (; j < cnt; ++j)
+        a0 += near_term_f64<KER>(x, y, z, s[j], kappa);
+    return (a0 + a1) + (a2 + a3);
+}
+
+// ---------------------------------------------------------------------------
+// Batch/cluster approximation (eq. 11): sum_k G(x, s_k) qhat_k over the
+// (n+1)^3 tensor grid.  With the grid separable, r^2 = a_k1 + b_k2 + c_k3
+// where a, b, c are the squared 1-D distances, formed once per target.
+// `nd` ([3][n+1] points) and `qh` ([P] charges) are wave-uniform.
+// ---------------------------------------------------------------------------
+template <int N, int KER>
+__device__ __forceinline__ double far_sum_f64(double x, double y, double z,
+                                              const double* __restrict__ nd,
+                                              const double* __restrict__ qh, double kappa)
+{
+    constexpr int NP = N + 1;
+    double b2[NP], c2[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const double dy = y - nd[NP + k];
+        const double dz = z - nd[2 * NP + k];
+        b2[k] = dy * dy;
+        c2[k] = dz * dz;
+    }
+    double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll 1
+    for (int k1 = 0; k1 < NP; ++k1) {
+        const double dx = x - nd[k1];
+        const double a2 = dx * dx;
+        const double* __restrict__ q1 = qh + k1 * NP * NP;
+#pragma unroll
+        for (int k2 = 0; k2 < NP; ++k2) {
+            const double ab = a2 + b2[k2];
+#pragma unroll
+            for (int k3 = 0; k3 < NP; ++k3) {
+                const double r2 = ab + c2[k3];
+                const double g = green_f64<KER>(r2, rsqrt_f64(r2), kappa);
+                if ((k2 + k3) & 1)
+                    acc1 = __fma_rn(g, q1[k2 * NP + k3], acc1);
+                else
+                    acc0 = __fma_rn(g, q1[k2 * NP + k3], acc0);
+            }
+        }
+    }
+    return acc0 + acc1;
+}
+
+// ---------------------------------------------------------------------------
+// Interactions of one workgroup: 256 consecutive targets of one batch.
+// ---------------------------------------------------------------------------
+template <int N, int KER>
+__global__ __launch_bounds__(kGroupSize) void interact_f64(
+    const double4* __restrict__ tgt, const int64_t* __restrict__ tgt_orig,
+    const double4* __restrict__ src, const int32_t* __restrict__ group_batch,
+    const int64_t* __restrict__ group_first, const int64_t* __restrict__ batch_end,
+    const int32_t* __restrict__ far_off, const int32_t* __restrict__ far_slot,
+    const int32_t* __restrict__ near_off, const int64_t* __restrict__ near_begin,
+    const int64_t* __restrict__ near_count, const double* __restrict__ slot_nodes,
+    const double* __restrict__ qhat, double* __restrict__ phi, double kappa)
+{
+    constexpr int NP = N + 1;
+    constexpr int P = NP * NP * NP;
+    const int g = blockIdx.x;
+    const int b = group_batch[g];
+    const int64_t first = group_first[g];
+    const int64_t end = batch_end[b];
+    const int64_t wave_first = first + (threadIdx.x & ~63);
+    if (wave_first >= end)
+        return;  // the whole wave lies past the batch end
+    int64_t i = first + threadIdx.x;
+    const bool valid = i < end;
+    if (!valid)
+        i = end - 1;
+    const double4 t = tgt[i];
+    double acc = 0.0;
+
+    const int f_end = far_off[b + 1];
+    for (int f = far_off[b]; f < f_end; ++f) {
+        const int64_t slot = far_slot[f];
+        acc += far_sum_f64<N, KER>(t.x, t.y, t.z, slot_nodes + slot * 3 * NP, qhat + slot * P,
+                                   kappa);
+    }
+    const int n_end = near_off[b + 1];
+    for (int e = near_off[b]; e < n_end; ++e)
+        acc += near_sum_f64<KER>(t.x, t.y, t.z, src + near_begin[e], near_count[e], kappa);
+
+    if (valid)
+        phi[tgt_orig[i]] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Upward pass, eqs. 14-15.  One workgroup per chunk (<= chunk_size sources of
+// one cluster).  Tiles of kUpwardTile sources: lane j forms, in FP64,
+//   a_lk = w_k / (y_jl - s_lk), D_l = sum_k a_lk   (l = 1, 2, 3)
+// or, when |y_jl - s_lk'| < DBL_MIN, a_lk = delta_kk', D_l = 1 (eq. 5);
+// then qtilde_j = q_j / (D_1 D_2 D_3) (eq. 14), stored as A1 = a_1 * qtilde,
+// A2 = a_2, A3 = a_3.  Lanes over grid points k then accumulate
+// qhat_k += A1[k1] A2[k2] A3[k3] (eq. 15).
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void bary_factors(double yv, const double* __restrict__ s,
+                                             double* __restrict__ a, double& D)
+{
+    constexpr int NP = N + 1;
+    int hit = -1;
+#pragma unroll
+    for (int k = NP - 1; k >= 0; --k)
+        if (fabs(yv - s[k]) < DBL_MIN)
+            hit = k;  // lowest coincident index wins
+    if (hit >= 0) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            a[k] = (k == hit) ? 1.0 : 0.0;
+        D = 1.0;
+        return;
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const double w = ((k & 1) ? -1.0 : 1.0) * ((k == 0 || k == N) ? 0.5 : 1.0);
+        a[k] = w / (yv - s[k]);
+        sum += a[k];
+    }
+    D = sum;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void upward_partial_f64(
+    const double4* __restrict__ src, const int32_t* __restrict__ chunk_slot,
+    const int64_t* __restrict__ chunk_begin, const int64_t* __restrict__ chunk_count,
+    const double* __restrict__ slot_nodes, double* __restrict__ partial)
+{
+    constexpr int NP = N + 1;
+    constexpr int P = NP * NP * NP;
+    constexpr int KPT = (P + 255) / 256;
+    __shared__ double A1[kUpwardTile * NP];
+    __shared__ double A2[kUpwardTile * NP];
+    __shared__ double A3[kUpwardTile * NP];
+    __shared__ double sn[3 * NP];
+
+    const int c = blockIdx.x;
+    const int64_t slot = chunk_slot[c];
+    const int64_t begin = chunk_begin[c];
+    const int64_t count = chunk_count[c];
+    const int tid = threadIdx.x;
+    if (tid < 3 * NP)
+        sn[tid] = slot_nodes[slot * 3 * NP + tid];
+    __syncthreads();
+
+    double acc[KPT];
+    int kk1[KPT], kk2[KPT], kk3[KPT];
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+        acc[u] = 0.0;
+        const int k = tid + u * 256;
+        const int kc = k < P ? k : 0;
+        kk1[u] = kc / (NP * NP);
+        kk2[u] = (kc / NP) % NP;
+        kk3[u] = kc % NP;
+    }
+
+    for (int64_t t0 = 0; t0 < count; t0 += kUpwardTile) {
+        const int tn = static_cast<int>(count - t0 < kUpwardTile ? count - t0 : kUpwardTile);
+        if (tid < tn) {
+            const double4 p = src[begin + t0 + tid];
+            double a1[NP], a2[NP], a3[NP], D1, D2, D3;
+            bary_factors<N>(p.x, sn, a1, D1);
+            bary_factors<N>(p.y, sn + NP, a2, D2);
+            bary_factors<N>(p.z, sn + 2 * NP, a3, D3);
+            const double qt = p.w / (D1 * D2 * D3);
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                A1[tid * NP + k] = a1[k] * qt;
+                A2[tid * NP + k] = a2[k];
+                A3[tid * NP + k] = a3[k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < KPT; ++u) {
+            if (tid + u * 256 < P) {
+                double s = acc[u];
+                for (int j = 0; j < tn; ++j)
+                    s = __fma_rn(A1[j * NP + kk1[u]] * A2[j * NP + kk2[u]], A3[j * NP + kk3[u]], s);
+                acc[u] = s;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+        const int k = tid + u * 256;
+        if (k < P)
+            partial[static_cast<int64_t>(c) * P + k] = acc[u];
+    }
+}
+
+__global__ __launch_bounds__(256) void upward_reduce_f64(const int32_t* __restrict__ slot_chunk_off,
+                                                         const double* __restrict__ partial,
+                                                         double* __restrict__ qhat, int64_t nslots,
+                                                         int32_t P)
+{
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= nslots * P)
+        return;
+    const int64_t slot = idx / P;
+    const int64_t k = idx - slot * P;
+    double s = 0.0;
+    for (int32_t c = slot_chunk_off[slot]; c < slot_chunk_off[slot + 1]; ++c)
+        s += partial[static_cast<int64_t>(c) * P + k];
+    qhat[idx] = s;
+}
+
+__global__ __launch_bounds__(256) void gather_charges(double4* __restrict__ src,
+                                                      const int64_t* __restrict__ order,
+                                                      const double* __restrict__ q, int64_t ns)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j < ns)
+        src[j].w = q[order[j]];
+}
+
+__global__ __launch_bounds__(256) void pack_sources(int64_t ns, const double* __restrict__ x,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ z,
+                                                    const double* __restrict__ q,
+                                                    double4* __restrict__ out)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j < ns)
+        out[j] = make_double4(x[j], y[j], z[j], q[j]);
+}
+
+template <int KER>
+__global__ __launch_bounds__(256) void direct_f64(int64_t nt, const double* __restrict__ tx,
+                                                  const double* __restrict__ ty,
+                                                  const double* __restrict__ tz, int64_t ns,
+                                                  const double4* __restrict__ src,
+                                                  double* __restrict__ phi, double kappa)
+{
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x;
+    if (base + (threadIdx.x & ~63) >= nt)
+        return;
+    int64_t i = base + threadIdx.x;
+    const bool valid = i < nt;
+    if (!valid)
+        i = nt - 1;
+    const double acc = near_sum_f64<KER>(tx[i], ty[i], tz[i], src, ns, kappa);
+    if (valid)
+        phi[i] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch over the interpolation degree
+// ---------------------------------------------------------------------------
+
+template <int N, int KER>
+hipError_t run_interact(const DevicePlan& d, double* phi, double kappa, hipStream_t s)
+{
+    if (d.ngroups == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((interact_f64<N, KER>), dim3(static_cast<unsigned>(d.ngroups)),
+                       dim3(kGroupSize), 0, s, d.tgt, d.tgt_orig, d.src, d.group_batch,
+                       d.group_first, d.batch_end, d.far_off, d.far_slot, d.near_off,
+                       d.near_begin, d.near_count, d.slot_nodes, d.qhat, phi, kappa);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t run_upward(const DevicePlan& d, hipStream_t s)
+{
+    constexpr int NP = N + 1;
+    constexpr int P = NP * NP * NP;
+    if (d.nchunks == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((upward_partial_f64<N>), dim3(static_cast<unsigned>(d.nchunks)), dim3(256),
+                       0, s, d.src, d.chunk_slot, d.chunk_begin, d.chunk_count, d.slot_nodes,
+                       d.partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int64_t total = d.nslots * P;
+    hipLaunchKernelGGL(upward_reduce_f64, dim3(static_cast<unsigned>((total + 255) / 256)),
+                       dim3(256), 0, s, d.slot_chunk_off, d.partial, d.qhat, d.nslots,
+                       static_cast<int32_t>(P));
+    return hipGetLastError();
+}
+
+#define BLTC_DEGREE_CASES(X) \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+}  // namespace
+
+hipError_t launch_gather_charges(const DevicePlan& d, const double* q, hipStream_t s)
+{
+    if (d.ns == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(gather_charges, dim3(static_cast<unsigned>((d.ns + 255) / 256)), dim3(256),
+                       0, s, d.src, d.src_order, q, d.ns);
+    return hipGetLastError();
+}
+
+hipError_t launch_upward(const DevicePlan& d, hipStream_t s)
+{
+    switch (d.degree) {
+#define X(n) \
+    case n:  \
+        return run_upward<n>(d, s);
+        BLTC_DEGREE_CASES(X)
+#undef X
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* phi,
+                           hipStream_t s)
+{
+    const bool yuk = kp.kernel == 1;
+    switch (d.degree) {
+#define X(n)                                                                   \
+    case n:                                                                    \
+        return yuk ? run_interact<n, 1>(d, phi, kp.kappa, s)                   \
+                   : run_interact<n, 0>(d, phi, kp.kappa, s);
+        BLTC_DEGREE_CASES(X)
+#undef X
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pack_sources(int64_t ns, const double* x, const double* y, const double* z,
+                               const double* q, double4* out, hipStream_t s)
+{
+    if (ns == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(pack_sources, dim3(static_cast<unsigned>((ns + 255) / 256)), dim3(256), 0,
+                       s, ns, x, y, z, q, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct(int64_t nt, const double* tx, const double* ty, const double* tz,
+                         int64_t ns, const double4* src, const KernelParams& kp, double* phi,
+                         hipStream_t s)
+{
+    if (nt == 0)
+        return hipSuccess;
+    const dim3 grid(static_cast<unsigned>((nt + 255) / 256));
+    if (kp.kernel == 1)
+        hipLaunchKernelGGL(direct_f64<1>, grid, dim3(256), 0, s, nt, tx, ty, tz, ns, src, phi,
+                           kp.kappa);
+    else
+        hipLaunchKernelGGL(direct_f64<0>, grid, dim3(256), 0, s, nt, tx, ty, tz, ns, src, phi,
+                           kp.kappa);
+    return hipGetLastError();
+}
+
+}  // namespace bltc

@@ -1,0 +1,68 @@
+// kernels.hpp -- launch wrappers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bltc {
+
+constexpr int kMaxDegree = 16;
+constexpr int kGroupSize = 256;      // targets (lanes) per interaction workgroup
+constexpr int kUpwardTile = 128;     // sources staged per LDS tile in the upward pass
+
+// Device-side view of a plan (all device pointers).
+struct DevicePlan {
+    int32_t degree = 0;
+    int64_t nt = 0, ns = 0, nslots = 0, nchunks = 0, ngroups = 0, nbatches = 0;
+    // sources in tree order: x, y, z, charge of the current vector
+    double4* src = nullptr;
+    // targets in batch order: x, y, z, unused
+    double4* tgt = nullptr;
+    int64_t* tgt_orig = nullptr;      // caller index of each batch position
+    const int64_t* src_order = nullptr; // caller index of each tree position
+    // FP32 local copies (mixed precision): sources relative to their leaf center
+    float4* src32 = nullptr;          // x', y', z', q
+    double* leaf_center = nullptr;    // [nodes][3] (indexed by source node id)
+    // lists
+    int32_t* group_batch = nullptr;
+    int64_t* group_first = nullptr;
+    int64_t* batch_end = nullptr;
+    int32_t* far_off = nullptr;
+    int32_t* far_slot = nullptr;
+    int32_t* near_off = nullptr;
+    int64_t* near_begin = nullptr;
+    int64_t* near_count = nullptr;
+    int32_t* near_leaf = nullptr;
+    // upward pass
+    double* slot_nodes = nullptr;     // [slot][3][n+1]
+    int32_t* chunk_slot = nullptr;
+    int64_t* chunk_begin = nullptr;
+    int64_t* chunk_count = nullptr;
+    int32_t* slot_chunk_off = nullptr;
+    double* partial = nullptr;        // [chunk][P]
+    double* qhat = nullptr;           // [slot][P]
+    float* qhat32 = nullptr;          // [slot][P] (mixed precision)
+};
+
+struct KernelParams {
+    int32_t kernel = 0;     // 0 Coulomb, 1 Yukawa
+    int32_t precision = 0;  // 0 FP64, 1 FP32-mixed
+    double kappa = 0.0;
+};
+
+// src[j].w = q[order[j]]  for j < ns (a0: charges into tree order)
+hipError_t launch_gather_charges(const DevicePlan& d, const double* q, hipStream_t s);
+// upward pass: eqs. 14-15 per chunk, then the per-cluster reduction
+hipError_t launch_upward(const DevicePlan& d, hipStream_t s);
+// batch/cluster interactions: eqs. 9 and 11, phi written in caller order
+hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* phi,
+                           hipStream_t s);
+// GPU direct sum (eq. 1) of all targets against packed sources
+hipError_t launch_pack_sources(int64_t ns, const double* x, const double* y, const double* z,
+                               const double* q, double4* out, hipStream_t s);
+hipError_t launch_direct(int64_t nt, const double* tx, const double* ty, const double* tz,
+                         int64_t ns, const double4* src, const KernelParams& kp, double* phi,
+                         hipStream_t s);
+
+}  // namespace bltc

@@ -1,0 +1,351 @@
+// planner.cpp -- host planning of the treecode (Sec. II-D, Alg. 1, eq. 13).
+//
+// Tree rules (Sec. II-D, Sec. III-A).  Where the paper is silent the same
+// readings as the library's documentation apply:
+//  * every node keeps the minimal bounding box of its own particles; its
+//    center is the box midpoint (lo + hi)/2 and its radius half the diagonal;
+//  * a node is a leaf when it holds <= cap particles or its box is a point;
+//  * otherwise dimension l is split at the midpoint iff 2 L_l^2 >= L_max^2
+//    (aspect-ratio rule: 8, 4 or 2 children); a coordinate equal to the
+//    midpoint goes to the upper child; empty children are dropped; a split
+//    that leaves every particle in one child makes the node a leaf.
+// MAC (eq. 13): geometric part r_B + r_C < theta * R with
+// R = sqrt(dx*dx + dy*dy + dz*dz), size part (n+1)^3 < N_C, both strict.
+// Alg. 1 branch order: geometric failure recurses into the children of a
+// non-leaf cluster (direct sum at a leaf); a size-only failure is a direct sum
+// over the whole cluster.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+#include <thread>
+
+namespace bltc {
+namespace {
+
+template <class F>
+void parallel_for(int64_t n, F&& f)
+{
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t nthr = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 1, 16));
+    if (n < 64 || nthr == 1) {
+        for (int64_t i = 0; i < n; ++i)
+            f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    std::atomic_int64_t next{0};
+    for (int64_t t = 0; t < nthr; ++t)
+        th.emplace_back([&]() {
+            for (;;) {
+                int64_t i = next.fetch_add(16);
+                if (i >= n)
+                    break;
+                int64_t e = std::min<int64_t>(n, i + 16);
+                for (; i < e; ++i)
+                    f(i);
+            }
+        });
+    for (auto& t : th)
+        t.join();
+}
+
+int32_t push_node(Tree& t, int64_t begin, int64_t count, int32_t level, int32_t parent)
+{
+    t.begin.push_back(begin);
+    t.count.push_back(count);
+    for (int l = 0; l < 3; ++l) {
+        t.lo.push_back(0.0);
+        t.hi.push_back(0.0);
+        t.center.push_back(0.0);
+    }
+    t.radius.push_back(0.0);
+    t.first_child.push_back(-1);
+    t.nchild.push_back(0);
+    t.level.push_back(level);
+    t.parent.push_back(parent);
+    return static_cast<int32_t>(t.begin.size() - 1);
+}
+
+}  // namespace
+
+void build_tree(Tree& t, int64_t n, const double* x, const double* y, const double* z,
+                int64_t cap)
+{
+    t = Tree();
+    t.n = n;
+    t.order.resize(n);
+    std::iota(t.order.begin(), t.order.end(), int64_t(0));
+    t.x.assign(x, x + n);
+    t.y.assign(y, y + n);
+    t.z.assign(z, z + n);
+    if (n == 0)
+        return;
+    push_node(t, 0, n, 0, -1);
+
+    std::vector<uint8_t> code;
+    std::vector<int64_t> tmp_o;
+    std::vector<double> tmp_x, tmp_y, tmp_z;
+    // breadth-first: node ids grow as children are appended
+    for (int64_t id = 0; id < t.nodes(); ++id) {
+        const int64_t b = t.begin[id], c = t.count[id];
+        double lo[3] = {t.x[b], t.y[b], t.z[b]};
+        double hi[3] = {t.x[b], t.y[b], t.z[b]};
+        for (int64_t p = b + 1; p < b + c; ++p) {
+            const double v[3] = {t.x[p], t.y[p], t.z[p]};
+            for (int l = 0; l < 3; ++l) {
+                lo[l] = std::min(lo[l], v[l]);
+                hi[l] = std::max(hi[l], v[l]);
+            }
+        }
+        double L[3], ctr[3];
+        for (int l = 0; l < 3; ++l) {
+            t.lo[3 * id + l] = lo[l];
+            t.hi[3 * id + l] = hi[l];
+            ctr[l] = (lo[l] + hi[l]) / 2.0;
+            t.center[3 * id + l] = ctr[l];
+            L[l] = hi[l] - lo[l];
+        }
+        t.radius[id] = 0.5 * std::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
+        t.depth = std::max(t.depth, t.level[id]);
+        const double Lmax = std::max(L[0], std::max(L[1], L[2]));
+        if (c <= cap || Lmax == 0.0)
+            continue;
+        bool split[3];
+        for (int l = 0; l < 3; ++l)
+            split[l] = (2.0 * L[l] * L[l] >= Lmax * Lmax);
+
+        code.resize(c);
+        int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t p = 0; p < c; ++p) {
+            uint8_t k = 0;
+            if (split[0] && t.x[b + p] >= ctr[0]) k |= 1;
+            if (split[1] && t.y[b + p] >= ctr[1]) k |= 2;
+            if (split[2] && t.z[b + p] >= ctr[2]) k |= 4;
+            code[p] = k;
+            ++cnt[k];
+        }
+        int nonempty = 0;
+        for (int k = 0; k < 8; ++k)
+            nonempty += cnt[k] > 0;
+        if (nonempty < 2)
+            continue;
+        // stable counting sort of the node's range by child code
+        int64_t off[8];
+        int64_t run = 0;
+        for (int k = 0; k < 8; ++k) {
+            off[k] = run;
+            run += cnt[k];
+        }
+        tmp_o.resize(c);
+        tmp_x.resize(c);
+        tmp_y.resize(c);
+        tmp_z.resize(c);
+        for (int64_t p = 0; p < c; ++p) {
+            const int64_t d = off[code[p]]++;
+            tmp_o[d] = t.order[b + p];
+            tmp_x[d] = t.x[b + p];
+            tmp_y[d] = t.y[b + p];
+            tmp_z[d] = t.z[b + p];
+        }
+        std::copy(tmp_o.begin(), tmp_o.begin() + c, t.order.begin() + b);
+        std::copy(tmp_x.begin(), tmp_x.begin() + c, t.x.begin() + b);
+        std::copy(tmp_y.begin(), tmp_y.begin() + c, t.y.begin() + b);
+        std::copy(tmp_z.begin(), tmp_z.begin() + c, t.z.begin() + b);
+
+        const int32_t first = static_cast<int32_t>(t.nodes());
+        int64_t start = b;
+        int32_t nk = 0;
+        for (int k = 0; k < 8; ++k) {
+            if (cnt[k] == 0)
+                continue;
+            push_node(t, start, cnt[k], t.level[id] + 1, static_cast<int32_t>(id));
+            start += cnt[k];
+            ++nk;
+        }
+        t.first_child[id] = first;
+        t.nchild[id] = nk;
+    }
+}
+
+std::string make_plan(HostPlan& hp, const PlanParams& prm,
+                      int64_t nt, const double* tx, const double* ty, const double* tz,
+                      int64_t ns, const double* sx, const double* sy, const double* sz)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    hp = HostPlan();
+    hp.prm = prm;
+    hp.np = prm.degree + 1;
+    hp.P = static_cast<int64_t>(hp.np) * hp.np * hp.np;
+    const int32_t np = hp.np;
+
+    build_tree(hp.src, ns, sx, sy, sz, prm.leaf_size);
+    if (nt == ns && tx == sx && ty == sy && tz == sz && prm.batch_size == prm.leaf_size)
+        hp.tgt = hp.src;    // same particles, same capacity: identical partition
+    else
+        build_tree(hp.tgt, nt, tx, ty, tz, prm.batch_size);
+
+    const Tree& S = hp.src;
+    const Tree& T = hp.tgt;
+    // batches: leaves of the target tree, ordered by their first position
+    for (int64_t id = 0; id < T.nodes(); ++id)
+        if (T.nchild[id] == 0)
+            hp.batch_node.push_back(static_cast<int32_t>(id));
+    std::sort(hp.batch_node.begin(), hp.batch_node.end(),
+              [&](int32_t a, int32_t b) { return T.begin[a] < T.begin[b]; });
+    const int64_t nb = static_cast<int64_t>(hp.batch_node.size());
+    hp.batch_begin.resize(nb);
+    hp.batch_count.resize(nb);
+    for (int64_t b = 0; b < nb; ++b) {
+        hp.batch_begin[b] = T.begin[hp.batch_node[b]];
+        hp.batch_count[b] = T.count[hp.batch_node[b]];
+        for (int l = 0; l < 3; ++l) {
+            hp.batch_lo.push_back(T.lo[3 * hp.batch_node[b] + l]);
+            hp.batch_hi.push_back(T.hi[3 * hp.batch_node[b] + l]);
+        }
+    }
+    for (int64_t id = 0; id < S.nodes(); ++id)
+        hp.leaves += S.nchild[id] == 0;
+
+    // ---- interaction lists (Alg. 1), one traversal per batch --------------
+    std::vector<std::vector<int32_t>> approx(nb), direct(nb);
+    if (ns > 0) {
+        parallel_for(nb, [&](int64_t b) {
+            const int32_t bn = hp.batch_node[b];
+            const double cb[3] = {T.center[3 * bn], T.center[3 * bn + 1], T.center[3 * bn + 2]};
+            const double rb = T.radius[bn];
+            std::vector<int32_t> stack;
+            stack.push_back(0);
+            while (!stack.empty()) {
+                const int32_t c = stack.back();
+                stack.pop_back();
+                const double dx = cb[0] - S.center[3 * c];
+                const double dy = cb[1] - S.center[3 * c + 1];
+                const double dz = cb[2] - S.center[3 * c + 2];
+                const double R = std::sqrt(dx * dx + dy * dy + dz * dz);
+                const bool geometric = rb + S.radius[c] < prm.theta * R;
+                const bool size = hp.P < S.count[c];
+                if (geometric && size) {
+                    approx[b].push_back(c);
+                } else if (!geometric) {
+                    if (S.nchild[c] == 0) {
+                        direct[b].push_back(c);
+                    } else {
+                        for (int32_t k = S.nchild[c] - 1; k >= 0; --k)
+                            stack.push_back(S.first_child[c] + k);
+                    }
+                } else {
+                    direct[b].push_back(c);
+                }
+            }
+        });
+    }
+
+    // ---- slots: clusters that need modified charges ------------------------
+    hp.cluster_slot.assign(S.nodes(), -1);
+    for (int64_t b = 0; b < nb; ++b)
+        for (int32_t c : approx[b])
+            hp.cluster_slot[c] = 0;
+    for (int64_t c = 0; c < S.nodes(); ++c)
+        if (hp.cluster_slot[c] == 0) {
+            hp.cluster_slot[c] = static_cast<int32_t>(hp.slot_cluster.size());
+            hp.slot_cluster.push_back(static_cast<int32_t>(c));
+        }
+    const int64_t nslots = static_cast<int64_t>(hp.slot_cluster.size());
+    hp.slot_nodes.resize(nslots * 3 * np);
+    for (int64_t s = 0; s < nslots; ++s) {
+        const int32_t c = hp.slot_cluster[s];
+        for (int l = 0; l < 3; ++l) {
+            const double a = S.lo[3 * c + l], bb = S.hi[3 * c + l];
+            const double mid = (a + bb) / 2.0;
+            const double h = (bb - a) / 2.0;
+            for (int32_t k = 0; k < np; ++k)
+                hp.slot_nodes[(s * 3 + l) * np + k] =
+                    mid + h * std::cos(M_PI * static_cast<double>(k) / static_cast<double>(prm.degree));
+        }
+    }
+
+    // ---- flattened lists ----------------------------------------------------
+    hp.far_off.assign(nb + 1, 0);
+    hp.near_off.assign(nb + 1, 0);
+    hp.batch_cost.assign(nb, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t nbt = hp.batch_count[b];
+        for (int32_t c : approx[b]) {
+            hp.item_batch.push_back(static_cast<int32_t>(b));
+            hp.item_cluster.push_back(c);
+            hp.item_kind.push_back(0);
+            hp.far_slot.push_back(hp.cluster_slot[c]);
+            hp.far_evals += nbt * hp.P;
+            hp.batch_cost[b] += hp.P;
+        }
+        for (int32_t c : direct[b]) {
+            hp.item_batch.push_back(static_cast<int32_t>(b));
+            hp.item_cluster.push_back(c);
+            hp.item_kind.push_back(1);
+            hp.near_evals += nbt * S.count[c];
+            hp.batch_cost[b] += S.count[c];
+            // expand into the leaves below c (c itself when it is a leaf)
+            std::vector<int32_t> st{c};
+            std::vector<int32_t> leaves;
+            while (!st.empty()) {
+                const int32_t u = st.back();
+                st.pop_back();
+                if (S.nchild[u] == 0) {
+                    leaves.push_back(u);
+                } else {
+                    for (int32_t k = S.nchild[u] - 1; k >= 0; --k)
+                        st.push_back(S.first_child[u] + k);
+                }
+            }
+            for (int32_t u : leaves) {
+                hp.near_leaf.push_back(u);
+                hp.near_begin.push_back(S.begin[u]);
+                hp.near_count.push_back(S.count[u]);
+            }
+        }
+        hp.approx_pairs += static_cast<int64_t>(approx[b].size());
+        hp.direct_pairs += static_cast<int64_t>(direct[b].size());
+        hp.far_off[b + 1] = static_cast<int32_t>(hp.far_slot.size());
+        hp.near_off[b + 1] = static_cast<int32_t>(hp.near_begin.size());
+    }
+
+    // ---- upward-pass chunks ----------------------------------------------------
+    hp.slot_chunk_off.assign(nslots + 1, 0);
+    for (int64_t s = 0; s < nslots; ++s) {
+        const int32_t c = hp.slot_cluster[s];
+        hp.upward_terms += S.count[c] * hp.P;
+        for (int64_t off = 0; off < S.count[c]; off += prm.chunk_size) {
+            hp.chunk_slot.push_back(static_cast<int32_t>(s));
+            hp.chunk_begin.push_back(S.begin[c] + off);
+            hp.chunk_count.push_back(std::min<int64_t>(prm.chunk_size, S.count[c] - off));
+        }
+        hp.slot_chunk_off[s + 1] = static_cast<int32_t>(hp.chunk_slot.size());
+    }
+
+    // ---- interaction workgroups, heaviest batches first ------------------------
+    std::vector<int32_t> border(nb);
+    std::iota(border.begin(), border.end(), 0);
+    std::stable_sort(border.begin(), border.end(),
+                     [&](int32_t a, int32_t b) { return hp.batch_cost[a] > hp.batch_cost[b]; });
+    for (int32_t b : border)
+        for (int64_t f = 0; f < hp.batch_count[b]; f += prm.group_size) {
+            hp.group_batch.push_back(b);
+            hp.group_first.push_back(hp.batch_begin[b] + f);
+        }
+
+    hp.leaf_of_pos.assign(ns, -1);
+    for (int64_t id = 0; id < S.nodes(); ++id)
+        if (S.nchild[id] == 0)
+            for (int64_t p = S.begin[id]; p < S.begin[id] + S.count[id]; ++p)
+                hp.leaf_of_pos[p] = static_cast<int32_t>(id);
+
+    hp.setup_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return std::string();
+}
+
+}  // namespace bltc

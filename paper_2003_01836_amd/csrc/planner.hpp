@@ -1,0 +1,93 @@
+// planner.hpp -- host-side planning for the treecode: source tree, target
+// batches, interaction lists (Alg. 1, Sec. II-D, MAC eq. 13) and the flat work
+// arrays the GPU kernels consume.  Pure C++ (no HIP), compiled without FP
+// contraction so that every geometric decision follows its formula exactly.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace bltc {
+
+// Cluster tree over one point set.  Nodes are numbered breadth first; the
+// children of a node are consecutive.  Particles are stored contiguously per
+// node ("tree order").
+struct Tree {
+    int64_t n = 0;
+    std::vector<int64_t> order;          // original index of tree position p
+    std::vector<double> x, y, z;         // coordinates in tree order
+    std::vector<int64_t> begin, count;   // per node
+    std::vector<double> lo, hi;          // per node, 3 each: minimal bounding box
+    std::vector<double> center;          // per node, 3 each: box midpoint
+    std::vector<double> radius;          // per node: half the box diagonal
+    std::vector<int32_t> first_child, nchild, level, parent;
+    int32_t depth = 0;
+    int64_t nodes() const { return static_cast<int64_t>(begin.size()); }
+};
+
+struct PlanParams {
+    double theta = 0.7;
+    int32_t degree = 8;
+    int64_t leaf_size = 2000;
+    int64_t batch_size = 2000;
+    int32_t group_size = 256;       // targets per GPU workgroup
+    int64_t chunk_size = 1024;      // sources per upward-pass chunk
+};
+
+struct HostPlan {
+    PlanParams prm;
+    int32_t np = 0;                 // n + 1
+    int64_t P = 0;                  // (n + 1)^3
+    Tree src, tgt;
+
+    // batches = leaves of the target tree, in tree (depth-first) order
+    std::vector<int32_t> batch_node;
+    std::vector<int64_t> batch_begin, batch_count;
+    std::vector<double> batch_lo, batch_hi;   // [3] per batch: minimal box
+
+    // interaction items as found by the traversal (for inspection)
+    std::vector<int32_t> item_batch, item_cluster, item_kind;
+
+    // far field: per batch, the slots of its approximated clusters
+    std::vector<int32_t> far_off, far_slot;
+    // near field: per batch, leaf source ranges
+    std::vector<int32_t> near_off, near_leaf;
+    std::vector<int64_t> near_begin, near_count;
+
+    // clusters that need modified charges ("slots")
+    std::vector<int32_t> slot_cluster;   // cluster id of each slot
+    std::vector<int32_t> cluster_slot;   // slot of each cluster or -1
+    std::vector<double> slot_nodes;      // [slot][3][np] Chebyshev points
+
+    // upward-pass chunks: contiguous source ranges of one slot each
+    std::vector<int32_t> chunk_slot;
+    std::vector<int64_t> chunk_begin, chunk_count;
+    std::vector<int32_t> slot_chunk_off; // [nslots + 1]
+
+    // interaction workgroups: (batch, first target position), heaviest first
+    std::vector<int32_t> group_batch;
+    std::vector<int64_t> group_first;
+    std::vector<int64_t> batch_cost;     // kernel evaluations per target of each batch
+
+    // leaf centers (for local coordinates of the mixed-precision path)
+    std::vector<int32_t> leaf_of_pos;    // source leaf id of each tree position
+
+    // statistics
+    int64_t approx_pairs = 0, direct_pairs = 0;
+    int64_t far_evals = 0, near_evals = 0, upward_terms = 0;
+    int64_t leaves = 0;
+    double setup_seconds = 0.0;
+};
+
+// Builds the tree with leaf capacity `cap` (readings of the tree rules are
+// documented in planner.cpp).
+void build_tree(Tree& t, int64_t n, const double* x, const double* y, const double* z,
+                int64_t cap);
+
+// Full host plan.  Returns an empty string on success or an error message.
+std::string make_plan(HostPlan& hp, const PlanParams& prm,
+                      int64_t nt, const double* tx, const double* ty, const double* tz,
+                      int64_t ns, const double* sx, const double* sy, const double* sz);
+
+}  // namespace bltc

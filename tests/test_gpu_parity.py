@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+FP64 path bar: the library and the oracle evaluate the same tree, batches and
+lists (structural parity is tested on the host), so they differ only in the
+order of rounding (two-step modified charges of eqs. 14-15 versus eq. 12;
+refined hardware 1/sqrt versus sqrt and divide).  Per-element differences are
+bounded relative to the largest potential: max|d| <= 1e-12 * max|phi|, and the
+relative 2-norm difference (eq. 16) <= 1e-13.  These bounds are far inside the
+1e-6 relative-L2 target.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_01836_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL_MAX = 1e-12
+REL_L2 = 1e-13
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2003_01836_amd as bltc
+    bltc.version()   # fails loudly if the HIP library is missing
+    return torch.device("cuda:0")
+
+
+def _dev_soa(pos, dev):
+    return torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
+
+
+def _close(ref, got, rel_max=REL_MAX, rel_l2=REL_L2):
+    ref = np.asarray(ref)
+    got = np.asarray(got)
+    scale = np.max(np.abs(ref)) if ref.size else 1.0
+    assert np.all(np.isfinite(got))
+    assert np.max(np.abs(ref - got)) <= rel_max * max(scale, 1e-300), np.max(np.abs(ref - got)) / scale
+    assert oracle.rel_l2(ref, got) <= rel_l2
+
+
+def _run_plan(dev, tgt, src, q, **kw):
+    import paper_2003_01836_amd as bltc
+    t = _dev_soa(tgt, dev)
+    s = t if src is tgt else _dev_soa(src, dev)
+    qd = torch.from_numpy(np.ascontiguousarray(q)).to(dev)
+    plan = bltc.Plan(t, s, max_q=(q.shape[0] if q.ndim == 2 else 1), **kw)
+    phi = plan.execute(qd)
+    torch.cuda.synchronize()
+    return plan, phi.cpu().numpy()
+
+
+@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+def test_gpu_direct_sum_matches_oracle(dev, kernel, kappa):
+    import paper_2003_01836_amd as bltc
+    pos, q = inputs.uniform_cube(3001, 71)
+    t = _dev_soa(pos, dev)
+    phi = bltc.direct(t, t, torch.from_numpy(q[0]).to(dev), kernel=kernel, kappa=kappa)
+    ref = oracle.direct(pos, pos, q[0], kernel=oracle.YUKAWA if kernel == "yukawa" else 0, kappa=kappa)
+    _close(ref, phi.cpu().numpy(), 1e-13, 1e-14)
+
+
+@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+def test_fp64_treecode_small_config(dev, kernel, kappa):
+    # N = 10^4 uniform cube, theta 0.7, n = 4, N_L = N_B = 500 (several tiles, ragged batches)
+    pos, q = inputs.uniform_cube(10000, inputs.config_seed(0))
+    plan, phi = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=4, leaf_size=500, batch_size=500,
+                          kernel=kernel, kappa=kappa)
+    oc = oracle.Treecode(pos, pos, 0.7, 4, 500, 500)
+    kern = oracle.YUKAWA if kernel == "yukawa" else oracle.COULOMB
+    ref = oc.potential(q[0], kernel=kern, kappa=kappa)
+    _close(ref, phi)
+    # the method error itself (eq. 16) is the oracle's
+    d = oracle.direct(pos, pos, q[0], kernel=kern, kappa=kappa)
+    assert abs(oracle.rel_l2(d, phi) - oracle.rel_l2(d, ref)) <= 1e-3 * oracle.rel_l2(d, ref)
+
+
+def test_fp64_modified_charges_match_oracle(dev):
+    pos, q = inputs.uniform_cube(20000, 72)
+    plan, _ = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=5, leaf_size=300, batch_size=300)
+    oc = oracle.Treecode(pos, pos, 0.7, 5, 300, 300)
+    v = plan.view()
+    okey = {}
+    oorder = oc.source_order()
+    for c in range(oc.n_clusters):
+        info = oc.cluster(c)
+        okey[tuple(np.sort(oorder[info["begin"]:info["begin"] + info["count"]]))] = c
+    checked = 0
+    for c in np.unique(v["item_cluster"][v["item_kind"] == 0]):
+        key = tuple(np.sort(v["source_order"][v["cluster_begin"][c]:v["cluster_begin"][c] + v["cluster_count"][c]]))
+        ref = oc.modified_charges(okey[key], q[0])
+        got = plan.modified_charges(c)
+        assert np.max(np.abs(ref - got)) <= 1e-12 * np.max(np.abs(ref)), c
+        checked += 1
+    assert checked > 10
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 6, 8, 11, 16])
+def test_fp64_all_degrees(dev, degree):
+    pos, q = inputs.uniform_cube(6000, 80 + degree)
+    leaf = max(64, min(1500, (degree + 1) ** 3 + 50))
+    _, phi = _run_plan(dev, pos, pos, q[0], theta=0.8, degree=degree, leaf_size=leaf, batch_size=leaf)
+    ref = oracle.Treecode(pos, pos, 0.8, degree, leaf, leaf).potential(q[0])
+    _close(ref, phi)
+
+
+def test_fp64_distinct_targets_and_sources(dev):
+    g = np.random.default_rng(9)
+    src = g.uniform(-1, 1, (12000, 3))
+    tgt = g.uniform(-0.3, 1.4, (7001, 3))
+    q = g.uniform(-1, 1, 12000)
+    _, phi = _run_plan(dev, tgt, src, q, theta=0.6, degree=6, leaf_size=400, batch_size=333)
+    ref = oracle.Treecode(tgt, src, 0.6, 6, 400, 333).potential(q)
+    _close(ref, phi)
+
+
+def test_fp64_plummer_yukawa(dev):
+    pos, q = inputs.plummer_sphere(30000, 73)
+    _, phi = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=6, leaf_size=400, batch_size=400,
+                       kernel="yukawa", kappa=0.5)
+    ref = oracle.Treecode(pos, pos, 0.7, 6, 400, 400).potential(q[0], kernel=oracle.YUKAWA, kappa=0.5)
+    _close(ref, phi)
+
+
+def test_fp64_theta_zero_is_direct_sum(dev):
+    pos, q = inputs.uniform_cube(4000, 74)
+    _, phi = _run_plan(dev, pos, pos, q[0], theta=0.0, degree=4, leaf_size=100, batch_size=100)
+    _close(oracle.direct(pos, pos, q[0]), phi)
+
+
+def test_fp64_multiple_charge_vectors(dev):
+    pos, q = inputs.uniform_cube(8000, 75, m=3)
+    _, phi = _run_plan(dev, pos, pos, q, theta=0.7, degree=4, leaf_size=300, batch_size=300)
+    oc = oracle.Treecode(pos, pos, 0.7, 4, 300, 300)
+    ref = oc.potential(q)
+    for m in range(3):
+        _close(ref[m], phi[m])
+
+
+def test_fp64_repeatable_bitwise(dev):
+    import paper_2003_01836_amd as bltc
+    pos, q = inputs.uniform_cube(20000, 76)
+    t = _dev_soa(pos, dev)
+    qd = torch.from_numpy(q[0]).to(dev)
+    plan = bltc.Plan(t, t, theta=0.7, degree=6, leaf_size=500, batch_size=500)
+    a = plan.execute(qd).cpu().numpy()
+    b = plan.execute(qd).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_edge_cases(dev):
+    import paper_2003_01836_amd as bltc
+    pos, q = inputs.uniform_cube(500, 77)
+    t = _dev_soa(pos, dev)
+    qd = torch.from_numpy(q[0]).to(dev)
+    empty = torch.zeros((3, 0), dtype=torch.float64, device=dev)
+    # no sources: potentials are zero
+    phi = bltc.potential(t, empty, torch.zeros(0, dtype=torch.float64, device=dev))
+    assert phi.shape == (500,) and torch.all(phi == 0)
+    # no targets: nothing to do
+    phi = bltc.potential(empty, t, qd)
+    assert phi.shape == (0,)
+    # one particle: its own potential is zero (self pair skipped)
+    one = t[:, :1].contiguous()
+    phi = bltc.potential(one, one, qd[:1].contiguous())
+    assert phi.item() == 0.0
+    # identical particles: every pair at zero distance
+    same = torch.full((3, 300), 0.25, dtype=torch.float64, device=dev)
+    phi = bltc.potential(same, same, torch.ones(300, dtype=torch.float64, device=dev), leaf_size=10,
+                         batch_size=10)
+    assert torch.all(phi == 0)
+    # duplicates among distinct points
+    dup = np.concatenate([pos, pos[:50]])
+    qq = np.concatenate([q[0], q[0][:50]])
+    phi = bltc.potential(_dev_soa(dup, dev), _dev_soa(dup, dev), torch.from_numpy(qq).to(dev),
+                         theta=0.5, degree=2, leaf_size=40, batch_size=40)
+    ref = oracle.Treecode(dup, dup, 0.5, 2, 40, 40).potential(qq)
+    _close(ref, phi.cpu().numpy())
+
+
+def test_invalid_arguments_on_device(dev):
+    import paper_2003_01836_amd as bltc
+    pos, q = inputs.uniform_cube(100, 78)
+    t = _dev_soa(pos, dev)
+    bad = t.clone()
+    bad[0, 5] = float("nan")
+    with pytest.raises(bltc.InvalidArgument):
+        bltc.Plan(bad, bad)
+    plan = bltc.Plan(t, t, max_q=1)
+    with pytest.raises(bltc.InvalidArgument):
+        plan.execute(torch.zeros((2, 100), dtype=torch.float64, device=dev))
+
+
+def test_fp64_full_size_sampled(dev):
+    # the benchmark workload: N = 10^6 uniform cube, theta 0.7, n = 8, N_L = N_B = 2000;
+    # the oracle evaluates 1000 sampled targets through their own batches
+    n = 1_000_000
+    pos, q = inputs.uniform_cube(n, inputs.config_seed(1))
+    smp = inputs.sample_indices(n, 1000, inputs.sample_seed(1))
+    _, phi = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=8, leaf_size=2000, batch_size=2000)
+    ref = oracle.Treecode(pos, pos, 0.7, 8, 2000, 2000).potential(q[0], sample=smp)
+    _close(ref, phi[smp])
