@@ -58,8 +58,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="uniform-1M", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed", "both"])
-    ap.add_argument("--cpu-sample", type=int, default=20000,
+    ap.add_argument("--precision", default="both", choices=["fp64", "fp32_mixed", "both"])
+    ap.add_argument("--cpu-sample", type=int, default=150000,
                     help="targets the CPU oracle evaluates for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (no errors, no CPU baseline)")
     args = ap.parse_args()

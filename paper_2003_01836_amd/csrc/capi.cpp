@@ -59,8 +59,6 @@ int check_params(const bltc_params* p)
         return fail(BLTC_EINVAL, "degree must be in 1..%d", bltc::kMaxDegree);
     if (p->leaf_size < 1 || p->batch_size < 1)
         return fail(BLTC_EINVAL, "leaf_size and batch_size must be >= 1");
-    if (p->precision == BLTC_FP32_MIXED)
-        return fail(BLTC_EUNSUPPORTED, "FP32-mixed precision is not available in this build");
     if (p->threads_per_target < 0 || p->threads_per_target > 1)
         return fail(BLTC_EUNSUPPORTED, "threads_per_target must be 0 or 1");
     return BLTC_OK;
@@ -201,6 +199,32 @@ int upload_plan(bltc_plan* plan, hipStream_t s)
     HIP_TRY(plan->put(&d.slot_chunk_off, hp.slot_chunk_off, s));
     HIP_TRY(plan->alloc(&d.partial, static_cast<size_t>(d.nchunks) * hp.P));
     HIP_TRY(plan->alloc(&d.qhat, static_cast<size_t>(d.nslots) * hp.P * plan->max_q));
+    if (plan->prm.precision == BLTC_FP32_MIXED) {
+        // sources relative to the center of their leaf, per-node and per-batch boxes
+        const int64_t nn = hp.src.nodes();
+        std::vector<double4> node_info(nn);
+        for (int64_t c = 0; c < nn; ++c)
+            node_info[c] = make_double4(hp.src.center[3 * c], hp.src.center[3 * c + 1],
+                                        hp.src.center[3 * c + 2], hp.src.radius[c]);
+        std::vector<float4> src32(d.ns);
+        for (int64_t j = 0; j < d.ns; ++j) {
+            const double4 c = node_info[hp.leaf_of_pos[j]];
+            src32[j] = make_float4(static_cast<float>(hp.src.x[j] - c.x),
+                                   static_cast<float>(hp.src.y[j] - c.y),
+                                   static_cast<float>(hp.src.z[j] - c.z), 0.0f);
+        }
+        std::vector<double4> batch_info(d.nbatches);
+        for (int64_t b = 0; b < d.nbatches; ++b) {
+            const int32_t bn = hp.batch_node[b];
+            batch_info[b] = make_double4(hp.tgt.center[3 * bn], hp.tgt.center[3 * bn + 1],
+                                         hp.tgt.center[3 * bn + 2], hp.tgt.radius[bn]);
+        }
+        HIP_TRY(plan->put(&d.src32, src32, s));
+        HIP_TRY(plan->put(&d.node_info, node_info, s));
+        HIP_TRY(plan->put(&d.batch_info, batch_info, s));
+        HIP_TRY(plan->alloc(&d.qhat32, static_cast<size_t>(d.nslots) * hp.P * plan->max_q));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     // host staging vectors die at return: finish the copies first
     HIP_TRY(hipStreamSynchronize(s));
     plan->uploaded = true;
@@ -259,12 +283,18 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
     };
     for (int32_t m = 0; m < num_q; ++m) {
         d.qhat = plan->d.qhat + static_cast<int64_t>(m) * d.nslots * hp.P;
+        if (plan->d.qhat32)
+            d.qhat32 = plan->d.qhat32 + static_cast<int64_t>(m) * d.nslots * hp.P;
         HIP_TRY(mark(m, 0));
         HIP_TRY(bltc::launch_gather_charges(d, q + static_cast<int64_t>(m) * q_ld, s));
         HIP_TRY(mark(m, 1));
         HIP_TRY(bltc::launch_upward(d, s));
         HIP_TRY(mark(m, 2));
-        HIP_TRY(bltc::launch_interact(d, kp, phi + static_cast<int64_t>(m) * phi_ld, s));
+        double* phi_m = phi + static_cast<int64_t>(m) * phi_ld;
+        if (kp.precision == BLTC_FP32_MIXED)
+            HIP_TRY(bltc::launch_interact_mixed(d, kp, phi_m, s));
+        else
+            HIP_TRY(bltc::launch_interact(d, kp, phi_m, s));
         HIP_TRY(mark(m, 3));
     }
     plan->timed_q = plan->timing ? num_q : 0;

@@ -1,0 +1,100 @@
+// device_common.hpp -- FP64 device helpers shared by the kernel files:
+// reciprocal square roots, the kernels G of eq. 2, and the direct
+// batch/cluster sum of eq. 9 over a wave-uniform source range.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bltc {
+namespace dev {
+
+// ---------------------------------------------------------------------------
+// FP64 reciprocal square root from the hardware estimate y0 (v_rsq_f64,
+// relative error about 2^-24), refined with e = 1 - r2*y0^2:
+//  * third-order Householder step y = y0 (1 + e/2 + 3e^2/8): truncation term
+//    5e^3/16, so the result is correct to rounding (direct sums, eq. 9);
+//  * second-order (Newton) step y = y0 (1 + e/2): truncation term 3e^2/8,
+//    a few 1e-15 relative, used for the proxy-point sums of eq. 11 whose own
+//    approximation error is many orders larger.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rsqrt_refine3(double r2, double y)
+{
+    const double t = r2 * y;
+    const double e = __fma_rn(-t, y, 1.0);
+    const double p = __fma_rn(0.375, e, 0.5);
+    const double s = y * e;
+    return __fma_rn(s, p, y);
+}
+
+__device__ __forceinline__ double rsqrt_f64(double r2)
+{
+    return rsqrt_refine3(r2, __builtin_amdgcn_rsq(r2));
+}
+
+__device__ __forceinline__ double rsqrt_f64_newton(double r2)
+{
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double t = r2 * y;
+    const double e = __fma_rn(-t, y, 1.0);
+    return __fma_rn(y * e, 0.5, y);
+}
+
+// Estimate of 1/sqrt(r2) that is exactly +0 when r2 == 0: the estimate of 0 is
+// +inf, whose low word is zero, so clearing the high word yields +0 and the
+// refinement then returns 0.  Pairs at zero distance thus contribute nothing.
+__device__ __forceinline__ double rsqrt_f64_or_zero(double r2)
+{
+    const double y = __builtin_amdgcn_rsq(r2);
+    const int lo = __double2loint(y);
+    const int hi = r2 > 0.0 ? __double2hiint(y) : 0;
+    return rsqrt_refine3(r2, __hiloint2double(hi, lo));
+}
+
+// G as a function of r^2 and 1/r (eq. 2).
+template <int KER>
+__device__ __forceinline__ double green_f64(double r2, double rinv, double kappa)
+{
+    if constexpr (KER == 0) {
+        return rinv;
+    } else {
+        return exp(-kappa * (r2 * rinv)) * rinv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Direct batch/cluster sum over a contiguous source range (eq. 9), pairs at
+// zero distance skipped.  `s` is wave-uniform.
+// ---------------------------------------------------------------------------
+template <int KER>
+__device__ __forceinline__ double near_term_f64(double x, double y, double z, const double4 p,
+                                                double kappa)
+{
+    const double dx = x - p.x;
+    const double dy = y - p.y;
+    const double dz = z - p.z;
+    const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+    return green_f64<KER>(r2, rsqrt_f64_or_zero(r2), kappa) * p.w;
+}
+
+template <int KER>
+__device__ __forceinline__ double near_sum_f64(double x, double y, double z,
+                                               const double4* __restrict__ s, int32_t cnt,
+                                               double kappa)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int32_t j = 0;
+    for (; j + 4 <= cnt; j += 4) {
+        a0 += near_term_f64<KER>(x, y, z, s[j], kappa);
+        a1 += near_term_f64<KER>(x, y, z, s[j + 1], kappa);
+        a2 += near_term_f64<KER>(x, y, z, s[j + 2], kappa);
+        a3 += near_term_f64<KER>(x, y, z, s[j + 3], kappa);
+    }
+    for (; j < cnt; ++j)
+        a0 += near_term_f64<KER>(x, y, z, s[j], kappa);
+    return (a0 + a1) + (a2 + a3);
+}
+
+}  // namespace dev
+}  // namespace bltc

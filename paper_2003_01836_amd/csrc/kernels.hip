@@ -13,72 +13,14 @@
 //    over grid points accumulate eq. 15; a second kernel sums the chunks of
 //    each cluster in a fixed order (deterministic).
 #include "kernels.hpp"
+#include "device_common.hpp"
 
 #include <cfloat>
 
 namespace bltc {
 namespace {
 
-// ---------------------------------------------------------------------------
-// FP64 reciprocal square root: the hardware estimate (v_rsq_f64) refined by
-// one third-order Householder step for x^{-1/2}: with e = 1 - r2*y0^2,
-// y = y0 * (1 + e/2 + 3e^2/8).  The truncation term is 5e^3/16, far below the
-// FP64 rounding unit for the estimate's accuracy.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double rsqrt_f64(double r2)
-{
-    const double y = __builtin_amdgcn_rsq(r2);
-    const double t = r2 * y;
-    const double e = __fma_rn(-t, y, 1.0);
-    const double p = __fma_rn(0.375, e, 0.5);
-    const double s = y * e;
-    return __fma_rn(s, p, y);
-}
-
-// G as a function of r^2 and 1/r (eq. 2).
-template <int KER>
-__device__ __forceinline__ double green_f64(double r2, double rinv, double kappa)
-{
-    if constexpr (KER == 0) {
-        return rinv;
-    } else {
-        return exp(-kappa * (r2 * rinv)) * rinv;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Direct batch/cluster sum over a contiguous source range (eq. 9), pairs at
-// zero distance skipped.  `s` is wave-uniform.
-// ---------------------------------------------------------------------------
-template <int KER>
-__device__ __forceinline__ double near_term_f64(double x, double y, double z, const double4 p,
-                                                double kappa)
-{
-    const double dx = x - p.x;
-    const double dy = y - p.y;
-    const double dz = z - p.z;
-    const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-    const double g = green_f64<KER>(r2, rsqrt_f64(r2), kappa);
-    return (r2 > 0.0 ? g : 0.0) * p.w;
-}
-
-template <int KER>
-__device__ __forceinline__ double near_sum_f64(double x, double y, double z,
-                                               const double4* __restrict__ s, int64_t cnt,
-                                               double kappa)
-{
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int64_t j = 0;
-    for (; j + 4 <= cnt; j += 4) {
-        a0 += near_term_f64<KER>(x, y, z, s[j], kappa);
-        a1 += near_term_f64<KER>(x, y, z, s[j + 1], kappa);
-        a2 += near_term_f64<KER>(x, y, z, s[j + 2], kappa);
-        a3 += near_term_f64<KER>(x, y, z, s[j + 3], kappa);
-    }
-    for (; j < cnt; ++j)
-        a0 += near_term_f64<KER>(x, y, z, s[j], kappa);
-    return (a0 + a1) + (a2 + a3);
-}
+using namespace dev;
 
 // ---------------------------------------------------------------------------
 // Batch/cluster approximation (eq. 11): sum_k G(x, s_k) qhat_k over the
@@ -112,7 +54,7 @@ __device__ __forceinline__ double far_sum_f64(double x, double y, double z,
 #pragma unroll
             for (int k3 = 0; k3 < NP; ++k3) {
                 const double r2 = ab + c2[k3];
-                const double g = green_f64<KER>(r2, rsqrt_f64(r2), kappa);
+                const double g = green_f64<KER>(r2, rsqrt_f64_newton(r2), kappa);
                 if ((k2 + k3) & 1)
                     acc1 = __fma_rn(g, q1[k2 * NP + k3], acc1);
                 else
@@ -160,7 +102,8 @@ __global__ __launch_bounds__(kGroupSize) void interact_f64(
     }
     const int n_end = near_off[b + 1];
     for (int e = near_off[b]; e < n_end; ++e)
-        acc += near_sum_f64<KER>(t.x, t.y, t.z, src + near_begin[e], near_count[e], kappa);
+        acc += near_sum_f64<KER>(t.x, t.y, t.z, src + near_begin[e],
+                                 static_cast<int32_t>(near_count[e]), kappa);
 
     if (valid)
         phi[tgt_orig[i]] = acc;
@@ -275,7 +218,8 @@ __global__ __launch_bounds__(256) void upward_partial_f64(
 
 __global__ __launch_bounds__(256) void upward_reduce_f64(const int32_t* __restrict__ slot_chunk_off,
                                                          const double* __restrict__ partial,
-                                                         double* __restrict__ qhat, int64_t nslots,
+                                                         double* __restrict__ qhat,
+                                                         float* __restrict__ qhat32, int64_t nslots,
                                                          int32_t P)
 {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -287,15 +231,22 @@ __global__ __launch_bounds__(256) void upward_reduce_f64(const int32_t* __restri
     for (int32_t c = slot_chunk_off[slot]; c < slot_chunk_off[slot + 1]; ++c)
         s += partial[static_cast<int64_t>(c) * P + k];
     qhat[idx] = s;
+    if (qhat32)
+        qhat32[idx] = static_cast<float>(s);
 }
 
 __global__ __launch_bounds__(256) void gather_charges(double4* __restrict__ src,
+                                                      float4* __restrict__ src32,
                                                       const int64_t* __restrict__ order,
                                                       const double* __restrict__ q, int64_t ns)
 {
     const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (j < ns)
-        src[j].w = q[order[j]];
+    if (j < ns) {
+        const double v = q[order[j]];
+        src[j].w = v;
+        if (src32)
+            src32[j].w = static_cast<float>(v);
+    }
 }
 
 __global__ __launch_bounds__(256) void pack_sources(int64_t ns, const double* __restrict__ x,
@@ -323,7 +274,12 @@ __global__ __launch_bounds__(256) void direct_f64(int64_t nt, const double* __re
     const bool valid = i < nt;
     if (!valid)
         i = nt - 1;
-    const double acc = near_sum_f64<KER>(tx[i], ty[i], tz[i], src, ns, kappa);
+    double acc = 0.0;
+    for (int64_t j0 = 0; j0 < ns; j0 += (int64_t(1) << 30)) {
+        const int64_t left = ns - j0;
+        const int32_t cnt = static_cast<int32_t>(left < (int64_t(1) << 30) ? left : (int64_t(1) << 30));
+        acc += near_sum_f64<KER>(tx[i], ty[i], tz[i], src + j0, cnt, kappa);
+    }
     if (valid)
         phi[i] = acc;
 }
@@ -359,7 +315,7 @@ hipError_t run_upward(const DevicePlan& d, hipStream_t s)
         return e;
     const int64_t total = d.nslots * P;
     hipLaunchKernelGGL(upward_reduce_f64, dim3(static_cast<unsigned>((total + 255) / 256)),
-                       dim3(256), 0, s, d.slot_chunk_off, d.partial, d.qhat, d.nslots,
+                       dim3(256), 0, s, d.slot_chunk_off, d.partial, d.qhat, d.qhat32, d.nslots,
                        static_cast<int32_t>(P));
     return hipGetLastError();
 }
@@ -374,7 +330,7 @@ hipError_t launch_gather_charges(const DevicePlan& d, const double* q, hipStream
     if (d.ns == 0)
         return hipSuccess;
     hipLaunchKernelGGL(gather_charges, dim3(static_cast<unsigned>((d.ns + 255) / 256)), dim3(256),
-                       0, s, d.src, d.src_order, q, d.ns);
+                       0, s, d.src, d.src32, d.src_order, q, d.ns);
     return hipGetLastError();
 }
 

@@ -21,9 +21,10 @@ struct DevicePlan {
     double4* tgt = nullptr;
     int64_t* tgt_orig = nullptr;      // caller index of each batch position
     const int64_t* src_order = nullptr; // caller index of each tree position
-    // FP32 local copies (mixed precision): sources relative to their leaf center
-    float4* src32 = nullptr;          // x', y', z', q
-    double* leaf_center = nullptr;    // [nodes][3] (indexed by source node id)
+    // FP32-mixed path: sources relative to the center of their leaf
+    float4* src32 = nullptr;          // x - c_x, y - c_y, z - c_z, q (tree order)
+    double4* node_info = nullptr;     // per source node: box center, radius
+    double4* batch_info = nullptr;    // per batch: box center, radius
     // lists
     int32_t* group_batch = nullptr;
     int64_t* group_first = nullptr;
@@ -51,13 +52,16 @@ struct KernelParams {
     double kappa = 0.0;
 };
 
-// src[j].w = q[order[j]]  for j < ns (a0: charges into tree order)
+// src[j].w = q[order[j]] (and src32[j].w when present), j < ns: charges into tree order
 hipError_t launch_gather_charges(const DevicePlan& d, const double* q, hipStream_t s);
 // upward pass: eqs. 14-15 per chunk, then the per-cluster reduction
 hipError_t launch_upward(const DevicePlan& d, hipStream_t s);
 // batch/cluster interactions: eqs. 9 and 11, phi written in caller order
 hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* phi,
                            hipStream_t s);
+// the same in FP32-mixed arithmetic (kernels_mixed.hip)
+hipError_t launch_interact_mixed(const DevicePlan& d, const KernelParams& kp, double* phi,
+                                 hipStream_t s);
 // GPU direct sum (eq. 1) of all targets against packed sources
 hipError_t launch_pack_sources(int64_t ns, const double* x, const double* y, const double* z,
                                const double* q, double4* out, hipStream_t s);

@@ -1,0 +1,238 @@
+// kernels_mixed.hip -- FP32-mixed batch/cluster interactions (eqs. 9 and 11).
+//
+// Same mapping as the FP64 kernel (one target per lane, wave-uniform lists and
+// sources through the scalar cache), with the kernel evaluations in FP32:
+//  * direct sums (eq. 9) use local coordinates: sources are stored relative to
+//    the center of their leaf; each lane forms its target's offset from that
+//    center once per batch/leaf pair, in FP64, and rounds it to FP32, so the
+//    FP32 differences carry relative rounding errors of the local extent,
+//    not of the domain;
+//  * pairs closer than tau = kTauRel * (local extent) -- this includes pairs at
+//    zero distance -- take an FP64 branch (exact coordinates, FP64 kernel), so
+//    the coordinate rounding never exceeds about 2^-24 / kTauRel = 1e-5 of a
+//    term;
+//  * approximations (eq. 11) use FP32 squared 1-D distances (formed in FP64,
+//    rounded once per target and pair) and FP32 modified charges;
+//  * FP32 partial sums cover at most kFlushEvery sources or (n+1)^2 proxy
+//    points before they are added to the lane's FP64 accumulator.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace bltc {
+namespace {
+
+using namespace dev;
+
+constexpr double kTauRel = 6.0e-3;
+constexpr int kFlushEvery = 128;
+
+template <int KER>
+__device__ __forceinline__ float green_f32(float r2, float rinv, float neg_kappa_log2e)
+{
+    if constexpr (KER == 0) {
+        return rinv;
+    } else {
+        return __builtin_amdgcn_exp2f(neg_kappa_log2e * (r2 * rinv)) * rinv;
+    }
+}
+
+// FP32 kernel value of one source for a lane's local target coordinates.
+template <int KER>
+__device__ __forceinline__ float near_value_f32(float x, float y, float z, const float4 p,
+                                                float nk, float& r2)
+{
+    const float dx = x - p.x;
+    const float dy = y - p.y;
+    const float dz = z - p.z;
+    r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+    return green_f32<KER>(r2, __builtin_amdgcn_rsqf(r2), nk);
+}
+
+// Sources [j, j+4): FP32 values; if any of them is closer than tau (rare, one
+// branch per 4 sources), those terms are redone in FP64 into `acc` and their
+// FP32 values are zeroed.
+template <int KER>
+__device__ __forceinline__ void near_quad_mixed(float x, float y, float z,
+                                                const float4* __restrict__ s32,
+                                                const double4* __restrict__ s64, float tau2,
+                                                float nk, double xt, double yt, double zt,
+                                                double kappa, double& acc, float& a0, float& a1,
+                                                float& a2, float& a3)
+{
+    const float4 p0 = s32[0], p1 = s32[1], p2 = s32[2], p3 = s32[3];
+    float r0, r1, r2, r3;
+    float g0 = near_value_f32<KER>(x, y, z, p0, nk, r0);
+    float g1 = near_value_f32<KER>(x, y, z, p1, nk, r1);
+    float g2 = near_value_f32<KER>(x, y, z, p2, nk, r2);
+    float g3 = near_value_f32<KER>(x, y, z, p3, nk, r3);
+    if (fminf(fminf(r0, r1), fminf(r2, r3)) < tau2) {
+        if (r0 < tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[0], kappa); g0 = 0.0f; }
+        if (r1 < tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[1], kappa); g1 = 0.0f; }
+        if (r2 < tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[2], kappa); g2 = 0.0f; }
+        if (r3 < tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[3], kappa); g3 = 0.0f; }
+    }
+    a0 = __fmaf_rn(g0, p0.w, a0);
+    a1 = __fmaf_rn(g1, p1.w, a1);
+    a2 = __fmaf_rn(g2, p2.w, a2);
+    a3 = __fmaf_rn(g3, p3.w, a3);
+}
+
+template <int KER>
+__device__ __forceinline__ double near_sum_mixed(double xt, double yt, double zt,
+                                                 const float4* __restrict__ s32,
+                                                 const double4* __restrict__ s64, int32_t cnt,
+                                                 const double4 leaf, float tau2, float nk,
+                                                 double kappa)
+{
+    const float x = static_cast<float>(xt - leaf.x);
+    const float y = static_cast<float>(yt - leaf.y);
+    const float z = static_cast<float>(zt - leaf.z);
+    double acc = 0.0;
+    for (int32_t j0 = 0; j0 < cnt; j0 += kFlushEvery) {
+        const int32_t j1 = (cnt - j0 < kFlushEvery) ? cnt : j0 + kFlushEvery;
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+        int32_t j = j0;
+        for (; j + 4 <= j1; j += 4)
+            near_quad_mixed<KER>(x, y, z, s32 + j, s64 + j, tau2, nk, xt, yt, zt, kappa, acc, a0,
+                                 a1, a2, a3);
+        for (; j < j1; ++j) {
+            float r;
+            float g = near_value_f32<KER>(x, y, z, s32[j], nk, r);
+            if (r < tau2) {
+                acc += near_term_f64<KER>(xt, yt, zt, s64[j], kappa);
+                g = 0.0f;
+            }
+            a0 = __fmaf_rn(g, s32[j].w, a0);
+        }
+        acc += static_cast<double>((a0 + a1) + (a2 + a3));
+    }
+    return acc;
+}
+
+template <int N, int KER>
+__device__ __forceinline__ double far_sum_mixed(double xt, double yt, double zt,
+                                                const double* __restrict__ nd,
+                                                const float* __restrict__ qh, float nk)
+{
+    constexpr int NP = N + 1;
+    float b2[NP], c2[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const float dy = static_cast<float>(yt - nd[NP + k]);
+        const float dz = static_cast<float>(zt - nd[2 * NP + k]);
+        b2[k] = dy * dy;
+        c2[k] = dz * dz;
+    }
+    double acc = 0.0;
+#pragma unroll 1
+    for (int k1 = 0; k1 < NP; ++k1) {
+        const float dx = static_cast<float>(xt - nd[k1]);
+        const float a2 = dx * dx;
+        const float* __restrict__ q1 = qh + k1 * NP * NP;
+        float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+        for (int k2 = 0; k2 < NP; ++k2) {
+            const float ab = a2 + b2[k2];
+#pragma unroll
+            for (int k3 = 0; k3 < NP; ++k3) {
+                const float r2 = ab + c2[k3];
+                const float g = green_f32<KER>(r2, __builtin_amdgcn_rsqf(r2), nk);
+                if ((k2 + k3) & 1)
+                    s1 = __fmaf_rn(g, q1[k2 * NP + k3], s1);
+                else
+                    s0 = __fmaf_rn(g, q1[k2 * NP + k3], s0);
+            }
+        }
+        acc += static_cast<double>(s0 + s1);
+    }
+    return acc;
+}
+
+template <int N, int KER>
+__global__ __launch_bounds__(kGroupSize) void interact_mixed(
+    const double4* __restrict__ tgt, const int64_t* __restrict__ tgt_orig,
+    const double4* __restrict__ src, const float4* __restrict__ src32,
+    const double4* __restrict__ node_info, const double4* __restrict__ batch_info,
+    const int32_t* __restrict__ group_batch, const int64_t* __restrict__ group_first,
+    const int64_t* __restrict__ batch_end, const int32_t* __restrict__ far_off,
+    const int32_t* __restrict__ far_slot, const int32_t* __restrict__ near_off,
+    const int64_t* __restrict__ near_begin, const int64_t* __restrict__ near_count,
+    const int32_t* __restrict__ near_leaf, const double* __restrict__ slot_nodes,
+    const float* __restrict__ qhat32, double* __restrict__ phi, double kappa)
+{
+    constexpr int NP = N + 1;
+    constexpr int P = NP * NP * NP;
+    const int g = blockIdx.x;
+    const int b = group_batch[g];
+    const int64_t first = group_first[g];
+    const int64_t end = batch_end[b];
+    const int64_t wave_first = first + (threadIdx.x & ~63);
+    if (wave_first >= end)
+        return;  // the whole wave lies past the batch end
+    int64_t i = first + threadIdx.x;
+    const bool valid = i < end;
+    if (!valid)
+        i = end - 1;
+    const double4 t = tgt[i];
+    const float nk = static_cast<float>(-kappa * 1.4426950408889634);
+    double acc = 0.0;
+
+    const int f_end = far_off[b + 1];
+    for (int f = far_off[b]; f < f_end; ++f) {
+        const int64_t slot = far_slot[f];
+        acc += far_sum_mixed<N, KER>(t.x, t.y, t.z, slot_nodes + slot * 3 * NP,
+                                     qhat32 + slot * P, nk);
+    }
+    const double4 bi = batch_info[b];
+    const int n_end = near_off[b + 1];
+    for (int e = near_off[b]; e < n_end; ++e) {
+        const double4 li = node_info[near_leaf[e]];
+        const double dx = bi.x - li.x, dy = bi.y - li.y, dz = bi.z - li.z;
+        const double extent = sqrt(dx * dx + dy * dy + dz * dz) + bi.w + 2.0 * li.w;
+        const double tau = kTauRel * extent;
+        const float tau2 = static_cast<float>(tau * tau);
+        const int64_t nb = near_begin[e];
+        acc += near_sum_mixed<KER>(t.x, t.y, t.z, src32 + nb, src + nb,
+                                   static_cast<int32_t>(near_count[e]), li, tau2, nk, kappa);
+    }
+    if (valid)
+        phi[tgt_orig[i]] = acc;
+}
+
+template <int N, int KER>
+hipError_t run_interact_mixed(const DevicePlan& d, double* phi, double kappa, hipStream_t s)
+{
+    if (d.ngroups == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL((interact_mixed<N, KER>), dim3(static_cast<unsigned>(d.ngroups)),
+                       dim3(kGroupSize), 0, s, d.tgt, d.tgt_orig, d.src, d.src32, d.node_info,
+                       d.batch_info, d.group_batch, d.group_first, d.batch_end, d.far_off,
+                       d.far_slot, d.near_off, d.near_begin, d.near_count, d.near_leaf,
+                       d.slot_nodes, d.qhat32, phi, kappa);
+    return hipGetLastError();
+}
+
+#define BLTC_DEGREE_CASES(X) \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+}  // namespace
+
+hipError_t launch_interact_mixed(const DevicePlan& d, const KernelParams& kp, double* phi,
+                                 hipStream_t s)
+{
+    if (!d.src32 || !d.node_info || !d.batch_info || !d.qhat32)
+        return hipErrorInvalidValue;
+    const bool yuk = kp.kernel == 1;
+    switch (d.degree) {
+#define X(n)                                                                   \
+    case n:                                                                    \
+        return yuk ? run_interact_mixed<n, 1>(d, phi, kp.kappa, s)             \
+                   : run_interact_mixed<n, 0>(d, phi, kp.kappa, s);
+        BLTC_DEGREE_CASES(X)
+#undef X
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace bltc

@@ -204,3 +204,84 @@ def test_fp64_full_size_sampled(dev):
     _, phi = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=8, leaf_size=2000, batch_size=2000)
     ref = oracle.Treecode(pos, pos, 0.7, 8, 2000, 2000).potential(q[0], sample=smp)
     _close(ref, phi[smp])
+
+
+# --------------------------------------------------------------------------
+# FP32-mixed path: relative 2-norm error against the FP64 oracle <= 1e-6
+# --------------------------------------------------------------------------
+MIXED_REL_L2 = 1e-6
+
+
+@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+def test_mixed_small_config(dev, kernel, kappa):
+    pos, q = inputs.uniform_cube(10000, inputs.config_seed(0))
+    _, phi = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=4, leaf_size=500, batch_size=500,
+                       kernel=kernel, kappa=kappa, precision="fp32_mixed")
+    kern = oracle.YUKAWA if kernel == "yukawa" else oracle.COULOMB
+    ref = oracle.Treecode(pos, pos, 0.7, 4, 500, 500).potential(q[0], kernel=kern, kappa=kappa)
+    assert oracle.rel_l2(ref, phi) <= MIXED_REL_L2
+    d = oracle.direct(pos, pos, q[0], kernel=kern, kappa=kappa)
+    # equal accuracy: the treecode error is not made worse by the FP32 arithmetic
+    assert oracle.rel_l2(d, phi) <= 1.1 * oracle.rel_l2(d, ref)
+
+
+@pytest.mark.parametrize("degree", [1, 4, 8, 12, 16])
+def test_mixed_all_degrees(dev, degree):
+    pos, q = inputs.uniform_cube(6000, 90 + degree)
+    leaf = max(64, min(1500, (degree + 1) ** 3 + 50))
+    _, phi = _run_plan(dev, pos, pos, q[0], theta=0.8, degree=degree, leaf_size=leaf,
+                       batch_size=leaf, precision="fp32_mixed")
+    ref = oracle.Treecode(pos, pos, 0.8, degree, leaf, leaf).potential(q[0])
+    assert oracle.rel_l2(ref, phi) <= MIXED_REL_L2
+
+
+def test_mixed_planted_close_pairs(dev):
+    # pairs at separations 1e-7 .. 1e-3 and exact duplicates take the FP64 branch
+    g = np.random.default_rng(12)
+    base, q = inputs.uniform_cube(20000, 91)
+    k = 400
+    offs = g.standard_normal((k, 3))
+    offs *= (10.0 ** g.uniform(-7, -3, k) / np.linalg.norm(offs, axis=1))[:, None]
+    pos = np.concatenate([base, base[:k] + offs, base[k:k + 50]])
+    qq = np.concatenate([q[0], g.uniform(-1, 1, k + 50)])
+    _, phi = _run_plan(dev, pos, pos, qq, theta=0.7, degree=6, leaf_size=600, batch_size=600,
+                       precision="fp32_mixed")
+    ref = oracle.Treecode(pos, pos, 0.7, 6, 600, 600).potential(qq)
+    assert oracle.rel_l2(ref, phi) <= MIXED_REL_L2
+    close = np.arange(len(base) - 0, len(base) + k)
+    # the planted targets themselves, where the close terms dominate
+    assert oracle.rel_l2(ref[close], phi[close]) <= MIXED_REL_L2
+
+
+def test_mixed_plummer_yukawa(dev):
+    pos, q = inputs.plummer_sphere(30000, 93)
+    _, phi = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=6, leaf_size=400, batch_size=400,
+                       kernel="yukawa", kappa=0.5, precision="fp32_mixed")
+    ref = oracle.Treecode(pos, pos, 0.7, 6, 400, 400).potential(q[0], kernel=oracle.YUKAWA, kappa=0.5)
+    assert oracle.rel_l2(ref, phi) <= MIXED_REL_L2
+
+
+def test_mixed_distinct_targets_and_multiple_vectors(dev):
+    g = np.random.default_rng(19)
+    src = g.uniform(-1, 1, (12000, 3))
+    tgt = g.uniform(-0.3, 1.4, (7001, 3))
+    q = g.uniform(-1, 1, (2, 12000))
+    _, phi = _run_plan(dev, tgt, src, q, theta=0.6, degree=6, leaf_size=400, batch_size=333,
+                       precision="fp32_mixed")
+    ref = oracle.Treecode(tgt, src, 0.6, 6, 400, 333).potential(q)
+    for m in range(2):
+        assert oracle.rel_l2(ref[m], phi[m]) <= MIXED_REL_L2
+
+
+def test_mixed_full_size_sampled_and_full_n_vs_fp64(dev):
+    # the benchmark workload; FP32-mixed against the oracle on 1000 sampled targets, and
+    # against the GPU FP64 path (itself parity-checked above) on all 10^6 targets
+    n = 1_000_000
+    pos, q = inputs.uniform_cube(n, inputs.config_seed(1))
+    smp = inputs.sample_indices(n, 1000, inputs.sample_seed(1))
+    _, mixed = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=8, leaf_size=2000, batch_size=2000,
+                         precision="fp32_mixed")
+    _, full = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=8, leaf_size=2000, batch_size=2000)
+    ref = oracle.Treecode(pos, pos, 0.7, 8, 2000, 2000).potential(q[0], sample=smp)
+    assert oracle.rel_l2(ref, mixed[smp]) <= MIXED_REL_L2
+    assert oracle.rel_l2(full, mixed) <= MIXED_REL_L2
