@@ -7,8 +7,10 @@
 //    center once per batch/leaf pair, in FP64, and rounds it to FP32, so the
 //    FP32 differences carry relative rounding errors of the local extent,
 //    not of the domain;
-//  * pairs closer than tau = kTauRel * (local extent) -- this includes pairs at
-//    zero distance -- take an FP64 branch (exact coordinates, FP64 kernel), so
+//  * pairs with r^2 <= tau^2, tau = kTauRel * (local extent) -- this includes
+//    pairs at zero distance even when the extent is zero (a one-particle batch
+//    against its own one-particle leaf) -- take an FP64 branch (exact
+//    coordinates, FP64 kernel), so
 //    the coordinate rounding never exceeds about 2^-24 / kTauRel = 1e-5 of a
 //    term;
 //  * approximations (eq. 11) use FP32 squared 1-D distances (formed in FP64,
@@ -65,11 +67,11 @@ __device__ __forceinline__ void near_quad_mixed(float x, float y, float z,
     float g1 = near_value_f32<KER>(x, y, z, p1, nk, r1);
     float g2 = near_value_f32<KER>(x, y, z, p2, nk, r2);
     float g3 = near_value_f32<KER>(x, y, z, p3, nk, r3);
-    if (fminf(fminf(r0, r1), fminf(r2, r3)) < tau2) {
-        if (r0 < tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[0], kappa); g0 = 0.0f; }
-        if (r1 < tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[1], kappa); g1 = 0.0f; }
-        if (r2 < tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[2], kappa); g2 = 0.0f; }
-        if (r3 < tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[3], kappa); g3 = 0.0f; }
+    if (fminf(fminf(r0, r1), fminf(r2, r3)) <= tau2) {
+        if (r0 <= tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[0], kappa); g0 = 0.0f; }
+        if (r1 <= tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[1], kappa); g1 = 0.0f; }
+        if (r2 <= tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[2], kappa); g2 = 0.0f; }
+        if (r3 <= tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[3], kappa); g3 = 0.0f; }
     }
     a0 = __fmaf_rn(g0, p0.w, a0);
     a1 = __fmaf_rn(g1, p1.w, a1);
@@ -98,7 +100,7 @@ __device__ __forceinline__ double near_sum_mixed(double xt, double yt, double zt
         for (; j < j1; ++j) {
             float r;
             float g = near_value_f32<KER>(x, y, z, s32[j], nk, r);
-            if (r < tau2) {
+            if (r <= tau2) {
                 acc += near_term_f64<KER>(xt, yt, zt, s64[j], kappa);
                 g = 0.0f;
             }

@@ -152,8 +152,12 @@ def test_fp64_repeatable_bitwise(dev):
     assert np.array_equal(a, b)
 
 
-def test_edge_cases(dev):
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_edge_cases(dev, precision):
+    import functools
     import paper_2003_01836_amd as bltc
+    bltc_potential = bltc.potential
+    bltc = type("B", (), {"potential": staticmethod(functools.partial(bltc_potential, precision=precision))})
     pos, q = inputs.uniform_cube(500, 77)
     t = _dev_soa(pos, dev)
     qd = torch.from_numpy(q[0]).to(dev)
@@ -179,7 +183,21 @@ def test_edge_cases(dev):
     phi = bltc.potential(_dev_soa(dup, dev), _dev_soa(dup, dev), torch.from_numpy(qq).to(dev),
                          theta=0.5, degree=2, leaf_size=40, batch_size=40)
     ref = oracle.Treecode(dup, dup, 0.5, 2, 40, 40).potential(qq)
-    _close(ref, phi.cpu().numpy())
+    if precision == "fp64":
+        _close(ref, phi.cpu().numpy())
+    else:
+        assert oracle.rel_l2(ref, phi.cpu().numpy()) <= 1e-6
+    # isolated particles: one-particle leaves and batches (zero-extent boxes)
+    g = np.random.default_rng(3)
+    iso = np.concatenate([g.uniform(-1, 1, (300, 3)), g.uniform(-1, 1, (20, 3)) * 50.0])
+    qi = g.uniform(-1, 1, len(iso))
+    ti = _dev_soa(iso, dev)
+    phi = bltc.potential(ti, ti, torch.from_numpy(qi).to(dev), theta=0.7, degree=2, leaf_size=30,
+                         batch_size=30, kernel="yukawa", kappa=0.5)
+    ref = oracle.Treecode(iso, iso, 0.7, 2, 30, 30).potential(qi, kernel=oracle.YUKAWA, kappa=0.5)
+    got = phi.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    assert oracle.rel_l2(ref, got) <= (1e-13 if precision == "fp64" else 1e-6)
 
 
 def test_invalid_arguments_on_device(dev):
