@@ -5,7 +5,7 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libbltc.so")
+LIB_PATH = os.environ.get("BLTC_LIBRARY") or os.path.join(_PKG, "libbltc.so")
 
 BLTC_OK = 0
 BLTC_EINVAL = -1

@@ -53,20 +53,22 @@ def _run_all(cmds):
         raise RuntimeError("build failed:\n" + msg)
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str = BUILD) -> str:
+    """Compiles libbltc.so; `defines` are extra -D flags for the HIP sources."""
+    os.makedirs(build_dir, exist_ok=True)
     hipcc = _hipcc()
+    hip_flags = HIP_FLAGS + ["-D" + d for d in defines]
     objs = {
-        "planner": os.path.join(BUILD, "planner.o"),
-        "kernels": os.path.join(BUILD, "kernels.o"),
-        "mixed": os.path.join(BUILD, "kernels_mixed.o"),
-        "capi": os.path.join(BUILD, "capi.o"),
+        "planner": os.path.join(build_dir, "planner.o"),
+        "kernels": os.path.join(build_dir, "kernels.o"),
+        "mixed": os.path.join(build_dir, "kernels_mixed.o"),
+        "capi": os.path.join(build_dir, "capi.o"),
     }
     cmds = [
         ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
-        [hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", objs["kernels"]],
-        [hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, "kernels_mixed.hip"), "-o", objs["mixed"]],
-        [hipcc] + HIP_FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, "capi.cpp"), "-o", objs["capi"]],
+        [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", objs["kernels"]],
+        [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_mixed.hip"), "-o", objs["mixed"]],
+        [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "capi.cpp"), "-o", objs["capi"]],
     ]
     if not os.path.exists(os.path.join(CSRC, "kernels_mixed.hip")):
         cmds.pop(2)
@@ -75,11 +77,11 @@ def build(verbose: bool = False) -> str:
         for c in cmds:
             print(" ".join(c))
     _run_all(cmds)
-    tmp = LIB + ".tmp"
+    tmp = lib_path + ".tmp"
     link = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + list(objs.values()) + ["-lpthread"]
     _run_all([link])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

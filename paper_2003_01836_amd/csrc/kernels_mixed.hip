@@ -10,9 +10,10 @@
 //  * pairs with r^2 <= tau^2, tau = kTauRel * (local extent) -- this includes
 //    pairs at zero distance even when the extent is zero (a one-particle batch
 //    against its own one-particle leaf) -- take an FP64 branch (exact
-//    coordinates, FP64 kernel), so
-//    the coordinate rounding never exceeds about 2^-24 / kTauRel = 1e-5 of a
-//    term;
+//    coordinates, FP64 kernel), so the coordinate rounding never exceeds
+//    about 2^-24 / kTauRel (a few 1e-6) of a term, and the aggregate
+//    coordinate error, which is dominated by the closest pairs, scales as
+//    kTauRel^-1/2;
 //  * approximations (eq. 11) use FP32 squared 1-D distances (formed in FP64,
 //    rounded once per target and pair) and FP32 modified charges;
 //  * FP32 partial sums cover at most kFlushEvery sources or (n+1)^2 proxy
@@ -25,7 +26,10 @@ namespace {
 
 using namespace dev;
 
-constexpr double kTauRel = 6.0e-3;
+#ifndef BLTC_TAU_REL
+#define BLTC_TAU_REL 2.4e-2
+#endif
+constexpr double kTauRel = BLTC_TAU_REL;
 constexpr int kFlushEvery = 128;
 
 template <int KER>
