@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=150000,
                     help="targets the CPU oracle evaluates for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (no errors, no CPU baseline)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -87,6 +89,15 @@ def main():
     qd = torch.from_numpy(q[0]).to(dev)
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     smp = inputs.sample_indices(n, w["samples"], inputs.sample_seed(w["cfg"]))
+
+    if args.copy_calibration > 0:
+        nel = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(nel, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + written")
+        del a, b
 
     precisions = ["fp64", "fp32_mixed"] if args.precision == "both" else [args.precision]
     results = {}

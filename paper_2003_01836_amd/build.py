@@ -62,17 +62,16 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         "planner": os.path.join(build_dir, "planner.o"),
         "kernels": os.path.join(build_dir, "kernels.o"),
         "mixed": os.path.join(build_dir, "kernels_mixed.o"),
+        "mrhs": os.path.join(build_dir, "kernels_mrhs.o"),
         "capi": os.path.join(build_dir, "capi.o"),
     }
     cmds = [
         ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
         [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", objs["kernels"]],
         [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_mixed.hip"), "-o", objs["mixed"]],
+        [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_mrhs.hip"), "-o", objs["mrhs"]],
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "capi.cpp"), "-o", objs["capi"]],
     ]
-    if not os.path.exists(os.path.join(CSRC, "kernels_mixed.hip")):
-        cmds.pop(2)
-        objs.pop("mixed")
     if verbose:
         for c in cmds:
             print(" ".join(c))

@@ -199,7 +199,17 @@ int upload_plan(bltc_plan* plan, hipStream_t s)
     HIP_TRY(plan->put(&d.slot_chunk_off, hp.slot_chunk_off, s));
     HIP_TRY(plan->alloc(&d.partial, static_cast<size_t>(d.nchunks) * hp.P));
     HIP_TRY(plan->alloc(&d.qhat, static_cast<size_t>(d.nslots) * hp.P * plan->max_q));
-    if (plan->prm.precision == BLTC_FP32_MIXED) {
+    const bool mixed = plan->prm.precision == BLTC_FP32_MIXED;
+    if (plan->max_q > 1) {
+        HIP_TRY(plan->put(&d.slot_cluster, hp.slot_cluster, s));
+        HIP_TRY(plan->alloc(&d.qm, static_cast<size_t>(d.ns) * 16));
+        HIP_TRY(plan->alloc(&d.qhat16, static_cast<size_t>(d.nslots) * hp.P * 16));
+        if (mixed) {
+            HIP_TRY(plan->alloc(&d.qm32, static_cast<size_t>(d.ns) * 16));
+            HIP_TRY(plan->alloc(&d.qhat16f, static_cast<size_t>(d.nslots) * hp.P * 16));
+        }
+    }
+    if (mixed) {
         // sources relative to the center of their leaf, per-node and per-batch boxes
         const int64_t nn = hp.src.nodes();
         std::vector<double4> node_info(nn);
@@ -270,34 +280,54 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
     kp.precision = plan->prm.precision;
     kp.kappa = plan->prm.kappa;
     bltc::DevicePlan d = plan->d;
+    // one charge vector: the scalar-charge kernels; several: passes of up to 16
+    // vectors whose kernel values are shared (matrix-core contraction)
+    const int32_t units = num_q == 1 ? 1 : (num_q + 15) / 16;
     if (plan->timing) {
-        while (static_cast<int32_t>(plan->events.size()) < 4 * num_q) {
+        while (static_cast<int32_t>(plan->events.size()) < 4 * units) {
             hipEvent_t e;
             HIP_TRY(hipEventCreate(&e));
             plan->events.push_back(e);
         }
     }
     plan->timed_q = 0;
-    auto mark = [&](int32_t m, int k) -> hipError_t {
-        return plan->timing ? hipEventRecord(plan->events[4 * m + k], s) : hipSuccess;
+    auto mark = [&](int32_t u, int k) -> hipError_t {
+        return plan->timing ? hipEventRecord(plan->events[4 * u + k], s) : hipSuccess;
     };
-    for (int32_t m = 0; m < num_q; ++m) {
-        d.qhat = plan->d.qhat + static_cast<int64_t>(m) * d.nslots * hp.P;
-        if (plan->d.qhat32)
-            d.qhat32 = plan->d.qhat32 + static_cast<int64_t>(m) * d.nslots * hp.P;
-        HIP_TRY(mark(m, 0));
-        HIP_TRY(bltc::launch_gather_charges(d, q + static_cast<int64_t>(m) * q_ld, s));
-        HIP_TRY(mark(m, 1));
+    const int64_t slice = d.nslots * hp.P;
+    if (num_q == 1) {
+        HIP_TRY(mark(0, 0));
+        HIP_TRY(bltc::launch_gather_charges(d, q, s));
+        HIP_TRY(mark(0, 1));
         HIP_TRY(bltc::launch_upward(d, s));
-        HIP_TRY(mark(m, 2));
-        double* phi_m = phi + static_cast<int64_t>(m) * phi_ld;
+        HIP_TRY(mark(0, 2));
         if (kp.precision == BLTC_FP32_MIXED)
-            HIP_TRY(bltc::launch_interact_mixed(d, kp, phi_m, s));
+            HIP_TRY(bltc::launch_interact_mixed(d, kp, phi, s));
         else
-            HIP_TRY(bltc::launch_interact(d, kp, phi_m, s));
-        HIP_TRY(mark(m, 3));
+            HIP_TRY(bltc::launch_interact(d, kp, phi, s));
+        HIP_TRY(mark(0, 3));
+    } else {
+        for (int32_t u = 0; u < units; ++u) {
+            const int32_t m0 = 16 * u;
+            const int32_t mc = std::min<int32_t>(16, num_q - m0);
+            HIP_TRY(mark(u, 0));
+            HIP_TRY(bltc::launch_gather_charges16(d, q + static_cast<int64_t>(m0) * q_ld, q_ld, mc, s));
+            HIP_TRY(mark(u, 1));
+            for (int32_t m = 0; m < mc; ++m) {
+                d.qhat = plan->d.qhat + static_cast<int64_t>(m) * slice;
+                d.qhat32 = nullptr;
+                HIP_TRY(bltc::launch_gather_charges(d, q + static_cast<int64_t>(m0 + m) * q_ld, s));
+                HIP_TRY(bltc::launch_upward(d, s));
+            }
+            d.qhat = plan->d.qhat;
+            HIP_TRY(bltc::launch_pack_qhat16(d, mc, s));
+            HIP_TRY(mark(u, 2));
+            HIP_TRY(bltc::launch_interact_mrhs(d, kp, phi + static_cast<int64_t>(m0) * phi_ld, phi_ld,
+                                               mc, s));
+            HIP_TRY(mark(u, 3));
+        }
     }
-    plan->timed_q = plan->timing ? num_q : 0;
+    plan->timed_q = plan->timing ? units : 0;
     return BLTC_OK;
 }
 

@@ -82,6 +82,8 @@ __global__ __launch_bounds__(kGroupSize) void interact_f64(
     constexpr int P = NP * NP * NP;
     const int g = blockIdx.x;
     const int b = group_batch[g];
+    if (b < 0)
+        return;  // empty slot of the per-die schedule
     const int64_t first = group_first[g];
     const int64_t end = batch_end[b];
     const int64_t wave_first = first + (threadIdx.x & ~63);

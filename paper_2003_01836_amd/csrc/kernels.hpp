@@ -42,8 +42,14 @@ struct DevicePlan {
     int64_t* chunk_count = nullptr;
     int32_t* slot_chunk_off = nullptr;
     double* partial = nullptr;        // [chunk][P]
-    double* qhat = nullptr;           // [slot][P]
+    double* qhat = nullptr;           // [q][slot][P]
     float* qhat32 = nullptr;          // [slot][P] (mixed precision)
+    // several charge vectors at once (16 per pass)
+    int32_t* slot_cluster = nullptr;  // cluster id of each slot
+    double* qm = nullptr;             // [ns][16] charges in tree order
+    float* qm32 = nullptr;            // [ns][16] (mixed precision)
+    double* qhat16 = nullptr;         // [slot][P][16]
+    float* qhat16f = nullptr;         // [slot][P][16] (mixed precision)
 };
 
 struct KernelParams {
@@ -62,6 +68,15 @@ hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* 
 // the same in FP32-mixed arithmetic (kernels_mixed.hip)
 hipError_t launch_interact_mixed(const DevicePlan& d, const KernelParams& kp, double* phi,
                                  hipStream_t s);
+// several charge vectors (kernels_mrhs.hip): charges of vectors m0..m0+mc-1
+// into qm/qm32 (tree order, zero padded to 16), modified charges of the mc
+// vectors (qhat[m][slot][k]) into qhat16/qhat16f, and the interactions of all
+// mc vectors: phi[m * phi_ld + i], m < mc
+hipError_t launch_gather_charges16(const DevicePlan& d, const double* q, int64_t q_ld, int32_t mc,
+                                   hipStream_t s);
+hipError_t launch_pack_qhat16(const DevicePlan& d, int32_t mc, hipStream_t s);
+hipError_t launch_interact_mrhs(const DevicePlan& d, const KernelParams& kp, double* phi,
+                                int64_t phi_ld, int32_t mc, hipStream_t s);
 // GPU direct sum (eq. 1) of all targets against packed sources
 hipError_t launch_pack_sources(int64_t ns, const double* x, const double* y, const double* z,
                                const double* q, double4* out, hipStream_t s);

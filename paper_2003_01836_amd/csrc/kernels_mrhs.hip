@@ -1,0 +1,403 @@
+// kernels_mrhs.hip -- batch/cluster interactions for up to 16 charge vectors
+// at once (eqs. 9 and 11 with a matrix of charges).
+//
+// The kernel values G(x_i, y_j) do not depend on the charge vector, so a pair
+// is evaluated once and contracted with all right-hand sides on the matrix
+// cores:  Phi[i][m] += sum_j G[i][j] Q[j][m].  A wave owns 64 targets of one
+// batch as four 16-target tiles.  Per step of 4 sources (or proxy points),
+// lane l evaluates G for target row (l % 16) of each tile and source column
+// (l / 16) on the VALU -- exactly the MFMA A-operand layout -- and loads
+// Q[source l/16][rhs l%16] -- the B-operand layout -- so the G tile goes
+// straight from the VALU into v_mfma_*_16x16x4 without any shuffle.  The
+// matrix core runs concurrently with the VALU work of other waves.
+//
+// Result layouts of the 16x16x4 MFMAs on gfx950 (checked on the device):
+//   f64: lane l, register r holds D[4r + l/16][l % 16]
+//   f32: lane l, register r holds D[4(l/16) + r][l % 16]
+// Rows are targets, columns are right-hand sides.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace bltc {
+namespace {
+
+using namespace dev;
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int kRhs = 16;
+constexpr int kMixedFlushSteps = 32;   // FP32 MFMA partial sums cover <= 128 sources
+
+#ifndef BLTC_TAU_REL
+#define BLTC_TAU_REL 2.4e-2
+#endif
+constexpr double kTauRel = BLTC_TAU_REL;
+
+template <int KER>
+__device__ __forceinline__ float green_f32(float r2, float rinv, float neg_kappa_log2e)
+{
+    if constexpr (KER == 0) {
+        return rinv;
+    } else {
+        return __builtin_amdgcn_exp2f(neg_kappa_log2e * (r2 * rinv)) * rinv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64: G in FP64 on the VALU, contraction on v_mfma_f64_16x16x4f64.
+// ---------------------------------------------------------------------------
+template <int KER>
+__global__ __launch_bounds__(kGroupSize) void interact_mrhs_f64(
+    const double4* __restrict__ tgt, const int64_t* __restrict__ tgt_orig,
+    const double4* __restrict__ src, const double* __restrict__ qm,
+    const int32_t* __restrict__ group_batch, const int64_t* __restrict__ group_first,
+    const int64_t* __restrict__ batch_end, const int32_t* __restrict__ far_off,
+    const int32_t* __restrict__ far_slot, const int32_t* __restrict__ near_off,
+    const int64_t* __restrict__ near_begin, const int64_t* __restrict__ near_count,
+    const double* __restrict__ slot_nodes, const double* __restrict__ qhat16, int32_t np,
+    double* __restrict__ phi, int64_t phi_ld, int32_t m_count, double kappa)
+{
+    const int g = blockIdx.x;
+    const int b = group_batch[g];
+    if (b < 0)
+        return;
+    const int64_t first = group_first[g];
+    const int64_t end = batch_end[b];
+    const int64_t wave_first = first + (threadIdx.x & ~63);
+    if (wave_first >= end)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15;
+    const int col = lane >> 4;
+
+    double tx[4], ty[4], tz[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        int64_t i = wave_first + 16 * t + row;
+        i = i < end ? i : end - 1;
+        const double4 v = tgt[i];
+        tx[t] = v.x;
+        ty[t] = v.y;
+        tz[t] = v.z;
+    }
+    d4v acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
+
+    const int P = np * np * np;
+    const int f_end = far_off[b + 1];
+    for (int f = far_off[b]; f < f_end; ++f) {
+        const int64_t slot = far_slot[f];
+        const double* __restrict__ nd = slot_nodes + slot * 3 * np;
+        const double* __restrict__ qh = qhat16 + slot * static_cast<int64_t>(P) * kRhs;
+        for (int k0 = 0; k0 < P; k0 += 4) {
+            const int k = k0 + col;
+            const bool ok = k < P;
+            const int kk = ok ? k : P - 1;
+            const int k1 = kk / (np * np);
+            const int k2 = (kk / np) - k1 * np;
+            const int k3 = kk - (kk / np) * np;
+            const double px = nd[k1], py = nd[np + k2], pz = nd[2 * np + k3];
+            const double bq = ok ? qh[static_cast<int64_t>(kk) * kRhs + row] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double dx = tx[t] - px, dy = ty[t] - py, dz = tz[t] - pz;
+                const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+                const double gv = green_f64<KER>(r2, rsqrt_f64_newton(r2), kappa);
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    const int n_end = near_off[b + 1];
+    for (int e = near_off[b]; e < n_end; ++e) {
+        const int64_t nb = near_begin[e];
+        const int32_t cnt = static_cast<int32_t>(near_count[e]);
+        for (int32_t j0 = 0; j0 < cnt; j0 += 4) {
+            const int32_t j = j0 + col;
+            const bool ok = j < cnt;
+            const int64_t jj = nb + (ok ? j : cnt - 1);
+            const double4 p = src[jj];
+            const double bq = ok ? qm[jj * kRhs + row] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double dx = tx[t] - p.x, dy = ty[t] - p.y, dz = tz[t] - p.z;
+                const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+                const double gv = green_f64<KER>(r2, rsqrt_f64_or_zero(r2), kappa);
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    if (row < m_count) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = wave_first + 16 * t + 4 * r + col;
+                if (i < end)
+                    phi[row * phi_ld + tgt_orig[i]] = acc[t][r];
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32-mixed: G in FP32 on local coordinates (close pairs from FP64
+// coordinates), contraction on v_mfma_f32_16x16x4f32, FP32 partial sums over
+// <= kMixedFlushSteps steps, accumulated per target and right-hand side in FP64.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void flush_f32(f4v (&part)[4], double (&acc)[4][4])
+{
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            acc[t][r] += static_cast<double>(part[t][r]);
+        part[t] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+}
+
+template <int KER>
+__global__ __launch_bounds__(kGroupSize) void interact_mrhs_mixed(
+    const double4* __restrict__ tgt, const int64_t* __restrict__ tgt_orig,
+    const double4* __restrict__ src, const float4* __restrict__ src32,
+    const float* __restrict__ qm32, const double4* __restrict__ node_info,
+    const double4* __restrict__ batch_info, const int32_t* __restrict__ group_batch,
+    const int64_t* __restrict__ group_first, const int64_t* __restrict__ batch_end,
+    const int32_t* __restrict__ far_off, const int32_t* __restrict__ far_slot,
+    const int32_t* __restrict__ near_off, const int64_t* __restrict__ near_begin,
+    const int64_t* __restrict__ near_count, const int32_t* __restrict__ near_leaf,
+    const int32_t* __restrict__ slot_cluster, const double* __restrict__ slot_nodes,
+    const float* __restrict__ qhat16, int32_t np, double* __restrict__ phi, int64_t phi_ld,
+    int32_t m_count, double kappa)
+{
+    const int g = blockIdx.x;
+    const int b = group_batch[g];
+    if (b < 0)
+        return;
+    const int64_t first = group_first[g];
+    const int64_t end = batch_end[b];
+    const int64_t wave_first = first + (threadIdx.x & ~63);
+    if (wave_first >= end)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int row = lane & 15;
+    const int col = lane >> 4;
+    const float nk = static_cast<float>(-kappa * 1.4426950408889634);
+
+    double tx[4], ty[4], tz[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        int64_t i = wave_first + 16 * t + row;
+        i = i < end ? i : end - 1;
+        const double4 v = tgt[i];
+        tx[t] = v.x;
+        ty[t] = v.y;
+        tz[t] = v.z;
+    }
+    double acc[4][4];
+    f4v part[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        part[t] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            acc[t][r] = 0.0;
+    }
+
+    const int P = np * np * np;
+    const int f_end = far_off[b + 1];
+    for (int f = far_off[b]; f < f_end; ++f) {
+        const int64_t slot = far_slot[f];
+        const double4 ci = node_info[slot_cluster[slot]];
+        // targets and proxy points relative to the cluster center
+        float ux[4], uy[4], uz[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            ux[t] = static_cast<float>(tx[t] - ci.x);
+            uy[t] = static_cast<float>(ty[t] - ci.y);
+            uz[t] = static_cast<float>(tz[t] - ci.z);
+        }
+        const double* __restrict__ nd = slot_nodes + slot * 3 * np;
+        const float* __restrict__ qh = qhat16 + slot * static_cast<int64_t>(P) * kRhs;
+        int steps = 0;
+        for (int k0 = 0; k0 < P; k0 += 4) {
+            const int k = k0 + col;
+            const bool ok = k < P;
+            const int kk = ok ? k : P - 1;
+            const int k1 = kk / (np * np);
+            const int k2 = (kk / np) - k1 * np;
+            const int k3 = kk - (kk / np) * np;
+            const float px = static_cast<float>(nd[k1] - ci.x);
+            const float py = static_cast<float>(nd[np + k2] - ci.y);
+            const float pz = static_cast<float>(nd[2 * np + k3] - ci.z);
+            const float bq = ok ? qh[static_cast<int64_t>(kk) * kRhs + row] : 0.0f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float dx = ux[t] - px, dy = uy[t] - py, dz = uz[t] - pz;
+                const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+                const float gv = green_f32<KER>(r2, __builtin_amdgcn_rsqf(r2), nk);
+                part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, bq, part[t], 0, 0, 0);
+            }
+            if (++steps == kMixedFlushSteps) {
+                flush_f32(part, acc);
+                steps = 0;
+            }
+        }
+        flush_f32(part, acc);
+    }
+
+    const double4 bi = batch_info[b];
+    const int n_end = near_off[b + 1];
+    for (int e = near_off[b]; e < n_end; ++e) {
+        const double4 li = node_info[near_leaf[e]];
+        const double ddx = bi.x - li.x, ddy = bi.y - li.y, ddz = bi.z - li.z;
+        const double extent = sqrt(ddx * ddx + ddy * ddy + ddz * ddz) + bi.w + 2.0 * li.w;
+        const double tau = kTauRel * extent;
+        const float tau2 = static_cast<float>(tau * tau);
+        float ux[4], uy[4], uz[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            ux[t] = static_cast<float>(tx[t] - li.x);
+            uy[t] = static_cast<float>(ty[t] - li.y);
+            uz[t] = static_cast<float>(tz[t] - li.z);
+        }
+        const int64_t nb = near_begin[e];
+        const int32_t cnt = static_cast<int32_t>(near_count[e]);
+        int steps = 0;
+        for (int32_t j0 = 0; j0 < cnt; j0 += 4) {
+            const int32_t j = j0 + col;
+            const bool ok = j < cnt;
+            const int64_t jj = nb + (ok ? j : cnt - 1);
+            const float4 p = src32[jj];
+            const float bq = ok ? qm32[jj * kRhs + row] : 0.0f;
+            float gv[4], r2v[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float dx = ux[t] - p.x, dy = uy[t] - p.y, dz = uz[t] - p.z;
+                r2v[t] = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+                gv[t] = green_f32<KER>(r2v[t], __builtin_amdgcn_rsqf(r2v[t]), nk);
+            }
+            if (fminf(fminf(r2v[0], r2v[1]), fminf(r2v[2], r2v[3])) <= tau2) {
+                // close pairs: the kernel value from the exact coordinates, in FP64
+                const double4 p64 = src[jj];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (r2v[t] <= tau2) {
+                        const double dx = tx[t] - p64.x, dy = ty[t] - p64.y, dz = tz[t] - p64.z;
+                        const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+                        gv[t] = static_cast<float>(green_f64<KER>(r2, rsqrt_f64_or_zero(r2), kappa));
+                    }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t], bq, part[t], 0, 0, 0);
+            if (++steps == kMixedFlushSteps) {
+                flush_f32(part, acc);
+                steps = 0;
+            }
+        }
+        flush_f32(part, acc);
+    }
+    if (row < m_count) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = wave_first + 16 * t + 4 * col + r;
+                if (i < end)
+                    phi[row * phi_ld + tgt_orig[i]] = acc[t][r];
+            }
+    }
+}
+
+// charges of up to 16 vectors into tree order, padded with zeros:
+// qm[j][m] = q[(m0 + m) * q_ld + order[j]] for m < mc
+__global__ __launch_bounds__(256) void gather_charges16(double* __restrict__ qm,
+                                                        float* __restrict__ qm32,
+                                                        const int64_t* __restrict__ order,
+                                                        const double* __restrict__ q, int64_t q_ld,
+                                                        int32_t mc, int64_t ns)
+{
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= ns * kRhs)
+        return;
+    const int64_t j = idx / kRhs;
+    const int m = static_cast<int>(idx - j * kRhs);
+    const double v = m < mc ? q[m * q_ld + order[j]] : 0.0;
+    qm[idx] = v;
+    if (qm32)
+        qm32[idx] = static_cast<float>(v);
+}
+
+// qhat16[slot][k][m] = qhat[m][slot][k] for m < mc, zero otherwise
+__global__ __launch_bounds__(256) void pack_qhat16(double* __restrict__ q16,
+                                                   float* __restrict__ q16f,
+                                                   const double* __restrict__ qhat, int64_t nslots,
+                                                   int32_t P, int32_t mc)
+{
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t total = nslots * P * kRhs;
+    if (idx >= total)
+        return;
+    const int64_t sk = idx / kRhs;
+    const int m = static_cast<int>(idx - sk * kRhs);
+    const double v = m < mc ? qhat[static_cast<int64_t>(m) * nslots * P + sk] : 0.0;
+    q16[idx] = v;
+    if (q16f)
+        q16f[idx] = static_cast<float>(v);
+}
+
+}  // namespace
+
+hipError_t launch_gather_charges16(const DevicePlan& d, const double* q, int64_t q_ld, int32_t mc,
+                                   hipStream_t s)
+{
+    if (d.ns == 0)
+        return hipSuccess;
+    const int64_t total = d.ns * kRhs;
+    hipLaunchKernelGGL(gather_charges16, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
+                       0, s, d.qm, d.qm32, d.src_order, q, q_ld, mc, d.ns);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_qhat16(const DevicePlan& d, int32_t mc, hipStream_t s)
+{
+    const int32_t np = d.degree + 1;
+    const int32_t P = np * np * np;
+    const int64_t total = d.nslots * P * kRhs;
+    if (total == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(pack_qhat16, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s,
+                       d.qhat16, d.qhat16f, d.qhat, d.nslots, P, mc);
+    return hipGetLastError();
+}
+
+hipError_t launch_interact_mrhs(const DevicePlan& d, const KernelParams& kp, double* phi,
+                                int64_t phi_ld, int32_t mc, hipStream_t s)
+{
+    if (d.ngroups == 0)
+        return hipSuccess;
+    const int32_t np = d.degree + 1;
+    const dim3 grid(static_cast<unsigned>(d.ngroups)), block(kGroupSize);
+    const bool yuk = kp.kernel == 1;
+    if (kp.precision == 1) {
+        if (!d.src32 || !d.qm32 || !d.qhat16f)
+            return hipErrorInvalidValue;
+        auto k = yuk ? interact_mrhs_mixed<1> : interact_mrhs_mixed<0>;
+        hipLaunchKernelGGL(k, grid, block, 0, s, d.tgt, d.tgt_orig, d.src, d.src32, d.qm32,
+                           d.node_info, d.batch_info, d.group_batch, d.group_first, d.batch_end,
+                           d.far_off, d.far_slot, d.near_off, d.near_begin, d.near_count,
+                           d.near_leaf, d.slot_cluster, d.slot_nodes, d.qhat16f, np, phi, phi_ld,
+                           mc, kp.kappa);
+    } else {
+        auto k = yuk ? interact_mrhs_f64<1> : interact_mrhs_f64<0>;
+        hipLaunchKernelGGL(k, grid, block, 0, s, d.tgt, d.tgt_orig, d.src, d.qm, d.group_batch,
+                           d.group_first, d.batch_end, d.far_off, d.far_slot, d.near_off,
+                           d.near_begin, d.near_count, d.slot_nodes, d.qhat16, np, phi, phi_ld, mc,
+                           kp.kappa);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bltc

@@ -326,16 +326,48 @@ std::string make_plan(HostPlan& hp, const PlanParams& prm,
         hp.slot_chunk_off[s + 1] = static_cast<int32_t>(hp.chunk_slot.size());
     }
 
-    // ---- interaction workgroups, heaviest batches first ------------------------
-    std::vector<int32_t> border(nb);
-    std::iota(border.begin(), border.end(), 0);
-    std::stable_sort(border.begin(), border.end(),
-                     [&](int32_t a, int32_t b) { return hp.batch_cost[a] > hp.batch_cost[b]; });
-    for (int32_t b : border)
-        for (int64_t f = 0; f < hp.batch_count[b]; f += prm.group_size) {
-            hp.group_batch.push_back(b);
-            hp.group_first.push_back(hp.batch_begin[b] + f);
+    // ---- interaction workgroups ------------------------------------------------
+    // Workgroups are dispatched round-robin over the dies (workgroup k on die
+    // k % X), and each die has its own L2.  Batches in tree order are split into
+    // X contiguous segments of equal work (neighbouring batches share most of
+    // their near-field sources), each segment is ordered heaviest batch first,
+    // and the segments are interleaved so that segment x lands on die x.
+    {
+        const int32_t X = std::max(1, prm.xcds);
+        std::vector<double> work(nb);
+        double total = 0.0;
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t ng = (hp.batch_count[b] + prm.group_size - 1) / prm.group_size;
+            work[b] = static_cast<double>(hp.batch_cost[b] + 1) * static_cast<double>(ng);
+            total += work[b];
         }
+        std::vector<std::vector<int32_t>> seg(X);
+        double run_w = 0.0;
+        for (int64_t b = 0; b < nb; ++b) {
+            int32_t x = static_cast<int32_t>(run_w * X / (total > 0.0 ? total : 1.0));
+            x = std::min(x, X - 1);
+            seg[x].push_back(static_cast<int32_t>(b));
+            run_w += work[b];
+        }
+        std::vector<std::vector<std::pair<int32_t, int64_t>>> queue(X);
+        size_t longest = 0;
+        for (int32_t x = 0; x < X; ++x) {
+            std::stable_sort(seg[x].begin(), seg[x].end(), [&](int32_t a, int32_t b) {
+                return hp.batch_cost[a] > hp.batch_cost[b];
+            });
+            for (int32_t b : seg[x])
+                for (int64_t f = 0; f < hp.batch_count[b]; f += prm.group_size)
+                    queue[x].emplace_back(b, hp.batch_begin[b] + f);
+            longest = std::max(longest, queue[x].size());
+        }
+        hp.group_batch.assign(longest * X, -1);
+        hp.group_first.assign(longest * X, 0);
+        for (int32_t x = 0; x < X; ++x)
+            for (size_t i = 0; i < queue[x].size(); ++i) {
+                hp.group_batch[i * X + x] = queue[x][i].first;
+                hp.group_first[i * X + x] = queue[x][i].second;
+            }
+    }
 
     hp.leaf_of_pos.assign(ns, -1);
     for (int64_t id = 0; id < S.nodes(); ++id)

@@ -33,6 +33,7 @@ struct PlanParams {
     int64_t batch_size = 2000;
     int32_t group_size = 256;       // targets per GPU workgroup
     int64_t chunk_size = 1024;      // sources per upward-pass chunk
+    int32_t xcds = 8;               // accelerator dies that round-robin the workgroups
 };
 
 struct HostPlan {
@@ -65,7 +66,9 @@ struct HostPlan {
     std::vector<int64_t> chunk_begin, chunk_count;
     std::vector<int32_t> slot_chunk_off; // [nslots + 1]
 
-    // interaction workgroups: (batch, first target position), heaviest first
+    // interaction workgroups: (batch, first target position); batch -1 marks an
+    // empty slot.  Workgroup k runs on die k % xcds: each die gets a spatially
+    // contiguous, cost-balanced segment of batches, heaviest batch first.
     std::vector<int32_t> group_batch;
     std::vector<int64_t> group_first;
     std::vector<int64_t> batch_cost;     // kernel evaluations per target of each batch

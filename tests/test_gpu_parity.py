@@ -303,3 +303,45 @@ def test_mixed_full_size_sampled_and_full_n_vs_fp64(dev):
     ref = oracle.Treecode(pos, pos, 0.7, 8, 2000, 2000).potential(q[0], sample=smp)
     assert oracle.rel_l2(ref, mixed[smp]) <= MIXED_REL_L2
     assert oracle.rel_l2(full, mixed) <= MIXED_REL_L2
+
+
+# --------------------------------------------------------------------------
+# several charge vectors: kernel values shared, contraction on the matrix cores
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [2, 16, 21])
+@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+def test_fp64_many_charge_vectors(dev, m, kernel, kappa):
+    pos, q = inputs.uniform_cube(9001, 100 + m, m=m)
+    _, phi = _run_plan(dev, pos, pos, q, theta=0.7, degree=5, leaf_size=400, batch_size=400,
+                       kernel=kernel, kappa=kappa)
+    kern = oracle.YUKAWA if kernel == "yukawa" else oracle.COULOMB
+    ref = oracle.Treecode(pos, pos, 0.7, 5, 400, 400).potential(q, kernel=kern, kappa=kappa)
+    for i in range(m):
+        _close(ref[i], phi[i])
+
+
+@pytest.mark.parametrize("m", [3, 16])
+@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+def test_mixed_many_charge_vectors(dev, m, kernel, kappa):
+    pos, q = inputs.uniform_cube(9001, 120 + m, m=m)
+    _, phi = _run_plan(dev, pos, pos, q, theta=0.7, degree=6, leaf_size=400, batch_size=400,
+                       kernel=kernel, kappa=kappa, precision="fp32_mixed")
+    kern = oracle.YUKAWA if kernel == "yukawa" else oracle.COULOMB
+    ref = oracle.Treecode(pos, pos, 0.7, 6, 400, 400).potential(q, kernel=kern, kappa=kappa)
+    for i in range(m):
+        assert oracle.rel_l2(ref[i], phi[i]) <= MIXED_REL_L2
+
+
+def test_many_vectors_plummer_distinct_targets(dev):
+    g = np.random.default_rng(29)
+    src, q = inputs.plummer_sphere(15000, 131, m=16)
+    tgt = g.uniform(-2, 2, (5003, 3))
+    for precision in ("fp64", "fp32_mixed"):
+        _, phi = _run_plan(dev, tgt, src, q, theta=0.7, degree=7, leaf_size=700, batch_size=300,
+                           precision=precision)
+        ref = oracle.Treecode(tgt, src, 0.7, 7, 700, 300).potential(q)
+        for i in range(16):
+            if precision == "fp64":
+                _close(ref[i], phi[i])
+            else:
+                assert oracle.rel_l2(ref[i], phi[i]) <= MIXED_REL_L2
