@@ -69,7 +69,9 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
         [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", objs["kernels"]],
         [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_mixed.hip"), "-o", objs["mixed"]],
-        [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_mrhs.hip"), "-o", objs["mrhs"]],
+        # MFMA accumulators stay in VGPRs (no AGPR round trip around every step)
+        [hipcc] + hip_flags + ["-mllvm", "-amdgpu-mfma-vgpr-form",
+                               "-c", os.path.join(CSRC, "kernels_mrhs.hip"), "-o", objs["mrhs"]],
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "capi.cpp"), "-o", objs["capi"]],
     ]
     if verbose:

@@ -201,6 +201,30 @@ int upload_plan(bltc_plan* plan, hipStream_t s)
     HIP_TRY(plan->alloc(&d.qhat, static_cast<size_t>(d.nslots) * hp.P * plan->max_q));
     const bool mixed = plan->prm.precision == BLTC_FP32_MIXED;
     if (plan->max_q > 1) {
+        // expanded proxy grids for the multi-vector kernels
+        const int32_t np = hp.np;
+        std::vector<double4> prox(static_cast<size_t>(d.nslots) * hp.P);
+        std::vector<float4> prox32(mixed ? prox.size() : 0);
+        for (int64_t sl = 0; sl < d.nslots; ++sl) {
+            const double* nd = hp.slot_nodes.data() + sl * 3 * np;
+            const int32_t c = hp.slot_cluster[sl];
+            const double cx = hp.src.center[3 * c], cy = hp.src.center[3 * c + 1],
+                         cz = hp.src.center[3 * c + 2];
+            for (int32_t k1 = 0; k1 < np; ++k1)
+                for (int32_t k2 = 0; k2 < np; ++k2)
+                    for (int32_t k3 = 0; k3 < np; ++k3) {
+                        const size_t k = static_cast<size_t>(sl) * hp.P + (k1 * np + k2) * np + k3;
+                        prox[k] = make_double4(nd[k1], nd[np + k2], nd[2 * np + k3], 0.0);
+                        if (mixed)
+                            prox32[k] = make_float4(static_cast<float>(nd[k1] - cx),
+                                                    static_cast<float>(nd[np + k2] - cy),
+                                                    static_cast<float>(nd[2 * np + k3] - cz), 0.0f);
+                    }
+        }
+        HIP_TRY(plan->put(&d.proxies, prox, s));
+        if (mixed)
+            HIP_TRY(plan->put(&d.proxies32, prox32, s));
+        HIP_TRY(hipStreamSynchronize(s));
         HIP_TRY(plan->put(&d.slot_cluster, hp.slot_cluster, s));
         HIP_TRY(plan->alloc(&d.qm, static_cast<size_t>(d.ns) * 16));
         HIP_TRY(plan->alloc(&d.qhat16, static_cast<size_t>(d.nslots) * hp.P * 16));

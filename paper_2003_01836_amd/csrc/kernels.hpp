@@ -49,6 +49,8 @@ struct DevicePlan {
     double* qm = nullptr;             // [ns][16] charges in tree order
     float* qm32 = nullptr;            // [ns][16] (mixed precision)
     double* qhat16 = nullptr;         // [slot][P][16]
+    double4* proxies = nullptr;       // [slot][P] expanded Chebyshev grid (x, y, z, -)
+    float4* proxies32 = nullptr;      // [slot][P] grid relative to the cluster center
     float* qhat16f = nullptr;         // [slot][P][16] (mixed precision)
 };
 

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kGroupSize) void interact_mrhs_f64(
     const int64_t* __restrict__ batch_end, const int32_t* __restrict__ far_off,
     const int32_t* __restrict__ far_slot, const int32_t* __restrict__ near_off,
     const int64_t* __restrict__ near_begin, const int64_t* __restrict__ near_count,
-    const double* __restrict__ slot_nodes, const double* __restrict__ qhat16, int32_t np,
+    const double4* __restrict__ proxies, const double* __restrict__ qhat16, int32_t np,
     double* __restrict__ phi, int64_t phi_ld, int32_t m_count, double kappa)
 {
     const int g = blockIdx.x;
@@ -90,20 +90,22 @@ __global__ __launch_bounds__(kGroupSize) void interact_mrhs_f64(
     const int f_end = far_off[b + 1];
     for (int f = far_off[b]; f < f_end; ++f) {
         const int64_t slot = far_slot[f];
-        const double* __restrict__ nd = slot_nodes + slot * 3 * np;
+        const double4* __restrict__ px = proxies + slot * P;
         const double* __restrict__ qh = qhat16 + slot * static_cast<int64_t>(P) * kRhs;
+        // software pipeline: the next step's proxy point and charge are in flight
+        int kk = col < P ? col : P - 1;
+        double4 pn = px[kk];
+        double qn = qh[static_cast<int64_t>(kk) * kRhs + row];
         for (int k0 = 0; k0 < P; k0 += 4) {
-            const int k = k0 + col;
-            const bool ok = k < P;
-            const int kk = ok ? k : P - 1;
-            const int k1 = kk / (np * np);
-            const int k2 = (kk / np) - k1 * np;
-            const int k3 = kk - (kk / np) * np;
-            const double px = nd[k1], py = nd[np + k2], pz = nd[2 * np + k3];
-            const double bq = ok ? qh[static_cast<int64_t>(kk) * kRhs + row] : 0.0;
+            const double4 p = pn;
+            const double bq = (k0 + col < P) ? qn : 0.0;
+            kk = k0 + 4 + col;
+            kk = kk < P ? kk : P - 1;
+            pn = px[kk];
+            qn = qh[static_cast<int64_t>(kk) * kRhs + row];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const double dx = tx[t] - px, dy = ty[t] - py, dz = tz[t] - pz;
+                const double dx = tx[t] - p.x, dy = ty[t] - p.y, dz = tz[t] - p.z;
                 const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
                 const double gv = green_f64<KER>(r2, rsqrt_f64_newton(r2), kappa);
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
@@ -114,12 +116,16 @@ __global__ __launch_bounds__(kGroupSize) void interact_mrhs_f64(
     for (int e = near_off[b]; e < n_end; ++e) {
         const int64_t nb = near_begin[e];
         const int32_t cnt = static_cast<int32_t>(near_count[e]);
+        int64_t jj = nb + (col < cnt ? col : cnt - 1);
+        double4 pn = src[jj];
+        double qn = qm[jj * kRhs + row];
         for (int32_t j0 = 0; j0 < cnt; j0 += 4) {
-            const int32_t j = j0 + col;
-            const bool ok = j < cnt;
-            const int64_t jj = nb + (ok ? j : cnt - 1);
-            const double4 p = src[jj];
-            const double bq = ok ? qm[jj * kRhs + row] : 0.0;
+            const double4 p = pn;
+            const double bq = (j0 + col < cnt) ? qn : 0.0;
+            const int32_t jn = j0 + 4 + col;
+            jj = nb + (jn < cnt ? jn : cnt - 1);
+            pn = src[jj];
+            qn = qm[jj * kRhs + row];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const double dx = tx[t] - p.x, dy = ty[t] - p.y, dz = tz[t] - p.z;
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(kGroupSize) void interact_mrhs_mixed(
     const int32_t* __restrict__ far_off, const int32_t* __restrict__ far_slot,
     const int32_t* __restrict__ near_off, const int64_t* __restrict__ near_begin,
     const int64_t* __restrict__ near_count, const int32_t* __restrict__ near_leaf,
-    const int32_t* __restrict__ slot_cluster, const double* __restrict__ slot_nodes,
+    const int32_t* __restrict__ slot_cluster, const float4* __restrict__ proxies32,
     const float* __restrict__ qhat16, int32_t np, double* __restrict__ phi, int64_t phi_ld,
     int32_t m_count, double kappa)
 {
@@ -210,7 +216,7 @@ __global__ __launch_bounds__(kGroupSize) void interact_mrhs_mixed(
     for (int f = far_off[b]; f < f_end; ++f) {
         const int64_t slot = far_slot[f];
         const double4 ci = node_info[slot_cluster[slot]];
-        // targets and proxy points relative to the cluster center
+        // targets relative to the cluster center (proxy points are stored so)
         float ux[4], uy[4], uz[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -218,23 +224,22 @@ __global__ __launch_bounds__(kGroupSize) void interact_mrhs_mixed(
             uy[t] = static_cast<float>(ty[t] - ci.y);
             uz[t] = static_cast<float>(tz[t] - ci.z);
         }
-        const double* __restrict__ nd = slot_nodes + slot * 3 * np;
+        const float4* __restrict__ px = proxies32 + slot * P;
         const float* __restrict__ qh = qhat16 + slot * static_cast<int64_t>(P) * kRhs;
+        int kk = col < P ? col : P - 1;
+        float4 pn = px[kk];
+        float qn = qh[static_cast<int64_t>(kk) * kRhs + row];
         int steps = 0;
         for (int k0 = 0; k0 < P; k0 += 4) {
-            const int k = k0 + col;
-            const bool ok = k < P;
-            const int kk = ok ? k : P - 1;
-            const int k1 = kk / (np * np);
-            const int k2 = (kk / np) - k1 * np;
-            const int k3 = kk - (kk / np) * np;
-            const float px = static_cast<float>(nd[k1] - ci.x);
-            const float py = static_cast<float>(nd[np + k2] - ci.y);
-            const float pz = static_cast<float>(nd[2 * np + k3] - ci.z);
-            const float bq = ok ? qh[static_cast<int64_t>(kk) * kRhs + row] : 0.0f;
+            const float4 p = pn;
+            const float bq = (k0 + col < P) ? qn : 0.0f;
+            kk = k0 + 4 + col;
+            kk = kk < P ? kk : P - 1;
+            pn = px[kk];
+            qn = qh[static_cast<int64_t>(kk) * kRhs + row];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const float dx = ux[t] - px, dy = uy[t] - py, dz = uz[t] - pz;
+                const float dx = ux[t] - p.x, dy = uy[t] - p.y, dz = uz[t] - p.z;
                 const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
                 const float gv = green_f32<KER>(r2, __builtin_amdgcn_rsqf(r2), nk);
                 part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, bq, part[t], 0, 0, 0);
@@ -264,13 +269,18 @@ __global__ __launch_bounds__(kGroupSize) void interact_mrhs_mixed(
         }
         const int64_t nb = near_begin[e];
         const int32_t cnt = static_cast<int32_t>(near_count[e]);
+        int64_t jj = nb + (col < cnt ? col : cnt - 1);
+        float4 pn = src32[jj];
+        float qn = qm32[jj * kRhs + row];
         int steps = 0;
         for (int32_t j0 = 0; j0 < cnt; j0 += 4) {
-            const int32_t j = j0 + col;
-            const bool ok = j < cnt;
-            const int64_t jj = nb + (ok ? j : cnt - 1);
-            const float4 p = src32[jj];
-            const float bq = ok ? qm32[jj * kRhs + row] : 0.0f;
+            const float4 p = pn;
+            const float bq = (j0 + col < cnt) ? qn : 0.0f;
+            const int64_t jc = jj;
+            const int32_t jn = j0 + 4 + col;
+            jj = nb + (jn < cnt ? jn : cnt - 1);
+            pn = src32[jj];
+            qn = qm32[jj * kRhs + row];
             float gv[4], r2v[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -280,7 +290,7 @@ __global__ __launch_bounds__(kGroupSize) void interact_mrhs_mixed(
             }
             if (fminf(fminf(r2v[0], r2v[1]), fminf(r2v[2], r2v[3])) <= tau2) {
                 // close pairs: the kernel value from the exact coordinates, in FP64
-                const double4 p64 = src[jj];
+                const double4 p64 = src[jc];
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
                     if (r2v[t] <= tau2) {
@@ -382,19 +392,21 @@ hipError_t launch_interact_mrhs(const DevicePlan& d, const KernelParams& kp, dou
     const dim3 grid(static_cast<unsigned>(d.ngroups)), block(kGroupSize);
     const bool yuk = kp.kernel == 1;
     if (kp.precision == 1) {
-        if (!d.src32 || !d.qm32 || !d.qhat16f)
+        if (!d.src32 || !d.qm32 || !d.qhat16f || !d.proxies32)
             return hipErrorInvalidValue;
         auto k = yuk ? interact_mrhs_mixed<1> : interact_mrhs_mixed<0>;
         hipLaunchKernelGGL(k, grid, block, 0, s, d.tgt, d.tgt_orig, d.src, d.src32, d.qm32,
                            d.node_info, d.batch_info, d.group_batch, d.group_first, d.batch_end,
                            d.far_off, d.far_slot, d.near_off, d.near_begin, d.near_count,
-                           d.near_leaf, d.slot_cluster, d.slot_nodes, d.qhat16f, np, phi, phi_ld,
+                           d.near_leaf, d.slot_cluster, d.proxies32, d.qhat16f, np, phi, phi_ld,
                            mc, kp.kappa);
     } else {
+        if (!d.qm || !d.qhat16 || !d.proxies)
+            return hipErrorInvalidValue;
         auto k = yuk ? interact_mrhs_f64<1> : interact_mrhs_f64<0>;
         hipLaunchKernelGGL(k, grid, block, 0, s, d.tgt, d.tgt_orig, d.src, d.qm, d.group_batch,
                            d.group_first, d.batch_end, d.far_off, d.far_slot, d.near_off,
-                           d.near_begin, d.near_count, d.slot_nodes, d.qhat16, np, phi, phi_ld, mc,
+                           d.near_begin, d.near_count, d.proxies, d.qhat16, np, phi, phi_ld, mc,
                            kp.kappa);
     }
     return hipGetLastError();
