@@ -63,6 +63,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         "kernels": os.path.join(build_dir, "kernels.o"),
         "mixed": os.path.join(build_dir, "kernels_mixed.o"),
         "mrhs": os.path.join(build_dir, "kernels_mrhs.o"),
+        "upward": os.path.join(build_dir, "kernels_upward.o"),
         "capi": os.path.join(build_dir, "capi.o"),
     }
     cmds = [
@@ -72,6 +73,8 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         # MFMA accumulators stay in VGPRs (no AGPR round trip around every step)
         [hipcc] + hip_flags + ["-mllvm", "-amdgpu-mfma-vgpr-form",
                                "-c", os.path.join(CSRC, "kernels_mrhs.hip"), "-o", objs["mrhs"]],
+        [hipcc] + hip_flags + ["-mllvm", "-amdgpu-mfma-vgpr-form",
+                               "-c", os.path.join(CSRC, "kernels_upward.hip"), "-o", objs["upward"]],
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "capi.cpp"), "-o", objs["capi"]],
     ]
     if verbose:

@@ -105,6 +105,7 @@ struct bltc_plan {
     bltc::DevicePlan d;
     std::vector<void*> allocations;
     bool timing = false;
+    int32_t last_q = 0;                  // charge vectors of the last execution
     int32_t timed_q = 0;                 // charge vectors covered by the recorded events
     std::vector<hipEvent_t> events;      // 4 per charge vector
 
@@ -197,8 +198,11 @@ int upload_plan(bltc_plan* plan, hipStream_t s)
     HIP_TRY(plan->put(&d.chunk_begin, hp.chunk_begin, s));
     HIP_TRY(plan->put(&d.chunk_count, hp.chunk_count, s));
     HIP_TRY(plan->put(&d.slot_chunk_off, hp.slot_chunk_off, s));
-    HIP_TRY(plan->alloc(&d.partial, static_cast<size_t>(d.nchunks) * hp.P));
-    HIP_TRY(plan->alloc(&d.qhat, static_cast<size_t>(d.nslots) * hp.P * plan->max_q));
+    HIP_TRY(plan->put(&d.chunk_dst, hp.chunk_dst, s));
+    // modified charges (first nslots rows) and the partial rows of multi-chunk
+    // clusters; [row][P] for one charge vector, [row][P][16] for several
+    const size_t mw_max = plan->max_q > 1 ? 16 : 1;
+    HIP_TRY(plan->alloc(&d.qhat, static_cast<size_t>(d.nslots + hp.npartial) * hp.P * mw_max));
     const bool mixed = plan->prm.precision == BLTC_FP32_MIXED;
     if (plan->max_q > 1) {
         // expanded proxy grids for the multi-vector kernels
@@ -227,7 +231,7 @@ int upload_plan(bltc_plan* plan, hipStream_t s)
         HIP_TRY(hipStreamSynchronize(s));
         HIP_TRY(plan->put(&d.slot_cluster, hp.slot_cluster, s));
         HIP_TRY(plan->alloc(&d.qm, static_cast<size_t>(d.ns) * 16));
-        HIP_TRY(plan->alloc(&d.qhat16, static_cast<size_t>(d.nslots) * hp.P * 16));
+        d.qhat16 = d.qhat;
         if (mixed) {
             HIP_TRY(plan->alloc(&d.qm32, static_cast<size_t>(d.ns) * 16));
             HIP_TRY(plan->alloc(&d.qhat16f, static_cast<size_t>(d.nslots) * hp.P * 16));
@@ -256,7 +260,7 @@ int upload_plan(bltc_plan* plan, hipStream_t s)
         HIP_TRY(plan->put(&d.src32, src32, s));
         HIP_TRY(plan->put(&d.node_info, node_info, s));
         HIP_TRY(plan->put(&d.batch_info, batch_info, s));
-        HIP_TRY(plan->alloc(&d.qhat32, static_cast<size_t>(d.nslots) * hp.P * plan->max_q));
+        HIP_TRY(plan->alloc(&d.qhat32, static_cast<size_t>(d.nslots) * hp.P));
         HIP_TRY(hipStreamSynchronize(s));
     }
     // host staging vectors die at return: finish the copies first
@@ -318,12 +322,11 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
     auto mark = [&](int32_t u, int k) -> hipError_t {
         return plan->timing ? hipEventRecord(plan->events[4 * u + k], s) : hipSuccess;
     };
-    const int64_t slice = d.nslots * hp.P;
     if (num_q == 1) {
         HIP_TRY(mark(0, 0));
         HIP_TRY(bltc::launch_gather_charges(d, q, s));
         HIP_TRY(mark(0, 1));
-        HIP_TRY(bltc::launch_upward(d, s));
+        HIP_TRY(bltc::launch_upward_mfma(d, 1, d.qhat, d.qhat32, s));
         HIP_TRY(mark(0, 2));
         if (kp.precision == BLTC_FP32_MIXED)
             HIP_TRY(bltc::launch_interact_mixed(d, kp, phi, s));
@@ -337,14 +340,7 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
             HIP_TRY(mark(u, 0));
             HIP_TRY(bltc::launch_gather_charges16(d, q + static_cast<int64_t>(m0) * q_ld, q_ld, mc, s));
             HIP_TRY(mark(u, 1));
-            for (int32_t m = 0; m < mc; ++m) {
-                d.qhat = plan->d.qhat + static_cast<int64_t>(m) * slice;
-                d.qhat32 = nullptr;
-                HIP_TRY(bltc::launch_gather_charges(d, q + static_cast<int64_t>(m0 + m) * q_ld, s));
-                HIP_TRY(bltc::launch_upward(d, s));
-            }
-            d.qhat = plan->d.qhat;
-            HIP_TRY(bltc::launch_pack_qhat16(d, mc, s));
+            HIP_TRY(bltc::launch_upward_mfma(d, 16, d.qhat16, d.qhat16f, s));
             HIP_TRY(mark(u, 2));
             HIP_TRY(bltc::launch_interact_mrhs(d, kp, phi + static_cast<int64_t>(m0) * phi_ld, phi_ld,
                                                mc, s));
@@ -352,6 +348,7 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
         }
     }
     plan->timed_q = plan->timing ? units : 0;
+    plan->last_q = num_q;
     return BLTC_OK;
 }
 
@@ -552,12 +549,19 @@ int bltc_plan_modified_charges(bltc_plan* plan, int64_t cluster, int32_t qi, dou
     if (slot < 0)
         return fail(BLTC_EINVAL, "cluster %lld has no modified charges",
                     static_cast<long long>(cluster));
-    if (!plan->uploaded)
+    if (!plan->uploaded || plan->last_q == 0)
         return fail(BLTC_EINVAL, "plan has not been executed");
+    // one vector: qhat[slot][k]; several: the last pass of 16, qhat16[slot][k][m]
+    const int32_t m0 = plan->last_q == 1 ? 0 : 16 * ((plan->last_q - 1) / 16);
+    if (qi < m0 || qi >= plan->last_q)
+        return fail(BLTC_EINVAL, "charge vector %d is not in the last execution's last pass", qi);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const double* src = plan->d.qhat + (static_cast<int64_t>(qi) * plan->d.nslots + slot) * hp.P;
-    HIP_TRY(hipMemcpyAsync(out, src, hp.P * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> buf(plan->last_q == 1 ? hp.P : hp.P * 16);
+    const double* src = plan->d.qhat + static_cast<int64_t>(slot) * static_cast<int64_t>(buf.size());
+    HIP_TRY(hipMemcpyAsync(buf.data(), src, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t k = 0; k < hp.P; ++k)
+        out[k] = plan->last_q == 1 ? buf[k] : buf[k * 16 + (qi - m0)];
     return BLTC_OK;
 }
 

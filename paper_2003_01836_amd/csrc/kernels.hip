@@ -8,14 +8,9 @@
 //    data cache into SGPRs -- no LDS staging and no barriers.  Each lane owns
 //    its target's accumulator, so phi is written exactly once, in caller
 //    order, without atomics.
-//  * upward pass: one workgroup per chunk of a cluster's sources; lanes over
-//    sources form the 1-D barycentric factors of eq. 14 in LDS, then lanes
-//    over grid points accumulate eq. 15; a second kernel sums the chunks of
-//    each cluster in a fixed order (deterministic).
+//  * the upward pass lives in kernels_upward.hip (matrix cores).
 #include "kernels.hpp"
 #include "device_common.hpp"
-
-#include <cfloat>
 
 namespace bltc {
 namespace {
@@ -111,132 +106,6 @@ __global__ __launch_bounds__(kGroupSize) void interact_f64(
         phi[tgt_orig[i]] = acc;
 }
 
-// ---------------------------------------------------------------------------
-// Upward pass, eqs. 14-15.  One workgroup per chunk (<= chunk_size sources of
-// one cluster).  Tiles of kUpwardTile sources: lane j forms, in FP64,
-//   a_lk = w_k / (y_jl - s_lk), D_l = sum_k a_lk   (l = 1, 2, 3)
-// or, when |y_jl - s_lk'| < DBL_MIN, a_lk = delta_kk', D_l = 1 (eq. 5);
-// then qtilde_j = q_j / (D_1 D_2 D_3) (eq. 14), stored as A1 = a_1 * qtilde,
-// A2 = a_2, A3 = a_3.  Lanes over grid points k then accumulate
-// qhat_k += A1[k1] A2[k2] A3[k3] (eq. 15).
-// ---------------------------------------------------------------------------
-template <int N>
-__device__ __forceinline__ void bary_factors(double yv, const double* __restrict__ s,
-                                             double* __restrict__ a, double& D)
-{
-    constexpr int NP = N + 1;
-    int hit = -1;
-#pragma unroll
-    for (int k = NP - 1; k >= 0; --k)
-        if (fabs(yv - s[k]) < DBL_MIN)
-            hit = k;  // lowest coincident index wins
-    if (hit >= 0) {
-#pragma unroll
-        for (int k = 0; k < NP; ++k)
-            a[k] = (k == hit) ? 1.0 : 0.0;
-        D = 1.0;
-        return;
-    }
-    double sum = 0.0;
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        const double w = ((k & 1) ? -1.0 : 1.0) * ((k == 0 || k == N) ? 0.5 : 1.0);
-        a[k] = w / (yv - s[k]);
-        sum += a[k];
-    }
-    D = sum;
-}
-
-template <int N>
-__global__ __launch_bounds__(256) void upward_partial_f64(
-    const double4* __restrict__ src, const int32_t* __restrict__ chunk_slot,
-    const int64_t* __restrict__ chunk_begin, const int64_t* __restrict__ chunk_count,
-    const double* __restrict__ slot_nodes, double* __restrict__ partial)
-{
-    constexpr int NP = N + 1;
-    constexpr int P = NP * NP * NP;
-    constexpr int KPT = (P + 255) / 256;
-    __shared__ double A1[kUpwardTile * NP];
-    __shared__ double A2[kUpwardTile * NP];
-    __shared__ double A3[kUpwardTile * NP];
-    __shared__ double sn[3 * NP];
-
-    const int c = blockIdx.x;
-    const int64_t slot = chunk_slot[c];
-    const int64_t begin = chunk_begin[c];
-    const int64_t count = chunk_count[c];
-    const int tid = threadIdx.x;
-    if (tid < 3 * NP)
-        sn[tid] = slot_nodes[slot * 3 * NP + tid];
-    __syncthreads();
-
-    double acc[KPT];
-    int kk1[KPT], kk2[KPT], kk3[KPT];
-#pragma unroll
-    for (int u = 0; u < KPT; ++u) {
-        acc[u] = 0.0;
-        const int k = tid + u * 256;
-        const int kc = k < P ? k : 0;
-        kk1[u] = kc / (NP * NP);
-        kk2[u] = (kc / NP) % NP;
-        kk3[u] = kc % NP;
-    }
-
-    for (int64_t t0 = 0; t0 < count; t0 += kUpwardTile) {
-        const int tn = static_cast<int>(count - t0 < kUpwardTile ? count - t0 : kUpwardTile);
-        if (tid < tn) {
-            const double4 p = src[begin + t0 + tid];
-            double a1[NP], a2[NP], a3[NP], D1, D2, D3;
-            bary_factors<N>(p.x, sn, a1, D1);
-            bary_factors<N>(p.y, sn + NP, a2, D2);
-            bary_factors<N>(p.z, sn + 2 * NP, a3, D3);
-            const double qt = p.w / (D1 * D2 * D3);
-#pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                A1[tid * NP + k] = a1[k] * qt;
-                A2[tid * NP + k] = a2[k];
-                A3[tid * NP + k] = a3[k];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < KPT; ++u) {
-            if (tid + u * 256 < P) {
-                double s = acc[u];
-                for (int j = 0; j < tn; ++j)
-                    s = __fma_rn(A1[j * NP + kk1[u]] * A2[j * NP + kk2[u]], A3[j * NP + kk3[u]], s);
-                acc[u] = s;
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < KPT; ++u) {
-        const int k = tid + u * 256;
-        if (k < P)
-            partial[static_cast<int64_t>(c) * P + k] = acc[u];
-    }
-}
-
-__global__ __launch_bounds__(256) void upward_reduce_f64(const int32_t* __restrict__ slot_chunk_off,
-                                                         const double* __restrict__ partial,
-                                                         double* __restrict__ qhat,
-                                                         float* __restrict__ qhat32, int64_t nslots,
-                                                         int32_t P)
-{
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= nslots * P)
-        return;
-    const int64_t slot = idx / P;
-    const int64_t k = idx - slot * P;
-    double s = 0.0;
-    for (int32_t c = slot_chunk_off[slot]; c < slot_chunk_off[slot + 1]; ++c)
-        s += partial[static_cast<int64_t>(c) * P + k];
-    qhat[idx] = s;
-    if (qhat32)
-        qhat32[idx] = static_cast<float>(s);
-}
-
 __global__ __launch_bounds__(256) void gather_charges(double4* __restrict__ src,
                                                       float4* __restrict__ src32,
                                                       const int64_t* __restrict__ order,
@@ -302,26 +171,6 @@ hipError_t run_interact(const DevicePlan& d, double* phi, double kappa, hipStrea
     return hipGetLastError();
 }
 
-template <int N>
-hipError_t run_upward(const DevicePlan& d, hipStream_t s)
-{
-    constexpr int NP = N + 1;
-    constexpr int P = NP * NP * NP;
-    if (d.nchunks == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL((upward_partial_f64<N>), dim3(static_cast<unsigned>(d.nchunks)), dim3(256),
-                       0, s, d.src, d.chunk_slot, d.chunk_begin, d.chunk_count, d.slot_nodes,
-                       d.partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    const int64_t total = d.nslots * P;
-    hipLaunchKernelGGL(upward_reduce_f64, dim3(static_cast<unsigned>((total + 255) / 256)),
-                       dim3(256), 0, s, d.slot_chunk_off, d.partial, d.qhat, d.qhat32, d.nslots,
-                       static_cast<int32_t>(P));
-    return hipGetLastError();
-}
-
 #define BLTC_DEGREE_CASES(X) \
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
@@ -334,19 +183,6 @@ hipError_t launch_gather_charges(const DevicePlan& d, const double* q, hipStream
     hipLaunchKernelGGL(gather_charges, dim3(static_cast<unsigned>((d.ns + 255) / 256)), dim3(256),
                        0, s, d.src, d.src32, d.src_order, q, d.ns);
     return hipGetLastError();
-}
-
-hipError_t launch_upward(const DevicePlan& d, hipStream_t s)
-{
-    switch (d.degree) {
-#define X(n) \
-    case n:  \
-        return run_upward<n>(d, s);
-        BLTC_DEGREE_CASES(X)
-#undef X
-    default:
-        return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* phi,

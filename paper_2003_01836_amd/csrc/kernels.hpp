@@ -9,7 +9,6 @@ namespace bltc {
 
 constexpr int kMaxDegree = 16;
 constexpr int kGroupSize = 256;      // targets (lanes) per interaction workgroup
-constexpr int kUpwardTile = 128;     // sources staged per LDS tile in the upward pass
 
 // Device-side view of a plan (all device pointers).
 struct DevicePlan {
@@ -41,14 +40,14 @@ struct DevicePlan {
     int64_t* chunk_begin = nullptr;
     int64_t* chunk_count = nullptr;
     int32_t* slot_chunk_off = nullptr;
-    double* partial = nullptr;        // [chunk][P]
-    double* qhat = nullptr;           // [q][slot][P]
+    int64_t* chunk_dst = nullptr;     // output row of each chunk (slot, or nslots + partial)
+    double* qhat = nullptr;           // [slot][P] or [slot][P][16], then partial rows
     float* qhat32 = nullptr;          // [slot][P] (mixed precision)
     // several charge vectors at once (16 per pass)
     int32_t* slot_cluster = nullptr;  // cluster id of each slot
     double* qm = nullptr;             // [ns][16] charges in tree order
     float* qm32 = nullptr;            // [ns][16] (mixed precision)
-    double* qhat16 = nullptr;         // [slot][P][16]
+    double* qhat16 = nullptr;         // [slot][P][16] (same storage as qhat)
     double4* proxies = nullptr;       // [slot][P] expanded Chebyshev grid (x, y, z, -)
     float4* proxies32 = nullptr;      // [slot][P] grid relative to the cluster center
     float* qhat16f = nullptr;         // [slot][P][16] (mixed precision)
@@ -62,8 +61,11 @@ struct KernelParams {
 
 // src[j].w = q[order[j]] (and src32[j].w when present), j < ns: charges into tree order
 hipError_t launch_gather_charges(const DevicePlan& d, const double* q, hipStream_t s);
-// upward pass: eqs. 14-15 per chunk, then the per-cluster reduction
-hipError_t launch_upward(const DevicePlan& d, hipStream_t s);
+// upward pass, eqs. 14-15, on the matrix cores (kernels_upward.hip): mw = 1 (charges in
+// src[j].w, result buf[slot][k]) or 16 (charges in qm, result buf[slot][k][16]);
+// buf holds nslots final rows followed by the partial rows of multi-chunk slots
+hipError_t launch_upward_mfma(const DevicePlan& d, int32_t mw, double* buf, float* qhat32,
+                              hipStream_t s);
 // batch/cluster interactions: eqs. 9 and 11, phi written in caller order
 hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* phi,
                            hipStream_t s);
@@ -71,12 +73,10 @@ hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* 
 hipError_t launch_interact_mixed(const DevicePlan& d, const KernelParams& kp, double* phi,
                                  hipStream_t s);
 // several charge vectors (kernels_mrhs.hip): charges of vectors m0..m0+mc-1
-// into qm/qm32 (tree order, zero padded to 16), modified charges of the mc
-// vectors (qhat[m][slot][k]) into qhat16/qhat16f, and the interactions of all
+// into qm/qm32 (tree order, zero padded to 16), and the interactions of all
 // mc vectors: phi[m * phi_ld + i], m < mc
 hipError_t launch_gather_charges16(const DevicePlan& d, const double* q, int64_t q_ld, int32_t mc,
                                    hipStream_t s);
-hipError_t launch_pack_qhat16(const DevicePlan& d, int32_t mc, hipStream_t s);
 hipError_t launch_interact_mrhs(const DevicePlan& d, const KernelParams& kp, double* phi,
                                 int64_t phi_ld, int32_t mc, hipStream_t s);
 // GPU direct sum (eq. 1) of all targets against packed sources

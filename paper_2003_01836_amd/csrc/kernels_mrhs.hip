@@ -340,24 +340,6 @@ __global__ __launch_bounds__(256) void gather_charges16(double* __restrict__ qm,
         qm32[idx] = static_cast<float>(v);
 }
 
-// qhat16[slot][k][m] = qhat[m][slot][k] for m < mc, zero otherwise
-__global__ __launch_bounds__(256) void pack_qhat16(double* __restrict__ q16,
-                                                   float* __restrict__ q16f,
-                                                   const double* __restrict__ qhat, int64_t nslots,
-                                                   int32_t P, int32_t mc)
-{
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t total = nslots * P * kRhs;
-    if (idx >= total)
-        return;
-    const int64_t sk = idx / kRhs;
-    const int m = static_cast<int>(idx - sk * kRhs);
-    const double v = m < mc ? qhat[static_cast<int64_t>(m) * nslots * P + sk] : 0.0;
-    q16[idx] = v;
-    if (q16f)
-        q16f[idx] = static_cast<float>(v);
-}
-
 }  // namespace
 
 hipError_t launch_gather_charges16(const DevicePlan& d, const double* q, int64_t q_ld, int32_t mc,
@@ -368,18 +350,6 @@ hipError_t launch_gather_charges16(const DevicePlan& d, const double* q, int64_t
     const int64_t total = d.ns * kRhs;
     hipLaunchKernelGGL(gather_charges16, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256),
                        0, s, d.qm, d.qm32, d.src_order, q, q_ld, mc, d.ns);
-    return hipGetLastError();
-}
-
-hipError_t launch_pack_qhat16(const DevicePlan& d, int32_t mc, hipStream_t s)
-{
-    const int32_t np = d.degree + 1;
-    const int32_t P = np * np * np;
-    const int64_t total = d.nslots * P * kRhs;
-    if (total == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(pack_qhat16, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s,
-                       d.qhat16, d.qhat16f, d.qhat, d.nslots, P, mc);
     return hipGetLastError();
 }
 

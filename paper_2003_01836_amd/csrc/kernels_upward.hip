@@ -1,0 +1,241 @@
+// kernels_upward.hip -- the upward pass (eqs. 14-15) as a dense contraction on
+// the matrix cores.
+//
+// For the sources j of one cluster, with the 1-D barycentric factors
+// a_l[j][k] = w_k / (y_jl - s_lk) (one-hot when the coordinate coincides with a
+// node, eq. 5) and q~_jm = q_jm / (D_1 D_2 D_3) (eq. 14), eq. 15 reads
+//     Qhat[(k1, m)][(k2, k3)] = sum_j (a_1[j][k1] q~_jm) * (a_2[j][k2] a_3[j][k3])
+// i.e. the product (a_1 o q~)^T (a_2 (.) a_3) of an N_C x (n+1)M and an
+// N_C x (n+1)^2 matrix (o: outer product per row, (.): row-wise Kronecker
+// product).  One workgroup takes a chunk of a cluster's sources and a set of
+// 16x16 output tiles; the factors of 128 sources at a time are formed in FP64
+// in LDS, and each wave accumulates its tiles with v_mfma_f64_16x16x4f64,
+// K = 4 sources per instruction.  Chunks of the same cluster are summed in a
+// fixed order by a second kernel (deterministic).
+#include <cfloat>
+
+#include "kernels.hpp"
+
+namespace bltc {
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 128;          // sources staged in LDS at a time
+constexpr int kTilesPerWave = 8;    // 16x16 output tiles accumulated per wave
+constexpr int kTilesPerGroup = 4 * kTilesPerWave;
+
+// 1-D factors of one coordinate (eqs. 4-5, 14), FP64; returns D_l.
+__device__ __forceinline__ double factors_rt(double yv, const double* __restrict__ s, int np,
+                                             double* __restrict__ a)
+{
+    const int n = np - 1;
+    int hit = -1;
+    for (int k = np - 1; k >= 0; --k)
+        if (fabs(yv - s[k]) < DBL_MIN)
+            hit = k;
+    if (hit >= 0) {
+        for (int k = 0; k < np; ++k)
+            a[k] = (k == hit) ? 1.0 : 0.0;
+        return 1.0;
+    }
+    double sum = 0.0;
+    for (int k = 0; k < np; ++k) {
+        const double w = ((k & 1) ? -1.0 : 1.0) * ((k == 0 || k == n) ? 0.5 : 1.0);
+        const double v = w / (yv - s[k]);
+        a[k] = v;
+        sum += v;
+    }
+    return sum;
+}
+
+// grid: x = chunk, y = tile pass.  mw = 1 (one charge vector, taken from
+// src[j].w) or 16 (charges from qm[j][16]).  Output of a chunk: dst[k * mw + m]
+// with dst = out + chunk_dst[c] * P * mw (rows below nslots are the final
+// modified charges of single-chunk clusters, the others partial sums).
+// Tiles are dealt round-robin to the 4 waves: wave w of tile pass p owns
+// tiles p * 32 + w + 4u, u < 8.
+__global__ __launch_bounds__(256) void upward_mfma_f64(
+    const double4* __restrict__ src, const double* __restrict__ qm, int32_t mw,
+    const int32_t* __restrict__ chunk_slot, const int64_t* __restrict__ chunk_begin,
+    const int64_t* __restrict__ chunk_count, const int64_t* __restrict__ chunk_dst,
+    const double* __restrict__ slot_nodes, int32_t np, double* __restrict__ out)
+{
+    extern __shared__ double lds[];
+    const int np2 = np * np;
+    const int P = np2 * np;
+    double* __restrict__ A1 = lds;                   // [kTile][np]
+    double* __restrict__ A2 = A1 + kTile * np;       // [kTile][np]
+    double* __restrict__ A3 = A2 + kTile * np;       // [kTile][np]
+    double* __restrict__ SQ = A3 + kTile * np;       // [kTile][mw]  q~
+    double* __restrict__ SN = SQ + kTile * mw;       // [3][np]      nodes
+
+    const int c = blockIdx.x;
+    const int64_t slot = chunk_slot[c];
+    const int64_t begin = chunk_begin[c];
+    const int64_t count = chunk_count[c];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    if (tid < 3 * np)
+        SN[tid] = slot_nodes[slot * 3 * np + tid];
+
+    const int R = np * mw;                  // rows (k1, m)
+    const int RT = (R + 15) / 16;
+    const int CT = (np2 + 15) / 16;         // columns (k2, k3)
+    const int T = RT * CT;
+    const int tbase = blockIdx.y * kTilesPerGroup + wave;
+
+    // per owned tile: LDS offsets of this lane's row factor and column factors
+    int rk1[kTilesPerWave], rm[kTilesPerWave], ck2[kTilesPerWave], ck3[kTilesPerWave];
+    bool live[kTilesPerWave];
+    d4v acc[kTilesPerWave];
+#pragma unroll
+    for (int u = 0; u < kTilesPerWave; ++u) {
+        const int t = tbase + 4 * u;
+        live[u] = t < T;
+        const int rt = live[u] ? t / CT : 0;
+        const int ct = live[u] ? t - rt * CT : 0;
+        const int r = rt * 16 + (lane & 15);
+        const int cc = ct * 16 + (lane & 15);
+        // rows/cols past the end get index -1: their operand is zero
+        rk1[u] = r < R ? r / mw : -1;
+        rm[u] = r < R ? r - (r / mw) * mw : 0;
+        ck2[u] = cc < np2 ? cc / np : -1;
+        ck3[u] = cc < np2 ? cc - (cc / np) * np : 0;
+        acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
+    }
+    __syncthreads();
+
+    for (int64_t t0 = 0; t0 < count; t0 += kTile) {
+        const int tn = static_cast<int>(count - t0 < kTile ? count - t0 : kTile);
+        if (tid < kTile) {
+            if (tid < tn) {
+                const int64_t j = begin + t0 + tid;
+                const double4 p = src[j];
+                const double D = factors_rt(p.x, SN, np, A1 + tid * np) *
+                                 factors_rt(p.y, SN + np, np, A2 + tid * np) *
+                                 factors_rt(p.z, SN + 2 * np, np, A3 + tid * np);
+                const double inv = 1.0 / D;
+                if (mw == 1) {
+                    SQ[tid] = p.w * inv;
+                } else {
+                    for (int m = 0; m < mw; ++m)
+                        SQ[tid * mw + m] = qm[j * 16 + m] * inv;
+                }
+            } else {
+                // zero rows: the partial last step of the tile contributes nothing
+                for (int k = 0; k < np; ++k) {
+                    A1[tid * np + k] = 0.0;
+                    A2[tid * np + k] = 0.0;
+                    A3[tid * np + k] = 0.0;
+                }
+                for (int m = 0; m < mw; ++m)
+                    SQ[tid * mw + m] = 0.0;
+            }
+        }
+        __syncthreads();
+        if (tbase < T) {
+            const int steps = (tn + 3) / 4;
+            for (int st = 0; st < steps; ++st) {
+                const int j = 4 * st + (lane >> 4);
+#pragma unroll
+                for (int u = 0; u < kTilesPerWave; ++u) {
+                    if (!live[u])
+                        continue;
+                    const double av = rk1[u] >= 0 ? A1[j * np + rk1[u]] * SQ[j * mw + rm[u]] : 0.0;
+                    const double bv = ck2[u] >= 0 ? A2[j * np + ck2[u]] * A3[j * np + ck3[u]] : 0.0;
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // f64 result layout: lane l, register r holds D[4r + l/16][l % 16]
+    double* __restrict__ dst = out + chunk_dst[c] * static_cast<int64_t>(P) * mw;
+#pragma unroll
+    for (int u = 0; u < kTilesPerWave; ++u) {
+        if (!live[u])
+            continue;
+        const int t = tbase + 4 * u;
+        const int rt = t / CT;
+        const int ct = t - rt * CT;
+        const int cc = ct * 16 + (lane & 15);
+        if (cc >= np2)
+            continue;
+        const int k2 = cc / np, k3 = cc - (cc / np) * np;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = rt * 16 + 4 * r + (lane >> 4);
+            if (row < R) {
+                const int k1 = row / mw, m = row - (row / mw) * mw;
+                dst[static_cast<int64_t>((k1 * np + k2) * np + k3) * mw + m] = acc[u][r];
+            }
+        }
+    }
+}
+
+// qhat (and its FP32 copy) of every slot: the chunk result already in place
+// for single-chunk clusters, else the sum of the partials in chunk order
+__global__ __launch_bounds__(256) void upward_mfma_reduce(
+    const int32_t* __restrict__ slot_chunk_off, const int64_t* __restrict__ chunk_dst,
+    double* __restrict__ buf, float* __restrict__ qhat32, int64_t nslots, int64_t per_slot)
+{
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= nslots * per_slot)
+        return;
+    const int64_t slot = idx / per_slot;
+    const int64_t k = idx - slot * per_slot;
+    const int32_t c0 = slot_chunk_off[slot], c1 = slot_chunk_off[slot + 1];
+    double s;
+    if (c1 - c0 == 1) {
+        s = buf[idx];
+    } else {
+        s = 0.0;
+        for (int32_t c = c0; c < c1; ++c)
+            s += buf[chunk_dst[c] * per_slot + k];
+        buf[idx] = s;
+    }
+    if (qhat32)
+        qhat32[idx] = static_cast<float>(s);
+}
+
+}  // namespace
+
+hipError_t launch_upward_mfma(const DevicePlan& d, int32_t mw, double* buf, float* qhat32,
+                              hipStream_t s)
+{
+    if (d.nchunks == 0)
+        return hipSuccess;
+    const int32_t np = d.degree + 1;
+    const int32_t np2 = np * np;
+    const int32_t R = np * mw;
+    const int32_t T = ((R + 15) / 16) * ((np2 + 15) / 16);
+    const int32_t passes = (T + kTilesPerGroup - 1) / kTilesPerGroup;
+    const size_t lds = sizeof(double) * (static_cast<size_t>(3) * kTile * np +
+                                         static_cast<size_t>(kTile) * mw + 3 * np);
+    if (lds > 65536) {
+        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(upward_mfma_f64),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(lds));
+        if (a != hipSuccess)
+            return a;
+    }
+    hipLaunchKernelGGL(upward_mfma_f64, dim3(static_cast<unsigned>(d.nchunks), passes), dim3(256),
+                       lds, s, d.src, d.qm, mw, d.chunk_slot, d.chunk_begin, d.chunk_count,
+                       d.chunk_dst, d.slot_nodes, np, buf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int64_t per_slot = static_cast<int64_t>(np2) * np * mw;
+    const int64_t total = d.nslots * per_slot;
+    if (total == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(upward_mfma_reduce, dim3(static_cast<unsigned>((total + 255) / 256)),
+                       dim3(256), 0, s, d.slot_chunk_off, d.chunk_dst, buf, qhat32, d.nslots,
+                       per_slot);
+    return hipGetLastError();
+}
+
+}  // namespace bltc

@@ -324,6 +324,9 @@ std::string make_plan(HostPlan& hp, const PlanParams& prm,
             hp.chunk_count.push_back(std::min<int64_t>(prm.chunk_size, S.count[c] - off));
         }
         hp.slot_chunk_off[s + 1] = static_cast<int32_t>(hp.chunk_slot.size());
+        const int32_t c0 = hp.slot_chunk_off[s], c1 = hp.slot_chunk_off[s + 1];
+        for (int32_t c = c0; c < c1; ++c)
+            hp.chunk_dst.push_back(c1 - c0 == 1 ? s : nslots + hp.npartial++);
     }
 
     // ---- interaction workgroups ------------------------------------------------

@@ -32,7 +32,7 @@ struct PlanParams {
     int64_t leaf_size = 2000;
     int64_t batch_size = 2000;
     int32_t group_size = 256;       // targets per GPU workgroup
-    int64_t chunk_size = 1024;      // sources per upward-pass chunk
+    int64_t chunk_size = 8192;      // sources per upward-pass chunk
     int32_t xcds = 8;               // accelerator dies that round-robin the workgroups
 };
 
@@ -65,6 +65,9 @@ struct HostPlan {
     std::vector<int32_t> chunk_slot;
     std::vector<int64_t> chunk_begin, chunk_count;
     std::vector<int32_t> slot_chunk_off; // [nslots + 1]
+    std::vector<int64_t> chunk_dst;      // output row: the slot itself for single-chunk
+                                         // slots, else nslots + partial index
+    int64_t npartial = 0;
 
     // interaction workgroups: (batch, first target position); batch -1 marks an
     // empty slot.  Workgroup k runs on die k % xcds: each die gets a spatially

@@ -345,3 +345,27 @@ def test_many_vectors_plummer_distinct_targets(dev):
                 _close(ref[i], phi[i])
             else:
                 assert oracle.rel_l2(ref[i], phi[i]) <= MIXED_REL_L2
+
+
+@pytest.mark.parametrize("m", [1, 16])
+def test_modified_charges_multi_chunk_clusters(dev, m):
+    # clusters larger than one upward-pass chunk (8192 sources) are summed over chunks
+    pos, q = inputs.uniform_cube(40000, 140 + m, m=m)
+    plan, _ = _run_plan(dev, pos, pos, q if m > 1 else q[0], theta=0.9, degree=4, leaf_size=2000,
+                        batch_size=2000)
+    oc = oracle.Treecode(pos, pos, 0.9, 4, 2000, 2000)
+    v = plan.view()
+    oorder = oc.source_order()
+    okey = {}
+    for c in range(oc.n_clusters):
+        info = oc.cluster(c)
+        okey[tuple(np.sort(oorder[info["begin"]:info["begin"] + info["count"]]))] = c
+    approx = np.unique(v["item_cluster"][v["item_kind"] == 0])
+    big = [c for c in approx if v["cluster_count"][c] > 8192]
+    assert big, "the test needs clusters that span several chunks"
+    for c in list(big) + list(approx[:5]):
+        key = tuple(np.sort(v["source_order"][v["cluster_begin"][c]:v["cluster_begin"][c] + v["cluster_count"][c]]))
+        ref = oc.modified_charges(okey[key], q)
+        for qi in ([0] if m == 1 else [0, 7, 15]):
+            got = plan.modified_charges(c, qi)
+            assert np.max(np.abs(ref[qi] - got)) <= 1e-12 * np.max(np.abs(ref[qi])), (c, qi)
