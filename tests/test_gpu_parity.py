@@ -351,9 +351,12 @@ def test_many_vectors_plummer_distinct_targets(dev):
 def test_modified_charges_multi_chunk_clusters(dev, m):
     # clusters larger than one upward-pass chunk (8192 sources) are summed over chunks
     pos, q = inputs.uniform_cube(40000, 140 + m, m=m)
-    plan, _ = _run_plan(dev, pos, pos, q if m > 1 else q[0], theta=0.9, degree=4, leaf_size=2000,
+    # a near target cloud and a distant one: the root (5 chunks) and its children are approximated
+    g = np.random.default_rng(140 + m)
+    tgt = np.concatenate([g.uniform(-1, 1, (3000, 3)), g.uniform(-1, 1, (3000, 3)) + [8.0, 1.0, 0.0]])
+    plan, _ = _run_plan(dev, tgt, pos, q if m > 1 else q[0], theta=0.9, degree=4, leaf_size=2000,
                         batch_size=2000)
-    oc = oracle.Treecode(pos, pos, 0.9, 4, 2000, 2000)
+    oc = oracle.Treecode(tgt, pos, 0.9, 4, 2000, 2000)
     v = plan.view()
     oorder = oc.source_order()
     okey = {}
