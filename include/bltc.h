@@ -175,6 +175,40 @@ int bltc_plan_view_get(const bltc_plan* plan, bltc_plan_view* out);
 
 void bltc_plan_destroy(bltc_plan* plan);
 
+/* Many independent systems in one evaluation.  A batch is built from plans
+ * (one per system; each created with max_q >= 2, all with the same kernel and
+ * precision; the plans stay owned by the caller and must outlive the batch).
+ * bltc_batch_execute evaluates, for every system i, num_q[i] <= min(16, max_q)
+ * charge vectors q[i] (device, q_ld[i]) into phi[i] (device, phi_ld[i]):
+ * per-system charge gathers, one matrix-core upward pass (eqs. 14-15) over
+ * the chunks of all systems, and ONE persistent work-queue launch over every
+ * batch/cluster work unit of every system (eqs. 9, 11), heaviest first.  The
+ * sequence is captured into a hipGraph the first time a given set of
+ * buffers/counts is seen and replayed afterwards (a new set of buffers is
+ * re-captured; that call synchronises `stream`).  Enqueued on `stream`.
+ * Calls on one batch must not overlap.  BLTC_EINVAL on mismatched plans,
+ * counts or NULL buffers. */
+typedef struct bltc_batch bltc_batch;
+
+typedef struct {
+    int32_t systems;         /* plans in the batch                                  */
+    int32_t units;           /* work-queue units (system, 256-target group)         */
+    int32_t upward_units;    /* upward-pass chunks over all systems                 */
+    int32_t workgroups;      /* persistent workgroups of the work-queue launch      */
+    int64_t graph_captures;  /* hipGraphs captured so far                           */
+    int64_t launches;        /* executions so far                                   */
+} bltc_batch_info;
+
+int bltc_batch_create(bltc_batch** out, bltc_plan* const* plans, int32_t count, void* stream);
+int bltc_batch_execute(bltc_batch* batch, const double* const* q, const int32_t* num_q,
+                       const int64_t* q_ld, double* const* phi, const int64_t* phi_ld,
+                       void* stream);
+/* enable (default) or disable the hipGraph; without it every call enqueues
+ * the launches directly */
+int bltc_batch_set_graph(bltc_batch* batch, int32_t enable);
+int bltc_batch_info_get(const bltc_batch* batch, bltc_batch_info* out);
+void bltc_batch_destroy(bltc_batch* batch);
+
 /* GPU direct sum of eq. 1 (all pairs, pairs at zero distance skipped), FP64:
  * phi[m*phi_ld + i] for m < num_q.  Diagnostic / baseline path.  Enqueued on
  * `stream`. */

@@ -17,7 +17,7 @@ import numpy as np
 from . import _capi
 from ._capi import BLTCError, InvalidArgument  # noqa: F401
 
-__all__ = ["params", "Plan", "potential", "direct", "BLTCError", "InvalidArgument",
+__all__ = ["params", "Plan", "Batch", "potential", "direct", "BLTCError", "InvalidArgument",
            "library_path", "version"]
 
 _KERNELS = {"coulomb": _capi.COULOMB, "yukawa": _capi.YUKAWA}
@@ -200,6 +200,64 @@ class Plan:
                                                   _stream_handle(stream))
         _capi.check(rc)
         return out.reshape(n1, n1, n1)
+
+
+class Batch:
+    """Many systems evaluated together (`bltc_batch_create` / `bltc_batch_execute`): one
+    persistent work-queue launch over all systems, replayed from a hipGraph.  The plans
+    must be created with max_q >= 2 and outlive the batch."""
+
+    def __init__(self, plans, stream=None):
+        lib = _capi.load()
+        self._lib = lib
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        self._h = ctypes.c_void_p()
+        _capi.check(lib.bltc_batch_create(ctypes.byref(self._h), arr, len(self.plans),
+                                          _stream_handle(stream)))
+
+    def set_graph(self, enable=True):
+        _capi.check(self._lib.bltc_batch_set_graph(self._h, 1 if enable else 0))
+
+    def info(self) -> dict:
+        inf = _capi.BatchInfo()
+        _capi.check(self._lib.bltc_batch_info_get(self._h, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in _capi.BatchInfo._fields_}
+
+    def execute(self, charges, outs=None, stream=None):
+        """charges: one (m_i, ns_i) float64 device tensor per system; returns (m_i, nt_i) tensors."""
+        torch = _torch()
+        n = len(self.plans)
+        if len(charges) != n:
+            raise ValueError("one charge tensor per system")
+        qs, outs2 = [], []
+        for i, (p, q) in enumerate(zip(self.plans, charges)):
+            q2, _ = _charges_device(q, p.ns)
+            qs.append(q2)
+            if outs is None:
+                o = torch.empty((q2.shape[0], p.nt), dtype=torch.float64, device=q2.device)
+            else:
+                o = outs[i]
+                o = o.unsqueeze(0) if o.dim() == 1 else o
+            outs2.append(o)
+        qp = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs])
+        nq = (ctypes.c_int32 * n)(*[q.shape[0] for q in qs])
+        ql = (ctypes.c_int64 * n)(*[q.stride(0) if q.shape[0] > 1 else p.ns for q, p in zip(qs, self.plans)])
+        op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs2])
+        ol = (ctypes.c_int64 * n)(*[o.stride(0) if o.shape[0] > 1 else p.nt for o, p in zip(outs2, self.plans)])
+        _capi.check(self._lib.bltc_batch_execute(self._h, qp, nq, ql, op, ol, _stream_handle(stream)))
+        return outs2
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.bltc_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def potential(targets, sources, charges, *, stream=None, out=None, **kw):

@@ -23,7 +23,9 @@ FP32_MIXED = 1
 EXPORTS = (
     "bltc_params_default", "bltc_potential", "bltc_plan_create", "bltc_plan_create_host",
     "bltc_plan_execute", "bltc_plan_modified_charges", "bltc_plan_stats", "bltc_plan_view_get",
-    "bltc_plan_set_timing", "bltc_plan_phase_times", "bltc_plan_destroy", "bltc_direct", "bltc_status_string", "bltc_last_error", "bltc_version",
+    "bltc_plan_set_timing", "bltc_plan_phase_times", "bltc_plan_destroy", "bltc_direct",
+    "bltc_batch_create", "bltc_batch_execute", "bltc_batch_set_graph", "bltc_batch_info_get",
+    "bltc_batch_destroy", "bltc_status_string", "bltc_last_error", "bltc_version",
 )
 
 
@@ -78,6 +80,17 @@ class PlanView(ctypes.Structure):
     ]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("systems", ctypes.c_int32),
+        ("units", ctypes.c_int32),
+        ("upward_units", ctypes.c_int32),
+        ("workgroups", ctypes.c_int32),
+        ("graph_captures", ctypes.c_int64),
+        ("launches", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 
@@ -107,6 +120,13 @@ def load():
     lib.bltc_plan_destroy.argtypes = [vp]
     lib.bltc_plan_destroy.restype = None
     lib.bltc_direct.argtypes = [PP, i64, vp, vp, vp, i64, vp, vp, vp, vp, i32, i64, vp, i64, vp]
+    lib.bltc_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
+    lib.bltc_batch_execute.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(i64), vp]
+    lib.bltc_batch_set_graph.argtypes = [vp, i32]
+    lib.bltc_batch_info_get.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    lib.bltc_batch_destroy.argtypes = [vp]
+    lib.bltc_batch_destroy.restype = None
     lib.bltc_status_string.argtypes = [ctypes.c_int]
     lib.bltc_status_string.restype = ctypes.c_char_p
     lib.bltc_last_error.argtypes = []
@@ -114,7 +134,8 @@ def load():
     lib.bltc_version.restype = ctypes.c_char_p
     for name in ("bltc_potential", "bltc_plan_create", "bltc_plan_create_host", "bltc_plan_execute",
                  "bltc_plan_modified_charges", "bltc_plan_stats", "bltc_plan_view_get", "bltc_direct",
-                 "bltc_plan_set_timing", "bltc_plan_phase_times"):
+                 "bltc_plan_set_timing", "bltc_plan_phase_times", "bltc_batch_create",
+                 "bltc_batch_execute", "bltc_batch_set_graph", "bltc_batch_info_get"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

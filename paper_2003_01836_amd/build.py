@@ -65,6 +65,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         "mrhs": os.path.join(build_dir, "kernels_mrhs.o"),
         "upward": os.path.join(build_dir, "kernels_upward.o"),
         "capi": os.path.join(build_dir, "capi.o"),
+        "batch": os.path.join(build_dir, "batch.o"),
     }
     cmds = [
         ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
@@ -76,6 +77,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         [hipcc] + hip_flags + ["-mllvm", "-amdgpu-mfma-vgpr-form",
                                "-c", os.path.join(CSRC, "kernels_upward.hip"), "-o", objs["upward"]],
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "capi.cpp"), "-o", objs["capi"]],
+        [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "batch.cpp"), "-o", objs["batch"]],
     ]
     if verbose:
         for c in cmds:

@@ -13,35 +13,12 @@
 #include <string>
 #include <vector>
 
-#include "kernels.hpp"
-#include "planner.hpp"
+#include "internal.hpp"
+
+using bltc_detail::fail;
+using bltc_detail::hip_fail;
 
 namespace {
-
-thread_local std::string g_last_error;
-
-int fail(int code, const char* fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    std::vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return code;
-}
-
-int hip_fail(hipError_t e, const char* what)
-{
-    return fail(BLTC_EHIP, "%s: %s", what, hipGetErrorString(e));
-}
-
-#define HIP_TRY(call)                                   \
-    do {                                                \
-        hipError_t e_ = (call);                         \
-        if (e_ != hipSuccess)                           \
-            return hip_fail(e_, #call);                 \
-    } while (0)
 
 int check_params(const bltc_params* p)
 {
@@ -82,59 +59,8 @@ int check_finite(int64_t n, const double* x, const double* y, const double* z, c
     return BLTC_OK;
 }
 
-template <class T>
-hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s)
-{
-    const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), bytes);
-    if (e != hipSuccess)
-        return e;
-    if (!v.empty())
-        e = hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
-    return e;
-}
 
 }  // namespace
-
-struct bltc_plan {
-    bltc_params prm{};
-    int32_t max_q = 1;
-    bltc::HostPlan hp;
-    bool uploaded = false;
-    int device = -1;
-    bltc::DevicePlan d;
-    std::vector<void*> allocations;
-    bool timing = false;
-    int32_t last_q = 0;                  // charge vectors of the last execution
-    int32_t timed_q = 0;                 // charge vectors covered by the recorded events
-    std::vector<hipEvent_t> events;      // 4 per charge vector
-
-    ~bltc_plan()
-    {
-        for (hipEvent_t e : events)
-            (void)hipEventDestroy(e);
-        for (void* p : allocations)
-            (void)hipFree(p);
-    }
-
-    template <class T>
-    hipError_t put(T** dst, const std::vector<T>& v, hipStream_t s)
-    {
-        hipError_t e = upload(dst, v, s);
-        if (e == hipSuccess)
-            allocations.push_back(*dst);
-        return e;
-    }
-
-    template <class T>
-    hipError_t alloc(T** dst, size_t count)
-    {
-        hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(1, count) * sizeof(T));
-        if (e == hipSuccess)
-            allocations.push_back(*dst);
-        return e;
-    }
-};
 
 namespace {
 
@@ -154,7 +80,9 @@ int make_host_plan(bltc_plan* plan, const bltc_params* p, int64_t nt, const doub
     return BLTC_OK;
 }
 
-int upload_plan(bltc_plan* plan, hipStream_t s)
+}  // namespace
+
+int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
 {
     if (plan->uploaded)
         return BLTC_OK;
@@ -269,6 +197,8 @@ int upload_plan(bltc_plan* plan, hipStream_t s)
     return BLTC_OK;
 }
 
+namespace {
+
 int zero_phi(int64_t nt, int32_t num_q, double* phi, int64_t phi_ld, hipStream_t s)
 {
     for (int32_t m = 0; m < num_q; ++m)
@@ -295,7 +225,7 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
         return fail(BLTC_EINVAL, "q is NULL");
     if (q_ld < ns && num_q > 1)
         return fail(BLTC_EINVAL, "q_ld must be >= ns");
-    int rc = upload_plan(plan, s);
+    int rc = bltc_internal_upload_plan(plan, s);
     if (rc != BLTC_OK)
         return rc;
     int dev = -1;
@@ -485,7 +415,7 @@ int bltc_plan_create(bltc_plan** out, const bltc_params* p, int64_t nt, const do
     if (rc != BLTC_OK)
         return rc;
     try {
-        rc = upload_plan(*out, s);
+        rc = bltc_internal_upload_plan(*out, s);
     } catch (const std::bad_alloc&) {
         rc = fail(BLTC_ENOMEM, "host allocation failed while uploading");
     }
@@ -711,7 +641,7 @@ const char* bltc_status_string(int code)
 
 const char* bltc_last_error(void)
 {
-    return g_last_error.c_str();
+    return bltc_detail::last_error().c_str();
 }
 
 const char* bltc_version(void)

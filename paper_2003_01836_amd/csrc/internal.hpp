@@ -1,0 +1,103 @@
+// internal.hpp -- definitions shared by the C-ABI sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "bltc.h"
+#include "kernels.hpp"
+#include "planner.hpp"
+
+namespace bltc_detail {
+
+inline std::string& last_error()
+{
+    static thread_local std::string msg;
+    return msg;
+}
+
+inline int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    last_error() = buf;
+    return code;
+}
+
+inline int hip_fail(hipError_t e, const char* what)
+{
+    return fail(BLTC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s)
+{
+    const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), bytes);
+    if (e != hipSuccess)
+        return e;
+    if (!v.empty())
+        e = hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    return e;
+}
+
+}  // namespace bltc_detail
+
+#define HIP_TRY(call)                                              \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess)                                      \
+            return bltc_detail::hip_fail(e_, #call);               \
+    } while (0)
+
+struct bltc_plan {
+    bltc_params prm{};
+    int32_t max_q = 1;
+    bltc::HostPlan hp;
+    bool uploaded = false;
+    int device = -1;
+    bltc::DevicePlan d;
+    std::vector<void*> allocations;
+    bool timing = false;
+    int32_t last_q = 0;                  // charge vectors of the last execution
+    int32_t timed_q = 0;                 // charge vectors covered by the recorded events
+    std::vector<hipEvent_t> events;      // 4 per charge vector
+
+    ~bltc_plan()
+    {
+        for (hipEvent_t e : events)
+            (void)hipEventDestroy(e);
+        for (void* p : allocations)
+            (void)hipFree(p);
+    }
+
+    template <class T>
+    hipError_t put(T** dst, const std::vector<T>& v, hipStream_t s)
+    {
+        hipError_t e = bltc_detail::upload(dst, v, s);
+        if (e == hipSuccess)
+            allocations.push_back(*dst);
+        return e;
+    }
+
+    template <class T>
+    hipError_t alloc(T** dst, size_t count)
+    {
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(1, count) * sizeof(T));
+        if (e == hipSuccess)
+            allocations.push_back(*dst);
+        return e;
+    }
+};
+
+
+// device side of a plan (uploads on first use); synchronises the stream
+int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s);

@@ -53,6 +53,38 @@ struct DevicePlan {
     float* qhat16f = nullptr;         // [slot][P][16] (mixed precision)
 };
 
+// Everything the multi-vector interaction of one system needs (passed by value
+// to a kernel, or as an array for the work-queue kernel).
+struct MrhsDesc {
+    const double4* tgt;
+    const int64_t* tgt_orig;
+    const double4* src;
+    const float4* src32;
+    const double* qm;
+    const float* qm32;
+    const double4* node_info;
+    const double4* batch_info;
+    const int32_t* group_batch;
+    const int64_t* group_first;
+    const int64_t* batch_end;
+    const int32_t* far_off;
+    const int32_t* far_slot;
+    const int32_t* near_off;
+    const int64_t* near_begin;
+    const int64_t* near_count;
+    const int32_t* near_leaf;
+    const int32_t* slot_cluster;
+    const double4* proxies;
+    const float4* proxies32;
+    const double* qhat16;
+    const float* qhat16f;
+    double* phi;
+    int64_t phi_ld;
+    int32_t np;
+    int32_t mc;
+    double kappa;
+};
+
 struct KernelParams {
     int32_t kernel = 0;     // 0 Coulomb, 1 Yukawa
     int32_t precision = 0;  // 0 FP64, 1 FP32-mixed
@@ -66,6 +98,25 @@ hipError_t launch_gather_charges(const DevicePlan& d, const double* q, hipStream
 // buf holds nslots final rows followed by the partial rows of multi-chunk slots
 hipError_t launch_upward_mfma(const DevicePlan& d, int32_t mw, double* buf, float* qhat32,
                               hipStream_t s);
+// pieces of the same for many systems in one launch (unit = system, chunk)
+struct UpwardDesc {
+    const double4* src;
+    const double* qm;
+    const int32_t* chunk_slot;
+    const int64_t* chunk_begin;
+    const int64_t* chunk_count;
+    const int64_t* chunk_dst;
+    const double* slot_nodes;
+    double* buf;
+    int32_t np;
+};
+size_t upward_lds_bytes(int32_t np, int32_t mw);
+int32_t upward_passes(int32_t np, int32_t mw);
+hipError_t upward_prepare(size_t lds);
+hipError_t launch_upward_many(const UpwardDesc* descs, const int2* units, int32_t nunits,
+                              int32_t mw, int32_t passes, size_t lds, hipStream_t s);
+hipError_t launch_upward_reduce(const DevicePlan& d, int32_t mw, double* buf, float* qhat32,
+                                hipStream_t s);
 // batch/cluster interactions: eqs. 9 and 11, phi written in caller order
 hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* phi,
                            hipStream_t s);
@@ -79,6 +130,14 @@ hipError_t launch_gather_charges16(const DevicePlan& d, const double* q, int64_t
                                    hipStream_t s);
 hipError_t launch_interact_mrhs(const DevicePlan& d, const KernelParams& kp, double* phi,
                                 int64_t phi_ld, int32_t mc, hipStream_t s);
+MrhsDesc make_mrhs_desc(const DevicePlan& d, const KernelParams& kp, double* phi, int64_t phi_ld,
+                        int32_t mc);
+// work queue over (system, group) units of many systems; counter reset first
+hipError_t launch_reset_counter(int32_t* counter, hipStream_t s);
+hipError_t launch_interact_queue(const MrhsDesc* descs, const int2* units, int32_t nunits,
+                                 int32_t* counter, const KernelParams& kp, int32_t workgroups,
+                                 hipStream_t s);
+const void* interact_queue_symbol(const KernelParams& kp);
 // GPU direct sum (eq. 1) of all targets against packed sources
 hipError_t launch_pack_sources(int64_t ns, const double* x, const double* y, const double* z,
                                const double* q, double4* out, hipStream_t s);

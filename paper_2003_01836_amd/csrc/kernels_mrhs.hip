@@ -48,22 +48,29 @@ __device__ __forceinline__ float green_f32(float r2, float rinv, float neg_kappa
 // FP64: G in FP64 on the VALU, contraction on v_mfma_f64_16x16x4f64.
 // ---------------------------------------------------------------------------
 template <int KER>
-__global__ __launch_bounds__(kGroupSize) void interact_mrhs_f64(
-    const double4* __restrict__ tgt, const int64_t* __restrict__ tgt_orig,
-    const double4* __restrict__ src, const double* __restrict__ qm,
-    const int32_t* __restrict__ group_batch, const int64_t* __restrict__ group_first,
-    const int64_t* __restrict__ batch_end, const int32_t* __restrict__ far_off,
-    const int32_t* __restrict__ far_slot, const int32_t* __restrict__ near_off,
-    const int64_t* __restrict__ near_begin, const int64_t* __restrict__ near_count,
-    const double4* __restrict__ proxies, const double* __restrict__ qhat16, int32_t np,
-    double* __restrict__ phi, int64_t phi_ld, int32_t m_count, double kappa)
+__device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g)
 {
-    const int g = blockIdx.x;
-    const int b = group_batch[g];
+    const double4* __restrict__ tgt = d.tgt;
+    const int64_t* __restrict__ tgt_orig = d.tgt_orig;
+    const double4* __restrict__ src = d.src;
+    const double* __restrict__ qm = d.qm;
+    const int32_t* __restrict__ far_off = d.far_off;
+    const int32_t* __restrict__ far_slot = d.far_slot;
+    const int32_t* __restrict__ near_off = d.near_off;
+    const int64_t* __restrict__ near_begin = d.near_begin;
+    const int64_t* __restrict__ near_count = d.near_count;
+    const double4* __restrict__ proxies = d.proxies;
+    const double* __restrict__ qhat16 = d.qhat16;
+    double* __restrict__ phi = d.phi;
+    const int32_t np = d.np;
+    const int64_t phi_ld = d.phi_ld;
+    const int32_t m_count = d.mc;
+    const double kappa = d.kappa;
+    const int b = d.group_batch[g];
     if (b < 0)
         return;
-    const int64_t first = group_first[g];
-    const int64_t end = batch_end[b];
+    const int64_t first = d.group_first[g];
+    const int64_t end = d.batch_end[b];
     const int64_t wave_first = first + (threadIdx.x & ~63);
     if (wave_first >= end)
         return;
@@ -164,25 +171,34 @@ __device__ __forceinline__ void flush_f32(f4v (&part)[4], double (&acc)[4][4])
 }
 
 template <int KER>
-__global__ __launch_bounds__(kGroupSize) void interact_mrhs_mixed(
-    const double4* __restrict__ tgt, const int64_t* __restrict__ tgt_orig,
-    const double4* __restrict__ src, const float4* __restrict__ src32,
-    const float* __restrict__ qm32, const double4* __restrict__ node_info,
-    const double4* __restrict__ batch_info, const int32_t* __restrict__ group_batch,
-    const int64_t* __restrict__ group_first, const int64_t* __restrict__ batch_end,
-    const int32_t* __restrict__ far_off, const int32_t* __restrict__ far_slot,
-    const int32_t* __restrict__ near_off, const int64_t* __restrict__ near_begin,
-    const int64_t* __restrict__ near_count, const int32_t* __restrict__ near_leaf,
-    const int32_t* __restrict__ slot_cluster, const float4* __restrict__ proxies32,
-    const float* __restrict__ qhat16, int32_t np, double* __restrict__ phi, int64_t phi_ld,
-    int32_t m_count, double kappa)
+__device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g)
 {
-    const int g = blockIdx.x;
-    const int b = group_batch[g];
+    const double4* __restrict__ tgt = d.tgt;
+    const int64_t* __restrict__ tgt_orig = d.tgt_orig;
+    const double4* __restrict__ src = d.src;
+    const float4* __restrict__ src32 = d.src32;
+    const float* __restrict__ qm32 = d.qm32;
+    const double4* __restrict__ node_info = d.node_info;
+    const double4* __restrict__ batch_info = d.batch_info;
+    const int32_t* __restrict__ far_off = d.far_off;
+    const int32_t* __restrict__ far_slot = d.far_slot;
+    const int32_t* __restrict__ near_off = d.near_off;
+    const int64_t* __restrict__ near_begin = d.near_begin;
+    const int64_t* __restrict__ near_count = d.near_count;
+    const int32_t* __restrict__ near_leaf = d.near_leaf;
+    const int32_t* __restrict__ slot_cluster = d.slot_cluster;
+    const float4* __restrict__ proxies32 = d.proxies32;
+    const float* __restrict__ qhat16 = d.qhat16f;
+    double* __restrict__ phi = d.phi;
+    const int32_t np = d.np;
+    const int64_t phi_ld = d.phi_ld;
+    const int32_t m_count = d.mc;
+    const double kappa = d.kappa;
+    const int b = d.group_batch[g];
     if (b < 0)
         return;
-    const int64_t first = group_first[g];
-    const int64_t end = batch_end[b];
+    const int64_t first = d.group_first[g];
+    const int64_t end = d.batch_end[b];
     const int64_t wave_first = first + (threadIdx.x & ~63);
     if (wave_first >= end)
         return;
@@ -321,6 +337,49 @@ __global__ __launch_bounds__(kGroupSize) void interact_mrhs_mixed(
     }
 }
 
+template <int KER, int PREC>
+__global__ __launch_bounds__(kGroupSize) void interact_mrhs(MrhsDesc d)
+{
+    if constexpr (PREC == 0)
+        group_mrhs_f64<KER>(d, blockIdx.x);
+    else
+        group_mrhs_mixed<KER>(d, blockIdx.x);
+}
+
+// Persistent work queue over the groups of many systems: every workgroup
+// repeatedly takes the next unit (system, group) -- heaviest first -- until
+// the queue is empty.  The counter is reset by reset_counter before a launch.
+template <int KER, int PREC>
+__global__ __launch_bounds__(kGroupSize) void interact_queue(const MrhsDesc* __restrict__ descs,
+                                                             const int2* __restrict__ units,
+                                                             int32_t nunits,
+                                                             int32_t* __restrict__ counter)
+{
+    __shared__ int32_t next;
+    for (;;) {
+        if (threadIdx.x == 0)
+            next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t u = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();
+        if (u >= nunits)
+            break;
+        const int2 w = units[u];
+        const int32_t sys = __builtin_amdgcn_readfirstlane(w.x);
+        const int32_t g = __builtin_amdgcn_readfirstlane(w.y);
+        if constexpr (PREC == 0)
+            group_mrhs_f64<KER>(descs[sys], g);
+        else
+            group_mrhs_mixed<KER>(descs[sys], g);
+    }
+}
+
+__global__ void reset_counter(int32_t* counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        counter[0] = 0;
+}
+
 // charges of up to 16 vectors into tree order, padded with zeros:
 // qm[j][m] = q[(m0 + m) * q_ld + order[j]] for m < mc
 __global__ __launch_bounds__(256) void gather_charges16(double* __restrict__ qm,
@@ -353,33 +412,95 @@ hipError_t launch_gather_charges16(const DevicePlan& d, const double* q, int64_t
     return hipGetLastError();
 }
 
+MrhsDesc make_mrhs_desc(const DevicePlan& d, const KernelParams& kp, double* phi, int64_t phi_ld,
+                        int32_t mc)
+{
+    MrhsDesc m;
+    m.tgt = d.tgt;
+    m.tgt_orig = d.tgt_orig;
+    m.src = d.src;
+    m.src32 = d.src32;
+    m.qm = d.qm;
+    m.qm32 = d.qm32;
+    m.node_info = d.node_info;
+    m.batch_info = d.batch_info;
+    m.group_batch = d.group_batch;
+    m.group_first = d.group_first;
+    m.batch_end = d.batch_end;
+    m.far_off = d.far_off;
+    m.far_slot = d.far_slot;
+    m.near_off = d.near_off;
+    m.near_begin = d.near_begin;
+    m.near_count = d.near_count;
+    m.near_leaf = d.near_leaf;
+    m.slot_cluster = d.slot_cluster;
+    m.proxies = d.proxies;
+    m.proxies32 = d.proxies32;
+    m.qhat16 = d.qhat16;
+    m.qhat16f = d.qhat16f;
+    m.phi = phi;
+    m.phi_ld = phi_ld;
+    m.np = d.degree + 1;
+    m.mc = mc;
+    m.kappa = kp.kappa;
+    return m;
+}
+
+static bool mrhs_tables_ok(const DevicePlan& d, int32_t precision)
+{
+    if (precision == 1)
+        return d.src32 && d.qm32 && d.qhat16f && d.proxies32 && d.node_info && d.batch_info;
+    return d.qm && d.qhat16 && d.proxies;
+}
+
 hipError_t launch_interact_mrhs(const DevicePlan& d, const KernelParams& kp, double* phi,
                                 int64_t phi_ld, int32_t mc, hipStream_t s)
 {
     if (d.ngroups == 0)
         return hipSuccess;
-    const int32_t np = d.degree + 1;
+    if (!mrhs_tables_ok(d, kp.precision))
+        return hipErrorInvalidValue;
+    const MrhsDesc m = make_mrhs_desc(d, kp, phi, phi_ld, mc);
     const dim3 grid(static_cast<unsigned>(d.ngroups)), block(kGroupSize);
     const bool yuk = kp.kernel == 1;
-    if (kp.precision == 1) {
-        if (!d.src32 || !d.qm32 || !d.qhat16f || !d.proxies32)
-            return hipErrorInvalidValue;
-        auto k = yuk ? interact_mrhs_mixed<1> : interact_mrhs_mixed<0>;
-        hipLaunchKernelGGL(k, grid, block, 0, s, d.tgt, d.tgt_orig, d.src, d.src32, d.qm32,
-                           d.node_info, d.batch_info, d.group_batch, d.group_first, d.batch_end,
-                           d.far_off, d.far_slot, d.near_off, d.near_begin, d.near_count,
-                           d.near_leaf, d.slot_cluster, d.proxies32, d.qhat16f, np, phi, phi_ld,
-                           mc, kp.kappa);
-    } else {
-        if (!d.qm || !d.qhat16 || !d.proxies)
-            return hipErrorInvalidValue;
-        auto k = yuk ? interact_mrhs_f64<1> : interact_mrhs_f64<0>;
-        hipLaunchKernelGGL(k, grid, block, 0, s, d.tgt, d.tgt_orig, d.src, d.qm, d.group_batch,
-                           d.group_first, d.batch_end, d.far_off, d.far_slot, d.near_off,
-                           d.near_begin, d.near_count, d.proxies, d.qhat16, np, phi, phi_ld, mc,
-                           kp.kappa);
-    }
+    if (kp.precision == 1)
+        hipLaunchKernelGGL(yuk ? (interact_mrhs<1, 1>) : (interact_mrhs<0, 1>), grid, block, 0, s, m);
+    else
+        hipLaunchKernelGGL(yuk ? (interact_mrhs<1, 0>) : (interact_mrhs<0, 0>), grid, block, 0, s, m);
     return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(int32_t* counter, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_interact_queue(const MrhsDesc* descs, const int2* units, int32_t nunits,
+                                 int32_t* counter, const KernelParams& kp, int32_t workgroups,
+                                 hipStream_t s)
+{
+    if (nunits == 0)
+        return hipSuccess;
+    const dim3 grid(static_cast<unsigned>(workgroups)), block(kGroupSize);
+    const bool yuk = kp.kernel == 1;
+    if (kp.precision == 1)
+        hipLaunchKernelGGL(yuk ? (interact_queue<1, 1>) : (interact_queue<0, 1>), grid, block, 0, s,
+                           descs, units, nunits, counter);
+    else
+        hipLaunchKernelGGL(yuk ? (interact_queue<1, 0>) : (interact_queue<0, 0>), grid, block, 0, s,
+                           descs, units, nunits, counter);
+    return hipGetLastError();
+}
+
+const void* interact_queue_symbol(const KernelParams& kp)
+{
+    const bool yuk = kp.kernel == 1;
+    if (kp.precision == 1)
+        return yuk ? reinterpret_cast<const void*>(interact_queue<1, 1>)
+                   : reinterpret_cast<const void*>(interact_queue<0, 1>);
+    return yuk ? reinterpret_cast<const void*>(interact_queue<1, 0>)
+               : reinterpret_cast<const void*>(interact_queue<0, 0>);
 }
 
 }  // namespace bltc

@@ -55,13 +55,13 @@ __device__ __forceinline__ double factors_rt(double yv, const double* __restrict
 // modified charges of single-chunk clusters, the others partial sums).
 // Tiles are dealt round-robin to the 4 waves: wave w of tile pass p owns
 // tiles p * 32 + w + 4u, u < 8.
-__global__ __launch_bounds__(256) void upward_mfma_f64(
+__device__ __forceinline__ void upward_chunk(
     const double4* __restrict__ src, const double* __restrict__ qm, int32_t mw,
     const int32_t* __restrict__ chunk_slot, const int64_t* __restrict__ chunk_begin,
     const int64_t* __restrict__ chunk_count, const int64_t* __restrict__ chunk_dst,
-    const double* __restrict__ slot_nodes, int32_t np, double* __restrict__ out)
+    const double* __restrict__ slot_nodes, int32_t np, double* __restrict__ out, int c, int pass,
+    double* __restrict__ lds)
 {
-    extern __shared__ double lds[];
     const int np2 = np * np;
     const int P = np2 * np;
     double* __restrict__ A1 = lds;                   // [kTile][np]
@@ -70,7 +70,6 @@ __global__ __launch_bounds__(256) void upward_mfma_f64(
     double* __restrict__ SQ = A3 + kTile * np;       // [kTile][mw]  q~
     double* __restrict__ SN = SQ + kTile * mw;       // [3][np]      nodes
 
-    const int c = blockIdx.x;
     const int64_t slot = chunk_slot[c];
     const int64_t begin = chunk_begin[c];
     const int64_t count = chunk_count[c];
@@ -84,7 +83,7 @@ __global__ __launch_bounds__(256) void upward_mfma_f64(
     const int RT = (R + 15) / 16;
     const int CT = (np2 + 15) / 16;         // columns (k2, k3)
     const int T = RT * CT;
-    const int tbase = blockIdx.y * kTilesPerGroup + wave;
+    const int tbase = pass * kTilesPerGroup + wave;
 
     // per owned tile: LDS offsets of this lane's row factor and column factors
     int rk1[kTilesPerWave], rm[kTilesPerWave], ck2[kTilesPerWave], ck3[kTilesPerWave];
@@ -176,6 +175,33 @@ __global__ __launch_bounds__(256) void upward_mfma_f64(
     }
 }
 
+__global__ __launch_bounds__(256) void upward_mfma_f64(
+    const double4* __restrict__ src, const double* __restrict__ qm, int32_t mw,
+    const int32_t* __restrict__ chunk_slot, const int64_t* __restrict__ chunk_begin,
+    const int64_t* __restrict__ chunk_count, const int64_t* __restrict__ chunk_dst,
+    const double* __restrict__ slot_nodes, int32_t np, double* __restrict__ out)
+{
+    extern __shared__ double lds[];
+    upward_chunk(src, qm, mw, chunk_slot, chunk_begin, chunk_count, chunk_dst, slot_nodes, np, out,
+                 blockIdx.x, blockIdx.y, lds);
+}
+
+// the chunks of many systems in one launch: unit = (system, chunk)
+__global__ __launch_bounds__(256) void upward_mfma_f64_many(const UpwardDesc* __restrict__ descs,
+                                                            const int2* __restrict__ units,
+                                                            int32_t mw)
+{
+    extern __shared__ double lds[];
+    const int2 w = units[blockIdx.x];
+    const UpwardDesc& d = descs[__builtin_amdgcn_readfirstlane(w.x)];
+    const int32_t np2 = d.np * d.np;
+    const int32_t tiles = ((d.np * mw + 15) / 16) * ((np2 + 15) / 16);
+    if (static_cast<int32_t>(blockIdx.y) * kTilesPerGroup >= tiles)
+        return;  // this system needs fewer tile passes (uniform over the workgroup)
+    upward_chunk(d.src, d.qm, mw, d.chunk_slot, d.chunk_begin, d.chunk_count, d.chunk_dst,
+                 d.slot_nodes, d.np, d.buf, __builtin_amdgcn_readfirstlane(w.y), blockIdx.y, lds);
+}
+
 // qhat (and its FP32 copy) of every slot: the chunk result already in place
 // for single-chunk clusters, else the sum of the partials in chunk order
 __global__ __launch_bounds__(256) void upward_mfma_reduce(
@@ -203,38 +229,71 @@ __global__ __launch_bounds__(256) void upward_mfma_reduce(
 
 }  // namespace
 
-hipError_t launch_upward_mfma(const DevicePlan& d, int32_t mw, double* buf, float* qhat32,
-                              hipStream_t s)
+size_t upward_lds_bytes(int32_t np, int32_t mw)
 {
-    if (d.nchunks == 0)
+    return sizeof(double) *
+           (static_cast<size_t>(3) * kTile * np + static_cast<size_t>(kTile) * mw + 3 * np);
+}
+
+int32_t upward_passes(int32_t np, int32_t mw)
+{
+    const int32_t T = ((np * mw + 15) / 16) * ((np * np + 15) / 16);
+    return (T + kTilesPerGroup - 1) / kTilesPerGroup;
+}
+
+hipError_t upward_prepare(size_t lds)
+{
+    if (lds <= 65536)
         return hipSuccess;
-    const int32_t np = d.degree + 1;
-    const int32_t np2 = np * np;
-    const int32_t R = np * mw;
-    const int32_t T = ((R + 15) / 16) * ((np2 + 15) / 16);
-    const int32_t passes = (T + kTilesPerGroup - 1) / kTilesPerGroup;
-    const size_t lds = sizeof(double) * (static_cast<size_t>(3) * kTile * np +
-                                         static_cast<size_t>(kTile) * mw + 3 * np);
-    if (lds > 65536) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(upward_mfma_f64),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           static_cast<int>(lds));
-        if (a != hipSuccess)
-            return a;
-    }
-    hipLaunchKernelGGL(upward_mfma_f64, dim3(static_cast<unsigned>(d.nchunks), passes), dim3(256),
-                       lds, s, d.src, d.qm, mw, d.chunk_slot, d.chunk_begin, d.chunk_count,
-                       d.chunk_dst, d.slot_nodes, np, buf);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(upward_mfma_f64),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
     if (e != hipSuccess)
         return e;
-    const int64_t per_slot = static_cast<int64_t>(np2) * np * mw;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(upward_mfma_f64_many),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+}
+
+hipError_t launch_upward_reduce(const DevicePlan& d, int32_t mw, double* buf, float* qhat32,
+                                hipStream_t s)
+{
+    const int32_t np = d.degree + 1;
+    const int64_t per_slot = static_cast<int64_t>(np) * np * np * mw;
     const int64_t total = d.nslots * per_slot;
     if (total == 0)
         return hipSuccess;
     hipLaunchKernelGGL(upward_mfma_reduce, dim3(static_cast<unsigned>((total + 255) / 256)),
                        dim3(256), 0, s, d.slot_chunk_off, d.chunk_dst, buf, qhat32, d.nslots,
                        per_slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_upward_mfma(const DevicePlan& d, int32_t mw, double* buf, float* qhat32,
+                              hipStream_t s)
+{
+    if (d.nchunks == 0)
+        return hipSuccess;
+    const int32_t np = d.degree + 1;
+    const size_t lds = upward_lds_bytes(np, mw);
+    hipError_t e = upward_prepare(lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(upward_mfma_f64, dim3(static_cast<unsigned>(d.nchunks), upward_passes(np, mw)),
+                       dim3(256), lds, s, d.src, d.qm, mw, d.chunk_slot, d.chunk_begin,
+                       d.chunk_count, d.chunk_dst, d.slot_nodes, np, buf);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return launch_upward_reduce(d, mw, buf, qhat32, s);
+}
+
+hipError_t launch_upward_many(const UpwardDesc* descs, const int2* units, int32_t nunits,
+                              int32_t mw, int32_t passes, size_t lds, hipStream_t s)
+{
+    if (nunits == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(upward_mfma_f64_many, dim3(static_cast<unsigned>(nunits), passes), dim3(256),
+                       lds, s, descs, units, mw);
     return hipGetLastError();
 }
 

@@ -372,3 +372,88 @@ def test_modified_charges_multi_chunk_clusters(dev, m):
         for qi in ([0] if m == 1 else [0, 7, 15]):
             got = plan.modified_charges(c, qi)
             assert np.max(np.abs(ref[qi] - got)) <= 1e-12 * np.max(np.abs(ref[qi])), (c, qi)
+
+
+# --------------------------------------------------------------------------
+# many systems in one work-queue launch, replayed from a hipGraph
+# --------------------------------------------------------------------------
+def _systems(seed, sizes, m):
+    out = []
+    for k, n in enumerate(sizes):
+        if k % 3 == 2:
+            pos, q = inputs.plummer_sphere(n, seed + k, m=m)
+        else:
+            pos, q = inputs.uniform_cube(n, seed + k, m=m)
+        out.append((pos, q))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_batch_graph_replays_match_oracle(dev, precision):
+    import paper_2003_01836_amd as bltc
+    sizes = [3000, 17000, 800, 9000, 25000, 5000]
+    systems = _systems(500, sizes, 16)
+    plans, qd, refs = [], [], []
+    for k, (pos, q) in enumerate(systems):
+        leaf = 400 if k % 2 else 700
+        t = _dev_soa(pos, dev)
+        plans.append(bltc.Plan(t, t, theta=0.7, degree=6, leaf_size=leaf, batch_size=leaf, max_q=16,
+                               precision=precision))
+        mk = 16 if k != 3 else 5                   # one system with fewer vectors
+        qd.append(torch.from_numpy(np.ascontiguousarray(q[:mk])).to(dev))
+        refs.append(oracle.Treecode(pos, pos, 0.7, 6, leaf, leaf).potential(q[:mk]))
+    batch = bltc.Batch(plans)
+    outs = [torch.empty((qd[k].shape[0], sizes[k]), dtype=torch.float64, device=dev) for k in range(6)]
+    first = None
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        batch.execute(qd, outs)
+        torch.cuda.synchronize()
+        got = [o.cpu().numpy() for o in outs]
+        for k in range(6):
+            for i in range(qd[k].shape[0]):
+                if precision == "fp64":
+                    _close(refs[k][i], got[k][i])
+                else:
+                    assert oracle.rel_l2(refs[k][i], got[k][i]) <= MIXED_REL_L2
+        if first is None:
+            first = got
+        else:
+            for a, b in zip(first, got):
+                assert np.array_equal(a, b)         # every replay identical
+        # eager work between replays
+        plans[0].execute(qd[0][:3].contiguous())
+        torch.cuda.synchronize()
+    info = batch.info()
+    assert info["graph_captures"] == 1 and info["launches"] == 3 and info["systems"] == 6
+    # the same without the graph
+    batch.set_graph(False)
+    batch.execute(qd, outs)
+    torch.cuda.synchronize()
+    for a, o in zip(first, outs):
+        assert np.array_equal(a, o.cpu().numpy())
+    # new output buffers: captured again
+    batch.set_graph(True)
+    outs2 = [torch.empty_like(o) for o in outs]
+    batch.execute(qd, outs2)
+    torch.cuda.synchronize()
+    for a, o in zip(first, outs2):
+        assert np.array_equal(a, o.cpu().numpy())
+    assert batch.info()["graph_captures"] == 2
+
+
+def test_batch_rejects_bad_plans(dev):
+    import paper_2003_01836_amd as bltc
+    pos, q = inputs.uniform_cube(2000, 600)
+    t = _dev_soa(pos, dev)
+    p1 = bltc.Plan(t, t, max_q=1, leaf_size=200, batch_size=200)
+    with pytest.raises(bltc.InvalidArgument):
+        bltc.Batch([p1])
+    p2 = bltc.Plan(t, t, max_q=4, leaf_size=200, batch_size=200)
+    p3 = bltc.Plan(t, t, max_q=4, leaf_size=200, batch_size=200, precision="fp32_mixed")
+    with pytest.raises(bltc.InvalidArgument):
+        bltc.Batch([p2, p3])
+    b = bltc.Batch([p2])
+    with pytest.raises(bltc.InvalidArgument):
+        b.execute([torch.zeros((5, 2000), dtype=torch.float64, device=dev)])   # 5 > max_q
