@@ -52,12 +52,151 @@ WORKLOADS = {
 }
 
 
+def run_batched(args, dev):
+    """64 independent systems (sizes log-uniform in [1e4, 1e6], uniform cubes), 16 charge
+    vectors each, theta 0.7, n 8, leaf/batch size from the library's autotuner, one
+    persistent work-queue launch per evaluation replayed from a hipGraph."""
+    import numpy as np
+    import torch
+
+    import paper_2003_01836_amd as bltc
+    from paper_2003_01836_amd import inputs
+
+    prec = "fp32_mixed" if args.precision == "fp32_mixed" else "fp64"
+    sizes = inputs.log_uniform_sizes(64, inputs.config_seed(3))
+    log(f"batched: {len(sizes)} systems, {int(sizes.sum())} particles, 16 vectors, {prec}")
+    plans, qs, outs, pos_all, q_all, leaves = [], [], [], [], [], []
+    t_tune = 0.0
+    for k, n in enumerate(sizes):
+        pos, q = inputs.uniform_cube(int(n), inputs.config_seed(3) * 100 + k, m=16)
+        t = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
+        t0 = time.perf_counter()
+        leaf, _ = bltc.autotune(t, t, (1000, 2000, 3000, 4000), num_q=16, theta=0.7, degree=8,
+                                precision=prec)
+        t_tune += time.perf_counter() - t0
+        leaves.append(leaf)
+        plans.append(bltc.Plan(t, t, theta=0.7, degree=8, leaf_size=leaf, batch_size=leaf,
+                               precision=prec, max_q=16))
+        qs.append(torch.from_numpy(q).to(dev))
+        outs.append(torch.empty((16, int(n)), dtype=torch.float64, device=dev))
+        pos_all.append(pos)
+        q_all.append(q)
+    batch = bltc.Batch(plans)
+    for _ in range(args.warmup):
+        batch.execute(qs, outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.execute(qs, outs)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    total = int(sizes.sum())
+    errs = []
+    if not args.no_cpu:
+        import oracle
+        for k in range(0, 64, 8):
+            smp = inputs.sample_indices(int(sizes[k]), 200, inputs.sample_seed(3) + k)
+            oc = oracle.Treecode(pos_all[k], pos_all[k], 0.7, 8, leaves[k], leaves[k])
+            ref = oc.potential(q_all[k][:2], sample=smp)
+            got = outs[k][:2].cpu().numpy()[:, smp]
+            errs.append(max(rel_l2(ref[i], got[i]) for i in range(2)))
+    info = batch.info()
+    return {"workload": "batched-64x16", "precision": prec, "systems": 64, "particles": total,
+            "vectors": 16, "ms_per_step": ms, "targets_per_s": total / (ms * 1e-3),
+            "target_vectors_per_s": 16 * total / (ms * 1e-3), "autotune_s": t_tune,
+            "leaf_sizes": sorted(set(leaves)), "units": info["units"],
+            "workgroups": info["workgroups"], "graph_captures": info["graph_captures"],
+            "E_par_max_sampled": max(errs) if errs else None}
+
+
+def run_sweep(args, dev):
+    """Yukawa (kappa 0.5) on 2e6 Plummer-sphere particles: theta x n sweep, both paths.
+    Errors against the FP64 oracle (treecode) on 1000 sampled targets."""
+    import numpy as np
+    import torch
+
+    import paper_2003_01836_amd as bltc
+    from paper_2003_01836_amd import inputs
+
+    n = 2_000_000
+    pos, q = inputs.plummer_sphere(n, inputs.config_seed(2))
+    t = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
+    qd = torch.from_numpy(q[0]).to(dev)
+    smp = inputs.sample_indices(n, 1000, inputs.sample_seed(2))
+    rows = []
+    for theta in (0.5, 0.7, 0.8):
+        for deg in (4, 6, 8, 10):
+            ref = None
+            if not args.no_cpu:
+                import oracle
+                ref = oracle.Treecode(pos, pos, theta, deg, 2000, 2000).potential(
+                    q[0], kernel=oracle.YUKAWA, kappa=0.5, sample=smp)
+            for prec in ("fp64", "fp32_mixed"):
+                plan = bltc.Plan(t, t, theta=theta, degree=deg, leaf_size=2000, batch_size=2000,
+                                 kernel="yukawa", kappa=0.5, precision=prec)
+                phi = plan.execute(qd)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    plan.execute(qd, out=phi)
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0) / args.steps
+                row = {"theta": theta, "n": deg, "precision": prec, "ms": ms,
+                       "targets_per_s": n / (ms * 1e-3)}
+                if ref is not None:
+                    row["E_par"] = rel_l2(ref, phi.cpu().numpy()[smp])
+                rows.append(row)
+                log(f"sweep {row}")
+    return {"workload": "yukawa-plummer-2M sweep", "rows": rows}
+
+
+def run_large(args, dev):
+    """1.28e8 particles uniform in [-1,1]^3, Coulomb, theta 0.7, n 8, N_L = N_B = 4000."""
+    import numpy as np
+    import torch
+
+    import paper_2003_01836_amd as bltc
+    from paper_2003_01836_amd import inputs
+
+    n = args.large_n
+    log(f"large: generating {n} particles")
+    g = inputs.rng(inputs.config_seed(4))
+    pos = g.uniform(-1.0, 1.0, size=(3, n))        # SoA directly (the same distribution)
+    q = g.uniform(-1.0, 1.0, size=n)
+    t = torch.from_numpy(pos).to(dev)
+    qd = torch.from_numpy(q).to(dev)
+    res = {"workload": f"uniform-{n}", "particles": n}
+    for prec in ("fp64", "fp32_mixed"):
+        t0 = time.perf_counter()
+        plan = bltc.Plan(t, t, theta=0.7, degree=8, leaf_size=4000, batch_size=4000, precision=prec)
+        t_plan = time.perf_counter() - t0
+        st = plan.stats()
+        log(f"large {prec}: plan {t_plan:.1f}s {st['batches']} batches")
+        phi = torch.empty(n, dtype=torch.float64, device=dev)
+        plan.set_timing(True)
+        plan.execute(qd, out=phi)
+        ph = plan.phase_times()
+        res[prec] = {"plan_s": t_plan, "phases_ms": ph, "targets_per_s": n / (ph["total"] * 1e-3),
+                     "far_evals": st["far_evals"], "near_evals": st["near_evals"]}
+        log(f"large {prec}: {ph}")
+        res[prec + "_phi_sample"] = phi[:8].cpu().numpy().tolist()
+        if prec == "fp64":
+            phi64 = phi.clone()
+        else:
+            res["mixed_vs_fp64_fullN"] = float(torch.sqrt(torch.sum((phi - phi64) ** 2) /
+                                                          torch.sum(phi64 ** 2)).item())
+        del plan
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="uniform-1M", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="uniform-1M",
+                    choices=sorted(WORKLOADS) + ["batched-64x16", "yukawa-plummer-sweep", "uniform-large"])
+    ap.add_argument("--large-n", type=int, default=128_000_000)
     ap.add_argument("--precision", default="both", choices=["fp64", "fp32_mixed", "both"])
     ap.add_argument("--cpu-sample", type=int, default=150000,
                     help="targets the CPU oracle evaluates for the CPU baseline")
@@ -81,6 +220,11 @@ def main():
         print("no GPU visible", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
+    if args.workload in ("batched-64x16", "yukawa-plummer-sweep", "uniform-large"):
+        fn = {"batched-64x16": run_batched, "yukawa-plummer-sweep": run_sweep,
+              "uniform-large": run_large}[args.workload]
+        print(json.dumps(fn(args, dev)), flush=True)
+        return 0
     w = WORKLOADS[args.workload]
     n = w["n"]
     log(f"workload {args.workload}: generating {n} particles")

@@ -209,6 +209,24 @@ int bltc_batch_set_graph(bltc_batch* batch, int32_t enable);
 int bltc_batch_info_get(const bltc_batch* batch, bltc_batch_info* out);
 void bltc_batch_destroy(bltc_batch* batch);
 
+/* The library's tuner for the leaf and batch size (kept equal): for the
+ * given DEVICE coordinates it builds a plan for each of the `ncand` candidate
+ * sizes, times one evaluation of `num_q` (1..16) charge vectors on `stream`
+ * after a warm-up, and writes the fastest into out->leaf_size and
+ * out->batch_size (the other fields are copied from *p) and its device time
+ * into *best_ms.  With use_cache != 0 the choice is looked up in / appended
+ * to a text cache keyed by the problem class (log2 of the counts, theta,
+ * degree, kernel, precision, one or several vectors); the file is
+ * $BLTC_TUNE_CACHE, else $HOME/.bltc_tune_cache.  Synchronises `stream`.
+ * Theta and n set the accuracy; the leaf size only moves which pairs are
+ * approximated.  Candidates below (n+1)^3 can never be approximated as
+ * leaves. */
+int bltc_autotune(const bltc_params* p,
+                  int64_t nt, const double* tx, const double* ty, const double* tz,
+                  int64_t ns, const double* sx, const double* sy, const double* sz,
+                  int32_t num_q, const int32_t* candidates, int32_t ncand, int32_t use_cache,
+                  bltc_params* out, double* best_ms, void* stream);
+
 /* GPU direct sum of eq. 1 (all pairs, pairs at zero distance skipped), FP64:
  * phi[m*phi_ld + i] for m < num_q.  Diagnostic / baseline path.  Enqueued on
  * `stream`. */

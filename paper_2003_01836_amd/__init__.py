@@ -17,7 +17,7 @@ import numpy as np
 from . import _capi
 from ._capi import BLTCError, InvalidArgument  # noqa: F401
 
-__all__ = ["params", "Plan", "Batch", "potential", "direct", "BLTCError", "InvalidArgument",
+__all__ = ["params", "Plan", "Batch", "autotune", "potential", "direct", "BLTCError", "InvalidArgument",
            "library_path", "version"]
 
 _KERNELS = {"coulomb": _capi.COULOMB, "yukawa": _capi.YUKAWA}
@@ -258,6 +258,24 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def autotune(targets, sources, candidates=(1000, 2000, 3000, 4000), *, num_q=1, use_cache=True,
+             stream=None, **kw):
+    """Leaf/batch size chosen by timing each candidate on the GPU (`bltc_autotune`).
+
+    Returns (size, milliseconds of one evaluation with that size)."""
+    lib = _capi.load()
+    p = params(**kw)
+    nt, tp = _coords_device(targets, "targets")
+    ns, sp = _coords_device(sources, "sources")
+    cand = (ctypes.c_int32 * len(candidates))(*[int(c) for c in candidates])
+    out = _capi.Params()
+    ms = ctypes.c_double()
+    _capi.check(lib.bltc_autotune(ctypes.byref(p), nt, *tp, ns, *sp, int(num_q), cand, len(candidates),
+                                  1 if use_cache else 0, ctypes.byref(out), ctypes.byref(ms),
+                                  _stream_handle(stream)))
+    return out.leaf_size, ms.value
 
 
 def potential(targets, sources, charges, *, stream=None, out=None, **kw):

@@ -25,7 +25,7 @@ EXPORTS = (
     "bltc_plan_execute", "bltc_plan_modified_charges", "bltc_plan_stats", "bltc_plan_view_get",
     "bltc_plan_set_timing", "bltc_plan_phase_times", "bltc_plan_destroy", "bltc_direct",
     "bltc_batch_create", "bltc_batch_execute", "bltc_batch_set_graph", "bltc_batch_info_get",
-    "bltc_batch_destroy", "bltc_status_string", "bltc_last_error", "bltc_version",
+    "bltc_batch_destroy", "bltc_autotune", "bltc_status_string", "bltc_last_error", "bltc_version",
 )
 
 
@@ -127,6 +127,8 @@ def load():
     lib.bltc_batch_info_get.argtypes = [vp, ctypes.POINTER(BatchInfo)]
     lib.bltc_batch_destroy.argtypes = [vp]
     lib.bltc_batch_destroy.restype = None
+    lib.bltc_autotune.argtypes = [PP, i64, vp, vp, vp, i64, vp, vp, vp, i32, ctypes.POINTER(i32), i32,
+                                  i32, PP, ctypes.POINTER(d), vp]
     lib.bltc_status_string.argtypes = [ctypes.c_int]
     lib.bltc_status_string.restype = ctypes.c_char_p
     lib.bltc_last_error.argtypes = []
@@ -135,7 +137,8 @@ def load():
     for name in ("bltc_potential", "bltc_plan_create", "bltc_plan_create_host", "bltc_plan_execute",
                  "bltc_plan_modified_charges", "bltc_plan_stats", "bltc_plan_view_get", "bltc_direct",
                  "bltc_plan_set_timing", "bltc_plan_phase_times", "bltc_batch_create",
-                 "bltc_batch_execute", "bltc_batch_set_graph", "bltc_batch_info_get"):
+                 "bltc_batch_execute", "bltc_batch_set_graph", "bltc_batch_info_get",
+                 "bltc_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

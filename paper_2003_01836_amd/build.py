@@ -66,6 +66,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         "upward": os.path.join(build_dir, "kernels_upward.o"),
         "capi": os.path.join(build_dir, "capi.o"),
         "batch": os.path.join(build_dir, "batch.o"),
+        "autotune": os.path.join(build_dir, "autotune.o"),
     }
     cmds = [
         ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
@@ -78,6 +79,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
                                "-c", os.path.join(CSRC, "kernels_upward.hip"), "-o", objs["upward"]],
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "capi.cpp"), "-o", objs["capi"]],
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "batch.cpp"), "-o", objs["batch"]],
+        [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "autotune.cpp"), "-o", objs["autotune"]],
     ]
     if verbose:
         for c in cmds:

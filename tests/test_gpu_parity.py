@@ -457,3 +457,22 @@ def test_batch_rejects_bad_plans(dev):
     b = bltc.Batch([p2])
     with pytest.raises(bltc.InvalidArgument):
         b.execute([torch.zeros((5, 2000), dtype=torch.float64, device=dev)])   # 5 > max_q
+
+
+def test_autotune_picks_a_candidate_and_caches(dev, tmp_path, monkeypatch):
+    import paper_2003_01836_amd as bltc
+    monkeypatch.setenv("BLTC_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    pos, q = inputs.uniform_cube(60000, 700)
+    t = _dev_soa(pos, dev)
+    cands = (150, 400, 1200)
+    leaf, ms = bltc.autotune(t, t, cands, degree=4, theta=0.7)
+    assert leaf in cands and ms > 0
+    text = (tmp_path / "tune.txt").read_text()
+    assert f"|{leaf} " in text
+    # a second call is answered from the cache (same value, no new entry)
+    leaf2, ms2 = bltc.autotune(t, t, cands, degree=4, theta=0.7)
+    assert (leaf2, ms2) == (leaf, pytest.approx(ms, rel=1e-6))
+    assert (tmp_path / "tune.txt").read_text() == text
+    # the tuned plan is still exact against the oracle at its own leaf size
+    _, phi = _run_plan(dev, pos, pos, q[0], degree=4, theta=0.7, leaf_size=leaf, batch_size=leaf)
+    _close(oracle.Treecode(pos, pos, 0.7, 4, leaf, leaf).potential(q[0]), phi)
