@@ -64,8 +64,10 @@ bool cache_lookup(const std::string& key, int32_t* leaf, double* ms)
 void cache_store(const std::string& key, int32_t leaf, double ms)
 {
     std::ofstream f(cache_path(), std::ios::app);
-    if (f)
+    if (f) {
+        f.precision(17);
         f << key << "|" << leaf << " " << ms << "\n";
+    }
 }
 
 }  // namespace

@@ -471,7 +471,7 @@ def test_autotune_picks_a_candidate_and_caches(dev, tmp_path, monkeypatch):
     assert f"|{leaf} " in text
     # a second call is answered from the cache (same value, no new entry)
     leaf2, ms2 = bltc.autotune(t, t, cands, degree=4, theta=0.7)
-    assert (leaf2, ms2) == (leaf, pytest.approx(ms, rel=1e-6))
+    assert (leaf2, ms2) == (leaf, pytest.approx(ms, rel=1e-5))
     assert (tmp_path / "tune.txt").read_text() == text
     # the tuned plan is still exact against the oracle at its own leaf size
     _, phi = _run_plan(dev, pos, pos, q[0], degree=4, theta=0.7, leaf_size=leaf, batch_size=leaf)
