@@ -33,6 +33,33 @@ FLOPS_COULOMB = 11
 FLOPS_YUKAWA = 15                   # + r = r^2 * (1/r), -kappa r, exp, product
 
 
+KERNEL_SOURCES = {
+    "interact_mixed": ["kernels_mixed.hip", "device_common.hpp", "kernels.hpp"],
+    "interact_f64": ["kernels.hip", "device_common.hpp", "kernels.hpp"],
+}
+
+
+def counter_traffic(kernel, degree, ker_id):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when there is none for this instantiation or the kernel's sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "interact_uniform-1M_counters.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2003_01836_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    want = f"traffic_bytes {kernel}<{degree}, {ker_id}> "
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith(want):
+                parts = line[len(want):].split()
+                if len(parts) == 3 and parts[1] == "source" and parts[2] == h.hexdigest()[:16]:
+                    return float(parts[0])
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -313,6 +340,8 @@ def main():
     t_int = r["phases"]["interact"] * 1e-3
     achieved = evals * flops_eval / t_int / 1e12
     peak = FP64_VECTOR_PEAK_TFLOPS if best == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+    kname = "interact_f64" if best == "fp64" else "interact_mixed"
+    traffic = counter_traffic(kname, w["degree"], 1 if w["kernel"] == "yukawa" else 0)
     line = {
         "metric": "targets/s at rel-L2 err <=1e-6 (BLTC evaluation phase)",
         "value": n / (r["ms"] * 1e-3),
@@ -330,8 +359,8 @@ def main():
                                f"{w['kernel']}, theta={w['theta']}, n={w['degree']}, "
                                f"N_L=N_B={w['leaf']}", "path": best},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "interact", "flops_per_eval": flops_eval,
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": kname, "flops_per_eval": flops_eval,
                      "evals_per_launch": evals, "ms_per_launch": r["phases"]["interact"]},
         "cpu_baseline": cpu,
         "paths": {p: {"targets_per_s": n / (v["ms"] * 1e-3), "ms_per_step": v["ms"],
