@@ -1,0 +1,31 @@
+"""CPU checks of the benchmark's contract (no GPU needed)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_counter_traffic_is_null_for_changed_or_missing_kernels(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    # an instantiation without a committed counter run
+    assert bench.counter_traffic("interact_f64", 3, 1) is None
+    # a stale source hash is ignored
+    fake = tmp_path / "profiles"
+    fake.mkdir()
+    (fake / "interact_uniform-1M_counters.md").write_text(
+        "traffic_bytes interact_mixed<8, 0> 1.0e+09 source 0000000000000000\n")
+    csrc = tmp_path / "paper_2003_01836_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for f in bench.KERNEL_SOURCES["interact_mixed"]:
+        (csrc / f).write_text("x")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.counter_traffic("interact_mixed", 8, 0) is None
