@@ -206,13 +206,35 @@ def run_large(args, dev):
         res[prec] = {"plan_s": t_plan, "phases_ms": ph, "targets_per_s": n / (ph["total"] * 1e-3),
                      "far_evals": st["far_evals"], "near_evals": st["near_evals"]}
         log(f"large {prec}: {ph}")
-        res[prec + "_phi_sample"] = phi[:8].cpu().numpy().tolist()
         if prec == "fp64":
             phi64 = phi.clone()
         else:
             res["mixed_vs_fp64_fullN"] = float(torch.sqrt(torch.sum((phi - phi64) ** 2) /
                                                           torch.sum(phi64 ** 2)).item())
+            phim = phi
         del plan
+    if not args.no_cpu:
+        # errors on 10,000 sampled targets: against the FP64 direct sum (E_tc) and the
+        # oracle treecode (E_par), both from the CPU oracle
+        import oracle
+        smp = inputs.sample_indices(n, 10_000, inputs.sample_seed(4))
+        post = np.ascontiguousarray(pos.T)
+        del t
+        log("large: oracle direct sum on 10,000 targets")
+        t0 = time.perf_counter()
+        ds = oracle.direct(post[smp], post, q)
+        res["oracle_direct_s"] = time.perf_counter() - t0
+        log("large: oracle treecode on the same targets")
+        t0 = time.perf_counter()
+        oc = oracle.Treecode(post, post, 0.7, 8, 4000, 4000)
+        ref = oc.potential(q, sample=smp)
+        res["oracle_treecode_s"] = time.perf_counter() - t0
+        res["oracle_threads"] = oracle.max_threads()
+        g64 = phi64.cpu().numpy()[smp]
+        gm = phim.cpu().numpy()[smp]
+        res["E_tc"] = {"fp64": rel_l2(ds, g64), "fp32_mixed": rel_l2(ds, gm), "oracle": rel_l2(ds, ref)}
+        res["E_par"] = {"fp64": rel_l2(ref, g64), "fp32_mixed": rel_l2(ref, gm)}
+        log(f"large: E_tc {res['E_tc']} E_par {res['E_par']}")
     return res
 
 
