@@ -74,6 +74,9 @@ int make_host_plan(bltc_plan* plan, const bltc_params* p, int64_t nt, const doub
     pp.leaf_size = p->leaf_size;
     pp.batch_size = p->batch_size;
     pp.group_size = bltc::kGroupSize;
+    // upward-pass chunks: with one charge vector a chunk is a few MFMA tiles, so
+    // smaller chunks give more workgroups; 16 vectors fill 9x more tiles per chunk
+    pp.chunk_size = plan->max_q > 1 ? 8192 : 2048;
     std::string err = bltc::make_plan(plan->hp, pp, nt, tx, ty, tz, ns, sx, sy, sz);
     if (!err.empty())
         return fail(BLTC_EINTERNAL, "%s", err.c_str());

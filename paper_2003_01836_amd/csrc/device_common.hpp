@@ -52,14 +52,52 @@ __device__ __forceinline__ double rsqrt_f64_or_zero(double r2)
     return rsqrt_refine3(r2, __hiloint2double(hi, lo));
 }
 
+// ---------------------------------------------------------------------------
+// exp(x) for x <= 0 in FP64 (x = -kappa r in the Yukawa kernel), from
+// exp(x) = 2^(n/64) e^u with n = rint(64 x / ln 2) and u = x - n ln2/64
+// (Cody-Waite: ln2/64 split into a 32-bit head, so n * head is exact for
+// |n| < 2^21, and a tail), |u| <= ln2/128; e^u by its Taylor polynomial of
+// degree 5 (remainder below 4e-17); 2^(j/64) from a 64-entry table that each
+// workgroup fills in LDS with exp2 (fill_exp2_table).
+// ---------------------------------------------------------------------------
+constexpr double kLn2Over64Hi = 0x1.62e42fee00000p-7;
+constexpr double kLn2Over64Lo = 0x1.a39ef35793c76p-39;
+constexpr double k64OverLn2 = 92.33248261689366;
+
+struct YukawaArg {
+    double kappa;
+    const double* tab;   // 2^(j/64), j < 64 (LDS)
+};
+
+__device__ __forceinline__ void fill_exp2_table(double* tab)
+{
+    if (threadIdx.x < 64)
+        tab[threadIdx.x] = exp2(static_cast<double>(threadIdx.x) / 64.0);
+    __syncthreads();
+}
+
+__device__ __forceinline__ double exp_f64(double x, const double* __restrict__ tab)
+{
+    const double nd = __builtin_rint(x * k64OverLn2);
+    const int n = static_cast<int>(nd);
+    double u = __fma_rn(-nd, kLn2Over64Hi, x);
+    u = __fma_rn(-nd, kLn2Over64Lo, u);
+    double p = __fma_rn(u, 1.0 / 120.0, 1.0 / 24.0);
+    p = __fma_rn(u, p, 1.0 / 6.0);
+    p = __fma_rn(u, p, 0.5);
+    p = __fma_rn(u, p, 1.0);
+    p = __fma_rn(u, p, 1.0);
+    return ldexp(tab[n & 63] * p, n >> 6);
+}
+
 // G as a function of r^2 and 1/r (eq. 2).
 template <int KER>
-__device__ __forceinline__ double green_f64(double r2, double rinv, double kappa)
+__device__ __forceinline__ double green_f64(double r2, double rinv, const YukawaArg& ya)
 {
     if constexpr (KER == 0) {
         return rinv;
     } else {
-        return exp(-kappa * (r2 * rinv)) * rinv;
+        return exp_f64(-ya.kappa * (r2 * rinv), ya.tab) * rinv;
     }
 }
 
@@ -69,7 +107,7 @@ __device__ __forceinline__ double green_f64(double r2, double rinv, double kappa
 // ---------------------------------------------------------------------------
 template <int KER>
 __device__ __forceinline__ double near_term_f64(double x, double y, double z, const double4 p,
-                                                double kappa)
+                                                const YukawaArg& kappa)
 {
     const double dx = x - p.x;
     const double dy = y - p.y;
@@ -81,7 +119,7 @@ __device__ __forceinline__ double near_term_f64(double x, double y, double z, co
 template <int KER>
 __device__ __forceinline__ double near_sum_f64(double x, double y, double z,
                                                const double4* __restrict__ s, int32_t cnt,
-                                               double kappa)
+                                               const YukawaArg& kappa)
 {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int32_t j = 0;

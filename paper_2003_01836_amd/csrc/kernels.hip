@@ -26,7 +26,7 @@ using namespace dev;
 template <int N, int KER>
 __device__ __forceinline__ double far_sum_f64(double x, double y, double z,
                                               const double* __restrict__ nd,
-                                              const double* __restrict__ qh, double kappa)
+                                              const double* __restrict__ qh, const YukawaArg& kappa)
 {
     constexpr int NP = N + 1;
     double b2[NP], c2[NP];
@@ -71,10 +71,14 @@ __global__ __launch_bounds__(kGroupSize) void interact_f64(
     const int32_t* __restrict__ far_off, const int32_t* __restrict__ far_slot,
     const int32_t* __restrict__ near_off, const int64_t* __restrict__ near_begin,
     const int64_t* __restrict__ near_count, const double* __restrict__ slot_nodes,
-    const double* __restrict__ qhat, double* __restrict__ phi, double kappa)
+    const double* __restrict__ qhat, double* __restrict__ phi, double kappa_value)
 {
     constexpr int NP = N + 1;
     constexpr int P = NP * NP * NP;
+    __shared__ double exp_tab[64];
+    if constexpr (KER == 1)
+        fill_exp2_table(exp_tab);
+    const YukawaArg kappa{kappa_value, exp_tab};
     const int g = blockIdx.x;
     const int b = group_batch[g];
     if (b < 0)
@@ -136,8 +140,12 @@ __global__ __launch_bounds__(256) void direct_f64(int64_t nt, const double* __re
                                                   const double* __restrict__ ty,
                                                   const double* __restrict__ tz, int64_t ns,
                                                   const double4* __restrict__ src,
-                                                  double* __restrict__ phi, double kappa)
+                                                  double* __restrict__ phi, double kappa_value)
 {
+    __shared__ double exp_tab[64];
+    if constexpr (KER == 1)
+        fill_exp2_table(exp_tab);
+    const YukawaArg kappa{kappa_value, exp_tab};
     const int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x;
     if (base + (threadIdx.x & ~63) >= nt)
         return;

@@ -62,7 +62,7 @@ __device__ __forceinline__ void near_quad_mixed(float x, float y, float z,
                                                 const float4* __restrict__ s32,
                                                 const double4* __restrict__ s64, float tau2,
                                                 float nk, double xt, double yt, double zt,
-                                                double kappa, double& acc, float& a0, float& a1,
+                                                const YukawaArg& kappa, double& acc, float& a0, float& a1,
                                                 float& a2, float& a3)
 {
     const float4 p0 = s32[0], p1 = s32[1], p2 = s32[2], p3 = s32[3];
@@ -88,7 +88,7 @@ __device__ __forceinline__ double near_sum_mixed(double xt, double yt, double zt
                                                  const float4* __restrict__ s32,
                                                  const double4* __restrict__ s64, int32_t cnt,
                                                  const double4 leaf, float tau2, float nk,
-                                                 double kappa)
+                                                 const YukawaArg& kappa)
 {
     const float x = static_cast<float>(xt - leaf.x);
     const float y = static_cast<float>(yt - leaf.y);
@@ -164,10 +164,14 @@ __global__ __launch_bounds__(kGroupSize) void interact_mixed(
     const int32_t* __restrict__ far_slot, const int32_t* __restrict__ near_off,
     const int64_t* __restrict__ near_begin, const int64_t* __restrict__ near_count,
     const int32_t* __restrict__ near_leaf, const double* __restrict__ slot_nodes,
-    const float* __restrict__ qhat32, double* __restrict__ phi, double kappa)
+    const float* __restrict__ qhat32, double* __restrict__ phi, double kappa_value)
 {
     constexpr int NP = N + 1;
     constexpr int P = NP * NP * NP;
+    __shared__ double exp_tab[64];
+    if constexpr (KER == 1)
+        fill_exp2_table(exp_tab);
+    const YukawaArg kappa{kappa_value, exp_tab};
     const int g = blockIdx.x;
     const int b = group_batch[g];
     if (b < 0)
@@ -182,7 +186,7 @@ __global__ __launch_bounds__(kGroupSize) void interact_mixed(
     if (!valid)
         i = end - 1;
     const double4 t = tgt[i];
-    const float nk = static_cast<float>(-kappa * 1.4426950408889634);
+    const float nk = static_cast<float>(-kappa_value * 1.4426950408889634);
     double acc = 0.0;
 
     const int f_end = far_off[b + 1];

@@ -48,7 +48,7 @@ __device__ __forceinline__ float green_f32(float r2, float rinv, float neg_kappa
 // FP64: G in FP64 on the VALU, contraction on v_mfma_f64_16x16x4f64.
 // ---------------------------------------------------------------------------
 template <int KER>
-__device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g)
+__device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const double* exp_tab)
 {
     const double4* __restrict__ tgt = d.tgt;
     const int64_t* __restrict__ tgt_orig = d.tgt_orig;
@@ -65,7 +65,7 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g)
     const int32_t np = d.np;
     const int64_t phi_ld = d.phi_ld;
     const int32_t m_count = d.mc;
-    const double kappa = d.kappa;
+    const YukawaArg kappa{d.kappa, exp_tab};
     const int b = d.group_batch[g];
     if (b < 0)
         return;
@@ -171,7 +171,7 @@ __device__ __forceinline__ void flush_f32(f4v (&part)[4], double (&acc)[4][4])
 }
 
 template <int KER>
-__device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g)
+__device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const double* exp_tab)
 {
     const double4* __restrict__ tgt = d.tgt;
     const int64_t* __restrict__ tgt_orig = d.tgt_orig;
@@ -193,7 +193,7 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g)
     const int32_t np = d.np;
     const int64_t phi_ld = d.phi_ld;
     const int32_t m_count = d.mc;
-    const double kappa = d.kappa;
+    const YukawaArg kappa{d.kappa, exp_tab};
     const int b = d.group_batch[g];
     if (b < 0)
         return;
@@ -205,7 +205,7 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g)
     const int lane = threadIdx.x & 63;
     const int row = lane & 15;
     const int col = lane >> 4;
-    const float nk = static_cast<float>(-kappa * 1.4426950408889634);
+    const float nk = static_cast<float>(-d.kappa * 1.4426950408889634);
 
     double tx[4], ty[4], tz[4];
 #pragma unroll
@@ -340,10 +340,13 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g)
 template <int KER, int PREC>
 __global__ __launch_bounds__(kGroupSize) void interact_mrhs(MrhsDesc d)
 {
+    __shared__ double exp_tab[64];
+    if constexpr (KER == 1)
+        fill_exp2_table(exp_tab);
     if constexpr (PREC == 0)
-        group_mrhs_f64<KER>(d, blockIdx.x);
+        group_mrhs_f64<KER>(d, blockIdx.x, exp_tab);
     else
-        group_mrhs_mixed<KER>(d, blockIdx.x);
+        group_mrhs_mixed<KER>(d, blockIdx.x, exp_tab);
 }
 
 // Persistent work queue over the groups of many systems: every workgroup
@@ -356,6 +359,9 @@ __global__ __launch_bounds__(kGroupSize) void interact_queue(const MrhsDesc* __r
                                                              int32_t* __restrict__ counter)
 {
     __shared__ int32_t next;
+    __shared__ double exp_tab[64];
+    if constexpr (KER == 1)
+        fill_exp2_table(exp_tab);
     for (;;) {
         if (threadIdx.x == 0)
             next = atomicAdd(counter, 1);
@@ -368,9 +374,9 @@ __global__ __launch_bounds__(kGroupSize) void interact_queue(const MrhsDesc* __r
         const int32_t sys = __builtin_amdgcn_readfirstlane(w.x);
         const int32_t g = __builtin_amdgcn_readfirstlane(w.y);
         if constexpr (PREC == 0)
-            group_mrhs_f64<KER>(descs[sys], g);
+            group_mrhs_f64<KER>(descs[sys], g, exp_tab);
         else
-            group_mrhs_mixed<KER>(descs[sys], g);
+            group_mrhs_mixed<KER>(descs[sys], g, exp_tab);
     }
 }
 
