@@ -60,6 +60,17 @@ def counter_traffic(kernel, degree, ker_id):
     return None
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -204,6 +215,7 @@ def run_large(args, dev):
         plan.execute(qd, out=phi)
         ph = plan.phase_times()
         res[prec] = {"plan_s": t_plan, "phases_ms": ph, "targets_per_s": n / (ph["total"] * 1e-3),
+                     "end_to_end_targets_per_s": n / (t_plan + ph["total"] * 1e-3),
                      "far_evals": st["far_evals"], "near_evals": st["near_evals"]}
         log(f"large {prec}: {ph}")
         if prec == "fp64":
@@ -244,14 +256,57 @@ def run_large(args, dev):
     return res
 
 
+def run_setup(args, dev):
+    """Setup phase alone: plans built on the GPU (device coordinates) against the
+    host planner (host coordinates) on the same uniform cube, N_L = N_B = 4000."""
+    import numpy as np
+    import torch
+
+    import paper_2003_01836_amd as bltc
+    from paper_2003_01836_amd import inputs
+
+    n = args.large_n
+    log(f"setup: generating {n} particles")
+    g = inputs.rng(inputs.config_seed(4))
+    pos = g.uniform(-1.0, 1.0, size=(3, n))
+    t = torch.from_numpy(pos).to(dev)
+    kw = dict(theta=0.7, degree=8, leaf_size=4000, batch_size=4000)
+    res = {"workload": f"setup uniform-{n}", "particles": n}
+    for prec in ("fp64", "fp32_mixed"):
+        times = []
+        for rep in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = bltc.Plan(t, t, precision=prec, **kw)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            st = plan.stats()
+            del plan
+            log(f"setup {prec}: device plan {times[-1]:.3f}s")
+        res[prec] = {"device_plan_s": min(times), "device_plan_s_all": times,
+                     "clusters": st["clusters"], "batches": st["batches"],
+                     "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"]}
+    if n <= args.setup_host_max:
+        ph = np.ascontiguousarray(pos)
+        t0 = time.perf_counter()
+        hplan = bltc.Plan(ph, ph, host=True, **kw)
+        res["host_plan_s"] = time.perf_counter() - t0
+        log(f"setup: host plan {res['host_plan_s']:.3f}s")
+        del hplan
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="uniform-1M",
-                    choices=sorted(WORKLOADS) + ["batched-64x16", "yukawa-plummer-sweep", "uniform-large"])
+                    choices=sorted(WORKLOADS) + ["batched-64x16", "yukawa-plummer-sweep", "uniform-large",
+                                                 "setup"])
     ap.add_argument("--large-n", type=int, default=128_000_000)
+    ap.add_argument("--setup-host-max", type=int, default=20_000_000,
+                    help="setup workload: also time the host planner up to this many particles")
     ap.add_argument("--precision", default="both", choices=["fp64", "fp32_mixed", "both"])
     ap.add_argument("--cpu-sample", type=int, default=150000,
                     help="targets the CPU oracle evaluates for the CPU baseline")
@@ -275,9 +330,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
-    if args.workload in ("batched-64x16", "yukawa-plummer-sweep", "uniform-large"):
+    if args.workload in ("batched-64x16", "yukawa-plummer-sweep", "uniform-large", "setup"):
         fn = {"batched-64x16": run_batched, "yukawa-plummer-sweep": run_sweep,
-              "uniform-large": run_large}[args.workload]
+              "uniform-large": run_large, "setup": run_setup}[args.workload]
         print(json.dumps(fn(args, dev)), flush=True)
         return 0
     w = WORKLOADS[args.workload]
@@ -351,6 +406,7 @@ def main():
         _, ctimes = oc.potential(q[0], kernel=kern, kappa=w["kappa"], sample=cs, return_times=True)
         t_cpu = ctimes["upward"] + ctimes["eval"]
         cpu = {"value": len(cs) / t_cpu, "unit": "targets/s", "cores": oracle.max_threads(),
+               "cpu_model": cpu_model(),
                "kind": "oracle",
                "sample": (f"{len(cs)} sampled targets of the same plan: tree/lists built once "
                           f"({oc.t_setup:.2f}s, excluded); modified charges for every cluster their "
@@ -393,6 +449,7 @@ def main():
         "cpu_baseline": cpu,
         "paths": {p: {"targets_per_s": n / (v["ms"] * 1e-3), "ms_per_step": v["ms"],
                       "phases_ms": v["phases"], "plan_s": v["t_plan"],
+                      "end_to_end_targets_per_s": n / (v["t_plan"] + v["ms"] * 1e-3),
                       "evals_per_s": evals / (v["phases"]["interact"] * 1e-3),
                       **errors.get(p, {})} for p, v in results.items()},
         "oracle_E_tc": errors.get("oracle", {}).get("E_tc"),

@@ -67,6 +67,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         "capi": os.path.join(build_dir, "capi.o"),
         "batch": os.path.join(build_dir, "batch.o"),
         "autotune": os.path.join(build_dir, "autotune.o"),
+        "setup": os.path.join(build_dir, "setup_gpu.o"),
     }
     cmds = [
         ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
@@ -80,6 +81,8 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "capi.cpp"), "-o", objs["capi"]],
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "batch.cpp"), "-o", objs["batch"]],
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "autotune.cpp"), "-o", objs["autotune"]],
+        # geometric decisions (MAC) follow their formulas operation by operation
+        [hipcc] + hip_flags + ["-ffp-contract=off", "-c", os.path.join(CSRC, "setup_gpu.hip"), "-o", objs["setup"]],
     ]
     if verbose:
         for c in cmds:

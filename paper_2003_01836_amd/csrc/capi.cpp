@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "setup_gpu.hpp"
 
 using bltc_detail::fail;
 using bltc_detail::hip_fail;
@@ -64,9 +66,7 @@ int check_finite(int64_t n, const double* x, const double* y, const double* z, c
 
 namespace {
 
-int make_host_plan(bltc_plan* plan, const bltc_params* p, int64_t nt, const double* tx,
-                   const double* ty, const double* tz, int64_t ns, const double* sx,
-                   const double* sy, const double* sz)
+bltc::PlanParams plan_params(const bltc_plan* plan, const bltc_params* p)
 {
     bltc::PlanParams pp;
     pp.theta = p->theta;
@@ -77,9 +77,88 @@ int make_host_plan(bltc_plan* plan, const bltc_params* p, int64_t nt, const doub
     // upward-pass chunks: with one charge vector a chunk is a few MFMA tiles, so
     // smaller chunks give more workgroups; 16 vectors fill 9x more tiles per chunk
     pp.chunk_size = plan->max_q > 1 ? 8192 : 2048;
-    std::string err = bltc::make_plan(plan->hp, pp, nt, tx, ty, tz, ns, sx, sy, sz);
+    return pp;
+}
+
+int make_host_plan(bltc_plan* plan, const bltc_params* p, int64_t nt, const double* tx,
+                   const double* ty, const double* tz, int64_t ns, const double* sx,
+                   const double* sy, const double* sz)
+{
+    std::string err = bltc::make_plan(plan->hp, plan_params(plan, p), nt, tx, ty, tz, ns, sx, sy, sz);
     if (!err.empty())
         return fail(BLTC_EINTERNAL, "%s", err.c_str());
+    return BLTC_OK;
+}
+
+// Trees built on the device from device coordinates; the per-particle arrays
+// of the plan are written there directly, the node arrays come back to the
+// host for the interaction lists.
+int make_device_plan(bltc_plan* plan, const bltc_params* p, int64_t nt, const double* tx,
+                     const double* ty, const double* tz, int64_t ns, const double* sx,
+                     const double* sy, const double* sz, hipStream_t s)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    bltc::HostPlan& hp = plan->hp;
+    hp = bltc::HostPlan();
+    hp.prm = plan_params(plan, p);
+    bltc::DevicePlan& d = plan->d;
+    const bool mixed = p->precision == BLTC_FP32_MIXED;
+    HIP_TRY(hipGetDevice(&plan->device));
+    int64_t* src_order = nullptr;
+    HIP_TRY(plan->alloc(&d.src, static_cast<size_t>(ns)));
+    HIP_TRY(plan->alloc(&src_order, static_cast<size_t>(ns)));
+    d.src_order = src_order;
+    if (mixed)
+        HIP_TRY(plan->alloc(&d.src32, static_cast<size_t>(ns)));
+    HIP_TRY(plan->alloc(&d.tgt, static_cast<size_t>(nt)));
+    HIP_TRY(plan->alloc(&d.tgt_orig, static_cast<size_t>(nt)));
+    int64_t bad = -1;
+    std::string err = bltc::build_tree_device(hp.src, ns, sx, sy, sz, p->leaf_size, src_order,
+                                              d.src, mixed ? d.src32 : nullptr, s, &bad);
+    if (bad >= 0)
+        return fail(BLTC_EINVAL, "source coordinate %lld is not finite", static_cast<long long>(bad));
+    if (!err.empty())
+        return fail(BLTC_EHIP, "device tree build: %s", err.c_str());
+    if (nt == ns && tx == sx && ty == sy && tz == sz && p->batch_size == p->leaf_size) {
+        // same particles, same capacity: identical partition
+        hp.tgt = hp.src;
+        if (nt > 0) {
+            HIP_TRY(hipMemcpyAsync(d.tgt, d.src, nt * sizeof(double4), hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(d.tgt_orig, src_order, nt * sizeof(int64_t),
+                                   hipMemcpyDeviceToDevice, s));
+        }
+    } else {
+        err = bltc::build_tree_device(hp.tgt, nt, tx, ty, tz, p->batch_size, d.tgt_orig, d.tgt,
+                                      nullptr, s, &bad);
+        if (bad >= 0)
+            return fail(BLTC_EINVAL, "target coordinate %lld is not finite",
+                        static_cast<long long>(bad));
+        if (!err.empty())
+            return fail(BLTC_EHIP, "device tree build: %s", err.c_str());
+    }
+    bltc::plan_batches(hp);
+    bltc::DeviceLists dl;
+    auto alloc = [plan](void** ptr, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(ptr, std::max<size_t>(bytes, 1));
+        if (e == hipSuccess)
+            plan->allocations.push_back(*ptr);
+        return e;
+    };
+    err = bltc::build_lists_device(hp, dl, alloc, s);
+    if (!err.empty())
+        return fail(BLTC_EHIP, "device interaction lists: %s", err.c_str());
+    bltc::plan_schedule(hp);
+    d.far_slot = dl.far_slot;
+    d.near_leaf = dl.near_leaf;
+    d.near_begin = dl.near_begin;
+    d.near_count = dl.near_count;
+    plan->item_batch = dl.item_batch;
+    plan->item_cluster = dl.item_cluster;
+    plan->item_kind = dl.item_kind;
+    plan->n_items = dl.n_items;
+    plan->device_particles = true;
+    plan->device_lists = true;
+    hp.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BLTC_OK;
 }
 
@@ -100,30 +179,34 @@ int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
     d.ngroups = static_cast<int64_t>(hp.group_batch.size());
     d.nbatches = static_cast<int64_t>(hp.batch_begin.size());
 
-    std::vector<double4> src(d.ns), tgt(d.nt);
-    for (int64_t j = 0; j < d.ns; ++j)
-        src[j] = make_double4(hp.src.x[j], hp.src.y[j], hp.src.z[j], 0.0);
-    for (int64_t i = 0; i < d.nt; ++i)
-        tgt[i] = make_double4(hp.tgt.x[i], hp.tgt.y[i], hp.tgt.z[i], 0.0);
+    if (!plan->device_particles) {
+        std::vector<double4> src(d.ns), tgt(d.nt);
+        for (int64_t j = 0; j < d.ns; ++j)
+            src[j] = make_double4(hp.src.x[j], hp.src.y[j], hp.src.z[j], 0.0);
+        for (int64_t i = 0; i < d.nt; ++i)
+            tgt[i] = make_double4(hp.tgt.x[i], hp.tgt.y[i], hp.tgt.z[i], 0.0);
+        HIP_TRY(plan->put(&d.src, src, s));
+        HIP_TRY(plan->put(&d.tgt, tgt, s));
+        HIP_TRY(plan->put(&d.tgt_orig, hp.tgt.order, s));
+        int64_t* src_order = nullptr;
+        HIP_TRY(plan->put(&src_order, hp.src.order, s));
+        d.src_order = src_order;
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     std::vector<int64_t> batch_end(d.nbatches);
     for (int64_t b = 0; b < d.nbatches; ++b)
         batch_end[b] = hp.batch_begin[b] + hp.batch_count[b];
-
-    HIP_TRY(plan->put(&d.src, src, s));
-    HIP_TRY(plan->put(&d.tgt, tgt, s));
-    HIP_TRY(plan->put(&d.tgt_orig, hp.tgt.order, s));
-    int64_t* src_order = nullptr;
-    HIP_TRY(plan->put(&src_order, hp.src.order, s));
-    d.src_order = src_order;
     HIP_TRY(plan->put(&d.group_batch, hp.group_batch, s));
     HIP_TRY(plan->put(&d.group_first, hp.group_first, s));
     HIP_TRY(plan->put(&d.batch_end, batch_end, s));
     HIP_TRY(plan->put(&d.far_off, hp.far_off, s));
-    HIP_TRY(plan->put(&d.far_slot, hp.far_slot, s));
     HIP_TRY(plan->put(&d.near_off, hp.near_off, s));
-    HIP_TRY(plan->put(&d.near_begin, hp.near_begin, s));
-    HIP_TRY(plan->put(&d.near_count, hp.near_count, s));
-    HIP_TRY(plan->put(&d.near_leaf, hp.near_leaf, s));
+    if (!plan->device_lists) {
+        HIP_TRY(plan->put(&d.far_slot, hp.far_slot, s));
+        HIP_TRY(plan->put(&d.near_begin, hp.near_begin, s));
+        HIP_TRY(plan->put(&d.near_count, hp.near_count, s));
+        HIP_TRY(plan->put(&d.near_leaf, hp.near_leaf, s));
+    }
     HIP_TRY(plan->put(&d.slot_nodes, hp.slot_nodes, s));
     HIP_TRY(plan->put(&d.chunk_slot, hp.chunk_slot, s));
     HIP_TRY(plan->put(&d.chunk_begin, hp.chunk_begin, s));
@@ -175,12 +258,16 @@ int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
         for (int64_t c = 0; c < nn; ++c)
             node_info[c] = make_double4(hp.src.center[3 * c], hp.src.center[3 * c + 1],
                                         hp.src.center[3 * c + 2], hp.src.radius[c]);
-        std::vector<float4> src32(d.ns);
-        for (int64_t j = 0; j < d.ns; ++j) {
-            const double4 c = node_info[hp.leaf_of_pos[j]];
-            src32[j] = make_float4(static_cast<float>(hp.src.x[j] - c.x),
-                                   static_cast<float>(hp.src.y[j] - c.y),
-                                   static_cast<float>(hp.src.z[j] - c.z), 0.0f);
+        if (!plan->device_particles) {
+            std::vector<float4> src32(d.ns);
+            for (int64_t j = 0; j < d.ns; ++j) {
+                const double4 c = node_info[hp.leaf_of_pos[j]];
+                src32[j] = make_float4(static_cast<float>(hp.src.x[j] - c.x),
+                                       static_cast<float>(hp.src.y[j] - c.y),
+                                       static_cast<float>(hp.src.z[j] - c.z), 0.0f);
+            }
+            HIP_TRY(plan->put(&d.src32, src32, s));
+            HIP_TRY(hipStreamSynchronize(s));
         }
         std::vector<double4> batch_info(d.nbatches);
         for (int64_t b = 0; b < d.nbatches; ++b) {
@@ -188,7 +275,6 @@ int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
             batch_info[b] = make_double4(hp.tgt.center[3 * bn], hp.tgt.center[3 * bn + 1],
                                          hp.tgt.center[3 * bn + 2], hp.tgt.radius[bn]);
         }
-        HIP_TRY(plan->put(&d.src32, src32, s));
         HIP_TRY(plan->put(&d.node_info, node_info, s));
         HIP_TRY(plan->put(&d.batch_info, batch_info, s));
         HIP_TRY(plan->alloc(&d.qhat32, static_cast<size_t>(d.nslots) * hp.P));
@@ -333,41 +419,6 @@ int create_from_host(bltc_plan** out, const bltc_params* p, int64_t nt, const do
     return BLTC_OK;
 }
 
-// device -> host copies of coordinates; identical pointers stay identical
-int download_coords(int64_t nt, const double* tx, const double* ty, const double* tz, int64_t ns,
-                    const double* sx, const double* sy, const double* sz, std::vector<double>& h,
-                    const double* hp[6], hipStream_t s)
-{
-    const double* dev[6] = {tx, ty, tz, sx, sy, sz};
-    const int64_t cnt[6] = {nt, nt, nt, ns, ns, ns};
-    int64_t total = 0;
-    int64_t off[6];
-    for (int k = 0; k < 6; ++k) {
-        off[k] = -1;
-        for (int j = 0; j < k; ++j)
-            if (dev[j] == dev[k] && cnt[j] == cnt[k])
-                off[k] = off[j];
-        if (off[k] < 0) {
-            off[k] = total;
-            total += cnt[k];
-        }
-    }
-    h.resize(std::max<int64_t>(1, total));
-    for (int k = 0; k < 6; ++k) {
-        bool first = true;
-        for (int j = 0; j < k; ++j)
-            if (off[j] == off[k])
-                first = false;
-        if (first && cnt[k] > 0)
-            HIP_TRY(hipMemcpyAsync(h.data() + off[k], dev[k], cnt[k] * sizeof(double),
-                                   hipMemcpyDeviceToHost, s));
-    }
-    HIP_TRY(hipStreamSynchronize(s));
-    for (int k = 0; k < 6; ++k)
-        hp[k] = h.data() + off[k];
-    return BLTC_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -405,28 +456,26 @@ int bltc_plan_create(bltc_plan** out, const bltc_params* p, int64_t nt, const do
     if (rc != BLTC_OK)
         return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::vector<double> h;
-    const double* hp[6];
+    bltc_plan* plan = new (std::nothrow) bltc_plan();
+    if (!plan)
+        return fail(BLTC_ENOMEM, "cannot allocate plan");
+    plan->prm = *p;
+    plan->max_q = max_q;
     try {
-        rc = download_coords(nt, tx, ty, tz, ns, sx, sy, sz, h, hp, s);
+        rc = make_device_plan(plan, p, nt, tx, ty, tz, ns, sx, sy, sz, s);
+        if (rc == BLTC_OK)
+            rc = bltc_internal_upload_plan(plan, s);
     } catch (const std::bad_alloc&) {
-        rc = fail(BLTC_ENOMEM, "host allocation failed");
-    }
-    if (rc != BLTC_OK)
-        return rc;
-    rc = create_from_host(out, p, nt, hp[0], hp[1], hp[2], ns, hp[3], hp[4], hp[5], max_q);
-    if (rc != BLTC_OK)
-        return rc;
-    try {
-        rc = bltc_internal_upload_plan(*out, s);
-    } catch (const std::bad_alloc&) {
-        rc = fail(BLTC_ENOMEM, "host allocation failed while uploading");
+        rc = fail(BLTC_ENOMEM, "host allocation failed while planning");
+    } catch (const std::exception& ex) {
+        rc = fail(BLTC_EINTERNAL, "planning failed: %s", ex.what());
     }
     if (rc != BLTC_OK) {
-        delete *out;
-        *out = nullptr;
+        delete plan;
+        return rc;
     }
-    return rc;
+    *out = plan;
+    return BLTC_OK;
 }
 
 int bltc_plan_execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, double* phi,
@@ -531,9 +580,24 @@ int bltc_plan_view_get(const bltc_plan* plan, bltc_plan_view* out)
     out->ns = hp.src.n;
     out->n_clusters = hp.src.nodes();
     out->n_batches = static_cast<int64_t>(hp.batch_begin.size());
-    out->n_items = static_cast<int64_t>(hp.item_batch.size());
+    out->n_items = plan->device_lists ? plan->n_items : static_cast<int64_t>(hp.item_batch.size());
     out->source_order = hp.src.order.data();
     out->target_order = hp.tgt.order.data();
+    if (plan->device_particles) {
+        // tree orders live on the device: copy them once
+        if (plan->view_src_order.size() != static_cast<size_t>(hp.src.n)) {
+            plan->view_src_order.resize(hp.src.n);
+            plan->view_tgt_order.resize(hp.tgt.n);
+            if (hp.src.n > 0)
+                HIP_TRY(hipMemcpy(plan->view_src_order.data(), plan->d.src_order,
+                                  hp.src.n * sizeof(int64_t), hipMemcpyDeviceToHost));
+            if (hp.tgt.n > 0)
+                HIP_TRY(hipMemcpy(plan->view_tgt_order.data(), plan->d.tgt_orig,
+                                  hp.tgt.n * sizeof(int64_t), hipMemcpyDeviceToHost));
+        }
+        out->source_order = plan->view_src_order.data();
+        out->target_order = plan->view_tgt_order.data();
+    }
     out->cluster_begin = hp.src.begin.data();
     out->cluster_count = hp.src.count.data();
     out->cluster_lo = hp.src.lo.data();
@@ -548,6 +612,25 @@ int bltc_plan_view_get(const bltc_plan* plan, bltc_plan_view* out)
     out->item_batch = hp.item_batch.data();
     out->item_cluster = hp.item_cluster.data();
     out->item_kind = hp.item_kind.data();
+    if (plan->device_lists) {
+        if (plan->view_item_batch.size() != static_cast<size_t>(plan->n_items)) {
+            const size_t ni = static_cast<size_t>(plan->n_items);
+            plan->view_item_batch.resize(ni);
+            plan->view_item_cluster.resize(ni);
+            plan->view_item_kind.resize(ni);
+            if (ni > 0) {
+                HIP_TRY(hipMemcpy(plan->view_item_batch.data(), plan->item_batch,
+                                  ni * sizeof(int32_t), hipMemcpyDeviceToHost));
+                HIP_TRY(hipMemcpy(plan->view_item_cluster.data(), plan->item_cluster,
+                                  ni * sizeof(int32_t), hipMemcpyDeviceToHost));
+                HIP_TRY(hipMemcpy(plan->view_item_kind.data(), plan->item_kind,
+                                  ni * sizeof(int32_t), hipMemcpyDeviceToHost));
+            }
+        }
+        out->item_batch = plan->view_item_batch.data();
+        out->item_cluster = plan->view_item_cluster.data();
+        out->item_kind = plan->view_item_kind.data();
+    }
     return BLTC_OK;
 }
 

@@ -62,6 +62,18 @@ struct bltc_plan {
     bltc_params prm{};
     int32_t max_q = 1;
     bltc::HostPlan hp;
+    // true when the trees were built on the device: the per-particle arrays
+    // (positions, orders, local coordinates) exist only in device memory
+    bool device_particles = false;
+    // true when the interaction lists were built on the device
+    bool device_lists = false;
+    int64_t n_items = 0;                 // interaction items (device lists)
+    int32_t* item_batch = nullptr;       // device copies of the items (device lists)
+    int32_t* item_cluster = nullptr;
+    int32_t* item_kind = nullptr;
+    // host copies for bltc_plan_view_get (device-built plans)
+    mutable std::vector<int64_t> view_src_order, view_tgt_order;
+    mutable std::vector<int32_t> view_item_batch, view_item_cluster, view_item_kind;
     bool uploaded = false;
     int device = -1;
     bltc::DevicePlan d;

@@ -19,8 +19,10 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <numeric>
+#include <stdexcept>
 #include <thread>
 
 namespace bltc {
@@ -53,24 +55,50 @@ void parallel_for(int64_t n, F&& f)
         t.join();
 }
 
-int32_t push_node(Tree& t, int64_t begin, int64_t count, int32_t level, int32_t parent)
+}  // namespace
+
+int32_t Tree::add_node(int64_t b, int64_t c, int32_t lev, int32_t par)
 {
-    t.begin.push_back(begin);
-    t.count.push_back(count);
+    begin.push_back(b);
+    count.push_back(c);
     for (int l = 0; l < 3; ++l) {
-        t.lo.push_back(0.0);
-        t.hi.push_back(0.0);
-        t.center.push_back(0.0);
+        lo.push_back(0.0);
+        hi.push_back(0.0);
+        center.push_back(0.0);
     }
-    t.radius.push_back(0.0);
-    t.first_child.push_back(-1);
-    t.nchild.push_back(0);
-    t.level.push_back(level);
-    t.parent.push_back(parent);
-    return static_cast<int32_t>(t.begin.size() - 1);
+    radius.push_back(0.0);
+    first_child.push_back(-1);
+    nchild.push_back(0);
+    level.push_back(lev);
+    parent.push_back(par);
+    depth = std::max(depth, lev);
+    return static_cast<int32_t>(begin.size() - 1);
 }
 
-}  // namespace
+void Tree::set_box(int64_t id, const double a[3], const double b[3])
+{
+    double L[3];
+    for (int l = 0; l < 3; ++l) {
+        lo[3 * id + l] = a[l];
+        hi[3 * id + l] = b[l];
+        center[3 * id + l] = (a[l] + b[l]) / 2.0;
+        L[l] = b[l] - a[l];
+    }
+    radius[id] = 0.5 * std::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
+}
+
+bool node_split(const Tree& t, int64_t id, int64_t cap, bool split[3])
+{
+    double L[3];
+    for (int l = 0; l < 3; ++l)
+        L[l] = t.hi[3 * id + l] - t.lo[3 * id + l];
+    const double Lmax = std::max(L[0], std::max(L[1], L[2]));
+    if (t.count[id] <= cap || Lmax == 0.0)
+        return false;
+    for (int l = 0; l < 3; ++l)
+        split[l] = (2.0 * L[l] * L[l] >= Lmax * Lmax);
+    return true;
+}
 
 void build_tree(Tree& t, int64_t n, const double* x, const double* y, const double* z,
                 int64_t cap)
@@ -84,7 +112,7 @@ void build_tree(Tree& t, int64_t n, const double* x, const double* y, const doub
     t.z.assign(z, z + n);
     if (n == 0)
         return;
-    push_node(t, 0, n, 0, -1);
+    t.add_node(0, n, 0, -1);
 
     std::vector<uint8_t> code;
     std::vector<int64_t> tmp_o;
@@ -101,22 +129,11 @@ void build_tree(Tree& t, int64_t n, const double* x, const double* y, const doub
                 hi[l] = std::max(hi[l], v[l]);
             }
         }
-        double L[3], ctr[3];
-        for (int l = 0; l < 3; ++l) {
-            t.lo[3 * id + l] = lo[l];
-            t.hi[3 * id + l] = hi[l];
-            ctr[l] = (lo[l] + hi[l]) / 2.0;
-            t.center[3 * id + l] = ctr[l];
-            L[l] = hi[l] - lo[l];
-        }
-        t.radius[id] = 0.5 * std::sqrt(L[0] * L[0] + L[1] * L[1] + L[2] * L[2]);
-        t.depth = std::max(t.depth, t.level[id]);
-        const double Lmax = std::max(L[0], std::max(L[1], L[2]));
-        if (c <= cap || Lmax == 0.0)
-            continue;
+        t.set_box(id, lo, hi);
         bool split[3];
-        for (int l = 0; l < 3; ++l)
-            split[l] = (2.0 * L[l] * L[l] >= Lmax * Lmax);
+        if (!node_split(t, id, cap, split))
+            continue;
+        const double ctr[3] = {t.center[3 * id], t.center[3 * id + 1], t.center[3 * id + 2]};
 
         code.resize(c);
         int64_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -162,7 +179,7 @@ void build_tree(Tree& t, int64_t n, const double* x, const double* y, const doub
         for (int k = 0; k < 8; ++k) {
             if (cnt[k] == 0)
                 continue;
-            push_node(t, start, cnt[k], t.level[id] + 1, static_cast<int32_t>(id));
+            t.add_node(start, cnt[k], t.level[id] + 1, static_cast<int32_t>(id));
             start += cnt[k];
             ++nk;
         }
@@ -178,16 +195,31 @@ std::string make_plan(HostPlan& hp, const PlanParams& prm,
     auto t0 = std::chrono::steady_clock::now();
     hp = HostPlan();
     hp.prm = prm;
-    hp.np = prm.degree + 1;
-    hp.P = static_cast<int64_t>(hp.np) * hp.np * hp.np;
-    const int32_t np = hp.np;
 
     build_tree(hp.src, ns, sx, sy, sz, prm.leaf_size);
     if (nt == ns && tx == sx && ty == sy && tz == sz && prm.batch_size == prm.leaf_size)
         hp.tgt = hp.src;    // same particles, same capacity: identical partition
     else
         build_tree(hp.tgt, nt, tx, ty, tz, prm.batch_size);
+    plan_from_trees(hp);
 
+    const Tree& S = hp.src;
+    hp.leaf_of_pos.assign(ns, -1);
+    for (int64_t id = 0; id < S.nodes(); ++id)
+        if (S.nchild[id] == 0)
+            for (int64_t p = S.begin[id]; p < S.begin[id] + S.count[id]; ++p)
+                hp.leaf_of_pos[p] = static_cast<int32_t>(id);
+
+    hp.setup_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return std::string();
+}
+
+void plan_batches(HostPlan& hp)
+{
+    const PlanParams& prm = hp.prm;
+    hp.np = prm.degree + 1;
+    hp.P = static_cast<int64_t>(hp.np) * hp.np * hp.np;
     const Tree& S = hp.src;
     const Tree& T = hp.tgt;
     // batches: leaves of the target tree, ordered by their first position
@@ -209,6 +241,64 @@ std::string make_plan(HostPlan& hp, const PlanParams& prm,
     }
     for (int64_t id = 0; id < S.nodes(); ++id)
         hp.leaves += S.nchild[id] == 0;
+}
+
+void leaf_runs(const Tree& S, std::vector<int32_t>& leaf_list, std::vector<int64_t>& run_lo,
+               std::vector<int64_t>& run_hi)
+{
+    leaf_list.clear();
+    for (int64_t id = 0; id < S.nodes(); ++id)
+        if (S.nchild[id] == 0)
+            leaf_list.push_back(static_cast<int32_t>(id));
+    std::sort(leaf_list.begin(), leaf_list.end(),
+              [&](int32_t a, int32_t b) { return S.begin[a] < S.begin[b]; });
+    std::vector<int64_t> leaf_first(leaf_list.size());
+    for (size_t i = 0; i < leaf_list.size(); ++i)
+        leaf_first[i] = S.begin[leaf_list[i]];
+    run_lo.resize(S.nodes());
+    run_hi.resize(S.nodes());
+    for (int64_t c = 0; c < S.nodes(); ++c) {
+        run_lo[c] = std::lower_bound(leaf_first.begin(), leaf_first.end(), S.begin[c]) -
+                    leaf_first.begin();
+        run_hi[c] = std::lower_bound(leaf_first.begin(), leaf_first.end(),
+                                     S.begin[c] + S.count[c]) - leaf_first.begin();
+    }
+}
+
+void plan_slots(HostPlan& hp, const std::vector<uint8_t>& used)
+{
+    const Tree& S = hp.src;
+    const int32_t np = hp.np;
+    hp.cluster_slot.assign(S.nodes(), -1);
+    hp.slot_cluster.clear();
+    for (int64_t c = 0; c < S.nodes(); ++c)
+        if (used[c]) {
+            hp.cluster_slot[c] = static_cast<int32_t>(hp.slot_cluster.size());
+            hp.slot_cluster.push_back(static_cast<int32_t>(c));
+        }
+    const int64_t nslots = static_cast<int64_t>(hp.slot_cluster.size());
+    hp.slot_nodes.resize(nslots * 3 * np);
+    for (int64_t s = 0; s < nslots; ++s) {
+        const int32_t c = hp.slot_cluster[s];
+        for (int l = 0; l < 3; ++l) {
+            const double a = S.lo[3 * c + l], bb = S.hi[3 * c + l];
+            const double mid = (a + bb) / 2.0;
+            const double h = (bb - a) / 2.0;
+            for (int32_t k = 0; k < np; ++k)
+                hp.slot_nodes[(s * 3 + l) * np + k] =
+                    mid + h * std::cos(M_PI * static_cast<double>(k) / static_cast<double>(hp.prm.degree));
+        }
+    }
+}
+
+void plan_from_trees(HostPlan& hp)
+{
+    plan_batches(hp);
+    const PlanParams& prm = hp.prm;
+    const int64_t ns = hp.src.n;
+    const Tree& S = hp.src;
+    const Tree& T = hp.tgt;
+    const int64_t nb = static_cast<int64_t>(hp.batch_node.size());
 
     // ---- interaction lists (Alg. 1), one traversal per batch --------------
     std::vector<std::vector<int32_t>> approx(nb), direct(nb);
@@ -245,74 +335,94 @@ std::string make_plan(HostPlan& hp, const PlanParams& prm,
     }
 
     // ---- slots: clusters that need modified charges ------------------------
-    hp.cluster_slot.assign(S.nodes(), -1);
-    for (int64_t b = 0; b < nb; ++b)
-        for (int32_t c : approx[b])
-            hp.cluster_slot[c] = 0;
-    for (int64_t c = 0; c < S.nodes(); ++c)
-        if (hp.cluster_slot[c] == 0) {
-            hp.cluster_slot[c] = static_cast<int32_t>(hp.slot_cluster.size());
-            hp.slot_cluster.push_back(static_cast<int32_t>(c));
-        }
-    const int64_t nslots = static_cast<int64_t>(hp.slot_cluster.size());
-    hp.slot_nodes.resize(nslots * 3 * np);
-    for (int64_t s = 0; s < nslots; ++s) {
-        const int32_t c = hp.slot_cluster[s];
-        for (int l = 0; l < 3; ++l) {
-            const double a = S.lo[3 * c + l], bb = S.hi[3 * c + l];
-            const double mid = (a + bb) / 2.0;
-            const double h = (bb - a) / 2.0;
-            for (int32_t k = 0; k < np; ++k)
-                hp.slot_nodes[(s * 3 + l) * np + k] =
-                    mid + h * std::cos(M_PI * static_cast<double>(k) / static_cast<double>(prm.degree));
-        }
+    {
+        std::vector<uint8_t> used(S.nodes(), 0);
+        for (int64_t b = 0; b < nb; ++b)
+            for (int32_t c : approx[b])
+                used[c] = 1;
+        plan_slots(hp, used);
     }
 
     // ---- flattened lists ----------------------------------------------------
+    // The leaves below a node, in depth-first order, are the leaves inside its
+    // position range ordered by their first position: a contiguous run of the
+    // leaf list sorted by begin.
+    std::vector<int32_t> leaf_list;
+    std::vector<int64_t> run_lo, run_hi;
+    leaf_runs(S, leaf_list, run_lo, run_hi);
+    // sizes per batch, offsets, then every batch fills its own range
+    std::vector<int64_t> item_off(nb + 1, 0), far_o(nb + 1, 0), near_o(nb + 1, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t nn = 0;
+        for (int32_t c : direct[b])
+            nn += run_hi[c] - run_lo[c];
+        item_off[b + 1] = item_off[b] + static_cast<int64_t>(approx[b].size() + direct[b].size());
+        far_o[b + 1] = far_o[b] + static_cast<int64_t>(approx[b].size());
+        near_o[b + 1] = near_o[b] + nn;
+    }
+    if (far_o[nb] > INT32_MAX || near_o[nb] > INT32_MAX)
+        throw std::length_error("interaction lists exceed 2^31 entries");
     hp.far_off.assign(nb + 1, 0);
     hp.near_off.assign(nb + 1, 0);
+    for (int64_t b = 0; b <= nb; ++b) {
+        hp.far_off[b] = static_cast<int32_t>(far_o[b]);
+        hp.near_off[b] = static_cast<int32_t>(near_o[b]);
+    }
     hp.batch_cost.assign(nb, 0);
-    for (int64_t b = 0; b < nb; ++b) {
+    hp.item_batch.resize(item_off[nb]);
+    hp.item_cluster.resize(item_off[nb]);
+    hp.item_kind.resize(item_off[nb]);
+    hp.far_slot.resize(far_o[nb]);
+    hp.near_leaf.resize(near_o[nb]);
+    hp.near_begin.resize(near_o[nb]);
+    hp.near_count.resize(near_o[nb]);
+    std::vector<int64_t> far_ev(nb), near_ev(nb);
+    parallel_for(nb, [&](int64_t b) {
         const int64_t nbt = hp.batch_count[b];
+        int64_t it = item_off[b], f = far_o[b], q = near_o[b];
+        int64_t cost = 0, fe = 0, ne = 0;
         for (int32_t c : approx[b]) {
-            hp.item_batch.push_back(static_cast<int32_t>(b));
-            hp.item_cluster.push_back(c);
-            hp.item_kind.push_back(0);
-            hp.far_slot.push_back(hp.cluster_slot[c]);
-            hp.far_evals += nbt * hp.P;
-            hp.batch_cost[b] += hp.P;
+            hp.item_batch[it] = static_cast<int32_t>(b);
+            hp.item_cluster[it] = c;
+            hp.item_kind[it++] = 0;
+            hp.far_slot[f++] = hp.cluster_slot[c];
+            fe += nbt * hp.P;
+            cost += hp.P;
         }
         for (int32_t c : direct[b]) {
-            hp.item_batch.push_back(static_cast<int32_t>(b));
-            hp.item_cluster.push_back(c);
-            hp.item_kind.push_back(1);
-            hp.near_evals += nbt * S.count[c];
-            hp.batch_cost[b] += S.count[c];
-            // expand into the leaves below c (c itself when it is a leaf)
-            std::vector<int32_t> st{c};
-            std::vector<int32_t> leaves;
-            while (!st.empty()) {
-                const int32_t u = st.back();
-                st.pop_back();
-                if (S.nchild[u] == 0) {
-                    leaves.push_back(u);
-                } else {
-                    for (int32_t k = S.nchild[u] - 1; k >= 0; --k)
-                        st.push_back(S.first_child[u] + k);
-                }
-            }
-            for (int32_t u : leaves) {
-                hp.near_leaf.push_back(u);
-                hp.near_begin.push_back(S.begin[u]);
-                hp.near_count.push_back(S.count[u]);
+            hp.item_batch[it] = static_cast<int32_t>(b);
+            hp.item_cluster[it] = c;
+            hp.item_kind[it++] = 1;
+            ne += nbt * S.count[c];
+            cost += S.count[c];
+            // the leaves below c (c itself when it is a leaf)
+            for (int64_t r = run_lo[c]; r < run_hi[c]; ++r) {
+                const int32_t u = leaf_list[r];
+                hp.near_leaf[q] = u;
+                hp.near_begin[q] = S.begin[u];
+                hp.near_count[q++] = S.count[u];
             }
         }
+        hp.batch_cost[b] = cost;
+        far_ev[b] = fe;
+        near_ev[b] = ne;
+    });
+    for (int64_t b = 0; b < nb; ++b) {
+        hp.far_evals += far_ev[b];
+        hp.near_evals += near_ev[b];
         hp.approx_pairs += static_cast<int64_t>(approx[b].size());
         hp.direct_pairs += static_cast<int64_t>(direct[b].size());
-        hp.far_off[b + 1] = static_cast<int32_t>(hp.far_slot.size());
-        hp.near_off[b + 1] = static_cast<int32_t>(hp.near_begin.size());
     }
 
+    plan_schedule(hp);
+}
+
+void plan_schedule(HostPlan& hp)
+{
+    const PlanParams& prm = hp.prm;
+    const Tree& S = hp.src;
+    const int64_t nb = static_cast<int64_t>(hp.batch_node.size());
+    const int64_t nslots = static_cast<int64_t>(hp.slot_cluster.size());
     // ---- upward-pass chunks ----------------------------------------------------
     hp.slot_chunk_off.assign(nslots + 1, 0);
     for (int64_t s = 0; s < nslots; ++s) {
@@ -372,15 +482,6 @@ std::string make_plan(HostPlan& hp, const PlanParams& prm,
             }
     }
 
-    hp.leaf_of_pos.assign(ns, -1);
-    for (int64_t id = 0; id < S.nodes(); ++id)
-        if (S.nchild[id] == 0)
-            for (int64_t p = S.begin[id]; p < S.begin[id] + S.count[id]; ++p)
-                hp.leaf_of_pos[p] = static_cast<int32_t>(id);
-
-    hp.setup_seconds =
-        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return std::string();
 }
 
 }  // namespace bltc

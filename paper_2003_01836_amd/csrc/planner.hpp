@@ -24,7 +24,16 @@ struct Tree {
     std::vector<int32_t> first_child, nchild, level, parent;
     int32_t depth = 0;
     int64_t nodes() const { return static_cast<int64_t>(begin.size()); }
+    // appends a node (box fields zero) and returns its id
+    int32_t add_node(int64_t begin, int64_t count, int32_t level, int32_t parent);
+    // stores the minimal box of node id with its midpoint and half diagonal
+    void set_box(int64_t id, const double lo[3], const double hi[3]);
 };
+
+// Split decision of a node from its minimal box and particle count (tree rules
+// in planner.cpp).  Returns false when the node is a leaf; otherwise split[l]
+// tells whether dimension l is cut at the box midpoint.
+bool node_split(const Tree& t, int64_t id, int64_t cap, bool split[3]);
 
 struct PlanParams {
     double theta = 0.7;
@@ -95,5 +104,24 @@ void build_tree(Tree& t, int64_t n, const double* x, const double* y, const doub
 std::string make_plan(HostPlan& hp, const PlanParams& prm,
                       int64_t nt, const double* tx, const double* ty, const double* tz,
                       int64_t ns, const double* sx, const double* sy, const double* sz);
+
+// The part of the plan that needs only the node arrays of hp.src and hp.tgt
+// (batches, lists, slots, chunks, workgroup schedule); hp.prm is set first.
+// Used after the trees were built on the host or on the device.
+void plan_from_trees(HostPlan& hp);
+
+// Stages of plan_from_trees, for callers that build the lists elsewhere:
+// batches (and n + 1, P) from the target tree;
+void plan_batches(HostPlan& hp);
+// the leaves of the source tree sorted by first position, and for every node
+// the run [run_lo, run_hi) of that list holding the leaves below it (in
+// depth-first order);
+void leaf_runs(const Tree& S, std::vector<int32_t>& leaf_list, std::vector<int64_t>& run_lo,
+               std::vector<int64_t>& run_hi);
+// slots (clusters with modified charges, ascending id) from per-cluster flags;
+void plan_slots(HostPlan& hp, const std::vector<uint8_t>& used);
+// upward-pass chunks and the interaction workgroup schedule (needs the slots,
+// batch counts and batch_cost).
+void plan_schedule(HostPlan& hp);
 
 }  // namespace bltc

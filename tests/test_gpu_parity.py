@@ -99,6 +99,42 @@ def test_fp64_modified_charges_match_oracle(dev):
     assert checked > 10
 
 
+def test_gpu_parent_modified_charges_from_children(dev):
+    # The parent's Lagrange polynomials have degree n in each variable, so
+    # interpolating the children's modified charges onto the parent's grid
+    # reproduces the parent's: q^P_k = sum_child sum_m prod_l L^P_kl(s^child_ml) q^child_m.
+    # Checks the device upward pass level against level, with no oracle q-hat.
+    n = 4
+    pos, q = inputs.uniform_cube(120000, 73)
+    plan, _ = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=n, leaf_size=150, batch_size=150)
+    v = plan.view()
+    have = set(np.unique(v["item_cluster"][v["item_kind"] == 0]).tolist())
+    _, w = oracle.chebyshev(n)
+
+    def nodes(c):
+        return [oracle.chebyshev(n, v["cluster_lo"][c][d], v["cluster_hi"][c][d])[0] for d in range(3)]
+
+    checked = 0
+    for p in sorted(have):
+        nk = v["cluster_nchild"][p]
+        kids = list(range(v["cluster_first_child"][p], v["cluster_first_child"][p] + nk)) if nk > 0 else []
+        if not kids or not all(k in have for k in kids):
+            continue
+        sp = nodes(p)
+        total = np.zeros((n + 1,) * 3)
+        for ch in kids:
+            sc = nodes(ch)
+            T = [np.array([oracle.lagrange(n, sp[d], w, x) for x in sc[d]]) for d in range(3)]
+            total += np.einsum("ai,bj,ck,abc->ijk", T[0], T[1], T[2],
+                               plan.modified_charges(ch).reshape((n + 1,) * 3))
+        qp = plan.modified_charges(p).reshape((n + 1,) * 3)
+        assert np.max(np.abs(total - qp)) <= 1e-11 * np.max(np.abs(qp)), p
+        checked += 1
+        if checked == 6:
+            break
+    assert checked >= 1
+
+
 @pytest.mark.parametrize("degree", [1, 2, 3, 6, 8, 11, 16])
 def test_fp64_all_degrees(dev, degree):
     pos, q = inputs.uniform_cube(6000, 80 + degree)
