@@ -4,7 +4,8 @@ Plain FP64 C code (``bltc_oracle.c``) behind a ctypes wrapper.  It computes the
 direct sum of eq. (1) and the treecode of Alg. 1 (tree of source clusters,
 target batches, two-part MAC of eq. (13), modified charges of eq. (12) with the
 removable-singularity rule of eq. (5), approximation eq. (11) and direct sum
-eq. (9)) of Vaughn, Wilson and Krasny (2020).
+eq. (9)) of Vaughn, Wilson and Krasny (2020), and the cluster-particle variant
+(the same interpolation in the target variable) that the paper's outlook names.
 
 Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
 may import this package.  It shares no code with the GPU library and never
@@ -65,6 +66,18 @@ def _load():
     lib.oracle_tc_potential.argtypes = [vp, vp, i32, i64, i32, d, i64, vp, vp, i64, vp]
     lib.oracle_tc_potential.restype = ctypes.c_int
     lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_cp_create.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, d, i32, i64, i64]
+    lib.oracle_cp_create.restype = vp
+    lib.oracle_cp_destroy.argtypes = [vp]
+    lib.oracle_cp_sizes.argtypes = [vp, vp]
+    lib.oracle_cp_target_order.argtypes = [vp, vp]
+    lib.oracle_cp_source_order.argtypes = [vp, vp]
+    lib.oracle_cp_cluster.argtypes = [vp, i64, vp, vp, vp, vp]
+    lib.oracle_cp_batch.argtypes = [vp, i64, vp]
+    lib.oracle_cp_items.argtypes = [vp, vp, vp, vp]
+    lib.oracle_cp_proxy_potentials.argtypes = [vp, i32, vp, i32, d, vp]
+    lib.oracle_cp_potential.argtypes = [vp, vp, i32, d, i64, vp, vp, vp]
+    lib.oracle_cp_potential.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -243,6 +256,108 @@ class Treecode:
         if return_times:
             return res, {"upward": float(times[0]), "eval": float(times[1])}
         return res
+
+
+class ClusterParticle:
+    """Oracle barycentric cluster-particle treecode: the interpolation of the
+    BLTC applied to the target variable.  Targets form the cluster tree
+    (capacity leaf_size), the leaves of the source tree (capacity batch_size)
+    are the source batches; each source batch walks the target tree with the
+    MAC of eq. (13).  Single charge vector."""
+
+    def __init__(self, targets, sources, theta, degree, leaf_size, batch_size):
+        lib = _load()
+        self._t = _f64(targets)
+        self._s = _f64(sources)
+        self._tc_cols = [np.ascontiguousarray(self._t[:, c]) for c in range(3)]
+        self._sc_cols = [np.ascontiguousarray(self._s[:, c]) for c in range(3)]
+        self.nt = self._t.shape[0]
+        self.ns = self._s.shape[0]
+        self.degree = int(degree)
+        if not (1 <= self.degree <= 60):
+            raise ValueError("degree out of range")
+        tx, ty, tz = self._tc_cols
+        sx, sy, sz = self._sc_cols
+        self._h = lib.oracle_cp_create(self.nt, _ptr(tx), _ptr(ty), _ptr(tz),
+                                       self.ns, _ptr(sx), _ptr(sy), _ptr(sz),
+                                       float(theta), self.degree, int(leaf_size), int(batch_size))
+        if not self._h:
+            raise RuntimeError("oracle treecode creation failed")
+        sizes = np.zeros(4, dtype=np.int64)
+        lib.oracle_cp_sizes(self._h, _ptr(sizes))
+        self.n_clusters, self.n_batches, self.n_items, self.n_source_nodes = (int(v) for v in sizes)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _load().oracle_cp_destroy(h)
+            self._h = None
+
+    def target_order(self):
+        out = np.zeros(self.nt, dtype=np.int64)
+        _load().oracle_cp_target_order(self._h, _ptr(out))
+        return out
+
+    def source_order(self):
+        out = np.zeros(self.ns, dtype=np.int64)
+        _load().oracle_cp_source_order(self._h, _ptr(out))
+        return out
+
+    def cluster(self, i):
+        """Target cluster i (range in target tree order)."""
+        lo = np.zeros(3)
+        hi = np.zeros(3)
+        bc = np.zeros(2, dtype=np.int64)
+        ncl = np.zeros(10, dtype=np.int32)
+        _load().oracle_cp_cluster(self._h, int(i), _ptr(lo), _ptr(hi), _ptr(bc), _ptr(ncl))
+        nch = int(ncl[0])
+        return {"lo": lo, "hi": hi, "begin": int(bc[0]), "count": int(bc[1]),
+                "children": [int(c) for c in ncl[1:1 + nch]], "level": int(ncl[9])}
+
+    def batch(self, b):
+        """Source batch b (range in source tree order)."""
+        bc = np.zeros(2, dtype=np.int64)
+        _load().oracle_cp_batch(self._h, int(b), _ptr(bc))
+        return {"begin": int(bc[0]), "count": int(bc[1])}
+
+    def items(self):
+        """(source batch, target cluster, kind) for every interaction; kind 0 = approx."""
+        b = np.zeros(self.n_items, dtype=np.int64)
+        c = np.zeros(self.n_items, dtype=np.int32)
+        k = np.zeros(self.n_items, dtype=np.int32)
+        _load().oracle_cp_items(self._h, _ptr(b), _ptr(c), _ptr(k))
+        return b, c, k
+
+    def proxy_potentials(self, c, charges, kernel=COULOMB, kappa=0.0):
+        """Potentials at target cluster c's Chebyshev grid: (n+1, n+1, n+1)."""
+        q = _f64(charges)
+        if q.ndim != 1 or q.shape[0] != self.ns:
+            raise ValueError("charges must have one value per source")
+        np1 = self.degree + 1
+        out = np.zeros(np1 ** 3)
+        _load().oracle_cp_proxy_potentials(self._h, int(c), _ptr(q), int(kernel), float(kappa),
+                                           _ptr(out))
+        return out.reshape(np1, np1, np1)
+
+    def potential(self, charges, kernel=COULOMB, kappa=0.0, sample=None, return_times=False):
+        """Potential at all targets (caller order), or at `sample` (indices)."""
+        q = _f64(charges)
+        if q.ndim != 1 or q.shape[0] != self.ns:
+            raise ValueError("charges must have one value per source")
+        if sample is None:
+            n_eval, sp = self.nt, None
+        else:
+            smp = np.ascontiguousarray(sample, dtype=np.int64)
+            n_eval, sp = smp.shape[0], _ptr(smp)
+        phi = np.zeros(n_eval)
+        times = np.zeros(2)
+        rc = _load().oracle_cp_potential(self._h, _ptr(q), int(kernel), float(kappa), n_eval, sp,
+                                         _ptr(phi), _ptr(times))
+        if rc != 0:
+            raise ValueError("sample index out of range")
+        if return_times:
+            return phi, {"proxy": float(times[0]), "eval": float(times[1])}
+        return phi
 
 
 def rel_l2(ref, approx):

@@ -654,3 +654,376 @@ int oracle_tc_potential(const otc *tc, const double *q, int32_t m, int64_t q_ld,
     free(batch_used);
     return 0;
 }
+
+/* ========================================================================= */
+/* Barycentric cluster-particle treecode (CP).                                */
+/*                                                                            */
+/* Sec. V names the cluster-particle variant as a GPU extension: the same     */
+/* barycentric interpolation (eqs. 4-7) applied in the target variable.       */
+/* Readings (listed with the others in the design notes):                     */
+/*   R16 targets form the cluster tree (capacity leaf = N_L, the interpolated */
+/*       side); sources form a tree of capacity batch = N_B whose leaves are  */
+/*       the source batches; both trees follow R2 and R5-R8;                  */
+/*   R17 for a source batch S and target cluster T the MAC of eq. 13 reads    */
+/*       r_S + r_T < theta R and (n+1)^3 < N_T, with the branch order of R4   */
+/*       (ComputePotential with the roles of the two trees exchanged);        */
+/*   R18 an approximated pair adds to the proxy potentials of T,              */
+/*       phihat_T(t_k) += sum_{j in S} G(t_k, y_j) q_j, and every target      */
+/*       x in T receives sum_k L_k(x) phihat_T(t_k), L_k the tensor product  */
+/*       of eq. 4 over T's grid (eq. 5 rule for a coordinate on a node);      */
+/*   R19 a direct pair adds sum_{j in S, r != 0} G(x_i, y_j) q_j to every     */
+/*       target of T (R1).                                                    */
+/* For a symmetric kernel the CP matrix is the transpose of the BLTC matrix  */
+/* with targets and sources exchanged (same trees, same MAC decisions).       */
+/* ========================================================================= */
+typedef struct {
+    int64_t nt, ns;
+    const double *tx, *ty, *tz, *sx, *sy, *sz;
+    double theta;
+    int32_t n;
+    int64_t leaf, batch;
+    otree tgt;               /* target clusters (interpolated side) */
+    otree src;               /* source tree; its leaves are the source batches */
+    int32_t *batch_node;     /* source-tree node of each source batch, depth-first order */
+    int64_t n_batches;
+    oitem **items;           /* per source batch: (target cluster, kind) */
+    int64_t *n_items, *cap_items;
+    double t_setup;
+} ocp;
+
+static void cp_push(ocp *cp, int64_t b, int32_t cluster, int32_t kind)
+{
+    if (cp->n_items[b] == cp->cap_items[b]) {
+        cp->cap_items[b] = cp->cap_items[b] ? 2 * cp->cap_items[b] : 16;
+        cp->items[b] = (oitem *)realloc(cp->items[b], (size_t)cp->cap_items[b] * sizeof(oitem));
+    }
+    cp->items[b][cp->n_items[b]].cluster = cluster;
+    cp->items[b][cp->n_items[b]].kind = kind;
+    cp->n_items[b]++;
+}
+
+/* ComputePotential with the target tree traversed for a source batch (R17). */
+static void cp_traverse(ocp *cp, int64_t b, const onode *S, int32_t tid)
+{
+    const onode *T = &cp->tgt.nodes[tid];
+    double dx = S->center[0] - T->center[0];
+    double dy = S->center[1] - T->center[1];
+    double dz = S->center[2] - T->center[2];
+    double R = sqrt(dx * dx + dy * dy + dz * dz);
+    int64_t P = (int64_t)(cp->n + 1) * (cp->n + 1) * (cp->n + 1);
+    int geometric = (S->radius + T->radius < cp->theta * R);
+    int size = (P < T->count);
+    if (geometric && size) {
+        cp_push(cp, b, tid, 0);
+    } else if (!geometric) {
+        if (T->nchild == 0) {
+            cp_push(cp, b, tid, 1);
+        } else {
+            int32_t nk = T->nchild;
+            int32_t kids[8];
+            memcpy(kids, T->child, sizeof(kids));
+            for (int32_t c = 0; c < nk; ++c)
+                cp_traverse(cp, b, S, kids[c]);
+        }
+    } else {
+        cp_push(cp, b, tid, 1);
+    }
+}
+
+ocp *oracle_cp_create(int64_t nt, const double *tx, const double *ty, const double *tz,
+                      int64_t ns, const double *sx, const double *sy, const double *sz,
+                      double theta, int32_t degree, int64_t leaf, int64_t batch)
+{
+    double t0 = wall_seconds();
+    ocp *cp = (ocp *)calloc(1, sizeof(ocp));
+    cp->nt = nt; cp->ns = ns;
+    cp->tx = tx; cp->ty = ty; cp->tz = tz;
+    cp->sx = sx; cp->sy = sy; cp->sz = sz;
+    cp->theta = theta; cp->n = degree; cp->leaf = leaf; cp->batch = batch;
+    tree_build(&cp->tgt, nt, tx, ty, tz, leaf);
+    tree_build(&cp->src, ns, sx, sy, sz, batch);
+
+    int64_t nb = 0;
+    for (int64_t i = 0; i < cp->src.n_nodes; ++i)
+        nb += cp->src.nodes[i].nchild == 0;
+    cp->n_batches = nb;
+    cp->batch_node = (int32_t *)malloc((size_t)(nb > 0 ? nb : 1) * sizeof(int32_t));
+    {
+        int64_t sp = 0, k = 0;
+        int32_t *stack = (int32_t *)malloc((size_t)(cp->src.n_nodes + 1) * sizeof(int32_t));
+        if (cp->src.n_nodes > 0)
+            stack[sp++] = 0;
+        while (sp > 0) {
+            int32_t id = stack[--sp];
+            const onode *nd = &cp->src.nodes[id];
+            if (nd->nchild == 0) {
+                cp->batch_node[k++] = id;
+            } else {
+                for (int32_t c = nd->nchild - 1; c >= 0; --c)
+                    stack[sp++] = nd->child[c];
+            }
+        }
+        free(stack);
+    }
+    cp->items = (oitem **)calloc((size_t)(nb > 0 ? nb : 1), sizeof(oitem *));
+    cp->n_items = (int64_t *)calloc((size_t)(nb > 0 ? nb : 1), sizeof(int64_t));
+    cp->cap_items = (int64_t *)calloc((size_t)(nb > 0 ? nb : 1), sizeof(int64_t));
+    if (nt > 0) {
+        int64_t b;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (b = 0; b < nb; ++b)
+            cp_traverse(cp, b, &cp->src.nodes[cp->batch_node[b]], 0);
+    }
+    cp->t_setup = wall_seconds() - t0;
+    return cp;
+}
+
+void oracle_cp_destroy(ocp *cp)
+{
+    if (!cp)
+        return;
+    for (int64_t b = 0; b < cp->n_batches; ++b)
+        free(cp->items[b]);
+    free(cp->items);
+    free(cp->n_items);
+    free(cp->cap_items);
+    free(cp->batch_node);
+    tree_free(&cp->tgt);
+    tree_free(&cp->src);
+    free(cp);
+}
+
+/* sizes: target clusters, source batches, items, source-tree nodes */
+void oracle_cp_sizes(const ocp *cp, int64_t *out /* [4] */)
+{
+    int64_t total = 0;
+    for (int64_t b = 0; b < cp->n_batches; ++b)
+        total += cp->n_items[b];
+    out[0] = cp->tgt.n_nodes;
+    out[1] = cp->n_batches;
+    out[2] = total;
+    out[3] = cp->src.n_nodes;
+}
+
+void oracle_cp_target_order(const ocp *cp, int64_t *out)
+{
+    memcpy(out, cp->tgt.idx, (size_t)cp->nt * sizeof(int64_t));
+}
+
+void oracle_cp_source_order(const ocp *cp, int64_t *out)
+{
+    memcpy(out, cp->src.idx, (size_t)cp->ns * sizeof(int64_t));
+}
+
+/* target cluster i: lo[3], hi[3], begin, count (target tree order), nchild, children, level */
+void oracle_cp_cluster(const ocp *cp, int64_t i, double *lo, double *hi, int64_t *begin_count,
+                       int32_t *nchild_children_level)
+{
+    const onode *nd = &cp->tgt.nodes[i];
+    for (int l = 0; l < 3; ++l) {
+        lo[l] = nd->lo[l];
+        hi[l] = nd->hi[l];
+    }
+    begin_count[0] = nd->begin;
+    begin_count[1] = nd->count;
+    nchild_children_level[0] = nd->nchild;
+    for (int c = 0; c < 8; ++c)
+        nchild_children_level[1 + c] = c < nd->nchild ? nd->child[c] : -1;
+    nchild_children_level[9] = nd->level;
+}
+
+/* source batch b: begin, count in source tree order */
+void oracle_cp_batch(const ocp *cp, int64_t b, int64_t *begin_count)
+{
+    const onode *nd = &cp->src.nodes[cp->batch_node[b]];
+    begin_count[0] = nd->begin;
+    begin_count[1] = nd->count;
+}
+
+/* all items, source-batch-major: batch, target cluster, kind */
+void oracle_cp_items(const ocp *cp, int64_t *batch, int32_t *cluster, int32_t *kind)
+{
+    int64_t k = 0;
+    for (int64_t b = 0; b < cp->n_batches; ++b)
+        for (int64_t t = 0; t < cp->n_items[b]; ++t) {
+            batch[k] = b;
+            cluster[k] = cp->items[b][t].cluster;
+            kind[k] = cp->items[b][t].kind;
+            ++k;
+        }
+}
+
+/* Proxy potentials of target cluster c (R18): out[k] = sum over the source   */
+/* batches S approximated with c, sum_{j in S, r != 0} G(t_k, y_j) q_j,        */
+/* k = (k1*(n+1) + k2)*(n+1) + k3, t_k from R10 on c's box.                   */
+void oracle_cp_proxy_potentials(const ocp *cp, int32_t c, const double *q, int32_t kernel,
+                                double kappa, double *out)
+{
+    const onode *T = &cp->tgt.nodes[c];
+    int32_t n = cp->n, np = n + 1;
+    int64_t P = (int64_t)np * np * np;
+    double t[3][64], w[64];
+    for (int l = 0; l < 3; ++l)
+        oracle_chebyshev(n, T->lo[l], T->hi[l], t[l], w);
+    memset(out, 0, (size_t)P * sizeof(double));
+    for (int64_t b = 0; b < cp->n_batches; ++b)
+        for (int64_t it = 0; it < cp->n_items[b]; ++it) {
+            if (cp->items[b][it].cluster != c || cp->items[b][it].kind != 0)
+                continue;
+            const onode *S = &cp->src.nodes[cp->batch_node[b]];
+            for (int64_t a = S->begin; a < S->begin + S->count; ++a) {
+                int64_t j = cp->src.idx[a];
+                for (int32_t k1 = 0; k1 < np; ++k1)
+                    for (int32_t k2 = 0; k2 < np; ++k2)
+                        for (int32_t k3 = 0; k3 < np; ++k3) {
+                            double dx = t[0][k1] - cp->sx[j];
+                            double dy = t[1][k2] - cp->sy[j];
+                            double dz = t[2][k3] - cp->sz[j];
+                            double r = sqrt(dx * dx + dy * dy + dz * dz);
+                            if (r == 0.0)
+                                continue;
+                            out[((int64_t)k1 * np + k2) * np + k3] +=
+                                kernel_of_distance(r, kernel, kappa) * q[j];
+                        }
+            }
+        }
+}
+
+/* Evaluation: phi[s] at target sample[s] (all targets when sample == NULL):  */
+/* for every target cluster T on the path from the root to the target's leaf, */
+/* the direct sums of T's direct source batches (R19) and the interpolant of  */
+/* T's proxy potentials (R18).  times[0] = proxy potentials, times[1] = rest. */
+int oracle_cp_potential(const ocp *cp, const double *q, int32_t kernel, double kappa,
+                        int64_t n_sample, const int64_t *sample, double *phi, double *times)
+{
+    int32_t n = cp->n, np = n + 1;
+    int64_t P = (int64_t)np * np * np;
+    int64_t n_eval = sample ? n_sample : cp->nt;
+    int64_t nn = cp->tgt.n_nodes;
+    double t0 = wall_seconds();
+
+    /* target tree position of each target */
+    int64_t *pos = (int64_t *)malloc((size_t)(cp->nt > 0 ? cp->nt : 1) * sizeof(int64_t));
+    for (int64_t a = 0; a < cp->nt; ++a)
+        pos[cp->tgt.idx[a]] = a;
+    /* per target cluster: approximated and direct source batches */
+    int64_t *n_far = (int64_t *)calloc((size_t)(nn > 0 ? nn : 1), sizeof(int64_t));
+    int64_t *n_dir = (int64_t *)calloc((size_t)(nn > 0 ? nn : 1), sizeof(int64_t));
+    for (int64_t b = 0; b < cp->n_batches; ++b)
+        for (int64_t it = 0; it < cp->n_items[b]; ++it)
+            (cp->items[b][it].kind == 0 ? n_far : n_dir)[cp->items[b][it].cluster]++;
+    int64_t **dir = (int64_t **)calloc((size_t)(nn > 0 ? nn : 1), sizeof(int64_t *));
+    int64_t *fill = (int64_t *)calloc((size_t)(nn > 0 ? nn : 1), sizeof(int64_t));
+    for (int64_t c = 0; c < nn; ++c)
+        dir[c] = (int64_t *)malloc((size_t)(n_dir[c] > 0 ? n_dir[c] : 1) * sizeof(int64_t));
+    for (int64_t b = 0; b < cp->n_batches; ++b)
+        for (int64_t it = 0; it < cp->n_items[b]; ++it)
+            if (cp->items[b][it].kind == 1) {
+                int32_t c = cp->items[b][it].cluster;
+                dir[c][fill[c]++] = b;
+            }
+    /* proxy potentials of the clusters on the sampled targets' paths */
+    char *need = (char *)calloc((size_t)(nn > 0 ? nn : 1), 1);
+    for (int64_t s = 0; s < n_eval; ++s) {
+        int64_t i = sample ? sample[s] : s;
+        if (i < 0 || i >= cp->nt) {
+            free(need);
+            free(pos);
+            free(n_far);
+            free(n_dir);
+            for (int64_t c = 0; c < nn; ++c)
+                free(dir[c]);
+            free(dir);
+            free(fill);
+            return -1;
+        }
+        int64_t a = pos[i];
+        for (int32_t c = 0; c >= 0;) {
+            if (n_far[c] > 0)
+                need[c] = 1;
+            int32_t next = -1;
+            const onode *nd = &cp->tgt.nodes[c];
+            for (int32_t k = 0; k < nd->nchild; ++k) {
+                const onode *ch = &cp->tgt.nodes[nd->child[k]];
+                if (a >= ch->begin && a < ch->begin + ch->count)
+                    next = nd->child[k];
+            }
+            c = next;
+        }
+    }
+    double **phat = (double **)calloc((size_t)(nn > 0 ? nn : 1), sizeof(double *));
+    {
+        int64_t c;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (c = 0; c < nn; ++c)
+            if (need[c]) {
+                double *buf = (double *)malloc((size_t)P * sizeof(double));
+                oracle_cp_proxy_potentials(cp, (int32_t)c, q, kernel, kappa, buf);
+                phat[c] = buf;
+            }
+    }
+    double t1 = wall_seconds();
+    {
+        int64_t s;
+#pragma omp parallel for schedule(dynamic, 8)
+        for (s = 0; s < n_eval; ++s) {
+            int64_t i = sample ? sample[s] : s;
+            int64_t a = pos[i];
+            double x[3] = {cp->tx[i], cp->ty[i], cp->tz[i]};
+            double acc = 0.0;
+            double nodes[64], w[64], L[3][64];
+            for (int32_t c = 0; c >= 0;) {
+                const onode *T = &cp->tgt.nodes[c];
+                for (int64_t u = 0; u < n_dir[c]; ++u) {
+                    const onode *S = &cp->src.nodes[cp->batch_node[dir[c][u]]];
+                    for (int64_t e = S->begin; e < S->begin + S->count; ++e) {
+                        int64_t j = cp->src.idx[e];
+                        double dx = x[0] - cp->sx[j];
+                        double dy = x[1] - cp->sy[j];
+                        double dz = x[2] - cp->sz[j];
+                        double r = sqrt(dx * dx + dy * dy + dz * dz);
+                        if (r == 0.0)
+                            continue;
+                        acc += kernel_of_distance(r, kernel, kappa) * q[j];
+                    }
+                }
+                if (phat[c]) {
+                    for (int l = 0; l < 3; ++l) {
+                        oracle_chebyshev(n, T->lo[l], T->hi[l], nodes, w);
+                        oracle_lagrange(n, nodes, w, x[l], L[l]);
+                    }
+                    for (int32_t k1 = 0; k1 < np; ++k1)
+                        for (int32_t k2 = 0; k2 < np; ++k2)
+                            for (int32_t k3 = 0; k3 < np; ++k3)
+                                acc += L[0][k1] * L[1][k2] * L[2][k3] *
+                                       phat[c][((int64_t)k1 * np + k2) * np + k3];
+                }
+                int32_t next = -1;
+                for (int32_t k = 0; k < T->nchild; ++k) {
+                    const onode *ch = &cp->tgt.nodes[T->child[k]];
+                    if (a >= ch->begin && a < ch->begin + ch->count)
+                        next = T->child[k];
+                }
+                c = next;
+            }
+            phi[s] = acc;
+        }
+    }
+    double t2 = wall_seconds();
+    if (times) {
+        times[0] = t1 - t0;
+        times[1] = t2 - t1;
+    }
+    for (int64_t c = 0; c < nn; ++c) {
+        free(phat[c]);
+        free(dir[c]);
+    }
+    free(phat);
+    free(dir);
+    free(fill);
+    free(need);
+    free(pos);
+    free(n_far);
+    free(n_dir);
+    return 0;
+}
