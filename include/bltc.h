@@ -9,7 +9,9 @@
  * Chebyshev points of the 2nd kind (eqs. 6-7, 12; computed in the two-step form
  * of eqs. 14-15 with the removable-singularity rule of eq. 5), then for every
  * batch/cluster pair either the approximation of eq. 11 (MAC of eq. 13 holds)
- * or the direct sum of eq. 9 (it fails).
+ * or the direct sum of eq. 9 (it fails).  The same interpolation applied to
+ * the target variable (the cluster-particle treecode that the paper's outlook,
+ * Sec. V, names) is available as a second method.
  *
  * Conventions shared by every entry point:
  *  - Counts are int64_t.  Coordinates are structure-of-arrays FP64: x, y, z are
@@ -58,23 +60,41 @@ typedef enum { BLTC_COULOMB = 0, BLTC_YUKAWA = 1 } bltc_kernel;
  *                   pairs closer than a fixed cut-off stay FP64. */
 typedef enum { BLTC_FP64 = 0, BLTC_FP32_MIXED = 1 } bltc_precision;
 
+/* Which side is interpolated.
+ *  BLTC_PARTICLE_CLUSTER  the paper's BLTC (Alg. 1): source clusters carry
+ *                         modified charges (eq. 12) on their Chebyshev grids,
+ *                         targets are grouped in batches.
+ *  BLTC_CLUSTER_PARTICLE  targets form the cluster tree and sources the
+ *                         batches: an approximated (source batch S, target
+ *                         cluster T) pair adds the potential of S at T's
+ *                         Chebyshev points; every target then receives the
+ *                         barycentric interpolant (eqs. 4-5) of the proxy
+ *                         potentials of each cluster on its root-to-leaf path.
+ *                         MAC of eq. 13 with the roles exchanged:
+ *                         r_S + r_T < theta R and (n+1)^3 < N_T.  One charge
+ *                         vector per execution; not usable in a bltc_batch. */
+typedef enum { BLTC_PARTICLE_CLUSTER = 0, BLTC_CLUSTER_PARTICLE = 1 } bltc_method;
+
 typedef struct {
     int32_t kernel;              /* bltc_kernel                                         */
     int32_t precision;           /* bltc_precision                                      */
     double kappa;                /* Yukawa inverse Debye length, >= 0 (eq. 2)           */
     double theta;                /* MAC parameter, 0 <= theta < 1 (eq. 13); 0 = direct  */
     int32_t degree;              /* interpolation degree n, 1..16 (eqs. 6-8)            */
-    int32_t leaf_size;           /* N_L >= 1: clusters with <= N_L sources are leaves  */
-    int32_t batch_size;          /* N_B >= 1: batches hold <= N_B targets              */
+    int32_t leaf_size;           /* N_L >= 1: leaf capacity of the interpolated side's  */
+                                 /* cluster tree (sources; targets for CLUSTER_PARTICLE) */
+    int32_t batch_size;          /* N_B >= 1: capacity of the batches of the other side */
     int32_t threads_per_target;  /* 0 or 1 (reserved for split target evaluation)      */
+    int32_t method;              /* bltc_method                                         */
 } bltc_params;
 
-/* Fills *p with the defaults: Coulomb, FP64, theta 0.7, degree 8, N_L = N_B = 2000. */
+/* Fills *p with the defaults: Coulomb, FP64, theta 0.7, degree 8,
+ * N_L = N_B = 2000, BLTC_PARTICLE_CLUSTER. */
 void bltc_params_default(bltc_params* p);
 
 /* One-shot evaluation (Alg. 1): builds the tree, batches and interaction lists
- * on the host (coordinates are copied device->host), then computes
- * phi[m*phi_ld + i], m < num_q, on the GPU.  Synchronises `stream`.
+ * (on the GPU, as bltc_plan_create), then computes phi[m*phi_ld + i],
+ * m < num_q, on the GPU.  Synchronises `stream`.
  * nt == 0 is a no-op; ns == 0 writes zeros.  Coordinates must be finite
  * (BLTC_EINVAL otherwise). */
 int bltc_potential(const bltc_params* p,
@@ -87,9 +107,15 @@ int bltc_potential(const bltc_params* p,
  * coordinates in tree order) so that charges can vary between executions. */
 typedef struct bltc_plan bltc_plan;
 
-/* Creates a plan from DEVICE coordinates (copied device->host for planning,
- * then uploaded in tree order on `stream`; synchronises `stream`).
- * max_q >= 1 bounds num_q of later executions. */
+/* Creates a plan from DEVICE coordinates.  The setup phase runs on the GPU
+ * on `stream`: both trees are built there (only per-node data comes back to
+ * the host, which takes the split decisions), and for BLTC_PARTICLE_CLUSTER
+ * the interaction lists of Alg. 1 are built there as well; particles are
+ * written in tree order directly into the plan's device arrays.  The result
+ * equals the plan bltc_plan_create_host builds from the same coordinates.
+ * Synchronises `stream`.  max_q >= 1 bounds num_q of later executions
+ * (max_q must be 1 for BLTC_CLUSTER_PARTICLE).  At most 2^31 - 1 particles
+ * per side.  Non-finite coordinates: BLTC_EINVAL. */
 int bltc_plan_create(bltc_plan** out, const bltc_params* p,
                      int64_t nt, const double* tx, const double* ty, const double* tz,
                      int64_t ns, const double* sx, const double* sy, const double* sz,
@@ -115,10 +141,17 @@ int bltc_plan_execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q
  * source cluster `cluster` (an index into the cluster arrays of
  * bltc_plan_view) and charge vector `qi` into the HOST buffer out[(n+1)^3],
  * ordered k = (k1*(n+1) + k2)*(n+1) + k3.  Synchronises `stream`.
- * BLTC_EINVAL if the cluster is in no approximation list (no charges formed). */
+ * BLTC_EINVAL if the cluster is in no approximation list (no charges formed).
+ * For BLTC_CLUSTER_PARTICLE plans `cluster` is a target cluster and out
+ * receives its proxy potentials (qi = 0). */
 int bltc_plan_modified_charges(bltc_plan* plan, int64_t cluster, int32_t qi,
                                double* out, void* stream);
 
+/* For BLTC_CLUSTER_PARTICLE plans the cluster fields describe the target
+ * tree, the batches are the source batches, far_evals counts the proxy
+ * potential evaluations (sum over approx pairs of (n+1)^3 * N_S) and
+ * upward_terms the interpolation terms (sum over approx clusters of
+ * N_T * (n+1)^3). */
 typedef struct {
     int64_t clusters;        /* source clusters in the tree                         */
     int64_t leaves;          /* leaf clusters                                       */
@@ -129,11 +162,11 @@ typedef struct {
     int64_t far_evals;       /* sum over approx pairs of N_B * (n+1)^3               */
     int64_t near_evals;      /* sum over direct pairs of N_B * N_C                   */
     int64_t upward_terms;    /* sum over approx clusters of N_C * (n+1)^3            */
-    int32_t depth;           /* deepest source-tree level (root = 0)                */
+    int32_t depth;           /* deepest cluster-tree level (root = 0)               */
     int32_t degree;
     int32_t leaf_size;
     int32_t batch_size;
-    double setup_seconds;    /* host planning time                                  */
+    double setup_seconds;    /* planning time (trees and lists)                     */
 } bltc_stats;
 
 int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out);
@@ -150,7 +183,12 @@ int bltc_plan_phase_times(bltc_plan* plan, double* ms /* [4] */);
 
 /* Read-only HOST view of a plan's structure (valid until the plan is
  * destroyed).  Cluster ids index the cluster arrays; the children of cluster c
- * are cluster_first_child[c] .. + cluster_nchild[c] - 1. */
+ * are cluster_first_child[c] .. + cluster_nchild[c] - 1.  For plans built on
+ * the GPU the orders and items are copied to the host on the first call.
+ * For BLTC_CLUSTER_PARTICLE plans the clusters are the target tree's nodes
+ * (cluster_begin/count index target_order), the batches are the source
+ * batches (batch_begin/count index source_order) and an item is (source
+ * batch, target cluster, kind). */
 typedef struct {
     int64_t nt, ns, n_clusters, n_batches, n_items;
     const int64_t* source_order;        /* [ns] original index at tree position    */

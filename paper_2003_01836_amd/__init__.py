@@ -22,6 +22,10 @@ __all__ = ["params", "Plan", "Batch", "autotune", "potential", "direct", "BLTCEr
 
 _KERNELS = {"coulomb": _capi.COULOMB, "yukawa": _capi.YUKAWA}
 _PRECISIONS = {"fp64": _capi.FP64, "fp32_mixed": _capi.FP32_MIXED, "mixed": _capi.FP32_MIXED}
+# "bltc": the paper's particle-cluster treecode (sources interpolated);
+# "cp": cluster-particle (targets interpolated)
+_METHODS = {"bltc": _capi.PARTICLE_CLUSTER, "particle_cluster": _capi.PARTICLE_CLUSTER,
+            "cp": _capi.CLUSTER_PARTICLE, "cluster_particle": _capi.CLUSTER_PARTICLE}
 
 
 def library_path() -> str:
@@ -33,7 +37,7 @@ def version() -> str:
 
 
 def params(kernel="coulomb", kappa=0.0, theta=0.7, degree=8, leaf_size=2000, batch_size=2000,
-           precision="fp64", threads_per_target=0) -> _capi.Params:
+           precision="fp64", threads_per_target=0, method="bltc") -> _capi.Params:
     p = _capi.Params()
     _capi.load().bltc_params_default(ctypes.byref(p))
     p.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
@@ -44,6 +48,7 @@ def params(kernel="coulomb", kappa=0.0, theta=0.7, degree=8, leaf_size=2000, bat
     p.leaf_size = int(leaf_size)
     p.batch_size = int(batch_size)
     p.threads_per_target = int(threads_per_target)
+    p.method = _METHODS[method] if isinstance(method, str) else int(method)
     return p
 
 

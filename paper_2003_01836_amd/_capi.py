@@ -18,6 +18,8 @@ COULOMB = 0
 YUKAWA = 1
 FP64 = 0
 FP32_MIXED = 1
+PARTICLE_CLUSTER = 0
+CLUSTER_PARTICLE = 1
 
 # every exported symbol of include/bltc.h
 EXPORTS = (
@@ -39,6 +41,7 @@ class Params(ctypes.Structure):
         ("leaf_size", ctypes.c_int32),
         ("batch_size", ctypes.c_int32),
         ("threads_per_target", ctypes.c_int32),
+        ("method", ctypes.c_int32),
     ]
 
 

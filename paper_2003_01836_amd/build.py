@@ -68,6 +68,8 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         "batch": os.path.join(build_dir, "batch.o"),
         "autotune": os.path.join(build_dir, "autotune.o"),
         "setup": os.path.join(build_dir, "setup_gpu.o"),
+        "cp": os.path.join(build_dir, "cp.o"),
+        "kernels_cp": os.path.join(build_dir, "kernels_cp.o"),
     }
     cmds = [
         ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
@@ -83,6 +85,8 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "autotune.cpp"), "-o", objs["autotune"]],
         # geometric decisions (MAC) follow their formulas operation by operation
         [hipcc] + hip_flags + ["-ffp-contract=off", "-c", os.path.join(CSRC, "setup_gpu.hip"), "-o", objs["setup"]],
+        [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "cp.cpp"), "-o", objs["cp"]],
+        [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_cp.hip"), "-o", objs["kernels_cp"]],
     ]
     if verbose:
         for c in cmds:

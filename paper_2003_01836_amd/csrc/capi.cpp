@@ -40,6 +40,8 @@ int check_params(const bltc_params* p)
         return fail(BLTC_EINVAL, "leaf_size and batch_size must be >= 1");
     if (p->threads_per_target < 0 || p->threads_per_target > 1)
         return fail(BLTC_EUNSUPPORTED, "threads_per_target must be 0 or 1");
+    if (p->method != BLTC_PARTICLE_CLUSTER && p->method != BLTC_CLUSTER_PARTICLE)
+        return fail(BLTC_EINVAL, "method must be BLTC_PARTICLE_CLUSTER or BLTC_CLUSTER_PARTICLE");
     return BLTC_OK;
 }
 
@@ -168,6 +170,8 @@ int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
 {
     if (plan->uploaded)
         return BLTC_OK;
+    if (plan->cp)
+        return bltc_cp::upload(plan, s);
     const bltc::HostPlan& hp = plan->hp;
     bltc::DevicePlan& d = plan->d;
     HIP_TRY(hipGetDevice(&plan->device));
@@ -299,7 +303,8 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
             int64_t phi_ld, hipStream_t s)
 {
     const bltc::HostPlan& hp = plan->hp;
-    const int64_t nt = hp.tgt.n, ns = hp.src.n;
+    const int64_t nt = plan->cp ? plan->cpp.tgt.n : hp.tgt.n;
+    const int64_t ns = plan->cp ? plan->cpp.src.n : hp.src.n;
     if (num_q < 1 || num_q > plan->max_q)
         return fail(BLTC_EINVAL, "num_q must be in 1..max_q (%d)", plan->max_q);
     if (nt == 0)
@@ -322,6 +327,8 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
     if (dev != plan->device)
         return fail(BLTC_EINVAL, "plan was uploaded on device %d, current device is %d",
                     plan->device, dev);
+    if (plan->cp)
+        return bltc_cp::execute(plan, q, num_q, phi, s);
     bltc::KernelParams kp;
     kp.kernel = plan->prm.kernel;
     kp.precision = plan->prm.precision;
@@ -387,6 +394,8 @@ int create_common(bltc_plan** out, const bltc_params* p, int64_t nt, const doubl
         return rc;
     if (max_q < 1)
         return fail(BLTC_EINVAL, "max_q must be >= 1");
+    if (p->method == BLTC_CLUSTER_PARTICLE && max_q != 1)
+        return fail(BLTC_EUNSUPPORTED, "cluster-particle plans take one charge vector (max_q = 1)");
     return BLTC_OK;
 }
 
@@ -405,7 +414,10 @@ int create_from_host(bltc_plan** out, const bltc_params* p, int64_t nt, const do
     plan->prm = *p;
     plan->max_q = max_q;
     try {
-        rc = make_host_plan(plan, p, nt, tx, ty, tz, ns, sx, sy, sz);
+        if (p->method == BLTC_CLUSTER_PARTICLE)
+            rc = bltc_cp::create_host(plan, plan_params(plan, p), nt, tx, ty, tz, ns, sx, sy, sz);
+        else
+            rc = make_host_plan(plan, p, nt, tx, ty, tz, ns, sx, sy, sz);
     } catch (const std::bad_alloc&) {
         rc = fail(BLTC_ENOMEM, "host allocation failed while planning");
     } catch (const std::exception& ex) {
@@ -436,6 +448,7 @@ void bltc_params_default(bltc_params* p)
     p->leaf_size = 2000;
     p->batch_size = 2000;
     p->threads_per_target = 0;
+    p->method = BLTC_PARTICLE_CLUSTER;
 }
 
 int bltc_plan_create_host(bltc_plan** out, const bltc_params* p, int64_t nt, const double* tx,
@@ -462,7 +475,10 @@ int bltc_plan_create(bltc_plan** out, const bltc_params* p, int64_t nt, const do
     plan->prm = *p;
     plan->max_q = max_q;
     try {
-        rc = make_device_plan(plan, p, nt, tx, ty, tz, ns, sx, sy, sz, s);
+        if (p->method == BLTC_CLUSTER_PARTICLE)
+            rc = bltc_cp::create_device(plan, plan_params(plan, p), nt, tx, ty, tz, ns, sx, sy, sz, s);
+        else
+            rc = make_device_plan(plan, p, nt, tx, ty, tz, ns, sx, sy, sz, s);
         if (rc == BLTC_OK)
             rc = bltc_internal_upload_plan(plan, s);
     } catch (const std::bad_alloc&) {
@@ -522,6 +538,11 @@ int bltc_plan_modified_charges(bltc_plan* plan, int64_t cluster, int32_t qi, dou
 {
     if (!plan || !out)
         return fail(BLTC_EINVAL, "NULL argument");
+    if (plan->cp) {
+        if (qi != 0)
+            return fail(BLTC_EINVAL, "cluster-particle plans have one charge vector");
+        return bltc_cp::proxy_potentials(plan, cluster, out, static_cast<hipStream_t>(stream));
+    }
     const bltc::HostPlan& hp = plan->hp;
     if (cluster < 0 || cluster >= hp.src.nodes())
         return fail(BLTC_EINVAL, "cluster index out of range");
@@ -553,6 +574,13 @@ int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out)
         return fail(BLTC_EINVAL, "NULL argument");
     const bltc::HostPlan& hp = plan->hp;
     std::memset(out, 0, sizeof(*out));
+    if (plan->cp) {
+        bltc_cp::stats(plan, out);
+        out->degree = plan->prm.degree;
+        out->leaf_size = plan->prm.leaf_size;
+        out->batch_size = plan->prm.batch_size;
+        return BLTC_OK;
+    }
     out->clusters = hp.src.nodes();
     out->leaves = hp.leaves;
     out->batches = static_cast<int64_t>(hp.batch_begin.size());
@@ -576,6 +604,8 @@ int bltc_plan_view_get(const bltc_plan* plan, bltc_plan_view* out)
         return fail(BLTC_EINVAL, "NULL argument");
     const bltc::HostPlan& hp = plan->hp;
     std::memset(out, 0, sizeof(*out));
+    if (plan->cp)
+        return bltc_cp::view(plan, out);
     out->nt = hp.tgt.n;
     out->ns = hp.src.n;
     out->n_clusters = hp.src.nodes();

@@ -74,6 +74,16 @@ struct bltc_plan {
     // host copies for bltc_plan_view_get (device-built plans)
     mutable std::vector<int64_t> view_src_order, view_tgt_order;
     mutable std::vector<int32_t> view_item_batch, view_item_cluster, view_item_kind;
+    mutable std::vector<double> view_batch_lo, view_batch_hi;
+    // cluster-particle plans (method BLTC_CLUSTER_PARTICLE): host plan, the
+    // proxy-potential and direct launches, interpolation lists, proxy potentials
+    bool cp = false;
+    bltc::CpPlan cpp;
+    bltc::DevicePlan dprox, ddir;
+    int32_t* cp_path_off = nullptr;
+    int32_t* cp_path_slot = nullptr;
+    double* cp_slot_nodes = nullptr;
+    double* cp_phat = nullptr;
     bool uploaded = false;
     int device = -1;
     bltc::DevicePlan d;
@@ -113,3 +123,18 @@ struct bltc_plan {
 
 // device side of a plan (uploads on first use); synchronises the stream
 int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s);
+
+// cluster-particle plans (cp.cpp)
+namespace bltc_cp {
+int create_host(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const double* tx,
+                const double* ty, const double* tz, int64_t ns, const double* sx, const double* sy,
+                const double* sz);
+int create_device(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const double* tx,
+                  const double* ty, const double* tz, int64_t ns, const double* sx,
+                  const double* sy, const double* sz, hipStream_t s);
+int upload(bltc_plan* plan, hipStream_t s);
+int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStream_t s);
+int proxy_potentials(bltc_plan* plan, int64_t cluster, double* out, hipStream_t s);
+void stats(const bltc_plan* plan, bltc_stats* out);
+int view(const bltc_plan* plan, bltc_plan_view* out);
+}  // namespace bltc_cp

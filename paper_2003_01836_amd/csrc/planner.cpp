@@ -417,11 +417,55 @@ void plan_from_trees(HostPlan& hp)
     plan_schedule(hp);
 }
 
+// Workgroups are dispatched round-robin over the dies (workgroup k on die
+// k % X), and each die has its own L2.  Batches in tree order are split into
+// X contiguous segments of equal work (neighbouring batches share most of
+// their near-field sources), each segment is ordered heaviest batch first,
+// and the segments are interleaved so that segment x lands on die x.
+void group_schedule(const std::vector<int64_t>& begin, const std::vector<int64_t>& count,
+                    const std::vector<int64_t>& cost, int32_t group_size, int32_t xcds,
+                    std::vector<int32_t>& group_batch, std::vector<int64_t>& group_first)
+{
+    const int64_t nb = static_cast<int64_t>(begin.size());
+    const int32_t X = std::max(1, xcds);
+    std::vector<double> work(nb);
+    double total = 0.0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t ng = (count[b] + group_size - 1) / group_size;
+        work[b] = static_cast<double>(cost[b] + 1) * static_cast<double>(ng);
+        total += work[b];
+    }
+    std::vector<std::vector<int32_t>> seg(X);
+    double run_w = 0.0;
+    for (int64_t b = 0; b < nb; ++b) {
+        int32_t x = static_cast<int32_t>(run_w * X / (total > 0.0 ? total : 1.0));
+        x = std::min(x, X - 1);
+        seg[x].push_back(static_cast<int32_t>(b));
+        run_w += work[b];
+    }
+    std::vector<std::vector<std::pair<int32_t, int64_t>>> queue(X);
+    size_t longest = 0;
+    for (int32_t x = 0; x < X; ++x) {
+        std::stable_sort(seg[x].begin(), seg[x].end(),
+                         [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+        for (int32_t b : seg[x])
+            for (int64_t f = 0; f < count[b]; f += group_size)
+                queue[x].emplace_back(b, begin[b] + f);
+        longest = std::max(longest, queue[x].size());
+    }
+    group_batch.assign(longest * X, -1);
+    group_first.assign(longest * X, 0);
+    for (int32_t x = 0; x < X; ++x)
+        for (size_t i = 0; i < queue[x].size(); ++i) {
+            group_batch[i * X + x] = queue[x][i].first;
+            group_first[i * X + x] = queue[x][i].second;
+        }
+}
+
 void plan_schedule(HostPlan& hp)
 {
     const PlanParams& prm = hp.prm;
     const Tree& S = hp.src;
-    const int64_t nb = static_cast<int64_t>(hp.batch_node.size());
     const int64_t nslots = static_cast<int64_t>(hp.slot_cluster.size());
     // ---- upward-pass chunks ----------------------------------------------------
     hp.slot_chunk_off.assign(nslots + 1, 0);
@@ -439,49 +483,215 @@ void plan_schedule(HostPlan& hp)
             hp.chunk_dst.push_back(c1 - c0 == 1 ? s : nslots + hp.npartial++);
     }
 
-    // ---- interaction workgroups ------------------------------------------------
-    // Workgroups are dispatched round-robin over the dies (workgroup k on die
-    // k % X), and each die has its own L2.  Batches in tree order are split into
-    // X contiguous segments of equal work (neighbouring batches share most of
-    // their near-field sources), each segment is ordered heaviest batch first,
-    // and the segments are interleaved so that segment x lands on die x.
+    group_schedule(hp.batch_begin, hp.batch_count, hp.batch_cost, prm.group_size, prm.xcds,
+                   hp.group_batch, hp.group_first);
+}
+
+// ---------------------------------------------------------------------------
+// Cluster-particle treecode (interpolation on the target side)
+// ---------------------------------------------------------------------------
+namespace {
+
+// leaves of a tree ordered by first position
+void leaves_by_begin(const Tree& t, std::vector<int32_t>& node, std::vector<int64_t>& begin,
+                     std::vector<int64_t>& count)
+{
+    node.clear();
+    for (int64_t id = 0; id < t.nodes(); ++id)
+        if (t.nchild[id] == 0)
+            node.push_back(static_cast<int32_t>(id));
+    std::sort(node.begin(), node.end(), [&](int32_t a, int32_t b) { return t.begin[a] < t.begin[b]; });
+    begin.resize(node.size());
+    count.resize(node.size());
+    for (size_t i = 0; i < node.size(); ++i) {
+        begin[i] = t.begin[node[i]];
+        count[i] = t.count[node[i]];
+    }
+}
+
+}  // namespace
+
+void cp_plan_from_trees(CpPlan& cp)
+{
+    const PlanParams& prm = cp.prm;
+    cp.np = prm.degree + 1;
+    cp.P = static_cast<int64_t>(cp.np) * cp.np * cp.np;
+    const Tree& T = cp.tgt;
+    const Tree& S = cp.src;
+    leaves_by_begin(S, cp.sb_node, cp.sb_begin, cp.sb_count);
+    leaves_by_begin(T, cp.tl_node, cp.tl_begin, cp.tl_count);
+    const int64_t nsb = static_cast<int64_t>(cp.sb_node.size());
+    const int64_t ntl = static_cast<int64_t>(cp.tl_node.size());
+    const int64_t nn = T.nodes();
+    cp.leaves = ntl;
+
+    // ---- walks: every source batch over the target tree (Alg. 1, roles exchanged)
+    std::vector<std::vector<int32_t>> approx(nsb), direct(nsb);
+    if (nn > 0) {
+        parallel_for(nsb, [&](int64_t b) {
+            const int32_t sn = cp.sb_node[b];
+            const double cs[3] = {S.center[3 * sn], S.center[3 * sn + 1], S.center[3 * sn + 2]};
+            const double rs = S.radius[sn];
+            std::vector<int32_t> stack{0};
+            while (!stack.empty()) {
+                const int32_t c = stack.back();
+                stack.pop_back();
+                const double dx = cs[0] - T.center[3 * c];
+                const double dy = cs[1] - T.center[3 * c + 1];
+                const double dz = cs[2] - T.center[3 * c + 2];
+                const double R = std::sqrt(dx * dx + dy * dy + dz * dz);
+                const bool geometric = rs + T.radius[c] < prm.theta * R;
+                const bool size = cp.P < T.count[c];
+                if (geometric && size) {
+                    approx[b].push_back(c);
+                } else if (!geometric && T.nchild[c] > 0) {
+                    for (int32_t k = T.nchild[c] - 1; k >= 0; --k)
+                        stack.push_back(T.first_child[c] + k);
+                } else {
+                    direct[b].push_back(c);
+                }
+            }
+        });
+    }
+    for (int64_t b = 0; b < nsb; ++b) {
+        for (int32_t c : approx[b]) {
+            cp.item_batch.push_back(static_cast<int32_t>(b));
+            cp.item_cluster.push_back(c);
+            cp.item_kind.push_back(0);
+        }
+        for (int32_t c : direct[b]) {
+            cp.item_batch.push_back(static_cast<int32_t>(b));
+            cp.item_cluster.push_back(c);
+            cp.item_kind.push_back(1);
+        }
+        cp.approx_pairs += static_cast<int64_t>(approx[b].size());
+        cp.direct_pairs += static_cast<int64_t>(direct[b].size());
+    }
+
+    // ---- slots and their Chebyshev grids
+    cp.cluster_slot.assign(nn, -1);
+    std::vector<int64_t> nfar(nn, 0);
+    for (int64_t b = 0; b < nsb; ++b)
+        for (int32_t c : approx[b])
+            ++nfar[c];
+    for (int64_t c = 0; c < nn; ++c)
+        if (nfar[c] > 0) {
+            cp.cluster_slot[c] = static_cast<int32_t>(cp.slot_cluster.size());
+            cp.slot_cluster.push_back(static_cast<int32_t>(c));
+        }
+    const int64_t nslots = static_cast<int64_t>(cp.slot_cluster.size());
+    const int32_t np = cp.np;
+    cp.slot_nodes.resize(nslots * 3 * np);
+    for (int64_t sl = 0; sl < nslots; ++sl) {
+        const int32_t c = cp.slot_cluster[sl];
+        for (int l = 0; l < 3; ++l) {
+            const double a = T.lo[3 * c + l], bb = T.hi[3 * c + l];
+            const double mid = (a + bb) / 2.0;
+            const double h = (bb - a) / 2.0;
+            for (int32_t k = 0; k < np; ++k)
+                cp.slot_nodes[(sl * 3 + l) * np + k] =
+                    mid + h * std::cos(M_PI * static_cast<double>(k) / static_cast<double>(prm.degree));
+        }
+        cp.interp_terms += T.count[c] * cp.P;
+    }
+
+    // ---- proxy lists: per slot, its source batches in batch order
+    cp.pf_off.assign(nslots + 1, 0);
+    for (int64_t sl = 0; sl < nslots; ++sl)
+        cp.pf_off[sl + 1] = cp.pf_off[sl] + static_cast<int32_t>(nfar[cp.slot_cluster[sl]]);
+    const int64_t npf = cp.pf_off[nslots];
+    cp.pf_leaf.resize(npf);
+    cp.pf_begin.resize(npf);
+    cp.pf_count.resize(npf);
+    cp.pf_cost.assign(nslots, 0);
     {
-        const int32_t X = std::max(1, prm.xcds);
-        std::vector<double> work(nb);
-        double total = 0.0;
-        for (int64_t b = 0; b < nb; ++b) {
-            const int64_t ng = (hp.batch_count[b] + prm.group_size - 1) / prm.group_size;
-            work[b] = static_cast<double>(hp.batch_cost[b] + 1) * static_cast<double>(ng);
-            total += work[b];
-        }
-        std::vector<std::vector<int32_t>> seg(X);
-        double run_w = 0.0;
-        for (int64_t b = 0; b < nb; ++b) {
-            int32_t x = static_cast<int32_t>(run_w * X / (total > 0.0 ? total : 1.0));
-            x = std::min(x, X - 1);
-            seg[x].push_back(static_cast<int32_t>(b));
-            run_w += work[b];
-        }
-        std::vector<std::vector<std::pair<int32_t, int64_t>>> queue(X);
-        size_t longest = 0;
-        for (int32_t x = 0; x < X; ++x) {
-            std::stable_sort(seg[x].begin(), seg[x].end(), [&](int32_t a, int32_t b) {
-                return hp.batch_cost[a] > hp.batch_cost[b];
-            });
-            for (int32_t b : seg[x])
-                for (int64_t f = 0; f < hp.batch_count[b]; f += prm.group_size)
-                    queue[x].emplace_back(b, hp.batch_begin[b] + f);
-            longest = std::max(longest, queue[x].size());
-        }
-        hp.group_batch.assign(longest * X, -1);
-        hp.group_first.assign(longest * X, 0);
-        for (int32_t x = 0; x < X; ++x)
-            for (size_t i = 0; i < queue[x].size(); ++i) {
-                hp.group_batch[i * X + x] = queue[x][i].first;
-                hp.group_first[i * X + x] = queue[x][i].second;
+        std::vector<int32_t> fill(cp.pf_off.begin(), cp.pf_off.end() - 1);
+        for (int64_t b = 0; b < nsb; ++b)
+            for (int32_t c : approx[b]) {
+                const int32_t sl = cp.cluster_slot[c];
+                const int32_t e = fill[sl]++;
+                cp.pf_leaf[e] = cp.sb_node[b];
+                cp.pf_begin[e] = cp.sb_begin[b];
+                cp.pf_count[e] = cp.sb_count[b];
+                cp.pf_cost[sl] += cp.sb_count[b];
+                cp.proxy_evals += cp.P * cp.sb_count[b];
             }
     }
 
+    // ---- direct lists: per target leaf, the source batches of the direct
+    // pairs of every cluster containing it, in batch order
+    std::vector<int32_t> leaf_list;
+    std::vector<int64_t> run_lo, run_hi;
+    leaf_runs(T, leaf_list, run_lo, run_hi);     // leaf_list equals tl_node
+    std::vector<int64_t> ndir(ntl, 0);
+    for (int64_t b = 0; b < nsb; ++b)
+        for (int32_t c : direct[b]) {
+            for (int64_t r = run_lo[c]; r < run_hi[c]; ++r)
+                ++ndir[r];
+            cp.near_evals += T.count[c] * cp.sb_count[b];
+        }
+    cp.dn_off.assign(ntl + 1, 0);
+    for (int64_t t = 0; t < ntl; ++t) {
+        const int64_t v = cp.dn_off[t] + ndir[t];
+        if (v > INT32_MAX)
+            throw std::length_error("direct lists exceed 2^31 entries");
+        cp.dn_off[t + 1] = static_cast<int32_t>(v);
+    }
+    const int64_t ndn = cp.dn_off[ntl];
+    cp.dn_leaf.resize(ndn);
+    cp.dn_begin.resize(ndn);
+    cp.dn_count.resize(ndn);
+    cp.dn_cost.assign(ntl, 0);
+    {
+        std::vector<int64_t> fill(cp.dn_off.begin(), cp.dn_off.end() - 1);
+        for (int64_t b = 0; b < nsb; ++b)
+            for (int32_t c : direct[b])
+                for (int64_t r = run_lo[c]; r < run_hi[c]; ++r) {
+                    const int64_t e = fill[r]++;
+                    cp.dn_leaf[e] = cp.sb_node[b];
+                    cp.dn_begin[e] = cp.sb_begin[b];
+                    cp.dn_count[e] = cp.sb_count[b];
+                    cp.dn_cost[r] += cp.sb_count[b];
+                }
+    }
+
+    // ---- interpolation lists: slots on each target leaf's root-to-leaf path
+    cp.dw_off.assign(ntl + 1, 0);
+    for (int64_t t = 0; t < ntl; ++t) {
+        std::vector<int32_t> path;
+        for (int32_t u = cp.tl_node[t]; u >= 0; u = T.parent[u])
+            if (cp.cluster_slot[u] >= 0)
+                path.push_back(cp.cluster_slot[u]);
+        std::reverse(path.begin(), path.end());
+        cp.dw_slot.insert(cp.dw_slot.end(), path.begin(), path.end());
+        cp.dw_off[t + 1] = static_cast<int32_t>(cp.dw_slot.size());
+        cp.dn_cost[t] += static_cast<int64_t>(path.size()) * cp.P;
+    }
+
+    // ---- workgroups
+    std::vector<int64_t> pbegin(nslots), pcount(nslots, cp.P);
+    for (int64_t sl = 0; sl < nslots; ++sl)
+        pbegin[sl] = sl * cp.P;
+    group_schedule(pbegin, pcount, cp.pf_cost, prm.group_size, prm.xcds, cp.pg_batch, cp.pg_first);
+    group_schedule(cp.tl_begin, cp.tl_count, cp.dn_cost, prm.group_size, prm.xcds, cp.dg_batch,
+                   cp.dg_first);
+}
+
+void make_cp_plan(CpPlan& cp, const PlanParams& prm,
+                  int64_t nt, const double* tx, const double* ty, const double* tz,
+                  int64_t ns, const double* sx, const double* sy, const double* sz)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    cp = CpPlan();
+    cp.prm = prm;
+    build_tree(cp.tgt, nt, tx, ty, tz, prm.leaf_size);
+    if (nt == ns && tx == sx && ty == sy && tz == sz && prm.batch_size == prm.leaf_size)
+        cp.src = cp.tgt;
+    else
+        build_tree(cp.src, ns, sx, sy, sz, prm.batch_size);
+    cp_plan_from_trees(cp);
+    cp.setup_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 }  // namespace bltc

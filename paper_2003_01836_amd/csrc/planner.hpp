@@ -124,4 +124,65 @@ void plan_slots(HostPlan& hp, const std::vector<uint8_t>& used);
 // batch counts and batch_cost).
 void plan_schedule(HostPlan& hp);
 
+// Workgroups of group_size consecutive positions over batches [begin, begin +
+// count), cost-ordered per die (see planner.cpp); batch -1 marks padding.
+void group_schedule(const std::vector<int64_t>& begin, const std::vector<int64_t>& count,
+                    const std::vector<int64_t>& cost, int32_t group_size, int32_t xcds,
+                    std::vector<int32_t>& group_batch, std::vector<int64_t>& group_first);
+
+// ---------------------------------------------------------------------------
+// Cluster-particle treecode: the interpolation moves to the target side.
+// Targets form the cluster tree (capacity leaf_size); the leaves of the source
+// tree (capacity batch_size) are the source batches, and every source batch
+// walks the target tree with the MAC of eq. 13 (roles exchanged).  An
+// approximated pair (S, T) adds the potential of S's sources at T's
+// Chebyshev points (the proxy potentials of T); a direct pair adds S's direct
+// sum to every target of T; every target finally receives the interpolant of
+// the proxy potentials of each cluster on its root-to-leaf path.
+// ---------------------------------------------------------------------------
+struct CpPlan {
+    PlanParams prm;
+    int32_t np = 0;
+    int64_t P = 0;
+    Tree tgt, src;
+
+    // source batches (leaves of the source tree) and target leaves, each
+    // ordered by first position
+    std::vector<int32_t> sb_node, tl_node;
+    std::vector<int64_t> sb_begin, sb_count, tl_begin, tl_count;
+
+    // items as found by the walks: source batch, target cluster, kind
+    std::vector<int32_t> item_batch, item_cluster, item_kind;
+
+    // slots: target clusters with proxy potentials (ascending id)
+    std::vector<int32_t> slot_cluster, cluster_slot;
+    std::vector<double> slot_nodes;      // [slot][3][np]
+
+    // proxy potentials: per slot, the source ranges (source batches)
+    std::vector<int32_t> pf_off, pf_leaf;
+    std::vector<int64_t> pf_begin, pf_count, pf_cost;
+    // direct sums: per target leaf, the source ranges
+    std::vector<int32_t> dn_off, dn_leaf;
+    std::vector<int64_t> dn_begin, dn_count, dn_cost;
+    // interpolation: per target leaf, the slots on its root-to-leaf path (root first)
+    std::vector<int32_t> dw_off, dw_slot;
+
+    // workgroups: over proxy points (batch = slot) and over target leaves
+    std::vector<int32_t> pg_batch, dg_batch;
+    std::vector<int64_t> pg_first, dg_first;
+
+    int64_t approx_pairs = 0, direct_pairs = 0;
+    int64_t proxy_evals = 0, near_evals = 0, interp_terms = 0;
+    int64_t leaves = 0;
+    double setup_seconds = 0.0;
+};
+
+// Everything after the two trees (cp.prm, cp.tgt, cp.src set).
+void cp_plan_from_trees(CpPlan& cp);
+
+// Host planning of the cluster-particle treecode from host coordinates.
+void make_cp_plan(CpPlan& cp, const PlanParams& prm,
+                  int64_t nt, const double* tx, const double* ty, const double* tz,
+                  int64_t ns, const double* sx, const double* sy, const double* sz);
+
 }  // namespace bltc

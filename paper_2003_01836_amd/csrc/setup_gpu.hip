@@ -605,6 +605,9 @@ std::string build_tree_device(Tree& t, int64_t n, const double* x, const double*
 // ---------------------------------------------------------------------------
 namespace {
 
+// one batch per lane; small workgroups spread the few waves over many CUs
+constexpr int kListThreads = 64;
+
 struct TravNode {
     double cx, cy, cz, r;   // box center and radius
     int64_t count;          // particles
@@ -632,12 +635,12 @@ __device__ __forceinline__ bool mac_geometric(const TravBatch& b, const TravNode
     return b.r + c.r < theta * R;
 }
 
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kListThreads)
 count_lists(int64_t nb, const TravBatch* __restrict__ batches, const TravNode* __restrict__ nodes,
             double theta, int64_t P, const int64_t* __restrict__ run_len,
             ListCounts* __restrict__ counts, uint8_t* __restrict__ used)
 {
-    const int64_t b = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * kListThreads + threadIdx.x;
     if (b >= nb)
         return;
     const TravBatch tb = batches[b];
@@ -682,11 +685,11 @@ struct ListOut {
     int32_t* item_kind;
 };
 
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kListThreads)
 fill_lists(int64_t nb, const TravBatch* __restrict__ batches, const TravNode* __restrict__ nodes,
            double theta, int64_t P, ListOut o)
 {
-    const int64_t b = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * kListThreads + threadIdx.x;
     if (b >= nb)
         return;
     const TravBatch tb = batches[b];
@@ -778,8 +781,8 @@ std::string build_lists_device(HostPlan& hp, DeviceLists& out, const DeviceAlloc
     TB_TRY(counts_d.reserve(nb));
     std::vector<uint8_t> zeros(nn, 0);
     TB_TRY(used_d.put(zeros, s));
-    const uint32_t grid = static_cast<uint32_t>((nb + kThreads - 1) / kThreads);
-    count_lists<<<grid, kThreads, 0, s>>>(nb, batches_d.p, nodes_d.p, hp.prm.theta, hp.P,
+    const uint32_t grid = static_cast<uint32_t>((nb + kListThreads - 1) / kListThreads);
+    count_lists<<<grid, kListThreads, 0, s>>>(nb, batches_d.p, nodes_d.p, hp.prm.theta, hp.P,
                                           run_len_d.p, counts_d.p, used_d.p);
     TB_TRY(hipGetLastError());
     std::vector<ListCounts> counts(nb);
@@ -846,7 +849,7 @@ std::string build_lists_device(HostPlan& hp, DeviceLists& out, const DeviceAlloc
     o.item_batch = out.item_batch;
     o.item_cluster = out.item_cluster;
     o.item_kind = out.item_kind;
-    fill_lists<<<grid, kThreads, 0, s>>>(nb, batches_d.p, nodes_d.p, hp.prm.theta, hp.P, o);
+    fill_lists<<<grid, kListThreads, 0, s>>>(nb, batches_d.p, nodes_d.p, hp.prm.theta, hp.P, o);
     TB_TRY(hipGetLastError());
     // the tables are freed on return: finish first
     TB_TRY(hipStreamSynchronize(s));

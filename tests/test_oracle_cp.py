@@ -104,3 +104,20 @@ def test_sampled_mode_matches_full_mode():
     full = cp.potential(q)
     smp = inputs.sample_indices(7000, 300, 15)
     assert np.array_equal(cp.potential(q, sample=smp), full[smp])
+
+
+def test_mac_is_strict_at_equality():
+    # target cluster: 9 points on [0, 2] x {0} x {0} (center 1, radius 1); source
+    # batch: (4,0,0), (6,0,0) (center 5, radius 1); R = 4, theta = 0.5: r_S + r_T
+    # equals theta R exactly, so the strict MAC rejects the pair (reading 17) and
+    # the result is the direct sum, although (n+1)^3 = 8 < 9 allows approximation
+    X = np.c_[np.linspace(0.0, 2.0, 9), np.zeros(9), np.zeros(9)]
+    Y = np.array([[4.0, 0.0, 0.0], [6.0, 0.0, 0.0]])
+    q = np.array([0.7, -0.3])
+    cp = oracle.ClusterParticle(X, Y, 0.5, 1, 9, 2)
+    b, c, k = cp.items()
+    assert list(k) == [1]
+    assert oracle.rel_l2(oracle.direct(X, Y, q), cp.potential(q)) <= 1e-15
+    # slightly larger theta: approximated
+    cp2 = oracle.ClusterParticle(X, Y, 0.5000001, 1, 9, 2)
+    assert list(cp2.items()[2]) == [0]
