@@ -17,19 +17,12 @@
 #include <numeric>
 
 #include "internal.hpp"
+#include "kernels_cp.hpp"
 #include "setup_gpu.hpp"
 
 using bltc_detail::fail;
 
 namespace bltc_cp {
-namespace {
-
-void zero_device_plan_counts(bltc::DevicePlan& d)
-{
-    d.nt = d.ns = d.nslots = d.nchunks = d.ngroups = d.nbatches = 0;
-}
-
-}  // namespace
 
 int create_host(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const double* tx,
                 const double* ty, const double* tz, int64_t ns, const double* sx, const double* sy,

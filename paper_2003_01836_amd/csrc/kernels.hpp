@@ -138,12 +138,6 @@ hipError_t launch_interact_queue(const MrhsDesc* descs, const int2* units, int32
                                  int32_t* counter, const KernelParams& kp, int32_t workgroups,
                                  hipStream_t s);
 const void* interact_queue_symbol(const KernelParams& kp);
-// cluster-particle treecode (kernels_cp.hip): phi[tgt_orig[i]] += the interpolant of
-// the proxy potentials phat[slot][P] of every slot listed for the target's leaf
-// (path_off/path_slot per batch of d), grids slot_nodes[slot][3][n+1]
-hipError_t launch_interpolate_targets(const DevicePlan& d, const int32_t* path_off,
-                                      const int32_t* path_slot, const double* slot_nodes,
-                                      const double* phat, double* phi, hipStream_t s);
 // GPU direct sum (eq. 1) of all targets against packed sources
 hipError_t launch_pack_sources(int64_t ns, const double* x, const double* y, const double* z,
                                const double* q, double4* out, hipStream_t s);

@@ -15,7 +15,7 @@
 // cluster grids and proxy potentials are wave-uniform (scalar loads).
 #include <cfloat>
 
-#include "kernels.hpp"
+#include "kernels_cp.hpp"
 
 namespace bltc {
 namespace {

@@ -78,7 +78,7 @@ def test_cp_proxy_potentials_match_oracle(dev):
     for c in np.unique(v["item_cluster"][v["item_kind"] == 0]):
         key = tuple(np.sort(tord[v["cluster_begin"][c]:v["cluster_begin"][c] + v["cluster_count"][c]]))
         ref = oc.proxy_potentials(okey[key], q[0]).reshape(-1)
-        got = plan.modified_charges(c)
+        got = np.asarray(plan.modified_charges(c)).reshape(-1)
         assert np.max(np.abs(ref - got)) <= 1e-12 * np.max(np.abs(ref)), c
         checked += 1
     assert checked > 10
