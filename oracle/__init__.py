@@ -5,7 +5,8 @@ direct sum of eq. (1) and the treecode of Alg. 1 (tree of source clusters,
 target batches, two-part MAC of eq. (13), modified charges of eq. (12) with the
 removable-singularity rule of eq. (5), approximation eq. (11) and direct sum
 eq. (9)) of Vaughn, Wilson and Krasny (2020), and the cluster-particle variant
-(the same interpolation in the target variable) that the paper's outlook names.
+(the same interpolation in the target variable) and the cluster-cluster
+variant (both sides interpolated) that the paper's outlook names.
 
 Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
 may import this package.  It shares no code with the GPU library and never
@@ -78,6 +79,16 @@ def _load():
     lib.oracle_cp_proxy_potentials.argtypes = [vp, i32, vp, i32, d, vp]
     lib.oracle_cp_potential.argtypes = [vp, vp, i32, d, i64, vp, vp, vp]
     lib.oracle_cp_potential.restype = ctypes.c_int
+    lib.oracle_cc_create.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, d, i32, i64, i64]
+    lib.oracle_cc_create.restype = vp
+    lib.oracle_cc_destroy.argtypes = [vp]
+    lib.oracle_cc_sizes.argtypes = [vp, vp]
+    lib.oracle_cc_orders.argtypes = [vp, vp, vp]
+    lib.oracle_cc_node.argtypes = [vp, i32, i64, vp, vp, vp]
+    lib.oracle_cc_pairs.argtypes = [vp, vp, vp, vp]
+    lib.oracle_cc_proxy_potentials.argtypes = [vp, i32, vp, i32, d, vp]
+    lib.oracle_cc_potential.argtypes = [vp, vp, i32, d, i64, vp, vp, vp]
+    lib.oracle_cc_potential.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -352,6 +363,96 @@ class ClusterParticle:
         phi = np.zeros(n_eval)
         times = np.zeros(2)
         rc = _load().oracle_cp_potential(self._h, _ptr(q), int(kernel), float(kappa), n_eval, sp,
+                                         _ptr(phi), _ptr(times))
+        if rc != 0:
+            raise ValueError("sample index out of range")
+        if return_times:
+            return phi, {"proxy": float(times[0]), "eval": float(times[1])}
+        return phi
+
+
+class ClusterCluster:
+    """Oracle barycentric cluster-cluster treecode: source tree (capacity
+    leaf_size) with modified charges, target tree (capacity batch_size) with
+    proxy potentials, a dual walk from the roots choosing per accepted pair
+    cluster-cluster, particle-cluster, cluster-particle or direct by the
+    (n+1)^3 size test on each side.  Single charge vector."""
+
+    KINDS = ("cc", "pc", "cp", "direct")
+
+    def __init__(self, targets, sources, theta, degree, leaf_size, batch_size):
+        lib = _load()
+        self._t = _f64(targets)
+        self._s = _f64(sources)
+        self._tc_cols = [np.ascontiguousarray(self._t[:, c]) for c in range(3)]
+        self._sc_cols = [np.ascontiguousarray(self._s[:, c]) for c in range(3)]
+        self.nt = self._t.shape[0]
+        self.ns = self._s.shape[0]
+        self.degree = int(degree)
+        if not (1 <= self.degree <= 60):
+            raise ValueError("degree out of range")
+        tx, ty, tz = self._tc_cols
+        sx, sy, sz = self._sc_cols
+        self._h = lib.oracle_cc_create(self.nt, _ptr(tx), _ptr(ty), _ptr(tz),
+                                       self.ns, _ptr(sx), _ptr(sy), _ptr(sz),
+                                       float(theta), self.degree, int(leaf_size), int(batch_size))
+        if not self._h:
+            raise RuntimeError("oracle treecode creation failed")
+        sizes = np.zeros(3, dtype=np.int64)
+        lib.oracle_cc_sizes(self._h, _ptr(sizes))
+        self.n_target_nodes, self.n_source_nodes, self.n_pairs = (int(v) for v in sizes)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _load().oracle_cc_destroy(h)
+            self._h = None
+
+    def orders(self):
+        """(target order, source order): original index at each tree position."""
+        t = np.zeros(self.nt, dtype=np.int64)
+        s = np.zeros(self.ns, dtype=np.int64)
+        _load().oracle_cc_orders(self._h, _ptr(t), _ptr(s))
+        return t, s
+
+    def node(self, side, i):
+        """Node i of the target (side 0) or source (side 1) tree."""
+        lo = np.zeros(3)
+        hi = np.zeros(3)
+        bc = np.zeros(2, dtype=np.int64)
+        _load().oracle_cc_node(self._h, int(side), int(i), _ptr(lo), _ptr(hi), _ptr(bc))
+        return {"lo": lo, "hi": hi, "begin": int(bc[0]), "count": int(bc[1])}
+
+    def pairs(self):
+        """(target node, source node, kind) in walk order; kind 0 cc, 1 pc, 2 cp, 3 direct."""
+        t = np.zeros(self.n_pairs, dtype=np.int32)
+        s = np.zeros(self.n_pairs, dtype=np.int32)
+        k = np.zeros(self.n_pairs, dtype=np.int32)
+        _load().oracle_cc_pairs(self._h, _ptr(t), _ptr(s), _ptr(k))
+        return t, s, k
+
+    def proxy_potentials(self, c, charges, kernel=COULOMB, kappa=0.0):
+        q = _f64(charges)
+        if q.ndim != 1 or q.shape[0] != self.ns:
+            raise ValueError("charges must have one value per source")
+        np1 = self.degree + 1
+        out = np.zeros(np1 ** 3)
+        _load().oracle_cc_proxy_potentials(self._h, int(c), _ptr(q), int(kernel), float(kappa),
+                                           _ptr(out))
+        return out.reshape(np1, np1, np1)
+
+    def potential(self, charges, kernel=COULOMB, kappa=0.0, sample=None, return_times=False):
+        q = _f64(charges)
+        if q.ndim != 1 or q.shape[0] != self.ns:
+            raise ValueError("charges must have one value per source")
+        if sample is None:
+            n_eval, sp = self.nt, None
+        else:
+            smp = np.ascontiguousarray(sample, dtype=np.int64)
+            n_eval, sp = smp.shape[0], _ptr(smp)
+        phi = np.zeros(n_eval)
+        times = np.zeros(2)
+        rc = _load().oracle_cc_potential(self._h, _ptr(q), int(kernel), float(kappa), n_eval, sp,
                                          _ptr(phi), _ptr(times))
         if rc != 0:
             raise ValueError("sample index out of range")

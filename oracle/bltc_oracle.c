@@ -1027,3 +1027,376 @@ int oracle_cp_potential(const ocp *cp, const double *q, int32_t kernel, double k
     free(n_dir);
     return 0;
 }
+
+/* ========================================================================= */
+/* Barycentric cluster-cluster treecode (CC), named with the CP variant in    */
+/* the paper's outlook (Sec. V).  Both sides are interpolated.                */
+/* Readings (listed with the others in the design notes):                     */
+/*   R20 sources form a tree of capacity leaf (N_L), targets a tree of         */
+/*       capacity batch (N_B); both follow R2 and R5-R8;                       */
+/*   R21 a dual walk starts at the pair of roots.  For a pair (T, S) with     */
+/*       r_T + r_S < theta R (R3) the interaction is approximated on every    */
+/*       side larger than (n+1)^3: CC when P < N_T and P < N_S (proxy         */
+/*       potentials of T from the modified charges of S), PC when only        */
+/*       P < N_S (targets of T from S's modified charges, eq. 11), CP when    */
+/*       only P < N_T (proxy potentials of T from S's particles), a direct    */
+/*       sum when neither;                                                    */
+/*   R22 otherwise two leaves interact directly; else a leaf is never split,  */
+/*       of two non-leaves the one with the larger radius is split, and equal */
+/*       radii split both (child pairs in target-major order);                */
+/*   R23 every target receives its direct and PC terms from all clusters on   */
+/*       its root-to-leaf path and the interpolant (R18) of the proxy         */
+/*       potentials of each of them.                                          */
+/* Exchanging targets and sources (and N_L with N_B) mirrors every decision,  */
+/* so for a symmetric kernel the matrix is the transpose of the exchanged     */
+/* problem's.                                                                 */
+/* ========================================================================= */
+typedef struct {
+    int32_t t, s;     /* target node, source node */
+    int32_t kind;     /* 0 CC, 1 PC, 2 CP, 3 direct */
+} opair;
+
+typedef struct {
+    int64_t nt, ns;
+    const double *tx, *ty, *tz, *sx, *sy, *sz;
+    double theta;
+    int32_t n;
+    int64_t leaf, batch;
+    otree tgt, src;
+    opair *pairs;
+    int64_t n_pairs, cap_pairs;
+    double t_setup;
+} occ;
+
+static void cc_push(occ *cc, int32_t t, int32_t s, int32_t kind)
+{
+    if (cc->n_pairs == cc->cap_pairs) {
+        cc->cap_pairs = cc->cap_pairs ? 2 * cc->cap_pairs : 64;
+        cc->pairs = (opair *)realloc(cc->pairs, (size_t)cc->cap_pairs * sizeof(opair));
+    }
+    cc->pairs[cc->n_pairs].t = t;
+    cc->pairs[cc->n_pairs].s = s;
+    cc->pairs[cc->n_pairs].kind = kind;
+    cc->n_pairs++;
+}
+
+/* the dual walk (R21, R22) */
+static void cc_walk(occ *cc, int32_t t, int32_t s)
+{
+    const onode *T = &cc->tgt.nodes[t];
+    const onode *S = &cc->src.nodes[s];
+    double dx = T->center[0] - S->center[0];
+    double dy = T->center[1] - S->center[1];
+    double dz = T->center[2] - S->center[2];
+    double R = sqrt(dx * dx + dy * dy + dz * dz);
+    int64_t P = (int64_t)(cc->n + 1) * (cc->n + 1) * (cc->n + 1);
+    if (T->radius + S->radius < cc->theta * R) {
+        int big_t = P < T->count, big_s = P < S->count;
+        cc_push(cc, t, s, big_t && big_s ? 0 : (big_s ? 1 : (big_t ? 2 : 3)));
+        return;
+    }
+    int leaf_t = T->nchild == 0, leaf_s = S->nchild == 0;
+    if (leaf_t && leaf_s) {
+        cc_push(cc, t, s, 3);
+        return;
+    }
+    int split_t, split_s;
+    if (leaf_s) {
+        split_t = 1; split_s = 0;
+    } else if (leaf_t) {
+        split_t = 0; split_s = 1;
+    } else if (T->radius > S->radius) {
+        split_t = 1; split_s = 0;
+    } else if (S->radius > T->radius) {
+        split_t = 0; split_s = 1;
+    } else {
+        split_t = 1; split_s = 1;
+    }
+    int32_t kt[8], ks[8], nkt = 1, nks = 1;
+    kt[0] = t;
+    ks[0] = s;
+    if (split_t) {
+        nkt = T->nchild;
+        memcpy(kt, T->child, sizeof(kt));
+    }
+    if (split_s) {
+        nks = S->nchild;
+        memcpy(ks, S->child, sizeof(ks));
+    }
+    for (int32_t a = 0; a < nkt; ++a)
+        for (int32_t b = 0; b < nks; ++b)
+            cc_walk(cc, kt[a], ks[b]);
+}
+
+occ *oracle_cc_create(int64_t nt, const double *tx, const double *ty, const double *tz,
+                      int64_t ns, const double *sx, const double *sy, const double *sz,
+                      double theta, int32_t degree, int64_t leaf, int64_t batch)
+{
+    double t0 = wall_seconds();
+    occ *cc = (occ *)calloc(1, sizeof(occ));
+    cc->nt = nt; cc->ns = ns;
+    cc->tx = tx; cc->ty = ty; cc->tz = tz;
+    cc->sx = sx; cc->sy = sy; cc->sz = sz;
+    cc->theta = theta; cc->n = degree; cc->leaf = leaf; cc->batch = batch;
+    tree_build(&cc->tgt, nt, tx, ty, tz, batch);
+    tree_build(&cc->src, ns, sx, sy, sz, leaf);
+    if (nt > 0 && ns > 0)
+        cc_walk(cc, 0, 0);
+    cc->t_setup = wall_seconds() - t0;
+    return cc;
+}
+
+void oracle_cc_destroy(occ *cc)
+{
+    if (!cc)
+        return;
+    free(cc->pairs);
+    tree_free(&cc->tgt);
+    tree_free(&cc->src);
+    free(cc);
+}
+
+/* sizes: target nodes, source nodes, pairs */
+void oracle_cc_sizes(const occ *cc, int64_t *out /* [3] */)
+{
+    out[0] = cc->tgt.n_nodes;
+    out[1] = cc->src.n_nodes;
+    out[2] = cc->n_pairs;
+}
+
+void oracle_cc_orders(const occ *cc, int64_t *target_order, int64_t *source_order)
+{
+    memcpy(target_order, cc->tgt.idx, (size_t)cc->nt * sizeof(int64_t));
+    memcpy(source_order, cc->src.idx, (size_t)cc->ns * sizeof(int64_t));
+}
+
+/* node i of the target (side 0) or source (side 1) tree: lo, hi, begin, count */
+void oracle_cc_node(const occ *cc, int32_t side, int64_t i, double *lo, double *hi,
+                    int64_t *begin_count)
+{
+    const onode *nd = side == 0 ? &cc->tgt.nodes[i] : &cc->src.nodes[i];
+    for (int l = 0; l < 3; ++l) {
+        lo[l] = nd->lo[l];
+        hi[l] = nd->hi[l];
+    }
+    begin_count[0] = nd->begin;
+    begin_count[1] = nd->count;
+}
+
+void oracle_cc_pairs(const occ *cc, int32_t *t, int32_t *s, int32_t *kind)
+{
+    for (int64_t k = 0; k < cc->n_pairs; ++k) {
+        t[k] = cc->pairs[k].t;
+        s[k] = cc->pairs[k].s;
+        kind[k] = cc->pairs[k].kind;
+    }
+}
+
+/* modified charges of source node c by eq. 12 (as oracle_tc_modified_charges) */
+static void cc_modified_charges(const occ *cc, int32_t c, const double *q, double *qhat)
+{
+    const onode *nd = &cc->src.nodes[c];
+    int32_t n = cc->n, np = n + 1;
+    int64_t P = (int64_t)np * np * np;
+    double s[3][64], w[64], L[3][64];
+    for (int l = 0; l < 3; ++l)
+        oracle_chebyshev(n, nd->lo[l], nd->hi[l], s[l], w);
+    memset(qhat, 0, (size_t)P * sizeof(double));
+    const double *p[3] = {cc->sx, cc->sy, cc->sz};
+    for (int64_t a = nd->begin; a < nd->begin + nd->count; ++a) {
+        int64_t j = cc->src.idx[a];
+        for (int l = 0; l < 3; ++l)
+            oracle_lagrange(n, s[l], w, p[l][j], L[l]);
+        for (int32_t k1 = 0; k1 < np; ++k1)
+            for (int32_t k2 = 0; k2 < np; ++k2)
+                for (int32_t k3 = 0; k3 < np; ++k3)
+                    qhat[((int64_t)k1 * np + k2) * np + k3] +=
+                        L[0][k1] * L[1][k2] * L[2][k3] * q[j];
+    }
+}
+
+/* sum over the grid of source node s of G(x, s_m) qhat_m (eq. 11) */
+static double cc_from_grid(const occ *cc, int32_t s, const double *qhat, const double x[3],
+                           int32_t kernel, double kappa)
+{
+    const onode *S = &cc->src.nodes[s];
+    int32_t n = cc->n, np = n + 1;
+    double g[3][64], w[64];
+    for (int l = 0; l < 3; ++l)
+        oracle_chebyshev(n, S->lo[l], S->hi[l], g[l], w);
+    double acc = 0.0;
+    for (int32_t k1 = 0; k1 < np; ++k1)
+        for (int32_t k2 = 0; k2 < np; ++k2)
+            for (int32_t k3 = 0; k3 < np; ++k3) {
+                double dx = x[0] - g[0][k1], dy = x[1] - g[1][k2], dz = x[2] - g[2][k3];
+                double r = sqrt(dx * dx + dy * dy + dz * dz);
+                acc += kernel_of_distance(r, kernel, kappa) * qhat[((int64_t)k1 * np + k2) * np + k3];
+            }
+    return acc;
+}
+
+/* sum over the particles of source node s of G(x, y_j) q_j, r != 0 (R1) */
+static double cc_from_particles(const occ *cc, int32_t s, const double *q, const double x[3],
+                                int32_t kernel, double kappa)
+{
+    const onode *S = &cc->src.nodes[s];
+    double acc = 0.0;
+    for (int64_t a = S->begin; a < S->begin + S->count; ++a) {
+        int64_t j = cc->src.idx[a];
+        double dx = x[0] - cc->sx[j], dy = x[1] - cc->sy[j], dz = x[2] - cc->sz[j];
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r == 0.0)
+            continue;
+        acc += kernel_of_distance(r, kernel, kappa) * q[j];
+    }
+    return acc;
+}
+
+/* Proxy potentials of target node c (R21): CC pairs through the source      */
+/* cluster's modified charges, CP pairs through its particles.                */
+void oracle_cc_proxy_potentials(const occ *cc, int32_t c, const double *q, int32_t kernel,
+                                double kappa, double *out)
+{
+    const onode *T = &cc->tgt.nodes[c];
+    int32_t n = cc->n, np = n + 1;
+    int64_t P = (int64_t)np * np * np;
+    double t[3][64], w[64];
+    for (int l = 0; l < 3; ++l)
+        oracle_chebyshev(n, T->lo[l], T->hi[l], t[l], w);
+    memset(out, 0, (size_t)P * sizeof(double));
+    double *qhat = (double *)malloc((size_t)P * sizeof(double));
+    for (int64_t k = 0; k < cc->n_pairs; ++k) {
+        const opair *pr = &cc->pairs[k];
+        if (pr->t != c || (pr->kind != 0 && pr->kind != 2))
+            continue;
+        if (pr->kind == 0)
+            cc_modified_charges(cc, pr->s, q, qhat);
+        for (int32_t k1 = 0; k1 < np; ++k1)
+            for (int32_t k2 = 0; k2 < np; ++k2)
+                for (int32_t k3 = 0; k3 < np; ++k3) {
+                    double x[3] = {t[0][k1], t[1][k2], t[2][k3]};
+                    out[((int64_t)k1 * np + k2) * np + k3] +=
+                        pr->kind == 0 ? cc_from_grid(cc, pr->s, qhat, x, kernel, kappa)
+                                      : cc_from_particles(cc, pr->s, q, x, kernel, kappa);
+                }
+    }
+    free(qhat);
+}
+
+/* Evaluation (R23): phi[s] at target sample[s] (all targets when NULL). */
+int oracle_cc_potential(const occ *cc, const double *q, int32_t kernel, double kappa,
+                        int64_t n_sample, const int64_t *sample, double *phi, double *times)
+{
+    int32_t n = cc->n, np = n + 1;
+    int64_t P = (int64_t)np * np * np;
+    int64_t n_eval = sample ? n_sample : cc->nt;
+    int64_t nn = cc->tgt.n_nodes, ms = cc->src.n_nodes;
+    double t0 = wall_seconds();
+    for (int64_t s = 0; s < n_eval; ++s) {
+        int64_t i = sample ? sample[s] : s;
+        if (i < 0 || i >= cc->nt)
+            return -1;
+    }
+    int64_t *pos = (int64_t *)malloc((size_t)(cc->nt > 0 ? cc->nt : 1) * sizeof(int64_t));
+    for (int64_t a = 0; a < cc->nt; ++a)
+        pos[cc->tgt.idx[a]] = a;
+    /* pairs grouped by target node */
+    int64_t *off = (int64_t *)calloc((size_t)(nn + 1), sizeof(int64_t));
+    for (int64_t k = 0; k < cc->n_pairs; ++k)
+        off[cc->pairs[k].t + 1]++;
+    for (int64_t c = 0; c < nn; ++c)
+        off[c + 1] += off[c];
+    int64_t *by_t = (int64_t *)malloc((size_t)(cc->n_pairs > 0 ? cc->n_pairs : 1) * sizeof(int64_t));
+    {
+        int64_t *fill = (int64_t *)malloc((size_t)(nn > 0 ? nn : 1) * sizeof(int64_t));
+        for (int64_t c = 0; c < nn; ++c)
+            fill[c] = off[c];
+        for (int64_t k = 0; k < cc->n_pairs; ++k)
+            by_t[fill[cc->pairs[k].t]++] = k;
+        free(fill);
+    }
+    /* modified charges of the sources in CC or PC pairs */
+    char *need_s = (char *)calloc((size_t)(ms > 0 ? ms : 1), 1);
+    char *need_t = (char *)calloc((size_t)(nn > 0 ? nn : 1), 1);
+    for (int64_t k = 0; k < cc->n_pairs; ++k) {
+        if (cc->pairs[k].kind <= 1)
+            need_s[cc->pairs[k].s] = 1;
+        if (cc->pairs[k].kind == 0 || cc->pairs[k].kind == 2)
+            need_t[cc->pairs[k].t] = 1;
+    }
+    double **qhat = (double **)calloc((size_t)(ms > 0 ? ms : 1), sizeof(double *));
+    double **phat = (double **)calloc((size_t)(nn > 0 ? nn : 1), sizeof(double *));
+    {
+        int64_t c;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (c = 0; c < ms; ++c)
+            if (need_s[c]) {
+                qhat[c] = (double *)malloc((size_t)P * sizeof(double));
+                cc_modified_charges(cc, (int32_t)c, q, qhat[c]);
+            }
+#pragma omp parallel for schedule(dynamic, 1)
+        for (c = 0; c < nn; ++c)
+            if (need_t[c]) {
+                phat[c] = (double *)malloc((size_t)P * sizeof(double));
+                oracle_cc_proxy_potentials(cc, (int32_t)c, q, kernel, kappa, phat[c]);
+            }
+    }
+    double t1 = wall_seconds();
+    {
+        int64_t s;
+#pragma omp parallel for schedule(dynamic, 8)
+        for (s = 0; s < n_eval; ++s) {
+            int64_t i = sample ? sample[s] : s;
+            int64_t a = pos[i];
+            double x[3] = {cc->tx[i], cc->ty[i], cc->tz[i]};
+            double acc = 0.0;
+            double nodes[64], w[64], L[3][64];
+            for (int32_t c = 0; c >= 0;) {
+                const onode *T = &cc->tgt.nodes[c];
+                for (int64_t u = off[c]; u < off[c + 1]; ++u) {
+                    const opair *pr = &cc->pairs[by_t[u]];
+                    if (pr->kind == 1)
+                        acc += cc_from_grid(cc, pr->s, qhat[pr->s], x, kernel, kappa);
+                    else if (pr->kind == 3)
+                        acc += cc_from_particles(cc, pr->s, q, x, kernel, kappa);
+                }
+                if (phat[c]) {
+                    for (int l = 0; l < 3; ++l) {
+                        oracle_chebyshev(n, T->lo[l], T->hi[l], nodes, w);
+                        oracle_lagrange(n, nodes, w, x[l], L[l]);
+                    }
+                    for (int32_t k1 = 0; k1 < np; ++k1)
+                        for (int32_t k2 = 0; k2 < np; ++k2)
+                            for (int32_t k3 = 0; k3 < np; ++k3)
+                                acc += L[0][k1] * L[1][k2] * L[2][k3] *
+                                       phat[c][((int64_t)k1 * np + k2) * np + k3];
+                }
+                int32_t next = -1;
+                for (int32_t k = 0; k < T->nchild; ++k) {
+                    const onode *ch = &cc->tgt.nodes[T->child[k]];
+                    if (a >= ch->begin && a < ch->begin + ch->count)
+                        next = T->child[k];
+                }
+                c = next;
+            }
+            phi[s] = acc;
+        }
+    }
+    double t2 = wall_seconds();
+    if (times) {
+        times[0] = t1 - t0;
+        times[1] = t2 - t1;
+    }
+    for (int64_t c = 0; c < ms; ++c)
+        free(qhat[c]);
+    for (int64_t c = 0; c < nn; ++c)
+        free(phat[c]);
+    free(qhat);
+    free(phat);
+    free(need_s);
+    free(need_t);
+    free(by_t);
+    free(off);
+    free(pos);
+    return 0;
+}
