@@ -256,9 +256,10 @@ def run_large(args, dev):
     return res
 
 
-def run_cp(args, dev):
-    """Cluster-particle treecode (targets interpolated) on the headline workload:
-    10^6 uniform, Coulomb, theta 0.7, n 8, N_L = N_B = 2000, FP64 and FP32-mixed."""
+def run_variant(args, dev):
+    """Cluster-particle (targets interpolated) or cluster-cluster (both sides)
+    treecode on the headline workload: 10^6 uniform, Coulomb, theta 0.7, n 8,
+    N_L = N_B = 2000, FP64 and FP32-mixed."""
     import numpy as np
     import torch
 
@@ -273,12 +274,13 @@ def run_cp(args, dev):
     qd = torch.from_numpy(q[0]).to(dev)
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     smp = inputs.sample_indices(n, w["samples"], inputs.sample_seed(w["cfg"]))
-    res = {"workload": f"cp uniform-1M: N={n}, coulomb, theta={w['theta']}, n={w['degree']}, "
+    method = args.workload
+    res = {"workload": f"{method} uniform-1M: N={n}, coulomb, theta={w['theta']}, n={w['degree']}, "
                        f"N_L=N_B={w['leaf']}", "paths": {}}
     got = {}
     for prec in ("fp64", "fp32_mixed"):
         t0 = time.perf_counter()
-        plan = bltc.Plan(t, t, method="cp", theta=w["theta"], degree=w["degree"],
+        plan = bltc.Plan(t, t, method=method, theta=w["theta"], degree=w["degree"],
                          leaf_size=w["leaf"], batch_size=w["batch"], precision=prec)
         t_plan = time.perf_counter() - t0
         st = plan.stats()
@@ -300,30 +302,31 @@ def run_cp(args, dev):
             "end_to_end_targets_per_s": n / (t_plan + ms * 1e-3),
             "phases_ms": {"gather": ph["gather"], "proxy_potentials": ph["upward"],
                           "direct_and_interpolation": ph["interact"], "total": ph["total"]},
-            "proxy_evals": st["far_evals"], "near_evals": st["near_evals"],
+            "approx_evals": st["far_evals"], "near_evals": st["near_evals"],
             "interp_terms": st["upward_terms"],
-            "proxy_evals_per_s": st["far_evals"] / (ph["upward"] * 1e-3),
             "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"]}
-        log(f"cp {prec}: {ms:.2f} ms/step, phases {ph}")
+        log(f"{method} {prec}: {ms:.2f} ms/step, phases {ph}")
         del plan
     if not args.no_cpu:
         import oracle
-        oc = oracle.ClusterParticle(pos, pos, w["theta"], w["degree"], w["leaf"], w["batch"])
+        cls = oracle.ClusterParticle if method == "cp" else oracle.ClusterCluster
+        oc = cls(pos, pos, w["theta"], w["degree"], w["leaf"], w["batch"])
         ref, times = oc.potential(q[0], sample=smp, return_times=True)
         ds = oracle.direct(pos[smp], pos, q[0])
         for prec, v in got.items():
             res["paths"][prec]["E_par"] = rel_l2(ref, v[smp])
             res["paths"][prec]["E_tc"] = rel_l2(ds, v[smp])
         res["oracle_E_tc"] = rel_l2(ds, ref)
-        # the oracle forms the proxy potentials of every cluster on the sampled
-        # paths (nearly all of them) and evaluates the sample: extrapolate
+        # the oracle forms the proxy potentials (and modified charges) of every
+        # cluster on the sampled paths (nearly all of them) and evaluates the
+        # sample: extrapolate
         t_full = times["proxy"] + times["eval"] * n / len(smp)
         res["cpu_baseline"] = {"value": n / t_full, "unit": "targets/s",
                                "cores": oracle.max_threads(), "kind": "oracle",
                                "sample": f"{len(smp)} sampled targets: proxy potentials "
                                          f"{times['proxy']:.1f}s + evaluation {times['eval']:.2f}s, "
                                          f"extrapolated to N"}
-        log(f"cp: errors {[(p, res['paths'][p]['E_par'], res['paths'][p]['E_tc']) for p in got]}")
+        log(f"{method}: errors {[(p, res['paths'][p]['E_par'], res['paths'][p]['E_tc']) for p in got]}")
     return res
 
 
@@ -374,7 +377,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="uniform-1M",
                     choices=sorted(WORKLOADS) + ["batched-64x16", "yukawa-plummer-sweep", "uniform-large",
-                                                 "setup", "cp"])
+                                                 "setup", "cp", "cc"])
     ap.add_argument("--large-n", type=int, default=128_000_000)
     ap.add_argument("--setup-host-max", type=int, default=20_000_000,
                     help="setup workload: also time the host planner up to this many particles")
@@ -401,9 +404,11 @@ def main():
         print("no GPU visible", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
-    if args.workload in ("batched-64x16", "yukawa-plummer-sweep", "uniform-large", "setup", "cp"):
+    if args.workload in ("batched-64x16", "yukawa-plummer-sweep", "uniform-large", "setup", "cp",
+                         "cc"):
         fn = {"batched-64x16": run_batched, "yukawa-plummer-sweep": run_sweep,
-              "uniform-large": run_large, "setup": run_setup, "cp": run_cp}[args.workload]
+              "uniform-large": run_large, "setup": run_setup, "cp": run_variant,
+              "cc": run_variant}[args.workload]
         print(json.dumps(fn(args, dev)), flush=True)
         return 0
     w = WORKLOADS[args.workload]

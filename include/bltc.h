@@ -72,8 +72,23 @@ typedef enum { BLTC_FP64 = 0, BLTC_FP32_MIXED = 1 } bltc_precision;
  *                         potentials of each cluster on its root-to-leaf path.
  *                         MAC of eq. 13 with the roles exchanged:
  *                         r_S + r_T < theta R and (n+1)^3 < N_T.  One charge
- *                         vector per execution; not usable in a bltc_batch. */
-typedef enum { BLTC_PARTICLE_CLUSTER = 0, BLTC_CLUSTER_PARTICLE = 1 } bltc_method;
+ *                         vector per execution; not usable in a bltc_batch.
+ *  BLTC_CLUSTER_CLUSTER   both sides interpolated: source tree of capacity
+ *                         N_L (modified charges), target tree of capacity N_B
+ *                         (proxy potentials).  A dual walk from the roots
+ *                         accepts pairs with r_T + r_S < theta R and
+ *                         approximates every side with more than (n+1)^3
+ *                         particles (grid to grid, grid to targets, sources
+ *                         to grid, or a direct sum when neither); rejected
+ *                         pairs split the larger non-leaf cluster (both when
+ *                         the radii are equal) until two leaves meet, which
+ *                         are summed directly.  One charge vector per
+ *                         execution; not usable in a bltc_batch. */
+typedef enum {
+    BLTC_PARTICLE_CLUSTER = 0,
+    BLTC_CLUSTER_PARTICLE = 1,
+    BLTC_CLUSTER_CLUSTER = 2
+} bltc_method;
 
 typedef struct {
     int32_t kernel;              /* bltc_kernel                                         */
@@ -114,7 +129,7 @@ typedef struct bltc_plan bltc_plan;
  * written in tree order directly into the plan's device arrays.  The result
  * equals the plan bltc_plan_create_host builds from the same coordinates.
  * Synchronises `stream`.  max_q >= 1 bounds num_q of later executions
- * (max_q must be 1 for BLTC_CLUSTER_PARTICLE).  At most 2^31 - 1 particles
+ * (max_q must be 1 for BLTC_CLUSTER_PARTICLE and BLTC_CLUSTER_CLUSTER).  At most 2^31 - 1 particles
  * per side.  Non-finite coordinates: BLTC_EINVAL. */
 int bltc_plan_create(bltc_plan** out, const bltc_params* p,
                      int64_t nt, const double* tx, const double* ty, const double* tz,
@@ -143,7 +158,9 @@ int bltc_plan_execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q
  * ordered k = (k1*(n+1) + k2)*(n+1) + k3.  Synchronises `stream`.
  * BLTC_EINVAL if the cluster is in no approximation list (no charges formed).
  * For BLTC_CLUSTER_PARTICLE plans `cluster` is a target cluster and out
- * receives its proxy potentials (qi = 0). */
+ * receives its proxy potentials (qi = 0); for BLTC_CLUSTER_CLUSTER plans it is
+ * a node of the target tree (a batch index of bltc_plan_view) and out
+ * receives its proxy potentials. */
 int bltc_plan_modified_charges(bltc_plan* plan, int64_t cluster, int32_t qi,
                                double* out, void* stream);
 
@@ -188,7 +205,10 @@ int bltc_plan_phase_times(bltc_plan* plan, double* ms /* [4] */);
  * For BLTC_CLUSTER_PARTICLE plans the clusters are the target tree's nodes
  * (cluster_begin/count index target_order), the batches are the source
  * batches (batch_begin/count index source_order) and an item is (source
- * batch, target cluster, kind). */
+ * batch, target cluster, kind).  For BLTC_CLUSTER_CLUSTER plans the clusters
+ * are the source tree's nodes, the batches ALL nodes of the target tree, and
+ * an item is a pair of the dual walk (target node, source node, kind 0
+ * grid-grid, 1 grid-targets, 2 sources-grid, 3 direct). */
 typedef struct {
     int64_t nt, ns, n_clusters, n_batches, n_items;
     const int64_t* source_order;        /* [ns] original index at tree position    */

@@ -23,9 +23,10 @@ __all__ = ["params", "Plan", "Batch", "autotune", "potential", "direct", "BLTCEr
 _KERNELS = {"coulomb": _capi.COULOMB, "yukawa": _capi.YUKAWA}
 _PRECISIONS = {"fp64": _capi.FP64, "fp32_mixed": _capi.FP32_MIXED, "mixed": _capi.FP32_MIXED}
 # "bltc": the paper's particle-cluster treecode (sources interpolated);
-# "cp": cluster-particle (targets interpolated)
+# "cp": cluster-particle (targets interpolated); "cc": cluster-cluster (both)
 _METHODS = {"bltc": _capi.PARTICLE_CLUSTER, "particle_cluster": _capi.PARTICLE_CLUSTER,
-            "cp": _capi.CLUSTER_PARTICLE, "cluster_particle": _capi.CLUSTER_PARTICLE}
+            "cp": _capi.CLUSTER_PARTICLE, "cluster_particle": _capi.CLUSTER_PARTICLE,
+            "cc": _capi.CLUSTER_CLUSTER, "cluster_cluster": _capi.CLUSTER_CLUSTER}
 
 
 def library_path() -> str:

@@ -20,6 +20,7 @@ FP64 = 0
 FP32_MIXED = 1
 PARTICLE_CLUSTER = 0
 CLUSTER_PARTICLE = 1
+CLUSTER_CLUSTER = 2
 
 # every exported symbol of include/bltc.h
 EXPORTS = (

@@ -69,6 +69,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         "autotune": os.path.join(build_dir, "autotune.o"),
         "setup": os.path.join(build_dir, "setup_gpu.o"),
         "cp": os.path.join(build_dir, "cp.o"),
+        "cc": os.path.join(build_dir, "cc.o"),
         "kernels_cp": os.path.join(build_dir, "kernels_cp.o"),
     }
     cmds = [
@@ -86,6 +87,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         # geometric decisions (MAC) follow their formulas operation by operation
         [hipcc] + hip_flags + ["-ffp-contract=off", "-c", os.path.join(CSRC, "setup_gpu.hip"), "-o", objs["setup"]],
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "cp.cpp"), "-o", objs["cp"]],
+        [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "cc.cpp"), "-o", objs["cc"]],
         [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_cp.hip"), "-o", objs["kernels_cp"]],
     ]
     if verbose:

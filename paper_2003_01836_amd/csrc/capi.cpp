@@ -40,8 +40,10 @@ int check_params(const bltc_params* p)
         return fail(BLTC_EINVAL, "leaf_size and batch_size must be >= 1");
     if (p->threads_per_target < 0 || p->threads_per_target > 1)
         return fail(BLTC_EUNSUPPORTED, "threads_per_target must be 0 or 1");
-    if (p->method != BLTC_PARTICLE_CLUSTER && p->method != BLTC_CLUSTER_PARTICLE)
-        return fail(BLTC_EINVAL, "method must be BLTC_PARTICLE_CLUSTER or BLTC_CLUSTER_PARTICLE");
+    if (p->method != BLTC_PARTICLE_CLUSTER && p->method != BLTC_CLUSTER_PARTICLE &&
+        p->method != BLTC_CLUSTER_CLUSTER)
+        return fail(BLTC_EINVAL, "method must be BLTC_PARTICLE_CLUSTER, BLTC_CLUSTER_PARTICLE or "
+                                 "BLTC_CLUSTER_CLUSTER");
     return BLTC_OK;
 }
 
@@ -172,6 +174,8 @@ int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
         return BLTC_OK;
     if (plan->cp)
         return bltc_cp::upload(plan, s);
+    if (plan->cc)
+        return bltc_cc::upload(plan, s);
     const bltc::HostPlan& hp = plan->hp;
     bltc::DevicePlan& d = plan->d;
     HIP_TRY(hipGetDevice(&plan->device));
@@ -303,8 +307,8 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
             int64_t phi_ld, hipStream_t s)
 {
     const bltc::HostPlan& hp = plan->hp;
-    const int64_t nt = plan->cp ? plan->cpp.tgt.n : hp.tgt.n;
-    const int64_t ns = plan->cp ? plan->cpp.src.n : hp.src.n;
+    const int64_t nt = plan->cp ? plan->cpp.tgt.n : plan->cc ? plan->ccp.tgt.n : hp.tgt.n;
+    const int64_t ns = plan->cp ? plan->cpp.src.n : plan->cc ? plan->ccp.src.n : hp.src.n;
     if (num_q < 1 || num_q > plan->max_q)
         return fail(BLTC_EINVAL, "num_q must be in 1..max_q (%d)", plan->max_q);
     if (nt == 0)
@@ -329,6 +333,8 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
                     plan->device, dev);
     if (plan->cp)
         return bltc_cp::execute(plan, q, num_q, phi, s);
+    if (plan->cc)
+        return bltc_cc::execute(plan, q, num_q, phi, s);
     bltc::KernelParams kp;
     kp.kernel = plan->prm.kernel;
     kp.precision = plan->prm.precision;
@@ -394,8 +400,9 @@ int create_common(bltc_plan** out, const bltc_params* p, int64_t nt, const doubl
         return rc;
     if (max_q < 1)
         return fail(BLTC_EINVAL, "max_q must be >= 1");
-    if (p->method == BLTC_CLUSTER_PARTICLE && max_q != 1)
-        return fail(BLTC_EUNSUPPORTED, "cluster-particle plans take one charge vector (max_q = 1)");
+    if (p->method != BLTC_PARTICLE_CLUSTER && max_q != 1)
+        return fail(BLTC_EUNSUPPORTED, "cluster-particle and cluster-cluster plans take one charge "
+                                       "vector (max_q = 1)");
     return BLTC_OK;
 }
 
@@ -416,6 +423,8 @@ int create_from_host(bltc_plan** out, const bltc_params* p, int64_t nt, const do
     try {
         if (p->method == BLTC_CLUSTER_PARTICLE)
             rc = bltc_cp::create_host(plan, plan_params(plan, p), nt, tx, ty, tz, ns, sx, sy, sz);
+        else if (p->method == BLTC_CLUSTER_CLUSTER)
+            rc = bltc_cc::create_host(plan, plan_params(plan, p), nt, tx, ty, tz, ns, sx, sy, sz);
         else
             rc = make_host_plan(plan, p, nt, tx, ty, tz, ns, sx, sy, sz);
     } catch (const std::bad_alloc&) {
@@ -477,6 +486,8 @@ int bltc_plan_create(bltc_plan** out, const bltc_params* p, int64_t nt, const do
     try {
         if (p->method == BLTC_CLUSTER_PARTICLE)
             rc = bltc_cp::create_device(plan, plan_params(plan, p), nt, tx, ty, tz, ns, sx, sy, sz, s);
+        else if (p->method == BLTC_CLUSTER_CLUSTER)
+            rc = bltc_cc::create_device(plan, plan_params(plan, p), nt, tx, ty, tz, ns, sx, sy, sz, s);
         else
             rc = make_device_plan(plan, p, nt, tx, ty, tz, ns, sx, sy, sz, s);
         if (rc == BLTC_OK)
@@ -538,10 +549,11 @@ int bltc_plan_modified_charges(bltc_plan* plan, int64_t cluster, int32_t qi, dou
 {
     if (!plan || !out)
         return fail(BLTC_EINVAL, "NULL argument");
-    if (plan->cp) {
+    if (plan->cp || plan->cc) {
         if (qi != 0)
-            return fail(BLTC_EINVAL, "cluster-particle plans have one charge vector");
-        return bltc_cp::proxy_potentials(plan, cluster, out, static_cast<hipStream_t>(stream));
+            return fail(BLTC_EINVAL, "cluster-particle and cluster-cluster plans have one charge vector");
+        return plan->cp ? bltc_cp::proxy_potentials(plan, cluster, out, static_cast<hipStream_t>(stream))
+                        : bltc_cc::proxy_potentials(plan, cluster, out, static_cast<hipStream_t>(stream));
     }
     const bltc::HostPlan& hp = plan->hp;
     if (cluster < 0 || cluster >= hp.src.nodes())
@@ -574,8 +586,11 @@ int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out)
         return fail(BLTC_EINVAL, "NULL argument");
     const bltc::HostPlan& hp = plan->hp;
     std::memset(out, 0, sizeof(*out));
-    if (plan->cp) {
-        bltc_cp::stats(plan, out);
+    if (plan->cp || plan->cc) {
+        if (plan->cp)
+            bltc_cp::stats(plan, out);
+        else
+            bltc_cc::stats(plan, out);
         out->degree = plan->prm.degree;
         out->leaf_size = plan->prm.leaf_size;
         out->batch_size = plan->prm.batch_size;
@@ -606,6 +621,8 @@ int bltc_plan_view_get(const bltc_plan* plan, bltc_plan_view* out)
     std::memset(out, 0, sizeof(*out));
     if (plan->cp)
         return bltc_cp::view(plan, out);
+    if (plan->cc)
+        return bltc_cc::view(plan, out);
     out->nt = hp.tgt.n;
     out->ns = hp.src.n;
     out->n_clusters = hp.src.nodes();

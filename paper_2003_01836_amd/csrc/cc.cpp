@@ -1,0 +1,419 @@
+// cc.cpp -- plans of the cluster-cluster treecode (method
+// BLTC_CLUSTER_CLUSTER): both sides interpolated, pairs from a dual walk.
+//
+// One evaluation:
+//  1. charges into source-tree order, modified charges of the source slots
+//     (the BLTC upward pass on the matrix cores, eqs. 14-15);
+//  2. the source array holds the ns particles followed by the Chebyshev grids
+//     of the source slots; the grids' charges are set to the modified charges
+//     (`proxy_charges`), so a cluster-cluster pair is a "direct sum" over P
+//     grid points;
+//  3. proxy potentials of the target slots: the interaction kernel over the
+//     target grids as targets, lists holding source-grid ranges
+//     (cluster-cluster pairs) and particle ranges (cluster-particle pairs);
+//  4. targets by target leaf: far lists (particle-cluster pairs, eq. 11 with
+//     the modified charges) and direct lists, phi written once;
+//  5. interpolation of the proxy potentials of every target slot on each
+//     target's path (kernels_cp.hip), phi +=.
+#include <chrono>
+#include <cstring>
+#include <numeric>
+
+#include "internal.hpp"
+#include "kernels_cp.hpp"
+#include "setup_gpu.hpp"
+
+using bltc_detail::fail;
+
+namespace bltc_cc {
+
+int create_host(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const double* tx,
+                const double* ty, const double* tz, int64_t ns, const double* sx, const double* sy,
+                const double* sz)
+{
+    plan->cc = true;
+    bltc::make_cc_plan(plan->ccp, pp, nt, tx, ty, tz, ns, sx, sy, sz);
+    return BLTC_OK;
+}
+
+int create_device(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const double* tx,
+                  const double* ty, const double* tz, int64_t ns, const double* sx,
+                  const double* sy, const double* sz, hipStream_t s)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    plan->cc = true;
+    bltc::CcPlan& cc = plan->ccp;
+    cc = bltc::CcPlan();
+    cc.prm = pp;
+    const bool mixed = plan->prm.precision == BLTC_FP32_MIXED;
+    HIP_TRY(hipGetDevice(&plan->device));
+    // particles are written by the tree build; the grid tail of the source
+    // arrays is filled at upload, once the slots are known
+    bltc::DevicePlan& du = plan->d;
+    bltc::DevicePlan& dd = plan->ddir;
+    int64_t* src_order = nullptr;
+    HIP_TRY(plan->alloc(&plan->cc_src_particles, static_cast<size_t>(ns)));
+    HIP_TRY(plan->alloc(&src_order, static_cast<size_t>(ns)));
+    du.src_order = src_order;
+    if (mixed)
+        HIP_TRY(plan->alloc(&plan->cc_src32_particles, static_cast<size_t>(ns)));
+    HIP_TRY(plan->alloc(&dd.tgt, static_cast<size_t>(nt)));
+    HIP_TRY(plan->alloc(&dd.tgt_orig, static_cast<size_t>(nt)));
+    int64_t bad = -1;
+    std::string err = bltc::build_tree_device(cc.src, ns, sx, sy, sz, pp.leaf_size, src_order,
+                                              plan->cc_src_particles,
+                                              mixed ? plan->cc_src32_particles : nullptr, s, &bad);
+    if (bad >= 0)
+        return fail(BLTC_EINVAL, "source coordinate %lld is not finite", static_cast<long long>(bad));
+    if (!err.empty())
+        return fail(BLTC_EHIP, "device tree build: %s", err.c_str());
+    if (nt == ns && tx == sx && ty == sy && tz == sz && pp.batch_size == pp.leaf_size) {
+        cc.tgt = cc.src;
+        if (nt > 0) {
+            HIP_TRY(hipMemcpyAsync(dd.tgt, plan->cc_src_particles, nt * sizeof(double4),
+                                   hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(dd.tgt_orig, src_order, nt * sizeof(int64_t),
+                                   hipMemcpyDeviceToDevice, s));
+        }
+    } else {
+        err = bltc::build_tree_device(cc.tgt, nt, tx, ty, tz, pp.batch_size, dd.tgt_orig, dd.tgt,
+                                      nullptr, s, &bad);
+        if (bad >= 0)
+            return fail(BLTC_EINVAL, "target coordinate %lld is not finite",
+                        static_cast<long long>(bad));
+        if (!err.empty())
+            return fail(BLTC_EHIP, "device tree build: %s", err.c_str());
+    }
+    bltc::cc_plan_from_trees(cc);
+    plan->device_particles = true;
+    cc.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return BLTC_OK;
+}
+
+int upload(bltc_plan* plan, hipStream_t s)
+{
+    if (plan->uploaded)
+        return BLTC_OK;
+    const bltc::CcPlan& cc = plan->ccp;
+    const bool mixed = plan->prm.precision == BLTC_FP32_MIXED;
+    bltc::DevicePlan& du = plan->d;
+    bltc::DevicePlan& px = plan->dprox;
+    bltc::DevicePlan& dd = plan->ddir;
+    HIP_TRY(hipGetDevice(&plan->device));
+    const int64_t nt = cc.tgt.n, ns = cc.src.n;
+    const int64_t nns = cc.src.nodes();
+    const int64_t nss = static_cast<int64_t>(cc.sslot_cluster.size());
+    const int64_t nts = static_cast<int64_t>(cc.tslot_cluster.size());
+    const int64_t ntl = static_cast<int64_t>(cc.tl_node.size());
+    const int32_t np = cc.np;
+    const int64_t P = cc.P;
+    const int64_t nsrc = ns + nss * P;     // particles, then the source grids
+
+    auto expand = [&](const std::vector<double>& nodes, int64_t nslots) {
+        std::vector<double4> g(static_cast<size_t>(nslots * P));
+        for (int64_t sl = 0; sl < nslots; ++sl) {
+            const double* nd = nodes.data() + sl * 3 * np;
+            for (int32_t k1 = 0; k1 < np; ++k1)
+                for (int32_t k2 = 0; k2 < np; ++k2)
+                    for (int32_t k3 = 0; k3 < np; ++k3)
+                        g[static_cast<size_t>(sl * P + (k1 * np + k2) * np + k3)] =
+                            make_double4(nd[k1], nd[np + k2], nd[2 * np + k3], 0.0);
+        }
+        return g;
+    };
+
+    // ---- source array: particles in tree order, then the source grids
+    HIP_TRY(plan->alloc(&du.src, static_cast<size_t>(nsrc)));
+    if (mixed)
+        HIP_TRY(plan->alloc(&du.src32, static_cast<size_t>(nsrc)));
+    if (plan->device_particles) {
+        if (ns > 0) {
+            HIP_TRY(hipMemcpyAsync(du.src, plan->cc_src_particles, ns * sizeof(double4),
+                                   hipMemcpyDeviceToDevice, s));
+            if (mixed)
+                HIP_TRY(hipMemcpyAsync(du.src32, plan->cc_src32_particles, ns * sizeof(float4),
+                                       hipMemcpyDeviceToDevice, s));
+        }
+    } else {
+        std::vector<double4> src(ns), tgt(nt);
+        for (int64_t j = 0; j < ns; ++j)
+            src[j] = make_double4(cc.src.x[j], cc.src.y[j], cc.src.z[j], 0.0);
+        for (int64_t i = 0; i < nt; ++i)
+            tgt[i] = make_double4(cc.tgt.x[i], cc.tgt.y[i], cc.tgt.z[i], 0.0);
+        if (ns > 0)
+            HIP_TRY(hipMemcpyAsync(du.src, src.data(), ns * sizeof(double4), hipMemcpyHostToDevice, s));
+        HIP_TRY(plan->put(&dd.tgt, tgt, s));
+        HIP_TRY(plan->put(&dd.tgt_orig, cc.tgt.order, s));
+        int64_t* src_order = nullptr;
+        HIP_TRY(plan->put(&src_order, cc.src.order, s));
+        du.src_order = src_order;
+        if (mixed) {
+            // particles relative to the center of their source leaf
+            std::vector<float4> src32(ns);
+            for (int64_t u = 0; u < nns; ++u) {
+                if (cc.src.nchild[u] != 0)
+                    continue;
+                const double cx = cc.src.center[3 * u], cy = cc.src.center[3 * u + 1],
+                             cz = cc.src.center[3 * u + 2];
+                for (int64_t j = cc.src.begin[u]; j < cc.src.begin[u] + cc.src.count[u]; ++j)
+                    src32[j] = make_float4(static_cast<float>(cc.src.x[j] - cx),
+                                           static_cast<float>(cc.src.y[j] - cy),
+                                           static_cast<float>(cc.src.z[j] - cz), 0.0f);
+            }
+            if (ns > 0)
+                HIP_TRY(hipMemcpyAsync(du.src32, src32.data(), ns * sizeof(float4),
+                                       hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    const std::vector<double4> sgrid = expand(cc.sslot_nodes, nss);
+    if (nss > 0)
+        HIP_TRY(hipMemcpyAsync(du.src + ns, sgrid.data(), sgrid.size() * sizeof(double4),
+                               hipMemcpyHostToDevice, s));
+    std::vector<float4> sgrid32;
+    if (mixed && nss > 0) {
+        // grid points relative to their cluster's center
+        sgrid32.resize(sgrid.size());
+        for (int64_t sl = 0; sl < nss; ++sl) {
+            const int32_t c = cc.sslot_cluster[sl];
+            for (int64_t k = 0; k < P; ++k) {
+                const double4 g = sgrid[static_cast<size_t>(sl * P + k)];
+                sgrid32[static_cast<size_t>(sl * P + k)] =
+                    make_float4(static_cast<float>(g.x - cc.src.center[3 * c]),
+                                static_cast<float>(g.y - cc.src.center[3 * c + 1]),
+                                static_cast<float>(g.z - cc.src.center[3 * c + 2]), 0.0f);
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(du.src32 + ns, sgrid32.data(), sgrid32.size() * sizeof(float4),
+                               hipMemcpyHostToDevice, s));
+    }
+
+    // ---- upward pass over the source slots
+    du.degree = px.degree = dd.degree = plan->prm.degree;
+    du.ns = ns;
+    du.nslots = nss;
+    du.nchunks = static_cast<int64_t>(cc.chunk_slot.size());
+    HIP_TRY(plan->put(&du.slot_nodes, cc.sslot_nodes, s));
+    HIP_TRY(plan->put(&du.chunk_slot, cc.chunk_slot, s));
+    HIP_TRY(plan->put(&du.chunk_begin, cc.chunk_begin, s));
+    HIP_TRY(plan->put(&du.chunk_count, cc.chunk_count, s));
+    HIP_TRY(plan->put(&du.slot_chunk_off, cc.slot_chunk_off, s));
+    HIP_TRY(plan->put(&du.chunk_dst, cc.chunk_dst, s));
+    HIP_TRY(plan->alloc(&du.qhat, static_cast<size_t>((nss + cc.npartial) * P)));
+    if (mixed)
+        HIP_TRY(plan->alloc(&du.qhat32, static_cast<size_t>(nss * P)));
+
+    // ---- proxy potentials of the target slots
+    const std::vector<double4> tgrid = expand(cc.tslot_nodes, nts);
+    std::vector<int64_t> tgrid_orig(tgrid.size()), tgrid_end(nts), leaf_end(ntl);
+    std::iota(tgrid_orig.begin(), tgrid_orig.end(), int64_t(0));
+    for (int64_t u = 0; u < nts; ++u)
+        tgrid_end[u] = (u + 1) * P;
+    for (int64_t r = 0; r < ntl; ++r)
+        leaf_end[r] = cc.tl_begin[r] + cc.tl_count[r];
+    const std::vector<int32_t> zero_off(nts + 1, 0), one_i(1, 0);
+    px.src = dd.src = du.src;
+    px.src32 = dd.src32 = du.src32;
+    px.ns = dd.ns = ns;
+    px.nt = nts * P;
+    px.nbatches = nts;
+    px.ngroups = static_cast<int64_t>(cc.pg_batch.size());
+    HIP_TRY(plan->put(&px.tgt, tgrid, s));
+    HIP_TRY(plan->put(&px.tgt_orig, tgrid_orig, s));
+    HIP_TRY(plan->put(&px.group_batch, cc.pg_batch, s));
+    HIP_TRY(plan->put(&px.group_first, cc.pg_first, s));
+    HIP_TRY(plan->put(&px.batch_end, tgrid_end, s));
+    HIP_TRY(plan->put(&px.far_off, zero_off, s));
+    HIP_TRY(plan->put(&px.far_slot, one_i, s));
+    HIP_TRY(plan->put(&px.near_off, cc.pf_off, s));
+    HIP_TRY(plan->put(&px.near_begin, cc.pf_begin, s));
+    HIP_TRY(plan->put(&px.near_count, cc.pf_count, s));
+    HIP_TRY(plan->put(&px.near_leaf, cc.pf_leaf, s));
+    px.slot_nodes = du.slot_nodes;
+    px.qhat = du.qhat;
+    px.qhat32 = du.qhat32;
+
+    // ---- targets by target leaf
+    dd.nt = nt;
+    dd.nbatches = ntl;
+    dd.ngroups = static_cast<int64_t>(cc.dg_batch.size());
+    HIP_TRY(plan->put(&dd.group_batch, cc.dg_batch, s));
+    HIP_TRY(plan->put(&dd.group_first, cc.dg_first, s));
+    HIP_TRY(plan->put(&dd.batch_end, leaf_end, s));
+    HIP_TRY(plan->put(&dd.far_off, cc.far_off, s));
+    HIP_TRY(plan->put(&dd.far_slot, cc.far_slot, s));
+    HIP_TRY(plan->put(&dd.near_off, cc.dn_off, s));
+    HIP_TRY(plan->put(&dd.near_begin, cc.dn_begin, s));
+    HIP_TRY(plan->put(&dd.near_count, cc.dn_count, s));
+    HIP_TRY(plan->put(&dd.near_leaf, cc.dn_leaf, s));
+    dd.slot_nodes = du.slot_nodes;
+    dd.qhat = du.qhat;
+    dd.qhat32 = du.qhat32;
+
+    HIP_TRY(plan->put(&plan->cp_path_off, cc.dw_off, s));
+    HIP_TRY(plan->put(&plan->cp_path_slot, cc.dw_slot, s));
+    HIP_TRY(plan->put(&plan->cp_slot_nodes, cc.tslot_nodes, s));
+    HIP_TRY(plan->alloc(&plan->cp_phat, static_cast<size_t>(nts * P)));
+
+    if (mixed) {
+        // source nodes, then one entry per source slot (its grid's frame)
+        std::vector<double4> node_info(nns + nss);
+        for (int64_t c = 0; c < nns; ++c)
+            node_info[c] = make_double4(cc.src.center[3 * c], cc.src.center[3 * c + 1],
+                                        cc.src.center[3 * c + 2], cc.src.radius[c]);
+        for (int64_t sl = 0; sl < nss; ++sl)
+            node_info[nns + sl] = node_info[cc.sslot_cluster[sl]];
+        std::vector<double4> bi_p(nts), bi_d(ntl);
+        for (int64_t u = 0; u < nts; ++u) {
+            const int32_t c = cc.tslot_cluster[u];
+            bi_p[u] = make_double4(cc.tgt.center[3 * c], cc.tgt.center[3 * c + 1],
+                                   cc.tgt.center[3 * c + 2], cc.tgt.radius[c]);
+        }
+        for (int64_t r = 0; r < ntl; ++r) {
+            const int32_t c = cc.tl_node[r];
+            bi_d[r] = make_double4(cc.tgt.center[3 * c], cc.tgt.center[3 * c + 1],
+                                   cc.tgt.center[3 * c + 2], cc.tgt.radius[c]);
+        }
+        HIP_TRY(plan->put(&px.node_info, node_info, s));
+        dd.node_info = px.node_info;
+        HIP_TRY(plan->put(&px.batch_info, bi_p, s));
+        HIP_TRY(plan->put(&dd.batch_info, bi_d, s));
+        if (!du.qhat32) {
+            HIP_TRY(plan->alloc(&du.qhat32, 1));
+            px.qhat32 = dd.qhat32 = du.qhat32;
+        }
+    }
+    // host staging vectors die at return: finish the copies first
+    HIP_TRY(hipStreamSynchronize(s));
+    plan->uploaded = true;
+    return BLTC_OK;
+}
+
+int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStream_t s)
+{
+    if (num_q != 1)
+        return fail(BLTC_EUNSUPPORTED, "cluster-cluster plans take one charge vector");
+    int rc = upload(plan, s);
+    if (rc != BLTC_OK)
+        return rc;
+    const bltc::CcPlan& cc = plan->ccp;
+    bltc::KernelParams kp;
+    kp.kernel = plan->prm.kernel;
+    kp.precision = plan->prm.precision;
+    kp.kappa = plan->prm.kappa;
+    const bool mixed = kp.precision == BLTC_FP32_MIXED;
+    bltc::DevicePlan& du = plan->d;
+    if (plan->timing) {
+        while (plan->events.size() < 4) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            plan->events.push_back(e);
+        }
+    }
+    auto mark = [&](int k) -> hipError_t {
+        return plan->timing ? hipEventRecord(plan->events[k], s) : hipSuccess;
+    };
+    plan->timed_q = 0;
+    HIP_TRY(mark(0));
+    HIP_TRY(bltc::launch_gather_charges(du, q, s));
+    HIP_TRY(mark(1));
+    HIP_TRY(bltc::launch_upward_mfma(du, 1, du.qhat, mixed ? du.qhat32 : nullptr, s));
+    const int64_t nss = static_cast<int64_t>(cc.sslot_cluster.size());
+    HIP_TRY(bltc::launch_proxy_charges(du.src + du.ns, mixed ? du.src32 + du.ns : nullptr, du.qhat,
+                                       nss * cc.P, s));
+    if (mixed)
+        HIP_TRY(bltc::launch_interact_mixed(plan->dprox, kp, plan->cp_phat, s));
+    else
+        HIP_TRY(bltc::launch_interact(plan->dprox, kp, plan->cp_phat, s));
+    HIP_TRY(mark(2));
+    if (mixed)
+        HIP_TRY(bltc::launch_interact_mixed(plan->ddir, kp, phi, s));
+    else
+        HIP_TRY(bltc::launch_interact(plan->ddir, kp, phi, s));
+    HIP_TRY(bltc::launch_interpolate_targets(plan->ddir, plan->cp_path_off, plan->cp_path_slot,
+                                             plan->cp_slot_nodes, plan->cp_phat, phi, s));
+    HIP_TRY(mark(3));
+    plan->timed_q = plan->timing ? 1 : 0;
+    plan->last_q = 1;
+    return BLTC_OK;
+}
+
+int proxy_potentials(bltc_plan* plan, int64_t cluster, double* out, hipStream_t s)
+{
+    const bltc::CcPlan& cc = plan->ccp;
+    if (cluster < 0 || cluster >= cc.tgt.nodes())
+        return fail(BLTC_EINVAL, "target node index out of range");
+    const int32_t slot = cc.cluster_tslot[cluster];
+    if (slot < 0)
+        return fail(BLTC_EINVAL, "target node %lld has no proxy potentials",
+                    static_cast<long long>(cluster));
+    if (!plan->uploaded || plan->last_q == 0)
+        return fail(BLTC_EINVAL, "plan has not been executed");
+    HIP_TRY(hipMemcpyAsync(out, plan->cp_phat + static_cast<int64_t>(slot) * cc.P,
+                           cc.P * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return BLTC_OK;
+}
+
+void stats(const bltc_plan* plan, bltc_stats* out)
+{
+    const bltc::CcPlan& cc = plan->ccp;
+    out->clusters = cc.src.nodes();
+    int64_t leaves = 0;
+    for (int64_t u = 0; u < cc.src.nodes(); ++u)
+        leaves += cc.src.nchild[u] == 0;
+    out->leaves = leaves;
+    out->batches = static_cast<int64_t>(cc.tl_node.size());
+    out->approx_pairs = cc.kind_pairs[0] + cc.kind_pairs[1] + cc.kind_pairs[2];
+    out->direct_pairs = cc.kind_pairs[3];
+    out->approx_clusters = static_cast<int64_t>(cc.sslot_cluster.size());
+    out->far_evals = cc.cc_evals + cc.pc_evals + cc.cp_evals;
+    out->near_evals = cc.near_evals;
+    out->upward_terms = cc.upward_terms + cc.interp_terms;
+    out->depth = std::max(cc.src.depth, cc.tgt.depth);
+    out->setup_seconds = cc.setup_seconds;
+}
+
+int view(const bltc_plan* plan, bltc_plan_view* out)
+{
+    const bltc::CcPlan& cc = plan->ccp;
+    out->nt = cc.tgt.n;
+    out->ns = cc.src.n;
+    out->n_clusters = cc.src.nodes();
+    out->n_batches = cc.tgt.nodes();
+    out->n_items = static_cast<int64_t>(cc.pair_t.size());
+    out->source_order = cc.src.order.data();
+    out->target_order = cc.tgt.order.data();
+    if (plan->device_particles) {
+        if (plan->view_src_order.size() != static_cast<size_t>(cc.src.n)) {
+            plan->view_src_order.resize(cc.src.n);
+            plan->view_tgt_order.resize(cc.tgt.n);
+            if (cc.src.n > 0)
+                HIP_TRY(hipMemcpy(plan->view_src_order.data(), plan->d.src_order,
+                                  cc.src.n * sizeof(int64_t), hipMemcpyDeviceToHost));
+            if (cc.tgt.n > 0)
+                HIP_TRY(hipMemcpy(plan->view_tgt_order.data(), plan->ddir.tgt_orig,
+                                  cc.tgt.n * sizeof(int64_t), hipMemcpyDeviceToHost));
+        }
+        out->source_order = plan->view_src_order.data();
+        out->target_order = plan->view_tgt_order.data();
+    }
+    out->cluster_begin = cc.src.begin.data();
+    out->cluster_count = cc.src.count.data();
+    out->cluster_lo = cc.src.lo.data();
+    out->cluster_hi = cc.src.hi.data();
+    out->cluster_first_child = cc.src.first_child.data();
+    out->cluster_nchild = cc.src.nchild.data();
+    out->cluster_level = cc.src.level.data();
+    out->batch_begin = cc.tgt.begin.data();
+    out->batch_count = cc.tgt.count.data();
+    out->batch_lo = cc.tgt.lo.data();
+    out->batch_hi = cc.tgt.hi.data();
+    out->item_batch = cc.pair_t.data();
+    out->item_cluster = cc.pair_s.data();
+    out->item_kind = cc.pair_kind.data();
+    return BLTC_OK;
+}
+
+}  // namespace bltc_cc

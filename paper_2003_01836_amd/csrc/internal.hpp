@@ -84,6 +84,15 @@ struct bltc_plan {
     int32_t* cp_path_slot = nullptr;
     double* cp_slot_nodes = nullptr;
     double* cp_phat = nullptr;
+    // cluster-cluster plans (method BLTC_CLUSTER_CLUSTER): host plan and the
+    // particles as written by the device tree build (copied into the source
+    // array, which also holds the source grids, at upload); the interaction
+    // launches, interpolation lists and proxy potentials use the members above,
+    // the upward pass uses d
+    bool cc = false;
+    bltc::CcPlan ccp;
+    double4* cc_src_particles = nullptr;
+    float4* cc_src32_particles = nullptr;
     bool uploaded = false;
     int device = -1;
     bltc::DevicePlan d;
@@ -138,3 +147,18 @@ int proxy_potentials(bltc_plan* plan, int64_t cluster, double* out, hipStream_t 
 void stats(const bltc_plan* plan, bltc_stats* out);
 int view(const bltc_plan* plan, bltc_plan_view* out);
 }  // namespace bltc_cp
+
+// cluster-cluster plans (cc.cpp)
+namespace bltc_cc {
+int create_host(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const double* tx,
+                const double* ty, const double* tz, int64_t ns, const double* sx, const double* sy,
+                const double* sz);
+int create_device(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const double* tx,
+                  const double* ty, const double* tz, int64_t ns, const double* sx,
+                  const double* sy, const double* sz, hipStream_t s);
+int upload(bltc_plan* plan, hipStream_t s);
+int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStream_t s);
+int proxy_potentials(bltc_plan* plan, int64_t cluster, double* out, hipStream_t s);
+void stats(const bltc_plan* plan, bltc_stats* out);
+int view(const bltc_plan* plan, bltc_plan_view* out);
+}  // namespace bltc_cc

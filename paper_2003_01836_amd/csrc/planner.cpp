@@ -265,10 +265,49 @@ void leaf_runs(const Tree& S, std::vector<int32_t>& leaf_list, std::vector<int64
     }
 }
 
+void grid_nodes(const Tree& t, const std::vector<int32_t>& clusters, int32_t degree,
+                std::vector<double>& out)
+{
+    const int32_t np = degree + 1;
+    const int64_t nc = static_cast<int64_t>(clusters.size());
+    out.resize(nc * 3 * np);
+    for (int64_t s = 0; s < nc; ++s) {
+        const int32_t c = clusters[s];
+        for (int l = 0; l < 3; ++l) {
+            const double a = t.lo[3 * c + l], bb = t.hi[3 * c + l];
+            const double mid = (a + bb) / 2.0;
+            const double h = (bb - a) / 2.0;
+            for (int32_t k = 0; k < np; ++k)
+                out[(s * 3 + l) * np + k] =
+                    mid + h * std::cos(M_PI * static_cast<double>(k) / static_cast<double>(degree));
+        }
+    }
+}
+
+void upward_chunks(const Tree& S, const std::vector<int32_t>& slot_cluster, int64_t chunk_size,
+                   std::vector<int32_t>& chunk_slot, std::vector<int64_t>& chunk_begin,
+                   std::vector<int64_t>& chunk_count, std::vector<int32_t>& slot_chunk_off,
+                   std::vector<int64_t>& chunk_dst, int64_t& npartial)
+{
+    const int64_t nslots = static_cast<int64_t>(slot_cluster.size());
+    slot_chunk_off.assign(nslots + 1, 0);
+    for (int64_t s = 0; s < nslots; ++s) {
+        const int32_t c = slot_cluster[s];
+        for (int64_t off = 0; off < S.count[c]; off += chunk_size) {
+            chunk_slot.push_back(static_cast<int32_t>(s));
+            chunk_begin.push_back(S.begin[c] + off);
+            chunk_count.push_back(std::min<int64_t>(chunk_size, S.count[c] - off));
+        }
+        slot_chunk_off[s + 1] = static_cast<int32_t>(chunk_slot.size());
+        const int32_t c0 = slot_chunk_off[s], c1 = slot_chunk_off[s + 1];
+        for (int32_t c = c0; c < c1; ++c)
+            chunk_dst.push_back(c1 - c0 == 1 ? s : nslots + npartial++);
+    }
+}
+
 void plan_slots(HostPlan& hp, const std::vector<uint8_t>& used)
 {
     const Tree& S = hp.src;
-    const int32_t np = hp.np;
     hp.cluster_slot.assign(S.nodes(), -1);
     hp.slot_cluster.clear();
     for (int64_t c = 0; c < S.nodes(); ++c)
@@ -276,19 +315,7 @@ void plan_slots(HostPlan& hp, const std::vector<uint8_t>& used)
             hp.cluster_slot[c] = static_cast<int32_t>(hp.slot_cluster.size());
             hp.slot_cluster.push_back(static_cast<int32_t>(c));
         }
-    const int64_t nslots = static_cast<int64_t>(hp.slot_cluster.size());
-    hp.slot_nodes.resize(nslots * 3 * np);
-    for (int64_t s = 0; s < nslots; ++s) {
-        const int32_t c = hp.slot_cluster[s];
-        for (int l = 0; l < 3; ++l) {
-            const double a = S.lo[3 * c + l], bb = S.hi[3 * c + l];
-            const double mid = (a + bb) / 2.0;
-            const double h = (bb - a) / 2.0;
-            for (int32_t k = 0; k < np; ++k)
-                hp.slot_nodes[(s * 3 + l) * np + k] =
-                    mid + h * std::cos(M_PI * static_cast<double>(k) / static_cast<double>(hp.prm.degree));
-        }
-    }
+    grid_nodes(S, hp.slot_cluster, hp.prm.degree, hp.slot_nodes);
 }
 
 void plan_from_trees(HostPlan& hp)
@@ -468,20 +495,10 @@ void plan_schedule(HostPlan& hp)
     const Tree& S = hp.src;
     const int64_t nslots = static_cast<int64_t>(hp.slot_cluster.size());
     // ---- upward-pass chunks ----------------------------------------------------
-    hp.slot_chunk_off.assign(nslots + 1, 0);
-    for (int64_t s = 0; s < nslots; ++s) {
-        const int32_t c = hp.slot_cluster[s];
-        hp.upward_terms += S.count[c] * hp.P;
-        for (int64_t off = 0; off < S.count[c]; off += prm.chunk_size) {
-            hp.chunk_slot.push_back(static_cast<int32_t>(s));
-            hp.chunk_begin.push_back(S.begin[c] + off);
-            hp.chunk_count.push_back(std::min<int64_t>(prm.chunk_size, S.count[c] - off));
-        }
-        hp.slot_chunk_off[s + 1] = static_cast<int32_t>(hp.chunk_slot.size());
-        const int32_t c0 = hp.slot_chunk_off[s], c1 = hp.slot_chunk_off[s + 1];
-        for (int32_t c = c0; c < c1; ++c)
-            hp.chunk_dst.push_back(c1 - c0 == 1 ? s : nslots + hp.npartial++);
-    }
+    for (int64_t s = 0; s < nslots; ++s)
+        hp.upward_terms += S.count[hp.slot_cluster[s]] * hp.P;
+    upward_chunks(S, hp.slot_cluster, prm.chunk_size, hp.chunk_slot, hp.chunk_begin, hp.chunk_count,
+                  hp.slot_chunk_off, hp.chunk_dst, hp.npartial);
 
     group_schedule(hp.batch_begin, hp.batch_count, hp.batch_cost, prm.group_size, prm.xcds,
                    hp.group_batch, hp.group_first);
@@ -580,20 +597,9 @@ void cp_plan_from_trees(CpPlan& cp)
             cp.slot_cluster.push_back(static_cast<int32_t>(c));
         }
     const int64_t nslots = static_cast<int64_t>(cp.slot_cluster.size());
-    const int32_t np = cp.np;
-    cp.slot_nodes.resize(nslots * 3 * np);
-    for (int64_t sl = 0; sl < nslots; ++sl) {
-        const int32_t c = cp.slot_cluster[sl];
-        for (int l = 0; l < 3; ++l) {
-            const double a = T.lo[3 * c + l], bb = T.hi[3 * c + l];
-            const double mid = (a + bb) / 2.0;
-            const double h = (bb - a) / 2.0;
-            for (int32_t k = 0; k < np; ++k)
-                cp.slot_nodes[(sl * 3 + l) * np + k] =
-                    mid + h * std::cos(M_PI * static_cast<double>(k) / static_cast<double>(prm.degree));
-        }
-        cp.interp_terms += T.count[c] * cp.P;
-    }
+    grid_nodes(T, cp.slot_cluster, prm.degree, cp.slot_nodes);
+    for (int64_t sl = 0; sl < nslots; ++sl)
+        cp.interp_terms += T.count[cp.slot_cluster[sl]] * cp.P;
 
     // ---- proxy lists: per slot, its source batches in batch order
     cp.pf_off.assign(nslots + 1, 0);
@@ -691,6 +697,252 @@ void make_cp_plan(CpPlan& cp, const PlanParams& prm,
         build_tree(cp.src, ns, sx, sy, sz, prm.batch_size);
     cp_plan_from_trees(cp);
     cp.setup_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------------------
+// Cluster-cluster treecode (both sides interpolated)
+// ---------------------------------------------------------------------------
+void cc_plan_from_trees(CcPlan& cc)
+{
+    const PlanParams& prm = cc.prm;
+    cc.np = prm.degree + 1;
+    cc.P = static_cast<int64_t>(cc.np) * cc.np * cc.np;
+    const Tree& T = cc.tgt;
+    const Tree& S = cc.src;
+    const int64_t P = cc.P;
+    const int64_t nnt = T.nodes(), nns = S.nodes();
+
+    // ---- dual walk (explicit stack, children pushed in reverse: the visiting
+    // order of the recursive walk)
+    if (nnt > 0 && nns > 0) {
+        std::vector<std::pair<int32_t, int32_t>> stack{{0, 0}};
+        while (!stack.empty()) {
+            const int32_t t = stack.back().first, s = stack.back().second;
+            stack.pop_back();
+            const double dx = T.center[3 * t] - S.center[3 * s];
+            const double dy = T.center[3 * t + 1] - S.center[3 * s + 1];
+            const double dz = T.center[3 * t + 2] - S.center[3 * s + 2];
+            const double R = std::sqrt(dx * dx + dy * dy + dz * dz);
+            int32_t kind = -1;
+            if (T.radius[t] + S.radius[s] < prm.theta * R) {
+                const bool bt = P < T.count[t], bs = P < S.count[s];
+                kind = bt && bs ? 0 : (bs ? 1 : (bt ? 2 : 3));
+            } else if (T.nchild[t] == 0 && S.nchild[s] == 0) {
+                kind = 3;
+            }
+            if (kind >= 0) {
+                cc.pair_t.push_back(t);
+                cc.pair_s.push_back(s);
+                cc.pair_kind.push_back(kind);
+                ++cc.kind_pairs[kind];
+                continue;
+            }
+            bool split_t, split_s;
+            if (S.nchild[s] == 0) {
+                split_t = true;
+                split_s = false;
+            } else if (T.nchild[t] == 0) {
+                split_t = false;
+                split_s = true;
+            } else if (T.radius[t] > S.radius[s]) {
+                split_t = true;
+                split_s = false;
+            } else if (S.radius[s] > T.radius[t]) {
+                split_t = false;
+                split_s = true;
+            } else {
+                split_t = split_s = true;
+            }
+            const int32_t nkt = split_t ? T.nchild[t] : 1, nks = split_s ? S.nchild[s] : 1;
+            for (int32_t a = nkt - 1; a >= 0; --a)
+                for (int32_t b = nks - 1; b >= 0; --b)
+                    stack.emplace_back(split_t ? T.first_child[t] + a : t,
+                                       split_s ? S.first_child[s] + b : s);
+        }
+    }
+    const int64_t npairs = static_cast<int64_t>(cc.pair_t.size());
+
+    // ---- slots on both sides
+    cc.cluster_sslot.assign(nns, -1);
+    cc.cluster_tslot.assign(nnt, -1);
+    {
+        std::vector<uint8_t> us(nns, 0), ut(nnt, 0);
+        for (int64_t k = 0; k < npairs; ++k) {
+            if (cc.pair_kind[k] <= 1)
+                us[cc.pair_s[k]] = 1;
+            if (cc.pair_kind[k] == 0 || cc.pair_kind[k] == 2)
+                ut[cc.pair_t[k]] = 1;
+        }
+        for (int64_t c = 0; c < nns; ++c)
+            if (us[c]) {
+                cc.cluster_sslot[c] = static_cast<int32_t>(cc.sslot_cluster.size());
+                cc.sslot_cluster.push_back(static_cast<int32_t>(c));
+            }
+        for (int64_t c = 0; c < nnt; ++c)
+            if (ut[c]) {
+                cc.cluster_tslot[c] = static_cast<int32_t>(cc.tslot_cluster.size());
+                cc.tslot_cluster.push_back(static_cast<int32_t>(c));
+            }
+    }
+    const int64_t nts = static_cast<int64_t>(cc.tslot_cluster.size());
+    grid_nodes(S, cc.sslot_cluster, prm.degree, cc.sslot_nodes);
+    grid_nodes(T, cc.tslot_cluster, prm.degree, cc.tslot_nodes);
+    for (int32_t c : cc.sslot_cluster)
+        cc.upward_terms += S.count[c] * P;
+    for (int32_t c : cc.tslot_cluster)
+        cc.interp_terms += T.count[c] * P;
+    upward_chunks(S, cc.sslot_cluster, prm.chunk_size, cc.chunk_slot, cc.chunk_begin, cc.chunk_count,
+                  cc.slot_chunk_off, cc.chunk_dst, cc.npartial);
+
+    // leaf runs: the leaves below a node, in depth-first order
+    std::vector<int32_t> s_leaves, t_leaves;
+    std::vector<int64_t> s_lo, s_hi, t_lo, t_hi;
+    leaf_runs(S, s_leaves, s_lo, s_hi);
+    leaf_runs(T, t_leaves, t_lo, t_hi);
+    leaves_by_begin(T, cc.tl_node, cc.tl_begin, cc.tl_count);     // equals t_leaves
+    const int64_t ntl = static_cast<int64_t>(cc.tl_node.size());
+
+    // ---- proxy lists per target slot (pairs in walk order)
+    std::vector<int64_t> npf(nts, 0);
+    for (int64_t k = 0; k < npairs; ++k) {
+        const int32_t kind = cc.pair_kind[k];
+        if (kind == 0)
+            npf[cc.cluster_tslot[cc.pair_t[k]]] += 1;
+        else if (kind == 2)
+            npf[cc.cluster_tslot[cc.pair_t[k]]] += s_hi[cc.pair_s[k]] - s_lo[cc.pair_s[k]];
+    }
+    cc.pf_off.assign(nts + 1, 0);
+    for (int64_t u = 0; u < nts; ++u) {
+        const int64_t v = cc.pf_off[u] + npf[u];
+        if (v > INT32_MAX)
+            throw std::length_error("proxy lists exceed 2^31 entries");
+        cc.pf_off[u + 1] = static_cast<int32_t>(v);
+    }
+    cc.pf_leaf.resize(cc.pf_off[nts]);
+    cc.pf_begin.resize(cc.pf_off[nts]);
+    cc.pf_count.resize(cc.pf_off[nts]);
+    cc.pf_cost.assign(nts, 0);
+    {
+        std::vector<int64_t> fill(cc.pf_off.begin(), cc.pf_off.end() - 1);
+        for (int64_t k = 0; k < npairs; ++k) {
+            const int32_t kind = cc.pair_kind[k], t = cc.pair_t[k], s = cc.pair_s[k];
+            if (kind == 0) {
+                const int32_t u = cc.cluster_tslot[t], ss = cc.cluster_sslot[s];
+                const int64_t e = fill[u]++;
+                cc.pf_leaf[e] = static_cast<int32_t>(nns + ss);
+                cc.pf_begin[e] = S.n + ss * P;
+                cc.pf_count[e] = P;
+                cc.pf_cost[u] += P;
+                cc.cc_evals += P * P;
+            } else if (kind == 2) {
+                const int32_t u = cc.cluster_tslot[t];
+                for (int64_t r = s_lo[s]; r < s_hi[s]; ++r) {
+                    const int32_t lf = s_leaves[r];
+                    const int64_t e = fill[u]++;
+                    cc.pf_leaf[e] = lf;
+                    cc.pf_begin[e] = S.begin[lf];
+                    cc.pf_count[e] = S.count[lf];
+                }
+                cc.pf_cost[u] += S.count[s];
+                cc.cp_evals += P * S.count[s];
+            }
+        }
+    }
+
+    // ---- per target leaf: particle-cluster slots and direct ranges of the
+    // pairs of every cluster on its path (pairs in walk order)
+    std::vector<int64_t> nfar(ntl, 0), nnear(ntl, 0);
+    for (int64_t k = 0; k < npairs; ++k) {
+        const int32_t kind = cc.pair_kind[k], t = cc.pair_t[k], s = cc.pair_s[k];
+        if (kind != 1 && kind != 3)
+            continue;
+        for (int64_t r = t_lo[t]; r < t_hi[t]; ++r) {
+            if (kind == 1)
+                ++nfar[r];
+            else
+                nnear[r] += s_hi[s] - s_lo[s];
+        }
+        if (kind == 1)
+            cc.pc_evals += T.count[t] * P;
+        else
+            cc.near_evals += T.count[t] * S.count[s];
+    }
+    cc.far_off.assign(ntl + 1, 0);
+    cc.dn_off.assign(ntl + 1, 0);
+    for (int64_t r = 0; r < ntl; ++r) {
+        const int64_t f = cc.far_off[r] + nfar[r], d = cc.dn_off[r] + nnear[r];
+        if (f > INT32_MAX || d > INT32_MAX)
+            throw std::length_error("interaction lists exceed 2^31 entries");
+        cc.far_off[r + 1] = static_cast<int32_t>(f);
+        cc.dn_off[r + 1] = static_cast<int32_t>(d);
+    }
+    cc.far_slot.resize(cc.far_off[ntl]);
+    cc.dn_leaf.resize(cc.dn_off[ntl]);
+    cc.dn_begin.resize(cc.dn_off[ntl]);
+    cc.dn_count.resize(cc.dn_off[ntl]);
+    cc.dn_cost.assign(ntl, 0);
+    {
+        std::vector<int64_t> ff(cc.far_off.begin(), cc.far_off.end() - 1);
+        std::vector<int64_t> fd(cc.dn_off.begin(), cc.dn_off.end() - 1);
+        for (int64_t k = 0; k < npairs; ++k) {
+            const int32_t kind = cc.pair_kind[k], t = cc.pair_t[k], s = cc.pair_s[k];
+            if (kind != 1 && kind != 3)
+                continue;
+            for (int64_t r = t_lo[t]; r < t_hi[t]; ++r) {
+                if (kind == 1) {
+                    cc.far_slot[ff[r]++] = cc.cluster_sslot[s];
+                    cc.dn_cost[r] += P;
+                } else {
+                    for (int64_t q = s_lo[s]; q < s_hi[s]; ++q) {
+                        const int32_t lf = s_leaves[q];
+                        const int64_t e = fd[r]++;
+                        cc.dn_leaf[e] = lf;
+                        cc.dn_begin[e] = S.begin[lf];
+                        cc.dn_count[e] = S.count[lf];
+                    }
+                    cc.dn_cost[r] += S.count[s];
+                }
+            }
+        }
+    }
+
+    // ---- interpolation lists
+    cc.dw_off.assign(ntl + 1, 0);
+    for (int64_t r = 0; r < ntl; ++r) {
+        std::vector<int32_t> path;
+        for (int32_t u = cc.tl_node[r]; u >= 0; u = T.parent[u])
+            if (cc.cluster_tslot[u] >= 0)
+                path.push_back(cc.cluster_tslot[u]);
+        std::reverse(path.begin(), path.end());
+        cc.dw_slot.insert(cc.dw_slot.end(), path.begin(), path.end());
+        cc.dw_off[r + 1] = static_cast<int32_t>(cc.dw_slot.size());
+        cc.dn_cost[r] += static_cast<int64_t>(path.size()) * P;
+    }
+
+    // ---- workgroups
+    std::vector<int64_t> pbegin(nts), pcount(nts, P);
+    for (int64_t u = 0; u < nts; ++u)
+        pbegin[u] = u * P;
+    group_schedule(pbegin, pcount, cc.pf_cost, prm.group_size, prm.xcds, cc.pg_batch, cc.pg_first);
+    group_schedule(cc.tl_begin, cc.tl_count, cc.dn_cost, prm.group_size, prm.xcds, cc.dg_batch,
+                   cc.dg_first);
+}
+
+void make_cc_plan(CcPlan& cc, const PlanParams& prm,
+                  int64_t nt, const double* tx, const double* ty, const double* tz,
+                  int64_t ns, const double* sx, const double* sy, const double* sz)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    cc = CcPlan();
+    cc.prm = prm;
+    build_tree(cc.src, ns, sx, sy, sz, prm.leaf_size);
+    if (nt == ns && tx == sx && ty == sy && tz == sz && prm.batch_size == prm.leaf_size)
+        cc.tgt = cc.src;
+    else
+        build_tree(cc.tgt, nt, tx, ty, tz, prm.batch_size);
+    cc_plan_from_trees(cc);
+    cc.setup_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 

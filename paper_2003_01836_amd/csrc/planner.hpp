@@ -120,6 +120,16 @@ void leaf_runs(const Tree& S, std::vector<int32_t>& leaf_list, std::vector<int64
                std::vector<int64_t>& run_hi);
 // slots (clusters with modified charges, ascending id) from per-cluster flags;
 void plan_slots(HostPlan& hp, const std::vector<uint8_t>& used);
+// Chebyshev points out[slot][3][n+1] of the boxes of the listed clusters
+// (c + h cos(pi k / n), k = 0 at the upper end);
+void grid_nodes(const Tree& t, const std::vector<int32_t>& clusters, int32_t degree,
+                std::vector<double>& out);
+// upward-pass chunks (<= chunk_size sources) of the listed clusters: chunk_dst
+// is the slot of a single-chunk cluster, else nslots + a partial row index;
+void upward_chunks(const Tree& S, const std::vector<int32_t>& slot_cluster, int64_t chunk_size,
+                   std::vector<int32_t>& chunk_slot, std::vector<int64_t>& chunk_begin,
+                   std::vector<int64_t>& chunk_count, std::vector<int32_t>& slot_chunk_off,
+                   std::vector<int64_t>& chunk_dst, int64_t& npartial);
 // upward-pass chunks and the interaction workgroup schedule (needs the slots,
 // batch counts and batch_cost).
 void plan_schedule(HostPlan& hp);
@@ -182,6 +192,71 @@ void cp_plan_from_trees(CpPlan& cp);
 
 // Host planning of the cluster-particle treecode from host coordinates.
 void make_cp_plan(CpPlan& cp, const PlanParams& prm,
+                  int64_t nt, const double* tx, const double* ty, const double* tz,
+                  int64_t ns, const double* sx, const double* sy, const double* sz);
+
+// ---------------------------------------------------------------------------
+// Cluster-cluster treecode: both sides interpolated.  Sources form a tree of
+// capacity leaf_size (modified charges), targets a tree of capacity
+// batch_size (proxy potentials).  A dual walk from the roots accepts pairs
+// with the MAC of eq. 13 and approximates every side larger than (n+1)^3:
+// kind 0 cluster-cluster, 1 particle-cluster, 2 cluster-particle, 3 direct.
+// Rejected pairs split the larger non-leaf cluster (both when the radii are
+// equal) until two leaves meet, which are summed directly.
+// ---------------------------------------------------------------------------
+struct CcPlan {
+    PlanParams prm;
+    int32_t np = 0;
+    int64_t P = 0;
+    Tree tgt, src;
+
+    // pairs in walk order
+    std::vector<int32_t> pair_t, pair_s, pair_kind;
+
+    // source slots: source clusters in kind 0 or 1 pairs (ascending id), their
+    // grids and upward-pass chunks
+    std::vector<int32_t> sslot_cluster, cluster_sslot;
+    std::vector<double> sslot_nodes;
+    std::vector<int32_t> chunk_slot, slot_chunk_off;
+    std::vector<int64_t> chunk_begin, chunk_count, chunk_dst;
+    int64_t npartial = 0;
+
+    // target slots: target clusters in kind 0 or 2 pairs (ascending id)
+    std::vector<int32_t> tslot_cluster, cluster_tslot;
+    std::vector<double> tslot_nodes;
+
+    // proxy potentials, per target slot: ranges of the source array, which
+    // holds the ns particles followed by the grids of the source slots
+    // (P points each); pf_leaf is the source leaf of a particle range and
+    // nodes + source slot for a grid
+    std::vector<int32_t> pf_off, pf_leaf;
+    std::vector<int64_t> pf_begin, pf_count, pf_cost;
+
+    // target leaves ordered by first position; per leaf the particle-cluster
+    // source slots and the direct source ranges of every cluster on its path
+    std::vector<int32_t> tl_node;
+    std::vector<int64_t> tl_begin, tl_count;
+    std::vector<int32_t> far_off, far_slot;
+    std::vector<int32_t> dn_off, dn_leaf;
+    std::vector<int64_t> dn_begin, dn_count, dn_cost;
+    // interpolation: per target leaf, the target slots on its path (root first)
+    std::vector<int32_t> dw_off, dw_slot;
+
+    // workgroups: over proxy points (batch = target slot) and over target leaves
+    std::vector<int32_t> pg_batch, dg_batch;
+    std::vector<int64_t> pg_first, dg_first;
+
+    int64_t kind_pairs[4] = {0, 0, 0, 0};
+    int64_t cc_evals = 0, pc_evals = 0, cp_evals = 0, near_evals = 0;
+    int64_t upward_terms = 0, interp_terms = 0;
+    double setup_seconds = 0.0;
+};
+
+// Everything after the two trees (cc.prm, cc.tgt, cc.src set).
+void cc_plan_from_trees(CcPlan& cc);
+
+// Host planning of the cluster-cluster treecode from host coordinates.
+void make_cc_plan(CcPlan& cc, const PlanParams& prm,
                   int64_t nt, const double* tx, const double* ty, const double* tz,
                   int64_t ns, const double* sx, const double* sy, const double* sz);
 
