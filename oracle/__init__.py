@@ -26,6 +26,9 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 COULOMB = 0
 YUKAWA = 1
+# regularized Coulomb 1/sqrt(r^2 + delta^2): delta is passed as `kappa` (the
+# kernel parameter) to every function of this module
+REGULARIZED = 2
 
 _lib = None
 

@@ -10,7 +10,8 @@
  * What it computes (Vaughn, Wilson, Krasny, "A GPU-Accelerated Barycentric
  * Lagrange Treecode", 2020):
  *   - the direct sum phi_i = sum_j G(x_i, y_j) q_j                 (Sec. II, eq. 1)
- *     with G = 1/r (Coulomb) or exp(-kappa r)/r (Yukawa)             (eq. 2);
+ *     with G = 1/r (Coulomb) or exp(-kappa r)/r (Yukawa)             (eq. 2),
+ *     or the regularized Coulomb kernel 1/sqrt(r^2 + delta^2);
  *   - the BLTC of Alg. 1: source-cluster tree and target batches
  *     (Sec. II-D), modified charges on each cluster's tensor grid of
  *     Chebyshev points of the 2nd kind (eqs. 4-7, 12) with the
@@ -38,7 +39,9 @@
  *   R10 nodes s_k = c + h cos(pi k / n), h = (hi - lo)/2, k = 0..n (k = 0 at
  *       the upper end), weights w_k = (-1)^k delta_k;
  *   R11 modified charges are formed for every cluster that appears in some
- *       approximation list (the same values Alg. 1 forms for all clusters).
+ *       approximation list (the same values Alg. 1 forms for all clusters);
+ *   R24 the regularized Coulomb kernel 1/sqrt(r^2 + delta^2) follows R1 as
+ *       well (pairs at exactly zero distance are skipped).
  *
  * Floating point: plain FP64, compiled without contraction so that the tree
  * and MAC decisions follow the formulas above operation by operation.
@@ -54,6 +57,7 @@
 
 #define ORACLE_COULOMB 0
 #define ORACLE_YUKAWA 1
+#define ORACLE_REGULARIZED 2
 
 static double wall_seconds(void)
 {
@@ -74,12 +78,18 @@ int oracle_max_threads(void)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Kernel G(x, y), eq. (2).                                                   */
+/* Kernel G(x, y) as a function of r = |x - y|: Coulomb 1/r and Yukawa        */
+/* exp(-kappa r)/r (eq. 2).  The method needs only kernel values (Sec. II),   */
+/* so any kernel smooth away from r = 0 and not oscillatory fits; the         */
+/* regularized Coulomb kernel 1/sqrt(r^2 + delta^2) (reading R24; delta is    */
+/* passed as the kernel parameter in place of kappa) is the third one built.  */
 /* ------------------------------------------------------------------------- */
 static double kernel_of_distance(double r, int kernel, double kappa)
 {
     if (kernel == ORACLE_YUKAWA)
         return exp(-kappa * r) / r;
+    if (kernel == ORACLE_REGULARIZED)
+        return 1.0 / sqrt(r * r + kappa * kappa);
     return 1.0 / r;
 }
 

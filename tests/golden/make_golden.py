@@ -11,6 +11,9 @@ Every value here comes from a closed form evaluated in 40-digit arithmetic
                      at each corner, 3 neighbours at distance 1, 3 at sqrt(2)
                      and 1 at sqrt(3), so phi = 3 G(1) + 3 G(sqrt 2) + G(sqrt 3).
   two_body.txt       Two charges q1, q2 at distance d: phi_1 = G(d) q2.
+  regularized_two_body.txt
+                     The same for the regularized Coulomb kernel
+                     G(d) = (d^2 + delta^2)^(-1/2).
 
 Run:  python tests/golden/make_golden.py
 """
@@ -48,6 +51,14 @@ def main():
             d, q2, kappa = mp.mpf(d), mp.mpf(q2), mp.mpf(kappa)
             f.write(f"{mp.nstr(d, 10)} {mp.nstr(q2, 10)} {mp.nstr(kappa, 10)} "
                     f"{mp.nstr(g(d, kappa) * q2, 25)}\n")
+
+    with open(os.path.join(HERE, "regularized_two_body.txt"), "w") as f:
+        f.write("# two charges at distance d, G = (d^2 + delta^2)^(-1/2): phi_1 = G(d) q2\n")
+        f.write("# d q2 delta phi_1\n")
+        for d, q2, delta in (("0.125", "0.75", "0.01"), ("1.5", "-0.25", "0.5"), ("3", "1", "4")):
+            d, q2, delta = mp.mpf(d), mp.mpf(q2), mp.mpf(delta)
+            f.write(f"{mp.nstr(d, 10)} {mp.nstr(q2, 10)} {mp.nstr(delta, 10)} "
+                    f"{mp.nstr(q2 / mp.sqrt(d * d + delta * delta), 25)}\n")
 
 
 if __name__ == "__main__":

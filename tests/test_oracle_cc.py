@@ -26,7 +26,8 @@ def _clouds(nx, ny, seed, shift=0.0):
     return g.uniform(-1, 1, (nx, 3)), g.uniform(-1, 1, (ny, 3)) + shift
 
 
-@pytest.mark.parametrize("kernel,kappa", [(oracle.COULOMB, 0.0), (oracle.YUKAWA, 0.6)])
+@pytest.mark.parametrize("kernel,kappa", [(oracle.COULOMB, 0.0), (oracle.YUKAWA, 0.6),
+                                          (oracle.REGULARIZED, 0.05)])
 @pytest.mark.parametrize("theta,degree,leaf,batch", [(0.7, 3, 150, 200), (0.5, 2, 64, 300),
                                                      (0.9, 4, 400, 100)])
 def test_duality(kernel, kappa, theta, degree, leaf, batch):

@@ -22,7 +22,8 @@ def _clouds(nx, ny, seed, shift=0.0):
     return g.uniform(-1, 1, (nx, 3)), g.uniform(-1, 1, (ny, 3)) + shift
 
 
-@pytest.mark.parametrize("kernel,kappa", [(oracle.COULOMB, 0.0), (oracle.YUKAWA, 0.7)])
+@pytest.mark.parametrize("kernel,kappa", [(oracle.COULOMB, 0.0), (oracle.YUKAWA, 0.7),
+                                          (oracle.REGULARIZED, 0.05)])
 @pytest.mark.parametrize("theta,degree,leaf,batch", [(0.7, 4, 200, 150), (0.5, 3, 90, 300),
                                                      (0.9, 6, 400, 64)])
 def test_duality_with_bltc(kernel, kappa, theta, degree, leaf, batch):

@@ -131,7 +131,32 @@ def test_direct_two_body_golden():
         assert phi[0] == pytest.approx(phi_ref, rel=1e-15)
 
 
-@pytest.mark.parametrize("kernel,kappa", [(oracle.COULOMB, 0.0), (oracle.YUKAWA, 0.5)])
+def test_direct_regularized_two_body_golden():
+    for d, q2, delta, phi_ref in read_golden("regularized_two_body.txt"):
+        pts = np.array([[0.0, 0.0, 0.0], [0.0, d, 0.0]])
+        phi = oracle.direct(pts, pts, np.array([0.3, q2]), kernel=oracle.REGULARIZED, kappa=delta)
+        assert phi[0] == pytest.approx(phi_ref, rel=1e-15)
+
+
+def test_regularized_kernel_limits():
+    g = np.random.default_rng(5)
+    t = g.uniform(-1, 1, (50, 3))
+    s = g.uniform(-1, 1, (300, 3))
+    q = g.uniform(-1, 1, 300)
+    # delta -> 0: the Coulomb kernel (delta^2 underflows next to r^2)
+    assert np.array_equal(oracle.direct(t, s, q, kernel=oracle.REGULARIZED, kappa=1e-200),
+                          oracle.direct(t, s, q, kernel=oracle.COULOMB))
+    # delta >> r: G -> 1/delta, phi -> sum(q)/delta with relative error <= (r/delta)^2 / 2
+    phi = oracle.direct(t, s, q, kernel=oracle.REGULARIZED, kappa=1e4)
+    assert np.allclose(phi * 1e4, q.sum(), rtol=0, atol=np.abs(q).sum() * 12 / 2e8)
+    # below the Coulomb value everywhere for positive charges
+    pos = np.abs(q)
+    assert np.all(oracle.direct(t, s, pos, kernel=oracle.REGULARIZED, kappa=0.1) <
+                  oracle.direct(t, s, pos, kernel=oracle.COULOMB))
+
+
+@pytest.mark.parametrize("kernel,kappa", [(oracle.COULOMB, 0.0), (oracle.YUKAWA, 0.5),
+                                          (oracle.REGULARIZED, 0.05)])
 def test_direct_vs_high_precision(kernel, kappa):
     g = np.random.default_rng(3)
     t = g.uniform(-1, 1, (7, 3))
@@ -143,7 +168,10 @@ def test_direct_vs_high_precision(kernel, kappa):
             acc = mp.mpf(0)
             for j in range(40):
                 r = mp.sqrt(sum((mp.mpf(t[i, c]) - mp.mpf(s[j, c])) ** 2 for c in range(3)))
-                acc += mp.e ** (-mp.mpf(kappa) * r) / r * mp.mpf(q[m, j])
+                if kernel == oracle.REGULARIZED:
+                    acc += mp.mpf(q[m, j]) / mp.sqrt(r * r + mp.mpf(kappa) ** 2)
+                else:
+                    acc += mp.e ** (-mp.mpf(kappa) * r) / r * mp.mpf(q[m, j])
             assert phi[m, i] == pytest.approx(float(acc), rel=1e-13, abs=1e-14)
 
 
@@ -423,7 +451,8 @@ def test_large_degree_means_all_direct():
     assert oracle.rel_l2(d, p) < 1e-14
 
 
-@pytest.mark.parametrize("kernel,kappa", [(oracle.COULOMB, 0.0), (oracle.YUKAWA, 0.5)])
+@pytest.mark.parametrize("kernel,kappa", [(oracle.COULOMB, 0.0), (oracle.YUKAWA, 0.5),
+                                          (oracle.REGULARIZED, 0.02)])
 def test_error_decreases_with_degree(kernel, kappa):
     pos, q = inputs.uniform_cube(12000, 41)
     d = oracle.direct(pos, pos, q[0], kernel=kernel, kappa=kappa)
