@@ -305,6 +305,16 @@ def run_variant(args, dev):
             "approx_evals": st["far_evals"], "near_evals": st["near_evals"],
             "interp_terms": st["upward_terms"],
             "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"]}
+        # the interaction launches (proxy potentials, direct sums and, for the
+        # cluster-cluster method, grid-grid and grid-targets pairs) are bound by
+        # VALU issue; the phases also hold the small upward / interpolation work
+        t_int = (ph["upward"] + ph["interact"]) * 1e-3
+        ach = (st["far_evals"] + st["near_evals"]) * FLOPS_COULOMB / t_int / 1e12
+        peak = FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+        res["paths"][prec]["roofline"] = {
+            "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+            "traffic": None, "kernel": "interact (proxy + targets launches)",
+            "flops_per_eval": FLOPS_COULOMB}
         log(f"{method} {prec}: {ms:.2f} ms/step, phases {ph}")
         del plan
     if not args.no_cpu:

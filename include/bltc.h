@@ -3,6 +3,8 @@
  *
  * The library evaluates potentials
  *     phi(x_i) = sum_j G(x_i, y_j) q_j,  G = 1/r (Coulomb) or exp(-kappa r)/r (Yukawa)
+ * or, since the method needs only kernel values, 1/sqrt(r^2 + delta^2)
+ * (regularized Coulomb)
  * (Vaughn, Wilson, Krasny 2020, Sec. II, eqs. 1-2) with the barycentric Lagrange
  * treecode of Alg. 1: a tree of source clusters and a set of target batches
  * (Sec. II-D), modified charges on each cluster's (n+1)^3 tensor grid of
@@ -50,7 +52,13 @@ typedef enum {
     BLTC_EINTERNAL = -5      /* internal consistency check failed                    */
 } bltc_status;
 
-typedef enum { BLTC_COULOMB = 0, BLTC_YUKAWA = 1 } bltc_kernel;
+/* Kernels (eq. 2 and one more smooth, non-oscillatory example): pairs at
+ * exactly zero distance are skipped for all of them. */
+typedef enum {
+    BLTC_COULOMB = 0,              /* 1/r                                     */
+    BLTC_YUKAWA = 1,               /* exp(-kappa r)/r                         */
+    BLTC_REGULARIZED_COULOMB = 2   /* 1/sqrt(r^2 + delta^2)                   */
+} bltc_kernel;
 
 /* Arithmetic of the evaluation.
  *  BLTC_FP64        every step in FP64.
@@ -101,10 +109,11 @@ typedef struct {
     int32_t batch_size;          /* N_B >= 1: capacity of the batches of the other side */
     int32_t threads_per_target;  /* 0 or 1 (reserved for split target evaluation)      */
     int32_t method;              /* bltc_method                                         */
+    double delta;                /* BLTC_REGULARIZED_COULOMB length, >= 0               */
 } bltc_params;
 
 /* Fills *p with the defaults: Coulomb, FP64, theta 0.7, degree 8,
- * N_L = N_B = 2000, BLTC_PARTICLE_CLUSTER. */
+ * N_L = N_B = 2000, BLTC_PARTICLE_CLUSTER, kappa = delta = 0. */
 void bltc_params_default(bltc_params* p);
 
 /* One-shot evaluation (Alg. 1): builds the tree, batches and interaction lists

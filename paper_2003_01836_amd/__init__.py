@@ -20,7 +20,7 @@ from ._capi import BLTCError, InvalidArgument  # noqa: F401
 __all__ = ["params", "Plan", "Batch", "autotune", "potential", "direct", "BLTCError", "InvalidArgument",
            "library_path", "version"]
 
-_KERNELS = {"coulomb": _capi.COULOMB, "yukawa": _capi.YUKAWA}
+_KERNELS = {"coulomb": _capi.COULOMB, "yukawa": _capi.YUKAWA, "regularized": _capi.REGULARIZED}
 _PRECISIONS = {"fp64": _capi.FP64, "fp32_mixed": _capi.FP32_MIXED, "mixed": _capi.FP32_MIXED}
 # "bltc": the paper's particle-cluster treecode (sources interpolated);
 # "cp": cluster-particle (targets interpolated); "cc": cluster-cluster (both)
@@ -38,7 +38,7 @@ def version() -> str:
 
 
 def params(kernel="coulomb", kappa=0.0, theta=0.7, degree=8, leaf_size=2000, batch_size=2000,
-           precision="fp64", threads_per_target=0, method="bltc") -> _capi.Params:
+           precision="fp64", threads_per_target=0, method="bltc", delta=0.0) -> _capi.Params:
     p = _capi.Params()
     _capi.load().bltc_params_default(ctypes.byref(p))
     p.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
@@ -50,6 +50,7 @@ def params(kernel="coulomb", kappa=0.0, theta=0.7, degree=8, leaf_size=2000, bat
     p.batch_size = int(batch_size)
     p.threads_per_target = int(threads_per_target)
     p.method = _METHODS[method] if isinstance(method, str) else int(method)
+    p.delta = float(delta)
     return p
 
 
@@ -303,11 +304,12 @@ def potential(targets, sources, charges, *, stream=None, out=None, **kw):
     return out[0] if (one and out.dim() == 2) else out
 
 
-def direct(targets, sources, charges, *, stream=None, out=None, kernel="coulomb", kappa=0.0):
+def direct(targets, sources, charges, *, stream=None, out=None, kernel="coulomb", kappa=0.0,
+           delta=0.0):
     """GPU FP64 direct sum of eq. (1) (`bltc_direct`)."""
     torch = _torch()
     lib = _capi.load()
-    p = params(kernel=kernel, kappa=kappa)
+    p = params(kernel=kernel, kappa=kappa, delta=delta)
     nt, tp = _coords_device(targets, "targets")
     ns, sp = _coords_device(sources, "sources")
     q2, one = _charges_device(charges, ns)

@@ -16,6 +16,7 @@ BLTC_EINTERNAL = -5
 
 COULOMB = 0
 YUKAWA = 1
+REGULARIZED = 2
 FP64 = 0
 FP32_MIXED = 1
 PARTICLE_CLUSTER = 0
@@ -43,6 +44,7 @@ class Params(ctypes.Structure):
         ("batch_size", ctypes.c_int32),
         ("threads_per_target", ctypes.c_int32),
         ("method", ctypes.c_int32),
+        ("delta", ctypes.c_double),
     ]
 
 

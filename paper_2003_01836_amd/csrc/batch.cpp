@@ -109,6 +109,7 @@ int bltc_batch_create(bltc_batch** out, bltc_plan* const* plans, int32_t count, 
     b->kp.kernel = plans[0]->prm.kernel;
     b->kp.precision = plans[0]->prm.precision;
     b->kp.kappa = plans[0]->prm.kappa;
+    b->kp.delta = plans[0]->prm.delta;
 
     // work-queue units: every non-empty group of every system, heaviest first
     struct Unit { int32_t sys, group; int64_t cost; };
@@ -212,8 +213,13 @@ int bltc_batch_execute(bltc_batch* b, const double* const* q, const int32_t* num
     if (key != b->key) {
         // new caller buffers: refresh the per-system descriptors, drop the graph
         std::vector<bltc::MrhsDesc> descs(count);
-        for (int32_t i = 0; i < count; ++i)
-            descs[i] = bltc::make_mrhs_desc(b->plans[i]->d, b->kp, phi[i], phi_ld[i], num_q[i]);
+        for (int32_t i = 0; i < count; ++i) {
+            // kernel constants per system (the kernel itself is shared)
+            bltc::KernelParams kpi = b->kp;
+            kpi.kappa = b->plans[i]->prm.kappa;
+            kpi.delta = b->plans[i]->prm.delta;
+            descs[i] = bltc::make_mrhs_desc(b->plans[i]->d, kpi, phi[i], phi_ld[i], num_q[i]);
+        }
         HIP_TRY(hipStreamSynchronize(s));
         HIP_TRY(hipMemcpy(b->d_descs, descs.data(), sizeof(bltc::MrhsDesc) * count,
                           hipMemcpyHostToDevice));

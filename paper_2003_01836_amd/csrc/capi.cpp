@@ -26,12 +26,16 @@ int check_params(const bltc_params* p)
 {
     if (!p)
         return fail(BLTC_EINVAL, "params is NULL");
-    if (p->kernel != BLTC_COULOMB && p->kernel != BLTC_YUKAWA)
-        return fail(BLTC_EINVAL, "kernel must be BLTC_COULOMB or BLTC_YUKAWA");
+    if (p->kernel != BLTC_COULOMB && p->kernel != BLTC_YUKAWA &&
+        p->kernel != BLTC_REGULARIZED_COULOMB)
+        return fail(BLTC_EINVAL,
+                    "kernel must be BLTC_COULOMB, BLTC_YUKAWA or BLTC_REGULARIZED_COULOMB");
     if (p->precision != BLTC_FP64 && p->precision != BLTC_FP32_MIXED)
         return fail(BLTC_EINVAL, "precision must be BLTC_FP64 or BLTC_FP32_MIXED");
     if (!(p->kappa >= 0.0) || !std::isfinite(p->kappa))
         return fail(BLTC_EINVAL, "kappa must be finite and >= 0");
+    if (!(p->delta >= 0.0) || !std::isfinite(p->delta))
+        return fail(BLTC_EINVAL, "delta must be finite and >= 0");
     if (!(p->theta >= 0.0 && p->theta < 1.0))
         return fail(BLTC_EINVAL, "theta must satisfy 0 <= theta < 1");
     if (p->degree < 1 || p->degree > bltc::kMaxDegree)
@@ -339,6 +343,7 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
     kp.kernel = plan->prm.kernel;
     kp.precision = plan->prm.precision;
     kp.kappa = plan->prm.kappa;
+    kp.delta = plan->prm.delta;
     bltc::DevicePlan d = plan->d;
     // one charge vector: the scalar-charge kernels; several: passes of up to 16
     // vectors whose kernel values are shared (matrix-core contraction)
@@ -458,6 +463,7 @@ void bltc_params_default(bltc_params* p)
     p->batch_size = 2000;
     p->threads_per_target = 0;
     p->method = BLTC_PARTICLE_CLUSTER;
+    p->delta = 0.0;
 }
 
 int bltc_plan_create_host(bltc_plan** out, const bltc_params* p, int64_t nt, const double* tx,
@@ -744,6 +750,7 @@ int bltc_direct(const bltc_params* p, int64_t nt, const double* tx, const double
     bltc::KernelParams kp;
     kp.kernel = p->kernel;
     kp.kappa = p->kappa;
+    kp.delta = p->delta;
     hipError_t e = hipSuccess;
     for (int32_t m = 0; m < num_q && e == hipSuccess; ++m) {
         e = bltc::launch_pack_sources(ns, sx, sy, sz, q + static_cast<int64_t>(m) * q_ld, packed, s);

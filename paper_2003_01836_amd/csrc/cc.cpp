@@ -302,6 +302,7 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStr
     kp.kernel = plan->prm.kernel;
     kp.precision = plan->prm.precision;
     kp.kappa = plan->prm.kappa;
+    kp.delta = plan->prm.delta;
     const bool mixed = kp.precision == BLTC_FP32_MIXED;
     bltc::DevicePlan& du = plan->d;
     if (plan->timing) {

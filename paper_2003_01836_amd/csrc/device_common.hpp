@@ -64,9 +64,10 @@ constexpr double kLn2Over64Hi = 0x1.62e42fee00000p-7;
 constexpr double kLn2Over64Lo = 0x1.a39ef35793c76p-39;
 constexpr double k64OverLn2 = 92.33248261689366;
 
-struct YukawaArg {
-    double kappa;
-    const double* tab;   // 2^(j/64), j < 64 (LDS)
+struct KernelArg {
+    double kappa;        // Yukawa
+    double delta2;       // regularized Coulomb: delta^2
+    const double* tab;   // 2^(j/64), j < 64 (LDS; Yukawa)
 };
 
 __device__ __forceinline__ void fill_exp2_table(double* tab)
@@ -90,14 +91,59 @@ __device__ __forceinline__ double exp_f64(double x, const double* __restrict__ t
     return ldexp(tab[n & 63] * p, n >> 6);
 }
 
-// G as a function of r^2 and 1/r (eq. 2).
+// G as a function of r^2 (eq. 2; KER 0 Coulomb 1/r, 1 Yukawa exp(-kappa r)/r,
+// 2 regularized Coulomb (r^2 + delta^2)^(-1/2)).  green_far_f64: well-separated
+// points (r > 0), 1/sqrt by one Newton step; green_near_f64: any pair, zero at
+// r = 0 (pairs at zero distance are skipped).
 template <int KER>
-__device__ __forceinline__ double green_f64(double r2, double rinv, const YukawaArg& ya)
+__device__ __forceinline__ double green_far_f64(double r2, const KernelArg& ka)
 {
     if constexpr (KER == 0) {
-        return rinv;
+        return rsqrt_f64_newton(r2);
+    } else if constexpr (KER == 1) {
+        const double rinv = rsqrt_f64_newton(r2);
+        return exp_f64(-ka.kappa * (r2 * rinv), ka.tab) * rinv;
     } else {
-        return exp_f64(-ya.kappa * (r2 * rinv), ya.tab) * rinv;
+        return rsqrt_f64_newton(r2 + ka.delta2);
+    }
+}
+
+template <int KER>
+__device__ __forceinline__ double green_near_f64(double r2, const KernelArg& ka)
+{
+    if constexpr (KER == 0) {
+        return rsqrt_f64_or_zero(r2);
+    } else if constexpr (KER == 1) {
+        const double rinv = rsqrt_f64_or_zero(r2);
+        return exp_f64(-ka.kappa * (r2 * rinv), ka.tab) * rinv;
+    } else {
+        const double g = rsqrt_f64(r2 + ka.delta2);
+        return r2 == 0.0 ? 0.0 : g;
+    }
+}
+
+// FP32 kernel values (FP32-mixed path): nk = -kappa log2(e); r^2 > 0 (pairs at
+// zero distance take the FP64 branch of the mixed near field).
+struct KernelArg32 {
+    float nk;
+    float delta2;
+};
+
+__device__ __forceinline__ KernelArg32 kernel_arg32(double kappa, double delta2)
+{
+    return KernelArg32{static_cast<float>(-kappa * 1.4426950408889634), static_cast<float>(delta2)};
+}
+
+template <int KER>
+__device__ __forceinline__ float green_f32(float r2, const KernelArg32& ka)
+{
+    if constexpr (KER == 0) {
+        return __builtin_amdgcn_rsqf(r2);
+    } else if constexpr (KER == 1) {
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        return __builtin_amdgcn_exp2f(ka.nk * (r2 * rinv)) * rinv;
+    } else {
+        return __builtin_amdgcn_rsqf(r2 + ka.delta2);
     }
 }
 
@@ -107,19 +153,19 @@ __device__ __forceinline__ double green_f64(double r2, double rinv, const Yukawa
 // ---------------------------------------------------------------------------
 template <int KER>
 __device__ __forceinline__ double near_term_f64(double x, double y, double z, const double4 p,
-                                                const YukawaArg& kappa)
+                                                const KernelArg& kappa)
 {
     const double dx = x - p.x;
     const double dy = y - p.y;
     const double dz = z - p.z;
     const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-    return green_f64<KER>(r2, rsqrt_f64_or_zero(r2), kappa) * p.w;
+    return green_near_f64<KER>(r2, kappa) * p.w;
 }
 
 template <int KER>
 __device__ __forceinline__ double near_sum_f64(double x, double y, double z,
                                                const double4* __restrict__ s, int32_t cnt,
-                                               const YukawaArg& kappa)
+                                               const KernelArg& kappa)
 {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int32_t j = 0;

@@ -26,7 +26,7 @@ using namespace dev;
 template <int N, int KER>
 __device__ __forceinline__ double far_sum_f64(double x, double y, double z,
                                               const double* __restrict__ nd,
-                                              const double* __restrict__ qh, const YukawaArg& kappa)
+                                              const double* __restrict__ qh, const KernelArg& kappa)
 {
     constexpr int NP = N + 1;
     double b2[NP], c2[NP];
@@ -49,7 +49,7 @@ __device__ __forceinline__ double far_sum_f64(double x, double y, double z,
 #pragma unroll
             for (int k3 = 0; k3 < NP; ++k3) {
                 const double r2 = ab + c2[k3];
-                const double g = green_f64<KER>(r2, rsqrt_f64_newton(r2), kappa);
+                const double g = green_far_f64<KER>(r2, kappa);
                 if ((k2 + k3) & 1)
                     acc1 = __fma_rn(g, q1[k2 * NP + k3], acc1);
                 else
@@ -71,14 +71,14 @@ __global__ __launch_bounds__(kGroupSize) void interact_f64(
     const int32_t* __restrict__ far_off, const int32_t* __restrict__ far_slot,
     const int32_t* __restrict__ near_off, const int64_t* __restrict__ near_begin,
     const int64_t* __restrict__ near_count, const double* __restrict__ slot_nodes,
-    const double* __restrict__ qhat, double* __restrict__ phi, double kappa_value)
+    const double* __restrict__ qhat, double* __restrict__ phi, KernelConst kc)
 {
     constexpr int NP = N + 1;
     constexpr int P = NP * NP * NP;
     __shared__ double exp_tab[64];
     if constexpr (KER == 1)
         fill_exp2_table(exp_tab);
-    const YukawaArg kappa{kappa_value, exp_tab};
+    const KernelArg kappa{kc.kappa, kc.delta2, exp_tab};
     const int g = blockIdx.x;
     const int b = group_batch[g];
     if (b < 0)
@@ -140,12 +140,12 @@ __global__ __launch_bounds__(256) void direct_f64(int64_t nt, const double* __re
                                                   const double* __restrict__ ty,
                                                   const double* __restrict__ tz, int64_t ns,
                                                   const double4* __restrict__ src,
-                                                  double* __restrict__ phi, double kappa_value)
+                                                  double* __restrict__ phi, KernelConst kc)
 {
     __shared__ double exp_tab[64];
     if constexpr (KER == 1)
         fill_exp2_table(exp_tab);
-    const YukawaArg kappa{kappa_value, exp_tab};
+    const KernelArg kappa{kc.kappa, kc.delta2, exp_tab};
     const int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x;
     if (base + (threadIdx.x & ~63) >= nt)
         return;
@@ -168,14 +168,14 @@ __global__ __launch_bounds__(256) void direct_f64(int64_t nt, const double* __re
 // ---------------------------------------------------------------------------
 
 template <int N, int KER>
-hipError_t run_interact(const DevicePlan& d, double* phi, double kappa, hipStream_t s)
+hipError_t run_interact(const DevicePlan& d, double* phi, KernelConst kc, hipStream_t s)
 {
     if (d.ngroups == 0)
         return hipSuccess;
     hipLaunchKernelGGL((interact_f64<N, KER>), dim3(static_cast<unsigned>(d.ngroups)),
                        dim3(kGroupSize), 0, s, d.tgt, d.tgt_orig, d.src, d.group_batch,
                        d.group_first, d.batch_end, d.far_off, d.far_slot, d.near_off,
-                       d.near_begin, d.near_count, d.slot_nodes, d.qhat, phi, kappa);
+                       d.near_begin, d.near_count, d.slot_nodes, d.qhat, phi, kc);
     return hipGetLastError();
 }
 
@@ -196,12 +196,13 @@ hipError_t launch_gather_charges(const DevicePlan& d, const double* q, hipStream
 hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* phi,
                            hipStream_t s)
 {
-    const bool yuk = kp.kernel == 1;
+    const KernelConst kc = kp.kconst();
     switch (d.degree) {
 #define X(n)                                                                   \
     case n:                                                                    \
-        return yuk ? run_interact<n, 1>(d, phi, kp.kappa, s)                   \
-                   : run_interact<n, 0>(d, phi, kp.kappa, s);
+        return kp.kernel == 1 ? run_interact<n, 1>(d, phi, kc, s)              \
+             : kp.kernel == 2 ? run_interact<n, 2>(d, phi, kc, s)              \
+                              : run_interact<n, 0>(d, phi, kc, s);
         BLTC_DEGREE_CASES(X)
 #undef X
     default:
@@ -226,12 +227,13 @@ hipError_t launch_direct(int64_t nt, const double* tx, const double* ty, const d
     if (nt == 0)
         return hipSuccess;
     const dim3 grid(static_cast<unsigned>((nt + 255) / 256));
+    const KernelConst kc = kp.kconst();
     if (kp.kernel == 1)
-        hipLaunchKernelGGL(direct_f64<1>, grid, dim3(256), 0, s, nt, tx, ty, tz, ns, src, phi,
-                           kp.kappa);
+        hipLaunchKernelGGL(direct_f64<1>, grid, dim3(256), 0, s, nt, tx, ty, tz, ns, src, phi, kc);
+    else if (kp.kernel == 2)
+        hipLaunchKernelGGL(direct_f64<2>, grid, dim3(256), 0, s, nt, tx, ty, tz, ns, src, phi, kc);
     else
-        hipLaunchKernelGGL(direct_f64<0>, grid, dim3(256), 0, s, nt, tx, ty, tz, ns, src, phi,
-                           kp.kappa);
+        hipLaunchKernelGGL(direct_f64<0>, grid, dim3(256), 0, s, nt, tx, ty, tz, ns, src, phi, kc);
     return hipGetLastError();
 }
 

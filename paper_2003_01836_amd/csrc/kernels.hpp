@@ -53,6 +53,13 @@ struct DevicePlan {
     float* qhat16f = nullptr;         // [slot][P][16] (mixed precision)
 };
 
+// Constants of the kernel G passed to the interaction kernels: kappa of the
+// Yukawa kernel and delta^2 of the regularized Coulomb kernel.
+struct KernelConst {
+    double kappa;
+    double delta2;
+};
+
 // Everything the multi-vector interaction of one system needs (passed by value
 // to a kernel, or as an array for the work-queue kernel).
 struct MrhsDesc {
@@ -82,13 +89,15 @@ struct MrhsDesc {
     int64_t phi_ld;
     int32_t np;
     int32_t mc;
-    double kappa;
+    KernelConst kc;
 };
 
 struct KernelParams {
-    int32_t kernel = 0;     // 0 Coulomb, 1 Yukawa
+    int32_t kernel = 0;     // 0 Coulomb, 1 Yukawa, 2 regularized Coulomb
     int32_t precision = 0;  // 0 FP64, 1 FP32-mixed
     double kappa = 0.0;
+    double delta = 0.0;
+    KernelConst kconst() const { return KernelConst{kappa, delta * delta}; }
 };
 
 // src[j].w = q[order[j]] (and src32[j].w when present), j < ns: charges into tree order

@@ -32,26 +32,16 @@ using namespace dev;
 constexpr double kTauRel = BLTC_TAU_REL;
 constexpr int kFlushEvery = 128;
 
-template <int KER>
-__device__ __forceinline__ float green_f32(float r2, float rinv, float neg_kappa_log2e)
-{
-    if constexpr (KER == 0) {
-        return rinv;
-    } else {
-        return __builtin_amdgcn_exp2f(neg_kappa_log2e * (r2 * rinv)) * rinv;
-    }
-}
-
 // FP32 kernel value of one source for a lane's local target coordinates.
 template <int KER>
 __device__ __forceinline__ float near_value_f32(float x, float y, float z, const float4 p,
-                                                float nk, float& r2)
+                                                const KernelArg32& nk, float& r2)
 {
     const float dx = x - p.x;
     const float dy = y - p.y;
     const float dz = z - p.z;
     r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-    return green_f32<KER>(r2, __builtin_amdgcn_rsqf(r2), nk);
+    return green_f32<KER>(r2, nk);
 }
 
 // Sources [j, j+4): FP32 values; if any of them is closer than tau (rare, one
@@ -61,8 +51,9 @@ template <int KER>
 __device__ __forceinline__ void near_quad_mixed(float x, float y, float z,
                                                 const float4* __restrict__ s32,
                                                 const double4* __restrict__ s64, float tau2,
-                                                float nk, double xt, double yt, double zt,
-                                                const YukawaArg& kappa, double& acc, float& a0, float& a1,
+                                                const KernelArg32& nk, double xt, double yt,
+                                                double zt,
+                                                const KernelArg& kappa, double& acc, float& a0, float& a1,
                                                 float& a2, float& a3)
 {
     const float4 p0 = s32[0], p1 = s32[1], p2 = s32[2], p3 = s32[3];
@@ -87,8 +78,9 @@ template <int KER>
 __device__ __forceinline__ double near_sum_mixed(double xt, double yt, double zt,
                                                  const float4* __restrict__ s32,
                                                  const double4* __restrict__ s64, int32_t cnt,
-                                                 const double4 leaf, float tau2, float nk,
-                                                 const YukawaArg& kappa)
+                                                 const double4 leaf, float tau2,
+                                                 const KernelArg32& nk,
+                                                 const KernelArg& kappa)
 {
     const float x = static_cast<float>(xt - leaf.x);
     const float y = static_cast<float>(yt - leaf.y);
@@ -118,7 +110,8 @@ __device__ __forceinline__ double near_sum_mixed(double xt, double yt, double zt
 template <int N, int KER>
 __device__ __forceinline__ double far_sum_mixed(double xt, double yt, double zt,
                                                 const double* __restrict__ nd,
-                                                const float* __restrict__ qh, float nk)
+                                                const float* __restrict__ qh,
+                                                const KernelArg32& nk)
 {
     constexpr int NP = N + 1;
     float b2[NP], c2[NP];
@@ -142,7 +135,7 @@ __device__ __forceinline__ double far_sum_mixed(double xt, double yt, double zt,
 #pragma unroll
             for (int k3 = 0; k3 < NP; ++k3) {
                 const float r2 = ab + c2[k3];
-                const float g = green_f32<KER>(r2, __builtin_amdgcn_rsqf(r2), nk);
+                const float g = green_f32<KER>(r2, nk);
                 if ((k2 + k3) & 1)
                     s1 = __fmaf_rn(g, q1[k2 * NP + k3], s1);
                 else
@@ -164,14 +157,14 @@ __global__ __launch_bounds__(kGroupSize) void interact_mixed(
     const int32_t* __restrict__ far_slot, const int32_t* __restrict__ near_off,
     const int64_t* __restrict__ near_begin, const int64_t* __restrict__ near_count,
     const int32_t* __restrict__ near_leaf, const double* __restrict__ slot_nodes,
-    const float* __restrict__ qhat32, double* __restrict__ phi, double kappa_value)
+    const float* __restrict__ qhat32, double* __restrict__ phi, KernelConst kc)
 {
     constexpr int NP = N + 1;
     constexpr int P = NP * NP * NP;
     __shared__ double exp_tab[64];
     if constexpr (KER == 1)
         fill_exp2_table(exp_tab);
-    const YukawaArg kappa{kappa_value, exp_tab};
+    const KernelArg kappa{kc.kappa, kc.delta2, exp_tab};
     const int g = blockIdx.x;
     const int b = group_batch[g];
     if (b < 0)
@@ -186,7 +179,7 @@ __global__ __launch_bounds__(kGroupSize) void interact_mixed(
     if (!valid)
         i = end - 1;
     const double4 t = tgt[i];
-    const float nk = static_cast<float>(-kappa_value * 1.4426950408889634);
+    const KernelArg32 nk = kernel_arg32(kc.kappa, kc.delta2);
     double acc = 0.0;
 
     const int f_end = far_off[b + 1];
@@ -212,7 +205,7 @@ __global__ __launch_bounds__(kGroupSize) void interact_mixed(
 }
 
 template <int N, int KER>
-hipError_t run_interact_mixed(const DevicePlan& d, double* phi, double kappa, hipStream_t s)
+hipError_t run_interact_mixed(const DevicePlan& d, double* phi, KernelConst kc, hipStream_t s)
 {
     if (d.ngroups == 0)
         return hipSuccess;
@@ -220,7 +213,7 @@ hipError_t run_interact_mixed(const DevicePlan& d, double* phi, double kappa, hi
                        dim3(kGroupSize), 0, s, d.tgt, d.tgt_orig, d.src, d.src32, d.node_info,
                        d.batch_info, d.group_batch, d.group_first, d.batch_end, d.far_off,
                        d.far_slot, d.near_off, d.near_begin, d.near_count, d.near_leaf,
-                       d.slot_nodes, d.qhat32, phi, kappa);
+                       d.slot_nodes, d.qhat32, phi, kc);
     return hipGetLastError();
 }
 
@@ -234,12 +227,13 @@ hipError_t launch_interact_mixed(const DevicePlan& d, const KernelParams& kp, do
 {
     if (!d.src32 || !d.node_info || !d.batch_info || !d.qhat32)
         return hipErrorInvalidValue;
-    const bool yuk = kp.kernel == 1;
+    const KernelConst kc = kp.kconst();
     switch (d.degree) {
 #define X(n)                                                                   \
     case n:                                                                    \
-        return yuk ? run_interact_mixed<n, 1>(d, phi, kp.kappa, s)             \
-                   : run_interact_mixed<n, 0>(d, phi, kp.kappa, s);
+        return kp.kernel == 1 ? run_interact_mixed<n, 1>(d, phi, kc, s)        \
+             : kp.kernel == 2 ? run_interact_mixed<n, 2>(d, phi, kc, s)        \
+                              : run_interact_mixed<n, 0>(d, phi, kc, s);
         BLTC_DEGREE_CASES(X)
 #undef X
     default:

@@ -34,16 +34,6 @@ constexpr int kMixedFlushSteps = 32;   // FP32 MFMA partial sums cover <= 128 so
 #endif
 constexpr double kTauRel = BLTC_TAU_REL;
 
-template <int KER>
-__device__ __forceinline__ float green_f32(float r2, float rinv, float neg_kappa_log2e)
-{
-    if constexpr (KER == 0) {
-        return rinv;
-    } else {
-        return __builtin_amdgcn_exp2f(neg_kappa_log2e * (r2 * rinv)) * rinv;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // FP64: G in FP64 on the VALU, contraction on v_mfma_f64_16x16x4f64.
 // ---------------------------------------------------------------------------
@@ -65,7 +55,7 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
     const int32_t np = d.np;
     const int64_t phi_ld = d.phi_ld;
     const int32_t m_count = d.mc;
-    const YukawaArg kappa{d.kappa, exp_tab};
+    const KernelArg kappa{d.kc.kappa, d.kc.delta2, exp_tab};
     const int b = d.group_batch[g];
     if (b < 0)
         return;
@@ -114,7 +104,7 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
             for (int t = 0; t < 4; ++t) {
                 const double dx = tx[t] - p.x, dy = ty[t] - p.y, dz = tz[t] - p.z;
                 const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-                const double gv = green_f64<KER>(r2, rsqrt_f64_newton(r2), kappa);
+                const double gv = green_far_f64<KER>(r2, kappa);
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
             }
         }
@@ -137,7 +127,7 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
             for (int t = 0; t < 4; ++t) {
                 const double dx = tx[t] - p.x, dy = ty[t] - p.y, dz = tz[t] - p.z;
                 const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-                const double gv = green_f64<KER>(r2, rsqrt_f64_or_zero(r2), kappa);
+                const double gv = green_near_f64<KER>(r2, kappa);
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
             }
         }
@@ -193,7 +183,7 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
     const int32_t np = d.np;
     const int64_t phi_ld = d.phi_ld;
     const int32_t m_count = d.mc;
-    const YukawaArg kappa{d.kappa, exp_tab};
+    const KernelArg kappa{d.kc.kappa, d.kc.delta2, exp_tab};
     const int b = d.group_batch[g];
     if (b < 0)
         return;
@@ -205,7 +195,7 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
     const int lane = threadIdx.x & 63;
     const int row = lane & 15;
     const int col = lane >> 4;
-    const float nk = static_cast<float>(-d.kappa * 1.4426950408889634);
+    const KernelArg32 nk = kernel_arg32(d.kc.kappa, d.kc.delta2);
 
     double tx[4], ty[4], tz[4];
 #pragma unroll
@@ -257,7 +247,7 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
             for (int t = 0; t < 4; ++t) {
                 const float dx = ux[t] - p.x, dy = uy[t] - p.y, dz = uz[t] - p.z;
                 const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-                const float gv = green_f32<KER>(r2, __builtin_amdgcn_rsqf(r2), nk);
+                const float gv = green_f32<KER>(r2, nk);
                 part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, bq, part[t], 0, 0, 0);
             }
             if (++steps == kMixedFlushSteps) {
@@ -302,7 +292,7 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
             for (int t = 0; t < 4; ++t) {
                 const float dx = ux[t] - p.x, dy = uy[t] - p.y, dz = uz[t] - p.z;
                 r2v[t] = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-                gv[t] = green_f32<KER>(r2v[t], __builtin_amdgcn_rsqf(r2v[t]), nk);
+                gv[t] = green_f32<KER>(r2v[t], nk);
             }
             if (fminf(fminf(r2v[0], r2v[1]), fminf(r2v[2], r2v[3])) <= tau2) {
                 // close pairs: the kernel value from the exact coordinates, in FP64
@@ -312,7 +302,7 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
                     if (r2v[t] <= tau2) {
                         const double dx = tx[t] - p64.x, dy = ty[t] - p64.y, dz = tz[t] - p64.z;
                         const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-                        gv[t] = static_cast<float>(green_f64<KER>(r2, rsqrt_f64_or_zero(r2), kappa));
+                        gv[t] = static_cast<float>(green_near_f64<KER>(r2, kappa));
                     }
             }
 #pragma unroll
@@ -448,7 +438,7 @@ MrhsDesc make_mrhs_desc(const DevicePlan& d, const KernelParams& kp, double* phi
     m.phi_ld = phi_ld;
     m.np = d.degree + 1;
     m.mc = mc;
-    m.kappa = kp.kappa;
+    m.kc = kp.kconst();
     return m;
 }
 
@@ -468,12 +458,26 @@ hipError_t launch_interact_mrhs(const DevicePlan& d, const KernelParams& kp, dou
         return hipErrorInvalidValue;
     const MrhsDesc m = make_mrhs_desc(d, kp, phi, phi_ld, mc);
     const dim3 grid(static_cast<unsigned>(d.ngroups)), block(kGroupSize);
-    const bool yuk = kp.kernel == 1;
+    void (*fn)(MrhsDesc) = nullptr;
     if (kp.precision == 1)
-        hipLaunchKernelGGL(yuk ? (interact_mrhs<1, 1>) : (interact_mrhs<0, 1>), grid, block, 0, s, m);
+        fn = kp.kernel == 1 ? interact_mrhs<1, 1> : kp.kernel == 2 ? interact_mrhs<2, 1>
+                                                                   : interact_mrhs<0, 1>;
     else
-        hipLaunchKernelGGL(yuk ? (interact_mrhs<1, 0>) : (interact_mrhs<0, 0>), grid, block, 0, s, m);
+        fn = kp.kernel == 1 ? interact_mrhs<1, 0> : kp.kernel == 2 ? interact_mrhs<2, 0>
+                                                                   : interact_mrhs<0, 0>;
+    hipLaunchKernelGGL(fn, grid, block, 0, s, m);
     return hipGetLastError();
+}
+
+using QueueKernel = void (*)(const MrhsDesc*, const int2*, int32_t, int32_t*);
+
+static QueueKernel queue_kernel(const KernelParams& kp)
+{
+    if (kp.precision == 1)
+        return kp.kernel == 1 ? interact_queue<1, 1> : kp.kernel == 2 ? interact_queue<2, 1>
+                                                                      : interact_queue<0, 1>;
+    return kp.kernel == 1 ? interact_queue<1, 0> : kp.kernel == 2 ? interact_queue<2, 0>
+                                                                  : interact_queue<0, 0>;
 }
 
 hipError_t launch_reset_counter(int32_t* counter, hipStream_t s)
@@ -489,24 +493,13 @@ hipError_t launch_interact_queue(const MrhsDesc* descs, const int2* units, int32
     if (nunits == 0)
         return hipSuccess;
     const dim3 grid(static_cast<unsigned>(workgroups)), block(kGroupSize);
-    const bool yuk = kp.kernel == 1;
-    if (kp.precision == 1)
-        hipLaunchKernelGGL(yuk ? (interact_queue<1, 1>) : (interact_queue<0, 1>), grid, block, 0, s,
-                           descs, units, nunits, counter);
-    else
-        hipLaunchKernelGGL(yuk ? (interact_queue<1, 0>) : (interact_queue<0, 0>), grid, block, 0, s,
-                           descs, units, nunits, counter);
+    hipLaunchKernelGGL(queue_kernel(kp), grid, block, 0, s, descs, units, nunits, counter);
     return hipGetLastError();
 }
 
 const void* interact_queue_symbol(const KernelParams& kp)
 {
-    const bool yuk = kp.kernel == 1;
-    if (kp.precision == 1)
-        return yuk ? reinterpret_cast<const void*>(interact_queue<1, 1>)
-                   : reinterpret_cast<const void*>(interact_queue<0, 1>);
-    return yuk ? reinterpret_cast<const void*>(interact_queue<1, 0>)
-               : reinterpret_cast<const void*>(interact_queue<0, 0>);
+    return reinterpret_cast<const void*>(queue_kernel(kp));
 }
 
 }  // namespace bltc

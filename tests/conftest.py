@@ -24,3 +24,18 @@ def read_golden(name):
                 continue
             rows.append([float(v) for v in line.split()])
     return rows
+
+
+# kernel cases of the GPU parity tests: (library kernel name, its parameter)
+KERNEL_CASES = [("coulomb", 0.0), ("yukawa", 0.5), ("regularized", 0.01)]
+
+
+def kernel_kwargs(kernel, param):
+    """Library keyword arguments and the oracle's (kernel id, parameter) for a
+    kernel case; the oracle takes delta of the regularized kernel as kappa."""
+    import oracle
+    if kernel == "regularized":
+        return {"kernel": kernel, "delta": param}, oracle.REGULARIZED, param
+    if kernel == "yukawa":
+        return {"kernel": kernel, "kappa": param}, oracle.YUKAWA, param
+    return {"kernel": kernel}, oracle.COULOMB, 0.0

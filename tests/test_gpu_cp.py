@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.conftest import KERNEL_CASES, kernel_kwargs
 from paper_2003_01836_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -51,12 +52,12 @@ def _run(dev, tgt, src, q, **kw):
     return plan, phi.cpu().numpy()
 
 
-@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+@pytest.mark.parametrize("kernel,kappa", KERNEL_CASES)
 def test_cp_fp64_small_config(dev, kernel, kappa):
     pos, q = inputs.uniform_cube(10000, inputs.config_seed(0))
     plan, phi = _run(dev, pos, pos, q[0], theta=0.7, degree=4, leaf_size=500, batch_size=500,
-                     kernel=kernel, kappa=kappa)
-    kern = oracle.YUKAWA if kernel == "yukawa" else oracle.COULOMB
+                     **kernel_kwargs(kernel, kappa)[0])
+    kern = kernel_kwargs(kernel, kappa)[1]
     oc = oracle.ClusterParticle(pos, pos, 0.7, 4, 500, 500)
     ref = oc.potential(q[0], kernel=kern, kappa=kappa)
     _close(ref, phi)
@@ -137,12 +138,12 @@ def test_cp_device_and_host_plans_agree(dev, precision):
     assert np.array_equal(pd.execute(qd).cpu().numpy(), ph.execute(qd).cpu().numpy())
 
 
-@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+@pytest.mark.parametrize("kernel,kappa", KERNEL_CASES)
 def test_cp_mixed_matches_oracle(dev, kernel, kappa):
     pos, q = inputs.uniform_cube(20000, 86)
     _, phi = _run(dev, pos, pos, q[0], theta=0.7, degree=6, leaf_size=400, batch_size=400,
-                  kernel=kernel, kappa=kappa, precision="fp32_mixed")
-    kern = oracle.YUKAWA if kernel == "yukawa" else oracle.COULOMB
+                  **kernel_kwargs(kernel, kappa)[0], precision="fp32_mixed")
+    kern = kernel_kwargs(kernel, kappa)[1]
     ref = oracle.ClusterParticle(pos, pos, 0.7, 6, 400, 400).potential(q[0], kernel=kern,
                                                                         kappa=kappa)
     assert np.all(np.isfinite(phi))

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.conftest import KERNEL_CASES, kernel_kwargs
 from paper_2003_01836_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -54,24 +55,24 @@ def _run_plan(dev, tgt, src, q, **kw):
     return plan, phi.cpu().numpy()
 
 
-@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+@pytest.mark.parametrize("kernel,kappa", KERNEL_CASES)
 def test_gpu_direct_sum_matches_oracle(dev, kernel, kappa):
     import paper_2003_01836_amd as bltc
     pos, q = inputs.uniform_cube(3001, 71)
     t = _dev_soa(pos, dev)
-    phi = bltc.direct(t, t, torch.from_numpy(q[0]).to(dev), kernel=kernel, kappa=kappa)
-    ref = oracle.direct(pos, pos, q[0], kernel=oracle.YUKAWA if kernel == "yukawa" else 0, kappa=kappa)
+    phi = bltc.direct(t, t, torch.from_numpy(q[0]).to(dev), **kernel_kwargs(kernel, kappa)[0])
+    ref = oracle.direct(pos, pos, q[0], kernel=kernel_kwargs(kernel, kappa)[1], kappa=kappa)
     _close(ref, phi.cpu().numpy(), 1e-13, 1e-14)
 
 
-@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+@pytest.mark.parametrize("kernel,kappa", KERNEL_CASES)
 def test_fp64_treecode_small_config(dev, kernel, kappa):
     # N = 10^4 uniform cube, theta 0.7, n = 4, N_L = N_B = 500 (several tiles, ragged batches)
     pos, q = inputs.uniform_cube(10000, inputs.config_seed(0))
     plan, phi = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=4, leaf_size=500, batch_size=500,
-                          kernel=kernel, kappa=kappa)
+                          **kernel_kwargs(kernel, kappa)[0])
     oc = oracle.Treecode(pos, pos, 0.7, 4, 500, 500)
-    kern = oracle.YUKAWA if kernel == "yukawa" else oracle.COULOMB
+    kern = kernel_kwargs(kernel, kappa)[1]
     ref = oc.potential(q[0], kernel=kern, kappa=kappa)
     _close(ref, phi)
     # the method error itself (eq. 16) is the oracle's
@@ -266,12 +267,12 @@ def test_fp64_full_size_sampled(dev):
 MIXED_REL_L2 = 1e-6
 
 
-@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+@pytest.mark.parametrize("kernel,kappa", KERNEL_CASES)
 def test_mixed_small_config(dev, kernel, kappa):
     pos, q = inputs.uniform_cube(10000, inputs.config_seed(0))
     _, phi = _run_plan(dev, pos, pos, q[0], theta=0.7, degree=4, leaf_size=500, batch_size=500,
-                       kernel=kernel, kappa=kappa, precision="fp32_mixed")
-    kern = oracle.YUKAWA if kernel == "yukawa" else oracle.COULOMB
+                       **kernel_kwargs(kernel, kappa)[0], precision="fp32_mixed")
+    kern = kernel_kwargs(kernel, kappa)[1]
     ref = oracle.Treecode(pos, pos, 0.7, 4, 500, 500).potential(q[0], kernel=kern, kappa=kappa)
     assert oracle.rel_l2(ref, phi) <= MIXED_REL_L2
     d = oracle.direct(pos, pos, q[0], kernel=kern, kappa=kappa)
@@ -345,24 +346,24 @@ def test_mixed_full_size_sampled_and_full_n_vs_fp64(dev):
 # several charge vectors: kernel values shared, contraction on the matrix cores
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("m", [2, 16, 21])
-@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+@pytest.mark.parametrize("kernel,kappa", KERNEL_CASES)
 def test_fp64_many_charge_vectors(dev, m, kernel, kappa):
     pos, q = inputs.uniform_cube(9001, 100 + m, m=m)
     _, phi = _run_plan(dev, pos, pos, q, theta=0.7, degree=5, leaf_size=400, batch_size=400,
-                       kernel=kernel, kappa=kappa)
-    kern = oracle.YUKAWA if kernel == "yukawa" else oracle.COULOMB
+                       **kernel_kwargs(kernel, kappa)[0])
+    kern = kernel_kwargs(kernel, kappa)[1]
     ref = oracle.Treecode(pos, pos, 0.7, 5, 400, 400).potential(q, kernel=kern, kappa=kappa)
     for i in range(m):
         _close(ref[i], phi[i])
 
 
 @pytest.mark.parametrize("m", [3, 16])
-@pytest.mark.parametrize("kernel,kappa", [("coulomb", 0.0), ("yukawa", 0.5)])
+@pytest.mark.parametrize("kernel,kappa", KERNEL_CASES)
 def test_mixed_many_charge_vectors(dev, m, kernel, kappa):
     pos, q = inputs.uniform_cube(9001, 120 + m, m=m)
     _, phi = _run_plan(dev, pos, pos, q, theta=0.7, degree=6, leaf_size=400, batch_size=400,
-                       kernel=kernel, kappa=kappa, precision="fp32_mixed")
-    kern = oracle.YUKAWA if kernel == "yukawa" else oracle.COULOMB
+                       **kernel_kwargs(kernel, kappa)[0], precision="fp32_mixed")
+    kern = kernel_kwargs(kernel, kappa)[1]
     ref = oracle.Treecode(pos, pos, 0.7, 6, 400, 400).potential(q, kernel=kern, kappa=kappa)
     for i in range(m):
         assert oracle.rel_l2(ref[i], phi[i]) <= MIXED_REL_L2
