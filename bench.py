@@ -203,10 +203,11 @@ def run_large(args, dev):
     q = g.uniform(-1.0, 1.0, size=n)
     t = torch.from_numpy(pos).to(dev)
     qd = torch.from_numpy(q).to(dev)
-    res = {"workload": f"uniform-{n}", "particles": n}
+    res = {"workload": f"uniform-{n}", "particles": n, "method": args.large_method}
     for prec in ("fp64", "fp32_mixed"):
         t0 = time.perf_counter()
-        plan = bltc.Plan(t, t, theta=0.7, degree=8, leaf_size=4000, batch_size=4000, precision=prec)
+        plan = bltc.Plan(t, t, theta=0.7, degree=8, leaf_size=4000, batch_size=4000, precision=prec,
+                         method=args.large_method)
         t_plan = time.perf_counter() - t0
         st = plan.stats()
         log(f"large {prec}: plan {t_plan:.1f}s {st['batches']} batches")
@@ -389,6 +390,8 @@ def main():
                     choices=sorted(WORKLOADS) + ["batched-64x16", "yukawa-plummer-sweep", "uniform-large",
                                                  "setup", "cp", "cc"])
     ap.add_argument("--large-n", type=int, default=128_000_000)
+    ap.add_argument("--large-method", default="bltc", choices=["bltc", "cp", "cc"],
+                    help="uniform-large workload: treecode variant")
     ap.add_argument("--setup-host-max", type=int, default=20_000_000,
                     help="setup workload: also time the host planner up to this many particles")
     ap.add_argument("--precision", default="both", choices=["fp64", "fp32_mixed", "both"])

@@ -4,16 +4,13 @@
 // One evaluation:
 //  1. charges into source-tree order, modified charges of the source slots
 //     (the BLTC upward pass on the matrix cores, eqs. 14-15);
-//  2. the source array holds the ns particles followed by the Chebyshev grids
-//     of the source slots; the grids' charges are set to the modified charges
-//     (`proxy_charges`), so a cluster-cluster pair is a "direct sum" over P
-//     grid points;
-//  3. proxy potentials of the target slots: the interaction kernel over the
-//     target grids as targets, lists holding source-grid ranges
-//     (cluster-cluster pairs) and particle ranges (cluster-particle pairs);
-//  4. targets by target leaf: far lists (particle-cluster pairs, eq. 11 with
-//     the modified charges) and direct lists, phi written once;
-//  5. interpolation of the proxy potentials of every target slot on each
+//  2. proxy potentials of the target slots: the interaction kernel over the
+//     target grids as targets; a grid-grid pair is a far-field entry (eq. 11
+//     at the grid points, separable in the source grid), a sources-grid pair
+//     a particle range;
+//  3. targets by target leaf: far lists (grid-targets pairs, eq. 11) and
+//     direct lists, phi written once;
+//  4. interpolation of the proxy potentials of every target slot on each
 //     target's path (kernels_cp.hip), phi +=.
 #include <chrono>
 #include <cstring>
@@ -47,22 +44,19 @@ int create_device(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const
     cc.prm = pp;
     const bool mixed = plan->prm.precision == BLTC_FP32_MIXED;
     HIP_TRY(hipGetDevice(&plan->device));
-    // particles are written by the tree build; the grid tail of the source
-    // arrays is filled at upload, once the slots are known
     bltc::DevicePlan& du = plan->d;
     bltc::DevicePlan& dd = plan->ddir;
     int64_t* src_order = nullptr;
-    HIP_TRY(plan->alloc(&plan->cc_src_particles, static_cast<size_t>(ns)));
+    HIP_TRY(plan->alloc(&du.src, static_cast<size_t>(ns)));
     HIP_TRY(plan->alloc(&src_order, static_cast<size_t>(ns)));
     du.src_order = src_order;
     if (mixed)
-        HIP_TRY(plan->alloc(&plan->cc_src32_particles, static_cast<size_t>(ns)));
+        HIP_TRY(plan->alloc(&du.src32, static_cast<size_t>(ns)));
     HIP_TRY(plan->alloc(&dd.tgt, static_cast<size_t>(nt)));
     HIP_TRY(plan->alloc(&dd.tgt_orig, static_cast<size_t>(nt)));
     int64_t bad = -1;
     std::string err = bltc::build_tree_device(cc.src, ns, sx, sy, sz, pp.leaf_size, src_order,
-                                              plan->cc_src_particles,
-                                              mixed ? plan->cc_src32_particles : nullptr, s, &bad);
+                                              du.src, mixed ? du.src32 : nullptr, s, &bad);
     if (bad >= 0)
         return fail(BLTC_EINVAL, "source coordinate %lld is not finite", static_cast<long long>(bad));
     if (!err.empty())
@@ -70,8 +64,7 @@ int create_device(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const
     if (nt == ns && tx == sx && ty == sy && tz == sz && pp.batch_size == pp.leaf_size) {
         cc.tgt = cc.src;
         if (nt > 0) {
-            HIP_TRY(hipMemcpyAsync(dd.tgt, plan->cc_src_particles, nt * sizeof(double4),
-                                   hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(dd.tgt, du.src, nt * sizeof(double4), hipMemcpyDeviceToDevice, s));
             HIP_TRY(hipMemcpyAsync(dd.tgt_orig, src_order, nt * sizeof(int64_t),
                                    hipMemcpyDeviceToDevice, s));
         }
@@ -107,7 +100,6 @@ int upload(bltc_plan* plan, hipStream_t s)
     const int64_t ntl = static_cast<int64_t>(cc.tl_node.size());
     const int32_t np = cc.np;
     const int64_t P = cc.P;
-    const int64_t nsrc = ns + nss * P;     // particles, then the source grids
 
     auto expand = [&](const std::vector<double>& nodes, int64_t nslots) {
         std::vector<double4> g(static_cast<size_t>(nslots * P));
@@ -122,26 +114,14 @@ int upload(bltc_plan* plan, hipStream_t s)
         return g;
     };
 
-    // ---- source array: particles in tree order, then the source grids
-    HIP_TRY(plan->alloc(&du.src, static_cast<size_t>(nsrc)));
-    if (mixed)
-        HIP_TRY(plan->alloc(&du.src32, static_cast<size_t>(nsrc)));
-    if (plan->device_particles) {
-        if (ns > 0) {
-            HIP_TRY(hipMemcpyAsync(du.src, plan->cc_src_particles, ns * sizeof(double4),
-                                   hipMemcpyDeviceToDevice, s));
-            if (mixed)
-                HIP_TRY(hipMemcpyAsync(du.src32, plan->cc_src32_particles, ns * sizeof(float4),
-                                       hipMemcpyDeviceToDevice, s));
-        }
-    } else {
+    // ---- particles in tree order (host-built plans)
+    if (!plan->device_particles) {
         std::vector<double4> src(ns), tgt(nt);
         for (int64_t j = 0; j < ns; ++j)
             src[j] = make_double4(cc.src.x[j], cc.src.y[j], cc.src.z[j], 0.0);
         for (int64_t i = 0; i < nt; ++i)
             tgt[i] = make_double4(cc.tgt.x[i], cc.tgt.y[i], cc.tgt.z[i], 0.0);
-        if (ns > 0)
-            HIP_TRY(hipMemcpyAsync(du.src, src.data(), ns * sizeof(double4), hipMemcpyHostToDevice, s));
+        HIP_TRY(plan->put(&du.src, src, s));
         HIP_TRY(plan->put(&dd.tgt, tgt, s));
         HIP_TRY(plan->put(&dd.tgt_orig, cc.tgt.order, s));
         int64_t* src_order = nullptr;
@@ -160,33 +140,9 @@ int upload(bltc_plan* plan, hipStream_t s)
                                            static_cast<float>(cc.src.y[j] - cy),
                                            static_cast<float>(cc.src.z[j] - cz), 0.0f);
             }
-            if (ns > 0)
-                HIP_TRY(hipMemcpyAsync(du.src32, src32.data(), ns * sizeof(float4),
-                                       hipMemcpyHostToDevice, s));
-            HIP_TRY(hipStreamSynchronize(s));
+            HIP_TRY(plan->put(&du.src32, src32, s));
         }
         HIP_TRY(hipStreamSynchronize(s));
-    }
-    const std::vector<double4> sgrid = expand(cc.sslot_nodes, nss);
-    if (nss > 0)
-        HIP_TRY(hipMemcpyAsync(du.src + ns, sgrid.data(), sgrid.size() * sizeof(double4),
-                               hipMemcpyHostToDevice, s));
-    std::vector<float4> sgrid32;
-    if (mixed && nss > 0) {
-        // grid points relative to their cluster's center
-        sgrid32.resize(sgrid.size());
-        for (int64_t sl = 0; sl < nss; ++sl) {
-            const int32_t c = cc.sslot_cluster[sl];
-            for (int64_t k = 0; k < P; ++k) {
-                const double4 g = sgrid[static_cast<size_t>(sl * P + k)];
-                sgrid32[static_cast<size_t>(sl * P + k)] =
-                    make_float4(static_cast<float>(g.x - cc.src.center[3 * c]),
-                                static_cast<float>(g.y - cc.src.center[3 * c + 1]),
-                                static_cast<float>(g.z - cc.src.center[3 * c + 2]), 0.0f);
-            }
-        }
-        HIP_TRY(hipMemcpyAsync(du.src32 + ns, sgrid32.data(), sgrid32.size() * sizeof(float4),
-                               hipMemcpyHostToDevice, s));
     }
 
     // ---- upward pass over the source slots
@@ -212,7 +168,6 @@ int upload(bltc_plan* plan, hipStream_t s)
         tgrid_end[u] = (u + 1) * P;
     for (int64_t r = 0; r < ntl; ++r)
         leaf_end[r] = cc.tl_begin[r] + cc.tl_count[r];
-    const std::vector<int32_t> zero_off(nts + 1, 0), one_i(1, 0);
     px.src = dd.src = du.src;
     px.src32 = dd.src32 = du.src32;
     px.ns = dd.ns = ns;
@@ -224,8 +179,8 @@ int upload(bltc_plan* plan, hipStream_t s)
     HIP_TRY(plan->put(&px.group_batch, cc.pg_batch, s));
     HIP_TRY(plan->put(&px.group_first, cc.pg_first, s));
     HIP_TRY(plan->put(&px.batch_end, tgrid_end, s));
-    HIP_TRY(plan->put(&px.far_off, zero_off, s));
-    HIP_TRY(plan->put(&px.far_slot, one_i, s));
+    HIP_TRY(plan->put(&px.far_off, cc.gg_off, s));
+    HIP_TRY(plan->put(&px.far_slot, cc.gg_slot, s));
     HIP_TRY(plan->put(&px.near_off, cc.pf_off, s));
     HIP_TRY(plan->put(&px.near_begin, cc.pf_begin, s));
     HIP_TRY(plan->put(&px.near_count, cc.pf_count, s));
@@ -257,13 +212,11 @@ int upload(bltc_plan* plan, hipStream_t s)
     HIP_TRY(plan->alloc(&plan->cp_phat, static_cast<size_t>(nts * P)));
 
     if (mixed) {
-        // source nodes, then one entry per source slot (its grid's frame)
-        std::vector<double4> node_info(nns + nss);
+        // per source node (the lists name source leaves): center and radius
+        std::vector<double4> node_info(nns);
         for (int64_t c = 0; c < nns; ++c)
             node_info[c] = make_double4(cc.src.center[3 * c], cc.src.center[3 * c + 1],
                                         cc.src.center[3 * c + 2], cc.src.radius[c]);
-        for (int64_t sl = 0; sl < nss; ++sl)
-            node_info[nns + sl] = node_info[cc.sslot_cluster[sl]];
         std::vector<double4> bi_p(nts), bi_d(ntl);
         for (int64_t u = 0; u < nts; ++u) {
             const int32_t c = cc.tslot_cluster[u];
@@ -320,9 +273,6 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStr
     HIP_TRY(bltc::launch_gather_charges(du, q, s));
     HIP_TRY(mark(1));
     HIP_TRY(bltc::launch_upward_mfma(du, 1, du.qhat, mixed ? du.qhat32 : nullptr, s));
-    const int64_t nss = static_cast<int64_t>(cc.sslot_cluster.size());
-    HIP_TRY(bltc::launch_proxy_charges(du.src + du.ns, mixed ? du.src32 + du.ns : nullptr, du.qhat,
-                                       nss * cc.P, s));
     if (mixed)
         HIP_TRY(bltc::launch_interact_mixed(plan->dprox, kp, plan->cp_phat, s));
     else

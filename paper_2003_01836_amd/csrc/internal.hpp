@@ -84,15 +84,11 @@ struct bltc_plan {
     int32_t* cp_path_slot = nullptr;
     double* cp_slot_nodes = nullptr;
     double* cp_phat = nullptr;
-    // cluster-cluster plans (method BLTC_CLUSTER_CLUSTER): host plan and the
-    // particles as written by the device tree build (copied into the source
-    // array, which also holds the source grids, at upload); the interaction
-    // launches, interpolation lists and proxy potentials use the members above,
-    // the upward pass uses d
+    // cluster-cluster plans (method BLTC_CLUSTER_CLUSTER): host plan; the
+    // interaction launches, interpolation lists and proxy potentials use the
+    // members above, the upward pass uses d
     bool cc = false;
     bltc::CcPlan ccp;
-    double4* cc_src_particles = nullptr;
-    float4* cc_src32_particles = nullptr;
     bool uploaded = false;
     int device = -1;
     bltc::DevicePlan d;

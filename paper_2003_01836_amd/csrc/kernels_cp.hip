@@ -97,34 +97,10 @@ __global__ __launch_bounds__(kGroupSize) void interpolate_targets(
         phi[tgt_orig[i]] += acc;
 }
 
-// the Chebyshev grids of the source clusters appended to the source array act
-// as sources whose charges are the modified charges (cluster-cluster pairs)
-__global__ __launch_bounds__(256) void proxy_charges(double4* __restrict__ tail,
-                                                     float4* __restrict__ tail32,
-                                                     const double* __restrict__ qhat, int64_t n)
-{
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i < n) {
-        tail[i].w = qhat[i];
-        if (tail32)
-            tail32[i].w = static_cast<float>(qhat[i]);
-    }
-}
-
 #define BLTC_DEGREE_CASES(X) \
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
 }  // namespace
-
-hipError_t launch_proxy_charges(double4* tail, float4* tail32, const double* qhat, int64_t n,
-                                hipStream_t s)
-{
-    if (n == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(proxy_charges, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s,
-                       tail, tail32, qhat, n);
-    return hipGetLastError();
-}
 
 hipError_t launch_interpolate_targets(const DevicePlan& d, const int32_t* path_off,
                                       const int32_t* path_slot, const double* slot_nodes,

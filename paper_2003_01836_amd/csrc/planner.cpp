@@ -803,36 +803,39 @@ void cc_plan_from_trees(CcPlan& cc)
     leaves_by_begin(T, cc.tl_node, cc.tl_begin, cc.tl_count);     // equals t_leaves
     const int64_t ntl = static_cast<int64_t>(cc.tl_node.size());
 
-    // ---- proxy lists per target slot (pairs in walk order)
-    std::vector<int64_t> npf(nts, 0);
+    // ---- proxy lists per target slot (pairs in walk order): grid-grid pairs
+    // as far-field entries (the target grid points are the "targets" of eq.
+    // 11), sources-grid pairs as particle ranges
+    std::vector<int64_t> npf(nts, 0), ngg(nts, 0);
     for (int64_t k = 0; k < npairs; ++k) {
         const int32_t kind = cc.pair_kind[k];
         if (kind == 0)
-            npf[cc.cluster_tslot[cc.pair_t[k]]] += 1;
+            ngg[cc.cluster_tslot[cc.pair_t[k]]] += 1;
         else if (kind == 2)
             npf[cc.cluster_tslot[cc.pair_t[k]]] += s_hi[cc.pair_s[k]] - s_lo[cc.pair_s[k]];
     }
     cc.pf_off.assign(nts + 1, 0);
+    cc.gg_off.assign(nts + 1, 0);
     for (int64_t u = 0; u < nts; ++u) {
-        const int64_t v = cc.pf_off[u] + npf[u];
-        if (v > INT32_MAX)
+        const int64_t v = cc.pf_off[u] + npf[u], w = cc.gg_off[u] + ngg[u];
+        if (v > INT32_MAX || w > INT32_MAX)
             throw std::length_error("proxy lists exceed 2^31 entries");
         cc.pf_off[u + 1] = static_cast<int32_t>(v);
+        cc.gg_off[u + 1] = static_cast<int32_t>(w);
     }
     cc.pf_leaf.resize(cc.pf_off[nts]);
     cc.pf_begin.resize(cc.pf_off[nts]);
     cc.pf_count.resize(cc.pf_off[nts]);
+    cc.gg_slot.resize(cc.gg_off[nts]);
     cc.pf_cost.assign(nts, 0);
     {
         std::vector<int64_t> fill(cc.pf_off.begin(), cc.pf_off.end() - 1);
+        std::vector<int64_t> gfill(cc.gg_off.begin(), cc.gg_off.end() - 1);
         for (int64_t k = 0; k < npairs; ++k) {
             const int32_t kind = cc.pair_kind[k], t = cc.pair_t[k], s = cc.pair_s[k];
             if (kind == 0) {
-                const int32_t u = cc.cluster_tslot[t], ss = cc.cluster_sslot[s];
-                const int64_t e = fill[u]++;
-                cc.pf_leaf[e] = static_cast<int32_t>(nns + ss);
-                cc.pf_begin[e] = S.n + ss * P;
-                cc.pf_count[e] = P;
+                const int32_t u = cc.cluster_tslot[t];
+                cc.gg_slot[gfill[u]++] = cc.cluster_sslot[s];
                 cc.pf_cost[u] += P;
                 cc.cc_evals += P * P;
             } else if (kind == 2) {

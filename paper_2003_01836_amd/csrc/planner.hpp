@@ -225,10 +225,10 @@ struct CcPlan {
     std::vector<int32_t> tslot_cluster, cluster_tslot;
     std::vector<double> tslot_nodes;
 
-    // proxy potentials, per target slot: ranges of the source array, which
-    // holds the ns particles followed by the grids of the source slots
-    // (P points each); pf_leaf is the source leaf of a particle range and
-    // nodes + source slot for a grid
+    // proxy potentials, per target slot: the source slots of its grid-grid
+    // pairs (evaluated like the far field, eq. 11, at the grid points) and
+    // the particle ranges (source leaves) of its sources-grid pairs
+    std::vector<int32_t> gg_off, gg_slot;
     std::vector<int32_t> pf_off, pf_leaf;
     std::vector<int64_t> pf_begin, pf_count, pf_cost;
 
