@@ -82,6 +82,13 @@ def _load():
     lib.oracle_cp_proxy_potentials.argtypes = [vp, i32, vp, i32, d, vp]
     lib.oracle_cp_potential.argtypes = [vp, vp, i32, d, i64, vp, vp, vp]
     lib.oracle_cp_potential.restype = ctypes.c_int
+    lib.oracle_kernel_derivatives.argtypes = [d, i32, d, vp]
+    lib.oracle_hermite_basis.argtypes = [i32, vp, vp, d, vp, vp]
+    lib.oracle_tc_create_hermite.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, d, i32, i64, i64]
+    lib.oracle_tc_create_hermite.restype = vp
+    lib.oracle_tc_hermite_charges.argtypes = [vp, i32, vp, vp]
+    lib.oracle_tc_hermite_potential.argtypes = [vp, vp, i32, d, i64, vp, vp, vp]
+    lib.oracle_tc_hermite_potential.restype = ctypes.c_int
     lib.oracle_cc_create.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, d, i32, i64, i64]
     lib.oracle_cc_create.restype = vp
     lib.oracle_cc_destroy.argtypes = [vp]
@@ -155,11 +162,30 @@ def lagrange(n, s, w, x):
     return L
 
 
+def kernel_derivatives(r, kernel=COULOMB, kappa=0.0):
+    """G(r) and g1 = G'/r, g2 = g1'/r, g3 = g2'/r of a radial kernel at r > 0."""
+    g = np.zeros(4)
+    _load().oracle_kernel_derivatives(float(r), int(kernel), float(kappa), _ptr(g))
+    return g
+
+
+def hermite_basis(n, s, w, x):
+    """Hermite basis A_k(x), B_k(x), k = 0..n, on the nodes s with weights w."""
+    s = _f64(s)
+    w = _f64(w)
+    A = np.zeros(n + 1)
+    B = np.zeros(n + 1)
+    _load().oracle_hermite_basis(int(n), _ptr(s), _ptr(w), float(x), _ptr(A), _ptr(B))
+    return A, B
+
+
 class Treecode:
     """Oracle BLTC (Alg. 1): trees, batches and interaction lists are built here;
-    modified charges and potentials on demand."""
+    modified charges and potentials on demand.  hermite=True: the barycentric
+    Hermite treecode (8 (n+1)^3 modified charges per cluster, kernel
+    derivatives in the approximation, size test against 8 (n+1)^3)."""
 
-    def __init__(self, targets, sources, theta, degree, leaf_size, batch_size):
+    def __init__(self, targets, sources, theta, degree, leaf_size, batch_size, hermite=False):
         lib = _load()
         self._t = _f64(targets)
         self._s = _f64(sources)
@@ -172,9 +198,10 @@ class Treecode:
             raise ValueError("degree out of range")
         tx, ty, tz = self._tc_cols
         sx, sy, sz = self._sc_cols
-        self._h = lib.oracle_tc_create(self.nt, _ptr(tx), _ptr(ty), _ptr(tz),
-                                       self.ns, _ptr(sx), _ptr(sy), _ptr(sz),
-                                       float(theta), self.degree, int(leaf_size), int(batch_size))
+        self.hermite = bool(hermite)
+        create = lib.oracle_tc_create_hermite if self.hermite else lib.oracle_tc_create
+        self._h = create(self.nt, _ptr(tx), _ptr(ty), _ptr(tz), self.ns, _ptr(sx), _ptr(sy),
+                         _ptr(sz), float(theta), self.degree, int(leaf_size), int(batch_size))
         if not self._h:
             raise RuntimeError("oracle treecode creation failed")
         sizes = np.zeros(5, dtype=np.int64)
@@ -247,8 +274,19 @@ class Treecode:
         out = out.reshape(np1, np1, np1, m).transpose(3, 0, 1, 2)
         return out[0] if one else out
 
+    def hermite_charges(self, c, charges):
+        """Hermite modified charges of cluster c: (8, n+1, n+1, n+1), component
+        4 a1 + 2 a2 + a3 for the derivative orders (a1, a2, a3)."""
+        q = _f64(charges)
+        np1 = self.degree + 1
+        out = np.zeros(8 * np1 ** 3)
+        _load().oracle_tc_hermite_charges(self._h, int(c), _ptr(q), _ptr(out))
+        return out.reshape(8, np1, np1, np1)
+
     def potential(self, charges, kernel=COULOMB, kappa=0.0, sample=None, return_times=False):
         """Treecode potential at all targets (caller order), or at `sample` (indices)."""
+        if self.hermite:
+            return self._hermite_potential(charges, kernel, kappa, sample, return_times)
         q = _charges_2d(charges)
         one = np.asarray(charges).ndim == 1
         m = q.shape[0]
@@ -270,6 +308,29 @@ class Treecode:
         if return_times:
             return res, {"upward": float(times[0]), "eval": float(times[1])}
         return res
+
+
+def _hermite_potential_impl(tc, charges, kernel, kappa, sample, return_times):
+    q = _f64(charges)
+    if q.ndim != 1 or q.shape[0] != tc.ns:
+        raise ValueError("the Hermite treecode takes one charge vector")
+    if sample is None:
+        n_eval, sp = tc.nt, None
+    else:
+        smp = np.ascontiguousarray(sample, dtype=np.int64)
+        n_eval, sp = smp.shape[0], _ptr(smp)
+    phi = np.zeros(n_eval)
+    times = np.zeros(2)
+    rc = _load().oracle_tc_hermite_potential(tc._h, _ptr(q), int(kernel), float(kappa), n_eval, sp,
+                                             _ptr(phi), _ptr(times))
+    if rc != 0:
+        raise ValueError("sample index out of range")
+    if return_times:
+        return phi, {"upward": float(times[0]), "eval": float(times[1])}
+    return phi
+
+
+Treecode._hermite_potential = _hermite_potential_impl
 
 
 class ClusterParticle:

@@ -311,6 +311,7 @@ typedef struct {
     const double *tx, *ty, *tz, *sx, *sy, *sz;
     double theta;
     int32_t n;       /* interpolation degree */
+    int32_t comps;   /* values per grid node: 1 (Lagrange), 8 (Hermite, R25) */
     int64_t leaf, batch;
     otree src, tgt;
     int32_t *batch_node;     /* target-tree node id of each batch (leaves, DFS order) */
@@ -341,7 +342,7 @@ static void compute_potential(otc *tc, int64_t b, const onode *B, int32_t cid)
     double dy = B->center[1] - C->center[1];
     double dz = B->center[2] - C->center[2];
     double R = sqrt(dx * dx + dy * dy + dz * dz);
-    int64_t P = (int64_t)(tc->n + 1) * (tc->n + 1) * (tc->n + 1);
+    int64_t P = (int64_t)tc->comps * (tc->n + 1) * (tc->n + 1) * (tc->n + 1);
     int geometric = (B->radius + C->radius < tc->theta * R);
     int size = (P < C->count);
     if (geometric && size) {
@@ -361,9 +362,9 @@ static void compute_potential(otc *tc, int64_t b, const onode *B, int32_t cid)
     }
 }
 
-otc *oracle_tc_create(int64_t nt, const double *tx, const double *ty, const double *tz,
+static otc *tc_create(int64_t nt, const double *tx, const double *ty, const double *tz,
                       int64_t ns, const double *sx, const double *sy, const double *sz,
-                      double theta, int32_t degree, int64_t leaf, int64_t batch)
+                      double theta, int32_t degree, int64_t leaf, int64_t batch, int32_t comps)
 {
     double t0 = wall_seconds();
     otc *tc = (otc *)calloc(1, sizeof(otc));
@@ -371,6 +372,7 @@ otc *oracle_tc_create(int64_t nt, const double *tx, const double *ty, const doub
     tc->tx = tx; tc->ty = ty; tc->tz = tz;
     tc->sx = sx; tc->sy = sy; tc->sz = sz;
     tc->theta = theta; tc->n = degree; tc->leaf = leaf; tc->batch = batch;
+    tc->comps = comps;
 
     tree_build(&tc->src, ns, sx, sy, sz, leaf);
     tree_build(&tc->tgt, nt, tx, ty, tz, batch);
@@ -420,6 +422,13 @@ otc *oracle_tc_create(int64_t nt, const double *tx, const double *ty, const doub
     }
     tc->t_setup = wall_seconds() - t0;
     return tc;
+}
+
+otc *oracle_tc_create(int64_t nt, const double *tx, const double *ty, const double *tz,
+                      int64_t ns, const double *sx, const double *sy, const double *sz,
+                      double theta, int32_t degree, int64_t leaf, int64_t batch)
+{
+    return tc_create(nt, tx, ty, tz, ns, sx, sy, sz, theta, degree, leaf, batch, 1);
 }
 
 void oracle_tc_destroy(otc *tc)
@@ -1408,5 +1417,204 @@ int oracle_cc_potential(const occ *cc, const double *q, int32_t kernel, double k
     free(by_t);
     free(off);
     free(pos);
+    return 0;
+}
+
+/* ========================================================================= */
+/* Barycentric Hermite treecode (the paper's outlook, Sec. V: like the BLTC   */
+/* but with low-order partial derivatives of the kernel).                     */
+/* Readings (listed with the others in the design notes):                     */
+/*   R25 the interpolant in y is the tensor-product Hermite interpolant on    */
+/*       the same Chebyshev grid (eqs. 6-7): per dimension                    */
+/*         f(y) ~ sum_k f(s_k) A_k(y) + f'(s_k) B_k(y),                       */
+/*         A_k = (1 - 2 c_k (y - s_k)) L_k(y)^2,  B_k = (y - s_k) L_k(y)^2,    */
+/*       L_k from eq. 4 (eq. 5 rule at a node), c_k = L_k'(s_k) =             */
+/*       sum_{j != k} 1 / (s_k - s_j); exact for degree <= 2n + 1;            */
+/*   R26 a cluster carries 8 (n+1)^3 modified charges                         */
+/*         qhat^a_k = sum_j q_j prod_l (a_l ? B_kl(y_jl) : A_kl(y_jl)),       */
+/*       a in {0,1}^3, and the approximation is                               */
+/*         phi(x) ~ sum_k sum_a d^a_y G(x, s_k) qhat^a_k;                     */
+/*   R27 the size part of the MAC compares 8 (n+1)^3 with N_C.                */
+/* For a radial kernel G(r), with d = x - y, g1 = G'/r, g2 = g1'/r,           */
+/* g3 = g2'/r:  d_yi G = -d_i g1,  d_yi d_yj G = d_i d_j g2 (i != j),          */
+/* d_y1 d_y2 d_y3 G = -d_1 d_2 d_3 g3.                                        */
+/* ========================================================================= */
+
+/* G, g1, g2, g3 of the kernels at distance r > 0 */
+void oracle_kernel_derivatives(double r, int32_t kernel, double kappa, double *g)
+{
+    if (kernel == ORACLE_YUKAWA) {
+        double e = exp(-kappa * r), kr = kappa * r;
+        g[0] = e / r;
+        g[1] = -e * (1.0 + kr) / (r * r * r);
+        g[2] = e * (3.0 + 3.0 * kr + kr * kr) / pow(r, 5.0);
+        g[3] = -e * (15.0 + 15.0 * kr + 6.0 * kr * kr + kr * kr * kr) / pow(r, 7.0);
+    } else if (kernel == ORACLE_REGULARIZED) {
+        double u = r * r + kappa * kappa;
+        g[0] = 1.0 / sqrt(u);
+        g[1] = -pow(u, -1.5);
+        g[2] = 3.0 * pow(u, -2.5);
+        g[3] = -15.0 * pow(u, -3.5);
+    } else {
+        g[0] = 1.0 / r;
+        g[1] = -1.0 / (r * r * r);
+        g[2] = 3.0 / pow(r, 5.0);
+        g[3] = -15.0 / pow(r, 7.0);
+    }
+}
+
+/* 1-D Hermite basis A_k(x), B_k(x), k = 0..n, on nodes s (R25); at a node    */
+/* (R9, lowest k) A is one-hot and B zero, also when the nodes coincide.      */
+void oracle_hermite_basis(int32_t n, const double *s, const double *w, double x, double *A,
+                          double *B)
+{
+    double L[64];
+    int32_t hit = -1;
+    for (int32_t k = n; k >= 0; --k)
+        if (fabs(x - s[k]) < DBL_MIN)
+            hit = k;
+    if (hit >= 0) {
+        for (int32_t k = 0; k <= n; ++k) {
+            A[k] = k == hit ? 1.0 : 0.0;
+            B[k] = 0.0;
+        }
+        return;
+    }
+    oracle_lagrange(n, s, w, x, L);
+    for (int32_t k = 0; k <= n; ++k) {
+        double c = 0.0;
+        for (int32_t j = 0; j <= n; ++j)
+            if (j != k)
+                c += 1.0 / (s[k] - s[j]);
+        double d = x - s[k];
+        A[k] = (1.0 - 2.0 * c * d) * L[k] * L[k];
+        B[k] = d * L[k] * L[k];
+    }
+}
+
+otc *oracle_tc_create_hermite(int64_t nt, const double *tx, const double *ty, const double *tz,
+                              int64_t ns, const double *sx, const double *sy, const double *sz,
+                              double theta, int32_t degree, int64_t leaf, int64_t batch)
+{
+    return tc_create(nt, tx, ty, tz, ns, sx, sy, sz, theta, degree, leaf, batch, 8);
+}
+
+/* Hermite modified charges of cluster c (R26): out[a * P + k], a = 4 a1 + 2 a2 + a3,
+ * k = (k1*(n+1) + k2)*(n+1) + k3. */
+void oracle_tc_hermite_charges(const otc *tc, int32_t c, const double *q, double *out)
+{
+    const onode *nd = &tc->src.nodes[c];
+    int32_t n = tc->n, np = n + 1;
+    int64_t P = (int64_t)np * np * np;
+    double s[3][64], w[64], A[3][64], B[3][64];
+    for (int l = 0; l < 3; ++l)
+        oracle_chebyshev(n, nd->lo[l], nd->hi[l], s[l], w);
+    memset(out, 0, (size_t)(8 * P) * sizeof(double));
+    const double *p[3] = {tc->sx, tc->sy, tc->sz};
+    for (int64_t e = nd->begin; e < nd->begin + nd->count; ++e) {
+        int64_t j = tc->src.idx[e];
+        for (int l = 0; l < 3; ++l)
+            oracle_hermite_basis(n, s[l], w, p[l][j], A[l], B[l]);
+        for (int a = 0; a < 8; ++a)
+            for (int32_t k1 = 0; k1 < np; ++k1)
+                for (int32_t k2 = 0; k2 < np; ++k2)
+                    for (int32_t k3 = 0; k3 < np; ++k3) {
+                        double h = ((a & 4) ? B[0][k1] : A[0][k1]) * ((a & 2) ? B[1][k2] : A[1][k2]) *
+                                   ((a & 1) ? B[2][k3] : A[2][k3]);
+                        out[a * P + ((int64_t)k1 * np + k2) * np + k3] += h * q[j];
+                    }
+    }
+}
+
+/* Evaluation with the Hermite approximation for the approximated clusters  */
+/* (R26) and the direct sum (eq. 9) for the others; phi[s] at sample[s].     */
+int oracle_tc_hermite_potential(const otc *tc, const double *q, int32_t kernel, double kappa,
+                                int64_t n_sample, const int64_t *sample, double *phi,
+                                double *times)
+{
+    int32_t n = tc->n, np = n + 1;
+    int64_t P = (int64_t)np * np * np;
+    int64_t n_eval = sample ? n_sample : tc->nt;
+    int64_t nn = tc->src.n_nodes;
+    double t0 = wall_seconds();
+    for (int64_t s = 0; s < n_eval; ++s) {
+        int64_t i = sample ? sample[s] : s;
+        if (i < 0 || i >= tc->nt)
+            return -1;
+    }
+    char *need = (char *)calloc((size_t)(nn > 0 ? nn : 1), 1);
+    for (int64_t s = 0; s < n_eval; ++s) {
+        int64_t b = tc->batch_of_pos[tc->target_pos[sample ? sample[s] : s]];
+        for (int64_t t = 0; t < tc->n_items[b]; ++t)
+            if (tc->items[b][t].kind == 0)
+                need[tc->items[b][t].cluster] = 1;
+    }
+    double **qh = (double **)calloc((size_t)(nn > 0 ? nn : 1), sizeof(double *));
+    {
+        int64_t c;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (c = 0; c < nn; ++c)
+            if (need[c]) {
+                qh[c] = (double *)malloc((size_t)(8 * P) * sizeof(double));
+                oracle_tc_hermite_charges(tc, (int32_t)c, q, qh[c]);
+            }
+    }
+    double t1 = wall_seconds();
+    {
+        int64_t s;
+#pragma omp parallel for schedule(dynamic, 8)
+        for (s = 0; s < n_eval; ++s) {
+            int64_t i = sample ? sample[s] : s;
+            int64_t b = tc->batch_of_pos[tc->target_pos[i]];
+            double x = tc->tx[i], y = tc->ty[i], z = tc->tz[i];
+            double acc = 0.0, nodes[3][64], w[64], g[4];
+            for (int64_t t = 0; t < tc->n_items[b]; ++t) {
+                const oitem *it = &tc->items[b][t];
+                const onode *C = &tc->src.nodes[it->cluster];
+                if (it->kind == 0) {
+                    for (int l = 0; l < 3; ++l)
+                        oracle_chebyshev(n, C->lo[l], C->hi[l], nodes[l], w);
+                    const double *Q = qh[it->cluster];
+                    for (int32_t k1 = 0; k1 < np; ++k1)
+                        for (int32_t k2 = 0; k2 < np; ++k2)
+                            for (int32_t k3 = 0; k3 < np; ++k3) {
+                                double d1 = x - nodes[0][k1], d2 = y - nodes[1][k2],
+                                       d3 = z - nodes[2][k3];
+                                double r = sqrt(d1 * d1 + d2 * d2 + d3 * d3);
+                                oracle_kernel_derivatives(r, kernel, kappa, g);
+                                int64_t k = ((int64_t)k1 * np + k2) * np + k3;
+                                /* d^a_y G for a = (a1, a2, a3), index 4 a1 + 2 a2 + a3 */
+                                acc += g[0] * Q[0 * P + k];
+                                acc += -d3 * g[1] * Q[1 * P + k];
+                                acc += -d2 * g[1] * Q[2 * P + k];
+                                acc += d2 * d3 * g[2] * Q[3 * P + k];
+                                acc += -d1 * g[1] * Q[4 * P + k];
+                                acc += d1 * d3 * g[2] * Q[5 * P + k];
+                                acc += d1 * d2 * g[2] * Q[6 * P + k];
+                                acc += -d1 * d2 * d3 * g[3] * Q[7 * P + k];
+                            }
+                } else {
+                    for (int64_t e = C->begin; e < C->begin + C->count; ++e) {
+                        int64_t j = tc->src.idx[e];
+                        double d1 = x - tc->sx[j], d2 = y - tc->sy[j], d3 = z - tc->sz[j];
+                        double r = sqrt(d1 * d1 + d2 * d2 + d3 * d3);
+                        if (r == 0.0)
+                            continue;
+                        acc += kernel_of_distance(r, kernel, kappa) * q[j];
+                    }
+                }
+            }
+            phi[s] = acc;
+        }
+    }
+    double t2 = wall_seconds();
+    if (times) {
+        times[0] = t1 - t0;
+        times[1] = t2 - t1;
+    }
+    for (int64_t c = 0; c < nn; ++c)
+        free(qh[c]);
+    free(qh);
+    free(need);
     return 0;
 }
