@@ -31,6 +31,10 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
 # 3 differences, 3 squares and 2 sums, 1 reciprocal square root, 1 multiply-add (2)
 FLOPS_COULOMB = 11
 FLOPS_YUKAWA = 15                   # + r = r^2 * (1/r), -kappa r, exp, product
+# Hermite approximation, per grid point and target (Coulomb): distance 8, reciprocal
+# square root 1, g1..g3 from 1/r 6, d1 d2 and d1 d2 d3 2, first-order sum 5,
+# second-order sum 6, third-order product 1, combination with g0..g3 7, accumulate 1
+FLOPS_HERMITE_POINT = 37
 
 
 KERNEL_SOURCES = {
@@ -341,6 +345,77 @@ def run_variant(args, dev):
     return res
 
 
+def run_hermite(args, dev):
+    """Barycentric Hermite treecode (FP64) on the headline geometry: 10^6 uniform,
+    Coulomb, theta 0.7, N_L = N_B = 2000, degrees 2..4 (8 (n+1)^3 <= 1000 modified
+    charges per cluster, against 729 for the BLTC at n = 8)."""
+    import numpy as np
+    import torch
+
+    import paper_2003_01836_amd as bltc
+    from paper_2003_01836_amd import inputs
+
+    w = WORKLOADS["uniform-1M"]
+    n = w["n"]
+    log(f"hermite: generating {n} particles")
+    pos, q = inputs.uniform_cube(n, inputs.config_seed(w["cfg"]))
+    t = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
+    qd = torch.from_numpy(q[0]).to(dev)
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    smp = inputs.sample_indices(n, w["samples"], inputs.sample_seed(w["cfg"]))
+    res = {"workload": f"hermite uniform-1M: N={n}, coulomb, theta={w['theta']}, "
+                       f"N_L=N_B={w['leaf']}, fp64", "degrees": {}}
+    got = {}
+    for deg in args.hermite_degrees:
+        t0 = time.perf_counter()
+        plan = bltc.Plan(t, t, method="hermite", theta=w["theta"], degree=deg,
+                         leaf_size=w["leaf"], batch_size=w["batch"])
+        t_plan = time.perf_counter() - t0
+        st = plan.stats()
+        for _ in range(args.warmup):
+            plan.execute(qd, out=phi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.execute(qd, out=phi)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        plan.set_timing(True)
+        ph = {"gather": 0.0, "upward": 0.0, "interact": 0.0, "total": 0.0}
+        for _ in range(args.steps):
+            plan.execute(qd, out=phi)
+            for k, v in plan.phase_times().items():
+                ph[k] += v / args.steps
+        plan.set_timing(False)
+        got[deg] = phi.cpu().numpy()
+        points = st["far_evals"] // 8      # far_evals counts 8 values per grid point
+        flops = points * FLOPS_HERMITE_POINT + st["near_evals"] * FLOPS_COULOMB
+        ach = flops / (ph["interact"] * 1e-3) / 1e12
+        res["degrees"][deg] = {
+            "ms_per_step": ms, "targets_per_s": n / (ms * 1e-3), "plan_s": t_plan,
+            "phases_ms": ph, "grid_point_evals": points, "near_evals": st["near_evals"],
+            "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"],
+            "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
+                         "traffic": None, "kernel": f"interact_hermite_f64<{deg}, 0>",
+                         "flops_per_grid_point": FLOPS_HERMITE_POINT,
+                         "flops_per_near_eval": FLOPS_COULOMB}}
+        log(f"hermite n={deg}: {ms:.2f} ms/step, phases {ph}")
+        del plan
+    if not args.no_cpu:
+        import oracle
+        ds = oracle.direct(pos[smp], pos, q[0])
+        for deg, v in got.items():
+            oc = oracle.Treecode(pos, pos, w["theta"], deg, w["leaf"], w["batch"], hermite=True)
+            ref, times = oc.potential(q[0], sample=smp, return_times=True)
+            res["degrees"][deg]["E_par"] = rel_l2(ref, v[smp])
+            res["degrees"][deg]["E_tc"] = rel_l2(ds, v[smp])
+            res["degrees"][deg]["oracle_s"] = times
+            log(f"hermite n={deg}: E_par {res['degrees'][deg]['E_par']:.2e} "
+                f"E_tc {res['degrees'][deg]['E_tc']:.2e}")
+    return res
+
+
 def run_setup(args, dev):
     """Setup phase alone: plans built on the GPU (device coordinates) against the
     host planner (host coordinates) on the same uniform cube, N_L = N_B = 4000."""
@@ -388,10 +463,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="uniform-1M",
                     choices=sorted(WORKLOADS) + ["batched-64x16", "yukawa-plummer-sweep", "uniform-large",
-                                                 "setup", "cp", "cc"])
+                                                 "setup", "cp", "cc", "hermite"])
     ap.add_argument("--large-n", type=int, default=128_000_000)
     ap.add_argument("--large-method", default="bltc", choices=["bltc", "cp", "cc"],
                     help="uniform-large workload: treecode variant")
+    ap.add_argument("--hermite-degrees", type=int, nargs="+", default=[2, 3, 4],
+                    help="hermite workload: interpolation degrees")
     ap.add_argument("--setup-host-max", type=int, default=20_000_000,
                     help="setup workload: also time the host planner up to this many particles")
     ap.add_argument("--precision", default="both", choices=["fp64", "fp32_mixed", "both"])
@@ -418,10 +495,10 @@ def main():
         return 1
     dev = torch.device("cuda:0")
     if args.workload in ("batched-64x16", "yukawa-plummer-sweep", "uniform-large", "setup", "cp",
-                         "cc"):
+                         "cc", "hermite"):
         fn = {"batched-64x16": run_batched, "yukawa-plummer-sweep": run_sweep,
               "uniform-large": run_large, "setup": run_setup, "cp": run_variant,
-              "cc": run_variant}[args.workload]
+              "cc": run_variant, "hermite": run_hermite}[args.workload]
         print(json.dumps(fn(args, dev)), flush=True)
         return 0
     w = WORKLOADS[args.workload]

@@ -13,7 +13,9 @@
  * batch/cluster pair either the approximation of eq. 11 (MAC of eq. 13 holds)
  * or the direct sum of eq. 9 (it fails).  The same interpolation applied to
  * the target variable (the cluster-particle treecode that the paper's outlook,
- * Sec. V, names) is available as a second method.
+ * Sec. V, names) is available as a second method, the cluster-cluster
+ * treecode as a third, and the barycentric Hermite treecode (also named in
+ * Sec. V: kernel derivatives on the same grids) as a fourth.
  *
  * Conventions shared by every entry point:
  *  - Counts are int64_t.  Coordinates are structure-of-arrays FP64: x, y, z are
@@ -91,11 +93,23 @@ typedef enum { BLTC_FP64 = 0, BLTC_FP32_MIXED = 1 } bltc_precision;
  *                         pairs split the larger non-leaf cluster (both when
  *                         the radii are equal) until two leaves meet, which
  *                         are summed directly.  One charge vector per
+ *                         execution; not usable in a bltc_batch.
+ *  BLTC_HERMITE           particle-cluster as BLTC_PARTICLE_CLUSTER, with the
+ *                         tensor-product Hermite interpolant on the same
+ *                         Chebyshev grids: per dimension A_k = (1 - 2 c_k (y -
+ *                         s_k)) L_k^2 and B_k = (y - s_k) L_k^2, L_k of eq. 4,
+ *                         c_k = sum_{j != k} 1/(s_k - s_j).  A cluster carries
+ *                         8 (n+1)^3 modified charges, one per grid point k
+ *                         and derivative multi-index a in {0,1}^3, and the
+ *                         approximation sums d^a_y G(x, s_k) times them; the
+ *                         size part of the MAC compares 8 (n+1)^3 with N_C.
+ *                         BLTC_FP64 only, degree 1..10, one charge vector per
  *                         execution; not usable in a bltc_batch. */
 typedef enum {
     BLTC_PARTICLE_CLUSTER = 0,
     BLTC_CLUSTER_PARTICLE = 1,
-    BLTC_CLUSTER_CLUSTER = 2
+    BLTC_CLUSTER_CLUSTER = 2,
+    BLTC_HERMITE = 3
 } bltc_method;
 
 typedef struct {
@@ -138,7 +152,7 @@ typedef struct bltc_plan bltc_plan;
  * written in tree order directly into the plan's device arrays.  The result
  * equals the plan bltc_plan_create_host builds from the same coordinates.
  * Synchronises `stream`.  max_q >= 1 bounds num_q of later executions
- * (max_q must be 1 for BLTC_CLUSTER_PARTICLE and BLTC_CLUSTER_CLUSTER).  At most 2^31 - 1 particles
+ * (max_q must be 1 for every method but BLTC_PARTICLE_CLUSTER).  At most 2^31 - 1 particles
  * per side.  Non-finite coordinates: BLTC_EINVAL. */
 int bltc_plan_create(bltc_plan** out, const bltc_params* p,
                      int64_t nt, const double* tx, const double* ty, const double* tz,
@@ -169,7 +183,9 @@ int bltc_plan_execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q
  * For BLTC_CLUSTER_PARTICLE plans `cluster` is a target cluster and out
  * receives its proxy potentials (qi = 0); for BLTC_CLUSTER_CLUSTER plans it is
  * a node of the target tree (a batch index of bltc_plan_view) and out
- * receives its proxy potentials. */
+ * receives its proxy potentials.  For BLTC_HERMITE plans out holds
+ * 8 (n+1)^3 values, out[8 k + a] with a = 4 a1 + 2 a2 + a3 the derivative
+ * multi-index. */
 int bltc_plan_modified_charges(bltc_plan* plan, int64_t cluster, int32_t qi,
                                double* out, void* stream);
 

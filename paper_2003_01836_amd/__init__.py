@@ -23,10 +23,12 @@ __all__ = ["params", "Plan", "Batch", "autotune", "potential", "direct", "BLTCEr
 _KERNELS = {"coulomb": _capi.COULOMB, "yukawa": _capi.YUKAWA, "regularized": _capi.REGULARIZED}
 _PRECISIONS = {"fp64": _capi.FP64, "fp32_mixed": _capi.FP32_MIXED, "mixed": _capi.FP32_MIXED}
 # "bltc": the paper's particle-cluster treecode (sources interpolated);
-# "cp": cluster-particle (targets interpolated); "cc": cluster-cluster (both)
+# "cp": cluster-particle (targets interpolated); "cc": cluster-cluster (both);
+# "hermite": particle-cluster with the barycentric Hermite interpolant
 _METHODS = {"bltc": _capi.PARTICLE_CLUSTER, "particle_cluster": _capi.PARTICLE_CLUSTER,
             "cp": _capi.CLUSTER_PARTICLE, "cluster_particle": _capi.CLUSTER_PARTICLE,
-            "cc": _capi.CLUSTER_CLUSTER, "cluster_cluster": _capi.CLUSTER_CLUSTER}
+            "cc": _capi.CLUSTER_CLUSTER, "cluster_cluster": _capi.CLUSTER_CLUSTER,
+            "hermite": _capi.HERMITE}
 
 
 def library_path() -> str:
@@ -199,13 +201,17 @@ class Plan:
         }
 
     def modified_charges(self, cluster, qi=0, stream=None):
-        """Modified charges the last execution formed for a cluster: (n+1, n+1, n+1)."""
+        """Modified charges the last execution formed for a cluster: (n+1, n+1, n+1); for
+        the Hermite method (8, n+1, n+1, n+1), first index a = 4 a1 + 2 a2 + a3."""
         n1 = self.params.degree + 1
-        out = np.zeros(n1 ** 3)
+        hermite = self.params.method == _capi.HERMITE
+        out = np.zeros(n1 ** 3 * (8 if hermite else 1))
         rc = self._lib.bltc_plan_modified_charges(self._h, int(cluster), int(qi),
                                                   out.ctypes.data_as(ctypes.c_void_p),
                                                   _stream_handle(stream))
         _capi.check(rc)
+        if hermite:
+            return np.ascontiguousarray(np.moveaxis(out.reshape(n1, n1, n1, 8), -1, 0))
         return out.reshape(n1, n1, n1)
 
 

@@ -22,6 +22,7 @@ FP32_MIXED = 1
 PARTICLE_CLUSTER = 0
 CLUSTER_PARTICLE = 1
 CLUSTER_CLUSTER = 2
+HERMITE = 3
 
 # every exported symbol of include/bltc.h
 EXPORTS = (

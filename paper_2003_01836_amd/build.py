@@ -71,6 +71,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         "cp": os.path.join(build_dir, "cp.o"),
         "cc": os.path.join(build_dir, "cc.o"),
         "kernels_cp": os.path.join(build_dir, "kernels_cp.o"),
+        "kernels_hermite": os.path.join(build_dir, "kernels_hermite.o"),
     }
     cmds = [
         ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
@@ -89,6 +90,8 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "cp.cpp"), "-o", objs["cp"]],
         [hipcc] + hip_flags + ["-x", "hip", "-c", os.path.join(CSRC, "cc.cpp"), "-o", objs["cc"]],
         [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_cp.hip"), "-o", objs["kernels_cp"]],
+        [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_hermite.hip"), "-o",
+                               objs["kernels_hermite"]],
     ]
     if verbose:
         for c in cmds:

@@ -89,9 +89,9 @@ int bltc_batch_create(bltc_batch** out, bltc_plan* const* plans, int32_t count, 
     for (int32_t i = 0; i < count; ++i) {
         if (!plans[i])
             return fail(BLTC_EINVAL, "plan %d is NULL", i);
-        if (plans[i]->cp || plans[i]->cc)
-            return fail(BLTC_EUNSUPPORTED, "plan %d is a cluster-particle or cluster-cluster plan "
-                                           "(not batchable)", i);
+        if (plans[i]->cp || plans[i]->cc || plans[i]->prm.method == BLTC_HERMITE)
+            return fail(BLTC_EUNSUPPORTED, "plan %d is a cluster-particle, cluster-cluster or "
+                                           "Hermite plan (not batchable)", i);
         if (plans[i]->max_q < 2)
             return fail(BLTC_EINVAL, "plan %d was created with max_q < 2 (batches use the "
                                      "16-vector tables)", i);
@@ -139,7 +139,7 @@ int bltc_batch_create(bltc_batch** out, bltc_plan* const* plans, int32_t count, 
     b->nunits = static_cast<int32_t>(hu.size());
     b->nupunits = static_cast<int32_t>(hup.size());
     b->passes = bltc::upward_passes(max_np, b->mw);
-    b->lds = bltc::upward_lds_bytes(max_np, b->mw);
+    b->lds = bltc::upward_lds_bytes(max_np, b->mw, max_np);
 
     std::vector<bltc::UpwardDesc> ud(count);
     for (int32_t i = 0; i < count; ++i) {

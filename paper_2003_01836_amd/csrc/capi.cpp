@@ -45,9 +45,14 @@ int check_params(const bltc_params* p)
     if (p->threads_per_target < 0 || p->threads_per_target > 1)
         return fail(BLTC_EUNSUPPORTED, "threads_per_target must be 0 or 1");
     if (p->method != BLTC_PARTICLE_CLUSTER && p->method != BLTC_CLUSTER_PARTICLE &&
-        p->method != BLTC_CLUSTER_CLUSTER)
-        return fail(BLTC_EINVAL, "method must be BLTC_PARTICLE_CLUSTER, BLTC_CLUSTER_PARTICLE or "
-                                 "BLTC_CLUSTER_CLUSTER");
+        p->method != BLTC_CLUSTER_CLUSTER && p->method != BLTC_HERMITE)
+        return fail(BLTC_EINVAL, "method must be BLTC_PARTICLE_CLUSTER, BLTC_CLUSTER_PARTICLE, "
+                                 "BLTC_CLUSTER_CLUSTER or BLTC_HERMITE");
+    if (p->method == BLTC_HERMITE && p->precision != BLTC_FP64)
+        return fail(BLTC_EUNSUPPORTED, "the Hermite treecode runs in BLTC_FP64 only");
+    if (p->method == BLTC_HERMITE && p->degree > bltc::kMaxHermiteDegree)
+        return fail(BLTC_EUNSUPPORTED, "the Hermite treecode takes degree 1..%d",
+                    bltc::kMaxHermiteDegree);
     return BLTC_OK;
 }
 
@@ -82,6 +87,7 @@ bltc::PlanParams plan_params(const bltc_plan* plan, const bltc_params* p)
     pp.leaf_size = p->leaf_size;
     pp.batch_size = p->batch_size;
     pp.group_size = bltc::kGroupSize;
+    pp.comps = p->method == BLTC_HERMITE ? 8 : 1;
     // upward-pass chunks: with one charge vector a chunk is a few MFMA tiles, so
     // smaller chunks give more workgroups; 16 vectors fill 9x more tiles per chunk
     pp.chunk_size = plan->max_q > 1 ? 8192 : 2048;
@@ -184,6 +190,7 @@ int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
     bltc::DevicePlan& d = plan->d;
     HIP_TRY(hipGetDevice(&plan->device));
     d.degree = plan->prm.degree;
+    d.hermite = plan->prm.method == BLTC_HERMITE;
     d.nt = hp.tgt.n;
     d.ns = hp.src.n;
     d.nslots = static_cast<int64_t>(hp.slot_cluster.size());
@@ -229,6 +236,8 @@ int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
     // clusters; [row][P] for one charge vector, [row][P][16] for several
     const size_t mw_max = plan->max_q > 1 ? 16 : 1;
     HIP_TRY(plan->alloc(&d.qhat, static_cast<size_t>(d.nslots + hp.npartial) * hp.P * mw_max));
+    if (d.hermite)
+        HIP_TRY(plan->alloc(&d.qhat_h, static_cast<size_t>(d.nslots) * hp.P));
     const bool mixed = plan->prm.precision == BLTC_FP32_MIXED;
     if (plan->max_q > 1) {
         // expanded proxy grids for the multi-vector kernels
@@ -365,7 +374,9 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
         HIP_TRY(mark(0, 1));
         HIP_TRY(bltc::launch_upward_mfma(d, 1, d.qhat, d.qhat32, s));
         HIP_TRY(mark(0, 2));
-        if (kp.precision == BLTC_FP32_MIXED)
+        if (d.hermite)
+            HIP_TRY(bltc::launch_interact_hermite(d, kp, phi, s));
+        else if (kp.precision == BLTC_FP32_MIXED)
             HIP_TRY(bltc::launch_interact_mixed(d, kp, phi, s));
         else
             HIP_TRY(bltc::launch_interact(d, kp, phi, s));
@@ -406,8 +417,8 @@ int create_common(bltc_plan** out, const bltc_params* p, int64_t nt, const doubl
     if (max_q < 1)
         return fail(BLTC_EINVAL, "max_q must be >= 1");
     if (p->method != BLTC_PARTICLE_CLUSTER && max_q != 1)
-        return fail(BLTC_EUNSUPPORTED, "cluster-particle and cluster-cluster plans take one charge "
-                                       "vector (max_q = 1)");
+        return fail(BLTC_EUNSUPPORTED, "cluster-particle, cluster-cluster and Hermite plans take "
+                                       "one charge vector (max_q = 1)");
     return BLTC_OK;
 }
 
@@ -578,7 +589,9 @@ int bltc_plan_modified_charges(bltc_plan* plan, int64_t cluster, int32_t qi, dou
         return fail(BLTC_EINVAL, "charge vector %d is not in the last execution's last pass", qi);
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<double> buf(plan->last_q == 1 ? hp.P : hp.P * 16);
-    const double* src = plan->d.qhat + static_cast<int64_t>(slot) * static_cast<int64_t>(buf.size());
+    // Hermite: the charges regrouped per grid point, [slot][k][a]
+    const double* src = (plan->d.hermite ? plan->d.qhat_h : plan->d.qhat) +
+                        static_cast<int64_t>(slot) * static_cast<int64_t>(buf.size());
     HIP_TRY(hipMemcpyAsync(buf.data(), src, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (int64_t k = 0; k < hp.P; ++k)

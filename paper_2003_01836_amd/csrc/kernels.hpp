@@ -8,11 +8,13 @@
 namespace bltc {
 
 constexpr int kMaxDegree = 16;
+constexpr int kMaxHermiteDegree = 10;   // Hermite treecode: 8 (n+1)^3 charges per cluster
 constexpr int kGroupSize = 256;      // targets (lanes) per interaction workgroup
 
 // Device-side view of a plan (all device pointers).
 struct DevicePlan {
     int32_t degree = 0;
+    int32_t hermite = 0;              // Hermite interpolation: 8 (n+1)^3 values per slot
     int64_t nt = 0, ns = 0, nslots = 0, nchunks = 0, ngroups = 0, nbatches = 0;
     // sources in tree order: x, y, z, charge of the current vector
     double4* src = nullptr;
@@ -51,6 +53,8 @@ struct DevicePlan {
     double4* proxies = nullptr;       // [slot][P] expanded Chebyshev grid (x, y, z, -)
     float4* proxies32 = nullptr;      // [slot][P] grid relative to the cluster center
     float* qhat16f = nullptr;         // [slot][P][16] (mixed precision)
+    // Hermite: modified charges regrouped per grid point, [slot][(n+1)^3][8]
+    double* qhat_h = nullptr;
 };
 
 // Constants of the kernel G passed to the interaction kernels: kappa of the
@@ -119,13 +123,19 @@ struct UpwardDesc {
     double* buf;
     int32_t np;
 };
-size_t upward_lds_bytes(int32_t np, int32_t mw);
-int32_t upward_passes(int32_t np, int32_t mw);
+// nf: factors per dimension (np, or 2 np for the Hermite interpolation)
+size_t upward_lds_bytes(int32_t np, int32_t mw, int32_t nf);
+int32_t upward_passes(int32_t nf, int32_t mw);
 hipError_t upward_prepare(size_t lds);
 hipError_t launch_upward_many(const UpwardDesc* descs, const int2* units, int32_t nunits,
                               int32_t mw, int32_t passes, size_t lds, hipStream_t s);
 hipError_t launch_upward_reduce(const DevicePlan& d, int32_t mw, double* buf, float* qhat32,
                                 hipStream_t s);
+// (with d.hermite the upward pass forms 8 (n+1)^3 charges per slot and the
+// reduction writes them to d.qhat_h, [slot][k][a]; mw must be 1)
+// Hermite approximation and direct sums (kernels_hermite.hip), FP64, n <= 10
+hipError_t launch_interact_hermite(const DevicePlan& d, const KernelParams& kp, double* phi,
+                                   hipStream_t s);
 // batch/cluster interactions: eqs. 9 and 11, phi written in caller order
 hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* phi,
                            hipStream_t s);

@@ -12,6 +12,10 @@
 // in LDS, and each wave accumulates its tiles with v_mfma_f64_16x16x4f64,
 // K = 4 sources per instruction.  Chunks of the same cluster are summed in a
 // fixed order by a second kernel (deterministic).
+//
+// The Hermite variant has 2(n+1) factors per dimension -- A_k then B_k, the
+// Hermite basis on the same nodes -- and hence 8 (n+1)^3 outputs per cluster
+// in the layout ((a1 (n+1) + k1) 2(n+1) + a2 (n+1) + k2) 2(n+1) + a3 (n+1) + k3.
 #include <cfloat>
 
 #include "kernels.hpp"
@@ -49,6 +53,44 @@ __device__ __forceinline__ double factors_rt(double yv, const double* __restrict
     return sum;
 }
 
+// Hermite factors of one coordinate: a[k] = A_k(y) = (1 - 2 c_k (y - s_k)) L_k(y)^2,
+// a[np + k] = B_k(y) = (y - s_k) L_k(y)^2 with L_k from eq. 4 and c_k = L_k'(s_k)
+// (given); one-hot A and zero B at a node (eq. 5).  Returns 1 (the factors are
+// normalized).
+__device__ __forceinline__ double factors_hermite(double yv, const double* __restrict__ s,
+                                                  const double* __restrict__ c, int np,
+                                                  double* __restrict__ a)
+{
+    const int n = np - 1;
+    int hit = -1;
+    for (int k = np - 1; k >= 0; --k)
+        if (fabs(yv - s[k]) < DBL_MIN)
+            hit = k;
+    if (hit >= 0) {
+        for (int k = 0; k < np; ++k) {
+            a[k] = (k == hit) ? 1.0 : 0.0;
+            a[np + k] = 0.0;
+        }
+        return 1.0;
+    }
+    double sum = 0.0;
+    for (int k = 0; k < np; ++k) {
+        const double w = ((k & 1) ? -1.0 : 1.0) * ((k == 0 || k == n) ? 0.5 : 1.0);
+        const double v = w / (yv - s[k]);
+        a[k] = v;
+        sum += v;
+    }
+    const double inv = 1.0 / sum;
+    for (int k = 0; k < np; ++k) {
+        const double d = yv - s[k];
+        const double l = a[k] * inv;
+        const double l2 = l * l;
+        a[k] = (1.0 - 2.0 * c[k] * d) * l2;
+        a[np + k] = d * l2;
+    }
+    return 1.0;
+}
+
 // grid: x = chunk, y = tile pass.  mw = 1 (one charge vector, taken from
 // src[j].w) or 16 (charges from qm[j][16]).  Output of a chunk: dst[k * mw + m]
 // with dst = out + chunk_dst[c] * P * mw (rows below nslots are the final
@@ -59,16 +101,19 @@ __device__ __forceinline__ void upward_chunk(
     const double4* __restrict__ src, const double* __restrict__ qm, int32_t mw,
     const int32_t* __restrict__ chunk_slot, const int64_t* __restrict__ chunk_begin,
     const int64_t* __restrict__ chunk_count, const int64_t* __restrict__ chunk_dst,
-    const double* __restrict__ slot_nodes, int32_t np, double* __restrict__ out, int c, int pass,
-    double* __restrict__ lds)
+    const double* __restrict__ slot_nodes, int32_t np, int32_t nf, double* __restrict__ out,
+    int c, int pass, double* __restrict__ lds)
 {
-    const int np2 = np * np;
-    const int P = np2 * np;
-    double* __restrict__ A1 = lds;                   // [kTile][np]
-    double* __restrict__ A2 = A1 + kTile * np;       // [kTile][np]
-    double* __restrict__ A3 = A2 + kTile * np;       // [kTile][np]
-    double* __restrict__ SQ = A3 + kTile * np;       // [kTile][mw]  q~
+    // nf factors per dimension: np (Lagrange) or 2 np (Hermite)
+    const bool hermite = nf != np;
+    const int nf2 = nf * nf;
+    const int P = nf2 * nf;
+    double* __restrict__ A1 = lds;                   // [kTile][nf]
+    double* __restrict__ A2 = A1 + kTile * nf;       // [kTile][nf]
+    double* __restrict__ A3 = A2 + kTile * nf;       // [kTile][nf]
+    double* __restrict__ SQ = A3 + kTile * nf;       // [kTile][mw]  q~
     double* __restrict__ SN = SQ + kTile * mw;       // [3][np]      nodes
+    double* __restrict__ SC = SN + 3 * np;           // [3][np]      c_k (Hermite)
 
     const int64_t slot = chunk_slot[c];
     const int64_t begin = chunk_begin[c];
@@ -78,10 +123,23 @@ __device__ __forceinline__ void upward_chunk(
     const int wave = tid >> 6;
     if (tid < 3 * np)
         SN[tid] = slot_nodes[slot * 3 * np + tid];
+    if (hermite) {
+        __syncthreads();
+        if (tid < 3 * np) {
+            // c_k = L_k'(s_k) = sum_{j != k} 1 / (s_k - s_j) of dimension tid / np
+            const double* sd = SN + (tid / np) * np;
+            const int k = tid % np;
+            double cs = 0.0;
+            for (int j = 0; j < np; ++j)
+                if (j != k)
+                    cs += 1.0 / (sd[k] - sd[j]);
+            SC[tid] = cs;
+        }
+    }
 
-    const int R = np * mw;                  // rows (k1, m)
+    const int R = nf * mw;                  // rows (k1, m)
     const int RT = (R + 15) / 16;
-    const int CT = (np2 + 15) / 16;         // columns (k2, k3)
+    const int CT = (nf2 + 15) / 16;         // columns (k2, k3)
     const int T = RT * CT;
     const int tbase = pass * kTilesPerGroup + wave;
 
@@ -100,8 +158,8 @@ __device__ __forceinline__ void upward_chunk(
         // rows/cols past the end get index -1: their operand is zero
         rk1[u] = r < R ? r / mw : -1;
         rm[u] = r < R ? r - (r / mw) * mw : 0;
-        ck2[u] = cc < np2 ? cc / np : -1;
-        ck3[u] = cc < np2 ? cc - (cc / np) * np : 0;
+        ck2[u] = cc < nf2 ? cc / nf : -1;
+        ck3[u] = cc < nf2 ? cc - (cc / nf) * nf : 0;
         acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
     }
     __syncthreads();
@@ -112,9 +170,13 @@ __device__ __forceinline__ void upward_chunk(
             if (tid < tn) {
                 const int64_t j = begin + t0 + tid;
                 const double4 p = src[j];
-                const double D = factors_rt(p.x, SN, np, A1 + tid * np) *
-                                 factors_rt(p.y, SN + np, np, A2 + tid * np) *
-                                 factors_rt(p.z, SN + 2 * np, np, A3 + tid * np);
+                const double D =
+                    hermite ? factors_hermite(p.x, SN, SC, np, A1 + tid * nf) *
+                                  factors_hermite(p.y, SN + np, SC + np, np, A2 + tid * nf) *
+                                  factors_hermite(p.z, SN + 2 * np, SC + 2 * np, np, A3 + tid * nf)
+                            : factors_rt(p.x, SN, np, A1 + tid * nf) *
+                                  factors_rt(p.y, SN + np, np, A2 + tid * nf) *
+                                  factors_rt(p.z, SN + 2 * np, np, A3 + tid * nf);
                 const double inv = 1.0 / D;
                 if (mw == 1) {
                     SQ[tid] = p.w * inv;
@@ -124,10 +186,10 @@ __device__ __forceinline__ void upward_chunk(
                 }
             } else {
                 // zero rows: the partial last step of the tile contributes nothing
-                for (int k = 0; k < np; ++k) {
-                    A1[tid * np + k] = 0.0;
-                    A2[tid * np + k] = 0.0;
-                    A3[tid * np + k] = 0.0;
+                for (int k = 0; k < nf; ++k) {
+                    A1[tid * nf + k] = 0.0;
+                    A2[tid * nf + k] = 0.0;
+                    A3[tid * nf + k] = 0.0;
                 }
                 for (int m = 0; m < mw; ++m)
                     SQ[tid * mw + m] = 0.0;
@@ -142,8 +204,8 @@ __device__ __forceinline__ void upward_chunk(
                 for (int u = 0; u < kTilesPerWave; ++u) {
                     if (!live[u])
                         continue;
-                    const double av = rk1[u] >= 0 ? A1[j * np + rk1[u]] * SQ[j * mw + rm[u]] : 0.0;
-                    const double bv = ck2[u] >= 0 ? A2[j * np + ck2[u]] * A3[j * np + ck3[u]] : 0.0;
+                    const double av = rk1[u] >= 0 ? A1[j * nf + rk1[u]] * SQ[j * mw + rm[u]] : 0.0;
+                    const double bv = ck2[u] >= 0 ? A2[j * nf + ck2[u]] * A3[j * nf + ck3[u]] : 0.0;
                     acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
                 }
             }
@@ -161,15 +223,15 @@ __device__ __forceinline__ void upward_chunk(
         const int rt = t / CT;
         const int ct = t - rt * CT;
         const int cc = ct * 16 + (lane & 15);
-        if (cc >= np2)
+        if (cc >= nf2)
             continue;
-        const int k2 = cc / np, k3 = cc - (cc / np) * np;
+        const int k2 = cc / nf, k3 = cc - (cc / nf) * nf;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = rt * 16 + 4 * r + (lane >> 4);
             if (row < R) {
                 const int k1 = row / mw, m = row - (row / mw) * mw;
-                dst[static_cast<int64_t>((k1 * np + k2) * np + k3) * mw + m] = acc[u][r];
+                dst[static_cast<int64_t>((k1 * nf + k2) * nf + k3) * mw + m] = acc[u][r];
             }
         }
     }
@@ -179,11 +241,11 @@ __global__ __launch_bounds__(256) void upward_mfma_f64(
     const double4* __restrict__ src, const double* __restrict__ qm, int32_t mw,
     const int32_t* __restrict__ chunk_slot, const int64_t* __restrict__ chunk_begin,
     const int64_t* __restrict__ chunk_count, const int64_t* __restrict__ chunk_dst,
-    const double* __restrict__ slot_nodes, int32_t np, double* __restrict__ out)
+    const double* __restrict__ slot_nodes, int32_t np, int32_t nf, double* __restrict__ out)
 {
     extern __shared__ double lds[];
-    upward_chunk(src, qm, mw, chunk_slot, chunk_begin, chunk_count, chunk_dst, slot_nodes, np, out,
-                 blockIdx.x, blockIdx.y, lds);
+    upward_chunk(src, qm, mw, chunk_slot, chunk_begin, chunk_count, chunk_dst, slot_nodes, np, nf,
+                 out, blockIdx.x, blockIdx.y, lds);
 }
 
 // the chunks of many systems in one launch: unit = (system, chunk)
@@ -199,7 +261,8 @@ __global__ __launch_bounds__(256) void upward_mfma_f64_many(const UpwardDesc* __
     if (static_cast<int32_t>(blockIdx.y) * kTilesPerGroup >= tiles)
         return;  // this system needs fewer tile passes (uniform over the workgroup)
     upward_chunk(d.src, d.qm, mw, d.chunk_slot, d.chunk_begin, d.chunk_count, d.chunk_dst,
-                 d.slot_nodes, d.np, d.buf, __builtin_amdgcn_readfirstlane(w.y), blockIdx.y, lds);
+                 d.slot_nodes, d.np, d.np, d.buf, __builtin_amdgcn_readfirstlane(w.y), blockIdx.y,
+                 lds);
 }
 
 // qhat (and its FP32 copy) of every slot: the chunk result already in place
@@ -227,17 +290,45 @@ __global__ __launch_bounds__(256) void upward_mfma_reduce(
         qhat32[idx] = static_cast<float>(s);
 }
 
-}  // namespace
-
-size_t upward_lds_bytes(int32_t np, int32_t mw)
+// Hermite modified charges of every slot, regrouped per grid point:
+// qh[slot][k][a] (k = (k1 (n+1) + k2) (n+1) + k3, a = 4 a1 + 2 a2 + a3) is the
+// sum over the slot's chunks, in chunk order, of the blocked chunk result
+// buf[row][((a1 np + k1) nf + a2 np + k2) nf + a3 np + k3], nf = 2 np.  The
+// eight values of one grid point are then one 64-byte wave-uniform load.
+__global__ __launch_bounds__(256) void upward_reduce_hermite(
+    const int32_t* __restrict__ slot_chunk_off, const int64_t* __restrict__ chunk_dst,
+    const double* __restrict__ buf, double* __restrict__ qh, int64_t nslots, int32_t np)
 {
-    return sizeof(double) *
-           (static_cast<size_t>(3) * kTile * np + static_cast<size_t>(kTile) * mw + 3 * np);
+    const int64_t P = static_cast<int64_t>(np) * np * np;
+    const int64_t per_slot = 8 * P;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= nslots * per_slot)
+        return;
+    const int64_t slot = idx / per_slot;
+    const int64_t r = idx - slot * per_slot;
+    const int32_t k = static_cast<int32_t>(r >> 3), a = static_cast<int32_t>(r & 7);
+    const int32_t k1 = k / (np * np), k2 = (k / np) % np, k3 = k % np;
+    const int32_t nf = 2 * np;
+    const int64_t kb = ((((a >> 2) * np + k1) * nf + ((a >> 1) & 1) * np + k2) * nf) +
+                       (a & 1) * np + k3;
+    const int32_t c0 = slot_chunk_off[slot], c1 = slot_chunk_off[slot + 1];
+    double s = 0.0;
+    for (int32_t c = c0; c < c1; ++c)
+        s += buf[chunk_dst[c] * per_slot + kb];
+    qh[idx] = s;
 }
 
-int32_t upward_passes(int32_t np, int32_t mw)
+}  // namespace
+
+size_t upward_lds_bytes(int32_t np, int32_t mw, int32_t nf)
 {
-    const int32_t T = ((np * mw + 15) / 16) * ((np * np + 15) / 16);
+    return sizeof(double) *
+           (static_cast<size_t>(3) * kTile * nf + static_cast<size_t>(kTile) * mw + 6 * np);
+}
+
+int32_t upward_passes(int32_t nf, int32_t mw)
+{
+    const int32_t T = ((nf * mw + 15) / 16) * ((nf * nf + 15) / 16);
     return (T + kTilesPerGroup - 1) / kTilesPerGroup;
 }
 
@@ -257,11 +348,19 @@ hipError_t upward_prepare(size_t lds)
 hipError_t launch_upward_reduce(const DevicePlan& d, int32_t mw, double* buf, float* qhat32,
                                 hipStream_t s)
 {
-    const int32_t np = d.degree + 1;
-    const int64_t per_slot = static_cast<int64_t>(np) * np * np * mw;
+    const int32_t nf = d.hermite ? 2 * (d.degree + 1) : d.degree + 1;
+    const int64_t per_slot = static_cast<int64_t>(nf) * nf * nf * mw;
     const int64_t total = d.nslots * per_slot;
     if (total == 0)
         return hipSuccess;
+    if (d.hermite) {
+        if (mw != 1 || !d.qhat_h)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(upward_reduce_hermite, dim3(static_cast<unsigned>((total + 255) / 256)),
+                           dim3(256), 0, s, d.slot_chunk_off, d.chunk_dst, buf, d.qhat_h, d.nslots,
+                           d.degree + 1);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(upward_mfma_reduce, dim3(static_cast<unsigned>((total + 255) / 256)),
                        dim3(256), 0, s, d.slot_chunk_off, d.chunk_dst, buf, qhat32, d.nslots,
                        per_slot);
@@ -274,13 +373,14 @@ hipError_t launch_upward_mfma(const DevicePlan& d, int32_t mw, double* buf, floa
     if (d.nchunks == 0)
         return hipSuccess;
     const int32_t np = d.degree + 1;
-    const size_t lds = upward_lds_bytes(np, mw);
+    const int32_t nf = d.hermite ? 2 * np : np;
+    const size_t lds = upward_lds_bytes(np, mw, nf);
     hipError_t e = upward_prepare(lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(upward_mfma_f64, dim3(static_cast<unsigned>(d.nchunks), upward_passes(np, mw)),
+    hipLaunchKernelGGL(upward_mfma_f64, dim3(static_cast<unsigned>(d.nchunks), upward_passes(nf, mw)),
                        dim3(256), lds, s, d.src, d.qm, mw, d.chunk_slot, d.chunk_begin,
-                       d.chunk_count, d.chunk_dst, d.slot_nodes, np, buf);
+                       d.chunk_count, d.chunk_dst, d.slot_nodes, np, nf, buf);
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;

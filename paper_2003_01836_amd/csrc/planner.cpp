@@ -219,7 +219,7 @@ void plan_batches(HostPlan& hp)
 {
     const PlanParams& prm = hp.prm;
     hp.np = prm.degree + 1;
-    hp.P = static_cast<int64_t>(hp.np) * hp.np * hp.np;
+    hp.P = static_cast<int64_t>(prm.comps) * hp.np * hp.np * hp.np;
     const Tree& S = hp.src;
     const Tree& T = hp.tgt;
     // batches: leaves of the target tree, ordered by their first position

@@ -43,12 +43,13 @@ struct PlanParams {
     int32_t group_size = 256;       // targets per GPU workgroup
     int64_t chunk_size = 8192;      // sources per upward-pass chunk
     int32_t xcds = 8;               // accelerator dies that round-robin the workgroups
+    int32_t comps = 1;              // modified charges per grid point: 1, or 8 (Hermite)
 };
 
 struct HostPlan {
     PlanParams prm;
     int32_t np = 0;                 // n + 1
-    int64_t P = 0;                  // (n + 1)^3
+    int64_t P = 0;                  // comps (n + 1)^3: modified charges per cluster
     Tree src, tgt;
 
     // batches = leaves of the target tree, in tree (depth-first) order

@@ -1,0 +1,206 @@
+"""GPU barycentric Hermite treecode (method "hermite") against the oracle's.
+
+The library and the oracle build the same trees and lists (checked on the
+host in test_planner_structure.py), so the two differ only in rounding order:
+in FP64, max|d| <= 1e-12 max|phi| and rel-L2 <= 1e-13, as for the BLTC.  The
+modified charges of every approximated cluster are compared with the
+oracle's, component by component (8 per grid point).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.conftest import KERNEL_CASES, kernel_kwargs
+from paper_2003_01836_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL_MAX = 1e-12
+REL_L2 = 1e-13
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2003_01836_amd as bltc
+    bltc.version()
+    return torch.device("cuda:0")
+
+
+def _soa(pos):
+    return np.ascontiguousarray(np.asarray(pos, dtype=np.float64).T)
+
+
+def _close(ref, got, rel_max=REL_MAX, rel_l2=REL_L2):
+    ref = np.asarray(ref)
+    got = np.asarray(got)
+    assert np.all(np.isfinite(got))
+    scale = np.max(np.abs(ref)) if ref.size else 1.0
+    assert np.max(np.abs(ref - got)) <= rel_max * max(scale, 1e-300)
+    assert oracle.rel_l2(ref, got) <= rel_l2
+
+
+def _run(dev, tgt, src, q, **kw):
+    import paper_2003_01836_amd as bltc
+    t = torch.from_numpy(_soa(tgt)).to(dev)
+    s = t if src is tgt else torch.from_numpy(_soa(src)).to(dev)
+    plan = bltc.Plan(t, s, method="hermite", **kw)
+    phi = plan.execute(torch.from_numpy(np.ascontiguousarray(q)).to(dev))
+    torch.cuda.synchronize()
+    return plan, phi.cpu().numpy()
+
+
+@pytest.mark.parametrize("kernel,kappa", KERNEL_CASES)
+def test_hermite_small_config(dev, kernel, kappa):
+    pos, q = inputs.uniform_cube(10000, inputs.config_seed(0))
+    plan, phi = _run(dev, pos, pos, q[0], theta=0.7, degree=3, leaf_size=1000, batch_size=500,
+                     **kernel_kwargs(kernel, kappa)[0])
+    kern = kernel_kwargs(kernel, kappa)[1]
+    oc = oracle.Treecode(pos, pos, 0.7, 3, 1000, 500, hermite=True)
+    ref = oc.potential(q[0], kernel=kern, kappa=kappa)
+    _close(ref, phi)
+    st = plan.stats()
+    assert st["approx_pairs"] > 0 and st["direct_pairs"] > 0
+
+
+def test_hermite_charges_match_oracle(dev):
+    pos, q = inputs.uniform_cube(20000, 181)
+    plan, _ = _run(dev, pos, pos, q[0], theta=0.7, degree=2, leaf_size=300, batch_size=300)
+    oc = oracle.Treecode(pos, pos, 0.7, 2, 300, 300, hermite=True)
+    v = plan.view()
+    sord, oord = v["source_order"], oc.source_order()
+    okey = {}
+    for c in range(oc.n_clusters):
+        info = oc.cluster(c)
+        okey[tuple(np.sort(oord[info["begin"]:info["begin"] + info["count"]]))] = c
+    checked = 0
+    for c in np.unique(v["item_cluster"][v["item_kind"] == 0]):
+        key = tuple(np.sort(sord[v["cluster_begin"][c]:v["cluster_begin"][c] + v["cluster_count"][c]]))
+        ref = oc.hermite_charges(okey[key], q[0])
+        got = plan.modified_charges(c)
+        assert got.shape == ref.shape == (8, 3, 3, 3)
+        # every component against the largest of its own order
+        for a in range(8):
+            assert np.max(np.abs(ref[a] - got[a])) <= 1e-12 * np.max(np.abs(ref[a])), (c, a)
+        checked += 1
+    assert checked > 10
+
+
+@pytest.mark.parametrize("degree,n,leaf", [(1, 12000, 64), (2, 12000, 256), (4, 40000, 1200),
+                                           (6, 80000, 3000), (8, 150000, 6000),
+                                           (10, 200000, 11000)])
+def test_hermite_degrees(dev, degree, n, leaf):
+    pos, q = inputs.uniform_cube(n, 90 + degree)
+    plan, phi = _run(dev, pos, pos, q[0], theta=0.8, degree=degree, leaf_size=leaf, batch_size=300)
+    assert plan.stats()["approx_pairs"] > 0
+    smp = inputs.sample_indices(n, 600, 191 + degree)
+    oc = oracle.Treecode(pos, pos, 0.8, degree, leaf, 300, hermite=True)
+    _close(oc.potential(q[0], sample=smp), phi[smp])
+
+
+def test_hermite_distinct_sets_yukawa(dev):
+    g = np.random.default_rng(182)
+    tgt = g.uniform(-1, 1, (9000, 3))
+    src = g.uniform(-0.4, 1.6, (11000, 3))
+    q = g.uniform(-1, 1, 11000)
+    _, phi = _run(dev, tgt, src, q, theta=0.7, degree=2, leaf_size=400, batch_size=150,
+                  kernel="yukawa", kappa=0.8)
+    oc = oracle.Treecode(tgt, src, 0.7, 2, 400, 150, hermite=True)
+    _close(oc.potential(q, kernel=oracle.YUKAWA, kappa=0.8), phi)
+
+
+def test_hermite_plummer(dev):
+    pos, q = inputs.plummer_sphere(30000, 183)
+    _, phi = _run(dev, pos, pos, q[0], theta=0.7, degree=3, leaf_size=800, batch_size=400)
+    oc = oracle.Treecode(pos, pos, 0.7, 3, 800, 400, hermite=True)
+    _close(oc.potential(q[0]), phi)
+
+
+def test_hermite_theta_zero_is_direct_sum(dev):
+    pos, q = inputs.uniform_cube(4000, 184)
+    plan, phi = _run(dev, pos, pos, q[0], theta=0.0, degree=2, leaf_size=100, batch_size=100)
+    assert plan.stats()["approx_pairs"] == 0
+    _close(oracle.direct(pos, pos, q[0]), phi, 1e-13, 1e-14)
+
+
+def test_hermite_more_accurate_than_lagrange_at_equal_degree(dev):
+    # the Hermite interpolant is exact to degree 2n + 1: at the same grids and
+    # lists it is far more accurate (same trees; leaves large enough for both)
+    import paper_2003_01836_amd as bltc
+    pos, q = inputs.uniform_cube(50000, 185)
+    t = torch.from_numpy(_soa(pos)).to(dev)
+    qd = torch.from_numpy(q[0]).to(dev)
+    smp = inputs.sample_indices(50000, 400, 186)
+    ref = oracle.direct(pos[smp], pos, q[0])
+    kw = dict(theta=0.7, degree=3, leaf_size=1500, batch_size=500)
+    e_h = oracle.rel_l2(ref, bltc.Plan(t, t, method="hermite", **kw).execute(qd).cpu().numpy()[smp])
+    e_l = oracle.rel_l2(ref, bltc.Plan(t, t, method="bltc", **kw).execute(qd).cpu().numpy()[smp])
+    assert e_h < 0.1 * e_l, (e_h, e_l)
+
+
+def test_hermite_device_and_host_plans_agree(dev):
+    import paper_2003_01836_amd as bltc
+    pos, q = inputs.uniform_cube(30000, 187)
+    kw = dict(method="hermite", theta=0.7, degree=3, leaf_size=800, batch_size=250)
+    th = _soa(pos)
+    td = torch.from_numpy(th).to(dev)
+    pd = bltc.Plan(td, td, **kw)
+    ph = bltc.Plan(th, th, host=True, **kw)
+    vd, vh = pd.view(), ph.view()
+    for k in ("source_order", "target_order", "cluster_begin", "cluster_count", "batch_begin",
+              "batch_count"):
+        assert np.array_equal(vd[k], vh[k]), k
+    assert (sorted(zip(vd["item_batch"], vd["item_cluster"], vd["item_kind"])) ==
+            sorted(zip(vh["item_batch"], vh["item_cluster"], vh["item_kind"])))
+    qd = torch.from_numpy(q[0]).to(dev)
+    assert np.array_equal(pd.execute(qd).cpu().numpy(), ph.execute(qd).cpu().numpy())
+
+
+def test_hermite_edge_cases(dev):
+    import paper_2003_01836_amd as bltc
+    g = np.random.default_rng(188)
+    e = torch.zeros((3, 0), dtype=torch.float64, device=dev)
+    pos = g.uniform(-1, 1, (3000, 3))
+    q = g.uniform(-1, 1, 3000)
+    pd = torch.from_numpy(_soa(pos)).to(dev)
+    qd = torch.from_numpy(q).to(dev)
+    # no targets: nothing to do; no sources: zeros
+    assert bltc.Plan(e, pd, method="hermite").execute(qd).numel() == 0
+    z = bltc.Plan(pd, e, method="hermite").execute(torch.zeros(0, dtype=torch.float64, device=dev))
+    assert torch.all(z == 0)
+    # one target, ragged sizes, duplicated targets, identical targets
+    cases = [(pos[:1], 1, 64, 64), (pos[:257], 2, 250, 33),
+             (np.concatenate([pos, pos[:50]]), 1, 70, 40), (np.full((300, 3), 0.5), 2, 240, 10)]
+    for tgt, n, leaf, batch in cases:
+        t = torch.from_numpy(_soa(tgt)).to(dev)
+        phi = bltc.Plan(t, pd, method="hermite", degree=n, leaf_size=leaf,
+                        batch_size=batch).execute(qd).cpu().numpy()
+        oc = oracle.Treecode(tgt, pos, 0.7, n, leaf, batch, hermite=True)
+        _close(oc.potential(q), phi)
+
+
+def test_hermite_sources_on_grid_nodes(dev):
+    # lattice sources coincide with Chebyshev points of their boxes: the
+    # one-hot rule of eq. 5 for A, zero B
+    v = np.linspace(0.0, 1.0, 9)
+    lat = np.array([[a, b, c] for a in v for b in v for c in v])
+    q = np.random.default_rng(189).uniform(-1, 1, len(lat))
+    plan, phi = _run(dev, lat, lat, q, theta=0.6, degree=1, leaf_size=80, batch_size=20)
+    assert plan.stats()["approx_pairs"] > 0
+    oc = oracle.Treecode(lat, lat, 0.6, 1, 80, 20, hermite=True)
+    _close(oc.potential(q), phi)
+
+
+def test_hermite_rejects_unsupported(dev):
+    import paper_2003_01836_amd as bltc
+    pos, q = inputs.uniform_cube(1000, 190)
+    t = torch.from_numpy(_soa(pos)).to(dev)
+    with pytest.raises(bltc.BLTCError):
+        bltc.Plan(t, t, method="hermite", precision="fp32_mixed")
+    with pytest.raises(bltc.BLTCError):
+        bltc.Plan(t, t, method="hermite", degree=11)
+    plan = bltc.Plan(t, t, method="hermite")
+    with pytest.raises(bltc.BLTCError):
+        plan.execute(torch.from_numpy(np.stack([q[0], q[0]])).to(dev))

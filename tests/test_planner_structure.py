@@ -69,11 +69,11 @@ def _cluster_key(order, begin, count):
     return tuple(np.sort(order[begin:begin + count]).tolist())
 
 
-def _compare_with_oracle(tgt, src, theta, degree, leaf, batch):
+def _compare_with_oracle(tgt, src, theta, degree, leaf, batch, hermite=False):
     plan = bltc.Plan(_soa(tgt), _soa(src), host=True, theta=theta, degree=degree,
-                     leaf_size=leaf, batch_size=batch)
+                     leaf_size=leaf, batch_size=batch, method="hermite" if hermite else "bltc")
     v = plan.view()
-    oc = oracle.Treecode(tgt, src, theta, degree, leaf, batch)
+    oc = oracle.Treecode(tgt, src, theta, degree, leaf, batch, hermite=hermite)
     # clusters as sets of source indices, with boxes
     mine = {}
     for c in range(len(v["cluster_begin"])):
@@ -149,3 +149,48 @@ def test_stats_counts():
     assert st["far_evals"] == far and st["near_evals"] == near
     assert st["batches"] == oc.n_batches and st["clusters"] == oc.n_clusters
     assert st["degree"] == 4 and st["leaf_size"] == 500
+
+
+# --- barycentric Hermite treecode: same walk, size test against 8 (n+1)^3 ---
+
+@pytest.mark.parametrize("n,theta,degree,leaf", [
+    (10000, 0.7, 2, 500),
+    (20000, 0.6, 1, 100),
+    (20000, 0.8, 3, 700),
+    (3000, 0.9, 4, 100),        # 8 (n+1)^3 > N: size test fails everywhere
+])
+def test_hermite_structure_matches_oracle(n, theta, degree, leaf):
+    pos, _ = inputs.uniform_cube(n, 300 + n)
+    _compare_with_oracle(pos, pos, theta, degree, leaf, leaf, hermite=True)
+
+
+def test_hermite_structure_plummer_and_lattice():
+    pos, _ = inputs.plummer_sphere(20000, 8)
+    _compare_with_oracle(pos, pos, 0.7, 2, 400, 300, hermite=True)
+    v = np.linspace(0.0, 1.0, 9)
+    lat = np.array([[a, b, c] for a in v for b in v for c in v])
+    _compare_with_oracle(lat, lat, 0.6, 1, 80, 20, hermite=True)
+
+
+def test_hermite_size_test_differs_from_lagrange():
+    # clusters with (n+1)^3 < N_C <= 8 (n+1)^3 are approximated by the BLTC only
+    pos, _ = inputs.uniform_cube(20000, 9)
+    pl, _ = _compare_with_oracle(pos, pos, 0.7, 2, 150, 150)
+    ph, _ = _compare_with_oracle(pos, pos, 0.7, 2, 150, 150, hermite=True)
+    assert ph.stats()["approx_pairs"] < pl.stats()["approx_pairs"]
+    st = ph.stats()
+    v = ph.view()
+    far = sum(v["batch_count"][b] * 8 * 27 for b, k in zip(v["item_batch"], v["item_kind"]) if k == 0)
+    assert st["far_evals"] == far
+
+
+def test_hermite_unsupported_options_are_rejected():
+    pos, _ = inputs.uniform_cube(200, 1)
+    t = _soa(pos)
+    with pytest.raises(bltc.BLTCError):
+        bltc.Plan(t, t, host=True, method="hermite", precision="fp32_mixed")
+    with pytest.raises(bltc.BLTCError):
+        bltc.Plan(t, t, host=True, method="hermite", degree=11)
+    with pytest.raises(bltc.BLTCError):
+        bltc.Plan(t, t, host=True, method="hermite", max_q=2)
+    bltc.Plan(t, t, host=True, method="hermite", degree=10)
