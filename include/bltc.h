@@ -124,6 +124,12 @@ typedef struct {
     int32_t threads_per_target;  /* 0 or 1 (reserved for split target evaluation)      */
     int32_t method;              /* bltc_method                                         */
     double delta;                /* BLTC_REGULARIZED_COULOMB length, >= 0               */
+    int32_t no_symmetry;         /* 0: when the targets are the sources (same arrays,   */
+                                 /* N_B = N_L), methods BLTC_PARTICLE_CLUSTER and       */
+                                 /* BLTC_HERMITE with max_q = 1 evaluate each pair of   */
+                                 /* different leaves that are in each other's direct    */
+                                 /* lists once for both directions (G(x,y) = G(y,x));   */
+                                 /* 1: never.  Same potentials up to rounding order.    */
 } bltc_params;
 
 /* Fills *p with the defaults: Coulomb, FP64, theta 0.7, degree 8,
@@ -209,6 +215,9 @@ typedef struct {
     int32_t leaf_size;
     int32_t batch_size;
     double setup_seconds;    /* planning time (trees and lists)                     */
+    int64_t mutual_pair_evals; /* kernel values computed once for two direct terms:   */
+                             /* sum over mutual leaf pairs of N_B * N_C (no_symmetry */
+                             /* = 0; counted once the device side exists), else 0    */
 } bltc_stats;
 
 int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out);

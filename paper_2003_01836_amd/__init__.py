@@ -40,7 +40,8 @@ def version() -> str:
 
 
 def params(kernel="coulomb", kappa=0.0, theta=0.7, degree=8, leaf_size=2000, batch_size=2000,
-           precision="fp64", threads_per_target=0, method="bltc", delta=0.0) -> _capi.Params:
+           precision="fp64", threads_per_target=0, method="bltc", delta=0.0,
+           symmetry=True) -> _capi.Params:
     p = _capi.Params()
     _capi.load().bltc_params_default(ctypes.byref(p))
     p.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
@@ -53,6 +54,7 @@ def params(kernel="coulomb", kappa=0.0, theta=0.7, degree=8, leaf_size=2000, bat
     p.threads_per_target = int(threads_per_target)
     p.method = _METHODS[method] if isinstance(method, str) else int(method)
     p.delta = float(delta)
+    p.no_symmetry = 0 if symmetry else 1
     return p
 
 

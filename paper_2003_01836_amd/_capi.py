@@ -46,6 +46,7 @@ class Params(ctypes.Structure):
         ("threads_per_target", ctypes.c_int32),
         ("method", ctypes.c_int32),
         ("delta", ctypes.c_double),
+        ("no_symmetry", ctypes.c_int32),
     ]
 
 
@@ -65,6 +66,7 @@ class Stats(ctypes.Structure):
         ("leaf_size", ctypes.c_int32),
         ("batch_size", ctypes.c_int32),
         ("setup_seconds", ctypes.c_double),
+        ("mutual_pair_evals", ctypes.c_int64),
     ]
 
 

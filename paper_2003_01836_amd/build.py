@@ -72,6 +72,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         "cc": os.path.join(build_dir, "cc.o"),
         "kernels_cp": os.path.join(build_dir, "kernels_cp.o"),
         "kernels_hermite": os.path.join(build_dir, "kernels_hermite.o"),
+        "kernels_sym": os.path.join(build_dir, "kernels_sym.o"),
     }
     cmds = [
         ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
@@ -92,6 +93,8 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_cp.hip"), "-o", objs["kernels_cp"]],
         [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_hermite.hip"), "-o",
                                objs["kernels_hermite"]],
+        [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_sym.hip"), "-o",
+                               objs["kernels_sym"]],
     ]
     if verbose:
         for c in cmds:

@@ -44,6 +44,8 @@ int check_params(const bltc_params* p)
         return fail(BLTC_EINVAL, "leaf_size and batch_size must be >= 1");
     if (p->threads_per_target < 0 || p->threads_per_target > 1)
         return fail(BLTC_EUNSUPPORTED, "threads_per_target must be 0 or 1");
+    if (p->no_symmetry != 0 && p->no_symmetry != 1)
+        return fail(BLTC_EINVAL, "no_symmetry must be 0 or 1");
     if (p->method != BLTC_PARTICLE_CLUSTER && p->method != BLTC_CLUSTER_PARTICLE &&
         p->method != BLTC_CLUSTER_CLUSTER && p->method != BLTC_HERMITE)
         return fail(BLTC_EINVAL, "method must be BLTC_PARTICLE_CLUSTER, BLTC_CLUSTER_PARTICLE, "
@@ -136,6 +138,7 @@ int make_device_plan(bltc_plan* plan, const bltc_params* p, int64_t nt, const do
     if (nt == ns && tx == sx && ty == sy && tz == sz && p->batch_size == p->leaf_size) {
         // same particles, same capacity: identical partition
         hp.tgt = hp.src;
+        hp.same_tree = true;
         if (nt > 0) {
             HIP_TRY(hipMemcpyAsync(d.tgt, d.src, nt * sizeof(double4), hipMemcpyDeviceToDevice, s));
             HIP_TRY(hipMemcpyAsync(d.tgt_orig, src_order, nt * sizeof(int64_t),
@@ -176,6 +179,65 @@ int make_device_plan(bltc_plan* plan, const bltc_params* p, int64_t nt, const do
     return BLTC_OK;
 }
 
+// Mutual direct leaf pairs evaluated once (targets are the sources, one charge
+// vector): the units, the reduced direct lists and the per-batch unit results
+// on the device, and the workgroup schedule re-ordered for the work left to
+// the batches.  Plans that do not qualify keep their lists (d.sym = 0).
+int upload_symmetric(bltc_plan* plan, hipStream_t s)
+{
+    bltc::HostPlan& hp = plan->hp;
+    bltc::DevicePlan& d = plan->d;
+    if (plan->prm.no_symmetry || plan->max_q != 1 || !hp.same_tree ||
+        (plan->prm.method != BLTC_PARTICLE_CLUSTER && plan->prm.method != BLTC_HERMITE))
+        return BLTC_OK;
+    const int64_t nb = static_cast<int64_t>(hp.batch_node.size());
+    const int64_t nnear = nb > 0 ? hp.near_off[nb] : 0;
+    std::vector<int32_t> near_leaf;
+    if (plan->device_lists) {
+        near_leaf.resize(nnear);
+        if (nnear > 0)
+            HIP_TRY(hipMemcpy(near_leaf.data(), d.near_leaf, nnear * sizeof(int32_t),
+                              hipMemcpyDeviceToHost));
+    } else {
+        near_leaf = hp.near_leaf;
+    }
+    // unit results: at most 2^31 values (16 GiB)
+    bltc::SymPlan sp;
+    if (!bltc::plan_symmetric(hp, near_leaf, int64_t(1) << 31, bltc::kSymMaxCols, sp))
+        return BLTC_OK;
+    std::vector<bltc::SymUnit> units(sp.ub.size());
+    for (size_t k = 0; k < units.size(); ++k) {
+        const int32_t b = sp.ub[k], c = sp.uc[k];
+        units[k].tb = hp.batch_begin[b];
+        units[k].sb = hp.batch_begin[c];
+        units[k].off = sp.uoff[k];
+        units[k].nb = static_cast<int32_t>(hp.batch_count[b]);
+        units[k].nc = static_cast<int32_t>(hp.batch_count[c]);
+        units[k].batch = b;
+        units[k].leaf = hp.batch_node[c];
+    }
+    HIP_TRY(plan->put(&d.sym_unit, units, s));
+    HIP_TRY(plan->alloc(&d.sym_out, static_cast<size_t>(sp.out_size)));
+    HIP_TRY(plan->put(&d.sym_near_off, sp.near_off, s));
+    HIP_TRY(plan->put(&d.sym_near_begin, sp.near_begin, s));
+    HIP_TRY(plan->put(&d.sym_near_count, sp.near_count, s));
+    HIP_TRY(plan->put(&d.sym_near_leaf, sp.near_leaf, s));
+    HIP_TRY(plan->put(&d.sym_pc_off, sp.pc_off, s));
+    HIP_TRY(plan->put(&d.sym_pc_base, sp.pc_base, s));
+    HIP_TRY(plan->put(&d.batch_begin, hp.batch_begin, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    d.sym_units = static_cast<int64_t>(units.size());
+    d.sym_max_cols = sp.max_cols;
+    d.sym = 1;
+    plan->sym_pair_evals = sp.pair_evals;
+    hp.group_batch.clear();
+    hp.group_first.clear();
+    bltc::group_schedule(hp.batch_begin, hp.batch_count, sp.batch_cost, hp.prm.group_size,
+                         hp.prm.xcds, hp.group_batch, hp.group_first);
+    d.ngroups = static_cast<int64_t>(hp.group_batch.size());
+    return BLTC_OK;
+}
+
 }  // namespace
 
 int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
@@ -212,6 +274,9 @@ int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
         d.src_order = src_order;
         HIP_TRY(hipStreamSynchronize(s));
     }
+    int rc = upload_symmetric(plan, s);
+    if (rc != BLTC_OK)
+        return rc;
     std::vector<int64_t> batch_end(d.nbatches);
     for (int64_t b = 0; b < d.nbatches; ++b)
         batch_end[b] = hp.batch_begin[b] + hp.batch_count[b];
@@ -374,6 +439,8 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
         HIP_TRY(mark(0, 1));
         HIP_TRY(bltc::launch_upward_mfma(d, 1, d.qhat, d.qhat32, s));
         HIP_TRY(mark(0, 2));
+        if (d.sym)
+            HIP_TRY(bltc::launch_near_pairs(d, kp, s));
         if (d.hermite)
             HIP_TRY(bltc::launch_interact_hermite(d, kp, phi, s));
         else if (kp.precision == BLTC_FP32_MIXED)
@@ -629,6 +696,7 @@ int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out)
     out->leaf_size = plan->prm.leaf_size;
     out->batch_size = plan->prm.batch_size;
     out->setup_seconds = hp.setup_seconds;
+    out->mutual_pair_evals = plan->sym_pair_evals;
     return BLTC_OK;
 }
 

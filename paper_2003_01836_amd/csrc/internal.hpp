@@ -96,6 +96,8 @@ struct bltc_plan {
     bool timing = false;
     int32_t last_q = 0;                  // charge vectors of the last execution
     int32_t timed_q = 0;                 // charge vectors covered by the recorded events
+    int64_t sym_pair_evals = 0;          // kernel values of the mutual leaf pairs (each serving
+                                         // two direct terms), once uploaded
     std::vector<hipEvent_t> events;      // 4 per charge vector
 
     ~bltc_plan()

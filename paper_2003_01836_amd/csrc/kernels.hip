@@ -71,7 +71,10 @@ __global__ __launch_bounds__(kGroupSize) void interact_f64(
     const int32_t* __restrict__ far_off, const int32_t* __restrict__ far_slot,
     const int32_t* __restrict__ near_off, const int64_t* __restrict__ near_begin,
     const int64_t* __restrict__ near_count, const double* __restrict__ slot_nodes,
-    const double* __restrict__ qhat, double* __restrict__ phi, KernelConst kc)
+    const double* __restrict__ qhat,
+    const int32_t* __restrict__ pc_off, const int64_t* __restrict__ pc_base,
+    const double* __restrict__ pair_out, const int64_t* __restrict__ batch_begin,
+    double* __restrict__ phi, KernelConst kc)
 {
     constexpr int NP = N + 1;
     constexpr int P = NP * NP * NP;
@@ -106,6 +109,13 @@ __global__ __launch_bounds__(kGroupSize) void interact_f64(
         acc += near_sum_f64<KER>(t.x, t.y, t.z, src + near_begin[e],
                                  static_cast<int32_t>(near_count[e]), kappa);
 
+    if (pc_off) {
+        // mutual leaf pairs: this target's row or column sums of each unit
+        const int64_t pos = i - batch_begin[b];
+        const int pc_end = pc_off[b + 1];
+        for (int e = pc_off[b]; e < pc_end; ++e)
+            acc += pair_out[pc_base[e] + pos];
+    }
     if (valid)
         phi[tgt_orig[i]] = acc;
 }
@@ -172,10 +182,12 @@ hipError_t run_interact(const DevicePlan& d, double* phi, KernelConst kc, hipStr
 {
     if (d.ngroups == 0)
         return hipSuccess;
+    const NearLists nl = near_lists(d);
     hipLaunchKernelGGL((interact_f64<N, KER>), dim3(static_cast<unsigned>(d.ngroups)),
                        dim3(kGroupSize), 0, s, d.tgt, d.tgt_orig, d.src, d.group_batch,
-                       d.group_first, d.batch_end, d.far_off, d.far_slot, d.near_off,
-                       d.near_begin, d.near_count, d.slot_nodes, d.qhat, phi, kc);
+                       d.group_first, d.batch_end, d.far_off, d.far_slot, nl.off, nl.begin,
+                       nl.count, d.slot_nodes, d.qhat, nl.pc_off, nl.pc_base, nl.pair_out,
+                       nl.batch_begin, phi, kc);
     return hipGetLastError();
 }
 

@@ -11,6 +11,31 @@ constexpr int kMaxDegree = 16;
 constexpr int kMaxHermiteDegree = 10;   // Hermite treecode: 8 (n+1)^3 charges per cluster
 constexpr int kGroupSize = 256;      // targets (lanes) per interaction workgroup
 
+// The direct lists the single-vector interaction kernels walk: the plan's own,
+// or, when mutual leaf pairs are evaluated by launch_near_pairs, the reduced
+// lists plus per batch the unit results to add (pc_off == nullptr: none).
+struct NearLists {
+    const int32_t* off;
+    const int64_t* begin;
+    const int64_t* count;
+    const int32_t* leaf;
+    const int32_t* pc_off;
+    const int64_t* pc_base;
+    const double* pair_out;
+    const int64_t* batch_begin;
+};
+
+// One mutual pair of leaves (B, C) of a plan whose targets are its sources:
+// B's particles at tree positions [tb, tb + nb), C's at [sb, sb + nc); row sums
+// (potential at B's targets from C's sources) to out[off + i], column sums
+// (at C's targets from B's sources) to out[off + nb + j].
+struct SymUnit {
+    int64_t tb, sb, off;
+    int32_t nb, nc;
+    int32_t batch;    // B's batch (batch_info)
+    int32_t leaf;     // C's node (node_info)
+};
+
 // Device-side view of a plan (all device pointers).
 struct DevicePlan {
     int32_t degree = 0;
@@ -55,6 +80,21 @@ struct DevicePlan {
     float* qhat16f = nullptr;         // [slot][P][16] (mixed precision)
     // Hermite: modified charges regrouped per grid point, [slot][(n+1)^3][8]
     double* qhat_h = nullptr;
+    // symmetric near field (one charge vector): mutual leaf pairs evaluated once
+    // by launch_near_pairs; the interaction kernels then take the reduced direct
+    // lists and add, per target, the unit results listed in sym_pc_*
+    int32_t sym = 0;
+    int64_t sym_units = 0;
+    int64_t sym_max_cols = 0;
+    SymUnit* sym_unit = nullptr;
+    double* sym_out = nullptr;
+    int32_t* sym_near_off = nullptr;
+    int64_t* sym_near_begin = nullptr;
+    int64_t* sym_near_count = nullptr;
+    int32_t* sym_near_leaf = nullptr;
+    int32_t* sym_pc_off = nullptr;
+    int64_t* sym_pc_base = nullptr;
+    int64_t* batch_begin = nullptr;
 };
 
 // Constants of the kernel G passed to the interaction kernels: kappa of the
@@ -136,6 +176,19 @@ hipError_t launch_upward_reduce(const DevicePlan& d, int32_t mw, double* buf, fl
 // Hermite approximation and direct sums (kernels_hermite.hip), FP64, n <= 10
 hipError_t launch_interact_hermite(const DevicePlan& d, const KernelParams& kp, double* phi,
                                    hipStream_t s);
+inline NearLists near_lists(const DevicePlan& d)
+{
+    if (d.sym)
+        return NearLists{d.sym_near_off, d.sym_near_begin, d.sym_near_count, d.sym_near_leaf,
+                         d.sym_pc_off,   d.sym_pc_base,    d.sym_out,        d.batch_begin};
+    return NearLists{d.near_off, d.near_begin, d.near_count, d.near_leaf,
+                     nullptr,    nullptr,      nullptr,      nullptr};
+}
+// near field of the mutual leaf pairs (kernels_sym.hip): d.sym_units units
+// into d.sym_out, FP64 or FP32-mixed as kp.precision
+hipError_t launch_near_pairs(const DevicePlan& d, const KernelParams& kp, hipStream_t s);
+// largest leaf (column count) launch_near_pairs accepts
+constexpr int64_t kSymMaxCols = 8000;
 // batch/cluster interactions: eqs. 9 and 11, phi written in caller order
 hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* phi,
                            hipStream_t s);

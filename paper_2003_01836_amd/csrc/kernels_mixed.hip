@@ -157,7 +157,10 @@ __global__ __launch_bounds__(kGroupSize) void interact_mixed(
     const int32_t* __restrict__ far_slot, const int32_t* __restrict__ near_off,
     const int64_t* __restrict__ near_begin, const int64_t* __restrict__ near_count,
     const int32_t* __restrict__ near_leaf, const double* __restrict__ slot_nodes,
-    const float* __restrict__ qhat32, double* __restrict__ phi, KernelConst kc)
+    const float* __restrict__ qhat32,
+    const int32_t* __restrict__ pc_off, const int64_t* __restrict__ pc_base,
+    const double* __restrict__ pair_out, const int64_t* __restrict__ batch_begin,
+    double* __restrict__ phi, KernelConst kc)
 {
     constexpr int NP = N + 1;
     constexpr int P = NP * NP * NP;
@@ -200,6 +203,13 @@ __global__ __launch_bounds__(kGroupSize) void interact_mixed(
         acc += near_sum_mixed<KER>(t.x, t.y, t.z, src32 + nb, src + nb,
                                    static_cast<int32_t>(near_count[e]), li, tau2, nk, kappa);
     }
+    if (pc_off) {
+        // mutual leaf pairs: this target's row or column sums of each unit
+        const int64_t pos = i - batch_begin[b];
+        const int pc_end = pc_off[b + 1];
+        for (int e = pc_off[b]; e < pc_end; ++e)
+            acc += pair_out[pc_base[e] + pos];
+    }
     if (valid)
         phi[tgt_orig[i]] = acc;
 }
@@ -209,11 +219,12 @@ hipError_t run_interact_mixed(const DevicePlan& d, double* phi, KernelConst kc, 
 {
     if (d.ngroups == 0)
         return hipSuccess;
+    const NearLists nl = near_lists(d);
     hipLaunchKernelGGL((interact_mixed<N, KER>), dim3(static_cast<unsigned>(d.ngroups)),
                        dim3(kGroupSize), 0, s, d.tgt, d.tgt_orig, d.src, d.src32, d.node_info,
                        d.batch_info, d.group_batch, d.group_first, d.batch_end, d.far_off,
-                       d.far_slot, d.near_off, d.near_begin, d.near_count, d.near_leaf,
-                       d.slot_nodes, d.qhat32, phi, kc);
+                       d.far_slot, nl.off, nl.begin, nl.count, nl.leaf, d.slot_nodes, d.qhat32,
+                       nl.pc_off, nl.pc_base, nl.pair_out, nl.batch_begin, phi, kc);
     return hipGetLastError();
 }
 

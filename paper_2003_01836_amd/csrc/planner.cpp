@@ -17,6 +17,7 @@
 #include "planner.hpp"
 
 #include <algorithm>
+#include <map>
 #include <atomic>
 #include <chrono>
 #include <climits>
@@ -197,9 +198,10 @@ std::string make_plan(HostPlan& hp, const PlanParams& prm,
     hp.prm = prm;
 
     build_tree(hp.src, ns, sx, sy, sz, prm.leaf_size);
-    if (nt == ns && tx == sx && ty == sy && tz == sz && prm.batch_size == prm.leaf_size)
+    if (nt == ns && tx == sx && ty == sy && tz == sz && prm.batch_size == prm.leaf_size) {
         hp.tgt = hp.src;    // same particles, same capacity: identical partition
-    else
+        hp.same_tree = true;
+    } else
         build_tree(hp.tgt, nt, tx, ty, tz, prm.batch_size);
     plan_from_trees(hp);
 
@@ -502,6 +504,91 @@ void plan_schedule(HostPlan& hp)
 
     group_schedule(hp.batch_begin, hp.batch_count, hp.batch_cost, prm.group_size, prm.xcds,
                    hp.group_batch, hp.group_first);
+}
+
+bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, int64_t max_out,
+                    int64_t max_cols, SymPlan& sp)
+{
+    if (!hp.same_tree)
+        return false;
+    const Tree& S = hp.src;
+    const int64_t nb = static_cast<int64_t>(hp.batch_node.size());
+    if (static_cast<int64_t>(near_leaf.size()) != (nb > 0 ? hp.near_off[nb] : 0))
+        return false;
+    std::vector<int32_t> batch_of_node(S.nodes(), -1);
+    for (int64_t b = 0; b < nb; ++b)
+        batch_of_node[hp.batch_node[b]] = static_cast<int32_t>(b);
+    // sorted direct partners (as batches) of every batch, for membership tests
+    std::vector<std::vector<int32_t>> partners(nb);
+    for (int64_t b = 0; b < nb; ++b) {
+        for (int32_t e = hp.near_off[b]; e < hp.near_off[b + 1]; ++e) {
+            const int32_t c = batch_of_node[near_leaf[e]];
+            if (c < 0)
+                return false;   // a direct entry that is not a leaf
+            partners[b].push_back(c);
+        }
+        std::sort(partners[b].begin(), partners[b].end());
+    }
+    auto has = [&](int64_t b, int32_t c) {
+        return std::binary_search(partners[b].begin(), partners[b].end(), c);
+    };
+    // units: every mutual pair once, from its lower batch
+    std::vector<std::pair<int32_t, int32_t>> units;
+    for (int64_t b = 0; b < nb; ++b)
+        for (int32_t c : partners[b])
+            if (c > b && has(c, static_cast<int32_t>(b)))
+                units.emplace_back(static_cast<int32_t>(b), c);
+    if (units.empty())
+        return false;
+    auto evals = [&](const std::pair<int32_t, int32_t>& u) {
+        return hp.batch_count[u.first] * hp.batch_count[u.second];
+    };
+    std::stable_sort(units.begin(), units.end(),
+                     [&](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& c) {
+                         return evals(a) > evals(c);
+                     });
+    SymPlan out;
+    int64_t off = 0;
+    std::map<std::pair<int32_t, int32_t>, int64_t> unit_of;
+    for (size_t k = 0; k < units.size(); ++k) {
+        const auto& u = units[k];
+        out.ub.push_back(u.first);
+        out.uc.push_back(u.second);
+        out.uoff.push_back(off);
+        unit_of[u] = static_cast<int64_t>(k);
+        off += hp.batch_count[u.first] + hp.batch_count[u.second];
+        out.max_cols = std::max(out.max_cols, hp.batch_count[u.second]);
+        out.pair_evals += evals(u);
+    }
+    out.out_size = off;
+    if (out.out_size > max_out || out.max_cols > max_cols)
+        return false;
+    // reduced lists in the original list order, and the costs left to the batches
+    out.near_off.assign(nb + 1, 0);
+    out.pc_off.assign(nb + 1, 0);
+    out.batch_cost = hp.batch_cost;
+    for (int64_t b = 0; b < nb; ++b) {
+        for (int32_t e = hp.near_off[b]; e < hp.near_off[b + 1]; ++e) {
+            const int32_t leaf = near_leaf[e];
+            const int32_t c = batch_of_node[leaf];
+            const bool mutual = c != b && has(c, static_cast<int32_t>(b));
+            if (!mutual) {
+                out.near_leaf.push_back(leaf);
+                out.near_begin.push_back(S.begin[leaf]);
+                out.near_count.push_back(S.count[leaf]);
+                continue;
+            }
+            const int32_t lo = std::min<int32_t>(static_cast<int32_t>(b), c);
+            const int32_t hi = std::max<int32_t>(static_cast<int32_t>(b), c);
+            const int64_t u = unit_of[{lo, hi}];
+            out.pc_base.push_back(b == lo ? out.uoff[u] : out.uoff[u] + hp.batch_count[lo]);
+            out.batch_cost[b] -= S.count[leaf] - 1;   // one read instead of |C| evaluations
+        }
+        out.near_off[b + 1] = static_cast<int32_t>(out.near_leaf.size());
+        out.pc_off[b + 1] = static_cast<int32_t>(out.pc_base.size());
+    }
+    sp = std::move(out);
+    return true;
 }
 
 // ---------------------------------------------------------------------------

@@ -94,7 +94,38 @@ struct HostPlan {
     int64_t far_evals = 0, near_evals = 0, upward_terms = 0;
     int64_t leaves = 0;
     double setup_seconds = 0.0;
+
+    // targets are the sources (same arrays, same capacity): the target tree is
+    // the source tree and batch b is the leaf batch_node[b]
+    bool same_tree = false;
 };
+
+// Mutual direct pairs of a plan whose batches are the leaves of its source
+// tree.  G(x, y) = G(y, x), so two different leaves B and C, each in the
+// other's direct list, form one unit evaluated once for both directions: the
+// row sums (B's targets, C's sources) and the column sums (C's targets, B's
+// sources) go to out[off .. off + |B|) and out[off + |B| .. off + |B| + |C|).
+struct SymPlan {
+    std::vector<int32_t> ub, uc;        // batches of a unit, ub < uc; heaviest unit first
+    std::vector<int64_t> uoff;          // out offset of a unit
+    int64_t out_size = 0;
+    int64_t max_cols = 0;               // largest |C|
+    int64_t pair_evals = 0;             // sum over units of |B| |C|
+    // per batch: the direct entries that are not mutual (leaf, range) ...
+    std::vector<int32_t> near_off, near_leaf;
+    std::vector<int64_t> near_begin, near_count;
+    // ... and the out offsets of its side of every mutual pair, in list order
+    std::vector<int32_t> pc_off;
+    std::vector<int64_t> pc_base;
+    std::vector<int64_t> batch_cost;    // evaluations per target left to the batch's workgroups
+};
+
+// Builds sp from the direct lists (hp.near_off, the leaf of every entry in
+// near_leaf).  Returns false (sp untouched) when hp.same_tree is false, when
+// there is no mutual pair, or when out_size would exceed max_out values or a
+// leaf more than max_cols particles.
+bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, int64_t max_out,
+                    int64_t max_cols, SymPlan& sp);
 
 // Builds the tree with leaf capacity `cap` (readings of the tree rules are
 // documented in planner.cpp).
