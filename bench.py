@@ -37,9 +37,15 @@ FLOPS_YUKAWA = 15                   # + r = r^2 * (1/r), -kappa r, exp, product
 FLOPS_HERMITE_POINT = 37
 
 
+# a mutual direct pair (targets = sources): one kernel value (11) serving the
+# row term and the column term (+ 1 multiply-add, 2)
+FLOPS_MUTUAL_PAIR = 13
+
 KERNEL_SOURCES = {
     "interact_mixed": ["kernels_mixed.hip", "device_common.hpp", "kernels.hpp"],
     "interact_f64": ["kernels.hip", "device_common.hpp", "kernels.hpp"],
+    "near_pairs_mixed": ["kernels_sym.hip", "device_common.hpp", "kernels.hpp"],
+    "near_pairs_f64": ["kernels_sym.hip", "device_common.hpp", "kernels.hpp"],
 }
 
 
@@ -54,7 +60,8 @@ def counter_traffic(kernel, degree, ker_id):
     for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2003_01836_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    want = f"traffic_bytes {kernel}<{degree}, {ker_id}> "
+    want = (f"traffic_bytes {kernel}<{degree}, {ker_id}> " if kernel.startswith("interact")
+            else f"traffic_bytes {kernel}<{ker_id}> ")
     with open(path) as fh:
         for line in fh:
             if line.startswith(want):
@@ -381,7 +388,7 @@ def run_hermite(args, dev):
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / args.steps
         plan.set_timing(True)
-        ph = {"gather": 0.0, "upward": 0.0, "interact": 0.0, "total": 0.0}
+        ph = {"gather": 0.0, "upward": 0.0, "interact": 0.0, "total": 0.0, "mutual_pairs": 0.0}
         for _ in range(args.steps):
             plan.execute(qd, out=phi)
             for k, v in plan.phase_times().items():
@@ -389,15 +396,20 @@ def run_hermite(args, dev):
         plan.set_timing(False)
         got[deg] = phi.cpu().numpy()
         points = st["far_evals"] // 8      # far_evals counts 8 values per grid point
-        flops = points * FLOPS_HERMITE_POINT + st["near_evals"] * FLOPS_COULOMB
+        mutual = st["mutual_pair_evals"]   # direct kernel values serving two terms
+        flops = (points * FLOPS_HERMITE_POINT + (st["near_evals"] - 2 * mutual) * FLOPS_COULOMB +
+                 mutual * FLOPS_MUTUAL_PAIR)
         ach = flops / (ph["interact"] * 1e-3) / 1e12
         res["degrees"][deg] = {
             "ms_per_step": ms, "targets_per_s": n / (ms * 1e-3), "plan_s": t_plan,
             "phases_ms": ph, "grid_point_evals": points, "near_evals": st["near_evals"],
+            "mutual_pair_evals": mutual,
             "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"],
             "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
-                         "traffic": None, "kernel": f"interact_hermite_f64<{deg}, 0>",
+                         "traffic": None,
+                         "kernel": f"interaction phase: interact_hermite_f64<{deg}, 0> + "
+                                   f"near_pairs_f64<0>",
                          "flops_per_grid_point": FLOPS_HERMITE_POINT,
                          "flops_per_near_eval": FLOPS_COULOMB}}
         log(f"hermite n={deg}: {ms:.2f} ms/step, phases {ph}")
@@ -542,7 +554,7 @@ def main():
         ms_step = 1e3 * t_total / args.steps
         # per-phase device times (HIP events on the execution stream), separate pass
         plan.set_timing(True)
-        ph = {"gather": 0.0, "upward": 0.0, "interact": 0.0, "total": 0.0}
+        ph = {"gather": 0.0, "upward": 0.0, "interact": 0.0, "total": 0.0, "mutual_pairs": 0.0}
         for _ in range(args.steps):
             plan.execute(qd, out=phi)
             for k, v in plan.phase_times().items():
@@ -586,12 +598,32 @@ def main():
     r = results[best]
     st = r["stats"]
     flops_eval = FLOPS_YUKAWA if w["kernel"] == "yukawa" else FLOPS_COULOMB
+    flops_pair = flops_eval + 2
     evals = st["far_evals"] + st["near_evals"]
-    t_int = r["phases"]["interact"] * 1e-3
-    achieved = evals * flops_eval / t_int / 1e12
+    ker_id = 1 if w["kernel"] == "yukawa" else 0
     peak = FP64_VECTOR_PEAK_TFLOPS if best == "fp64" else FP32_VECTOR_PEAK_TFLOPS
-    kname = "interact_f64" if best == "fp64" else "interact_mixed"
-    traffic = counter_traffic(kname, w["degree"], 1 if w["kernel"] == "yukawa" else 0)
+    suffix = "f64" if best == "fp64" else "mixed"
+    # the interaction phase is two launches when mutual direct pairs are evaluated
+    # once: the pair kernel (kernel values = mutual_pair_evals, each serving two
+    # direct terms) and the batch kernel (far field, the other direct terms)
+    mutual = st.get("mutual_pair_evals", 0)
+    t_pairs = r["phases"].get("mutual_pairs", 0.0)
+    t_batch = r["phases"]["interact"] - t_pairs
+    kernels = {
+        f"interact_{suffix}": {"evals": evals - 2 * mutual, "flops_per_eval": flops_eval,
+                               "ms_per_launch": t_batch},
+    }
+    if mutual:
+        kernels[f"near_pairs_{suffix}"] = {"evals": mutual, "flops_per_eval": flops_pair,
+                                           "ms_per_launch": t_pairs}
+    for kn, kv in kernels.items():
+        kv["achieved"] = kv["evals"] * kv["flops_per_eval"] / (kv["ms_per_launch"] * 1e-3) / 1e12
+        kv["frac"] = kv["achieved"] / peak
+        kv["traffic"] = counter_traffic(kn, w["degree"], ker_id)
+    kname = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])
+    kd = kernels[kname]
+    phase_flops = sum(v["evals"] * v["flops_per_eval"] for v in kernels.values())
+    phase_achieved = phase_flops / (r["phases"]["interact"] * 1e-3) / 1e12
     line = {
         "metric": "targets/s at rel-L2 err <=1e-6 (BLTC evaluation phase)",
         "value": n / (r["ms"] * 1e-3),
@@ -608,19 +640,23 @@ def main():
         "config": {"workload": f"{args.workload}: N={n} uniform [-1,1]^3, charges U[-1,1], "
                                f"{w['kernel']}, theta={w['theta']}, n={w['degree']}, "
                                f"N_L=N_B={w['leaf']}", "path": best},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic,
-                     "kernel": kname, "flops_per_eval": flops_eval,
-                     "evals_per_launch": evals, "ms_per_launch": r["phases"]["interact"]},
+        "roofline": {"bound": "alu", "achieved": kd["achieved"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": kd["frac"], "traffic": kd["traffic"],
+                     "kernel": kname, "flops_per_eval": kd["flops_per_eval"],
+                     "evals_per_launch": kd["evals"], "ms_per_launch": kd["ms_per_launch"],
+                     "interaction_kernels": kernels,
+                     "interaction_phase": {"achieved": phase_achieved, "frac": phase_achieved / peak,
+                                           "ms": r["phases"]["interact"]}},
         "cpu_baseline": cpu,
         "paths": {p: {"targets_per_s": n / (v["ms"] * 1e-3), "ms_per_step": v["ms"],
                       "phases_ms": v["phases"], "plan_s": v["t_plan"],
                       "end_to_end_targets_per_s": n / (v["t_plan"] + v["ms"] * 1e-3),
-                      "evals_per_s": evals / (v["phases"]["interact"] * 1e-3),
+                      "terms_per_s": evals / (v["phases"]["interact"] * 1e-3),
                       **errors.get(p, {})} for p, v in results.items()},
         "oracle_E_tc": errors.get("oracle", {}).get("E_tc"),
         "stats": {k: st[k] for k in ("clusters", "batches", "approx_pairs", "direct_pairs",
-                                     "far_evals", "near_evals", "upward_terms", "depth")},
+                                     "far_evals", "near_evals", "upward_terms", "depth",
+                                     "mutual_pair_evals")},
     }
     print(json.dumps(line), flush=True)
     return 0

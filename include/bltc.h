@@ -227,10 +227,12 @@ int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out);
  * stream around each phase; bltc_plan_phase_times waits for the last
  * execution's events and writes its device milliseconds:
  *   ms[0] charges gathered into tree order, ms[1] upward pass (eqs. 14-15),
- *   ms[2] batch/cluster interactions (eqs. 9, 11), ms[3] total.
+ *   ms[2] batch/cluster interactions (eqs. 9, 11), ms[3] total, ms[4] the
+ *   part of ms[2] spent on mutual direct leaf pairs (see no_symmetry; 0 when
+ *   the execution had none).
  * BLTC_EINVAL if timing is off or nothing was executed since it was enabled. */
 int bltc_plan_set_timing(bltc_plan* plan, int32_t enable);
-int bltc_plan_phase_times(bltc_plan* plan, double* ms /* [4] */);
+int bltc_plan_phase_times(bltc_plan* plan, double* ms /* [5] */);
 
 /* Read-only HOST view of a plan's structure (valid until the plan is
  * destroyed).  Cluster ids index the cluster arrays; the children of cluster c

@@ -168,9 +168,10 @@ class Plan:
 
     def phase_times(self) -> dict:
         """Device milliseconds of the last execution's phases (timing must be on)."""
-        ms = (ctypes.c_double * 4)()
+        ms = (ctypes.c_double * 5)()
         _capi.check(self._lib.bltc_plan_phase_times(self._h, ms))
-        return {"gather": ms[0], "upward": ms[1], "interact": ms[2], "total": ms[3]}
+        return {"gather": ms[0], "upward": ms[1], "interact": ms[2], "total": ms[3],
+                "mutual_pairs": ms[4]}
 
     def view(self) -> dict:
         """Copies of the plan's host-side structure (numpy arrays)."""

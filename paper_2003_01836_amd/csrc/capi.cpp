@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -439,8 +440,14 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
         HIP_TRY(mark(0, 1));
         HIP_TRY(bltc::launch_upward_mfma(d, 1, d.qhat, d.qhat32, s));
         HIP_TRY(mark(0, 2));
-        if (d.sym)
+        if (d.sym) {
             HIP_TRY(bltc::launch_near_pairs(d, kp, s));
+            if (plan->timing) {
+                if (!plan->ev_pairs)
+                    HIP_TRY(hipEventCreate(&plan->ev_pairs));
+                HIP_TRY(hipEventRecord(plan->ev_pairs, s));
+            }
+        }
         if (d.hermite)
             HIP_TRY(bltc::launch_interact_hermite(d, kp, phi, s));
         else if (kp.precision == BLTC_FP32_MIXED)
@@ -463,6 +470,7 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
         }
     }
     plan->timed_q = plan->timing ? units : 0;
+    plan->timed_pairs = plan->timing && num_q == 1 && d.sym;
     plan->last_q = num_q;
     return BLTC_OK;
 }
@@ -795,6 +803,12 @@ int bltc_plan_phase_times(bltc_plan* plan, double* ms)
     for (int k = 0; k < 3; ++k)
         ms[k] = acc[k];
     ms[3] = acc[0] + acc[1] + acc[2];
+    ms[4] = 0.0;
+    if (plan->timed_pairs) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, plan->events[2], plan->ev_pairs));
+        ms[4] = t;
+    }
     return BLTC_OK;
 }
 

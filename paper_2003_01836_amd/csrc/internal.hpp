@@ -99,11 +99,15 @@ struct bltc_plan {
     int64_t sym_pair_evals = 0;          // kernel values of the mutual leaf pairs (each serving
                                          // two direct terms), once uploaded
     std::vector<hipEvent_t> events;      // 4 per charge vector
+    hipEvent_t ev_pairs = nullptr;       // after the mutual-pair launch (timing)
+    bool timed_pairs = false;            // ev_pairs belongs to the recorded execution
 
     ~bltc_plan()
     {
         for (hipEvent_t e : events)
             (void)hipEventDestroy(e);
+        if (ev_pairs)
+            (void)hipEventDestroy(ev_pairs);
         for (void* p : allocations)
             (void)hipFree(p);
     }

@@ -189,6 +189,9 @@ inline NearLists near_lists(const DevicePlan& d)
 hipError_t launch_near_pairs(const DevicePlan& d, const KernelParams& kp, hipStream_t s);
 // largest leaf (column count) launch_near_pairs accepts
 constexpr int64_t kSymMaxCols = 8000;
+// the FP32-mixed path computes the kernel values of pairs closer than
+// kMixedTauRel * (distance of the box centers + r_B + 2 r_C) from FP64 coordinates
+constexpr double kMixedTauRel = 2.4e-2;
 // batch/cluster interactions: eqs. 9 and 11, phi written in caller order
 hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* phi,
                            hipStream_t s);

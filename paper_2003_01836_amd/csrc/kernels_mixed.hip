@@ -26,10 +26,7 @@ namespace {
 
 using namespace dev;
 
-#ifndef BLTC_TAU_REL
-#define BLTC_TAU_REL 2.4e-2
-#endif
-constexpr double kTauRel = BLTC_TAU_REL;
+constexpr double kTauRel = kMixedTauRel;
 constexpr int kFlushEvery = 128;
 
 // FP32 kernel value of one source for a lane's local target coordinates.
@@ -47,7 +44,7 @@ __device__ __forceinline__ float near_value_f32(float x, float y, float z, const
 // Sources [j, j+4): FP32 values; if any of them is closer than tau (rare, one
 // branch per 4 sources), those terms are redone in FP64 into `acc` and their
 // FP32 values are zeroed.
-template <int KER>
+template <int KER, bool CHECK>
 __device__ __forceinline__ void near_quad_mixed(float x, float y, float z,
                                                 const float4* __restrict__ s32,
                                                 const double4* __restrict__ s64, float tau2,
@@ -62,7 +59,7 @@ __device__ __forceinline__ void near_quad_mixed(float x, float y, float z,
     float g1 = near_value_f32<KER>(x, y, z, p1, nk, r1);
     float g2 = near_value_f32<KER>(x, y, z, p2, nk, r2);
     float g3 = near_value_f32<KER>(x, y, z, p3, nk, r3);
-    if (fminf(fminf(r0, r1), fminf(r2, r3)) <= tau2) {
+    if (CHECK && fminf(fminf(r0, r1), fminf(r2, r3)) <= tau2) {
         if (r0 <= tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[0], kappa); g0 = 0.0f; }
         if (r1 <= tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[1], kappa); g1 = 0.0f; }
         if (r2 <= tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[2], kappa); g2 = 0.0f; }
@@ -74,7 +71,8 @@ __device__ __forceinline__ void near_quad_mixed(float x, float y, float z,
     a3 = __fmaf_rn(g3, p3.w, a3);
 }
 
-template <int KER>
+// CHECK = false: the caller has shown that no pair is closer than tau
+template <int KER, bool CHECK>
 __device__ __forceinline__ double near_sum_mixed(double xt, double yt, double zt,
                                                  const float4* __restrict__ s32,
                                                  const double4* __restrict__ s64, int32_t cnt,
@@ -91,12 +89,12 @@ __device__ __forceinline__ double near_sum_mixed(double xt, double yt, double zt
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
         int32_t j = j0;
         for (; j + 4 <= j1; j += 4)
-            near_quad_mixed<KER>(x, y, z, s32 + j, s64 + j, tau2, nk, xt, yt, zt, kappa, acc, a0,
-                                 a1, a2, a3);
+            near_quad_mixed<KER, CHECK>(x, y, z, s32 + j, s64 + j, tau2, nk, xt, yt, zt, kappa,
+                                        acc, a0, a1, a2, a3);
         for (; j < j1; ++j) {
             float r;
             float g = near_value_f32<KER>(x, y, z, s32[j], nk, r);
-            if (r <= tau2) {
+            if (CHECK && r <= tau2) {
                 acc += near_term_f64<KER>(xt, yt, zt, s64[j], kappa);
                 g = 0.0f;
             }
@@ -196,12 +194,19 @@ __global__ __launch_bounds__(kGroupSize) void interact_mixed(
     for (int e = near_off[b]; e < n_end; ++e) {
         const double4 li = node_info[near_leaf[e]];
         const double dx = bi.x - li.x, dy = bi.y - li.y, dz = bi.z - li.z;
-        const double extent = sqrt(dx * dx + dy * dy + dz * dz) + bi.w + 2.0 * li.w;
+        const double dist = sqrt(dx * dx + dy * dy + dz * dz);
+        const double extent = dist + bi.w + 2.0 * li.w;
         const double tau = kTauRel * extent;
         const float tau2 = static_cast<float>(tau * tau);
         const int64_t nb = near_begin[e];
-        acc += near_sum_mixed<KER>(t.x, t.y, t.z, src32 + nb, src + nb,
-                                   static_cast<int32_t>(near_count[e]), li, tau2, nk, kappa);
+        const int32_t nc = static_cast<int32_t>(near_count[e]);
+        // bounding spheres further apart than tau: no pair needs the FP64 branch
+        if (dist - bi.w - li.w > 1.0625 * tau)
+            acc += near_sum_mixed<KER, false>(t.x, t.y, t.z, src32 + nb, src + nb, nc, li, tau2,
+                                              nk, kappa);
+        else
+            acc += near_sum_mixed<KER, true>(t.x, t.y, t.z, src32 + nb, src + nb, nc, li, tau2,
+                                             nk, kappa);
     }
     if (pc_off) {
         // mutual leaf pairs: this target's row or column sums of each unit

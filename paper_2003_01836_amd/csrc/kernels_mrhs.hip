@@ -29,10 +29,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int kRhs = 16;
 constexpr int kMixedFlushSteps = 32;   // FP32 MFMA partial sums cover <= 128 sources
 
-#ifndef BLTC_TAU_REL
-#define BLTC_TAU_REL 2.4e-2
-#endif
-constexpr double kTauRel = BLTC_TAU_REL;
+constexpr double kTauRel = kMixedTauRel;
 
 // ---------------------------------------------------------------------------
 // FP64: G in FP64 on the VALU, contraction on v_mfma_f64_16x16x4f64.

@@ -28,10 +28,7 @@ constexpr int kBlk = 8;           // sources per butterfly block
 constexpr int kChunks = 8;        // 64-target chunks held in registers at a time (FP32-mixed)
 constexpr int kChunks64 = 4;      // the same for the FP64 kernel (twice the registers)
 
-#ifndef BLTC_TAU_REL
-#define BLTC_TAU_REL 2.4e-2
-#endif
-constexpr double kTauRel = BLTC_TAU_REL;   // the mixed interaction kernel's cut-off
+constexpr double kTauRel = kMixedTauRel;   // the mixed interaction kernel's cut-off
 constexpr int kFlushEvery = 128;           // FP32 row sums span at most this many sources
 
 // lane l returns the sum over the wave's 64 lanes of v[l % kBlk] (v is consumed)
