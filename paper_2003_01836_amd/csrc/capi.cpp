@@ -203,20 +203,31 @@ int upload_symmetric(bltc_plan* plan, hipStream_t s)
         near_leaf = hp.near_leaf;
     }
     // unit results: at most 2^31 values (16 GiB)
+    const int64_t sub = plan->prm.precision == BLTC_FP32_MIXED ? bltc::kSymTargetsMixed
+                                                               : bltc::kSymTargetsF64;
     bltc::SymPlan sp;
-    if (!bltc::plan_symmetric(hp, near_leaf, int64_t(1) << 31, bltc::kSymMaxCols, sp))
+    if (!bltc::plan_symmetric(hp, near_leaf, sub, int64_t(1) << 31, sp))
         return BLTC_OK;
-    std::vector<bltc::SymUnit> units(sp.ub.size());
-    for (size_t k = 0; k < units.size(); ++k) {
+    std::vector<bltc::SymUnit> units;
+    for (size_t k = 0; k < sp.ub.size(); ++k) {
         const int32_t b = sp.ub[k], c = sp.uc[k];
-        units[k].tb = hp.batch_begin[b];
-        units[k].sb = hp.batch_begin[c];
-        units[k].off = sp.uoff[k];
-        units[k].nb = static_cast<int32_t>(hp.batch_count[b]);
-        units[k].nc = static_cast<int32_t>(hp.batch_count[c]);
-        units[k].batch = b;
-        units[k].leaf = hp.batch_node[c];
+        for (int32_t q = 0; q < sp.nsub[k]; ++q) {
+            bltc::SymUnit su;
+            su.tb = hp.batch_begin[b] + q * sub;
+            su.sb = hp.batch_begin[c];
+            su.roff = sp.roff[k] + q * sub;
+            su.coff = sp.coff[k] + q * hp.batch_count[c];
+            su.nb = static_cast<int32_t>(std::min<int64_t>(sub, hp.batch_count[b] - q * sub));
+            su.nc = static_cast<int32_t>(hp.batch_count[c]);
+            su.batch = b;
+            su.leaf = hp.batch_node[c];
+            units.push_back(su);
+        }
     }
+    // heaviest sub-unit first (one wave each)
+    std::stable_sort(units.begin(), units.end(), [](const bltc::SymUnit& a, const bltc::SymUnit& c) {
+        return static_cast<int64_t>(a.nb) * a.nc > static_cast<int64_t>(c.nb) * c.nc;
+    });
     HIP_TRY(plan->put(&d.sym_unit, units, s));
     HIP_TRY(plan->alloc(&d.sym_out, static_cast<size_t>(sp.out_size)));
     HIP_TRY(plan->put(&d.sym_near_off, sp.near_off, s));
@@ -228,7 +239,6 @@ int upload_symmetric(bltc_plan* plan, hipStream_t s)
     HIP_TRY(plan->put(&d.batch_begin, hp.batch_begin, s));
     HIP_TRY(hipStreamSynchronize(s));
     d.sym_units = static_cast<int64_t>(units.size());
-    d.sym_max_cols = sp.max_cols;
     d.sym = 1;
     plan->sym_pair_evals = sp.pair_evals;
     hp.group_batch.clear();

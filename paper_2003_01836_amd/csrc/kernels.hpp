@@ -25,12 +25,13 @@ struct NearLists {
     const int64_t* batch_begin;
 };
 
-// One mutual pair of leaves (B, C) of a plan whose targets are its sources:
-// B's particles at tree positions [tb, tb + nb), C's at [sb, sb + nc); row sums
-// (potential at B's targets from C's sources) to out[off + i], column sums
-// (at C's targets from B's sources) to out[off + nb + j].
+// A sub-unit of a mutual pair of leaves (B, C) of a plan whose targets are
+// its sources: nb of B's particles at tree positions [tb, tb + nb) against
+// C's particles at [sb, sb + nc); row sums (potential at those B targets from
+// C's sources) to out[roff + i], column sums (at C's targets from those B
+// sources) to out[coff + j].
 struct SymUnit {
-    int64_t tb, sb, off;
+    int64_t tb, sb, roff, coff;
     int32_t nb, nc;
     int32_t batch;    // B's batch (batch_info)
     int32_t leaf;     // C's node (node_info)
@@ -84,8 +85,7 @@ struct DevicePlan {
     // by launch_near_pairs; the interaction kernels then take the reduced direct
     // lists and add, per target, the unit results listed in sym_pc_*
     int32_t sym = 0;
-    int64_t sym_units = 0;
-    int64_t sym_max_cols = 0;
+    int64_t sym_units = 0;            // sub-units
     SymUnit* sym_unit = nullptr;
     double* sym_out = nullptr;
     int32_t* sym_near_off = nullptr;
@@ -187,8 +187,10 @@ inline NearLists near_lists(const DevicePlan& d)
 // near field of the mutual leaf pairs (kernels_sym.hip): d.sym_units units
 // into d.sym_out, FP64 or FP32-mixed as kp.precision
 hipError_t launch_near_pairs(const DevicePlan& d, const KernelParams& kp, hipStream_t s);
-// largest leaf (column count) launch_near_pairs accepts
-constexpr int64_t kSymMaxCols = 8000;
+// B targets per sub-unit of launch_near_pairs (one wave holds them all in
+// registers, 64 per chunk): FP32-mixed and FP64
+constexpr int64_t kSymTargetsMixed = 512;
+constexpr int64_t kSymTargetsF64 = 256;
 // the FP32-mixed path computes the kernel values of pairs closer than
 // kMixedTauRel * (distance of the box centers + r_B + 2 r_C) from FP64 coordinates
 constexpr double kMixedTauRel = 2.4e-2;

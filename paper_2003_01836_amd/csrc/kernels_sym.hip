@@ -3,19 +3,17 @@
 //
 // G(x, y) = G(y, x): for two different leaves B and C that are in each
 // other's direct lists, every kernel value serves both directions.  One wave
-// per unit (B, C).  The wave takes B's particles as targets in super-chunks of
-// up to kChunks x 64 (one target per lane and chunk, all in registers) and
-// streams C's particles through the scalar cache as wave-uniform sources in
-// blocks of kBlk.  Per pair it forms one kernel value g, adds the row term
-// g q_j to the lane's sum for that target and the column term g q_i to the
-// lane's column register of that source.  After a block, a butterfly over the
-// lanes (log2 kBlk xor-shuffle stages inside each group of kBlk lanes, then
+// per sub-unit: up to kChunks x 64 of B's particles as targets (one per lane
+// and chunk, all in registers) against all of C's particles, which stream
+// through the scalar cache as wave-uniform sources in blocks of kBlk.  Per
+// pair the wave forms one kernel value g, adds the row term g q_j to the
+// lane's sum for that target and the column term g q_i to the lane's column
+// register of that source.  After a block, a butterfly over the lanes
+// (log2 kBlk xor-shuffle stages inside each group of kBlk lanes, then
 // log2(64 / kBlk) across the groups) leaves in lane l the sum over the
-// super-chunk's targets of column l mod kBlk, which lanes 0..kBlk-1 add to
-// the unit's FP64 column sums in LDS; the butterfly's cost is shared by the
-// super-chunk's kChunks targets per lane.  Row sums are written per
-// super-chunk, column sums at the end; every order is fixed, so the results
-// are deterministic.
+// sub-unit's targets of column l mod kBlk, which lanes 0..kBlk-1 store; the
+// butterfly's cost is shared by the kChunks targets of a lane.  Every sum has
+// a fixed order, so the results are deterministic.
 #include "kernels.hpp"
 #include "device_common.hpp"
 
@@ -25,8 +23,10 @@ namespace {
 using namespace dev;
 
 constexpr int kBlk = 8;           // sources per butterfly block
-constexpr int kChunks = 8;        // 64-target chunks held in registers at a time (FP32-mixed)
+constexpr int kChunks = 8;        // 64-target chunks held in registers (FP32-mixed)
 constexpr int kChunks64 = 4;      // the same for the FP64 kernel (twice the registers)
+static_assert(kSymTargetsMixed == 64 * kChunks && kSymTargetsF64 == 64 * kChunks64,
+              "sub-unit sizes");
 
 constexpr double kTauRel = kMixedTauRel;   // the mixed interaction kernel's cut-off
 constexpr int kFlushEvery = 128;           // FP32 row sums span at most this many sources
@@ -61,72 +61,64 @@ __global__ __launch_bounds__(64) void near_pairs_f64(const SymUnit* __restrict__
                                                      const double4* __restrict__ src,
                                                      double* __restrict__ out, KernelConst kc)
 {
-    extern __shared__ double col[];   // [nc] column sums
     __shared__ double exp_tab[64];
     if constexpr (KER == 1)
         fill_exp2_table(exp_tab);
     const KernelArg ka{kc.kappa, kc.delta2, exp_tab};
     const SymUnit u = units[blockIdx.x];
     const int lane = threadIdx.x;
-    for (int j = lane; j < u.nc; j += 64)
-        col[j] = 0.0;
-    __syncthreads();
     const double4* __restrict__ S = src + u.sb;
-    for (int c0 = 0; c0 < u.nb; c0 += 64 * kChunks64) {
-        const int nch = min(kChunks64, (u.nb - c0 + 63) / 64);   // uniform
-        double tx[kChunks64], ty[kChunks64], tz[kChunks64], tq[kChunks64], a0[kChunks64], a1[kChunks64];
+    const int nch = (u.nb + 63) / 64;   // uniform, <= kChunks64 by construction
+    double tx[kChunks64], ty[kChunks64], tz[kChunks64], tq[kChunks64], a0[kChunks64],
+        a1[kChunks64];
 #pragma unroll
-        for (int k = 0; k < kChunks64; ++k) {
-            const int i = c0 + 64 * k + lane;
-            const double4 t = src[u.tb + (i < u.nb ? i : u.nb - 1)];
-            tx[k] = t.x;
-            ty[k] = t.y;
-            tz[k] = t.z;
-            tq[k] = i < u.nb ? t.w : 0.0;   // no column terms from lanes past the end
-            a0[k] = 0.0;
-            a1[k] = 0.0;
-        }
-        for (int s0 = 0; s0 < u.nc; s0 += kBlk) {
-            const int cnt = min(kBlk, u.nc - s0);   // uniform
-            double v[kBlk];
-#pragma unroll
-            for (int m = 0; m < kBlk; ++m)
-                v[m] = 0.0;
-#pragma unroll
-            for (int k = 0; k < kChunks64; ++k) {
-                if (k >= nch)
-                    break;
-#pragma unroll
-                for (int m = 0; m < kBlk; ++m) {
-                    if (m >= cnt)
-                        break;
-                    const double4 p = S[s0 + m];
-                    const double dx = tx[k] - p.x;
-                    const double dy = ty[k] - p.y;
-                    const double dz = tz[k] - p.z;
-                    const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-                    const double g = green_near_f64<KER>(r2, ka);
-                    if (m & 1)
-                        a1[k] = __fma_rn(g, p.w, a1[k]);
-                    else
-                        a0[k] = __fma_rn(g, p.w, a0[k]);
-                    v[m] = __fma_rn(g, tq[k], v[m]);
-                }
-            }
-            const double cs = column_sums(v, lane);
-            if (lane < cnt)
-                col[s0 + lane] += cs;
-        }
-#pragma unroll
-        for (int k = 0; k < kChunks64; ++k) {
-            const int i = c0 + 64 * k + lane;
-            if (k < nch && i < u.nb)
-                out[u.off + i] = a0[k] + a1[k];
-        }
+    for (int k = 0; k < kChunks64; ++k) {
+        const int i = 64 * k + lane;
+        const double4 t = src[u.tb + (i < u.nb ? i : u.nb - 1)];
+        tx[k] = t.x;
+        ty[k] = t.y;
+        tz[k] = t.z;
+        tq[k] = i < u.nb ? t.w : 0.0;   // no column terms from lanes past the end
+        a0[k] = 0.0;
+        a1[k] = 0.0;
     }
-    __syncthreads();
-    for (int j = lane; j < u.nc; j += 64)
-        out[u.off + u.nb + j] = col[j];
+    for (int s0 = 0; s0 < u.nc; s0 += kBlk) {
+        const int cnt = min(kBlk, u.nc - s0);   // uniform
+        double v[kBlk];
+#pragma unroll
+        for (int m = 0; m < kBlk; ++m)
+            v[m] = 0.0;
+#pragma unroll
+        for (int k = 0; k < kChunks64; ++k) {
+            if (k >= nch)
+                break;
+#pragma unroll
+            for (int m = 0; m < kBlk; ++m) {
+                if (m >= cnt)
+                    break;
+                const double4 p = S[s0 + m];
+                const double dx = tx[k] - p.x;
+                const double dy = ty[k] - p.y;
+                const double dz = tz[k] - p.z;
+                const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+                const double g = green_near_f64<KER>(r2, ka);
+                if (m & 1)
+                    a1[k] = __fma_rn(g, p.w, a1[k]);
+                else
+                    a0[k] = __fma_rn(g, p.w, a0[k]);
+                v[m] = __fma_rn(g, tq[k], v[m]);
+            }
+        }
+        const double cs = column_sums(v, lane);
+        if (lane < cnt)
+            out[u.coff + s0 + lane] = cs;
+    }
+#pragma unroll
+    for (int k = 0; k < kChunks64; ++k) {
+        const int i = 64 * k + lane;
+        if (k < nch && i < u.nb)
+            out[u.roff + i] = a0[k] + a1[k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -212,9 +204,6 @@ __global__ __launch_bounds__(64) void near_pairs_mixed(
     const float4* __restrict__ src32, const double4* __restrict__ node_info,
     const double4* __restrict__ batch_info, double* __restrict__ out, KernelConst kc)
 {
-    // [nc] column sums: FP32 (each is the sum of at most ceil(nb / 512)
-    // super-chunk sums), which leaves LDS for more waves per CU
-    extern __shared__ float colf[];
     __shared__ double exp_tab[64];
     if constexpr (KER == 1)
         fill_exp2_table(exp_tab);
@@ -222,8 +211,6 @@ __global__ __launch_bounds__(64) void near_pairs_mixed(
     const KernelArg32 nk = kernel_arg32(kc.kappa, kc.delta2);
     const SymUnit u = units[blockIdx.x];
     const int lane = threadIdx.x;
-    for (int j = lane; j < u.nc; j += 64)
-        colf[j] = 0.0f;
     // tau of the pair: the larger of the two directions' values
     const double4 bi = batch_info[u.batch];
     const double4 li = node_info[u.leaf];
@@ -232,67 +219,61 @@ __global__ __launch_bounds__(64) void near_pairs_mixed(
                           fmax(bi.w + 2.0 * li.w, li.w + 2.0 * bi.w);
     const double tau = kTauRel * extent;
     const float tau2 = static_cast<float>(tau * tau);
-    __syncthreads();
     const float4* __restrict__ S32 = src32 + u.sb;
     const double4* __restrict__ S64 = src + u.sb;
     const double4* __restrict__ T64 = src + u.tb;
-    for (int c0 = 0; c0 < u.nb; c0 += 64 * kChunks) {
-        const int nch = min(kChunks, (u.nb - c0 + 63) / 64);   // uniform
-        float tx[kChunks], ty[kChunks], tz[kChunks], tq[kChunks], ra[kChunks];
-        double acc[kChunks];
+    const int nch = (u.nb + 63) / 64;   // uniform, <= kChunks by construction
+    float tx[kChunks], ty[kChunks], tz[kChunks], tq[kChunks], ra[kChunks];
+    double acc[kChunks];
 #pragma unroll
-        for (int k = 0; k < kChunks; ++k) {
-            const int i = c0 + 64 * k + lane;
-            const int pos = i < u.nb ? i : u.nb - 1;
-            const double4 t = T64[pos];
-            tx[k] = static_cast<float>(t.x - li.x);
-            ty[k] = static_cast<float>(t.y - li.y);
-            tz[k] = static_cast<float>(t.z - li.z);
-            tq[k] = i < u.nb ? src32[u.tb + pos].w : 0.0f;   // no column terms past the end
-            ra[k] = 0.0f;
-            acc[k] = 0.0;
-        }
-        int s0 = 0;
-        for (; s0 + kBlk <= u.nc; s0 += kBlk) {
-            float v[kBlk];
+    for (int k = 0; k < kChunks; ++k) {
+        const int i = 64 * k + lane;
+        const int pos = i < u.nb ? i : u.nb - 1;
+        const double4 t = T64[pos];
+        tx[k] = static_cast<float>(t.x - li.x);
+        ty[k] = static_cast<float>(t.y - li.y);
+        tz[k] = static_cast<float>(t.z - li.z);
+        tq[k] = i < u.nb ? src32[u.tb + pos].w : 0.0f;   // no column terms past the end
+        ra[k] = 0.0f;
+        acc[k] = 0.0;
+    }
+    int s0 = 0;
+    for (; s0 + kBlk <= u.nc; s0 += kBlk) {
+        float v[kBlk];
 #pragma unroll
-            for (int m = 0; m < kBlk; ++m)
-                v[m] = 0.0f;
-            block_mixed<KER, true>(tx, ty, tz, tq, ra, v, nch, S32 + s0, S64 + s0, kBlk, T64, c0,
-                                   u.nb, tau2, nk, ka, lane);
-            const float cs = column_sums(v, lane);
-            if (lane < kBlk)
-                colf[s0 + lane] += cs;
-            if ((s0 + kBlk) % kFlushEvery == 0) {
+        for (int m = 0; m < kBlk; ++m)
+            v[m] = 0.0f;
+        block_mixed<KER, true>(tx, ty, tz, tq, ra, v, nch, S32 + s0, S64 + s0, kBlk, T64, 0, u.nb,
+                               tau2, nk, ka, lane);
+        const float cs = column_sums(v, lane);
+        if (lane < kBlk)
+            out[u.coff + s0 + lane] = static_cast<double>(cs);
+        if ((s0 + kBlk) % kFlushEvery == 0) {
 #pragma unroll
-                for (int k = 0; k < kChunks; ++k) {
-                    acc[k] += static_cast<double>(ra[k]);
-                    ra[k] = 0.0f;
-                }
+            for (int k = 0; k < kChunks; ++k) {
+                acc[k] += static_cast<double>(ra[k]);
+                ra[k] = 0.0f;
             }
         }
-        if (s0 < u.nc) {
-            const int cnt = u.nc - s0;
-            float v[kBlk];
-#pragma unroll
-            for (int m = 0; m < kBlk; ++m)
-                v[m] = 0.0f;
-            block_mixed<KER, false>(tx, ty, tz, tq, ra, v, nch, S32 + s0, S64 + s0, cnt, T64, c0,
-                                    u.nb, tau2, nk, ka, lane);
-            const float cs = column_sums(v, lane);
-            if (lane < cnt)
-                colf[s0 + lane] += cs;
-        }
-#pragma unroll
-        for (int k = 0; k < kChunks; ++k) {
-            const int i = c0 + 64 * k + lane;
-            if (k < nch && i < u.nb)
-                out[u.off + i] = acc[k] + static_cast<double>(ra[k]);
-        }
     }
-    __syncthreads();
-    for (int j = lane; j < u.nc; j += 64)
-        out[u.off + u.nb + j] = static_cast<double>(colf[j]);
+    if (s0 < u.nc) {
+        const int cnt = u.nc - s0;
+        float v[kBlk];
+#pragma unroll
+        for (int m = 0; m < kBlk; ++m)
+            v[m] = 0.0f;
+        block_mixed<KER, false>(tx, ty, tz, tq, ra, v, nch, S32 + s0, S64 + s0, cnt, T64, 0, u.nb,
+                                tau2, nk, ka, lane);
+        const float cs = column_sums(v, lane);
+        if (lane < cnt)
+            out[u.coff + s0 + lane] = static_cast<double>(cs);
+    }
+#pragma unroll
+    for (int k = 0; k < kChunks; ++k) {
+        const int i = 64 * k + lane;
+        if (k < nch && i < u.nb)
+            out[u.roff + i] = acc[k] + static_cast<double>(ra[k]);
+    }
 }
 
 }  // namespace
@@ -301,12 +282,11 @@ hipError_t launch_near_pairs(const DevicePlan& d, const KernelParams& kp, hipStr
 {
     if (!d.sym || d.sym_units == 0)
         return hipSuccess;
-    if (d.sym_max_cols < 1 || d.sym_max_cols > kSymMaxCols || !d.sym_unit || !d.sym_out)
+    if (!d.sym_unit || !d.sym_out)
         return hipErrorInvalidValue;
     const KernelConst kc = kp.kconst();
     const dim3 grid(static_cast<unsigned>(d.sym_units));
-    const size_t lds = static_cast<size_t>(d.sym_max_cols) *
-                       (kp.precision == 1 ? sizeof(float) : sizeof(double));
+    const size_t lds = 0;
     if (kp.precision == 1) {
         if (!d.src32 || !d.node_info || !d.batch_info)
             return hipErrorInvalidValue;

@@ -506,10 +506,10 @@ void plan_schedule(HostPlan& hp)
                    hp.group_batch, hp.group_first);
 }
 
-bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, int64_t max_out,
-                    int64_t max_cols, SymPlan& sp)
+bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, int64_t sub,
+                    int64_t max_out, SymPlan& sp)
 {
-    if (!hp.same_tree)
+    if (!hp.same_tree || sub < 1)
         return false;
     const Tree& S = hp.src;
     const int64_t nb = static_cast<int64_t>(hp.batch_node.size());
@@ -548,20 +548,24 @@ bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, i
                          return evals(a) > evals(c);
                      });
     SymPlan out;
+    out.sub = sub;
     int64_t off = 0;
     std::map<std::pair<int32_t, int32_t>, int64_t> unit_of;
     for (size_t k = 0; k < units.size(); ++k) {
         const auto& u = units[k];
+        const int64_t nbk = hp.batch_count[u.first], nck = hp.batch_count[u.second];
+        const int64_t ns = (nbk + sub - 1) / sub;
         out.ub.push_back(u.first);
         out.uc.push_back(u.second);
-        out.uoff.push_back(off);
+        out.nsub.push_back(static_cast<int32_t>(ns));
+        out.roff.push_back(off);
+        out.coff.push_back(off + nbk);
         unit_of[u] = static_cast<int64_t>(k);
-        off += hp.batch_count[u.first] + hp.batch_count[u.second];
-        out.max_cols = std::max(out.max_cols, hp.batch_count[u.second]);
+        off += nbk + ns * nck;
         out.pair_evals += evals(u);
     }
     out.out_size = off;
-    if (out.out_size > max_out || out.max_cols > max_cols)
+    if (out.out_size > max_out)
         return false;
     // reduced lists in the original list order, and the costs left to the batches
     out.near_off.assign(nb + 1, 0);
@@ -581,8 +585,14 @@ bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, i
             const int32_t lo = std::min<int32_t>(static_cast<int32_t>(b), c);
             const int32_t hi = std::max<int32_t>(static_cast<int32_t>(b), c);
             const int64_t u = unit_of[{lo, hi}];
-            out.pc_base.push_back(b == lo ? out.uoff[u] : out.uoff[u] + hp.batch_count[lo]);
-            out.batch_cost[b] -= S.count[leaf] - 1;   // one read instead of |C| evaluations
+            if (b == lo) {
+                out.pc_base.push_back(out.roff[u]);
+                out.batch_cost[b] -= S.count[leaf] - 1;   // one read instead of |C| evaluations
+            } else {
+                for (int32_t q = 0; q < out.nsub[u]; ++q)
+                    out.pc_base.push_back(out.coff[u] + q * hp.batch_count[b]);
+                out.batch_cost[b] -= S.count[leaf] - out.nsub[u];
+            }
         }
         out.near_off[b + 1] = static_cast<int32_t>(out.near_leaf.size());
         out.pc_off[b + 1] = static_cast<int32_t>(out.pc_base.size());

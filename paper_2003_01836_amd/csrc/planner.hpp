@@ -102,30 +102,34 @@ struct HostPlan {
 
 // Mutual direct pairs of a plan whose batches are the leaves of its source
 // tree.  G(x, y) = G(y, x), so two different leaves B and C, each in the
-// other's direct list, form one unit evaluated once for both directions: the
-// row sums (B's targets, C's sources) and the column sums (C's targets, B's
-// sources) go to out[off .. off + |B|) and out[off + |B| .. off + |B| + |C|).
+// other's direct list, form one unit evaluated once for both directions.  A
+// unit is cut into sub-units of at most `sub` of B's targets; sub-unit s
+// writes the row sums of its targets (potential at B's targets from C's
+// sources) to out[roff + s sub ..] and its column sums (at C's targets from
+// its B sources) to out[coff + s |C| .. + |C|).
 struct SymPlan {
     std::vector<int32_t> ub, uc;        // batches of a unit, ub < uc; heaviest unit first
-    std::vector<int64_t> uoff;          // out offset of a unit
+    std::vector<int64_t> roff, coff;    // out offsets of a unit's rows and first column block
+    std::vector<int32_t> nsub;          // sub-units of a unit: ceil(|B| / sub)
+    int64_t sub = 0;                    // B targets per sub-unit
     int64_t out_size = 0;
-    int64_t max_cols = 0;               // largest |C|
     int64_t pair_evals = 0;             // sum over units of |B| |C|
     // per batch: the direct entries that are not mutual (leaf, range) ...
     std::vector<int32_t> near_off, near_leaf;
     std::vector<int64_t> near_begin, near_count;
-    // ... and the out offsets of its side of every mutual pair, in list order
+    // ... and the out offsets of its rows or column blocks of every mutual
+    // pair, in list order (a B side: one entry; a C side: nsub entries)
     std::vector<int32_t> pc_off;
     std::vector<int64_t> pc_base;
     std::vector<int64_t> batch_cost;    // evaluations per target left to the batch's workgroups
 };
 
 // Builds sp from the direct lists (hp.near_off, the leaf of every entry in
-// near_leaf).  Returns false (sp untouched) when hp.same_tree is false, when
-// there is no mutual pair, or when out_size would exceed max_out values or a
-// leaf more than max_cols particles.
-bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, int64_t max_out,
-                    int64_t max_cols, SymPlan& sp);
+// near_leaf) with sub-units of `sub` targets.  Returns false (sp untouched)
+// when hp.same_tree is false, when there is no mutual pair, or when out_size
+// would exceed max_out values.
+bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, int64_t sub,
+                    int64_t max_out, SymPlan& sp);
 
 // Builds the tree with leaf capacity `cap` (readings of the tree rules are
 // documented in planner.cpp).
