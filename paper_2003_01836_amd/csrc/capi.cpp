@@ -241,12 +241,25 @@ int upload_symmetric(bltc_plan* plan, hipStream_t s)
     d.sym_units = static_cast<int64_t>(units.size());
     d.sym = 1;
     plan->sym_pair_evals = sp.pair_evals;
+    hp.batch_cost = sp.batch_cost;
+    return BLTC_OK;
+}
+
+// Plans with one charge vector: interaction workgroups of kGroupSizeSym
+// targets (one wave; a finer tail than kGroupSize), ordered by the work left
+// to each batch.
+void schedule_single_vector(bltc_plan* plan)
+{
+    bltc::HostPlan& hp = plan->hp;
+    if (plan->max_q != 1)
+        return;
+    hp.prm.group_size = bltc::kGroupSizeSym;
     hp.group_batch.clear();
     hp.group_first.clear();
-    bltc::group_schedule(hp.batch_begin, hp.batch_count, sp.batch_cost, hp.prm.group_size,
+    bltc::group_schedule(hp.batch_begin, hp.batch_count, hp.batch_cost, hp.prm.group_size,
                          hp.prm.xcds, hp.group_batch, hp.group_first);
-    d.ngroups = static_cast<int64_t>(hp.group_batch.size());
-    return BLTC_OK;
+    plan->d.ngroups = static_cast<int64_t>(hp.group_batch.size());
+    plan->d.group_threads = bltc::kGroupSizeSym;
 }
 
 }  // namespace
@@ -288,6 +301,7 @@ int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
     int rc = upload_symmetric(plan, s);
     if (rc != BLTC_OK)
         return rc;
+    schedule_single_vector(plan);
     std::vector<int64_t> batch_end(d.nbatches);
     for (int64_t b = 0; b < d.nbatches; ++b)
         batch_end[b] = hp.batch_begin[b] + hp.batch_count[b];

@@ -184,7 +184,7 @@ hipError_t run_interact(const DevicePlan& d, double* phi, KernelConst kc, hipStr
         return hipSuccess;
     const NearLists nl = near_lists(d);
     hipLaunchKernelGGL((interact_f64<N, KER>), dim3(static_cast<unsigned>(d.ngroups)),
-                       dim3(kGroupSize), 0, s, d.tgt, d.tgt_orig, d.src, d.group_batch,
+                       dim3(d.group_threads), 0, s, d.tgt, d.tgt_orig, d.src, d.group_batch,
                        d.group_first, d.batch_end, d.far_off, d.far_slot, nl.off, nl.begin,
                        nl.count, d.slot_nodes, d.qhat, nl.pc_off, nl.pc_base, nl.pair_out,
                        nl.batch_begin, phi, kc);

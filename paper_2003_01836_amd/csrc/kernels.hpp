@@ -10,6 +10,7 @@ namespace bltc {
 constexpr int kMaxDegree = 16;
 constexpr int kMaxHermiteDegree = 10;   // Hermite treecode: 8 (n+1)^3 charges per cluster
 constexpr int kGroupSize = 256;      // targets (lanes) per interaction workgroup
+constexpr int kGroupSizeSym = 64;    // the same for plans with mutual pairs (finer tail)
 
 // The direct lists the single-vector interaction kernels walk: the plan's own,
 // or, when mutual leaf pairs are evaluated by launch_near_pairs, the reduced
@@ -86,6 +87,9 @@ struct DevicePlan {
     // lists and add, per target, the unit results listed in sym_pc_*
     int32_t sym = 0;
     int64_t sym_units = 0;            // sub-units
+    // targets per workgroup of the single-vector interaction kernels (the plan's
+    // group size: kGroupSize, or kGroupSizeSym for plans with mutual pairs)
+    int32_t group_threads = 256;
     SymUnit* sym_unit = nullptr;
     double* sym_out = nullptr;
     int32_t* sym_near_off = nullptr;

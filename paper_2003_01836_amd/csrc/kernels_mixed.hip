@@ -226,7 +226,7 @@ hipError_t run_interact_mixed(const DevicePlan& d, double* phi, KernelConst kc, 
         return hipSuccess;
     const NearLists nl = near_lists(d);
     hipLaunchKernelGGL((interact_mixed<N, KER>), dim3(static_cast<unsigned>(d.ngroups)),
-                       dim3(kGroupSize), 0, s, d.tgt, d.tgt_orig, d.src, d.src32, d.node_info,
+                       dim3(d.group_threads), 0, s, d.tgt, d.tgt_orig, d.src, d.src32, d.node_info,
                        d.batch_info, d.group_batch, d.group_first, d.batch_end, d.far_off,
                        d.far_slot, nl.off, nl.begin, nl.count, nl.leaf, d.slot_nodes, d.qhat32,
                        nl.pc_off, nl.pc_base, nl.pair_out, nl.batch_begin, phi, kc);
