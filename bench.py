@@ -316,12 +316,15 @@ def run_variant(args, dev):
                           "direct_and_interpolation": ph["interact"], "total": ph["total"]},
             "approx_evals": st["far_evals"], "near_evals": st["near_evals"],
             "interp_terms": st["upward_terms"],
-            "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"]}
+            "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"],
+            "mutual_pair_evals": st["mutual_pair_evals"]}
         # the interaction launches (proxy potentials, direct sums and, for the
         # cluster-cluster method, grid-grid and grid-targets pairs) are bound by
         # VALU issue; the phases also hold the small upward / interpolation work
         t_int = (ph["upward"] + ph["interact"]) * 1e-3
-        ach = (st["far_evals"] + st["near_evals"]) * FLOPS_COULOMB / t_int / 1e12
+        mutual = st["mutual_pair_evals"]   # direct kernel values serving two terms
+        ach = ((st["far_evals"] + st["near_evals"] - 2 * mutual) * FLOPS_COULOMB +
+               mutual * FLOPS_MUTUAL_PAIR) / t_int / 1e12
         peak = FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS
         res["paths"][prec]["roofline"] = {
             "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
@@ -457,7 +460,8 @@ def run_setup(args, dev):
             log(f"setup {prec}: device plan {times[-1]:.3f}s")
         res[prec] = {"device_plan_s": min(times), "device_plan_s_all": times,
                      "clusters": st["clusters"], "batches": st["batches"],
-                     "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"]}
+                     "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"],
+            "mutual_pair_evals": st["mutual_pair_evals"]}
     if n <= args.setup_host_max:
         ph = np.ascontiguousarray(pos)
         t0 = time.perf_counter()

@@ -125,11 +125,12 @@ typedef struct {
     int32_t method;              /* bltc_method                                         */
     double delta;                /* BLTC_REGULARIZED_COULOMB length, >= 0               */
     int32_t no_symmetry;         /* 0: when the targets are the sources (same arrays,   */
-                                 /* N_B = N_L), methods BLTC_PARTICLE_CLUSTER and       */
-                                 /* BLTC_HERMITE with max_q = 1 evaluate each pair of   */
-                                 /* different leaves that are in each other's direct    */
-                                 /* lists once for both directions (G(x,y) = G(y,x));   */
-                                 /* 1: never.  Same potentials up to rounding order.    */
+                                 /* N_B = N_L), methods BLTC_PARTICLE_CLUSTER,          */
+                                 /* BLTC_HERMITE (max_q = 1) and BLTC_CLUSTER_CLUSTER   */
+                                 /* evaluate each pair of different leaves that are in  */
+                                 /* each other's direct lists once for both directions  */
+                                 /* (G(x,y) = G(y,x)); 1: never.  Same potentials up to */
+                                 /* rounding order.                                     */
 } bltc_params;
 
 /* Fills *p with the defaults: Coulomb, FP64, theta 0.7, degree 8,

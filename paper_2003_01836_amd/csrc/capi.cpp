@@ -180,10 +180,9 @@ int make_device_plan(bltc_plan* plan, const bltc_params* p, int64_t nt, const do
     return BLTC_OK;
 }
 
-// Mutual direct leaf pairs evaluated once (targets are the sources, one charge
-// vector): the units, the reduced direct lists and the per-batch unit results
-// on the device, and the workgroup schedule re-ordered for the work left to
-// the batches.  Plans that do not qualify keep their lists (d.sym = 0).
+// Mutual direct leaf pairs of a BLTC or Hermite plan evaluated once (targets
+// are the sources, one charge vector).  Plans that do not qualify keep their
+// lists (d.sym = 0).
 int upload_symmetric(bltc_plan* plan, hipStream_t s)
 {
     bltc::HostPlan& hp = plan->hp;
@@ -202,47 +201,9 @@ int upload_symmetric(bltc_plan* plan, hipStream_t s)
     } else {
         near_leaf = hp.near_leaf;
     }
-    // unit results: at most 2^31 values (16 GiB)
-    const int64_t sub = plan->prm.precision == BLTC_FP32_MIXED ? bltc::kSymTargetsMixed
-                                                               : bltc::kSymTargetsF64;
-    bltc::SymPlan sp;
-    if (!bltc::plan_symmetric(hp, near_leaf, sub, int64_t(1) << 31, sp))
-        return BLTC_OK;
-    std::vector<bltc::SymUnit> units;
-    for (size_t k = 0; k < sp.ub.size(); ++k) {
-        const int32_t b = sp.ub[k], c = sp.uc[k];
-        for (int32_t q = 0; q < sp.nsub[k]; ++q) {
-            bltc::SymUnit su;
-            su.tb = hp.batch_begin[b] + q * sub;
-            su.sb = hp.batch_begin[c];
-            su.roff = sp.roff[k] + q * sub;
-            su.coff = sp.coff[k] + q * hp.batch_count[c];
-            su.nb = static_cast<int32_t>(std::min<int64_t>(sub, hp.batch_count[b] - q * sub));
-            su.nc = static_cast<int32_t>(hp.batch_count[c]);
-            su.batch = b;
-            su.leaf = hp.batch_node[c];
-            units.push_back(su);
-        }
-    }
-    // heaviest sub-unit first (one wave each)
-    std::stable_sort(units.begin(), units.end(), [](const bltc::SymUnit& a, const bltc::SymUnit& c) {
-        return static_cast<int64_t>(a.nb) * a.nc > static_cast<int64_t>(c.nb) * c.nc;
-    });
-    HIP_TRY(plan->put(&d.sym_unit, units, s));
-    HIP_TRY(plan->alloc(&d.sym_out, static_cast<size_t>(sp.out_size)));
-    HIP_TRY(plan->put(&d.sym_near_off, sp.near_off, s));
-    HIP_TRY(plan->put(&d.sym_near_begin, sp.near_begin, s));
-    HIP_TRY(plan->put(&d.sym_near_count, sp.near_count, s));
-    HIP_TRY(plan->put(&d.sym_near_leaf, sp.near_leaf, s));
-    HIP_TRY(plan->put(&d.sym_pc_off, sp.pc_off, s));
-    HIP_TRY(plan->put(&d.sym_pc_base, sp.pc_base, s));
-    HIP_TRY(plan->put(&d.batch_begin, hp.batch_begin, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    d.sym_units = static_cast<int64_t>(units.size());
-    d.sym = 1;
-    plan->sym_pair_evals = sp.pair_evals;
-    hp.batch_cost = sp.batch_cost;
-    return BLTC_OK;
+    const bltc::DirectLists dl{&hp.src,      &hp.batch_node, &hp.batch_begin, &hp.batch_count,
+                               &hp.near_off, &near_leaf,     &hp.batch_cost};
+    return bltc_internal_upload_symmetric(plan, d, dl, &hp.batch_cost, s);
 }
 
 // Plans with one charge vector: interaction workgroups of kGroupSizeSym
@@ -557,6 +518,55 @@ int create_from_host(bltc_plan** out, const bltc_params* p, int64_t nt, const do
 
 }  // namespace
 
+int bltc_internal_upload_symmetric(bltc_plan* plan, bltc::DevicePlan& d,
+                                   const bltc::DirectLists& dl, std::vector<int64_t>* cost,
+                                   hipStream_t s)
+{
+    // unit results: at most 2^31 values (16 GiB)
+    const int64_t sub = plan->prm.precision == BLTC_FP32_MIXED ? bltc::kSymTargetsMixed
+                                                               : bltc::kSymTargetsF64;
+    bltc::SymPlan sp;
+    if (!bltc::plan_symmetric(dl, sub, int64_t(1) << 31, sp))
+        return BLTC_OK;
+    const std::vector<int64_t>& bbeg = *dl.batch_begin;
+    const std::vector<int64_t>& bcnt = *dl.batch_count;
+    std::vector<bltc::SymUnit> units;
+    for (size_t k = 0; k < sp.ub.size(); ++k) {
+        const int32_t b = sp.ub[k], c = sp.uc[k];
+        for (int32_t q = 0; q < sp.nsub[k]; ++q) {
+            bltc::SymUnit su;
+            su.tb = bbeg[b] + q * sub;
+            su.sb = bbeg[c];
+            su.roff = sp.roff[k] + q * sub;
+            su.coff = sp.coff[k] + q * bcnt[c];
+            su.nb = static_cast<int32_t>(std::min<int64_t>(sub, bcnt[b] - q * sub));
+            su.nc = static_cast<int32_t>(bcnt[c]);
+            su.batch = b;
+            su.leaf = (*dl.batch_node)[c];
+            units.push_back(su);
+        }
+    }
+    // heaviest sub-unit first (one wave each)
+    std::stable_sort(units.begin(), units.end(), [](const bltc::SymUnit& a, const bltc::SymUnit& c) {
+        return static_cast<int64_t>(a.nb) * a.nc > static_cast<int64_t>(c.nb) * c.nc;
+    });
+    HIP_TRY(plan->put(&d.sym_unit, units, s));
+    HIP_TRY(plan->alloc(&d.sym_out, static_cast<size_t>(sp.out_size)));
+    HIP_TRY(plan->put(&d.sym_near_off, sp.near_off, s));
+    HIP_TRY(plan->put(&d.sym_near_begin, sp.near_begin, s));
+    HIP_TRY(plan->put(&d.sym_near_count, sp.near_count, s));
+    HIP_TRY(plan->put(&d.sym_near_leaf, sp.near_leaf, s));
+    HIP_TRY(plan->put(&d.sym_pc_off, sp.pc_off, s));
+    HIP_TRY(plan->put(&d.sym_pc_base, sp.pc_base, s));
+    HIP_TRY(plan->put(&d.batch_begin, bbeg, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    d.sym_units = static_cast<int64_t>(units.size());
+    d.sym = 1;
+    plan->sym_pair_evals = sp.pair_evals;
+    *cost = sp.batch_cost;
+    return BLTC_OK;
+}
+
 extern "C" {
 
 void bltc_params_default(bltc_params* p)
@@ -712,6 +722,7 @@ int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out)
         out->degree = plan->prm.degree;
         out->leaf_size = plan->prm.leaf_size;
         out->batch_size = plan->prm.batch_size;
+        out->mutual_pair_evals = plan->sym_pair_evals;
         return BLTC_OK;
     }
     out->clusters = hp.src.nodes();

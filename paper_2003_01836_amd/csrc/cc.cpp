@@ -63,6 +63,7 @@ int create_device(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const
         return fail(BLTC_EHIP, "device tree build: %s", err.c_str());
     if (nt == ns && tx == sx && ty == sy && tz == sz && pp.batch_size == pp.leaf_size) {
         cc.tgt = cc.src;
+        cc.same_tree = true;
         if (nt > 0) {
             HIP_TRY(hipMemcpyAsync(dd.tgt, du.src, nt * sizeof(double4), hipMemcpyDeviceToDevice, s));
             HIP_TRY(hipMemcpyAsync(dd.tgt_orig, src_order, nt * sizeof(int64_t),
@@ -87,7 +88,7 @@ int upload(bltc_plan* plan, hipStream_t s)
 {
     if (plan->uploaded)
         return BLTC_OK;
-    const bltc::CcPlan& cc = plan->ccp;
+    bltc::CcPlan& cc = plan->ccp;
     const bool mixed = plan->prm.precision == BLTC_FP32_MIXED;
     bltc::DevicePlan& du = plan->d;
     bltc::DevicePlan& px = plan->dprox;
@@ -237,6 +238,25 @@ int upload(bltc_plan* plan, hipStream_t s)
             px.qhat32 = dd.qhat32 = du.qhat32;
         }
     }
+    // targets are the sources: mutual direct leaf pairs once for both directions,
+    // and the target-leaf workgroups (one wave each) re-ordered by the work left
+    if (cc.same_tree && !plan->prm.no_symmetry) {
+        const bltc::DirectLists dl{&cc.src,    &cc.tl_node, &cc.tl_begin, &cc.tl_count,
+                                   &cc.dn_off, &cc.dn_leaf, &cc.dn_cost};
+        int rc = bltc_internal_upload_symmetric(plan, dd, dl, &cc.dn_cost, s);
+        if (rc != BLTC_OK)
+            return rc;
+        if (dd.sym) {
+            cc.dg_batch.clear();
+            cc.dg_first.clear();
+            bltc::group_schedule(cc.tl_begin, cc.tl_count, cc.dn_cost, bltc::kGroupSizeSym,
+                                 cc.prm.xcds, cc.dg_batch, cc.dg_first);
+            HIP_TRY(plan->put(&dd.group_batch, cc.dg_batch, s));
+            HIP_TRY(plan->put(&dd.group_first, cc.dg_first, s));
+            dd.ngroups = static_cast<int64_t>(cc.dg_batch.size());
+            dd.group_threads = bltc::kGroupSizeSym;
+        }
+    }
     // host staging vectors die at return: finish the copies first
     HIP_TRY(hipStreamSynchronize(s));
     plan->uploaded = true;
@@ -278,6 +298,7 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStr
     else
         HIP_TRY(bltc::launch_interact(plan->dprox, kp, plan->cp_phat, s));
     HIP_TRY(mark(2));
+    HIP_TRY(bltc::launch_near_pairs(plan->ddir, kp, s));
     if (mixed)
         HIP_TRY(bltc::launch_interact_mixed(plan->ddir, kp, phi, s));
     else

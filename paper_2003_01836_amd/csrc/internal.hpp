@@ -135,6 +135,15 @@ struct bltc_plan {
 // device side of a plan (uploads on first use); synchronises the stream
 int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s);
 
+// Mutual direct pairs of one-tree direct lists evaluated once (see
+// plan_symmetric): plans the units, uploads them, the reduced lists and the
+// per-batch result offsets into d (d.sym = 1), and lowers the lists' batch_cost
+// in *cost to the work left to the batches.  Returns BLTC_OK and leaves d
+// alone when no pair qualifies; `sub` = targets per sub-unit.
+int bltc_internal_upload_symmetric(bltc_plan* plan, bltc::DevicePlan& d,
+                                   const bltc::DirectLists& dl, std::vector<int64_t>* cost,
+                                   hipStream_t s);
+
 // cluster-particle plans (cp.cpp)
 namespace bltc_cp {
 int create_host(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const double* tx,

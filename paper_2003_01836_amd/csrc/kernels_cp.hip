@@ -112,7 +112,7 @@ hipError_t launch_interpolate_targets(const DevicePlan& d, const int32_t* path_o
     switch (d.degree) {
 #define X(n)                                                                                  \
     case n:                                                                                   \
-        hipLaunchKernelGGL(interpolate_targets<n>, grid, dim3(kGroupSize), 0, s, d.tgt,       \
+        hipLaunchKernelGGL(interpolate_targets<n>, grid, dim3(d.group_threads), 0, s, d.tgt,  \
                            d.tgt_orig, d.group_batch, d.group_first, d.batch_end, path_off,   \
                            path_slot, slot_nodes, phat, phi);                                 \
         return hipGetLastError();

@@ -506,22 +506,26 @@ void plan_schedule(HostPlan& hp)
                    hp.group_batch, hp.group_first);
 }
 
-bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, int64_t sub,
-                    int64_t max_out, SymPlan& sp)
+bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, SymPlan& sp)
 {
-    if (!hp.same_tree || sub < 1)
+    if (sub < 1)
         return false;
-    const Tree& S = hp.src;
-    const int64_t nb = static_cast<int64_t>(hp.batch_node.size());
-    if (static_cast<int64_t>(near_leaf.size()) != (nb > 0 ? hp.near_off[nb] : 0))
+    const Tree& S = *dl.tree;
+    const std::vector<int32_t>& batch_node = *dl.batch_node;
+    const std::vector<int64_t>& batch_count = *dl.batch_count;
+    const std::vector<int32_t>& near_off = *dl.near_off;
+    const std::vector<int32_t>& near_leaf = *dl.near_leaf;
+    const int64_t nb = static_cast<int64_t>(batch_node.size());
+    if (static_cast<int64_t>(near_off.size()) != nb + 1 ||
+        static_cast<int64_t>(near_leaf.size()) != (nb > 0 ? near_off[nb] : 0))
         return false;
     std::vector<int32_t> batch_of_node(S.nodes(), -1);
     for (int64_t b = 0; b < nb; ++b)
-        batch_of_node[hp.batch_node[b]] = static_cast<int32_t>(b);
+        batch_of_node[batch_node[b]] = static_cast<int32_t>(b);
     // sorted direct partners (as batches) of every batch, for membership tests
     std::vector<std::vector<int32_t>> partners(nb);
     for (int64_t b = 0; b < nb; ++b) {
-        for (int32_t e = hp.near_off[b]; e < hp.near_off[b + 1]; ++e) {
+        for (int32_t e = near_off[b]; e < near_off[b + 1]; ++e) {
             const int32_t c = batch_of_node[near_leaf[e]];
             if (c < 0)
                 return false;   // a direct entry that is not a leaf
@@ -541,7 +545,7 @@ bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, i
     if (units.empty())
         return false;
     auto evals = [&](const std::pair<int32_t, int32_t>& u) {
-        return hp.batch_count[u.first] * hp.batch_count[u.second];
+        return batch_count[u.first] * batch_count[u.second];
     };
     std::stable_sort(units.begin(), units.end(),
                      [&](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& c) {
@@ -553,7 +557,7 @@ bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, i
     std::map<std::pair<int32_t, int32_t>, int64_t> unit_of;
     for (size_t k = 0; k < units.size(); ++k) {
         const auto& u = units[k];
-        const int64_t nbk = hp.batch_count[u.first], nck = hp.batch_count[u.second];
+        const int64_t nbk = batch_count[u.first], nck = batch_count[u.second];
         const int64_t ns = (nbk + sub - 1) / sub;
         out.ub.push_back(u.first);
         out.uc.push_back(u.second);
@@ -570,9 +574,9 @@ bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, i
     // reduced lists in the original list order, and the costs left to the batches
     out.near_off.assign(nb + 1, 0);
     out.pc_off.assign(nb + 1, 0);
-    out.batch_cost = hp.batch_cost;
+    out.batch_cost = (*dl.batch_cost);
     for (int64_t b = 0; b < nb; ++b) {
-        for (int32_t e = hp.near_off[b]; e < hp.near_off[b + 1]; ++e) {
+        for (int32_t e = near_off[b]; e < near_off[b + 1]; ++e) {
             const int32_t leaf = near_leaf[e];
             const int32_t c = batch_of_node[leaf];
             const bool mutual = c != b && has(c, static_cast<int32_t>(b));
@@ -590,7 +594,7 @@ bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, i
                 out.batch_cost[b] -= S.count[leaf] - 1;   // one read instead of |C| evaluations
             } else {
                 for (int32_t q = 0; q < out.nsub[u]; ++q)
-                    out.pc_base.push_back(out.coff[u] + q * hp.batch_count[b]);
+                    out.pc_base.push_back(out.coff[u] + q * batch_count[b]);
                 out.batch_cost[b] -= S.count[leaf] - out.nsub[u];
             }
         }
@@ -1037,9 +1041,10 @@ void make_cc_plan(CcPlan& cc, const PlanParams& prm,
     cc = CcPlan();
     cc.prm = prm;
     build_tree(cc.src, ns, sx, sy, sz, prm.leaf_size);
-    if (nt == ns && tx == sx && ty == sy && tz == sz && prm.batch_size == prm.leaf_size)
+    if (nt == ns && tx == sx && ty == sy && tz == sz && prm.batch_size == prm.leaf_size) {
         cc.tgt = cc.src;
-    else
+        cc.same_tree = true;
+    } else
         build_tree(cc.tgt, nt, tx, ty, tz, prm.batch_size);
     cc_plan_from_trees(cc);
     cc.setup_seconds =

@@ -124,12 +124,25 @@ struct SymPlan {
     std::vector<int64_t> batch_cost;    // evaluations per target left to the batch's workgroups
 };
 
-// Builds sp from the direct lists (hp.near_off, the leaf of every entry in
-// near_leaf) with sub-units of `sub` targets.  Returns false (sp untouched)
-// when hp.same_tree is false, when there is no mutual pair, or when out_size
-// would exceed max_out values.
-bool plan_symmetric(const HostPlan& hp, const std::vector<int32_t>& near_leaf, int64_t sub,
-                    int64_t max_out, SymPlan& sp);
+// The direct lists of a plan whose batches are the leaves of one tree (the
+// targets are the sources): batch b is the leaf batch_node[b] at positions
+// [batch_begin[b], + batch_count[b]); its direct entries are the leaves
+// near_leaf[near_off[b] .. near_off[b + 1]); batch_cost is the work per
+// target of each batch.
+struct DirectLists {
+    const Tree* tree;
+    const std::vector<int32_t>* batch_node;
+    const std::vector<int64_t>* batch_begin;
+    const std::vector<int64_t>* batch_count;
+    const std::vector<int32_t>* near_off;
+    const std::vector<int32_t>* near_leaf;
+    const std::vector<int64_t>* batch_cost;
+};
+
+// Builds sp from the direct lists with sub-units of `sub` targets.  Returns
+// false (sp untouched) when there is no mutual pair, when a direct entry is
+// not a batch's leaf, or when out_size would exceed max_out values.
+bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, SymPlan& sp);
 
 // Builds the tree with leaf capacity `cap` (readings of the tree rules are
 // documented in planner.cpp).
@@ -281,6 +294,9 @@ struct CcPlan {
     // workgroups: over proxy points (batch = target slot) and over target leaves
     std::vector<int32_t> pg_batch, dg_batch;
     std::vector<int64_t> pg_first, dg_first;
+
+    // targets are the sources (same arrays, same capacity): one tree
+    bool same_tree = false;
 
     int64_t kind_pairs[4] = {0, 0, 0, 0};
     int64_t cc_evals = 0, pc_evals = 0, cp_evals = 0, near_evals = 0;

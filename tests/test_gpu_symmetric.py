@@ -146,3 +146,41 @@ def test_symmetric_large_leaves(dev, precision):
         _close(ref, phi[smp])
     else:
         assert oracle.rel_l2(ref, phi[smp]) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("n,leaf", [(3000, 7), (40000, 1030), (30000, 513)])
+def test_symmetric_block_and_subunit_boundaries(dev, precision, n, leaf):
+    # leaves below one source block (fewer than 8 particles), and leaves just
+    # above one or two sub-units of targets (256 / 512): a last sub-unit of a
+    # few targets, a last block of a few sources
+    pos, q = inputs.uniform_cube(n, 420 + leaf)
+    ps, pn, a, b = _both(dev, pos, q[0], theta=0.6, degree=2 if leaf < 64 else 4, leaf_size=leaf,
+                         batch_size=leaf, precision=precision)
+    assert ps.stats()["mutual_pair_evals"] > 0
+    ref = oracle.Treecode(pos, pos, 0.6, 2 if leaf < 64 else 4, leaf, leaf).potential(q[0])
+    if precision == "fp64":
+        _close(b, a, 1e-13, 1e-14)
+        _close(ref, a)
+    else:
+        assert oracle.rel_l2(ref, a) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("kernel,kappa", KERNEL_CASES)
+def test_cluster_cluster_symmetric(dev, precision, kernel, kappa):
+    # the dual walk on one tree gives mutual direct leaf pairs as well
+    pos, q = inputs.uniform_cube(30000, 430)
+    kk, kern, kpar = kernel_kwargs(kernel, kappa)
+    ps, pn, a, b = _both(dev, pos, q[0], method="cc", theta=0.7, degree=4, leaf_size=300,
+                         batch_size=300, precision=precision, **kk)
+    assert ps.stats()["mutual_pair_evals"] > 0
+    assert pn.stats()["mutual_pair_evals"] == 0
+    ref = oracle.ClusterCluster(pos, pos, 0.7, 4, 300, 300).potential(q[0], kernel=kern,
+                                                                       kappa=kpar)
+    if precision == "fp64":
+        _close(b, a, 1e-13, 1e-14)
+        _close(ref, a)
+    else:
+        assert oracle.rel_l2(ref, a) <= 1e-6
+        assert oracle.rel_l2(ref, b) <= 1e-6
