@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cstring>
 #include <numeric>
+#include <vector>
 
 #include "internal.hpp"
 #include "kernels_cp.hpp"
@@ -67,17 +68,48 @@ int create_device(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const
         return fail(BLTC_EINVAL, "source coordinate %lld is not finite", static_cast<long long>(bad));
     if (!err.empty())
         return fail(BLTC_EHIP, "device tree build: %s", err.c_str());
+    cp.same_arrays = nt == ns && tx == sx && ty == sy && tz == sz && pp.batch_size == pp.leaf_size;
     bltc::cp_plan_from_trees(cp);
     plan->device_particles = true;
     cp.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BLTC_OK;
 }
 
+namespace {
+
+bool same_nodes(const bltc::Tree& a, const bltc::Tree& b)
+{
+    return a.n == b.n && a.begin == b.begin && a.count == b.count && a.nchild == b.nchild &&
+           a.first_child == b.first_child && a.lo == b.lo && a.hi == b.hi;
+}
+
+// Both trees of a device-built plan come from the same arrays with the same
+// capacity: the build is deterministic, and this confirms it (node arrays and
+// particle orders equal) before the one-tree evaluation relies on it.
+int confirm_same_tree(bltc_plan* plan)
+{
+    bltc::CpPlan& cp = plan->cpp;
+    if (!cp.same_arrays || cp.same_tree || !same_nodes(cp.src, cp.tgt))
+        return BLTC_OK;
+    const int64_t n = cp.src.n;
+    std::vector<int64_t> a(n), b(n);
+    if (n > 0) {
+        HIP_TRY(hipMemcpy(a.data(), plan->dprox.src_order, n * sizeof(int64_t),
+                          hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(b.data(), plan->ddir.tgt_orig, n * sizeof(int64_t),
+                          hipMemcpyDeviceToHost));
+    }
+    cp.same_tree = a == b;
+    return BLTC_OK;
+}
+
+}  // namespace
+
 int upload(bltc_plan* plan, hipStream_t s)
 {
     if (plan->uploaded)
         return BLTC_OK;
-    const bltc::CpPlan& cp = plan->cpp;
+    bltc::CpPlan& cp = plan->cpp;
     const bool mixed = plan->prm.precision == BLTC_FP32_MIXED;
     bltc::DevicePlan& px = plan->dprox;
     bltc::DevicePlan& dd = plan->ddir;
@@ -208,6 +240,30 @@ int upload(bltc_plan* plan, hipStream_t s)
         HIP_TRY(plan->alloc(&px.qhat32, 1));
         dd.qhat32 = px.qhat32;
     }
+    // targets are the sources: mutual direct leaf pairs once for both directions,
+    // and the target-leaf workgroups (one wave each) re-ordered by the work left
+    if (cp.same_arrays && !plan->prm.no_symmetry) {
+        int rc = plan->device_particles ? confirm_same_tree(plan) : BLTC_OK;
+        if (rc != BLTC_OK)
+            return rc;
+    }
+    if (cp.same_tree && !plan->prm.no_symmetry) {
+        const bltc::DirectLists dl{&cp.src,    &cp.tl_node, &cp.tl_begin, &cp.tl_count,
+                                   &cp.dn_off, &cp.dn_leaf, &cp.dn_cost};
+        int rc = bltc_internal_upload_symmetric(plan, dd, dl, &cp.dn_cost, s);
+        if (rc != BLTC_OK)
+            return rc;
+        if (dd.sym) {
+            cp.dg_batch.clear();
+            cp.dg_first.clear();
+            bltc::group_schedule(cp.tl_begin, cp.tl_count, cp.dn_cost, bltc::kGroupSizeSym,
+                                 cp.prm.xcds, cp.dg_batch, cp.dg_first);
+            HIP_TRY(plan->put(&dd.group_batch, cp.dg_batch, s));
+            HIP_TRY(plan->put(&dd.group_first, cp.dg_first, s));
+            dd.ngroups = static_cast<int64_t>(cp.dg_batch.size());
+            dd.group_threads = bltc::kGroupSizeSym;
+        }
+    }
     // host staging vectors die at return: finish the copies first
     HIP_TRY(hipStreamSynchronize(s));
     plan->uploaded = true;
@@ -246,6 +302,7 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStr
     else
         HIP_TRY(bltc::launch_interact(plan->dprox, kp, plan->cp_phat, s));
     HIP_TRY(mark(2));
+    HIP_TRY(bltc::launch_near_pairs(plan->ddir, kp, s));
     if (mixed)
         HIP_TRY(bltc::launch_interact_mixed(plan->ddir, kp, phi, s));
     else

@@ -792,9 +792,10 @@ void make_cp_plan(CpPlan& cp, const PlanParams& prm,
     cp = CpPlan();
     cp.prm = prm;
     build_tree(cp.tgt, nt, tx, ty, tz, prm.leaf_size);
-    if (nt == ns && tx == sx && ty == sy && tz == sz && prm.batch_size == prm.leaf_size)
+    if (nt == ns && tx == sx && ty == sy && tz == sz && prm.batch_size == prm.leaf_size) {
         cp.src = cp.tgt;
-    else
+        cp.same_arrays = cp.same_tree = true;
+    } else
         build_tree(cp.src, ns, sx, sy, sz, prm.batch_size);
     cp_plan_from_trees(cp);
     cp.setup_seconds =

@@ -204,6 +204,10 @@ struct CpPlan {
     int32_t np = 0;
     int64_t P = 0;
     Tree tgt, src;
+    // targets are the sources (same arrays, same capacity); same_tree once the
+    // two trees (and particle orders) are known to be identical
+    bool same_arrays = false;
+    bool same_tree = false;
 
     // source batches (leaves of the source tree) and target leaves, each
     // ordered by first position

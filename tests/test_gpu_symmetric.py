@@ -126,7 +126,7 @@ def test_symmetric_not_used_where_it_does_not_apply(dev):
     assert bltc.Plan(t, t2, leaf_size=400, batch_size=400).stats()["mutual_pair_evals"] == 0
     assert bltc.Plan(t, t, leaf_size=400, batch_size=300).stats()["mutual_pair_evals"] == 0
     assert bltc.Plan(t, t, leaf_size=400, batch_size=400, max_q=2).stats()["mutual_pair_evals"] == 0
-    assert bltc.Plan(t, t, leaf_size=400, batch_size=400, method="cp").stats()["mutual_pair_evals"] == 0
+    assert bltc.Plan(t, t, leaf_size=400, batch_size=300, method="cp").stats()["mutual_pair_evals"] == 0
 
 
 
@@ -166,18 +166,20 @@ def test_symmetric_block_and_subunit_boundaries(dev, precision, n, leaf):
         assert oracle.rel_l2(ref, a) <= 1e-6
 
 
+@pytest.mark.parametrize("method", ["cc", "cp"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 @pytest.mark.parametrize("kernel,kappa", KERNEL_CASES)
-def test_cluster_cluster_symmetric(dev, precision, kernel, kappa):
-    # the dual walk on one tree gives mutual direct leaf pairs as well
+def test_cluster_cluster_and_particle_symmetric(dev, method, precision, kernel, kappa):
+    # the dual walk (cc) and the walk of the source batches (cp) on one tree
+    # give mutual direct leaf pairs as well
     pos, q = inputs.uniform_cube(30000, 430)
     kk, kern, kpar = kernel_kwargs(kernel, kappa)
-    ps, pn, a, b = _both(dev, pos, q[0], method="cc", theta=0.7, degree=4, leaf_size=300,
+    ps, pn, a, b = _both(dev, pos, q[0], method=method, theta=0.7, degree=4, leaf_size=300,
                          batch_size=300, precision=precision, **kk)
     assert ps.stats()["mutual_pair_evals"] > 0
     assert pn.stats()["mutual_pair_evals"] == 0
-    ref = oracle.ClusterCluster(pos, pos, 0.7, 4, 300, 300).potential(q[0], kernel=kern,
-                                                                       kappa=kpar)
+    cls = oracle.ClusterCluster if method == "cc" else oracle.ClusterParticle
+    ref = cls(pos, pos, 0.7, 4, 300, 300).potential(q[0], kernel=kern, kappa=kpar)
     if precision == "fp64":
         _close(b, a, 1e-13, 1e-14)
         _close(ref, a)
