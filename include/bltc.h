@@ -130,7 +130,9 @@ typedef struct {
                                  /* evaluate each pair of different leaves that are in  */
                                  /* each other's direct lists once for both directions  */
                                  /* (G(x,y) = G(y,x)); 1: never.  Same potentials up to */
-                                 /* rounding order.                                     */
+                                 /* rounding order.  The pair results take 8 B per     */
+                                 /* target and pair (at most a quarter of the free      */
+                                 /* device memory: the heaviest pairs first).           */
 } bltc_params;
 
 /* Fills *p with the defaults: Coulomb, FP64, theta 0.7, degree 8,

@@ -522,11 +522,14 @@ int bltc_internal_upload_symmetric(bltc_plan* plan, bltc::DevicePlan& d,
                                    const bltc::DirectLists& dl, std::vector<int64_t>* cost,
                                    hipStream_t s)
 {
-    // unit results: at most 2^31 values (16 GiB)
+    // unit results (8 B each): at most a quarter of the free device memory
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const int64_t max_out = static_cast<int64_t>(free_b / 4 / sizeof(double));
     const int64_t sub = plan->prm.precision == BLTC_FP32_MIXED ? bltc::kSymTargetsMixed
                                                                : bltc::kSymTargetsF64;
     bltc::SymPlan sp;
-    if (!bltc::plan_symmetric(dl, sub, int64_t(1) << 31, sp))
+    if (!bltc::plan_symmetric(dl, sub, max_out, sp))
         return BLTC_OK;
     const std::vector<int64_t>& bbeg = *dl.batch_begin;
     const std::vector<int64_t>& bcnt = *dl.batch_count;

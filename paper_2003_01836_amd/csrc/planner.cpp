@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <map>
+#include <unordered_map>
 #include <atomic>
 #include <chrono>
 #include <climits>
@@ -551,25 +552,32 @@ bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, SymPlan
                      [&](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& c) {
                          return evals(a) > evals(c);
                      });
+    // heaviest first while the results fit in max_out values; the mutual pairs
+    // left over stay in the lists
     SymPlan out;
     out.sub = sub;
     int64_t off = 0;
-    std::map<std::pair<int32_t, int32_t>, int64_t> unit_of;
-    for (size_t k = 0; k < units.size(); ++k) {
-        const auto& u = units[k];
+    std::unordered_map<int64_t, int64_t> unit_of;
+    unit_of.reserve(units.size());
+    auto key = [](int32_t lo, int32_t hi) {
+        return (static_cast<int64_t>(lo) << 32) | static_cast<uint32_t>(hi);
+    };
+    for (const auto& u : units) {
         const int64_t nbk = batch_count[u.first], nck = batch_count[u.second];
         const int64_t ns = (nbk + sub - 1) / sub;
+        if (off + nbk + ns * nck > max_out)
+            continue;
+        unit_of[key(u.first, u.second)] = static_cast<int64_t>(out.ub.size());
         out.ub.push_back(u.first);
         out.uc.push_back(u.second);
         out.nsub.push_back(static_cast<int32_t>(ns));
         out.roff.push_back(off);
         out.coff.push_back(off + nbk);
-        unit_of[u] = static_cast<int64_t>(k);
         off += nbk + ns * nck;
         out.pair_evals += evals(u);
     }
     out.out_size = off;
-    if (out.out_size > max_out)
+    if (out.ub.empty())
         return false;
     // reduced lists in the original list order, and the costs left to the batches
     out.near_off.assign(nb + 1, 0);
@@ -579,16 +587,16 @@ bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, SymPlan
         for (int32_t e = near_off[b]; e < near_off[b + 1]; ++e) {
             const int32_t leaf = near_leaf[e];
             const int32_t c = batch_of_node[leaf];
-            const bool mutual = c != b && has(c, static_cast<int32_t>(b));
-            if (!mutual) {
+            const int32_t lo = std::min<int32_t>(static_cast<int32_t>(b), c);
+            const int32_t hi = std::max<int32_t>(static_cast<int32_t>(b), c);
+            const auto it = c != b ? unit_of.find(key(lo, hi)) : unit_of.end();
+            if (it == unit_of.end()) {
                 out.near_leaf.push_back(leaf);
                 out.near_begin.push_back(S.begin[leaf]);
                 out.near_count.push_back(S.count[leaf]);
                 continue;
             }
-            const int32_t lo = std::min<int32_t>(static_cast<int32_t>(b), c);
-            const int32_t hi = std::max<int32_t>(static_cast<int32_t>(b), c);
-            const int64_t u = unit_of[{lo, hi}];
+            const int64_t u = it->second;
             if (b == lo) {
                 out.pc_base.push_back(out.roff[u]);
                 out.batch_cost[b] -= S.count[leaf] - 1;   // one read instead of |C| evaluations

@@ -139,9 +139,10 @@ struct DirectLists {
     const std::vector<int64_t>* batch_cost;
 };
 
-// Builds sp from the direct lists with sub-units of `sub` targets.  Returns
-// false (sp untouched) when there is no mutual pair, when a direct entry is
-// not a batch's leaf, or when out_size would exceed max_out values.
+// Builds sp from the direct lists with sub-units of `sub` targets; the units
+// are taken heaviest first while out_size stays within max_out values (the
+// mutual pairs left over stay in the lists).  Returns false (sp untouched)
+// when no unit is taken or a direct entry is not a batch's leaf.
 bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, SymPlan& sp);
 
 // Builds the tree with leaf capacity `cap` (readings of the tree rules are
