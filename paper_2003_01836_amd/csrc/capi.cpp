@@ -217,7 +217,16 @@ void schedule_single_vector(bltc_plan* plan)
     hp.prm.group_size = bltc::kGroupSizeSym;
     hp.group_batch.clear();
     hp.group_first.clear();
-    bltc::group_schedule(hp.batch_begin, hp.batch_count, hp.batch_cost, hp.prm.group_size,
+    // time per target: a direct term costs about 2.2 far-field terms (three
+    // differences and squares against one add per kernel value)
+    const int64_t nb = static_cast<int64_t>(hp.batch_begin.size());
+    std::vector<int64_t> cost(nb);
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t far = static_cast<int64_t>(hp.far_off[b + 1] - hp.far_off[b]) * hp.P;
+        const int64_t near = std::max<int64_t>(0, hp.batch_cost[b] - far);
+        cost[b] = far + (near * 22) / 10;
+    }
+    bltc::group_schedule(hp.batch_begin, hp.batch_count, cost, hp.prm.group_size,
                          hp.prm.xcds, hp.group_batch, hp.group_first);
     plan->d.ngroups = static_cast<int64_t>(hp.group_batch.size());
     plan->d.group_threads = bltc::kGroupSizeSym;
