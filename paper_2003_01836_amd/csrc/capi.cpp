@@ -562,8 +562,16 @@ int bltc_internal_upload_symmetric(bltc_plan* plan, bltc::DevicePlan& d,
     std::stable_sort(units.begin(), units.end(), [](const bltc::SymUnit& a, const bltc::SymUnit& c) {
         return static_cast<int64_t>(a.nb) * a.nc > static_cast<int64_t>(c.nb) * c.nc;
     });
+    // the results first: if the device cannot hold them, keep the plain lists
+    double* out = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&out), static_cast<size_t>(sp.out_size) * sizeof(double)) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return BLTC_OK;
+    }
+    plan->allocations.push_back(out);
+    d.sym_out = out;
     HIP_TRY(plan->put(&d.sym_unit, units, s));
-    HIP_TRY(plan->alloc(&d.sym_out, static_cast<size_t>(sp.out_size)));
     HIP_TRY(plan->put(&d.sym_near_off, sp.near_off, s));
     HIP_TRY(plan->put(&d.sym_near_begin, sp.near_begin, s));
     HIP_TRY(plan->put(&d.sym_near_count, sp.near_count, s));
