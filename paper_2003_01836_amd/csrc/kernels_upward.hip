@@ -237,6 +237,241 @@ __device__ __forceinline__ void upward_chunk(
     }
 }
 
+// ---------------------------------------------------------------------------
+// One charge vector, Lagrange factors, n + 1 = NP <= 16 nodes per dimension:
+// the output Qhat[k1][(k2, k3)] has one row tile (k1 < NP <= 16) and
+// CT = ceil(NP^2 / 16) column tiles.  Every wave accumulates all CT tiles over
+// a quarter of the sources (wave w takes the steps of 4 sources st = w mod 4),
+// and the four partial tiles are summed in LDS in the fixed order
+// (w0 + w2) + (w1 + w3).  The factors of 128 sources at a time are formed by
+// two of the waves, in turns, with the degree known at compile time (the 3 NP
+// reciprocals of a source are independent and pipeline); the row operand
+// a_1[j][k1] q~_j is stored ready for the matrix core.  Factor rows have one
+// zero entry past the last node, which the lanes of rows k1 >= NP and of
+// columns past NP^2 read instead of branching.
+
+// |d| < DBL_MIN: zero or subnormal (class bits of -/+ zero and -/+ subnormal)
+__device__ __forceinline__ bool below_normal(double d)
+{
+    return __builtin_amdgcn_class(d, 0x0F0);
+}
+
+// The 1-D factors a_k = w_k / (y - s_k) of eq. 14 without the coincidence
+// rule, and D = sum_k a_k; `tiny` tells whether some |y - s_k| < DBL_MIN (then
+// these values are not used: the caller applies eq. 5).
+template <int NP>
+__device__ __forceinline__ double factors_np(double yv, const double* __restrict__ s,
+                                             double* __restrict__ a, bool& tiny)
+{
+    double sum = 0.0;
+    bool t = false;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const double d = yv - s[k];
+        t |= below_normal(d);
+        // 1/d: hardware estimate refined by two Newton steps r <- r + r (1 - d r)
+        double r = __builtin_amdgcn_rcp(d);
+        r = fma(fma(-d, r, 1.0), r, r);
+        r = fma(fma(-d, r, 1.0), r, r);
+        const double v = ((k & 1) ? -1.0 : 1.0) * ((k == 0 || k == NP - 1) ? 0.5 : 1.0) * r;
+        a[k] = v;
+        sum += v;
+    }
+    tiny = t;
+    return sum;
+}
+
+// eq. 5: the row of a coordinate that coincides with a node is one-hot at the
+// lowest such node, times `scale`
+template <int NP>
+__device__ __forceinline__ void one_hot_row(double yv, const double* __restrict__ s, double scale,
+                                            double* __restrict__ row)
+{
+    int hit = NP;
+#pragma unroll
+    for (int k = NP - 1; k >= 0; --k)
+        if (below_normal(yv - s[k]))
+            hit = k;
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+        row[k] = (k == hit) ? scale : 0.0;
+}
+
+template <int NP>
+constexpr int single_lds_doubles()
+{
+    // factor rows [kTile][NP + 1] x 3, or two waves' partial tiles [CT][4][64]
+    return 3 * kTile * (NP + 1) > 2 * ((NP * NP + 15) / 16) * 256
+               ? 3 * kTile * (NP + 1)
+               : 2 * ((NP * NP + 15) / 16) * 256;
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) void upward_single(
+    const double4* __restrict__ src, const int32_t* __restrict__ chunk_slot,
+    const int64_t* __restrict__ chunk_begin, const int64_t* __restrict__ chunk_count,
+    const int64_t* __restrict__ chunk_dst, const double* __restrict__ slot_nodes,
+    double* __restrict__ out)
+{
+    constexpr int NP2 = NP * NP;
+    constexpr int CT = (NP2 + 15) / 16;
+    constexpr int SP = NP + 1;                      // row stride: NP factors and a zero
+    __shared__ double lds[single_lds_doubles<NP>()];
+    double* __restrict__ A1 = lds;                  // [kTile][SP]  a_1 q~
+    double* __restrict__ A2 = A1 + kTile * SP;      // [kTile][SP]
+    double* __restrict__ A3 = A2 + kTile * SP;      // [kTile][SP]
+
+    const int c = blockIdx.x;
+    const int64_t slot = chunk_slot[c];
+    const int64_t begin = chunk_begin[c];
+    const int64_t count = chunk_count[c];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double* __restrict__ sn = slot_nodes + slot * 3 * NP;   // wave-uniform
+
+    // this lane's operand offsets: row k1 = lane % 16, columns ct * 16 + lane % 16
+    // (rows and columns past the end point at the zero entry)
+    const int k1 = lane & 15;
+    const int off1 = (lane >> 4) * SP + (k1 < NP ? k1 : NP);
+    int off2[CT], off3[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const int cc = ct * 16 + (lane & 15);
+        off2[ct] = (lane >> 4) * SP + (cc < NP2 ? cc / NP : 0);
+        off3[ct] = (lane >> 4) * SP + (cc < NP2 ? cc - (cc / NP) * NP : NP);
+    }
+    d4v acc[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+        acc[ct] = d4v{0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t t0 = 0; t0 < count; t0 += kTile) {
+        const int tn = static_cast<int>(count - t0 < kTile ? count - t0 : kTile);
+        // waves 0-1 and 2-3 take turns forming the factors (two SIMDs each)
+        const int ft = tid - ((static_cast<int>(t0 / kTile) & 1) ? kTile : 0);
+        if (ft >= 0 && ft < kTile) {
+            // z and y factors go to LDS as they are formed; x waits for q~.
+            // Rows past the chunk's end get q~ = 0 (their x row is zero).
+            double a[NP];
+            double4 p = double4{0.0, 0.0, 0.0, 0.0};
+            const bool live = ft < tn;
+            if (live)
+                p = src[begin + t0 + ft];
+            bool tz, ty, tx;
+            const double Dz = factors_np<NP>(p.z, sn + 2 * NP, a, tz);
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                A3[ft * SP + k] = a[k];
+            A3[ft * SP + NP] = 0.0;
+            const double Dy = factors_np<NP>(p.y, sn + NP, a, ty);
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                A2[ft * SP + k] = a[k];
+            A2[ft * SP + NP] = 0.0;
+            const double Dx = factors_np<NP>(p.x, sn, a, tx);
+            const double D = (tx ? 1.0 : Dx) * (ty ? 1.0 : Dy) * (tz ? 1.0 : Dz);
+            const double qt = live ? p.w / D : 0.0;
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                A1[ft * SP + k] = a[k] * qt;
+            A1[ft * SP + NP] = 0.0;
+            if (tx || ty || tz) {
+                // rare: a coordinate on a node (eq. 5)
+                if (tz)
+                    one_hot_row<NP>(p.z, sn + 2 * NP, 1.0, A3 + ft * SP);
+                if (ty)
+                    one_hot_row<NP>(p.y, sn + NP, 1.0, A2 + ft * SP);
+                if (tx)
+                    one_hot_row<NP>(p.x, sn, qt, A1 + ft * SP);
+            }
+        }
+        __syncthreads();
+        const int steps = (tn + 3) / 4;
+        for (int st = wave; st < steps; st += 4) {
+            const int jb = 4 * st * SP;
+            const double av = A1[jb + off1];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const double bv = A2[jb + off2[ct]] * A3[jb + off3[ct]];
+                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+    // (w0 + w2) + (w1 + w3) through LDS; lane l, register r holds D[4r + l/16][l % 16]
+    if (wave >= 2) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                lds[(((wave - 2) * CT + ct) * 4 + r) * 64 + lane] = acc[ct][r];
+    }
+    __syncthreads();
+    if (wave < 2) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                acc[ct][r] += lds[((wave * CT + ct) * 4 + r) * 64 + lane];
+    }
+    __syncthreads();
+    if (wave == 1) {
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                lds[(ct * 4 + r) * 64 + lane] = acc[ct][r];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double* __restrict__ dst = out + chunk_dst[c] * static_cast<int64_t>(NP2) * NP;
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            const int cc = ct * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 4 * r + (lane >> 4);
+                if (row < NP && cc < NP2)
+                    dst[row * NP2 + cc] = acc[ct][r] + lds[(ct * 4 + r) * 64 + lane];
+            }
+        }
+    }
+}
+
+template <int NP>
+hipError_t launch_single_np(const DevicePlan& d, double* buf, hipStream_t s)
+{
+    hipLaunchKernelGGL(upward_single<NP>, dim3(static_cast<unsigned>(d.nchunks)), dim3(256), 0, s,
+                       d.src, d.chunk_slot, d.chunk_begin, d.chunk_count, d.chunk_dst,
+                       d.slot_nodes, buf);
+    return hipGetLastError();
+}
+
+// n + 1 <= 16 nodes: the single-vector kernel; returns false for other degrees
+bool launch_single(const DevicePlan& d, double* buf, hipStream_t s, hipError_t* err)
+{
+    switch (d.degree + 1) {
+    case 2: *err = launch_single_np<2>(d, buf, s); return true;
+    case 3: *err = launch_single_np<3>(d, buf, s); return true;
+    case 4: *err = launch_single_np<4>(d, buf, s); return true;
+    case 5: *err = launch_single_np<5>(d, buf, s); return true;
+    case 6: *err = launch_single_np<6>(d, buf, s); return true;
+    case 7: *err = launch_single_np<7>(d, buf, s); return true;
+    case 8: *err = launch_single_np<8>(d, buf, s); return true;
+    case 9: *err = launch_single_np<9>(d, buf, s); return true;
+    case 10: *err = launch_single_np<10>(d, buf, s); return true;
+    case 11: *err = launch_single_np<11>(d, buf, s); return true;
+    case 12: *err = launch_single_np<12>(d, buf, s); return true;
+    case 13: *err = launch_single_np<13>(d, buf, s); return true;
+    case 14: *err = launch_single_np<14>(d, buf, s); return true;
+    case 15: *err = launch_single_np<15>(d, buf, s); return true;
+    case 16: *err = launch_single_np<16>(d, buf, s); return true;
+    default: return false;
+    }
+}
+
 __global__ __launch_bounds__(256) void upward_mfma_f64(
     const double4* __restrict__ src, const double* __restrict__ qm, int32_t mw,
     const int32_t* __restrict__ chunk_slot, const int64_t* __restrict__ chunk_begin,
@@ -372,10 +607,16 @@ hipError_t launch_upward_mfma(const DevicePlan& d, int32_t mw, double* buf, floa
 {
     if (d.nchunks == 0)
         return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (mw == 1 && !d.hermite && launch_single(d, buf, s, &e)) {
+        if (e != hipSuccess)
+            return e;
+        return launch_upward_reduce(d, mw, buf, qhat32, s);
+    }
     const int32_t np = d.degree + 1;
     const int32_t nf = d.hermite ? 2 * np : np;
     const size_t lds = upward_lds_bytes(np, mw, nf);
-    hipError_t e = upward_prepare(lds);
+    e = upward_prepare(lds);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(upward_mfma_f64, dim3(static_cast<unsigned>(d.nchunks), upward_passes(nf, mw)),

@@ -411,6 +411,44 @@ def test_modified_charges_multi_chunk_clusters(dev, m):
             assert np.max(np.abs(ref[qi] - got)) <= 1e-12 * np.max(np.abs(ref[qi])), (c, qi)
 
 
+@pytest.mark.parametrize("degree", list(range(1, 17)))
+def test_modified_charges_every_degree(dev, degree):
+    # one charge vector at every degree (n + 1 = 2..17 points per dimension):
+    # the root spans several upward-pass chunks with a ragged last one, its
+    # children one chunk each; some sources sit on Chebyshev points of the
+    # root in one, two or three coordinates (the rule of eq. 5)
+    g = np.random.default_rng(150 + degree)
+    src = g.uniform(-1, 1, (9001, 3))
+    src[0] = (-1.0, -1.0, -1.0)
+    src[1] = (1.0, 1.0, 1.0)          # root box [-1, 1]^3
+    s, _ = oracle.chebyshev(degree, -1.0, 1.0)
+    k = len(s)
+    for i in range(k):
+        src[2 + 3 * i, 0] = s[i]
+        src[3 + 3 * i, :2] = (s[i], s[(i + 1) % k])
+        src[4 + 3 * i] = (s[i], s[(i + 2) % k], s[(i + 3) % k])
+    q = g.uniform(-1, 1, len(src))
+    tgt = np.concatenate([g.uniform(-1, 1, (2000, 3)) + [9.0, 0.0, 0.0],
+                          g.uniform(-1, 1, (2000, 3)) + [2.6, 0.0, 0.0]])
+    plan, phi = _run_plan(dev, tgt, src, q, theta=0.7, degree=degree, leaf_size=2000,
+                          batch_size=300)
+    oc = oracle.Treecode(tgt, src, 0.7, degree, 2000, 300)
+    v = plan.view()
+    oorder = oc.source_order()
+    okey = {}
+    for c in range(oc.n_clusters):
+        info = oc.cluster(c)
+        okey[tuple(np.sort(oorder[info["begin"]:info["begin"] + info["count"]]))] = c
+    approx = np.unique(v["item_cluster"][v["item_kind"] == 0])
+    assert approx.size and v["cluster_count"][approx].max() == len(src)
+    for c in approx:
+        key = tuple(np.sort(v["source_order"][v["cluster_begin"][c]:v["cluster_begin"][c] + v["cluster_count"][c]]))
+        ref = oc.modified_charges(okey[key], q)
+        got = plan.modified_charges(c)
+        assert np.max(np.abs(ref - got)) <= 1e-12 * np.max(np.abs(ref)), c
+    _close(oc.potential(q), phi)
+
+
 # --------------------------------------------------------------------------
 # many systems in one work-queue launch, replayed from a hipGraph
 # --------------------------------------------------------------------------
