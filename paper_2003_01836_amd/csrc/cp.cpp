@@ -2,19 +2,20 @@
 // BLTC_CLUSTER_PARTICLE): the barycentric interpolation of Sec. II applied to
 // the target variable.
 //
-// Device layout reuses the interaction kernels twice:
-//  * proxy potentials: the "targets" are the Chebyshev points of every target
-//    cluster that some source batch approximates (one "batch" per cluster,
-//    (n+1)^3 points), their lists hold the source batches approximated with
-//    the cluster; the result is phat[slot][k];
-//  * direct sums: the targets in target-tree order, one batch per target
-//    leaf, lists holding the source batches of the direct pairs of every
-//    cluster on the leaf's root-to-leaf path; phi is written once;
+// Device layout:
+//  * proxy potentials (their own kernel, kernels_cp.hip): one "batch" per
+//    target cluster that some source batch approximates, its list holding
+//    those source batches; the result is phat[slot][k] at the cluster's
+//    (n+1)^3 Chebyshev points;
+//  * direct sums (the interaction kernels): the targets in target-tree
+//    order, one batch per target leaf, lists holding the source batches of
+//    the direct pairs of every cluster on the leaf's root-to-leaf path; phi
+//    is written once;
 // and then interpolate_targets adds, for every target, the interpolant of the
 // proxy potentials of each cluster on its path (kernels_cp.hip).
+#include <algorithm>
 #include <chrono>
 #include <cstring>
-#include <numeric>
 #include <vector>
 
 #include "internal.hpp"
@@ -24,6 +25,11 @@
 using bltc_detail::fail;
 
 namespace bltc_cp {
+
+// pieces of the proxy-potential lists (one wave per piece and part of the
+// grid): at least this many sources each, and about kProxyPieces in all
+constexpr int64_t kProxyPieceSources = 8192;
+constexpr int64_t kProxyPieces = 16384;
 
 int create_host(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const double* tx,
                 const double* ty, const double* tz, int64_t ns, const double* sx, const double* sy,
@@ -155,41 +161,62 @@ int upload(bltc_plan* plan, hipStream_t s)
     px.degree = dd.degree = plan->prm.degree;
     px.ns = dd.ns = ns;
 
-    // proxy points of the slots, expanded in the order of the proxy potentials
-    std::vector<double4> prox(static_cast<size_t>(nslots * P));
-    for (int64_t sl = 0; sl < nslots; ++sl) {
-        const double* nd = cp.slot_nodes.data() + sl * 3 * np;
-        for (int32_t k1 = 0; k1 < np; ++k1)
-            for (int32_t k2 = 0; k2 < np; ++k2)
-                for (int32_t k3 = 0; k3 < np; ++k3)
-                    prox[static_cast<size_t>(sl * P + (k1 * np + k2) * np + k3)] =
-                        make_double4(nd[k1], nd[np + k2], nd[2 * np + k3], 0.0);
-    }
-    std::vector<int64_t> prox_orig(prox.size());
-    std::iota(prox_orig.begin(), prox_orig.end(), int64_t(0));
-    std::vector<int64_t> prox_end(nslots), leaf_end(ntl);
-    for (int64_t sl = 0; sl < nslots; ++sl)
-        prox_end[sl] = (sl + 1) * P;
+    // proxy potentials: one "batch" per slot, its list the source batches
+    // approximated with the slot's cluster; the proxy points are formed from
+    // the slot's grid inside the kernel
+    std::vector<int64_t> leaf_end(ntl);
     for (int64_t t = 0; t < ntl; ++t)
         leaf_end[t] = cp.tl_begin[t] + cp.tl_count[t];
-    const std::vector<int32_t> far_off_p(nslots + 1, 0), far_off_d(ntl + 1, 0), one_i(1, 0);
+    const std::vector<int32_t> far_off_d(ntl + 1, 0), one_i(1, 0);
     const std::vector<double> one_d(1, 0.0);
 
+    // each slot's list cut into pieces of whole entries and at most
+    // `piece` sources (one entry may exceed it), so that the heaviest clusters
+    // do not set the run time; a slot's only piece writes its row, several
+    // pieces write partial rows past nslots
+    int64_t listed = 0;
+    for (const int64_t c : cp.pf_count)
+        listed += c;
+    const int64_t piece = std::max(kProxyPieceSources, (listed + kProxyPieces - 1) / kProxyPieces);
+    std::vector<int32_t> piece_slot, slot_piece_off(nslots + 1, 0);
+    std::vector<int64_t> piece_entry, piece_entries, piece_row;
+    int64_t rows = nslots;
+    for (int64_t sl = 0; sl < nslots; ++sl) {
+        const size_t first = piece_slot.size();
+        int32_t e0 = cp.pf_off[sl];
+        int64_t run = 0;
+        for (int32_t e = cp.pf_off[sl]; e < cp.pf_off[sl + 1]; ++e) {
+            if (run > 0 && run + cp.pf_count[e] > piece) {
+                piece_slot.push_back(static_cast<int32_t>(sl));
+                piece_entry.push_back(e0);
+                piece_entries.push_back(e - e0);
+                e0 = e;
+                run = 0;
+            }
+            run += cp.pf_count[e];
+        }
+        piece_slot.push_back(static_cast<int32_t>(sl));
+        piece_entry.push_back(e0);
+        piece_entries.push_back(cp.pf_off[sl + 1] - e0);
+        const size_t np_sl = piece_slot.size() - first;
+        for (size_t k = 0; k < np_sl; ++k)
+            piece_row.push_back(np_sl == 1 ? sl : rows++);
+        slot_piece_off[sl + 1] = static_cast<int32_t>(piece_slot.size());
+    }
+
     px.nt = nslots * P;
-    px.nslots = 0;
+    px.nslots = nslots;
+    px.nchunks = static_cast<int64_t>(piece_slot.size());
     px.nbatches = nslots;
-    px.ngroups = static_cast<int64_t>(cp.pg_batch.size());
-    HIP_TRY(plan->put(&px.tgt, prox, s));
-    HIP_TRY(plan->put(&px.tgt_orig, prox_orig, s));
-    HIP_TRY(plan->put(&px.group_batch, cp.pg_batch, s));
-    HIP_TRY(plan->put(&px.group_first, cp.pg_first, s));
-    HIP_TRY(plan->put(&px.batch_end, prox_end, s));
-    HIP_TRY(plan->put(&px.far_off, far_off_p, s));
-    HIP_TRY(plan->put(&px.far_slot, one_i, s));
-    HIP_TRY(plan->put(&px.near_off, cp.pf_off, s));
+    px.ngroups = 0;
     HIP_TRY(plan->put(&px.near_begin, cp.pf_begin, s));
     HIP_TRY(plan->put(&px.near_count, cp.pf_count, s));
     HIP_TRY(plan->put(&px.near_leaf, cp.pf_leaf, s));
+    HIP_TRY(plan->put(&px.chunk_slot, piece_slot, s));
+    HIP_TRY(plan->put(&px.chunk_begin, piece_entry, s));
+    HIP_TRY(plan->put(&px.chunk_count, piece_entries, s));
+    HIP_TRY(plan->put(&px.chunk_dst, piece_row, s));
+    HIP_TRY(plan->put(&px.slot_chunk_off, slot_piece_off, s));
     HIP_TRY(plan->put(&px.slot_nodes, one_d, s));
     HIP_TRY(plan->put(&px.qhat, one_d, s));
 
@@ -212,7 +239,7 @@ int upload(bltc_plan* plan, hipStream_t s)
     HIP_TRY(plan->put(&plan->cp_path_off, cp.dw_off, s));
     HIP_TRY(plan->put(&plan->cp_path_slot, cp.dw_slot, s));
     HIP_TRY(plan->put(&plan->cp_slot_nodes, cp.slot_nodes, s));
-    HIP_TRY(plan->alloc(&plan->cp_phat, static_cast<size_t>(nslots * P)));
+    HIP_TRY(plan->alloc(&plan->cp_phat, static_cast<size_t>(rows * P)));
 
     if (mixed) {
         // per source node (the lists name source leaves): center and radius;
@@ -297,10 +324,7 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStr
     HIP_TRY(mark(0));
     HIP_TRY(bltc::launch_gather_charges(plan->dprox, q, s));
     HIP_TRY(mark(1));
-    if (mixed)
-        HIP_TRY(bltc::launch_interact_mixed(plan->dprox, kp, plan->cp_phat, s));
-    else
-        HIP_TRY(bltc::launch_interact(plan->dprox, kp, plan->cp_phat, s));
+    HIP_TRY(bltc::launch_proxy_potentials(plan->dprox, plan->cp_slot_nodes, kp, plan->cp_phat, s));
     HIP_TRY(mark(2));
     HIP_TRY(bltc::launch_near_pairs(plan->ddir, kp, s));
     if (mixed)

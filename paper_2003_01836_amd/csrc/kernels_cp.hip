@@ -1,12 +1,12 @@
-// kernels_cp.hip -- cluster-particle treecode: interpolation of the proxy
-// potentials down to the targets.
+// kernels_cp.hip -- cluster-particle treecode: proxy potentials at the
+// target clusters' Chebyshev points, and their interpolation down to the
+// targets.
 //
-// Proxy potentials (the sources of a batch summed at a target cluster's
-// Chebyshev points) and direct sums reuse the interaction kernels: proxy
-// points are just targets whose "batch" is their cluster.  What is new is the
-// last step: every target receives, for each cluster on its root-to-leaf path
-// that has proxy potentials, the barycentric interpolant (eq. 4, tensor
-// product over x, y, z) of those potentials at its position:
+// Direct sums reuse the interaction kernels.  The proxy potentials have their
+// own kernel (below), which uses the tensor-product form of each cluster's
+// grid.  The last step: every target receives, for each cluster on its
+// root-to-leaf path that has proxy potentials, the barycentric interpolant
+// (eq. 4, tensor product over x, y, z) of those potentials at its position:
 //   phi(x) += sum_k L_k1(x1) L_k2(x2) L_k3(x3) phihat_k
 //           = (sum_k a_1k1 a_2k2 a_3k3 phihat_k) / (D_1 D_2 D_3),
 // with a_lk = w_k / (x_l - t_lk) and D_l = sum_k a_lk, or a one-hot row and
@@ -15,10 +15,13 @@
 // cluster grids and proxy potentials are wave-uniform (scalar loads).
 #include <cfloat>
 
+#include "device_common.hpp"
 #include "kernels_cp.hpp"
 
 namespace bltc {
 namespace {
+
+using namespace dev;
 
 template <int NP>
 __device__ __forceinline__ double interp_factors(double x, const double* __restrict__ t,
@@ -97,10 +100,199 @@ __global__ __launch_bounds__(kGroupSize) void interpolate_targets(
         phi[tgt_orig[i]] += acc;
 }
 
+// ---------------------------------------------------------------------------
+// Proxy potentials: for every target cluster B (a slot) and every source
+// batch C approximated with it, phat_B[k] += sum_{j in C} G(t_k, y_j) q_j at
+// B's Chebyshev points t_k = (t_1k1, t_2k2, t_3k3).  The grid is a tensor
+// product, so r^2 = (t_1k1 - y_1)^2 + [(t_2k2 - y_2)^2 + (t_3k3 - y_3)^2]:
+// a lane owns one (k2, k3) and three consecutive k1 and forms the bracket
+// once for its three terms.  Sources are wave-uniform (scalar loads).  The
+// pair is approximated, so r >= R - r_B - r_C > 0 (no zero-distance case).
+//
+// A slot's list is cut into pieces of at most a few thousand sources (runs of
+// whole list entries; d.chunk_* on the host side), one wave per (piece, part):
+// part w holds lane items 64 w .. 64 w + 63 of the slot's G (n+1)^2 items,
+// G = ceil((n+1)/3), item l = (g (n+1) + k2) (n+1) + k3 with k1 = 3 g + u,
+// u < 3.  A piece writes its sums to row piece_row of `out`: the slot itself
+// when it is the slot's only piece, else a partial row that the upward
+// pass's reduction adds up in piece order.  Workgroup b runs on die b mod 8;
+// all parts of a piece take the same die (they read the same sources).
+//
+// FP32-mixed: points and sources relative to the source batch's center, FP32
+// terms summed in FP32 for at most kProxyFlush sources, then in FP64; a batch
+// whose bounding sphere comes closer to B's than the close-pair cut-off of
+// the mixed near field (tau) takes FP64 terms instead.
+// ---------------------------------------------------------------------------
+constexpr int kProxyK1 = 3;
+constexpr int kProxyFlush = 128;
+
+template <int N>
+constexpr int proxy_parts()
+{
+    return (((N + 1 + kProxyK1 - 1) / kProxyK1) * (N + 1) * (N + 1) + 63) / 64;
+}
+
+template <int N, int KER, bool MIXED>
+__global__ __launch_bounds__(64) void proxy_potentials(
+    int64_t npieces, const int32_t* __restrict__ piece_slot,
+    const int64_t* __restrict__ piece_entry, const int64_t* __restrict__ piece_entries,
+    const int64_t* __restrict__ piece_row, const double* __restrict__ slot_nodes,
+    const double4* __restrict__ src, const float4* __restrict__ src32,
+    const double4* __restrict__ node_info, const double4* __restrict__ batch_info,
+    const int64_t* __restrict__ near_begin, const int64_t* __restrict__ near_count,
+    const int32_t* __restrict__ near_leaf, double* __restrict__ out, KernelConst kc)
+{
+    constexpr int NP = N + 1;
+    constexpr int NP2 = NP * NP;
+    constexpr int P = NP2 * NP;
+    constexpr int G = (NP + kProxyK1 - 1) / kProxyK1;
+    constexpr int parts = proxy_parts<N>();
+    __shared__ double exp_tab[64];
+    if constexpr (KER == 1)
+        fill_exp2_table(exp_tab);
+    const KernelArg ka{kc.kappa, kc.delta2, exp_tab};
+    const KernelArg32 nk = kernel_arg32(kc.kappa, kc.delta2);
+
+    const int64_t b = blockIdx.x;
+    const int64_t kd = b >> 3;
+    const int64_t piece = (kd / parts) * 8 + (b & 7);
+    if (piece >= npieces)
+        return;
+    const int64_t slot = piece_slot[piece];
+    const int lane = threadIdx.x;
+    const int item = static_cast<int>(kd % parts) * 64 + lane;
+    const bool live = item < G * NP2;
+    const int it = live ? item : 0;
+    const int g = it / NP2;
+    const int k2 = (it - g * NP2) / NP;
+    const int k3 = it - g * NP2 - k2 * NP;
+    const double* __restrict__ nd = slot_nodes + slot * 3 * NP;
+    double t1[kProxyK1];
+#pragma unroll
+    for (int u = 0; u < kProxyK1; ++u)
+        t1[u] = nd[kProxyK1 * g + u < NP ? kProxyK1 * g + u : NP - 1];
+    const double t2 = nd[NP + k2], t3 = nd[2 * NP + k3];
+
+    double acc[kProxyK1];
+#pragma unroll
+    for (int u = 0; u < kProxyK1; ++u)
+        acc[u] = 0.0;
+    const double4 bi = MIXED ? batch_info[slot] : double4{0.0, 0.0, 0.0, 0.0};
+    const int64_t e_end = piece_entry[piece] + piece_entries[piece];
+    for (int64_t e = piece_entry[piece]; e < e_end; ++e) {
+        const int64_t jb = near_begin[e];
+        const int32_t nc = static_cast<int32_t>(near_count[e]);
+        bool fast = false;
+        double4 li = double4{0.0, 0.0, 0.0, 0.0};
+        if constexpr (MIXED) {
+            li = node_info[near_leaf[e]];
+            const double dx = bi.x - li.x, dy = bi.y - li.y, dz = bi.z - li.z;
+            const double dist = sqrt(dx * dx + dy * dy + dz * dz);
+            const double tau = kMixedTauRel * (dist + bi.w + 2.0 * li.w);
+            fast = dist - bi.w - li.w > 1.0625 * tau;
+        }
+        if (fast) {
+            float l1[kProxyK1];
+#pragma unroll
+            for (int u = 0; u < kProxyK1; ++u)
+                l1[u] = static_cast<float>(t1[u] - li.x);
+            const float l2 = static_cast<float>(t2 - li.y), l3 = static_cast<float>(t3 - li.z);
+            const float4* __restrict__ S = src32 + jb;
+            for (int j0 = 0; j0 < nc; j0 += kProxyFlush) {
+                const int j1 = nc - j0 < kProxyFlush ? nc : j0 + kProxyFlush;
+                float ra[kProxyK1];
+#pragma unroll
+                for (int u = 0; u < kProxyK1; ++u)
+                    ra[u] = 0.0f;
+#pragma unroll 2
+                for (int j = j0; j < j1; ++j) {
+                    const float4 p = S[j];
+                    const float d2 = l2 - p.y, d3 = l3 - p.z;
+                    const float bc = __fmaf_rn(d2, d2, d3 * d3);
+#pragma unroll
+                    for (int u = 0; u < kProxyK1; ++u) {
+                        const float d1 = l1[u] - p.x;
+                        ra[u] = __fmaf_rn(green_f32<KER>(__fmaf_rn(d1, d1, bc), nk), p.w, ra[u]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kProxyK1; ++u)
+                    acc[u] += static_cast<double>(ra[u]);
+            }
+        } else {
+            const double4* __restrict__ S = src + jb;
+#pragma unroll 2
+            for (int j = 0; j < nc; ++j) {
+                const double4 p = S[j];
+                const double d2 = t2 - p.y, d3 = t3 - p.z;
+                const double bc = __fma_rn(d2, d2, d3 * d3);
+#pragma unroll
+                for (int u = 0; u < kProxyK1; ++u) {
+                    const double d1 = t1[u] - p.x;
+                    acc[u] = __fma_rn(green_far_f64<KER>(__fma_rn(d1, d1, bc), ka), p.w, acc[u]);
+                }
+            }
+        }
+    }
+    if (live) {
+        double* __restrict__ dst = out + piece_row[piece] * P + k2 * NP + k3;
+#pragma unroll
+        for (int u = 0; u < kProxyK1; ++u)
+            if (kProxyK1 * g + u < NP)
+                dst[(kProxyK1 * g + u) * NP2] = acc[u];
+    }
+}
+
+template <int N, int KER>
+hipError_t run_proxy(const DevicePlan& d, const double* slot_nodes, bool mixed, double* out,
+                     KernelConst kc, hipStream_t s)
+{
+    const int64_t blocks = ((d.nchunks + 7) / 8) * 8 * proxy_parts<N>();
+    if (mixed)
+        hipLaunchKernelGGL((proxy_potentials<N, KER, true>), dim3(static_cast<unsigned>(blocks)),
+                           dim3(64), 0, s, d.nchunks, d.chunk_slot, d.chunk_begin, d.chunk_count,
+                           d.chunk_dst, slot_nodes, d.src, d.src32, d.node_info, d.batch_info,
+                           d.near_begin, d.near_count, d.near_leaf, out, kc);
+    else
+        hipLaunchKernelGGL((proxy_potentials<N, KER, false>), dim3(static_cast<unsigned>(blocks)),
+                           dim3(64), 0, s, d.nchunks, d.chunk_slot, d.chunk_begin, d.chunk_count,
+                           d.chunk_dst, slot_nodes, d.src, d.src32, d.node_info, d.batch_info,
+                           d.near_begin, d.near_count, d.near_leaf, out, kc);
+    return hipGetLastError();
+}
+
 #define BLTC_DEGREE_CASES(X) \
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
 }  // namespace
+
+hipError_t launch_proxy_potentials(const DevicePlan& d, const double* slot_nodes,
+                                   const KernelParams& kp, double* out, hipStream_t s)
+{
+    if (d.nchunks == 0)
+        return hipSuccess;
+    const bool mixed = kp.precision == 1;
+    if (mixed && (!d.src32 || !d.node_info || !d.batch_info))
+        return hipErrorInvalidValue;
+    const KernelConst kc = kp.kconst();
+    hipError_t e = hipErrorInvalidValue;
+    switch (d.degree) {
+#define X(n)                                                                        \
+    case n:                                                                         \
+        e = kp.kernel == 1 ? run_proxy<n, 1>(d, slot_nodes, mixed, out, kc, s)      \
+          : kp.kernel == 2 ? run_proxy<n, 2>(d, slot_nodes, mixed, out, kc, s)      \
+                           : run_proxy<n, 0>(d, slot_nodes, mixed, out, kc, s);     \
+        break;
+        BLTC_DEGREE_CASES(X)
+#undef X
+    default:
+        return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess || d.nchunks == d.nslots)
+        return e;
+    // slots of several pieces: partial rows summed in piece order
+    return launch_upward_reduce(d, 1, out, nullptr, s);
+}
 
 hipError_t launch_interpolate_targets(const DevicePlan& d, const int32_t* path_off,
                                       const int32_t* path_slot, const double* slot_nodes,

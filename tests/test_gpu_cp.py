@@ -85,6 +85,46 @@ def test_cp_proxy_potentials_match_oracle(dev):
     assert checked > 10
 
 
+# (kernel, parameter, precision, theta, degree): every proxy-potential kernel
+# variant -- FP64 for the three kernels, FP32-mixed, and FP32-mixed at theta
+# 0.95, where source batches closer than the close-pair cut-off take FP64
+# terms; degree 13 has a last group of k1 with two of three points
+PROXY_CASES = [("coulomb", 0.0, "fp64", 0.7, 5), ("yukawa", 0.5, "fp64", 0.7, 8),
+               ("regularized", 0.01, "fp64", 0.7, 13), ("coulomb", 0.0, "fp32_mixed", 0.7, 8),
+               ("yukawa", 0.5, "fp32_mixed", 0.7, 4), ("coulomb", 0.0, "fp32_mixed", 0.95, 5)]
+
+
+@pytest.mark.parametrize("kernel,kappa,precision,theta,degree", PROXY_CASES)
+def test_cp_proxy_potentials_every_variant(dev, kernel, kappa, precision, theta, degree):
+    pos, q = inputs.uniform_cube(30000, 87 + degree)
+    leaf = max(300, (degree + 1) ** 3 + 1)
+    kk, kern, kpar = kernel_kwargs(kernel, kappa)
+    plan, phi = _run(dev, pos, pos, q[0], theta=theta, degree=degree, leaf_size=leaf,
+                     batch_size=leaf, precision=precision, **kk)
+    oc = oracle.ClusterParticle(pos, pos, theta, degree, leaf, leaf)
+    v = plan.view()
+    tord = v["target_order"]
+    okey = {}
+    for c in range(oc.n_clusters):
+        info = oc.cluster(c)
+        okey[tuple(np.sort(tord[info["begin"]:info["begin"] + info["count"]]))] = c
+    approx = np.unique(v["item_cluster"][v["item_kind"] == 0])
+    assert approx.size > 3
+    for c in approx:
+        key = tuple(np.sort(tord[v["cluster_begin"][c]:v["cluster_begin"][c] + v["cluster_count"][c]]))
+        ref = oc.proxy_potentials(okey[key], q[0], kernel=kern, kappa=kpar).reshape(-1)
+        got = np.asarray(plan.modified_charges(c)).reshape(-1)
+        if precision == "fp64":
+            assert np.max(np.abs(ref - got)) <= 1e-12 * np.max(np.abs(ref)), c
+        else:
+            assert oracle.rel_l2(ref, got) <= 1e-5, c
+    ref = oc.potential(q[0], kernel=kern, kappa=kpar)
+    if precision == "fp64":
+        _close(ref, phi)
+    else:
+        assert oracle.rel_l2(ref, phi) <= MIXED_L2
+
+
 @pytest.mark.parametrize("degree,n,leaf", [(1, 12000, 64), (2, 12000, 64), (7, 12000, 256),
                                            (12, 60000, 2500), (16, 60000, 2500)])
 def test_cp_fp64_degrees(dev, degree, n, leaf):
