@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kGroupSize) void interpolate_targets(
 // the mixed near field (tau) takes FP64 terms instead.
 // ---------------------------------------------------------------------------
 constexpr int kProxyK1 = 3;
-constexpr int kProxyFlush = 128;
+constexpr int kProxyFlush = 32;
 
 template <int N>
 constexpr int proxy_parts()
