@@ -31,6 +31,50 @@ namespace bltc_cp {
 constexpr int64_t kProxyPieceSources = 8192;
 constexpr int64_t kProxyPieces = 16384;
 
+int upload_pieces(bltc_plan* plan, bltc::DevicePlan& d, const std::vector<int32_t>& off,
+                  const std::vector<int64_t>& count, int64_t* rows, hipStream_t s)
+{
+    const int64_t nslots = static_cast<int64_t>(off.size()) - 1;
+    int64_t listed = 0;
+    for (const int64_t c : count)
+        listed += c;
+    const int64_t piece = std::max(kProxyPieceSources, (listed + kProxyPieces - 1) / kProxyPieces);
+    std::vector<int32_t> piece_slot, slot_piece_off(nslots + 1, 0);
+    std::vector<int64_t> piece_entry, piece_entries, piece_row;
+    int64_t nrows = nslots;
+    for (int64_t sl = 0; sl < nslots; ++sl) {
+        const size_t first = piece_slot.size();
+        int32_t e0 = off[sl];
+        int64_t run = 0;
+        for (int32_t e = off[sl]; e < off[sl + 1]; ++e) {
+            if (run > 0 && run + count[e] > piece) {
+                piece_slot.push_back(static_cast<int32_t>(sl));
+                piece_entry.push_back(e0);
+                piece_entries.push_back(e - e0);
+                e0 = e;
+                run = 0;
+            }
+            run += count[e];
+        }
+        piece_slot.push_back(static_cast<int32_t>(sl));
+        piece_entry.push_back(e0);
+        piece_entries.push_back(off[sl + 1] - e0);
+        const size_t np_sl = piece_slot.size() - first;
+        for (size_t k = 0; k < np_sl; ++k)
+            piece_row.push_back(np_sl == 1 ? sl : nrows++);
+        slot_piece_off[sl + 1] = static_cast<int32_t>(piece_slot.size());
+    }
+    d.nslots = nslots;
+    d.nchunks = static_cast<int64_t>(piece_slot.size());
+    HIP_TRY(plan->put(&d.chunk_slot, piece_slot, s));
+    HIP_TRY(plan->put(&d.chunk_begin, piece_entry, s));
+    HIP_TRY(plan->put(&d.chunk_count, piece_entries, s));
+    HIP_TRY(plan->put(&d.chunk_dst, piece_row, s));
+    HIP_TRY(plan->put(&d.slot_chunk_off, slot_piece_off, s));
+    *rows = nrows;
+    return BLTC_OK;
+}
+
 int create_host(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const double* tx,
                 const double* ty, const double* tz, int64_t ns, const double* sx, const double* sy,
                 const double* sz)
@@ -170,53 +214,16 @@ int upload(bltc_plan* plan, hipStream_t s)
     const std::vector<int32_t> far_off_d(ntl + 1, 0), one_i(1, 0);
     const std::vector<double> one_d(1, 0.0);
 
-    // each slot's list cut into pieces of whole entries and at most
-    // `piece` sources (one entry may exceed it), so that the heaviest clusters
-    // do not set the run time; a slot's only piece writes its row, several
-    // pieces write partial rows past nslots
-    int64_t listed = 0;
-    for (const int64_t c : cp.pf_count)
-        listed += c;
-    const int64_t piece = std::max(kProxyPieceSources, (listed + kProxyPieces - 1) / kProxyPieces);
-    std::vector<int32_t> piece_slot, slot_piece_off(nslots + 1, 0);
-    std::vector<int64_t> piece_entry, piece_entries, piece_row;
-    int64_t rows = nslots;
-    for (int64_t sl = 0; sl < nslots; ++sl) {
-        const size_t first = piece_slot.size();
-        int32_t e0 = cp.pf_off[sl];
-        int64_t run = 0;
-        for (int32_t e = cp.pf_off[sl]; e < cp.pf_off[sl + 1]; ++e) {
-            if (run > 0 && run + cp.pf_count[e] > piece) {
-                piece_slot.push_back(static_cast<int32_t>(sl));
-                piece_entry.push_back(e0);
-                piece_entries.push_back(e - e0);
-                e0 = e;
-                run = 0;
-            }
-            run += cp.pf_count[e];
-        }
-        piece_slot.push_back(static_cast<int32_t>(sl));
-        piece_entry.push_back(e0);
-        piece_entries.push_back(cp.pf_off[sl + 1] - e0);
-        const size_t np_sl = piece_slot.size() - first;
-        for (size_t k = 0; k < np_sl; ++k)
-            piece_row.push_back(np_sl == 1 ? sl : rows++);
-        slot_piece_off[sl + 1] = static_cast<int32_t>(piece_slot.size());
-    }
-
     px.nt = nslots * P;
-    px.nslots = nslots;
-    px.nchunks = static_cast<int64_t>(piece_slot.size());
     px.nbatches = nslots;
     px.ngroups = 0;
     HIP_TRY(plan->put(&px.near_begin, cp.pf_begin, s));
     HIP_TRY(plan->put(&px.near_count, cp.pf_count, s));
     HIP_TRY(plan->put(&px.near_leaf, cp.pf_leaf, s));
-    HIP_TRY(plan->put(&px.chunk_slot, piece_slot, s));
-    HIP_TRY(plan->put(&px.chunk_begin, piece_entry, s));
-    HIP_TRY(plan->put(&px.chunk_count, piece_entries, s));
-    HIP_TRY(plan->put(&px.chunk_dst, piece_row, s));
-    HIP_TRY(plan->put(&px.slot_chunk_off, slot_piece_off, s));
+    int64_t rows = 0;
+    int rc = upload_pieces(plan, px, cp.pf_off, cp.pf_count, &rows, s);
+    if (rc != BLTC_OK)
+        return rc;
     HIP_TRY(plan->put(&px.slot_nodes, one_d, s));
     HIP_TRY(plan->put(&px.qhat, one_d, s));
 
@@ -325,6 +332,10 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStr
     HIP_TRY(bltc::launch_gather_charges(plan->dprox, q, s));
     HIP_TRY(mark(1));
     HIP_TRY(bltc::launch_proxy_potentials(plan->dprox, plan->cp_slot_nodes, kp, plan->cp_phat, s));
+    if (plan->dprox.nchunks != plan->dprox.nslots) {
+        // clusters of several pieces: partial rows summed in piece order
+        HIP_TRY(bltc::launch_upward_reduce(plan->dprox, 1, plan->cp_phat, nullptr, s));
+    }
     HIP_TRY(mark(2));
     HIP_TRY(bltc::launch_near_pairs(plan->ddir, kp, s));
     if (mixed)

@@ -157,6 +157,16 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStr
 int proxy_potentials(bltc_plan* plan, int64_t cluster, double* out, hipStream_t s);
 void stats(const bltc_plan* plan, bltc_stats* out);
 int view(const bltc_plan* plan, bltc_plan_view* out);
+// Pieces of the proxy-potential lists off/count (one list per slot, entries
+// = source ranges): runs of whole entries of one slot with at most
+// max(8192, listed / 16384) sources, so that the heaviest clusters do not set
+// the run time of launch_proxy_potentials.  A slot's only piece writes the
+// slot's row, several pieces write partial rows past the slots (summed by
+// launch_upward_reduce).  Uploads d.chunk_slot / chunk_begin (first entry) /
+// chunk_count (entries) / chunk_dst (row) / slot_chunk_off, sets d.nchunks
+// and d.nslots, and returns the number of rows in *rows.
+int upload_pieces(bltc_plan* plan, bltc::DevicePlan& d, const std::vector<int32_t>& off,
+                  const std::vector<int64_t>& count, int64_t* rows, hipStream_t s);
 }  // namespace bltc_cp
 
 // cluster-cluster plans (cc.cpp)

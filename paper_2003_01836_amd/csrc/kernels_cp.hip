@@ -113,9 +113,8 @@ __global__ __launch_bounds__(kGroupSize) void interpolate_targets(
 // whole list entries; d.chunk_* on the host side), one wave per (piece, part):
 // part w holds lane items 64 w .. 64 w + 63 of the slot's G (n+1)^2 items,
 // G = ceil((n+1)/3), item l = (g (n+1) + k2) (n+1) + k3 with k1 = 3 g + u,
-// u < 3.  A piece writes its sums to row piece_row of `out`: the slot itself
-// when it is the slot's only piece, else a partial row that the upward
-// pass's reduction adds up in piece order.  Workgroup b runs on die b mod 8;
+// u < 3.  A piece writes its sums to row piece_row of `out` (the caller adds
+// up the rows of a slot in piece order).  Workgroup b runs on die b mod 8;
 // all parts of a piece take the same die (they read the same sources).
 //
 // FP32-mixed: points and sources relative to the source batch's center, FP32
@@ -288,10 +287,7 @@ hipError_t launch_proxy_potentials(const DevicePlan& d, const double* slot_nodes
     default:
         return hipErrorInvalidValue;
     }
-    if (e != hipSuccess || d.nchunks == d.nslots)
-        return e;
-    // slots of several pieces: partial rows summed in piece order
-    return launch_upward_reduce(d, 1, out, nullptr, s);
+    return e;
 }
 
 hipError_t launch_interpolate_targets(const DevicePlan& d, const int32_t* path_off,

@@ -14,12 +14,12 @@ hipError_t launch_interpolate_targets(const DevicePlan& d, const int32_t* path_o
                                       const int32_t* path_slot, const double* slot_nodes,
                                       const double* phat, double* phi, hipStream_t s);
 
-// out[slot][k] = sum over the sources of the source batches listed for the
-// slot (d.near_*) of G(t_k, y_j) q_j at the slot's Chebyshev points t_k
-// (grids slot_nodes[slot][3][n+1]), FP64 or FP32-mixed as kp.precision.  The
-// lists are cut into pieces d.chunk_slot/chunk_begin (first entry)/
-// chunk_count (entries)/chunk_dst (output row); rows past d.nslots of `out`
-// hold partial sums, added up per slot by slot_chunk_off (kernels_cp.hip)
+// Proxy potentials over the pieces of the slots' lists (d.chunk_slot, first
+// entry d.chunk_begin, entries d.chunk_count, output row d.chunk_dst; entries
+// d.near_begin/near_count/near_leaf): row r of `out` = sum over the piece's
+// sources of G(t_k, y_j) q_j at its slot's Chebyshev points t_k (grids
+// slot_nodes[slot][3][n+1]), FP64 or FP32-mixed as kp.precision; the caller
+// sums the rows of a slot of several pieces (kernels_cp.hip)
 hipError_t launch_proxy_potentials(const DevicePlan& d, const double* slot_nodes,
                                    const KernelParams& kp, double* out, hipStream_t s);
 
