@@ -42,7 +42,7 @@ FLOPS_HERMITE_POINT = 37
 FLOPS_MUTUAL_PAIR = 13
 
 KERNEL_SOURCES = {
-    "interact_mixed": ["kernels_mixed.hip", "device_common.hpp", "kernels.hpp"],
+    "interact_mixed": ["kernels_mixed.hip", "device_mixed.hpp", "device_common.hpp", "kernels.hpp"],
     "interact_f64": ["kernels.hip", "device_common.hpp", "kernels.hpp"],
     "near_pairs_mixed": ["kernels_sym.hip", "device_common.hpp", "kernels.hpp"],
     "near_pairs_f64": ["kernels_sym.hip", "device_common.hpp", "kernels.hpp"],
@@ -356,9 +356,9 @@ def run_variant(args, dev):
 
 
 def run_hermite(args, dev):
-    """Barycentric Hermite treecode (FP64) on the headline geometry: 10^6 uniform,
-    Coulomb, theta 0.7, N_L = N_B = 2000, degrees 2..4 (8 (n+1)^3 <= 1000 modified
-    charges per cluster, against 729 for the BLTC at n = 8)."""
+    """Barycentric Hermite treecode (FP64 and FP32-mixed) on the headline geometry:
+    10^6 uniform, Coulomb, theta 0.7, N_L = N_B = 2000, degrees 2..4 (8 (n+1)^3 <= 1000
+    modified charges per cluster, against 729 for the BLTC at n = 8)."""
     import numpy as np
     import torch
 
@@ -374,60 +374,65 @@ def run_hermite(args, dev):
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     smp = inputs.sample_indices(n, w["samples"], inputs.sample_seed(w["cfg"]))
     res = {"workload": f"hermite uniform-1M: N={n}, coulomb, theta={w['theta']}, "
-                       f"N_L=N_B={w['leaf']}, fp64", "degrees": {}}
+                       f"N_L=N_B={w['leaf']}", "degrees": {}}
     got = {}
     for deg in args.hermite_degrees:
-        t0 = time.perf_counter()
-        plan = bltc.Plan(t, t, method="hermite", theta=w["theta"], degree=deg,
-                         leaf_size=w["leaf"], batch_size=w["batch"])
-        t_plan = time.perf_counter() - t0
-        st = plan.stats()
-        for _ in range(args.warmup):
-            plan.execute(qd, out=phi)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            plan.execute(qd, out=phi)
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / args.steps
-        plan.set_timing(True)
-        ph = {"gather": 0.0, "upward": 0.0, "interact": 0.0, "total": 0.0, "mutual_pairs": 0.0}
-        for _ in range(args.steps):
-            plan.execute(qd, out=phi)
-            for k, v in plan.phase_times().items():
-                ph[k] += v / args.steps
-        plan.set_timing(False)
-        got[deg] = phi.cpu().numpy()
-        points = st["far_evals"] // 8      # far_evals counts 8 values per grid point
-        mutual = st["mutual_pair_evals"]   # direct kernel values serving two terms
-        flops = (points * FLOPS_HERMITE_POINT + (st["near_evals"] - 2 * mutual) * FLOPS_COULOMB +
-                 mutual * FLOPS_MUTUAL_PAIR)
-        ach = flops / (ph["interact"] * 1e-3) / 1e12
-        res["degrees"][deg] = {
-            "ms_per_step": ms, "targets_per_s": n / (ms * 1e-3), "plan_s": t_plan,
-            "phases_ms": ph, "grid_point_evals": points, "near_evals": st["near_evals"],
-            "mutual_pair_evals": mutual,
-            "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"],
-            "roofline": {"bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
-                         "traffic": None,
-                         "kernel": f"interaction phase: interact_hermite_f64<{deg}, 0> + "
-                                   f"near_pairs_f64<0>",
-                         "flops_per_grid_point": FLOPS_HERMITE_POINT,
-                         "flops_per_near_eval": FLOPS_COULOMB}}
-        log(f"hermite n={deg}: {ms:.2f} ms/step, phases {ph}")
-        del plan
+        res["degrees"][deg] = {}
+        for prec in ("fp64", "fp32_mixed"):
+            t0 = time.perf_counter()
+            plan = bltc.Plan(t, t, method="hermite", theta=w["theta"], degree=deg,
+                             leaf_size=w["leaf"], batch_size=w["batch"], precision=prec)
+            t_plan = time.perf_counter() - t0
+            st = plan.stats()
+            for _ in range(args.warmup):
+                plan.execute(qd, out=phi)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                plan.execute(qd, out=phi)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / args.steps
+            plan.set_timing(True)
+            ph = {"gather": 0.0, "upward": 0.0, "interact": 0.0, "total": 0.0, "mutual_pairs": 0.0}
+            for _ in range(args.steps):
+                plan.execute(qd, out=phi)
+                for k, v in plan.phase_times().items():
+                    ph[k] += v / args.steps
+            plan.set_timing(False)
+            got[(deg, prec)] = phi.cpu().numpy()
+            points = st["far_evals"] // 8      # far_evals counts 8 values per grid point
+            mutual = st["mutual_pair_evals"]   # direct kernel values serving two terms
+            flops = (points * FLOPS_HERMITE_POINT + (st["near_evals"] - 2 * mutual) * FLOPS_COULOMB +
+                     mutual * FLOPS_MUTUAL_PAIR)
+            ach = flops / (ph["interact"] * 1e-3) / 1e12
+            peak = FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+            kern = "f64" if prec == "fp64" else "mixed"
+            res["degrees"][deg][prec] = {
+                "ms_per_step": ms, "targets_per_s": n / (ms * 1e-3), "plan_s": t_plan,
+                "phases_ms": ph, "grid_point_evals": points, "near_evals": st["near_evals"],
+                "mutual_pair_evals": mutual,
+                "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"],
+                "roofline": {"bound": "alu", "achieved": ach, "peak": peak,
+                             "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                             "kernel": f"interaction phase: interact_hermite_{kern}<{deg}, 0> + "
+                                       f"near_pairs_{kern}<0>",
+                             "flops_per_grid_point": FLOPS_HERMITE_POINT,
+                             "flops_per_near_eval": FLOPS_COULOMB}}
+            log(f"hermite n={deg} {prec}: {ms:.2f} ms/step, phases {ph}")
+            del plan
     if not args.no_cpu:
         import oracle
         ds = oracle.direct(pos[smp], pos, q[0])
-        for deg, v in got.items():
+        for deg in args.hermite_degrees:
             oc = oracle.Treecode(pos, pos, w["theta"], deg, w["leaf"], w["batch"], hermite=True)
             ref, times = oc.potential(q[0], sample=smp, return_times=True)
-            res["degrees"][deg]["E_par"] = rel_l2(ref, v[smp])
-            res["degrees"][deg]["E_tc"] = rel_l2(ds, v[smp])
+            for prec in ("fp64", "fp32_mixed"):
+                v = got[(deg, prec)]
+                r = res["degrees"][deg][prec]
+                r["E_par"] = rel_l2(ref, v[smp])
+                r["E_tc"] = rel_l2(ds, v[smp])
+                log(f"hermite n={deg} {prec}: E_par {r['E_par']:.2e} E_tc {r['E_tc']:.2e}")
             res["degrees"][deg]["oracle_s"] = times
-            log(f"hermite n={deg}: E_par {res['degrees'][deg]['E_par']:.2e} "
-                f"E_tc {res['degrees'][deg]['E_tc']:.2e}")
     return res
 
 

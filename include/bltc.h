@@ -103,8 +103,11 @@ typedef enum { BLTC_FP64 = 0, BLTC_FP32_MIXED = 1 } bltc_precision;
  *                         and derivative multi-index a in {0,1}^3, and the
  *                         approximation sums d^a_y G(x, s_k) times them; the
  *                         size part of the MAC compares 8 (n+1)^3 with N_C.
- *                         BLTC_FP64 only, degree 1..10, one charge vector per
- *                         execution; not usable in a bltc_batch. */
+ *                         BLTC_FP64 or BLTC_FP32_MIXED (the far-field terms in
+ *                         FP32 from FP64-formed 1-D distances and FP32 copies
+ *                         of the charges, direct sums as for the BLTC), degree
+ *                         1..10, one charge vector per execution; not usable
+ *                         in a bltc_batch. */
 typedef enum {
     BLTC_PARTICLE_CLUSTER = 0,
     BLTC_CLUSTER_PARTICLE = 1,

@@ -51,8 +51,6 @@ int check_params(const bltc_params* p)
         p->method != BLTC_CLUSTER_CLUSTER && p->method != BLTC_HERMITE)
         return fail(BLTC_EINVAL, "method must be BLTC_PARTICLE_CLUSTER, BLTC_CLUSTER_PARTICLE, "
                                  "BLTC_CLUSTER_CLUSTER or BLTC_HERMITE");
-    if (p->method == BLTC_HERMITE && p->precision != BLTC_FP64)
-        return fail(BLTC_EUNSUPPORTED, "the Hermite treecode runs in BLTC_FP64 only");
     if (p->method == BLTC_HERMITE && p->degree > bltc::kMaxHermiteDegree)
         return fail(BLTC_EUNSUPPORTED, "the Hermite treecode takes degree 1..%d",
                     bltc::kMaxHermiteDegree);

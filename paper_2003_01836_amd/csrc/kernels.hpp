@@ -71,7 +71,7 @@ struct DevicePlan {
     int32_t* slot_chunk_off = nullptr;
     int64_t* chunk_dst = nullptr;     // output row of each chunk (slot, or nslots + partial)
     double* qhat = nullptr;           // [slot][P] or [slot][P][16], then partial rows
-    float* qhat32 = nullptr;          // [slot][P] (mixed precision)
+    float* qhat32 = nullptr;          // [slot][P] (mixed precision; Hermite [slot][(n+1)^3][8])
     // several charge vectors at once (16 per pass)
     int32_t* slot_cluster = nullptr;  // cluster id of each slot
     double* qm = nullptr;             // [ns][16] charges in tree order
@@ -176,8 +176,10 @@ hipError_t launch_upward_many(const UpwardDesc* descs, const int2* units, int32_
 hipError_t launch_upward_reduce(const DevicePlan& d, int32_t mw, double* buf, float* qhat32,
                                 hipStream_t s);
 // (with d.hermite the upward pass forms 8 (n+1)^3 charges per slot and the
-// reduction writes them to d.qhat_h, [slot][k][a]; mw must be 1)
-// Hermite approximation and direct sums (kernels_hermite.hip), FP64, n <= 10
+// reduction writes them to d.qhat_h, [slot][k][a], and their FP32 copy to
+// qhat32 when given; mw must be 1)
+// Hermite approximation and direct sums (kernels_hermite.hip), FP64 or
+// FP32-mixed as kp.precision, n <= 10
 hipError_t launch_interact_hermite(const DevicePlan& d, const KernelParams& kp, double* phi,
                                    hipStream_t s);
 inline NearLists near_lists(const DevicePlan& d)

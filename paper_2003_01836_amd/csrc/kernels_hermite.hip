@@ -14,8 +14,10 @@
 // 256 targets of one batch per workgroup, wave-uniform lists, grid nodes and
 // charges through the scalar cache (the eight charges of a grid point are
 // contiguous: one 64-byte load), phi written once per target in caller order.
+// An FP32-mixed form follows the FP64 kernel.
 #include "kernels.hpp"
 #include "device_common.hpp"
+#include "device_mixed.hpp"
 
 namespace bltc {
 namespace {
@@ -157,6 +159,164 @@ __global__ __launch_bounds__(kGroupSize) void interact_hermite_f64(
         phi[tgt_orig[i]] = acc;
 }
 
+// ---------------------------------------------------------------------------
+// FP32-mixed form.  With u = r^2 (u = r^2 + delta^2 for the regularized
+// kernel), ri = u^(-1/2) and the direction cosines f = d ri (|f_i| <= 1),
+// the term of one grid point is
+//     G [ Q_0 + ri (p1 S1 + ri (p2 S2 + ri p3 S3)) ]
+// with S1 = f1 Q_4 + f2 Q_2 + f3 Q_1, S2 = f1 f2 Q_6 + f3 (f1 Q_5 + f2 Q_3),
+// S3 = f1 f2 f3 Q_7 and p1, p2, p3 = 1, 3, 15 (Coulomb forms) or
+// 1 + kr, 3 + 3 kr + (kr)^2, 15 + 15 kr + 6 (kr)^2 + (kr)^3 (Yukawa, k = kappa):
+// the same sum as above, ordered so that no intermediate grows like a power
+// of 1/r beyond the first (FP32 range).  Squared 1-D distances are formed in
+// FP64 and rounded once per target and cluster; FP32 partial sums cover
+// (n+1)^2 grid points; direct sums as in the FP32-mixed BLTC.
+// ---------------------------------------------------------------------------
+// one grid point: r2 = |d|^2, d = x - s_k in FP32, Q its eight charges
+template <int KER>
+__device__ __forceinline__ float hermite_term_f32(float r2, float d1, float d2, float d3,
+                                                  const float* __restrict__ Q,
+                                                  const KernelArg32& nk, float kf)
+{
+    const float u = KER == 2 ? r2 + nk.delta2 : r2;
+    const float ri = __builtin_amdgcn_rsqf(u);
+    const float e1 = d1 * ri, e2 = d2 * ri, e3 = d3 * ri;   // direction cosines f
+    const float S1 = __fmaf_rn(e1, Q[4], __fmaf_rn(e2, Q[2], e3 * Q[1]));
+    const float e12 = e1 * e2;
+    const float S2 = __fmaf_rn(e12, Q[6], e3 * __fmaf_rn(e1, Q[5], e2 * Q[3]));
+    const float S3 = e12 * e3 * Q[7];
+    if constexpr (KER == 1) {
+        const float r = u * ri;
+        const float kr = kf * r;
+        const float g = __builtin_amdgcn_exp2f(nk.nk * r) * ri;
+        const float p1 = 1.0f + kr;
+        const float p2 = __fmaf_rn(kr, kr + 3.0f, 3.0f);
+        const float p3 = __fmaf_rn(kr, __fmaf_rn(kr, kr + 6.0f, 15.0f), 15.0f);
+        const float h = __fmaf_rn(ri, __fmaf_rn(p2, S2, ri * (p3 * S3)), p1 * S1);
+        return g * __fmaf_rn(ri, h, Q[0]);
+    } else {
+        const float h = __fmaf_rn(ri, __fmaf_rn(3.0f, S2, ri * (15.0f * S3)), S1);
+        return ri * __fmaf_rn(ri, h, Q[0]);
+    }
+}
+
+// sum over the (n+1)^3 grid of one cluster in FP32-mixed; qh = [(n+1)^3][8] FP32
+template <int N, int KER>
+__device__ __forceinline__ double far_sum_hermite_f32(double x, double y, double z,
+                                                      const double* __restrict__ nd,
+                                                      const float* __restrict__ qh,
+                                                      const KernelArg32& nk, float kf)
+{
+    constexpr int NP = N + 1;
+    float e2[NP], e3[NP], b2[NP], c2[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        e2[k] = static_cast<float>(y - nd[NP + k]);
+        e3[k] = static_cast<float>(z - nd[2 * NP + k]);
+        b2[k] = e2[k] * e2[k];
+        c2[k] = e3[k] * e3[k];
+    }
+    double acc = 0.0;
+#pragma unroll 1
+    for (int k1 = 0; k1 < NP; ++k1) {
+        const float d1 = static_cast<float>(x - nd[k1]);
+        const float a2 = d1 * d1;
+        const float* __restrict__ q1 = qh + k1 * NP * NP * 8;
+        float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+        for (int k2 = 0; k2 < NP; ++k2) {
+            const float ab = a2 + b2[k2];
+#pragma unroll
+            for (int k3 = 0; k3 < NP; ++k3) {
+                const float t = hermite_term_f32<KER>(ab + c2[k3], d1, e2[k2], e3[k3],
+                                                      q1 + (k2 * NP + k3) * 8, nk, kf);
+                if ((k2 + k3) & 1)
+                    s1 += t;
+                else
+                    s0 += t;
+            }
+        }
+        acc += static_cast<double>(s0 + s1);
+    }
+    return acc;
+}
+
+template <int N, int KER>
+__global__ __launch_bounds__(kGroupSize) void interact_hermite_mixed(
+    const double4* __restrict__ tgt, const int64_t* __restrict__ tgt_orig,
+    const double4* __restrict__ src, const float4* __restrict__ src32,
+    const double4* __restrict__ node_info, const double4* __restrict__ batch_info,
+    const int32_t* __restrict__ group_batch, const int64_t* __restrict__ group_first,
+    const int64_t* __restrict__ batch_end, const int32_t* __restrict__ far_off,
+    const int32_t* __restrict__ far_slot, const int32_t* __restrict__ near_off,
+    const int64_t* __restrict__ near_begin, const int64_t* __restrict__ near_count,
+    const int32_t* __restrict__ near_leaf, const double* __restrict__ slot_nodes,
+    const float* __restrict__ qh32,
+    const int32_t* __restrict__ pc_off, const int64_t* __restrict__ pc_base,
+    const double* __restrict__ pair_out, const int64_t* __restrict__ batch_begin,
+    double* __restrict__ phi, KernelConst kc)
+{
+    constexpr int NP = N + 1;
+    constexpr int P8 = 8 * NP * NP * NP;
+    __shared__ double exp_tab[64];
+    if constexpr (KER == 1)
+        fill_exp2_table(exp_tab);
+    const KernelArg ka{kc.kappa, kc.delta2, exp_tab};
+    const KernelArg32 nk = kernel_arg32(kc.kappa, kc.delta2);
+    const float kf = static_cast<float>(kc.kappa);
+    const int g = blockIdx.x;
+    const int b = group_batch[g];
+    if (b < 0)
+        return;  // empty slot of the per-die schedule
+    const int64_t first = group_first[g];
+    const int64_t end = batch_end[b];
+    if (first + (threadIdx.x & ~63) >= end)
+        return;  // the whole wave lies past the batch end
+    int64_t i = first + threadIdx.x;
+    const bool valid = i < end;
+    if (!valid)
+        i = end - 1;
+    const double4 t = tgt[i];
+    double acc = 0.0;
+    const int f_end = far_off[b + 1];
+    for (int f = far_off[b]; f < f_end; ++f) {
+        const int64_t slot = far_slot[f];
+        acc += far_sum_hermite_f32<N, KER>(t.x, t.y, t.z, slot_nodes + slot * 3 * NP,
+                                           qh32 + slot * P8, nk, kf);
+    }
+    const double4 bi = batch_info[b];
+    const int n_end = near_off[b + 1];
+    for (int e = near_off[b]; e < n_end; ++e) {
+        const int64_t nb = near_begin[e];
+        acc += near_entry_mixed<KER>(t.x, t.y, t.z, bi, node_info[near_leaf[e]], src32 + nb,
+                                     src + nb, static_cast<int32_t>(near_count[e]), nk, ka);
+    }
+    if (pc_off) {
+        // mutual leaf pairs: this target's row or column sums of each unit
+        const int64_t pos = i - batch_begin[b];
+        const int pc_end = pc_off[b + 1];
+        for (int e = pc_off[b]; e < pc_end; ++e)
+            acc += pair_out[pc_base[e] + pos];
+    }
+    if (valid)
+        phi[tgt_orig[i]] = acc;
+}
+
+template <int N, int KER>
+hipError_t run_interact_hermite_mixed(const DevicePlan& d, double* phi, KernelConst kc,
+                                      hipStream_t s)
+{
+    if (d.ngroups == 0)
+        return hipSuccess;
+    const NearLists nl = near_lists(d);
+    hipLaunchKernelGGL((interact_hermite_mixed<N, KER>), dim3(static_cast<unsigned>(d.ngroups)),
+                       dim3(d.group_threads), 0, s, d.tgt, d.tgt_orig, d.src, d.src32,
+                       d.node_info, d.batch_info, d.group_batch, d.group_first, d.batch_end,
+                       d.far_off, d.far_slot, nl.off, nl.begin, nl.count, nl.leaf, d.slot_nodes,
+                       d.qhat32, nl.pc_off, nl.pc_base, nl.pair_out, nl.batch_begin, phi, kc);
+    return hipGetLastError();
+}
+
 template <int N, int KER>
 hipError_t run_interact_hermite(const DevicePlan& d, double* phi, KernelConst kc, hipStream_t s)
 {
@@ -182,6 +342,21 @@ hipError_t launch_interact_hermite(const DevicePlan& d, const KernelParams& kp, 
     if (!d.hermite || !d.qhat_h)
         return hipErrorInvalidValue;
     const KernelConst kc = kp.kconst();
+    if (kp.precision == 1) {
+        if (!d.src32 || !d.node_info || !d.batch_info || !d.qhat32)
+            return hipErrorInvalidValue;
+        switch (d.degree) {
+#define X(n)                                                                         \
+    case n:                                                                          \
+        return kp.kernel == 1 ? run_interact_hermite_mixed<n, 1>(d, phi, kc, s)      \
+             : kp.kernel == 2 ? run_interact_hermite_mixed<n, 2>(d, phi, kc, s)      \
+                              : run_interact_hermite_mixed<n, 0>(d, phi, kc, s);
+            BLTC_HERMITE_DEGREE_CASES(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+        }
+    }
     switch (d.degree) {
 #define X(n)                                                                   \
     case n:                                                                    \

@@ -2,108 +2,20 @@
 //
 // Same mapping as the FP64 kernel (one target per lane, wave-uniform lists and
 // sources through the scalar cache), with the kernel evaluations in FP32:
-//  * direct sums (eq. 9) use local coordinates: sources are stored relative to
-//    the center of their leaf; each lane forms its target's offset from that
-//    center once per batch/leaf pair, in FP64, and rounds it to FP32, so the
-//    FP32 differences carry relative rounding errors of the local extent,
-//    not of the domain;
-//  * pairs with r^2 <= tau^2, tau = kTauRel * (local extent) -- this includes
-//    pairs at zero distance even when the extent is zero (a one-particle batch
-//    against its own one-particle leaf) -- take an FP64 branch (exact
-//    coordinates, FP64 kernel), so the coordinate rounding never exceeds
-//    about 2^-24 / kTauRel (a few 1e-6) of a term, and the aggregate
-//    coordinate error, which is dominated by the closest pairs, scales as
-//    kTauRel^-1/2;
+//  * direct sums (eq. 9): local coordinates and an FP64 branch for close
+//    pairs (device_mixed.hpp);
 //  * approximations (eq. 11) use FP32 squared 1-D distances (formed in FP64,
 //    rounded once per target and pair) and FP32 modified charges;
-//  * FP32 partial sums cover at most kFlushEvery sources or (n+1)^2 proxy
+//  * FP32 partial sums cover at most kMixedFlush sources or (n+1)^2 proxy
 //    points before they are added to the lane's FP64 accumulator.
 #include "device_common.hpp"
+#include "device_mixed.hpp"
 #include "kernels.hpp"
 
 namespace bltc {
 namespace {
 
 using namespace dev;
-
-constexpr double kTauRel = kMixedTauRel;
-constexpr int kFlushEvery = 128;
-
-// FP32 kernel value of one source for a lane's local target coordinates.
-template <int KER>
-__device__ __forceinline__ float near_value_f32(float x, float y, float z, const float4 p,
-                                                const KernelArg32& nk, float& r2)
-{
-    const float dx = x - p.x;
-    const float dy = y - p.y;
-    const float dz = z - p.z;
-    r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-    return green_f32<KER>(r2, nk);
-}
-
-// Sources [j, j+4): FP32 values; if any of them is closer than tau (rare, one
-// branch per 4 sources), those terms are redone in FP64 into `acc` and their
-// FP32 values are zeroed.
-template <int KER, bool CHECK>
-__device__ __forceinline__ void near_quad_mixed(float x, float y, float z,
-                                                const float4* __restrict__ s32,
-                                                const double4* __restrict__ s64, float tau2,
-                                                const KernelArg32& nk, double xt, double yt,
-                                                double zt,
-                                                const KernelArg& kappa, double& acc, float& a0, float& a1,
-                                                float& a2, float& a3)
-{
-    const float4 p0 = s32[0], p1 = s32[1], p2 = s32[2], p3 = s32[3];
-    float r0, r1, r2, r3;
-    float g0 = near_value_f32<KER>(x, y, z, p0, nk, r0);
-    float g1 = near_value_f32<KER>(x, y, z, p1, nk, r1);
-    float g2 = near_value_f32<KER>(x, y, z, p2, nk, r2);
-    float g3 = near_value_f32<KER>(x, y, z, p3, nk, r3);
-    if (CHECK && fminf(fminf(r0, r1), fminf(r2, r3)) <= tau2) {
-        if (r0 <= tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[0], kappa); g0 = 0.0f; }
-        if (r1 <= tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[1], kappa); g1 = 0.0f; }
-        if (r2 <= tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[2], kappa); g2 = 0.0f; }
-        if (r3 <= tau2) { acc += near_term_f64<KER>(xt, yt, zt, s64[3], kappa); g3 = 0.0f; }
-    }
-    a0 = __fmaf_rn(g0, p0.w, a0);
-    a1 = __fmaf_rn(g1, p1.w, a1);
-    a2 = __fmaf_rn(g2, p2.w, a2);
-    a3 = __fmaf_rn(g3, p3.w, a3);
-}
-
-// CHECK = false: the caller has shown that no pair is closer than tau
-template <int KER, bool CHECK>
-__device__ __forceinline__ double near_sum_mixed(double xt, double yt, double zt,
-                                                 const float4* __restrict__ s32,
-                                                 const double4* __restrict__ s64, int32_t cnt,
-                                                 const double4 leaf, float tau2,
-                                                 const KernelArg32& nk,
-                                                 const KernelArg& kappa)
-{
-    const float x = static_cast<float>(xt - leaf.x);
-    const float y = static_cast<float>(yt - leaf.y);
-    const float z = static_cast<float>(zt - leaf.z);
-    double acc = 0.0;
-    for (int32_t j0 = 0; j0 < cnt; j0 += kFlushEvery) {
-        const int32_t j1 = (cnt - j0 < kFlushEvery) ? cnt : j0 + kFlushEvery;
-        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-        int32_t j = j0;
-        for (; j + 4 <= j1; j += 4)
-            near_quad_mixed<KER, CHECK>(x, y, z, s32 + j, s64 + j, tau2, nk, xt, yt, zt, kappa,
-                                        acc, a0, a1, a2, a3);
-        for (; j < j1; ++j) {
-            float r;
-            float g = near_value_f32<KER>(x, y, z, s32[j], nk, r);
-            if (CHECK && r <= tau2) {
-                acc += near_term_f64<KER>(xt, yt, zt, s64[j], kappa);
-                g = 0.0f;
-            }
-            a0 = __fmaf_rn(g, s32[j].w, a0);
-        }
-        acc += static_cast<double>((a0 + a1) + (a2 + a3));
-    }
-    return acc;
-}
 
 template <int N, int KER>
 __device__ __forceinline__ double far_sum_mixed(double xt, double yt, double zt,
@@ -199,7 +111,7 @@ __global__ __launch_bounds__(kGroupSize) __attribute__((amdgpu_waves_per_eu(8, 8
         const double dx = bi.x - li.x, dy = bi.y - li.y, dz = bi.z - li.z;
         const double dist = sqrt(dx * dx + dy * dy + dz * dz);
         const double extent = dist + bi.w + 2.0 * li.w;
-        const double tau = kTauRel * extent;
+        const double tau = kMixedTauRel * extent;
         const float tau2 = static_cast<float>(tau * tau);
         const int64_t nb = near_begin[e];
         const int32_t nc = static_cast<int32_t>(near_count[e]);

@@ -525,14 +525,16 @@ __global__ __launch_bounds__(256) void upward_mfma_reduce(
         qhat32[idx] = static_cast<float>(s);
 }
 
-// Hermite modified charges of every slot, regrouped per grid point:
+// Hermite modified charges of every slot (and their FP32 copy), regrouped per
+// grid point:
 // qh[slot][k][a] (k = (k1 (n+1) + k2) (n+1) + k3, a = 4 a1 + 2 a2 + a3) is the
 // sum over the slot's chunks, in chunk order, of the blocked chunk result
 // buf[row][((a1 np + k1) nf + a2 np + k2) nf + a3 np + k3], nf = 2 np.  The
 // eight values of one grid point are then one 64-byte wave-uniform load.
 __global__ __launch_bounds__(256) void upward_reduce_hermite(
     const int32_t* __restrict__ slot_chunk_off, const int64_t* __restrict__ chunk_dst,
-    const double* __restrict__ buf, double* __restrict__ qh, int64_t nslots, int32_t np)
+    const double* __restrict__ buf, double* __restrict__ qh, float* __restrict__ qh32,
+    int64_t nslots, int32_t np)
 {
     const int64_t P = static_cast<int64_t>(np) * np * np;
     const int64_t per_slot = 8 * P;
@@ -551,6 +553,8 @@ __global__ __launch_bounds__(256) void upward_reduce_hermite(
     for (int32_t c = c0; c < c1; ++c)
         s += buf[chunk_dst[c] * per_slot + kb];
     qh[idx] = s;
+    if (qh32)
+        qh32[idx] = static_cast<float>(s);
 }
 
 }  // namespace
@@ -592,8 +596,8 @@ hipError_t launch_upward_reduce(const DevicePlan& d, int32_t mw, double* buf, fl
         if (mw != 1 || !d.qhat_h)
             return hipErrorInvalidValue;
         hipLaunchKernelGGL(upward_reduce_hermite, dim3(static_cast<unsigned>((total + 255) / 256)),
-                           dim3(256), 0, s, d.slot_chunk_off, d.chunk_dst, buf, d.qhat_h, d.nslots,
-                           d.degree + 1);
+                           dim3(256), 0, s, d.slot_chunk_off, d.chunk_dst, buf, d.qhat_h, qhat32,
+                           d.nslots, d.degree + 1);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(upward_mfma_reduce, dim3(static_cast<unsigned>((total + 255) / 256)),
