@@ -49,19 +49,30 @@ KERNEL_SOURCES = {
 }
 
 
-def counter_traffic(kernel, degree, ker_id):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
-    when there is none for this instantiation or the kernel's sources changed since."""
+# Issue-rate model of the FP32-mixed kernels: SIMD-cycles per wave instruction
+# (64 lanes) measured on the box by a dependency-free probe (8 independent
+# chains per lane) at the nominal clock: FP32 FMA-class instructions, and the
+# transcendental unit (v_rsq_f32, v_exp_f32), whose issue does not overlap.
+CYCLES_FMA32 = 2.86
+CYCLES_TRANS32 = 9.1
+SIMDS = 1024                        # 256 CU x 4 SIMD
+CLOCK_HZ = 2.4e9
+
+
+def counter_value(prefix, profile, kernel, degree, ker_id):
+    """A per-launch value of `kernel` from a committed rocprofv3 summary (lines
+    `<prefix> <kernel instantiation> <value> source <hash>`), or None when there is
+    none for this instantiation or the kernel's sources changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "interact_uniform-1M_counters.md")
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2003_01836_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    want = (f"traffic_bytes {kernel}<{degree}, {ker_id}> " if kernel.startswith("interact")
-            else f"traffic_bytes {kernel}<{ker_id}> ")
+    want = (f"{prefix} {kernel}<{degree}, {ker_id}> " if kernel.startswith("interact")
+            else f"{prefix} {kernel}<{ker_id}> ")
     with open(path) as fh:
         for line in fh:
             if line.startswith(want):
@@ -69,6 +80,27 @@ def counter_traffic(kernel, degree, ker_id):
                 if len(parts) == 3 and parts[1] == "source" and parts[2] == h.hexdigest()[:16]:
                     return float(parts[0])
     return None
+
+
+def counter_traffic(kernel, degree, ker_id):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, calibrated by a plain copy)."""
+    return counter_value("traffic_bytes", "interact_uniform-1M_counters.md", kernel, degree,
+                         ker_id)
+
+
+def issue_model(kernel, degree, ker_id, trans_per_eval, evals, ms):
+    """Shortest time at which the SIMDs could issue the VALU instructions that the
+    kernel issues per launch (SQ_INSTS_VALU of the committed counter summary: one
+    transcendental per kernel value, or two for Yukawa, the rest FMA-class), and its
+    ratio to the measured launch time; None where no counters fit the kernel."""
+    valu = counter_value("valu_insts", "interact_uniform-1M_valu_counters.md", kernel, degree,
+                         ker_id)
+    if valu is None or not kernel.endswith("mixed"):
+        return None
+    trans = trans_per_eval * evals / 64.0
+    cycles = (valu - trans) * CYCLES_FMA32 + trans * CYCLES_TRANS32
+    t_min = cycles / SIMDS / CLOCK_HZ * 1e3
+    return {"valu_insts": valu, "trans_insts": trans, "t_min_ms": t_min, "frac": t_min / ms}
 
 
 def cpu_model():
@@ -625,10 +657,13 @@ def main():
     if mutual:
         kernels[f"near_pairs_{suffix}"] = {"evals": mutual, "flops_per_eval": flops_pair,
                                            "ms_per_launch": t_pairs}
+    trans_per_eval = 2 if w["kernel"] == "yukawa" else 1
     for kn, kv in kernels.items():
         kv["achieved"] = kv["evals"] * kv["flops_per_eval"] / (kv["ms_per_launch"] * 1e-3) / 1e12
         kv["frac"] = kv["achieved"] / peak
         kv["traffic"] = counter_traffic(kn, w["degree"], ker_id)
+        kv["issue"] = issue_model(kn, w["degree"], ker_id, trans_per_eval, kv["evals"],
+                                  kv["ms_per_launch"])
     kname = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])
     kd = kernels[kname]
     phase_flops = sum(v["evals"] * v["flops_per_eval"] for v in kernels.values())
@@ -653,6 +688,7 @@ def main():
                      "frac": kd["frac"], "traffic": kd["traffic"],
                      "kernel": kname, "flops_per_eval": kd["flops_per_eval"],
                      "evals_per_launch": kd["evals"], "ms_per_launch": kd["ms_per_launch"],
+                     "issue": kd["issue"],
                      "interaction_kernels": kernels,
                      "interaction_phase": {"achieved": phase_achieved, "frac": phase_achieved / peak,
                                            "ms": r["phases"]["interact"]}},

@@ -29,3 +29,29 @@ def test_counter_traffic_is_null_for_changed_or_missing_kernels(tmp_path, monkey
         (csrc / f).write_text("x")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.counter_traffic("interact_mixed", 8, 0) is None
+
+
+def test_issue_model_from_the_committed_counters(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    # FP64 kernels and uncounted instantiations have no model
+    assert bench.issue_model("interact_f64", 8, 0, 1, 10 ** 9, 1.0) is None
+    assert bench.issue_model("interact_mixed", 3, 1, 2, 10 ** 9, 1.0) is None
+    # a counted kernel: (VALU - trans) FMA-class cycles + trans transcendental cycles
+    csrc = tmp_path / "paper_2003_01836_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for f in bench.KERNEL_SOURCES["near_pairs_mixed"]:
+        (csrc / f).write_text("x")
+    import hashlib
+    h = hashlib.sha256()
+    for f in bench.KERNEL_SOURCES["near_pairs_mixed"]:
+        h.update(b"x")
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "interact_uniform-1M_valu_counters.md").write_text(
+        f"valu_insts near_pairs_mixed<0> 1.0e+09 source {h.hexdigest()[:16]}\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    m = bench.issue_model("near_pairs_mixed", 8, 0, 1, 64 * 10 ** 8, 2.0)
+    cycles = (1e9 - 1e8) * bench.CYCLES_FMA32 + 1e8 * bench.CYCLES_TRANS32
+    assert abs(m["t_min_ms"] - cycles / bench.SIMDS / bench.CLOCK_HZ * 1e3) < 1e-9
+    assert abs(m["frac"] - m["t_min_ms"] / 2.0) < 1e-12
