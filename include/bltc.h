@@ -124,7 +124,14 @@ typedef struct {
     int32_t leaf_size;           /* N_L >= 1: leaf capacity of the interpolated side's  */
                                  /* cluster tree (sources; targets for CLUSTER_PARTICLE) */
     int32_t batch_size;          /* N_B >= 1: capacity of the batches of the other side */
-    int32_t threads_per_target;  /* 0 or 1 (reserved for split target evaluation)      */
+    int32_t threads_per_target;  /* 0 or 1: one lane per target; 2 or 4: each batch's   */
+                                 /* interaction lists cut into that many contiguous     */
+                                 /* pieces, each evaluated by its own lane of the       */
+                                 /* target (in different waves) into a partial          */
+                                 /* potential, summed per target in piece order: more   */
+                                 /* waves for problems with few targets.                */
+                                 /* BLTC_PARTICLE_CLUSTER with max_q = 1 only;          */
+                                 /* bltc_autotune picks it                              */
     int32_t method;              /* bltc_method                                         */
     double delta;                /* BLTC_REGULARIZED_COULOMB length, >= 0               */
     int32_t no_symmetry;         /* 0: when the targets are the sources (same arrays,   */
@@ -224,6 +231,7 @@ typedef struct {
     int64_t mutual_pair_evals; /* kernel values computed once for two direct terms:   */
                              /* sum over mutual leaf pairs of N_B * N_C (no_symmetry */
                              /* = 0; counted once the device side exists), else 0    */
+    int32_t threads_per_target; /* lanes per target of the interaction launch (1, 2, 4) */
 } bltc_stats;
 
 int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out);
@@ -309,14 +317,18 @@ int bltc_batch_set_graph(bltc_batch* batch, int32_t enable);
 int bltc_batch_info_get(const bltc_batch* batch, bltc_batch_info* out);
 void bltc_batch_destroy(bltc_batch* batch);
 
-/* The library's tuner for the leaf and batch size (kept equal): for the
- * given DEVICE coordinates it builds a plan for each of the `ncand` candidate
- * sizes, times one evaluation of `num_q` (1..16) charge vectors on `stream`
- * after a warm-up, and writes the fastest into out->leaf_size and
- * out->batch_size (the other fields are copied from *p) and its device time
- * into *best_ms.  With use_cache != 0 the choice is looked up in / appended
- * to a text cache keyed by the problem class (log2 of the counts, theta,
- * degree, kernel, precision, one or several vectors); the file is
+/* The library's tuner for the leaf and batch size (kept equal) and the
+ * threads per target: for the given DEVICE coordinates it builds a plan for
+ * each of the `ncand` candidate sizes, times one evaluation of `num_q`
+ * (1..16) charge vectors on `stream` after a warm-up, and writes the fastest
+ * into out->leaf_size and out->batch_size (the other fields are copied from
+ * *p) and its device time into *best_ms.  For BLTC_PARTICLE_CLUSTER with
+ * num_q = 1 and p->threads_per_target = 0 it then times 2 and 4 threads per
+ * target at that size and writes the fastest of 1, 2, 4 into
+ * out->threads_per_target.  With use_cache != 0 the choice is looked up in /
+ * appended to a text cache keyed by the problem class (log2 of the counts,
+ * theta, degree, kernel, precision, one or several vectors, whether threads
+ * per target are searched); the file is
  * $BLTC_TUNE_CACHE, else $HOME/.bltc_tune_cache.  Synchronises `stream`.
  * Theta and n set the accuracy; the leaf size only moves which pairs are
  * approximated.  Candidates below (n+1)^3 can never be approximated as

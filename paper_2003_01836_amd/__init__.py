@@ -277,10 +277,13 @@ class Batch:
 
 
 def autotune(targets, sources, candidates=(1000, 2000, 3000, 4000), *, num_q=1, use_cache=True,
-             stream=None, **kw):
-    """Leaf/batch size chosen by timing each candidate on the GPU (`bltc_autotune`).
+             stream=None, full=False, **kw):
+    """Leaf/batch size chosen by timing each candidate on the GPU (`bltc_autotune`);
+    with threads_per_target=0 (the default) for a one-vector BLTC problem, also the
+    threads per target (1, 2 or 4).
 
-    Returns (size, milliseconds of one evaluation with that size)."""
+    Returns (size, milliseconds of one evaluation), or with full=True
+    (size, threads per target, milliseconds)."""
     lib = _capi.load()
     p = params(**kw)
     nt, tp = _coords_device(targets, "targets")
@@ -291,6 +294,8 @@ def autotune(targets, sources, candidates=(1000, 2000, 3000, 4000), *, num_q=1, 
     _capi.check(lib.bltc_autotune(ctypes.byref(p), nt, *tp, ns, *sp, int(num_q), cand, len(candidates),
                                   1 if use_cache else 0, ctypes.byref(out), ctypes.byref(ms),
                                   _stream_handle(stream)))
+    if full:
+        return out.leaf_size, max(1, out.threads_per_target), ms.value
     return out.leaf_size, ms.value
 
 

@@ -67,6 +67,7 @@ class Stats(ctypes.Structure):
         ("batch_size", ctypes.c_int32),
         ("setup_seconds", ctypes.c_double),
         ("mutual_pair_evals", ctypes.c_int64),
+        ("threads_per_target", ctypes.c_int32),
     ]
 
 

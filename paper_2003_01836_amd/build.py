@@ -73,6 +73,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         "kernels_cp": os.path.join(build_dir, "kernels_cp.o"),
         "kernels_hermite": os.path.join(build_dir, "kernels_hermite.o"),
         "kernels_sym": os.path.join(build_dir, "kernels_sym.o"),
+        "kernels_split": os.path.join(build_dir, "kernels_split.o"),
     }
     cmds = [
         ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
@@ -95,6 +96,8 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
                                objs["kernels_hermite"]],
         [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_sym.hip"), "-o",
                                objs["kernels_sym"]],
+        [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_split.hip"), "-o",
+                               objs["kernels_split"]],
     ]
     if verbose:
         for c in cmds:

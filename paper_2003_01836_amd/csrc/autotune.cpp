@@ -1,19 +1,24 @@
 // autotune.cpp -- the library's own tuner for the leaf size N_L and batch
-// size N_B (kept equal, as in the paper's runs), C ABI bltc_autotune.
+// size N_B (kept equal, as in the paper's runs) and the threads per target,
+// C ABI bltc_autotune.
 //
 // For a given geometry the tuner builds a plan for each candidate size, times
 // one evaluation of each on the GPU (HIP events on the caller's stream, after
-// one warm-up), and keeps the fastest.  Choices are cached in a text file
+// one warm-up), and keeps the fastest; for one-vector BLTC plans whose
+// threads per target are left to it (0) it then times 2 and 4 lanes per
+// target at that size and keeps the fastest of 1, 2, 4.  Choices are cached in a text file
 // keyed by the problem class (log2 of the particle counts, theta, degree,
 // kernel, precision, one or several charge vectors), so later calls with a
 // similar problem skip the search.  The accuracy of the treecode is set by
 // theta and n; the leaf size changes which pairs are approximated and hence
 // the error slightly, never the bound the MAC enforces.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <sstream>
+#include <string>
 
 #include "internal.hpp"
 
@@ -33,14 +38,14 @@ std::string cache_path()
 std::string class_key(const bltc_params* p, int64_t nt, int64_t ns, int32_t num_q)
 {
     std::ostringstream k;
-    k << "v1 nt2=" << (nt > 0 ? static_cast<int>(std::lround(std::log2(static_cast<double>(nt)))) : 0)
+    k << "v2 nt2=" << (nt > 0 ? static_cast<int>(std::lround(std::log2(static_cast<double>(nt)))) : 0)
       << " ns2=" << (ns > 0 ? static_cast<int>(std::lround(std::log2(static_cast<double>(ns)))) : 0)
       << " theta=" << p->theta << " n=" << p->degree << " kernel=" << p->kernel
       << " prec=" << p->precision << " q=" << (num_q > 1 ? 16 : 1);
     return k.str();
 }
 
-bool cache_lookup(const std::string& key, int32_t* leaf, double* ms)
+bool cache_lookup(const std::string& key, int32_t* leaf, int32_t* tpt, double* ms)
 {
     std::ifstream f(cache_path());
     std::string line;
@@ -50,10 +55,11 @@ bool cache_lookup(const std::string& key, int32_t* leaf, double* ms)
         if (bar == std::string::npos || line.substr(0, bar) != key)
             continue;
         std::istringstream v(line.substr(bar + 1));
-        int32_t l = 0;
+        int32_t l = 0, tp = 0;
         double t = 0.0;
-        if (v >> l >> t && l > 0) {
+        if (v >> l >> t >> tp && l > 0 && (tp == 1 || tp == 2 || tp == 4)) {
             *leaf = l;
+            *tpt = tp;
             *ms = t;
             found = true;   // the last entry of a key wins
         }
@@ -61,12 +67,12 @@ bool cache_lookup(const std::string& key, int32_t* leaf, double* ms)
     return found;
 }
 
-void cache_store(const std::string& key, int32_t leaf, double ms)
+void cache_store(const std::string& key, int32_t leaf, int32_t tpt, double ms)
 {
     std::ofstream f(cache_path(), std::ios::app);
     if (f) {
         f.precision(17);
-        f << key << "|" << leaf << " " << ms << "\n";
+        f << key << "|" << leaf << " " << ms << " " << tpt << "\n";
     }
 }
 
@@ -92,12 +98,18 @@ extern "C" int bltc_autotune(const bltc_params* p, int64_t nt, const double* tx,
         *best_ms = 0.0;
     if (nt == 0 || ns == 0)
         return BLTC_OK;
-    const std::string key = class_key(p, nt, ns, num_q);
-    int32_t cached = 0;
+    // threads per target: searched for one-vector BLTC plans that leave it open
+    const bool tune_tpt =
+        p->threads_per_target == 0 && p->method == BLTC_PARTICLE_CLUSTER && num_q == 1;
+    const std::string key = class_key(p, nt, ns, num_q) + " tpt=" +
+                            std::to_string(tune_tpt ? 0 : std::max(1, p->threads_per_target));
+    int32_t cached = 0, cached_tpt = 1;
     double cached_ms = 0.0;
-    if (use_cache && cache_lookup(key, &cached, &cached_ms)) {
+    if (use_cache && cache_lookup(key, &cached, &cached_tpt, &cached_ms)) {
         out->leaf_size = cached;
         out->batch_size = cached;
+        if (tune_tpt)
+            out->threads_per_target = cached_tpt;
         if (best_ms)
             *best_ms = cached_ms;
         return BLTC_OK;
@@ -108,7 +120,7 @@ extern "C" int bltc_autotune(const bltc_params* p, int64_t nt, const double* tx,
     double* phi = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = BLTC_OK;
-    int32_t best = -1;
+    int32_t best = -1, best_tpt = 1;
     double best_t = 0.0;
     std::vector<double> ones(static_cast<size_t>(ns) * num_q, 1.0);
     do {
@@ -125,10 +137,16 @@ extern "C" int bltc_autotune(const bltc_params* p, int64_t nt, const double* tx,
             rc = bltc_detail::hip_fail(e, "autotune setup");
             break;
         }
-        for (int32_t c = 0; c < ncand && rc == BLTC_OK; ++c) {
+        // candidate sizes at the caller's threads per target, then (tune_tpt)
+        // 2 and 4 lanes per target at the best size
+        const int32_t nsteps = ncand + (tune_tpt ? 2 : 0);
+        for (int32_t c = 0; c < nsteps && rc == BLTC_OK; ++c) {
             bltc_params trial = *p;
-            trial.leaf_size = candidates[c];
-            trial.batch_size = candidates[c];
+            const int32_t leaf = c < ncand ? candidates[c] : best;
+            const int32_t tpt = c < ncand ? p->threads_per_target : (c == ncand ? 2 : 4);
+            trial.leaf_size = leaf;
+            trial.batch_size = leaf;
+            trial.threads_per_target = tpt;
             bltc_plan* plan = nullptr;
             rc = bltc_plan_create(&plan, &trial, nt, tx, ty, tz, ns, sx, sy, sz,
                                   num_q > 1 ? 16 : 1, stream);
@@ -151,7 +169,8 @@ extern "C" int bltc_autotune(const bltc_params* p, int64_t nt, const double* tx,
             }
             bltc_plan_destroy(plan);
             if (rc == BLTC_OK && (best < 0 || ms < best_t)) {
-                best = candidates[c];
+                best = leaf;
+                best_tpt = std::max(1, tpt);
                 best_t = ms;
             }
         }
@@ -168,9 +187,11 @@ extern "C" int bltc_autotune(const bltc_params* p, int64_t nt, const double* tx,
         return rc;
     out->leaf_size = best;
     out->batch_size = best;
+    if (tune_tpt)
+        out->threads_per_target = best_tpt;
     if (best_ms)
         *best_ms = best_t;
     if (use_cache)
-        cache_store(key, best, best_t);
+        cache_store(key, best, best_tpt, best_t);
     return BLTC_OK;
 }

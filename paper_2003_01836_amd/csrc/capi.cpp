@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "kernels_split.hpp"
 #include "setup_gpu.hpp"
 
 using bltc_detail::fail;
@@ -43,8 +44,9 @@ int check_params(const bltc_params* p)
         return fail(BLTC_EINVAL, "degree must be in 1..%d", bltc::kMaxDegree);
     if (p->leaf_size < 1 || p->batch_size < 1)
         return fail(BLTC_EINVAL, "leaf_size and batch_size must be >= 1");
-    if (p->threads_per_target < 0 || p->threads_per_target > 1)
-        return fail(BLTC_EUNSUPPORTED, "threads_per_target must be 0 or 1");
+    if (p->threads_per_target != 0 && p->threads_per_target != 1 && p->threads_per_target != 2 &&
+        p->threads_per_target != 4)
+        return fail(BLTC_EINVAL, "threads_per_target must be 0, 1, 2 or 4");
     if (p->no_symmetry != 0 && p->no_symmetry != 1)
         return fail(BLTC_EINVAL, "no_symmetry must be 0 or 1");
     if (p->method != BLTC_PARTICLE_CLUSTER && p->method != BLTC_CLUSTER_PARTICLE &&
@@ -230,6 +232,102 @@ void schedule_single_vector(bltc_plan* plan)
     plan->d.group_threads = bltc::kGroupSizeSym;
 }
 
+// Threads per target T > 1: batch b becomes the batches b T + p, p < T, whose
+// lists are contiguous pieces of b's far and (reduced) direct lists, over T
+// copies of the targets; copy p writes its partial potentials to row p of
+// plan->tpt_buf in caller order.  The mutual-pair results of b go with piece 0.
+int upload_split(bltc_plan* plan, hipStream_t s)
+{
+    const bltc::HostPlan& hp = plan->hp;
+    const bltc::DevicePlan& d = plan->d;
+    const int32_t T = plan->prm.threads_per_target;
+    const int64_t nb = d.nbatches, nt = d.nt;
+    bltc::DevicePlan& t = plan->dt;
+    t = d;
+    auto split = [&](const std::vector<int32_t>& off) {
+        std::vector<int32_t> out(static_cast<size_t>(nb * T + 1), 0);
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t n = off[b + 1] - off[b];
+            for (int32_t p = 0; p < T; ++p)
+                out[b * T + p] = static_cast<int32_t>(off[b] + n * p / T);
+        }
+        out[nb * T] = nb > 0 ? off[nb] : 0;
+        return out;
+    };
+    HIP_TRY(plan->put(&t.far_off, split(hp.far_off), s));
+    if (d.sym) {
+        HIP_TRY(plan->put(&t.sym_near_off, split(plan->sym_near_off_h), s));
+        std::vector<int32_t> pc_off(static_cast<size_t>(nb * T + 1), 0);
+        std::vector<int64_t> bbeg(static_cast<size_t>(nb * T));
+        for (int64_t b = 0; b < nb; ++b)
+            for (int32_t p = 0; p < T; ++p) {
+                pc_off[b * T + p] = p == 0 ? plan->sym_pc_off_h[b] : plan->sym_pc_off_h[b + 1];
+                bbeg[b * T + p] = p * nt + hp.batch_begin[b];
+            }
+        pc_off[nb * T] = nb > 0 ? plan->sym_pc_off_h[nb] : 0;
+        HIP_TRY(plan->put(&t.sym_pc_off, pc_off, s));
+        HIP_TRY(plan->put(&t.batch_begin, bbeg, s));
+    } else {
+        HIP_TRY(plan->put(&t.near_off, split(hp.near_off), s));
+    }
+    // T copies of the targets; copy p writes p nt + caller index
+    std::vector<int64_t> orig(static_cast<size_t>(nt));
+    if (plan->device_particles) {
+        if (nt > 0)
+            HIP_TRY(hipMemcpy(orig.data(), d.tgt_orig, nt * sizeof(int64_t), hipMemcpyDeviceToHost));
+    } else {
+        orig = hp.tgt.order;
+    }
+    std::vector<int64_t> orig_t(static_cast<size_t>(T * nt)), end_t(static_cast<size_t>(nb * T));
+    for (int32_t p = 0; p < T; ++p)
+        for (int64_t i = 0; i < nt; ++i)
+            orig_t[p * nt + i] = p * nt + orig[i];
+    HIP_TRY(plan->alloc(&t.tgt, static_cast<size_t>(T * nt)));
+    for (int32_t p = 0; p < T; ++p)
+        HIP_TRY(hipMemcpyAsync(t.tgt + p * nt, d.tgt, nt * sizeof(double4),
+                               hipMemcpyDeviceToDevice, s));
+    HIP_TRY(plan->put(&t.tgt_orig, orig_t, s));
+    // batches, their boxes (FP32-mixed) and the workgroup schedule, each
+    // piece with 1/T of its batch's work
+    std::vector<int64_t> begin_t(static_cast<size_t>(nb * T)), count_t(begin_t.size()),
+        cost_t(begin_t.size());
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t far = static_cast<int64_t>(hp.far_off[b + 1] - hp.far_off[b]) * hp.P;
+        const int64_t near = std::max<int64_t>(0, hp.batch_cost[b] - far);
+        const int64_t cost = far + (near * 22) / 10;
+        for (int32_t p = 0; p < T; ++p) {
+            begin_t[b * T + p] = p * nt + hp.batch_begin[b];
+            count_t[b * T + p] = hp.batch_count[b];
+            end_t[b * T + p] = begin_t[b * T + p] + hp.batch_count[b];
+            cost_t[b * T + p] = cost / T;
+        }
+    }
+    HIP_TRY(plan->put(&t.batch_end, end_t, s));
+    if (plan->prm.precision == BLTC_FP32_MIXED) {
+        std::vector<double4> bi(static_cast<size_t>(nb * T));
+        for (int64_t b = 0; b < nb; ++b) {
+            const int32_t bn = hp.batch_node[b];
+            for (int32_t p = 0; p < T; ++p)
+                bi[b * T + p] = make_double4(hp.tgt.center[3 * bn], hp.tgt.center[3 * bn + 1],
+                                             hp.tgt.center[3 * bn + 2], hp.tgt.radius[bn]);
+        }
+        HIP_TRY(plan->put(&t.batch_info, bi, s));
+    }
+    std::vector<int32_t> gb;
+    std::vector<int64_t> gf;
+    bltc::group_schedule(begin_t, count_t, cost_t, bltc::kGroupSizeSym, hp.prm.xcds, gb, gf);
+    HIP_TRY(plan->put(&t.group_batch, gb, s));
+    HIP_TRY(plan->put(&t.group_first, gf, s));
+    t.ngroups = static_cast<int64_t>(gb.size());
+    t.group_threads = bltc::kGroupSizeSym;
+    t.nbatches = nb * T;
+    t.nt = T * nt;
+    HIP_TRY(plan->alloc(&plan->tpt_buf, static_cast<size_t>(T * nt)));
+    HIP_TRY(hipStreamSynchronize(s));
+    plan->tpt = T;
+    return BLTC_OK;
+}
+
 }  // namespace
 
 int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
@@ -359,6 +457,11 @@ int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
         HIP_TRY(plan->alloc(&d.qhat32, static_cast<size_t>(d.nslots) * hp.P));
         HIP_TRY(hipStreamSynchronize(s));
     }
+    if (plan->prm.threads_per_target > 1) {
+        rc = upload_split(plan, s);
+        if (rc != BLTC_OK)
+            return rc;
+    }
     // host staging vectors die at return: finish the copies first
     HIP_TRY(hipStreamSynchronize(s));
     plan->uploaded = true;
@@ -440,12 +543,20 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
                 HIP_TRY(hipEventRecord(plan->ev_pairs, s));
             }
         }
-        if (d.hermite)
+        if (d.hermite) {
             HIP_TRY(bltc::launch_interact_hermite(d, kp, phi, s));
-        else if (kp.precision == BLTC_FP32_MIXED)
+        } else if (plan->tpt > 1) {
+            // several lanes per target: partial potentials, then their sum
+            if (kp.precision == BLTC_FP32_MIXED)
+                HIP_TRY(bltc::launch_interact_mixed(plan->dt, kp, plan->tpt_buf, s));
+            else
+                HIP_TRY(bltc::launch_interact(plan->dt, kp, plan->tpt_buf, s));
+            HIP_TRY(bltc::launch_sum_parts(plan->tpt_buf, d.nt, plan->tpt, phi, s));
+        } else if (kp.precision == BLTC_FP32_MIXED) {
             HIP_TRY(bltc::launch_interact_mixed(d, kp, phi, s));
-        else
+        } else {
             HIP_TRY(bltc::launch_interact(d, kp, phi, s));
+        }
         HIP_TRY(mark(0, 3));
     } else {
         for (int32_t u = 0; u < units; ++u) {
@@ -486,6 +597,9 @@ int create_common(bltc_plan** out, const bltc_params* p, int64_t nt, const doubl
     if (p->method != BLTC_PARTICLE_CLUSTER && max_q != 1)
         return fail(BLTC_EUNSUPPORTED, "cluster-particle, cluster-cluster and Hermite plans take "
                                        "one charge vector (max_q = 1)");
+    if (p->threads_per_target > 1 && (p->method != BLTC_PARTICLE_CLUSTER || max_q != 1))
+        return fail(BLTC_EUNSUPPORTED, "threads_per_target > 1 needs a BLTC_PARTICLE_CLUSTER plan "
+                                       "with max_q = 1");
     return BLTC_OK;
 }
 
@@ -570,6 +684,10 @@ int bltc_internal_upload_symmetric(bltc_plan* plan, bltc::DevicePlan& d,
     plan->allocations.push_back(out);
     d.sym_out = out;
     HIP_TRY(plan->put(&d.sym_unit, units, s));
+    if (&d == &plan->d) {
+        plan->sym_near_off_h = sp.near_off;
+        plan->sym_pc_off_h = sp.pc_off;
+    }
     HIP_TRY(plan->put(&d.sym_near_off, sp.near_off, s));
     HIP_TRY(plan->put(&d.sym_near_begin, sp.near_begin, s));
     HIP_TRY(plan->put(&d.sym_near_count, sp.near_count, s));
@@ -741,6 +859,7 @@ int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out)
         out->leaf_size = plan->prm.leaf_size;
         out->batch_size = plan->prm.batch_size;
         out->mutual_pair_evals = plan->sym_pair_evals;
+        out->threads_per_target = 1;
         return BLTC_OK;
     }
     out->clusters = hp.src.nodes();
@@ -758,6 +877,7 @@ int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out)
     out->batch_size = plan->prm.batch_size;
     out->setup_seconds = hp.setup_seconds;
     out->mutual_pair_evals = plan->sym_pair_evals;
+    out->threads_per_target = std::max(1, plan->prm.threads_per_target);
     return BLTC_OK;
 }
 

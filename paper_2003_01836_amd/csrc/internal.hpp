@@ -98,6 +98,14 @@ struct bltc_plan {
     int32_t timed_q = 0;                 // charge vectors covered by the recorded events
     int64_t sym_pair_evals = 0;          // kernel values of the mutual leaf pairs (each serving
                                          // two direct terms), once uploaded
+    // threads per target > 1 (one charge vector, BLTC): each batch's lists cut
+    // into tpt contiguous pieces, evaluated as separate batches over tpt
+    // copies of the targets (view dt) into tpt_buf[piece][target], then summed
+    // per target in piece order
+    int32_t tpt = 1;
+    bltc::DevicePlan dt;
+    double* tpt_buf = nullptr;
+    std::vector<int32_t> sym_near_off_h, sym_pc_off_h;   // host copies (mutual pairs)
     std::vector<hipEvent_t> events;      // 4 per charge vector
     hipEvent_t ev_pairs = nullptr;       // after the mutual-pair launch (timing)
     bool timed_pairs = false;            // ev_pairs belongs to the recorded execution

@@ -449,6 +449,45 @@ def test_modified_charges_every_degree(dev, degree):
     _close(oc.potential(q), phi)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("same", [True, False])
+def test_threads_per_target(dev, precision, same):
+    # 2 and 4 lanes per target split each batch's lists into contiguous pieces;
+    # the per-entry sums are unchanged, only the FP64 order across entries moves
+    g = np.random.default_rng(160)
+    src = g.uniform(-1, 1, (9000, 3))
+    tgt = src if same else g.uniform(-0.8, 1.3, (7001, 3))
+    q = g.uniform(-1, 1, len(src))
+    kw = dict(theta=0.7, degree=5, leaf_size=300, batch_size=300 if same else 251,
+              precision=precision)
+    plan1, phi1 = _run_plan(dev, tgt, src, q, **kw)
+    assert (plan1.stats()["mutual_pair_evals"] > 0) == same
+    for tpt in (2, 4):
+        plan, phi = _run_plan(dev, tgt, src, q, threads_per_target=tpt, **kw)
+        assert plan.stats()["threads_per_target"] == tpt
+        assert np.max(np.abs(phi - phi1)) <= 1e-12 * np.max(np.abs(phi1)), tpt
+    if precision == "fp64":
+        ref = oracle.Treecode(tgt, src, 0.7, 5, 300, 300 if same else 251).potential(q)
+        _close(ref, phi)
+
+
+def test_threads_per_target_autotuned(dev):
+    import paper_2003_01836_amd as bltc
+    pos, q = inputs.uniform_cube(4000, 161)
+    t = _dev_soa(pos, dev)
+    size, tpt, ms = bltc.autotune(t, t, candidates=(200, 400), use_cache=False, full=True,
+                                  theta=0.7, degree=4)
+    assert size in (200, 400) and tpt in (1, 2, 4) and ms > 0
+    plan = bltc.Plan(t, t, theta=0.7, degree=4, leaf_size=size, batch_size=size,
+                     threads_per_target=tpt)
+    phi = plan.execute(torch.from_numpy(q[0]).to(dev)).cpu().numpy()
+    _close(oracle.Treecode(pos, pos, 0.7, 4, size, size).potential(q[0]), phi)
+    # a fixed choice is kept
+    _, tpt_fixed, _ = bltc.autotune(t, t, candidates=(200,), use_cache=False, full=True,
+                                    theta=0.7, degree=4, threads_per_target=1)
+    assert tpt_fixed == 1
+
+
 # --------------------------------------------------------------------------
 # many systems in one work-queue launch, replayed from a hipGraph
 # --------------------------------------------------------------------------

@@ -193,3 +193,20 @@ def test_hermite_unsupported_options_are_rejected():
         bltc.Plan(t, t, host=True, method="hermite", max_q=2)
     bltc.Plan(t, t, host=True, method="hermite", degree=10)
     bltc.Plan(t, t, host=True, method="hermite", precision="fp32_mixed")
+
+
+def test_threads_per_target_options():
+    pos, _ = inputs.uniform_cube(300, 2)
+    t = _soa(pos)
+    for bad in (3, 5, -1):
+        with pytest.raises(bltc.BLTCError):
+            bltc.Plan(t, t, host=True, threads_per_target=bad)
+    # several lanes per target: one-vector BLTC plans only
+    with pytest.raises(bltc.BLTCError):
+        bltc.Plan(t, t, host=True, threads_per_target=2, method="cp")
+    with pytest.raises(bltc.BLTCError):
+        bltc.Plan(t, t, host=True, threads_per_target=2, method="hermite")
+    with pytest.raises(bltc.BLTCError):
+        bltc.Plan(t, t, host=True, threads_per_target=4, max_q=2)
+    for tpt, want in ((0, 1), (1, 1), (2, 2), (4, 4)):
+        assert bltc.Plan(t, t, host=True, threads_per_target=tpt).stats()["threads_per_target"] == want
