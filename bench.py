@@ -59,10 +59,12 @@ SIMDS = 1024                        # 256 CU x 4 SIMD
 CLOCK_HZ = 2.4e9
 
 
-def counter_value(prefix, profile, kernel, degree, ker_id):
+def counter_value(prefix, profile, kernel, degree, ker_id, tpt=1):
     """A per-launch value of `kernel` from a committed rocprofv3 summary (lines
-    `<prefix> <kernel instantiation> <value> source <hash>`), or None when there is
-    none for this instantiation or the kernel's sources changed since."""
+    `<prefix> <kernel instantiation> <value> source <hash> [tpt <threads per target>]`,
+    measured with that many threads per target, 1 when absent), or None when there
+    is none for this instantiation and threads per target or the kernel's sources
+    changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
@@ -77,24 +79,30 @@ def counter_value(prefix, profile, kernel, degree, ker_id):
         for line in fh:
             if line.startswith(want):
                 parts = line[len(want):].split()
-                if len(parts) == 3 and parts[1] == "source" and parts[2] == h.hexdigest()[:16]:
+                if len(parts) == 5 and parts[3] == "tpt":
+                    line_tpt = int(parts[4])
+                    parts = parts[:3]
+                else:
+                    line_tpt = 1
+                if (len(parts) == 3 and parts[1] == "source" and parts[2] == h.hexdigest()[:16]
+                        and line_tpt == tpt):
                     return float(parts[0])
     return None
 
 
-def counter_traffic(kernel, degree, ker_id):
+def counter_traffic(kernel, degree, ker_id, tpt=1):
     """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, calibrated by a plain copy)."""
     return counter_value("traffic_bytes", "interact_uniform-1M_counters.md", kernel, degree,
-                         ker_id)
+                         ker_id, tpt)
 
 
-def issue_model(kernel, degree, ker_id, trans_per_eval, evals, ms):
+def issue_model(kernel, degree, ker_id, trans_per_eval, evals, ms, tpt=1):
     """Shortest time at which the SIMDs could issue the VALU instructions that the
     kernel issues per launch (SQ_INSTS_VALU of the committed counter summary: one
     transcendental per kernel value, or two for Yukawa, the rest FMA-class), and its
     ratio to the measured launch time; None where no counters fit the kernel."""
     valu = counter_value("valu_insts", "interact_uniform-1M_valu_counters.md", kernel, degree,
-                         ker_id)
+                         ker_id, tpt)
     if valu is None or not kernel.endswith("mixed"):
         return None
     trans = trans_per_eval * evals / 64.0
@@ -525,6 +533,9 @@ def main():
     ap.add_argument("--setup-host-max", type=int, default=20_000_000,
                     help="setup workload: also time the host planner up to this many particles")
     ap.add_argument("--precision", default="both", choices=["fp64", "fp32_mixed", "both"])
+    ap.add_argument("--threads-per-target", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="headline workloads: lanes per target (0: the library's autotuner "
+                         "picks 1, 2 or 4 at the workload's leaf size)")
     ap.add_argument("--cpu-sample", type=int, default=150000,
                     help="targets the CPU oracle evaluates for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (no errors, no CPU baseline)")
@@ -575,10 +586,19 @@ def main():
     precisions = ["fp64", "fp32_mixed"] if args.precision == "both" else [args.precision]
     results = {}
     for prec in precisions:
+        tpt = args.threads_per_target
+        if tpt == 0 and w["leaf"] == w["batch"]:
+            # threads per target: the library's autotuner at the workload's leaf size
+            _, tpt, tune_ms = bltc.autotune(t_soa, t_soa, candidates=(w["leaf"],), use_cache=False,
+                                            full=True, theta=w["theta"], degree=w["degree"],
+                                            kernel=w["kernel"], kappa=w["kappa"], precision=prec)
+            log(f"{prec}: autotuner: {tpt} threads per target ({tune_ms:.2f} ms)")
+        tpt = max(1, tpt)
         log(f"{prec}: planning")
         t0 = time.perf_counter()
         plan = bltc.Plan(t_soa, t_soa, theta=w["theta"], degree=w["degree"], leaf_size=w["leaf"],
-                         batch_size=w["batch"], kernel=w["kernel"], kappa=w["kappa"], precision=prec)
+                         batch_size=w["batch"], kernel=w["kernel"], kappa=w["kappa"], precision=prec,
+                         threads_per_target=tpt)
         t_plan = time.perf_counter() - t0
         st = plan.stats()
         log(f"{prec}: plan {t_plan:.2f}s, {st['batches']} batches, {st['approx_pairs']} approx + "
@@ -604,7 +624,8 @@ def main():
         torch.cuda.synchronize()
         got = phi.cpu().numpy()
         log(f"{prec}: {ms_step:.3f} ms/step; phases {ph}")
-        results[prec] = dict(plan=plan, stats=st, ms=ms_step, phases=ph, phi=got, t_plan=t_plan)
+        results[prec] = dict(plan=plan, stats=st, ms=ms_step, phases=ph, phi=got, t_plan=t_plan,
+                             tpt=tpt)
 
     cpu = None
     errors = {}
@@ -661,9 +682,11 @@ def main():
     for kn, kv in kernels.items():
         kv["achieved"] = kv["evals"] * kv["flops_per_eval"] / (kv["ms_per_launch"] * 1e-3) / 1e12
         kv["frac"] = kv["achieved"] / peak
-        kv["traffic"] = counter_traffic(kn, w["degree"], ker_id)
+        # the pair kernel does not depend on the threads per target
+        kt = r["tpt"] if kn.startswith("interact") else 1
+        kv["traffic"] = counter_traffic(kn, w["degree"], ker_id, kt)
         kv["issue"] = issue_model(kn, w["degree"], ker_id, trans_per_eval, kv["evals"],
-                                  kv["ms_per_launch"])
+                                  kv["ms_per_launch"], kt)
     kname = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])
     kd = kernels[kname]
     phase_flops = sum(v["evals"] * v["flops_per_eval"] for v in kernels.values())
@@ -683,7 +706,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: N={n} uniform [-1,1]^3, charges U[-1,1], "
                                f"{w['kernel']}, theta={w['theta']}, n={w['degree']}, "
-                               f"N_L=N_B={w['leaf']}", "path": best},
+                               f"N_L=N_B={w['leaf']}", "path": best,
+                   "threads_per_target": r["tpt"]},
         "roofline": {"bound": "alu", "achieved": kd["achieved"], "peak": peak, "unit": "TFLOP/s",
                      "frac": kd["frac"], "traffic": kd["traffic"],
                      "kernel": kname, "flops_per_eval": kd["flops_per_eval"],
@@ -694,6 +718,7 @@ def main():
                                            "ms": r["phases"]["interact"]}},
         "cpu_baseline": cpu,
         "paths": {p: {"targets_per_s": n / (v["ms"] * 1e-3), "ms_per_step": v["ms"],
+                      "threads_per_target": v["tpt"],
                       "phases_ms": v["phases"], "plan_s": v["t_plan"],
                       "end_to_end_targets_per_s": n / (v["t_plan"] + v["ms"] * 1e-3),
                       "terms_per_s": evals / (v["phases"]["interact"] * 1e-3),
