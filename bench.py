@@ -419,9 +419,14 @@ def run_hermite(args, dev):
     for deg in args.hermite_degrees:
         res["degrees"][deg] = {}
         for prec in ("fp64", "fp32_mixed"):
+            # threads per target: the library's autotuner at the workload's leaf size
+            _, tpt, _ = bltc.autotune(t, t, candidates=(w["leaf"],), use_cache=False, full=True,
+                                      method="hermite", theta=w["theta"], degree=deg,
+                                      precision=prec)
             t0 = time.perf_counter()
             plan = bltc.Plan(t, t, method="hermite", theta=w["theta"], degree=deg,
-                             leaf_size=w["leaf"], batch_size=w["batch"], precision=prec)
+                             leaf_size=w["leaf"], batch_size=w["batch"], precision=prec,
+                             threads_per_target=tpt)
             t_plan = time.perf_counter() - t0
             st = plan.stats()
             for _ in range(args.warmup):
@@ -449,6 +454,7 @@ def run_hermite(args, dev):
             kern = "f64" if prec == "fp64" else "mixed"
             res["degrees"][deg][prec] = {
                 "ms_per_step": ms, "targets_per_s": n / (ms * 1e-3), "plan_s": t_plan,
+                "threads_per_target": tpt,
                 "phases_ms": ph, "grid_point_evals": points, "near_evals": st["near_evals"],
                 "mutual_pair_evals": mutual,
                 "approx_pairs": st["approx_pairs"], "direct_pairs": st["direct_pairs"],

@@ -130,8 +130,8 @@ typedef struct {
                                  /* target (in different waves) into a partial          */
                                  /* potential, summed per target in piece order: more   */
                                  /* waves for problems with few targets.                */
-                                 /* BLTC_PARTICLE_CLUSTER with max_q = 1 only;          */
-                                 /* bltc_autotune picks it                              */
+                                 /* BLTC_PARTICLE_CLUSTER and BLTC_HERMITE with         */
+                                 /* max_q = 1 only; bltc_autotune picks it              */
     int32_t method;              /* bltc_method                                         */
     double delta;                /* BLTC_REGULARIZED_COULOMB length, >= 0               */
     int32_t no_symmetry;         /* 0: when the targets are the sources (same arrays,   */
@@ -322,13 +322,13 @@ void bltc_batch_destroy(bltc_batch* batch);
  * each of the `ncand` candidate sizes, times one evaluation of `num_q`
  * (1..16) charge vectors on `stream` after a warm-up, and writes the fastest
  * into out->leaf_size and out->batch_size (the other fields are copied from
- * *p) and its device time into *best_ms.  For BLTC_PARTICLE_CLUSTER with
- * num_q = 1 and p->threads_per_target = 0 it then times 2 and 4 threads per
- * target at that size and writes the fastest of 1, 2, 4 into
- * out->threads_per_target.  With use_cache != 0 the choice is looked up in /
- * appended to a text cache keyed by the problem class (log2 of the counts,
- * theta, degree, kernel, precision, one or several vectors, whether threads
- * per target are searched); the file is
+ * *p) and its device time into *best_ms.  For BLTC_PARTICLE_CLUSTER and
+ * BLTC_HERMITE with num_q = 1 and p->threads_per_target = 0 it then times 2
+ * and 4 threads per target at that size and writes the fastest of 1, 2, 4
+ * into out->threads_per_target.  With use_cache != 0 the choice is looked up
+ * in / appended to a text cache keyed by the problem class (method, log2 of
+ * the counts, theta, degree, kernel, precision, one or several vectors,
+ * whether threads per target are searched); the file is
  * $BLTC_TUNE_CACHE, else $HOME/.bltc_tune_cache.  Synchronises `stream`.
  * Theta and n set the accuracy; the leaf size only moves which pairs are
  * approximated.  Candidates below (n+1)^3 can never be approximated as

@@ -4,11 +4,12 @@
 //
 // For a given geometry the tuner builds a plan for each candidate size, times
 // one evaluation of each on the GPU (HIP events on the caller's stream, after
-// one warm-up), and keeps the fastest; for one-vector BLTC plans whose
-// threads per target are left to it (0) it then times 2 and 4 lanes per
-// target at that size and keeps the fastest of 1, 2, 4.  Choices are cached in a text file
-// keyed by the problem class (log2 of the particle counts, theta, degree,
-// kernel, precision, one or several charge vectors), so later calls with a
+// one warm-up), and keeps the fastest; for one-vector BLTC and Hermite plans
+// whose threads per target are left to it (0) it then times 2 and 4 lanes
+// per target at that size and keeps the fastest of 1, 2, 4.  Choices are
+// cached in a text file keyed by the problem class (method, log2 of the
+// particle counts, theta, degree, kernel and its parameter, precision, one or
+// several charge vectors), so later calls with a
 // similar problem skip the search.  The accuracy of the treecode is set by
 // theta and n; the leaf size changes which pairs are approximated and hence
 // the error slightly, never the bound the MAC enforces.
@@ -41,7 +42,8 @@ std::string class_key(const bltc_params* p, int64_t nt, int64_t ns, int32_t num_
     k << "v2 nt2=" << (nt > 0 ? static_cast<int>(std::lround(std::log2(static_cast<double>(nt)))) : 0)
       << " ns2=" << (ns > 0 ? static_cast<int>(std::lround(std::log2(static_cast<double>(ns)))) : 0)
       << " theta=" << p->theta << " n=" << p->degree << " kernel=" << p->kernel
-      << " prec=" << p->precision << " q=" << (num_q > 1 ? 16 : 1);
+      << " prec=" << p->precision << " q=" << (num_q > 1 ? 16 : 1) << " method=" << p->method
+      << " delta=" << p->delta << " kappa=" << p->kappa;
     return k.str();
 }
 
@@ -99,8 +101,8 @@ extern "C" int bltc_autotune(const bltc_params* p, int64_t nt, const double* tx,
     if (nt == 0 || ns == 0)
         return BLTC_OK;
     // threads per target: searched for one-vector BLTC plans that leave it open
-    const bool tune_tpt =
-        p->threads_per_target == 0 && p->method == BLTC_PARTICLE_CLUSTER && num_q == 1;
+    const bool tune_tpt = p->threads_per_target == 0 && num_q == 1 &&
+                          (p->method == BLTC_PARTICLE_CLUSTER || p->method == BLTC_HERMITE);
     const std::string key = class_key(p, nt, ns, num_q) + " tpt=" +
                             std::to_string(tune_tpt ? 0 : std::max(1, p->threads_per_target));
     int32_t cached = 0, cached_tpt = 1;

@@ -543,15 +543,17 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
                 HIP_TRY(hipEventRecord(plan->ev_pairs, s));
             }
         }
-        if (d.hermite) {
-            HIP_TRY(bltc::launch_interact_hermite(d, kp, phi, s));
-        } else if (plan->tpt > 1) {
+        if (plan->tpt > 1) {
             // several lanes per target: partial potentials, then their sum
-            if (kp.precision == BLTC_FP32_MIXED)
+            if (d.hermite)
+                HIP_TRY(bltc::launch_interact_hermite(plan->dt, kp, plan->tpt_buf, s));
+            else if (kp.precision == BLTC_FP32_MIXED)
                 HIP_TRY(bltc::launch_interact_mixed(plan->dt, kp, plan->tpt_buf, s));
             else
                 HIP_TRY(bltc::launch_interact(plan->dt, kp, plan->tpt_buf, s));
             HIP_TRY(bltc::launch_sum_parts(plan->tpt_buf, d.nt, plan->tpt, phi, s));
+        } else if (d.hermite) {
+            HIP_TRY(bltc::launch_interact_hermite(d, kp, phi, s));
         } else if (kp.precision == BLTC_FP32_MIXED) {
             HIP_TRY(bltc::launch_interact_mixed(d, kp, phi, s));
         } else {
@@ -597,9 +599,10 @@ int create_common(bltc_plan** out, const bltc_params* p, int64_t nt, const doubl
     if (p->method != BLTC_PARTICLE_CLUSTER && max_q != 1)
         return fail(BLTC_EUNSUPPORTED, "cluster-particle, cluster-cluster and Hermite plans take "
                                        "one charge vector (max_q = 1)");
-    if (p->threads_per_target > 1 && (p->method != BLTC_PARTICLE_CLUSTER || max_q != 1))
-        return fail(BLTC_EUNSUPPORTED, "threads_per_target > 1 needs a BLTC_PARTICLE_CLUSTER plan "
-                                       "with max_q = 1");
+    if (p->threads_per_target > 1 &&
+        ((p->method != BLTC_PARTICLE_CLUSTER && p->method != BLTC_HERMITE) || max_q != 1))
+        return fail(BLTC_EUNSUPPORTED, "threads_per_target > 1 needs a BLTC_PARTICLE_CLUSTER or "
+                                       "BLTC_HERMITE plan with max_q = 1");
     return BLTC_OK;
 }
 

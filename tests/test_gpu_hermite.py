@@ -236,3 +236,14 @@ def test_hermite_mixed_any_length_scale(dev, scale):
     ref = oracle.Treecode(pos, pos, 0.7, 4, 700, 700, hermite=True).potential(q[0])
     assert np.all(np.isfinite(phi))
     assert oracle.rel_l2(ref, phi) <= MIXED_L2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_hermite_threads_per_target(dev, precision):
+    pos, q = inputs.uniform_cube(20000, 194)
+    kw = dict(theta=0.7, degree=3, leaf_size=700, batch_size=700, precision=precision)
+    _, phi1 = _run(dev, pos, pos, q[0], **kw)
+    for tpt in (2, 4):
+        plan, phi = _run(dev, pos, pos, q[0], threads_per_target=tpt, **kw)
+        assert plan.stats()["threads_per_target"] == tpt
+        assert np.max(np.abs(phi - phi1)) <= 1e-12 * np.max(np.abs(phi1)), tpt

@@ -205,8 +205,8 @@ def test_threads_per_target_options():
     with pytest.raises(bltc.BLTCError):
         bltc.Plan(t, t, host=True, threads_per_target=2, method="cp")
     with pytest.raises(bltc.BLTCError):
-        bltc.Plan(t, t, host=True, threads_per_target=2, method="hermite")
-    with pytest.raises(bltc.BLTCError):
         bltc.Plan(t, t, host=True, threads_per_target=4, max_q=2)
     for tpt, want in ((0, 1), (1, 1), (2, 2), (4, 4)):
         assert bltc.Plan(t, t, host=True, threads_per_target=tpt).stats()["threads_per_target"] == want
+    assert bltc.Plan(t, t, host=True, threads_per_target=2,
+                     method="hermite").stats()["threads_per_target"] == 2
