@@ -221,8 +221,12 @@ def run_sweep(args, dev):
                 ref = oracle.Treecode(pos, pos, theta, deg, 2000, 2000).potential(
                     q[0], kernel=oracle.YUKAWA, kappa=0.5, sample=smp)
             for prec in ("fp64", "fp32_mixed"):
+                # threads per target: the library's autotuner at leaf size 2000
+                _, tpt, _ = bltc.autotune(t, t, candidates=(2000,), use_cache=False, full=True,
+                                          theta=theta, degree=deg, kernel="yukawa", kappa=0.5,
+                                          precision=prec)
                 plan = bltc.Plan(t, t, theta=theta, degree=deg, leaf_size=2000, batch_size=2000,
-                                 kernel="yukawa", kappa=0.5, precision=prec)
+                                 kernel="yukawa", kappa=0.5, precision=prec, threads_per_target=tpt)
                 phi = plan.execute(qd)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -231,7 +235,7 @@ def run_sweep(args, dev):
                 torch.cuda.synchronize()
                 ms = 1e3 * (time.perf_counter() - t0) / args.steps
                 row = {"theta": theta, "n": deg, "precision": prec, "ms": ms,
-                       "targets_per_s": n / (ms * 1e-3)}
+                       "targets_per_s": n / (ms * 1e-3), "threads_per_target": tpt}
                 if ref is not None:
                     row["E_par"] = rel_l2(ref, phi.cpu().numpy()[smp])
                 rows.append(row)
