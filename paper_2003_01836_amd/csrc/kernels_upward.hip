@@ -297,29 +297,73 @@ __device__ __forceinline__ void one_hot_row(double yv, const double* __restrict_
         row[k] = (k == hit) ? scale : 0.0;
 }
 
+// Hermite factors of one coordinate for the single-vector kernel: row[k] =
+// scale A_k(y), row[NP + k] = scale B_k(y), A_k = (1 - 2 c_k (y - s_k)) L_k^2,
+// B_k = (y - s_k) L_k^2 with L_k of eq. 4 from the same reciprocals; a
+// coordinate on a node (eq. 5) gives a one-hot A and zero B.
 template <int NP>
-constexpr int single_lds_doubles()
+__device__ __forceinline__ void hermite_row(double yv, const double* __restrict__ s,
+                                            const double* __restrict__ cs, double scale,
+                                            double* __restrict__ row)
 {
-    // factor rows [kTile][NP + 1] x 3, or two waves' partial tiles [CT][4][64]
-    return 3 * kTile * (NP + 1) > 2 * ((NP * NP + 15) / 16) * 256
-               ? 3 * kTile * (NP + 1)
-               : 2 * ((NP * NP + 15) / 16) * 256;
+    double a[NP];
+    bool tiny;
+    const double inv = 1.0 / factors_np<NP>(yv, s, a, tiny);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const double d = yv - s[k];
+        const double l = a[k] * inv;
+        const double l2 = l * l;
+        row[k] = scale * (__fma_rn(-2.0 * cs[k], d, 1.0) * l2);
+        row[NP + k] = scale * (d * l2);
+    }
+    if (tiny) {
+        // rare: the coordinate is on a node
+        one_hot_row<NP>(yv, s, scale, row);
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            row[NP + k] = 0.0;
+    }
 }
 
-template <int NP>
+// NF factors per dimension: NP Lagrange factors or 2 NP Hermite factors
+template <int NP, bool HERM>
+constexpr int single_nf()
+{
+    return HERM ? 2 * NP : NP;
+}
+
+template <int NP, bool HERM>
+constexpr int single_lds_doubles()
+{
+    // factor rows [kTile][NF + 1] x 3 (+ c_k of the Hermite factors), or two
+    // waves' partial tiles [CT][4][64]
+    constexpr int NF = single_nf<NP, HERM>();
+    constexpr int rows = 3 * kTile * (NF + 1) + (HERM ? 3 * NP : 0);
+    constexpr int parts = 2 * ((NF * NF + 15) / 16) * 256;
+    return rows > parts ? rows : parts;
+}
+
+// HERM: the Hermite charges (8 (n+1)^3 per cluster, blocked layout
+// (f1 NF + f2) NF + f3 with f = a (n+1) + k): rows f1 = 2 NP <= 16, columns
+// (f2, f3), factors normalized (q instead of q~).
+template <int NP, bool HERM>
 __global__ __launch_bounds__(256) void upward_single(
     const double4* __restrict__ src, const int32_t* __restrict__ chunk_slot,
     const int64_t* __restrict__ chunk_begin, const int64_t* __restrict__ chunk_count,
     const int64_t* __restrict__ chunk_dst, const double* __restrict__ slot_nodes,
     double* __restrict__ out)
 {
-    constexpr int NP2 = NP * NP;
-    constexpr int CT = (NP2 + 15) / 16;
-    constexpr int SP = NP + 1;                      // row stride: NP factors and a zero
-    __shared__ double lds[single_lds_doubles<NP>()];
-    double* __restrict__ A1 = lds;                  // [kTile][SP]  a_1 q~
+    constexpr int NF = single_nf<NP, HERM>();
+    constexpr int NF2 = NF * NF;
+    constexpr int CT = (NF2 + 15) / 16;
+    constexpr int SP = NF + 1;                      // row stride: NF factors and a zero
+    static_assert(NF <= 16, "one row tile");
+    __shared__ double lds[single_lds_doubles<NP, HERM>()];
+    double* __restrict__ A1 = lds;                  // [kTile][SP]  x factors times q~ (q)
     double* __restrict__ A2 = A1 + kTile * SP;      // [kTile][SP]
     double* __restrict__ A3 = A2 + kTile * SP;      // [kTile][SP]
+    double* __restrict__ SC = A3 + kTile * SP;      // [3][NP] c_k (Hermite)
 
     const int c = blockIdx.x;
     const int64_t slot = chunk_slot[c];
@@ -329,17 +373,30 @@ __global__ __launch_bounds__(256) void upward_single(
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double* __restrict__ sn = slot_nodes + slot * 3 * NP;   // wave-uniform
+    if constexpr (HERM) {
+        // c_k = L_k'(s_k) = sum_{j != k} 1 / (s_k - s_j) of dimension tid / NP
+        if (tid < 3 * NP) {
+            const double* sd = sn + (tid / NP) * NP;
+            const int k = tid % NP;
+            double cs = 0.0;
+            for (int j = 0; j < NP; ++j)
+                if (j != k)
+                    cs += 1.0 / (sd[k] - sd[j]);
+            SC[tid] = cs;
+        }
+        __syncthreads();
+    }
 
-    // this lane's operand offsets: row k1 = lane % 16, columns ct * 16 + lane % 16
+    // this lane's operand offsets: row f1 = lane % 16, columns ct * 16 + lane % 16
     // (rows and columns past the end point at the zero entry)
     const int k1 = lane & 15;
-    const int off1 = (lane >> 4) * SP + (k1 < NP ? k1 : NP);
+    const int off1 = (lane >> 4) * SP + (k1 < NF ? k1 : NF);
     int off2[CT], off3[CT];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
         const int cc = ct * 16 + (lane & 15);
-        off2[ct] = (lane >> 4) * SP + (cc < NP2 ? cc / NP : 0);
-        off3[ct] = (lane >> 4) * SP + (cc < NP2 ? cc - (cc / NP) * NP : NP);
+        off2[ct] = (lane >> 4) * SP + (cc < NF2 ? cc / NF : 0);
+        off3[ct] = (lane >> 4) * SP + (cc < NF2 ? cc - (cc / NF) * NF : NF);
     }
     d4v acc[CT];
 #pragma unroll
@@ -351,39 +408,48 @@ __global__ __launch_bounds__(256) void upward_single(
         // waves 0-1 and 2-3 take turns forming the factors (two SIMDs each)
         const int ft = tid - ((static_cast<int>(t0 / kTile) & 1) ? kTile : 0);
         if (ft >= 0 && ft < kTile) {
-            // z and y factors go to LDS as they are formed; x waits for q~.
-            // Rows past the chunk's end get q~ = 0 (their x row is zero).
-            double a[NP];
+            // Rows past the chunk's end get charge 0 (their x row is zero).
             double4 p = double4{0.0, 0.0, 0.0, 0.0};
             const bool live = ft < tn;
             if (live)
                 p = src[begin + t0 + ft];
-            bool tz, ty, tx;
-            const double Dz = factors_np<NP>(p.z, sn + 2 * NP, a, tz);
+            if constexpr (HERM) {
+                hermite_row<NP>(p.z, sn + 2 * NP, SC + 2 * NP, 1.0, A3 + ft * SP);
+                hermite_row<NP>(p.y, sn + NP, SC + NP, 1.0, A2 + ft * SP);
+                hermite_row<NP>(p.x, sn, SC, live ? p.w : 0.0, A1 + ft * SP);
+                A1[ft * SP + NF] = 0.0;
+                A2[ft * SP + NF] = 0.0;
+                A3[ft * SP + NF] = 0.0;
+            } else {
+                // z and y factors go to LDS as they are formed; x waits for q~
+                double a[NP];
+                bool tz, ty, tx;
+                const double Dz = factors_np<NP>(p.z, sn + 2 * NP, a, tz);
 #pragma unroll
-            for (int k = 0; k < NP; ++k)
-                A3[ft * SP + k] = a[k];
-            A3[ft * SP + NP] = 0.0;
-            const double Dy = factors_np<NP>(p.y, sn + NP, a, ty);
+                for (int k = 0; k < NP; ++k)
+                    A3[ft * SP + k] = a[k];
+                A3[ft * SP + NP] = 0.0;
+                const double Dy = factors_np<NP>(p.y, sn + NP, a, ty);
 #pragma unroll
-            for (int k = 0; k < NP; ++k)
-                A2[ft * SP + k] = a[k];
-            A2[ft * SP + NP] = 0.0;
-            const double Dx = factors_np<NP>(p.x, sn, a, tx);
-            const double D = (tx ? 1.0 : Dx) * (ty ? 1.0 : Dy) * (tz ? 1.0 : Dz);
-            const double qt = live ? p.w / D : 0.0;
+                for (int k = 0; k < NP; ++k)
+                    A2[ft * SP + k] = a[k];
+                A2[ft * SP + NP] = 0.0;
+                const double Dx = factors_np<NP>(p.x, sn, a, tx);
+                const double D = (tx ? 1.0 : Dx) * (ty ? 1.0 : Dy) * (tz ? 1.0 : Dz);
+                const double qt = live ? p.w / D : 0.0;
 #pragma unroll
-            for (int k = 0; k < NP; ++k)
-                A1[ft * SP + k] = a[k] * qt;
-            A1[ft * SP + NP] = 0.0;
-            if (tx || ty || tz) {
-                // rare: a coordinate on a node (eq. 5)
-                if (tz)
-                    one_hot_row<NP>(p.z, sn + 2 * NP, 1.0, A3 + ft * SP);
-                if (ty)
-                    one_hot_row<NP>(p.y, sn + NP, 1.0, A2 + ft * SP);
-                if (tx)
-                    one_hot_row<NP>(p.x, sn, qt, A1 + ft * SP);
+                for (int k = 0; k < NP; ++k)
+                    A1[ft * SP + k] = a[k] * qt;
+                A1[ft * SP + NP] = 0.0;
+                if (tx || ty || tz) {
+                    // rare: a coordinate on a node (eq. 5)
+                    if (tz)
+                        one_hot_row<NP>(p.z, sn + 2 * NP, 1.0, A3 + ft * SP);
+                    if (ty)
+                        one_hot_row<NP>(p.y, sn + NP, 1.0, A2 + ft * SP);
+                    if (tx)
+                        one_hot_row<NP>(p.x, sn, qt, A1 + ft * SP);
+                }
             }
         }
         __syncthreads();
@@ -426,32 +492,45 @@ __global__ __launch_bounds__(256) void upward_single(
     }
     __syncthreads();
     if (wave == 0) {
-        double* __restrict__ dst = out + chunk_dst[c] * static_cast<int64_t>(NP2) * NP;
+        double* __restrict__ dst = out + chunk_dst[c] * static_cast<int64_t>(NF2) * NF;
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
             const int cc = ct * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 4 * r + (lane >> 4);
-                if (row < NP && cc < NP2)
-                    dst[row * NP2 + cc] = acc[ct][r] + lds[(ct * 4 + r) * 64 + lane];
+                if (row < NF && cc < NF2)
+                    dst[row * NF2 + cc] = acc[ct][r] + lds[(ct * 4 + r) * 64 + lane];
             }
         }
     }
 }
 
-template <int NP>
+template <int NP, bool HERM = false>
 hipError_t launch_single_np(const DevicePlan& d, double* buf, hipStream_t s)
 {
-    hipLaunchKernelGGL(upward_single<NP>, dim3(static_cast<unsigned>(d.nchunks)), dim3(256), 0, s,
-                       d.src, d.chunk_slot, d.chunk_begin, d.chunk_count, d.chunk_dst,
+    hipLaunchKernelGGL((upward_single<NP, HERM>), dim3(static_cast<unsigned>(d.nchunks)), dim3(256),
+                       0, s, d.src, d.chunk_slot, d.chunk_begin, d.chunk_count, d.chunk_dst,
                        d.slot_nodes, buf);
     return hipGetLastError();
 }
 
-// n + 1 <= 16 nodes: the single-vector kernel; returns false for other degrees
+// n + 1 <= 16 nodes (Hermite: n + 1 <= 8): the single-vector kernel; returns
+// false for other degrees
 bool launch_single(const DevicePlan& d, double* buf, hipStream_t s, hipError_t* err)
 {
+    if (d.hermite) {
+        switch (d.degree + 1) {
+        case 2: *err = launch_single_np<2, true>(d, buf, s); return true;
+        case 3: *err = launch_single_np<3, true>(d, buf, s); return true;
+        case 4: *err = launch_single_np<4, true>(d, buf, s); return true;
+        case 5: *err = launch_single_np<5, true>(d, buf, s); return true;
+        case 6: *err = launch_single_np<6, true>(d, buf, s); return true;
+        case 7: *err = launch_single_np<7, true>(d, buf, s); return true;
+        case 8: *err = launch_single_np<8, true>(d, buf, s); return true;
+        default: return false;
+        }
+    }
     switch (d.degree + 1) {
     case 2: *err = launch_single_np<2>(d, buf, s); return true;
     case 3: *err = launch_single_np<3>(d, buf, s); return true;
@@ -612,7 +691,7 @@ hipError_t launch_upward_mfma(const DevicePlan& d, int32_t mw, double* buf, floa
     if (d.nchunks == 0)
         return hipSuccess;
     hipError_t e = hipSuccess;
-    if (mw == 1 && !d.hermite && launch_single(d, buf, s, &e)) {
+    if (mw == 1 && launch_single(d, buf, s, &e)) {
         if (e != hipSuccess)
             return e;
         return launch_upward_reduce(d, mw, buf, qhat32, s);
