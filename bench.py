@@ -41,7 +41,9 @@ FLOPS_HERMITE_POINT = 37
 # row term and the column term (+ 1 multiply-add, 2)
 FLOPS_MUTUAL_PAIR = 13
 
+MFMA_F64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 matrix peak
 KERNEL_SOURCES = {
+    "upward_single": ["kernels_upward.hip", "kernels.hpp"],
     "interact_mixed": ["kernels_mixed.hip", "device_mixed.hpp", "device_common.hpp", "kernels.hpp"],
     "interact_f64": ["kernels.hip", "device_common.hpp", "kernels.hpp"],
     "near_pairs_mixed": ["kernels_sym.hip", "device_common.hpp", "kernels.hpp"],
@@ -73,8 +75,12 @@ def counter_value(prefix, profile, kernel, degree, ker_id, tpt=1):
     for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2003_01836_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    want = (f"{prefix} {kernel}<{degree}, {ker_id}> " if kernel.startswith("interact")
-            else f"{prefix} {kernel}<{ker_id}> ")
+    if kernel == "upward_single":
+        want = f"{prefix} {kernel}<{degree + 1}, false> "
+    elif kernel.startswith("interact"):
+        want = f"{prefix} {kernel}<{degree}, {ker_id}> "
+    else:
+        want = f"{prefix} {kernel}<{ker_id}> "
     with open(path) as fh:
         for line in fh:
             if line.startswith(want):
@@ -105,10 +111,28 @@ def issue_model(kernel, degree, ker_id, trans_per_eval, evals, ms, tpt=1):
                          ker_id, tpt)
     if valu is None or not kernel.endswith("mixed"):
         return None
-    trans = trans_per_eval * evals / 64.0
+    # the counted transcendental instructions where a run took them, else the model
+    trans = counter_value("trans_insts", "interact_uniform-1M_valu_counters.md", kernel, degree,
+                          ker_id, tpt)
+    if trans is None:
+        trans = trans_per_eval * evals / 64.0
     cycles = (valu - trans) * CYCLES_FMA32 + trans * CYCLES_TRANS32
     t_min = cycles / SIMDS / CLOCK_HZ * 1e3
     return {"valu_insts": valu, "trans_insts": trans, "t_min_ms": t_min, "frac": t_min / ms}
+
+
+def upward_roofline(degree, macs, ms):
+    """The upward pass of one charge vector against the FP64 matrix-core peak:
+    algorithmic flops 2 * sum_C N_C (n+1)^3 over the phase time (the kernel and
+    the chunk-sum reduction), and the matrix-core busy time per SIMD from the
+    committed counter summary (None when the kernel changed since)."""
+    achieved = 2.0 * macs / (ms * 1e-3) / 1e12
+    busy = counter_value("mfma_busy_cycles", "upward_uniform-1M_mfma_counters.md",
+                         "upward_single", degree, 0)
+    return {"kernel": f"upward_single<{degree + 1}, false>", "bound": "mfma",
+            "macs": macs, "ms": ms, "achieved": achieved, "peak": MFMA_F64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / MFMA_F64_PEAK_TFLOPS,
+            "mfma_busy_frac": None if busy is None else busy / SIMDS / (ms * 1e-3 * CLOCK_HZ)}
 
 
 def cpu_model():
@@ -725,7 +749,9 @@ def main():
                      "issue": kd["issue"],
                      "interaction_kernels": kernels,
                      "interaction_phase": {"achieved": phase_achieved, "frac": phase_achieved / peak,
-                                           "ms": r["phases"]["interact"]}},
+                                           "ms": r["phases"]["interact"]},
+                     "upward": upward_roofline(w["degree"], st["upward_terms"],
+                                               r["phases"]["upward"])},
         "cpu_baseline": cpu,
         "paths": {p: {"targets_per_s": n / (v["ms"] * 1e-3), "ms_per_step": v["ms"],
                       "threads_per_target": v["tpt"],
