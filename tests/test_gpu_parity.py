@@ -471,6 +471,37 @@ def test_threads_per_target(dev, precision, same):
         _close(ref, phi)
 
 
+@pytest.mark.parametrize("tpt", [2, 4])
+def test_threads_per_target_edge_cases(dev, tpt):
+    # one target; batches with fewer list entries than pieces (empty pieces);
+    # theta = 0 (all direct); a Plummer sphere in FP32-mixed
+    g = np.random.default_rng(162)
+    one = g.uniform(-1, 1, (1, 3))
+    src = g.uniform(-1, 1, (300, 3))
+    q = g.uniform(-1, 1, 300)
+    _, phi = _run_plan(dev, one, src, q, theta=0.7, degree=3, leaf_size=40, batch_size=40,
+                       threads_per_target=tpt)
+    _close(oracle.direct(one, src, q), phi, rel_max=1e-6, rel_l2=1e-6)
+    _, phi1 = _run_plan(dev, one, src, q, theta=0.7, degree=3, leaf_size=40, batch_size=40)
+    assert np.max(np.abs(phi - phi1)) <= 1e-12 * np.max(np.abs(phi1))
+    small = g.uniform(-1, 1, (257, 3))
+    qs = g.uniform(-1, 1, 257)
+    for theta in (0.0, 0.9):
+        _, a = _run_plan(dev, small, small, qs, theta=theta, degree=2, leaf_size=9, batch_size=9,
+                         threads_per_target=tpt)
+        _, b = _run_plan(dev, small, small, qs, theta=theta, degree=2, leaf_size=9, batch_size=9)
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b)), theta
+    pos, qp = inputs.plummer_sphere(30000, 163)
+    kw = dict(theta=0.7, degree=6, leaf_size=400, batch_size=400, precision="fp32_mixed",
+              kernel="yukawa", kappa=0.5)
+    _, a = _run_plan(dev, pos, pos, qp[0], threads_per_target=tpt, **kw)
+    _, b = _run_plan(dev, pos, pos, qp[0], **kw)
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+    ref = oracle.Treecode(pos, pos, 0.7, 6, 400, 400).potential(qp[0], kernel=oracle.YUKAWA,
+                                                                 kappa=0.5)
+    assert oracle.rel_l2(ref, a) <= MIXED_REL_L2
+
+
 def test_threads_per_target_autotuned(dev):
     import paper_2003_01836_amd as bltc
     pos, q = inputs.uniform_cube(4000, 161)
