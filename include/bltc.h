@@ -50,7 +50,7 @@ typedef enum {
     BLTC_EINVAL = -1,        /* invalid argument (message says which)              */
     BLTC_ENOMEM = -2,        /* host or device allocation failed                     */
     BLTC_EHIP = -3,          /* a HIP runtime call failed                            */
-    BLTC_EUNSUPPORTED = -4,  /* valid request this build does not support            */
+    BLTC_EUNSUPPORTED = -4,  /* valid request the library does not support           */
     BLTC_EINTERNAL = -5      /* internal consistency check failed                    */
 } bltc_status;
 
