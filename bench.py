@@ -214,12 +214,23 @@ def run_batched(args, dev):
             got = outs[k][:2].cpu().numpy()[:, smp]
             errs.append(max(rel_l2(ref[i], got[i]) for i in range(2)))
     info = batch.info()
+    # a kernel value G(x, y) (VALU, 11 flops) serves the 16 vectors through the
+    # matrix cores (16 multiply-adds); priced over the whole step
+    values = sum(p.stats()["far_evals"] + p.stats()["near_evals"] for p in plans)
+    t_s = ms * 1e-3
+    peak = FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+    mpeak = MFMA_F64_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+    roof = {"bound": "alu", "achieved": values * FLOPS_COULOMB / t_s / 1e12, "peak": peak,
+            "unit": "TFLOP/s", "frac": values * FLOPS_COULOMB / t_s / 1e12 / peak,
+            "traffic": None, "kernel": "interact_queue (whole step)", "kernel_values": values,
+            "contraction": {"bound": "mfma", "achieved": values * 32 / t_s / 1e12,
+                            "peak": mpeak, "frac": values * 32 / t_s / 1e12 / mpeak}}
     return {"workload": "batched-64x16", "precision": prec, "systems": 64, "particles": total,
             "vectors": 16, "ms_per_step": ms, "targets_per_s": total / (ms * 1e-3),
             "target_vectors_per_s": 16 * total / (ms * 1e-3), "autotune_s": t_tune,
             "leaf_sizes": sorted(set(leaves)), "units": info["units"],
             "workgroups": info["workgroups"], "graph_captures": info["graph_captures"],
-            "E_par_max_sampled": max(errs) if errs else None}
+            "roofline": roof, "E_par_max_sampled": max(errs) if errs else None}
 
 
 def run_sweep(args, dev):
