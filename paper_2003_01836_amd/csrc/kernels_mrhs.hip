@@ -31,6 +31,35 @@ constexpr int kMixedFlushSteps = 32;   // FP32 MFMA partial sums cover <= 128 so
 
 constexpr double kTauRel = kMixedTauRel;
 
+// Steps of 4 sources whose coordinates and charges are in flight ahead of the
+// step being evaluated (a ring of registers per lane).  The FP32 path gains
+// from a deep ring; the FP64 path is bound by its VALU and MFMA work, and more
+// registers would cost it a wave per SIMD.
+constexpr int kAheadF64 = 1;
+constexpr int kAheadMixed = 3;
+// FP32 partial sums are moved to FP64 after this many rounds of kAheadMixed steps
+constexpr int kFlushRounds = kMixedFlushSteps / kAheadMixed;
+
+// Loads and stores through the global address space: the descriptor's
+// pointers are read from memory, so the compiler cannot prove that they are
+// global, and a flat access in flight makes every wait cover all loads.
+// Coordinates are loaded as 3-vectors: a dead 4th register would be reused at
+// once and force a wait for the load.
+typedef float f3v __attribute__((ext_vector_type(3)));
+typedef double d3v __attribute__((ext_vector_type(3)));
+
+template <typename T>
+__device__ __forceinline__ T gload(const void* p)
+{
+    return *(const __attribute__((address_space(1))) T*)(p);
+}
+
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)(p) = v;
+}
+
 // ---------------------------------------------------------------------------
 // FP64: G in FP64 on the VALU, contraction on v_mfma_f64_16x16x4f64.
 // ---------------------------------------------------------------------------
@@ -53,11 +82,11 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
     const int64_t phi_ld = d.phi_ld;
     const int32_t m_count = d.mc;
     const KernelArg kappa{d.kc.kappa, d.kc.delta2, exp_tab};
-    const int b = d.group_batch[g];
+    const int b = gload<int32_t>(d.group_batch + g);
     if (b < 0)
         return;
-    const int64_t first = d.group_first[g];
-    const int64_t end = d.batch_end[b];
+    const int64_t first = gload<int64_t>(d.group_first + g);
+    const int64_t end = gload<int64_t>(d.batch_end + b);
     const int64_t wave_first = first + (threadIdx.x & ~63);
     if (wave_first >= end)
         return;
@@ -70,7 +99,7 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
     for (int t = 0; t < 4; ++t) {
         int64_t i = wave_first + 16 * t + row;
         i = i < end ? i : end - 1;
-        const double4 v = tgt[i];
+        const d3v v = gload<d3v>(tgt + i);
         tx[t] = v.x;
         ty[t] = v.y;
         tz[t] = v.z;
@@ -81,51 +110,78 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
         acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
 
     const int P = np * np * np;
-    const int f_end = far_off[b + 1];
-    for (int f = far_off[b]; f < f_end; ++f) {
-        const int64_t slot = far_slot[f];
+    const int f_end = gload<int32_t>(far_off + b + 1);
+    for (int f = gload<int32_t>(far_off + b); f < f_end; ++f) {
+        const int64_t slot = gload<int32_t>(far_slot + f);
         const double4* __restrict__ px = proxies + slot * P;
         const double* __restrict__ qh = qhat16 + slot * static_cast<int64_t>(P) * kRhs;
-        // software pipeline: the next step's proxy point and charge are in flight
-        int kk = col < P ? col : P - 1;
-        double4 pn = px[kk];
-        double qn = qh[static_cast<int64_t>(kk) * kRhs + row];
-        for (int k0 = 0; k0 < P; k0 += 4) {
-            const double4 p = pn;
-            const double bq = (k0 + col < P) ? qn : 0.0;
-            kk = k0 + 4 + col;
-            kk = kk < P ? kk : P - 1;
-            pn = px[kk];
-            qn = qh[static_cast<int64_t>(kk) * kRhs + row];
+        // software pipeline: the proxy points and charges of kAheadF64 steps
+        // are in flight; ring slot u serves steps u, u + kAheadF64, ... and is
+        // reloaded once its step is evaluated.  Whole rounds of steps are
+        // evaluated; steps past the end carry zero charges.
+        d3v pn[kAheadF64];
+        double qn[kAheadF64];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const double dx = tx[t] - p.x, dy = ty[t] - p.y, dz = tz[t] - p.z;
-                const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-                const double gv = green_far_f64<KER>(r2, kappa);
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
+        for (int a = 0; a < kAheadF64; ++a) {
+            const int kk = 4 * a + col < P ? 4 * a + col : P - 1;
+            pn[a] = gload<d3v>(px + kk);
+            qn[a] = gload<double>(qh + static_cast<int64_t>(kk) * kRhs + row);
+            // slot 0 first: the loop's first wait then leaves the other slots in flight
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int k1 = 0; k1 < P; k1 += 4 * kAheadF64) {
+#pragma unroll
+            for (int u = 0; u < kAheadF64; ++u) {
+                const int k0 = k1 + 4 * u;
+                const double bq = (k0 + col < P) ? qn[u] : 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double dx = tx[t] - pn[u].x, dy = ty[t] - pn[u].y, dz = tz[t] - pn[u].z;
+                    const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+                    const double gv = green_far_f64<KER>(r2, kappa);
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
+                }
+                int kk = k0 + 4 * kAheadF64 + col;
+                kk = kk < P ? kk : P - 1;
+                pn[u] = gload<d3v>(px + kk);
+                qn[u] = gload<double>(qh + static_cast<int64_t>(kk) * kRhs + row);
+                // keep the step's order: its reload is issued after its MFMAs
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
-    const int n_end = near_off[b + 1];
-    for (int e = near_off[b]; e < n_end; ++e) {
-        const int64_t nb = near_begin[e];
-        const int32_t cnt = static_cast<int32_t>(near_count[e]);
-        int64_t jj = nb + (col < cnt ? col : cnt - 1);
-        double4 pn = src[jj];
-        double qn = qm[jj * kRhs + row];
-        for (int32_t j0 = 0; j0 < cnt; j0 += 4) {
-            const double4 p = pn;
-            const double bq = (j0 + col < cnt) ? qn : 0.0;
-            const int32_t jn = j0 + 4 + col;
-            jj = nb + (jn < cnt ? jn : cnt - 1);
-            pn = src[jj];
-            qn = qm[jj * kRhs + row];
+    const int n_end = gload<int32_t>(near_off + b + 1);
+    for (int e = gload<int32_t>(near_off + b); e < n_end; ++e) {
+        const int64_t nb = gload<int64_t>(near_begin + e);
+        const int32_t cnt = static_cast<int32_t>(gload<int64_t>(near_count + e));
+        d3v pn[kAheadF64];
+        double qn[kAheadF64];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const double dx = tx[t] - p.x, dy = ty[t] - p.y, dz = tz[t] - p.z;
-                const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-                const double gv = green_near_f64<KER>(r2, kappa);
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
+        for (int a = 0; a < kAheadF64; ++a) {
+            const int64_t jj = nb + (4 * a + col < cnt ? 4 * a + col : cnt - 1);
+            pn[a] = gload<d3v>(src + jj);
+            qn[a] = gload<double>(qm + jj * kRhs + row);
+            // slot 0 first: the loop's first wait then leaves the other slots in flight
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int32_t j1 = 0; j1 < cnt; j1 += 4 * kAheadF64) {
+#pragma unroll
+            for (int u = 0; u < kAheadF64; ++u) {
+                const int32_t j0 = j1 + 4 * u;
+                const double bq = (j0 + col < cnt) ? qn[u] : 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double dx = tx[t] - pn[u].x, dy = ty[t] - pn[u].y, dz = tz[t] - pn[u].z;
+                    const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+                    const double gv = green_near_f64<KER>(r2, kappa);
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
+                }
+                const int32_t jn = j0 + 4 * kAheadF64 + col;
+                const int64_t jj = nb + (jn < cnt ? jn : cnt - 1);
+                pn[u] = gload<d3v>(src + jj);
+                qn[u] = gload<double>(qm + jj * kRhs + row);
+                // keep the step's order: its reload is issued after its MFMAs
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
@@ -136,7 +192,7 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = wave_first + 16 * t + 4 * r + col;
                 if (i < end)
-                    phi[row * phi_ld + tgt_orig[i]] = acc[t][r];
+                    gstore(phi + row * phi_ld + gload<int64_t>(tgt_orig + i), acc[t][r]);
             }
     }
 }
@@ -181,11 +237,11 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
     const int64_t phi_ld = d.phi_ld;
     const int32_t m_count = d.mc;
     const KernelArg kappa{d.kc.kappa, d.kc.delta2, exp_tab};
-    const int b = d.group_batch[g];
+    const int b = gload<int32_t>(d.group_batch + g);
     if (b < 0)
         return;
-    const int64_t first = d.group_first[g];
-    const int64_t end = d.batch_end[b];
+    const int64_t first = gload<int64_t>(d.group_first + g);
+    const int64_t end = gload<int64_t>(d.batch_end + b);
     const int64_t wave_first = first + (threadIdx.x & ~63);
     if (wave_first >= end)
         return;
@@ -199,7 +255,7 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
     for (int t = 0; t < 4; ++t) {
         int64_t i = wave_first + 16 * t + row;
         i = i < end ? i : end - 1;
-        const double4 v = tgt[i];
+        const d3v v = gload<d3v>(tgt + i);
         tx[t] = v.x;
         ty[t] = v.y;
         tz[t] = v.z;
@@ -215,10 +271,10 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
     }
 
     const int P = np * np * np;
-    const int f_end = far_off[b + 1];
-    for (int f = far_off[b]; f < f_end; ++f) {
-        const int64_t slot = far_slot[f];
-        const double4 ci = node_info[slot_cluster[slot]];
+    const int f_end = gload<int32_t>(far_off + b + 1);
+    for (int f = gload<int32_t>(far_off + b); f < f_end; ++f) {
+        const int64_t slot = gload<int32_t>(far_slot + f);
+        const d4v ci = gload<d4v>(node_info + gload<int32_t>(slot_cluster + slot));
         // targets relative to the cluster center (proxy points are stored so)
         float ux[4], uy[4], uz[4];
 #pragma unroll
@@ -229,36 +285,48 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
         }
         const float4* __restrict__ px = proxies32 + slot * P;
         const float* __restrict__ qh = qhat16 + slot * static_cast<int64_t>(P) * kRhs;
-        int kk = col < P ? col : P - 1;
-        float4 pn = px[kk];
-        float qn = qh[static_cast<int64_t>(kk) * kRhs + row];
-        int steps = 0;
-        for (int k0 = 0; k0 < P; k0 += 4) {
-            const float4 p = pn;
-            const float bq = (k0 + col < P) ? qn : 0.0f;
-            kk = k0 + 4 + col;
-            kk = kk < P ? kk : P - 1;
-            pn = px[kk];
-            qn = qh[static_cast<int64_t>(kk) * kRhs + row];
+        f3v pn[kAheadMixed];
+        float qn[kAheadMixed];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const float dx = ux[t] - p.x, dy = uy[t] - p.y, dz = uz[t] - p.z;
-                const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-                const float gv = green_f32<KER>(r2, nk);
-                part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, bq, part[t], 0, 0, 0);
+        for (int a = 0; a < kAheadMixed; ++a) {
+            const int kk = 4 * a + col < P ? 4 * a + col : P - 1;
+            pn[a] = gload<f3v>(px + kk);
+            qn[a] = gload<float>(qh + static_cast<int64_t>(kk) * kRhs + row);
+            // slot 0 first: the loop's first wait then leaves the other slots in flight
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        int rounds = 0;
+        for (int k1 = 0; k1 < P; k1 += 4 * kAheadMixed) {
+#pragma unroll
+            for (int u = 0; u < kAheadMixed; ++u) {
+                const int k0 = k1 + 4 * u;
+                const float bq = (k0 + col < P) ? qn[u] : 0.0f;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float dx = ux[t] - pn[u].x, dy = uy[t] - pn[u].y, dz = uz[t] - pn[u].z;
+                    const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+                    const float gv = green_f32<KER>(r2, nk);
+                    part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, bq, part[t], 0, 0, 0);
+                }
+                int kk = k0 + 4 * kAheadMixed + col;
+                kk = kk < P ? kk : P - 1;
+                pn[u] = gload<f3v>(px + kk);
+                qn[u] = gload<float>(qh + static_cast<int64_t>(kk) * kRhs + row);
+                // keep the step's order: its reload is issued after its MFMAs
+                __builtin_amdgcn_sched_barrier(0);
             }
-            if (++steps == kMixedFlushSteps) {
+            if (++rounds == kFlushRounds) {
                 flush_f32(part, acc);
-                steps = 0;
+                rounds = 0;
             }
         }
         flush_f32(part, acc);
     }
 
-    const double4 bi = batch_info[b];
-    const int n_end = near_off[b + 1];
-    for (int e = near_off[b]; e < n_end; ++e) {
-        const double4 li = node_info[near_leaf[e]];
+    const d4v bi = gload<d4v>(batch_info + b);
+    const int n_end = gload<int32_t>(near_off + b + 1);
+    for (int e = gload<int32_t>(near_off + b); e < n_end; ++e) {
+        const d4v li = gload<d4v>(node_info + gload<int32_t>(near_leaf + e));
         const double ddx = bi.x - li.x, ddy = bi.y - li.y, ddz = bi.z - li.z;
         const double extent = sqrt(ddx * ddx + ddy * ddy + ddz * ddz) + bi.w + 2.0 * li.w;
         const double tau = kTauRel * extent;
@@ -270,44 +338,55 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
             uy[t] = static_cast<float>(ty[t] - li.y);
             uz[t] = static_cast<float>(tz[t] - li.z);
         }
-        const int64_t nb = near_begin[e];
-        const int32_t cnt = static_cast<int32_t>(near_count[e]);
-        int64_t jj = nb + (col < cnt ? col : cnt - 1);
-        float4 pn = src32[jj];
-        float qn = qm32[jj * kRhs + row];
-        int steps = 0;
-        for (int32_t j0 = 0; j0 < cnt; j0 += 4) {
-            const float4 p = pn;
-            const float bq = (j0 + col < cnt) ? qn : 0.0f;
-            const int64_t jc = jj;
-            const int32_t jn = j0 + 4 + col;
-            jj = nb + (jn < cnt ? jn : cnt - 1);
-            pn = src32[jj];
-            qn = qm32[jj * kRhs + row];
-            float gv[4], r2v[4];
+        const int64_t nb = gload<int64_t>(near_begin + e);
+        const int32_t cnt = static_cast<int32_t>(gload<int64_t>(near_count + e));
+        f3v pn[kAheadMixed];
+        float qn[kAheadMixed];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const float dx = ux[t] - p.x, dy = uy[t] - p.y, dz = uz[t] - p.z;
-                r2v[t] = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
-                gv[t] = green_f32<KER>(r2v[t], nk);
-            }
-            if (fminf(fminf(r2v[0], r2v[1]), fminf(r2v[2], r2v[3])) <= tau2) {
-                // close pairs: the kernel value from the exact coordinates, in FP64
-                const double4 p64 = src[jc];
+        for (int a = 0; a < kAheadMixed; ++a) {
+            const int64_t jj = nb + (4 * a + col < cnt ? 4 * a + col : cnt - 1);
+            pn[a] = gload<f3v>(src32 + jj);
+            qn[a] = gload<float>(qm32 + jj * kRhs + row);
+            // slot 0 first: the loop's first wait then leaves the other slots in flight
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        int rounds = 0;
+        for (int32_t j1 = 0; j1 < cnt; j1 += 4 * kAheadMixed) {
+#pragma unroll
+            for (int u = 0; u < kAheadMixed; ++u) {
+                const int32_t j0 = j1 + 4 * u;
+                const float bq = (j0 + col < cnt) ? qn[u] : 0.0f;
+                float gv[4], r2v[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float dx = ux[t] - pn[u].x, dy = uy[t] - pn[u].y, dz = uz[t] - pn[u].z;
+                    r2v[t] = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+                    gv[t] = green_f32<KER>(r2v[t], nk);
+                }
+                if (fminf(fminf(r2v[0], r2v[1]), fminf(r2v[2], r2v[3])) <= tau2) {
+                    // close pairs: the kernel value from the exact coordinates, in FP64
+                    const d3v p64 = gload<d3v>(src + nb + (j0 + col < cnt ? j0 + col : cnt - 1));
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (r2v[t] <= tau2) {
+                            const double dx = tx[t] - p64.x, dy = ty[t] - p64.y, dz = tz[t] - p64.z;
+                            const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+                            gv[t] = static_cast<float>(green_near_f64<KER>(r2, kappa));
+                        }
+                }
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    if (r2v[t] <= tau2) {
-                        const double dx = tx[t] - p64.x, dy = ty[t] - p64.y, dz = tz[t] - p64.z;
-                        const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-                        gv[t] = static_cast<float>(green_near_f64<KER>(r2, kappa));
-                    }
+                    part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t], bq, part[t], 0, 0, 0);
+                const int32_t jn = j0 + 4 * kAheadMixed + col;
+                const int64_t jj = nb + (jn < cnt ? jn : cnt - 1);
+                pn[u] = gload<f3v>(src32 + jj);
+                qn[u] = gload<float>(qm32 + jj * kRhs + row);
+                // keep the step's order: its reload is issued after its MFMAs
+                __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t], bq, part[t], 0, 0, 0);
-            if (++steps == kMixedFlushSteps) {
+            if (++rounds == kFlushRounds) {
                 flush_f32(part, acc);
-                steps = 0;
+                rounds = 0;
             }
         }
         flush_f32(part, acc);
@@ -319,7 +398,7 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = wave_first + 16 * t + 4 * col + r;
                 if (i < end)
-                    phi[row * phi_ld + tgt_orig[i]] = acc[t][r];
+                    gstore(phi + row * phi_ld + gload<int64_t>(tgt_orig + i), acc[t][r]);
             }
     }
 }
