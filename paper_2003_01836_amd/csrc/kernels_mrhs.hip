@@ -54,6 +54,29 @@ __device__ __forceinline__ T gload(const void* p)
     return *(const __attribute__((address_space(1))) T*)(p);
 }
 
+// values the whole wave shares, moved to scalar registers (vector loads of
+// list entries are not known to be uniform)
+__device__ __forceinline__ int32_t uniform32(int32_t v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint64_t u = static_cast<uint64_t>(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// the same from a uniform base and a 32-bit byte offset (the SGPR-base form
+// of the load: no 64-bit address arithmetic per lane)
+template <typename T>
+__device__ __forceinline__ T gload_at(const void* base, uint32_t byte_off)
+{
+    return gload<T>(static_cast<const char*>(base) + byte_off);
+}
+
 template <typename T>
 __device__ __forceinline__ void gstore(T* p, T v)
 {
@@ -124,8 +147,8 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
 #pragma unroll
         for (int a = 0; a < kAheadF64; ++a) {
             const int kk = 4 * a + col < P ? 4 * a + col : P - 1;
-            pn[a] = gload<d3v>(px + kk);
-            qn[a] = gload<double>(qh + static_cast<int64_t>(kk) * kRhs + row);
+            pn[a] = gload_at<d3v>(px, static_cast<uint32_t>(kk) * 32u);
+            qn[a] = gload_at<double>(qh, (static_cast<uint32_t>(kk) * kRhs + row) * 8u);
             // slot 0 first: the loop's first wait then leaves the other slots in flight
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -143,8 +166,8 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
                 }
                 int kk = k0 + 4 * kAheadF64 + col;
                 kk = kk < P ? kk : P - 1;
-                pn[u] = gload<d3v>(px + kk);
-                qn[u] = gload<double>(qh + static_cast<int64_t>(kk) * kRhs + row);
+                pn[u] = gload_at<d3v>(px, static_cast<uint32_t>(kk) * 32u);
+                qn[u] = gload_at<double>(qh, (static_cast<uint32_t>(kk) * kRhs + row) * 8u);
                 // keep the step's order: its reload is issued after its MFMAs
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -152,15 +175,17 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
     }
     const int n_end = gload<int32_t>(near_off + b + 1);
     for (int e = gload<int32_t>(near_off + b); e < n_end; ++e) {
-        const int64_t nb = gload<int64_t>(near_begin + e);
-        const int32_t cnt = static_cast<int32_t>(gload<int64_t>(near_count + e));
+        const int64_t nb = uniform64(gload<int64_t>(near_begin + e));
+        const int32_t cnt = uniform32(static_cast<int32_t>(gload<int64_t>(near_count + e)));
+        const double4* sp = src + nb;
+        const double* qp = qm + nb * kRhs;
         d3v pn[kAheadF64];
         double qn[kAheadF64];
 #pragma unroll
         for (int a = 0; a < kAheadF64; ++a) {
-            const int64_t jj = nb + (4 * a + col < cnt ? 4 * a + col : cnt - 1);
-            pn[a] = gload<d3v>(src + jj);
-            qn[a] = gload<double>(qm + jj * kRhs + row);
+            const uint32_t jj = 4 * a + col < cnt ? 4 * a + col : cnt - 1;
+            pn[a] = gload_at<d3v>(sp, jj * 32u);
+            qn[a] = gload_at<double>(qp, (jj * kRhs + row) * 8u);
             // slot 0 first: the loop's first wait then leaves the other slots in flight
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -177,9 +202,9 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
                     acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
                 }
                 const int32_t jn = j0 + 4 * kAheadF64 + col;
-                const int64_t jj = nb + (jn < cnt ? jn : cnt - 1);
-                pn[u] = gload<d3v>(src + jj);
-                qn[u] = gload<double>(qm + jj * kRhs + row);
+                const uint32_t jj = jn < cnt ? jn : cnt - 1;
+                pn[u] = gload_at<d3v>(sp, jj * 32u);
+                qn[u] = gload_at<double>(qp, (jj * kRhs + row) * 8u);
                 // keep the step's order: its reload is issued after its MFMAs
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -290,8 +315,8 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
 #pragma unroll
         for (int a = 0; a < kAheadMixed; ++a) {
             const int kk = 4 * a + col < P ? 4 * a + col : P - 1;
-            pn[a] = gload<f3v>(px + kk);
-            qn[a] = gload<float>(qh + static_cast<int64_t>(kk) * kRhs + row);
+            pn[a] = gload_at<f3v>(px, static_cast<uint32_t>(kk) * 16u);
+            qn[a] = gload_at<float>(qh, (static_cast<uint32_t>(kk) * kRhs + row) * 4u);
             // slot 0 first: the loop's first wait then leaves the other slots in flight
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -310,8 +335,8 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
                 }
                 int kk = k0 + 4 * kAheadMixed + col;
                 kk = kk < P ? kk : P - 1;
-                pn[u] = gload<f3v>(px + kk);
-                qn[u] = gload<float>(qh + static_cast<int64_t>(kk) * kRhs + row);
+                pn[u] = gload_at<f3v>(px, static_cast<uint32_t>(kk) * 16u);
+                qn[u] = gload_at<float>(qh, (static_cast<uint32_t>(kk) * kRhs + row) * 4u);
                 // keep the step's order: its reload is issued after its MFMAs
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -338,15 +363,17 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
             uy[t] = static_cast<float>(ty[t] - li.y);
             uz[t] = static_cast<float>(tz[t] - li.z);
         }
-        const int64_t nb = gload<int64_t>(near_begin + e);
-        const int32_t cnt = static_cast<int32_t>(gload<int64_t>(near_count + e));
+        const int64_t nb = uniform64(gload<int64_t>(near_begin + e));
+        const int32_t cnt = uniform32(static_cast<int32_t>(gload<int64_t>(near_count + e)));
+        const float4* sp = src32 + nb;
+        const float* qp = qm32 + nb * kRhs;
         f3v pn[kAheadMixed];
         float qn[kAheadMixed];
 #pragma unroll
         for (int a = 0; a < kAheadMixed; ++a) {
-            const int64_t jj = nb + (4 * a + col < cnt ? 4 * a + col : cnt - 1);
-            pn[a] = gload<f3v>(src32 + jj);
-            qn[a] = gload<float>(qm32 + jj * kRhs + row);
+            const uint32_t jj = 4 * a + col < cnt ? 4 * a + col : cnt - 1;
+            pn[a] = gload_at<f3v>(sp, jj * 16u);
+            qn[a] = gload_at<float>(qp, (jj * kRhs + row) * 4u);
             // slot 0 first: the loop's first wait then leaves the other slots in flight
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -378,9 +405,9 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
                 for (int t = 0; t < 4; ++t)
                     part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[t], bq, part[t], 0, 0, 0);
                 const int32_t jn = j0 + 4 * kAheadMixed + col;
-                const int64_t jj = nb + (jn < cnt ? jn : cnt - 1);
-                pn[u] = gload<f3v>(src32 + jj);
-                qn[u] = gload<float>(qm32 + jj * kRhs + row);
+                const uint32_t jj = jn < cnt ? jn : cnt - 1;
+                pn[u] = gload_at<f3v>(sp, jj * 16u);
+                qn[u] = gload_at<float>(qp, (jj * kRhs + row) * 4u);
                 // keep the step's order: its reload is issued after its MFMAs
                 __builtin_amdgcn_sched_barrier(0);
             }
