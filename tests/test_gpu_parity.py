@@ -369,6 +369,41 @@ def test_mixed_many_charge_vectors(dev, m, kernel, kappa):
         assert oracle.rel_l2(ref[i], phi[i]) <= MIXED_REL_L2
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("degree,leaf", [(1, 3), (1, 13), (2, 7), (3, 25)])
+def test_many_vectors_short_lists(dev, precision, degree, leaf):
+    """Source lists and proxy grids (8, 27, 64 points) shorter than a round of
+    the multi-vector kernels' prefetch (3 steps of 4 sources on the FP32 path),
+    through one plan and through a work-queue batch of two systems: the
+    padded steps must carry zero charges."""
+    import paper_2003_01836_amd as bltc
+    systems = [inputs.uniform_cube(n, 140 + leaf + n, m=16) for n in (3001, 1207)]
+    refs = [oracle.Treecode(pos, pos, 0.7, degree, leaf, leaf).potential(q) for pos, q in systems]
+
+    def check(ref, got):
+        for i in range(16):
+            if precision == "fp64":
+                _close(ref[i], got[i])
+            else:
+                assert oracle.rel_l2(ref[i], got[i]) <= MIXED_REL_L2
+
+    pos, q = systems[0]
+    _, phi = _run_plan(dev, pos, pos, q, theta=0.7, degree=degree, leaf_size=leaf,
+                       batch_size=leaf, precision=precision)
+    check(refs[0], phi)
+    plans, qd, outs = [], [], []
+    for pos, q in systems:
+        t = _dev_soa(pos, dev)
+        plans.append(bltc.Plan(t, t, theta=0.7, degree=degree, leaf_size=leaf, batch_size=leaf,
+                               max_q=16, precision=precision))
+        qd.append(torch.from_numpy(np.ascontiguousarray(q)).to(dev))
+        outs.append(torch.full((16, pos.shape[0]), float("nan"), dtype=torch.float64, device=dev))
+    bltc.Batch(plans).execute(qd, outs)
+    torch.cuda.synchronize()
+    for ref, o in zip(refs, outs):
+        check(ref, o.cpu().numpy())
+
+
 def test_many_vectors_plummer_distinct_targets(dev):
     g = np.random.default_rng(29)
     src, q = inputs.plummer_sphere(15000, 131, m=16)
