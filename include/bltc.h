@@ -124,14 +124,21 @@ typedef struct {
     int32_t leaf_size;           /* N_L >= 1: leaf capacity of the interpolated side's  */
                                  /* cluster tree (sources; targets for CLUSTER_PARTICLE) */
     int32_t batch_size;          /* N_B >= 1: capacity of the batches of the other side */
-    int32_t threads_per_target;  /* 0 or 1: one lane per target; 2 or 4: each batch's   */
+                                 /* leaf_size = batch_size = 0: picked by the library's */
+                                 /* tuner (bltc_autotune over 1000, 2000, 3000, 4000,   */
+                                 /* cached) when a plan is created from device          */
+                                 /* coordinates; BLTC_EUNSUPPORTED for host plans.      */
+                                 /* One of them 0 and the other not: BLTC_EINVAL        */
+    int32_t threads_per_target;  /* 1: one lane per target; 2 or 4: each batch's        */
                                  /* interaction lists cut into that many contiguous     */
                                  /* pieces, each evaluated by its own lane of the       */
                                  /* target (in different waves) into a partial          */
                                  /* potential, summed per target in piece order: more   */
                                  /* waves for problems with few targets.                */
                                  /* BLTC_PARTICLE_CLUSTER and BLTC_HERMITE with         */
-                                 /* max_q = 1 only; bltc_autotune picks it              */
+                                 /* max_q = 1 only.  0: picked by the tuner among 1, 2, */
+                                 /* 4 for those plans when created from device          */
+                                 /* coordinates; one lane otherwise                     */
     int32_t method;              /* bltc_method                                         */
     double delta;                /* BLTC_REGULARIZED_COULOMB length, >= 0               */
     int32_t no_symmetry;         /* 0: when the targets are the sources (same arrays,   */
@@ -141,12 +148,26 @@ typedef struct {
                                  /* each other's direct lists once for both directions  */
                                  /* (G(x,y) = G(y,x)); 1: never.  Same potentials up to */
                                  /* rounding order.  The pair results take 8 B per     */
-                                 /* target and pair (at most a quarter of the free      */
-                                 /* device memory: the heaviest pairs first).           */
+                                 /* target and pair; when they exceed 16 GiB (or what  */
+                                 /* workspace_limit leaves), the pairs run in rounds   */
+                                 /* through a workspace of that size, each round       */
+                                 /* folded into per-target sums in a fixed order.      */
+                                 /* Pairs whose results alone exceed 4 GiB stay in the */
+                                 /* plain direct lists.                                 */
+    int64_t workspace_limit;     /* bytes of device memory a plan may hold (requested   */
+                                 /* sizes of its arrays; transient scratch of the setup */
+                                 /* phase not counted); 0: no limit.  A plan whose      */
+                                 /* arrays do not fit fails with BLTC_ENOMEM, also when */
+                                 /* the limit leaves no room for the results of its     */
+                                 /* largest mutual pair (set no_symmetry then); the     */
+                                 /* mutual-pair results take what the other arrays      */
+                                 /* leave, in rounds if needed.  Same potentials up to  */
+                                 /* rounding order for every limit that fits.           */
 } bltc_params;
 
 /* Fills *p with the defaults: Coulomb, FP64, theta 0.7, degree 8,
- * N_L = N_B = 2000, BLTC_PARTICLE_CLUSTER, kappa = delta = 0. */
+ * N_L = N_B = 2000, one thread per target, BLTC_PARTICLE_CLUSTER,
+ * kappa = delta = 0, no workspace limit. */
 void bltc_params_default(bltc_params* p);
 
 /* One-shot evaluation (Alg. 1): builds the tree, batches and interaction lists
@@ -232,6 +253,11 @@ typedef struct {
                              /* sum over mutual leaf pairs of N_B * N_C (no_symmetry */
                              /* = 0; counted once the device side exists), else 0    */
     int32_t threads_per_target; /* lanes per target of the interaction launch (1, 2, 4) */
+    int64_t workspace_bytes; /* device memory the plan holds (requested bytes; 0 before */
+                             /* the device side exists)                              */
+    int64_t mutual_pairs;    /* mutual leaf pairs evaluated once (no_symmetry = 0)      */
+    int64_t pair_workspace_bytes; /* part of workspace_bytes for their results         */
+    int32_t pair_rounds;     /* rounds of mutual-pair results (1: all at once)          */
 } bltc_stats;
 
 int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out);
@@ -308,6 +334,13 @@ typedef struct {
 } bltc_batch_info;
 
 int bltc_batch_create(bltc_batch** out, bltc_plan* const* plans, int32_t count, void* stream);
+/* One-shot form over plans[]: builds a batch of the `count` plans, evaluates
+ * it once as bltc_batch_execute (no hipGraph), synchronises `stream` and
+ * frees the batch.  For repeated evaluations keep a bltc_batch, which owns
+ * the work-queue tables and the captured graph between calls. */
+int bltc_batch_potential(bltc_plan* const* plans, int32_t count, const double* const* q,
+                         const int32_t* num_q, const int64_t* q_ld, double* const* phi,
+                         const int64_t* phi_ld, void* stream);
 int bltc_batch_execute(bltc_batch* batch, const double* const* q, const int32_t* num_q,
                        const int64_t* q_ld, double* const* phi, const int64_t* phi_ld,
                        void* stream);

@@ -17,8 +17,8 @@ import numpy as np
 from . import _capi
 from ._capi import BLTCError, InvalidArgument  # noqa: F401
 
-__all__ = ["params", "Plan", "Batch", "autotune", "potential", "direct", "BLTCError", "InvalidArgument",
-           "library_path", "version"]
+__all__ = ["params", "Plan", "Batch", "batch_potential", "autotune", "potential", "direct",
+           "BLTCError", "InvalidArgument", "library_path", "version"]
 
 _KERNELS = {"coulomb": _capi.COULOMB, "yukawa": _capi.YUKAWA, "regularized": _capi.REGULARIZED}
 _PRECISIONS = {"fp64": _capi.FP64, "fp32_mixed": _capi.FP32_MIXED, "mixed": _capi.FP32_MIXED}
@@ -40,8 +40,11 @@ def version() -> str:
 
 
 def params(kernel="coulomb", kappa=0.0, theta=0.7, degree=8, leaf_size=2000, batch_size=2000,
-           precision="fp64", threads_per_target=0, method="bltc", delta=0.0,
-           symmetry=True) -> _capi.Params:
+           precision="fp64", threads_per_target=1, method="bltc", delta=0.0,
+           symmetry=True, workspace_limit=0) -> _capi.Params:
+    """bltc_params: leaf_size = batch_size = 0 and threads_per_target = 0 leave the
+    choice to the library's tuner (plans from device coordinates); workspace_limit
+    caps the device bytes a plan holds (0: none)."""
     p = _capi.Params()
     _capi.load().bltc_params_default(ctypes.byref(p))
     p.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
@@ -55,6 +58,7 @@ def params(kernel="coulomb", kappa=0.0, theta=0.7, degree=8, leaf_size=2000, bat
     p.method = _METHODS[method] if isinstance(method, str) else int(method)
     p.delta = float(delta)
     p.no_symmetry = 0 if symmetry else 1
+    p.workspace_limit = int(workspace_limit)
     return p
 
 
@@ -242,27 +246,8 @@ class Batch:
 
     def execute(self, charges, outs=None, stream=None):
         """charges: one (m_i, ns_i) float64 device tensor per system; returns (m_i, nt_i) tensors."""
-        torch = _torch()
-        n = len(self.plans)
-        if len(charges) != n:
-            raise ValueError("one charge tensor per system")
-        qs, outs2 = [], []
-        for i, (p, q) in enumerate(zip(self.plans, charges)):
-            q2, _ = _charges_device(q, p.ns)
-            qs.append(q2)
-            if outs is None:
-                o = torch.empty((q2.shape[0], p.nt), dtype=torch.float64, device=q2.device)
-            else:
-                o = outs[i]
-                o = o.unsqueeze(0) if o.dim() == 1 else o
-            outs2.append(o)
-        qp = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs])
-        nq = (ctypes.c_int32 * n)(*[q.shape[0] for q in qs])
-        ql = (ctypes.c_int64 * n)(*[q.stride(0) if q.shape[0] > 1 else p.ns for q, p in zip(qs, self.plans)])
-        op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs2])
-        ol = (ctypes.c_int64 * n)(*[o.stride(0) if o.shape[0] > 1 else p.nt for o, p in zip(outs2, self.plans)])
-        _capi.check(self._lib.bltc_batch_execute(self._h, qp, nq, ql, op, ol, _stream_handle(stream)))
-        return outs2
+        return _batch_call(self.plans, charges, outs, stream,
+                           lambda *a: self._lib.bltc_batch_execute(self._h, *a))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -276,6 +261,39 @@ class Batch:
             pass
 
 
+def _batch_call(plans, charges, outs, stream, call):
+    torch = _torch()
+    n = len(plans)
+    if len(charges) != n:
+        raise ValueError("one charge tensor per system")
+    qs, outs2 = [], []
+    for i, (p, q) in enumerate(zip(plans, charges)):
+        q2, _ = _charges_device(q, p.ns)
+        qs.append(q2)
+        if outs is None:
+            o = torch.empty((q2.shape[0], p.nt), dtype=torch.float64, device=q2.device)
+        else:
+            o = outs[i]
+            o = o.unsqueeze(0) if o.dim() == 1 else o
+        outs2.append(o)
+    qp = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs])
+    nq = (ctypes.c_int32 * n)(*[q.shape[0] for q in qs])
+    ql = (ctypes.c_int64 * n)(*[q.stride(0) if q.shape[0] > 1 else p.ns for q, p in zip(qs, plans)])
+    op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs2])
+    ol = (ctypes.c_int64 * n)(*[o.stride(0) if o.shape[0] > 1 else p.nt for o, p in zip(outs2, plans)])
+    _capi.check(call(qp, nq, ql, op, ol, _stream_handle(stream)))
+    return outs2
+
+
+def batch_potential(plans, charges, outs=None, stream=None):
+    """One evaluation of many systems over a list of plans (`bltc_batch_potential`):
+    the work-queue launch of a Batch, built and freed in the call; synchronises."""
+    lib = _capi.load()
+    arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    return _batch_call(plans, charges, outs, stream,
+                       lambda *a: lib.bltc_batch_potential(arr, len(plans), *a))
+
+
 def autotune(targets, sources, candidates=(1000, 2000, 3000, 4000), *, num_q=1, use_cache=True,
              stream=None, full=False, **kw):
     """Leaf/batch size chosen by timing each candidate on the GPU (`bltc_autotune`);
@@ -285,6 +303,7 @@ def autotune(targets, sources, candidates=(1000, 2000, 3000, 4000), *, num_q=1, 
     Returns (size, milliseconds of one evaluation), or with full=True
     (size, threads per target, milliseconds)."""
     lib = _capi.load()
+    kw.setdefault("threads_per_target", 0)   # searched unless fixed by the caller
     p = params(**kw)
     nt, tp = _coords_device(targets, "targets")
     ns, sp = _coords_device(sources, "sources")

@@ -30,7 +30,8 @@ EXPORTS = (
     "bltc_plan_execute", "bltc_plan_modified_charges", "bltc_plan_stats", "bltc_plan_view_get",
     "bltc_plan_set_timing", "bltc_plan_phase_times", "bltc_plan_destroy", "bltc_direct",
     "bltc_batch_create", "bltc_batch_execute", "bltc_batch_set_graph", "bltc_batch_info_get",
-    "bltc_batch_destroy", "bltc_autotune", "bltc_status_string", "bltc_last_error", "bltc_version",
+    "bltc_batch_destroy", "bltc_batch_potential", "bltc_autotune", "bltc_status_string",
+    "bltc_last_error", "bltc_version",
 )
 
 
@@ -47,6 +48,7 @@ class Params(ctypes.Structure):
         ("method", ctypes.c_int32),
         ("delta", ctypes.c_double),
         ("no_symmetry", ctypes.c_int32),
+        ("workspace_limit", ctypes.c_int64),
     ]
 
 
@@ -68,6 +70,10 @@ class Stats(ctypes.Structure):
         ("setup_seconds", ctypes.c_double),
         ("mutual_pair_evals", ctypes.c_int64),
         ("threads_per_target", ctypes.c_int32),
+        ("workspace_bytes", ctypes.c_int64),
+        ("mutual_pairs", ctypes.c_int64),
+        ("pair_workspace_bytes", ctypes.c_int64),
+        ("pair_rounds", ctypes.c_int32),
     ]
 
 
@@ -137,6 +143,8 @@ def load():
     lib.bltc_batch_info_get.argtypes = [vp, ctypes.POINTER(BatchInfo)]
     lib.bltc_batch_destroy.argtypes = [vp]
     lib.bltc_batch_destroy.restype = None
+    lib.bltc_batch_potential.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                         ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(i64), vp]
     lib.bltc_autotune.argtypes = [PP, i64, vp, vp, vp, i64, vp, vp, vp, i32, ctypes.POINTER(i32), i32,
                                   i32, PP, ctypes.POINTER(d), vp]
     lib.bltc_status_string.argtypes = [ctypes.c_int]
@@ -148,7 +156,7 @@ def load():
                  "bltc_plan_modified_charges", "bltc_plan_stats", "bltc_plan_view_get", "bltc_direct",
                  "bltc_plan_set_timing", "bltc_plan_phase_times", "bltc_batch_create",
                  "bltc_batch_execute", "bltc_batch_set_graph", "bltc_batch_info_get",
-                 "bltc_autotune"):
+                 "bltc_batch_potential", "bltc_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -80,36 +80,40 @@ void cache_store(const std::string& key, int32_t leaf, int32_t tpt, double ms)
 
 }  // namespace
 
-extern "C" int bltc_autotune(const bltc_params* p, int64_t nt, const double* tx,
-                             const double* ty, const double* tz, int64_t ns, const double* sx,
-                             const double* sy, const double* sz, int32_t num_q,
-                             const int32_t* candidates, int32_t ncand, int32_t use_cache,
-                             bltc_params* out, double* best_ms, void* stream)
+namespace {
+
+// ncand = 0: the sizes of *p are kept and only the threads per target are
+// searched (the caller checked that they are open and searchable)
+int autotune_impl(const bltc_params* p, int64_t nt, const double* tx, const double* ty,
+                  const double* tz, int64_t ns, const double* sx, const double* sy,
+                  const double* sz, int32_t num_q, const int32_t* candidates, int32_t ncand,
+                  int32_t use_cache, bltc_params* out, double* best_ms, void* stream)
 {
-    if (!p || !out)
-        return fail(BLTC_EINVAL, "NULL argument");
-    if (!candidates || ncand < 1)
-        return fail(BLTC_EINVAL, "at least one candidate size is needed");
-    if (num_q < 1 || num_q > 16)
-        return fail(BLTC_EINVAL, "num_q must be in 1..16");
-    for (int32_t c = 0; c < ncand; ++c)
-        if (candidates[c] < 1)
-            return fail(BLTC_EINVAL, "candidate sizes must be >= 1");
     *out = *p;
     if (best_ms)
         *best_ms = 0.0;
     if (nt == 0 || ns == 0)
         return BLTC_OK;
+    const bool fixed = ncand == 0;
+    const int32_t fixed_size = p->leaf_size;
+    if (fixed) {
+        candidates = &fixed_size;
+        ncand = 1;
+    }
     // threads per target: searched for one-vector BLTC plans that leave it open
     const bool tune_tpt = p->threads_per_target == 0 && num_q == 1 &&
                           (p->method == BLTC_PARTICLE_CLUSTER || p->method == BLTC_HERMITE);
-    const std::string key = class_key(p, nt, ns, num_q) + " tpt=" +
-                            std::to_string(tune_tpt ? 0 : std::max(1, p->threads_per_target));
+    std::string key = class_key(p, nt, ns, num_q) + " tpt=" +
+                      std::to_string(tune_tpt ? 0 : std::max(1, p->threads_per_target));
+    if (fixed)
+        key += " sizes=" + std::to_string(p->leaf_size) + "," + std::to_string(p->batch_size);
     int32_t cached = 0, cached_tpt = 1;
     double cached_ms = 0.0;
     if (use_cache && cache_lookup(key, &cached, &cached_tpt, &cached_ms)) {
-        out->leaf_size = cached;
-        out->batch_size = cached;
+        if (!fixed) {
+            out->leaf_size = cached;
+            out->batch_size = cached;
+        }
         if (tune_tpt)
             out->threads_per_target = cached_tpt;
         if (best_ms)
@@ -145,9 +149,11 @@ extern "C" int bltc_autotune(const bltc_params* p, int64_t nt, const double* tx,
         for (int32_t c = 0; c < nsteps && rc == BLTC_OK; ++c) {
             bltc_params trial = *p;
             const int32_t leaf = c < ncand ? candidates[c] : best;
-            const int32_t tpt = c < ncand ? p->threads_per_target : (c == ncand ? 2 : 4);
-            trial.leaf_size = leaf;
-            trial.batch_size = leaf;
+            const int32_t tpt = c < ncand ? std::max(1, p->threads_per_target) : (c == ncand ? 2 : 4);
+            if (!fixed) {
+                trial.leaf_size = leaf;
+                trial.batch_size = leaf;
+            }
             trial.threads_per_target = tpt;
             bltc_plan* plan = nullptr;
             rc = bltc_plan_create(&plan, &trial, nt, tx, ty, tz, ns, sx, sy, sz,
@@ -187,13 +193,54 @@ extern "C" int bltc_autotune(const bltc_params* p, int64_t nt, const double* tx,
         (void)hipFree(phi);
     if (rc != BLTC_OK)
         return rc;
-    out->leaf_size = best;
-    out->batch_size = best;
+    if (!fixed) {
+        out->leaf_size = best;
+        out->batch_size = best;
+    }
     if (tune_tpt)
         out->threads_per_target = best_tpt;
     if (best_ms)
         *best_ms = best_t;
     if (use_cache)
         cache_store(key, best, best_tpt, best_t);
+    return BLTC_OK;
+}
+
+}  // namespace
+
+extern "C" int bltc_autotune(const bltc_params* p, int64_t nt, const double* tx,
+                             const double* ty, const double* tz, int64_t ns, const double* sx,
+                             const double* sy, const double* sz, int32_t num_q,
+                             const int32_t* candidates, int32_t ncand, int32_t use_cache,
+                             bltc_params* out, double* best_ms, void* stream)
+{
+    if (!p || !out)
+        return fail(BLTC_EINVAL, "NULL argument");
+    if (!candidates || ncand < 1)
+        return fail(BLTC_EINVAL, "at least one candidate size is needed");
+    if (num_q < 1 || num_q > 16)
+        return fail(BLTC_EINVAL, "num_q must be in 1..16");
+    for (int32_t c = 0; c < ncand; ++c)
+        if (candidates[c] < 1)
+            return fail(BLTC_EINVAL, "candidate sizes must be >= 1");
+    return autotune_impl(p, nt, tx, ty, tz, ns, sx, sy, sz, num_q, candidates, ncand, use_cache,
+                         out, best_ms, stream);
+}
+
+int bltc_internal_tune(const bltc_params* p, int64_t nt, const double* tx, const double* ty,
+                       const double* tz, int64_t ns, const double* sx, const double* sy,
+                       const double* sz, int32_t max_q, bltc_params* out, void* stream)
+{
+    static const int32_t kSizes[] = {1000, 2000, 3000, 4000};
+    const int32_t num_q = max_q > 1 ? 16 : 1;
+    const bool tpt_open = p->threads_per_target == 0 && max_q == 1 &&
+                          (p->method == BLTC_PARTICLE_CLUSTER || p->method == BLTC_HERMITE);
+    *out = *p;
+    if (p->leaf_size == 0)
+        return autotune_impl(p, nt, tx, ty, tz, ns, sx, sy, sz, num_q, kSizes, 4, 1, out,
+                             nullptr, stream);
+    if (tpt_open)
+        return autotune_impl(p, nt, tx, ty, tz, ns, sx, sy, sz, num_q, nullptr, 0, 1, out,
+                             nullptr, stream);
     return BLTC_OK;
 }

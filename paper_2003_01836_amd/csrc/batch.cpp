@@ -282,6 +282,26 @@ int bltc_batch_info_get(const bltc_batch* b, bltc_batch_info* out)
     return BLTC_OK;
 }
 
+int bltc_batch_potential(bltc_plan* const* plans, int32_t count, const double* const* q,
+                         const int32_t* num_q, const int64_t* q_ld, double* const* phi,
+                         const int64_t* phi_ld, void* stream)
+{
+    bltc_batch* b = nullptr;
+    int rc = bltc_batch_create(&b, plans, count, stream);
+    if (rc != BLTC_OK)
+        return rc;
+    rc = bltc_batch_set_graph(b, 0);
+    if (rc == BLTC_OK)
+        rc = bltc_batch_execute(b, q, num_q, q_ld, phi, phi_ld, stream);
+    if (rc == BLTC_OK) {
+        hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (e != hipSuccess)
+            rc = bltc_detail::hip_fail(e, "hipStreamSynchronize");
+    }
+    bltc_batch_destroy(b);
+    return rc;
+}
+
 void bltc_batch_destroy(bltc_batch* b)
 {
     delete b;

@@ -42,8 +42,11 @@ int check_params(const bltc_params* p)
         return fail(BLTC_EINVAL, "theta must satisfy 0 <= theta < 1");
     if (p->degree < 1 || p->degree > bltc::kMaxDegree)
         return fail(BLTC_EINVAL, "degree must be in 1..%d", bltc::kMaxDegree);
-    if (p->leaf_size < 1 || p->batch_size < 1)
-        return fail(BLTC_EINVAL, "leaf_size and batch_size must be >= 1");
+    if (p->leaf_size < 0 || p->batch_size < 0 || (p->leaf_size == 0) != (p->batch_size == 0))
+        return fail(BLTC_EINVAL, "leaf_size and batch_size must both be >= 1, or both 0 "
+                                 "(autotune)");
+    if (p->workspace_limit < 0)
+        return fail(BLTC_EINVAL, "workspace_limit must be >= 0 (0: no limit)");
     if (p->threads_per_target != 0 && p->threads_per_target != 1 && p->threads_per_target != 2 &&
         p->threads_per_target != 4)
         return fail(BLTC_EINVAL, "threads_per_target must be 0, 1, 2 or 4");
@@ -157,10 +160,7 @@ int make_device_plan(bltc_plan* plan, const bltc_params* p, int64_t nt, const do
     bltc::plan_batches(hp);
     bltc::DeviceLists dl;
     auto alloc = [plan](void** ptr, size_t bytes) -> hipError_t {
-        hipError_t e = hipMalloc(ptr, std::max<size_t>(bytes, 1));
-        if (e == hipSuccess)
-            plan->allocations.push_back(*ptr);
-        return e;
+        return plan->alloc_bytes(ptr, bytes);
     };
     err = bltc::build_lists_device(hp, dl, alloc, s);
     if (!err.empty())
@@ -330,14 +330,10 @@ int upload_split(bltc_plan* plan, hipStream_t s)
 
 }  // namespace
 
-int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
+namespace {
+
+int upload_particle_cluster(bltc_plan* plan, hipStream_t s)
 {
-    if (plan->uploaded)
-        return BLTC_OK;
-    if (plan->cp)
-        return bltc_cp::upload(plan, s);
-    if (plan->cc)
-        return bltc_cc::upload(plan, s);
     const bltc::HostPlan& hp = plan->hp;
     bltc::DevicePlan& d = plan->d;
     HIP_TRY(hipGetDevice(&plan->device));
@@ -468,6 +464,21 @@ int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
     return BLTC_OK;
 }
 
+}  // namespace
+
+int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
+{
+    int rc = BLTC_OK;
+    if (!plan->uploaded)
+        rc = plan->cp ? bltc_cp::upload(plan, s)
+           : plan->cc ? bltc_cc::upload(plan, s)
+                      : upload_particle_cluster(plan, s);
+    // the mutual-pair workspace last: it takes what the workspace limit leaves
+    if (rc == BLTC_OK)
+        rc = bltc_internal_finish_pairs(plan, s);
+    return rc;
+}
+
 namespace {
 
 int zero_phi(int64_t nt, int32_t num_q, double* phi, int64_t phi_ld, hipStream_t s)
@@ -536,7 +547,9 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, int64_t q_ld, doubl
         HIP_TRY(bltc::launch_upward_mfma(d, 1, d.qhat, d.qhat32, s));
         HIP_TRY(mark(0, 2));
         if (d.sym) {
-            HIP_TRY(bltc::launch_near_pairs(d, kp, s));
+            rc = bltc_internal_pairs(plan, d, kp, s);
+            if (rc != BLTC_OK)
+                return rc;
             if (plan->timing) {
                 if (!plan->ev_pairs)
                     HIP_TRY(hipEventCreate(&plan->ev_pairs));
@@ -611,6 +624,9 @@ int create_from_host(bltc_plan** out, const bltc_params* p, int64_t nt, const do
                      const double* sy, const double* sz, int32_t max_q)
 {
     int rc;
+    if (p->leaf_size == 0)
+        return fail(BLTC_EUNSUPPORTED, "leaf_size = batch_size = 0 (autotune) needs a plan "
+                                       "created from device coordinates");
     if ((rc = check_finite(nt, tx, ty, tz, "target")) != BLTC_OK)
         return rc;
     if ((rc = check_finite(ns, sx, sy, sz, "source")) != BLTC_OK)
@@ -620,6 +636,7 @@ int create_from_host(bltc_plan** out, const bltc_params* p, int64_t nt, const do
         return fail(BLTC_ENOMEM, "cannot allocate plan");
     plan->prm = *p;
     plan->max_q = max_q;
+    plan->limit = p->workspace_limit;
     try {
         if (p->method == BLTC_CLUSTER_PARTICLE)
             rc = bltc_cp::create_host(plan, plan_params(plan, p), nt, tx, ty, tz, ns, sx, sy, sz);
@@ -646,47 +663,12 @@ int bltc_internal_upload_symmetric(bltc_plan* plan, bltc::DevicePlan& d,
                                    const bltc::DirectLists& dl, std::vector<int64_t>* cost,
                                    hipStream_t s)
 {
-    // unit results (8 B each): at most a quarter of the free device memory
-    size_t free_b = 0, total_b = 0;
-    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    const int64_t max_out = static_cast<int64_t>(free_b / 4 / sizeof(double));
     const int64_t sub = plan->prm.precision == BLTC_FP32_MIXED ? bltc::kSymTargetsMixed
                                                                : bltc::kSymTargetsF64;
+    // every mutual pair whose results fit in a quarter of the round workspace
     bltc::SymPlan sp;
-    if (!bltc::plan_symmetric(dl, sub, max_out, sp))
+    if (!bltc::plan_symmetric(dl, sub, INT64_MAX, kPairWorkspaceBytes / 4 / sizeof(double), sp))
         return BLTC_OK;
-    const std::vector<int64_t>& bbeg = *dl.batch_begin;
-    const std::vector<int64_t>& bcnt = *dl.batch_count;
-    std::vector<bltc::SymUnit> units;
-    for (size_t k = 0; k < sp.ub.size(); ++k) {
-        const int32_t b = sp.ub[k], c = sp.uc[k];
-        for (int32_t q = 0; q < sp.nsub[k]; ++q) {
-            bltc::SymUnit su;
-            su.tb = bbeg[b] + q * sub;
-            su.sb = bbeg[c];
-            su.roff = sp.roff[k] + q * sub;
-            su.coff = sp.coff[k] + q * bcnt[c];
-            su.nb = static_cast<int32_t>(std::min<int64_t>(sub, bcnt[b] - q * sub));
-            su.nc = static_cast<int32_t>(bcnt[c]);
-            su.batch = b;
-            su.leaf = (*dl.batch_node)[c];
-            units.push_back(su);
-        }
-    }
-    // heaviest sub-unit first (one wave each)
-    std::stable_sort(units.begin(), units.end(), [](const bltc::SymUnit& a, const bltc::SymUnit& c) {
-        return static_cast<int64_t>(a.nb) * a.nc > static_cast<int64_t>(c.nb) * c.nc;
-    });
-    // the results first: if the device cannot hold them, keep the plain lists
-    double* out = nullptr;
-    if (hipMalloc(reinterpret_cast<void**>(&out), static_cast<size_t>(sp.out_size) * sizeof(double)) !=
-        hipSuccess) {
-        (void)hipGetLastError();
-        return BLTC_OK;
-    }
-    plan->allocations.push_back(out);
-    d.sym_out = out;
-    HIP_TRY(plan->put(&d.sym_unit, units, s));
     if (&d == &plan->d) {
         plan->sym_near_off_h = sp.near_off;
         plan->sym_pc_off_h = sp.pc_off;
@@ -697,12 +679,189 @@ int bltc_internal_upload_symmetric(bltc_plan* plan, bltc::DevicePlan& d,
     HIP_TRY(plan->put(&d.sym_near_leaf, sp.near_leaf, s));
     HIP_TRY(plan->put(&d.sym_pc_off, sp.pc_off, s));
     HIP_TRY(plan->put(&d.sym_pc_base, sp.pc_base, s));
-    HIP_TRY(plan->put(&d.batch_begin, bbeg, s));
+    HIP_TRY(plan->put(&d.batch_begin, *dl.batch_begin, s));
     HIP_TRY(hipStreamSynchronize(s));
-    d.sym_units = static_cast<int64_t>(units.size());
     d.sym = 1;
+    d.sym_rounds = 1;
     plan->sym_pair_evals = sp.pair_evals;
     *cost = sp.batch_cost;
+    bltc_plan::Pairs& pr = plan->pairs;
+    pr.d = &d;
+    pr.batch_begin = *dl.batch_begin;
+    pr.batch_count = *dl.batch_count;
+    pr.batch_node = *dl.batch_node;
+    pr.count = static_cast<int64_t>(sp.ub.size());
+    pr.sp = std::move(sp);
+    pr.pending = true;
+    return BLTC_OK;
+}
+
+int bltc_internal_finish_pairs(bltc_plan* plan, hipStream_t s)
+{
+    bltc_plan::Pairs& pr = plan->pairs;
+    if (!pr.pending)
+        return BLTC_OK;
+    bltc::DevicePlan& d = *pr.d;
+    const bltc::SymPlan& sp = pr.sp;
+    const int64_t nb = static_cast<int64_t>(pr.batch_begin.size());
+    const int64_t nu = static_cast<int64_t>(sp.ub.size());
+    const int64_t sub = sp.sub;
+    int64_t nsubunits = 0;
+    for (int64_t k = 0; k < nu; ++k)
+        nsubunits += sp.nsub[k];
+    const int64_t units_bytes = nsubunits * static_cast<int64_t>(sizeof(bltc::SymUnit));
+    const int64_t full_bytes = sp.out_size * static_cast<int64_t>(sizeof(double));
+    const int64_t left = plan->limit > 0 ? plan->limit - plan->bytes : INT64_MAX;
+    // one round: the whole result array; rounds: a workspace, the per-target
+    // sums, the per-round fold tables and the batch ranges
+    std::vector<int32_t> round_unit;
+    std::vector<int64_t> base;
+    int64_t ws_values = sp.out_size;
+    if (full_bytes + units_bytes <= std::min<int64_t>(kPairWorkspaceBytes, left)) {
+        round_unit = {0, static_cast<int32_t>(nu)};
+        base = {0, sp.out_size};
+    } else {
+        int64_t ntgt = 0;
+        for (int64_t b = 0; b < nb; ++b)
+            ntgt = std::max(ntgt, pr.batch_begin[b] + pr.batch_count[b]);
+        const int64_t npc = nb > 0 ? sp.pc_off[nb] : 0;
+        const int64_t fixed = units_bytes + ntgt * 8 + nb * 8 + npc * 8 + (nb + 1) * 4;
+        int64_t rounds = 1;
+        for (int it = 0;; ++it) {
+            const int64_t room = std::min<int64_t>(kPairWorkspaceBytes,
+                                                   left - fixed - rounds * (nb + 1) * 4);
+            const int64_t cap = room / static_cast<int64_t>(sizeof(double));
+            if (cap < 1 || !bltc::plan_pair_rounds(sp, cap, round_unit, base))
+                return bltc_detail::fail(
+                    BLTC_ENOMEM,
+                    "workspace_limit of %lld bytes leaves no room for the results of the "
+                    "largest mutual leaf pair (%lld bytes held); raise the limit or set "
+                    "no_symmetry",
+                    static_cast<long long>(plan->limit), static_cast<long long>(plan->bytes));
+            const int64_t r = static_cast<int64_t>(round_unit.size()) - 1;
+            if (r <= rounds || it > 8) {
+                ws_values = 0;
+                for (int64_t k = 0; k < r; ++k)
+                    ws_values = std::max(ws_values, base[k + 1] - base[k]);
+                break;
+            }
+            rounds = r;
+        }
+    }
+    const int32_t R = static_cast<int32_t>(round_unit.size()) - 1;
+    // sub-units round by round, each round heaviest first, offsets relative
+    // to the round's base
+    std::vector<bltc::SymUnit> units;
+    units.reserve(static_cast<size_t>(nsubunits));
+    std::vector<int32_t> round_sub(static_cast<size_t>(R) + 1, 0);
+    for (int32_t r = 0; r < R; ++r) {
+        const size_t first = units.size();
+        for (int32_t k = round_unit[r]; k < round_unit[r + 1]; ++k) {
+            const int32_t b = sp.ub[k], c = sp.uc[k];
+            for (int32_t q = 0; q < sp.nsub[k]; ++q) {
+                bltc::SymUnit su;
+                su.tb = pr.batch_begin[b] + q * sub;
+                su.sb = pr.batch_begin[c];
+                su.roff = sp.roff[k] - base[r] + q * sub;
+                su.coff = sp.coff[k] - base[r] + q * pr.batch_count[c];
+                su.nb = static_cast<int32_t>(std::min<int64_t>(sub, pr.batch_count[b] - q * sub));
+                su.nc = static_cast<int32_t>(pr.batch_count[c]);
+                su.batch = b;
+                su.leaf = pr.batch_node[c];
+                units.push_back(su);
+            }
+        }
+        // heaviest sub-unit first (one wave each)
+        std::stable_sort(units.begin() + static_cast<std::ptrdiff_t>(first), units.end(),
+                         [](const bltc::SymUnit& a, const bltc::SymUnit& c) {
+                             return static_cast<int64_t>(a.nb) * a.nc >
+                                    static_cast<int64_t>(c.nb) * c.nc;
+                         });
+        round_sub[r + 1] = static_cast<int32_t>(units.size());
+    }
+    const int64_t held = plan->bytes;
+    HIP_TRY(plan->put(&d.sym_unit, units, s));
+    HIP_TRY(plan->alloc(&d.sym_out, static_cast<size_t>(ws_values)));
+    d.sym_units = static_cast<int64_t>(units.size());
+    if (R > 1) {
+        // fold tables: per round and batch, the batch's result entries of that round
+        std::vector<int32_t> off(static_cast<size_t>(R) * (nb + 1), 0);
+        std::vector<int64_t> fbase;
+        for (int32_t r = 0; r < R; ++r) {
+            for (int64_t b = 0; b < nb; ++b) {
+                off[r * (nb + 1) + b] = static_cast<int32_t>(fbase.size());
+                for (int32_t e = sp.pc_off[b]; e < sp.pc_off[b + 1]; ++e)
+                    if (sp.pc_base[e] >= base[r] && sp.pc_base[e] < base[r + 1])
+                        fbase.push_back(sp.pc_base[e] - base[r]);
+            }
+            off[r * (nb + 1) + nb] = static_cast<int32_t>(fbase.size());
+        }
+        std::vector<int64_t> bend(static_cast<size_t>(nb));
+        int64_t ntgt = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            bend[b] = pr.batch_begin[b] + pr.batch_count[b];
+            ntgt = std::max(ntgt, bend[b]);
+        }
+        std::vector<int32_t> ident(static_cast<size_t>(nb) + 1);
+        for (int64_t b = 0; b <= nb; ++b)
+            ident[b] = static_cast<int32_t>(b);
+        HIP_TRY(plan->put(&pr.fold_off, off, s));
+        HIP_TRY(plan->put(&pr.fold_base, fbase, s));
+        HIP_TRY(plan->put(&pr.batch_end, bend, s));
+        HIP_TRY(plan->alloc(&d.sym_acc, static_cast<size_t>(ntgt)));
+        // the interaction kernels read the per-target sums: one entry per batch
+        int32_t* pc_off = nullptr;
+        HIP_TRY(plan->put(&pc_off, ident, s));
+        d.sym_pc_off = pc_off;
+        d.sym_pc_base = d.batch_begin;
+        if (&d == &plan->d)
+            plan->sym_pc_off_h = ident;
+        if (&d == &plan->d && plan->tpt > 1) {
+            // pieces of several lanes per target: the sums go with piece 0
+            const int32_t T = plan->tpt;
+            std::vector<int32_t> pc_t(static_cast<size_t>(nb * T + 1), 0);
+            for (int64_t b = 0; b < nb; ++b)
+                for (int32_t p = 0; p < T; ++p)
+                    pc_t[b * T + p] = p == 0 ? static_cast<int32_t>(b) : static_cast<int32_t>(b + 1);
+            pc_t[nb * T] = static_cast<int32_t>(nb);
+            HIP_TRY(plan->put(&plan->dt.sym_pc_off, pc_t, s));
+            plan->dt.sym_pc_base = d.batch_begin;
+        }
+    }
+    d.sym_rounds = R;
+    if (&d == &plan->d && plan->tpt > 1) {
+        plan->dt.sym_unit = d.sym_unit;
+        plan->dt.sym_units = d.sym_units;
+        plan->dt.sym_out = d.sym_out;
+        plan->dt.sym_acc = d.sym_acc;
+        plan->dt.sym_rounds = R;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    pr.round_unit = round_sub;
+    pr.rounds = R;
+    pr.workspace_bytes = plan->bytes - held;
+    pr.pending = false;
+    pr.sp = bltc::SymPlan();
+    return BLTC_OK;
+}
+
+int bltc_internal_pairs(bltc_plan* plan, const bltc::DevicePlan& d, const bltc::KernelParams& kp,
+                        hipStream_t s)
+{
+    if (!d.sym)
+        return BLTC_OK;
+    const bltc_plan::Pairs& pr = plan->pairs;
+    if (pr.rounds <= 1) {
+        HIP_TRY(bltc::launch_near_pairs(d, 0, d.sym_units, kp, s));
+        return BLTC_OK;
+    }
+    const int64_t nb = static_cast<int64_t>(pr.batch_begin.size());
+    for (int32_t r = 0; r < pr.rounds; ++r) {
+        HIP_TRY(bltc::launch_near_pairs(d, pr.round_unit[r], pr.round_unit[r + 1] - pr.round_unit[r],
+                                        kp, s));
+        HIP_TRY(bltc::launch_fold_pairs(nb, d.batch_begin, pr.batch_end, pr.fold_off + r * (nb + 1),
+                                        pr.fold_base, d.sym_out, d.sym_acc, r == 0, s));
+    }
     return BLTC_OK;
 }
 
@@ -720,9 +879,10 @@ void bltc_params_default(bltc_params* p)
     p->degree = 8;
     p->leaf_size = 2000;
     p->batch_size = 2000;
-    p->threads_per_target = 0;
+    p->threads_per_target = 1;
     p->method = BLTC_PARTICLE_CLUSTER;
     p->delta = 0.0;
+    p->workspace_limit = 0;
 }
 
 int bltc_plan_create_host(bltc_plan** out, const bltc_params* p, int64_t nt, const double* tx,
@@ -735,19 +895,36 @@ int bltc_plan_create_host(bltc_plan** out, const bltc_params* p, int64_t nt, con
     return create_from_host(out, p, nt, tx, ty, tz, ns, sx, sy, sz, max_q);
 }
 
-int bltc_plan_create(bltc_plan** out, const bltc_params* p, int64_t nt, const double* tx,
+int bltc_plan_create(bltc_plan** out, const bltc_params* p_in, int64_t nt, const double* tx,
                      const double* ty, const double* tz, int64_t ns, const double* sx,
                      const double* sy, const double* sz, int32_t max_q, void* stream)
 {
-    int rc = create_common(out, p, nt, tx, ty, tz, ns, sx, sy, sz, max_q);
+    int rc = create_common(out, p_in, nt, tx, ty, tz, ns, sx, sy, sz, max_q);
     if (rc != BLTC_OK)
         return rc;
+    // sizes or threads per target left open: the tuner times plans first
+    bltc_params tuned;
+    try {
+        rc = bltc_internal_tune(p_in, nt, tx, ty, tz, ns, sx, sy, sz, max_q, &tuned, stream);
+    } catch (const std::bad_alloc&) {
+        rc = fail(BLTC_ENOMEM, "host allocation failed while tuning");
+    } catch (const std::exception& ex) {
+        rc = fail(BLTC_EINTERNAL, "tuning failed: %s", ex.what());
+    }
+    if (rc != BLTC_OK)
+        return rc;
+    if (tuned.leaf_size == 0) {
+        // nothing to time on (no targets or no sources): the default size
+        tuned.leaf_size = tuned.batch_size = 2000;
+    }
+    const bltc_params* p = &tuned;
     hipStream_t s = static_cast<hipStream_t>(stream);
     bltc_plan* plan = new (std::nothrow) bltc_plan();
     if (!plan)
         return fail(BLTC_ENOMEM, "cannot allocate plan");
     plan->prm = *p;
     plan->max_q = max_q;
+    plan->limit = p->workspace_limit;
     try {
         if (p->method == BLTC_CLUSTER_PARTICLE)
             rc = bltc_cp::create_device(plan, plan_params(plan, p), nt, tx, ty, tz, ns, sx, sy, sz, s);
@@ -847,6 +1024,18 @@ int bltc_plan_modified_charges(bltc_plan* plan, int64_t cluster, int32_t qi, dou
     return BLTC_OK;
 }
 
+namespace {
+
+void pair_stats(const bltc_plan* plan, bltc_stats* out)
+{
+    out->workspace_bytes = plan->bytes;
+    out->mutual_pairs = plan->pairs.count;
+    out->pair_workspace_bytes = plan->pairs.workspace_bytes;
+    out->pair_rounds = plan->pairs.rounds;
+}
+
+}  // namespace
+
 int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out)
 {
     if (!plan || !out)
@@ -863,6 +1052,7 @@ int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out)
         out->batch_size = plan->prm.batch_size;
         out->mutual_pair_evals = plan->sym_pair_evals;
         out->threads_per_target = 1;
+        pair_stats(plan, out);
         return BLTC_OK;
     }
     out->clusters = hp.src.nodes();
@@ -881,6 +1071,7 @@ int bltc_plan_stats(const bltc_plan* plan, bltc_stats* out)
     out->setup_seconds = hp.setup_seconds;
     out->mutual_pair_evals = plan->sym_pair_evals;
     out->threads_per_target = std::max(1, plan->prm.threads_per_target);
+    pair_stats(plan, out);
     return BLTC_OK;
 }
 

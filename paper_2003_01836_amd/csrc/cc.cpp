@@ -267,7 +267,7 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStr
 {
     if (num_q != 1)
         return fail(BLTC_EUNSUPPORTED, "cluster-cluster plans take one charge vector");
-    int rc = upload(plan, s);
+    int rc = bltc_internal_upload_plan(plan, s);
     if (rc != BLTC_OK)
         return rc;
     const bltc::CcPlan& cc = plan->ccp;
@@ -298,7 +298,9 @@ int execute(bltc_plan* plan, const double* q, int32_t num_q, double* phi, hipStr
     else
         HIP_TRY(bltc::launch_interact(plan->dprox, kp, plan->cp_phat, s));
     HIP_TRY(mark(2));
-    HIP_TRY(bltc::launch_near_pairs(plan->ddir, kp, s));
+    rc = bltc_internal_pairs(plan, plan->ddir, kp, s);
+    if (rc != BLTC_OK)
+        return rc;
     if (mixed)
         HIP_TRY(bltc::launch_interact_mixed(plan->ddir, kp, phi, s));
     else

@@ -32,11 +32,28 @@ inline int fail(int code, const char* fmt, ...)
     return code;
 }
 
+// why the last allocation of the calling thread failed, when a plan's
+// workspace limit refused it (empty otherwise)
+inline std::string& limit_note()
+{
+    static thread_local std::string msg;
+    return msg;
+}
+
+// A failed HIP call: BLTC_ENOMEM for allocations (the device's or a plan's
+// workspace limit), BLTC_EHIP otherwise.
 inline int hip_fail(hipError_t e, const char* what)
 {
+    if (e == hipErrorOutOfMemory) {
+        std::string note;
+        note.swap(limit_note());
+        return fail(BLTC_ENOMEM, "%s: %s", what,
+                    note.empty() ? "out of device memory" : note.c_str());
+    }
     return fail(BLTC_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// device copy of a host vector (memory not owned by a plan)
 template <class T>
 hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s)
 {
@@ -50,6 +67,12 @@ hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s)
 }
 
 }  // namespace bltc_detail
+
+// Device memory for the results of mutual leaf pairs when the whole result
+// array does not fit: at most this many bytes per round (a plan's
+// workspace_limit can lower it).  Pairs whose results alone exceed a quarter
+// of it stay in the plain direct lists.
+constexpr int64_t kPairWorkspaceBytes = int64_t(16) << 30;
 
 #define HIP_TRY(call)                                              \
     do {                                                           \
@@ -109,6 +132,27 @@ struct bltc_plan {
     std::vector<hipEvent_t> events;      // 4 per charge vector
     hipEvent_t ev_pairs = nullptr;       // after the mutual-pair launch (timing)
     bool timed_pairs = false;            // ev_pairs belongs to the recorded execution
+    // device memory the plan holds (requested bytes) and its limit (0: none)
+    int64_t bytes = 0;
+    int64_t limit = 0;
+    // Mutual leaf pairs (d.sym): planned with the direct lists, their result
+    // workspace and sub-units sized once the rest of the device side exists
+    // (bltc_internal_finish_pairs), in one round when the whole result array
+    // fits under the workspace cap, else in rounds folded into per-target sums.
+    struct Pairs {
+        bltc::DevicePlan* d = nullptr;   // the view whose direct lists hold the pairs
+        bltc::SymPlan sp;                // every mutual pair taken
+        std::vector<int64_t> batch_begin, batch_count;
+        std::vector<int32_t> batch_node;
+        bool pending = false;
+        int64_t count = 0;               // mutual pairs evaluated once
+        int32_t rounds = 0;
+        int64_t workspace_bytes = 0;     // result workspace (and per-target sums)
+        std::vector<int32_t> round_unit; // rounds + 1 sub-unit offsets
+        int32_t* fold_off = nullptr;     // [rounds][batches + 1]
+        int64_t* fold_base = nullptr;
+        int64_t* batch_end = nullptr;    // device copy of begin + count per batch
+    } pairs;
 
     ~bltc_plan()
     {
@@ -120,22 +164,40 @@ struct bltc_plan {
             (void)hipFree(p);
     }
 
+    // every device allocation of the plan: counted against its limit
+    hipError_t alloc_bytes(void** dst, size_t bytes_wanted)
+    {
+        const size_t n = std::max<size_t>(1, bytes_wanted);
+        if (limit > 0 && bytes + static_cast<int64_t>(n) > limit) {
+            char buf[160];
+            std::snprintf(buf, sizeof(buf),
+                          "workspace_limit of %lld bytes reached (%lld held, %lld more needed)",
+                          static_cast<long long>(limit), static_cast<long long>(bytes),
+                          static_cast<long long>(n));
+            bltc_detail::limit_note() = buf;
+            return hipErrorOutOfMemory;
+        }
+        hipError_t e = hipMalloc(dst, n);
+        if (e == hipSuccess) {
+            allocations.push_back(*dst);
+            bytes += static_cast<int64_t>(n);
+        }
+        return e;
+    }
+
     template <class T>
     hipError_t put(T** dst, const std::vector<T>& v, hipStream_t s)
     {
-        hipError_t e = bltc_detail::upload(dst, v, s);
-        if (e == hipSuccess)
-            allocations.push_back(*dst);
+        hipError_t e = alloc_bytes(reinterpret_cast<void**>(dst), v.size() * sizeof(T));
+        if (e == hipSuccess && !v.empty())
+            e = hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
         return e;
     }
 
     template <class T>
     hipError_t alloc(T** dst, size_t count)
     {
-        hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(1, count) * sizeof(T));
-        if (e == hipSuccess)
-            allocations.push_back(*dst);
-        return e;
+        return alloc_bytes(reinterpret_cast<void**>(dst), count * sizeof(T));
     }
 };
 
@@ -144,13 +206,31 @@ struct bltc_plan {
 int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s);
 
 // Mutual direct pairs of one-tree direct lists evaluated once (see
-// plan_symmetric): plans the units, uploads them, the reduced lists and the
-// per-batch result offsets into d (d.sym = 1), and lowers the lists' batch_cost
-// in *cost to the work left to the batches.  Returns BLTC_OK and leaves d
-// alone when no pair qualifies; `sub` = targets per sub-unit.
+// plan_symmetric): plans them, uploads the reduced lists and the per-batch
+// result offsets into d (d.sym = 1), lowers the lists' batch_cost in *cost to
+// the work left to the batches, and leaves the result workspace and the
+// sub-units to bltc_internal_finish_pairs.  Returns BLTC_OK and leaves d alone
+// when no pair qualifies.  d must be a member of *plan (d or ddir).
 int bltc_internal_upload_symmetric(bltc_plan* plan, bltc::DevicePlan& d,
                                    const bltc::DirectLists& dl, std::vector<int64_t>* cost,
                                    hipStream_t s);
+// The result workspace of the planned mutual pairs, sized from what the
+// plan's workspace limit leaves once every other device array exists: one
+// round when all results fit (at most kPairWorkspaceBytes), else rounds.
+// BLTC_ENOMEM when the limit leaves no room for the largest pair.
+int bltc_internal_finish_pairs(bltc_plan* plan, hipStream_t s);
+// Enqueues the mutual-pair launches of d (every round, each folded into the
+// per-target sums when there are several).
+int bltc_internal_pairs(bltc_plan* plan, const bltc::DevicePlan& d, const bltc::KernelParams& kp,
+                        hipStream_t s);
+
+// Parameters left to the tuner (leaf_size = batch_size = 0, or threads per
+// target 0 for a one-vector BLTC or Hermite plan) filled in by timing plans
+// on the device (autotune.cpp; results cached as bltc_autotune's).  *out = *p
+// when nothing is open.
+int bltc_internal_tune(const bltc_params* p, int64_t nt, const double* tx, const double* ty,
+                       const double* tz, int64_t ns, const double* sx, const double* sy,
+                       const double* sz, int32_t max_q, bltc_params* out, void* stream);
 
 // cluster-particle plans (cp.cpp)
 namespace bltc_cp {

@@ -99,6 +99,12 @@ struct DevicePlan {
     int32_t* sym_pc_off = nullptr;
     int64_t* sym_pc_base = nullptr;
     int64_t* batch_begin = nullptr;
+    // results of the mutual pairs in several rounds through a bounded
+    // workspace (sym_rounds > 1): each round's results are folded into
+    // sym_acc (one FP64 value per target, tree order), and the interaction
+    // kernels read sym_acc through one entry per batch
+    int32_t sym_rounds = 0;
+    double* sym_acc = nullptr;
 };
 
 // Constants of the kernel G passed to the interaction kernels: kappa of the
@@ -186,13 +192,23 @@ inline NearLists near_lists(const DevicePlan& d)
 {
     if (d.sym)
         return NearLists{d.sym_near_off, d.sym_near_begin, d.sym_near_count, d.sym_near_leaf,
-                         d.sym_pc_off,   d.sym_pc_base,    d.sym_out,        d.batch_begin};
+                         d.sym_pc_off,   d.sym_pc_base,
+                         d.sym_rounds > 1 ? d.sym_acc : d.sym_out,            d.batch_begin};
     return NearLists{d.near_off, d.near_begin, d.near_count, d.near_leaf,
                      nullptr,    nullptr,      nullptr,      nullptr};
 }
-// near field of the mutual leaf pairs (kernels_sym.hip): d.sym_units units
-// into d.sym_out, FP64 or FP32-mixed as kp.precision
-hipError_t launch_near_pairs(const DevicePlan& d, const KernelParams& kp, hipStream_t s);
+// near field of the mutual leaf pairs (kernels_sym.hip): sub-units
+// d.sym_unit[first .. first + count) into d.sym_out, FP64 or FP32-mixed as
+// kp.precision
+hipError_t launch_near_pairs(const DevicePlan& d, int64_t first, int64_t count,
+                             const KernelParams& kp, hipStream_t s);
+// one round of mutual-pair results folded into the per-target sums: for batch
+// b (targets at [begin[b], end[b])) and target position p of the batch,
+// acc[begin[b] + p] = (first ? 0 : acc[...]) + sum over e in [off[b], off[b + 1])
+// of out[base[e] + p], in that order
+hipError_t launch_fold_pairs(int64_t nbatches, const int64_t* begin, const int64_t* end,
+                             const int32_t* off, const int64_t* base, const double* out,
+                             double* acc, bool first, hipStream_t s);
 // B targets per sub-unit of launch_near_pairs (one wave holds them all in
 // registers, 64 per chunk): FP32-mixed and FP64
 constexpr int64_t kSymTargetsMixed = 512;

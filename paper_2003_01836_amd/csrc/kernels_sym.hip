@@ -276,38 +276,74 @@ __global__ __launch_bounds__(64) void near_pairs_mixed(
     }
 }
 
+// One round of mutual-pair results into the per-target sums: one workgroup
+// per batch, one target per lane, the batch's entries of the round in order.
+__global__ __launch_bounds__(256) void fold_pairs(const int64_t* __restrict__ begin,
+                                                  const int64_t* __restrict__ end,
+                                                  const int32_t* __restrict__ off,
+                                                  const int64_t* __restrict__ base,
+                                                  const double* __restrict__ out,
+                                                  double* __restrict__ acc, int first)
+{
+    const int b = blockIdx.x;
+    const int64_t b0 = begin[b], b1 = end[b];
+    const int e0 = off[b], e1 = off[b + 1];
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) {
+        const int64_t p = i - b0;
+        double v = first ? 0.0 : acc[i];
+        for (int e = e0; e < e1; ++e)
+            v += out[base[e] + p];
+        acc[i] = v;
+    }
+}
+
 }  // namespace
 
-hipError_t launch_near_pairs(const DevicePlan& d, const KernelParams& kp, hipStream_t s)
+hipError_t launch_fold_pairs(int64_t nbatches, const int64_t* begin, const int64_t* end,
+                             const int32_t* off, const int64_t* base, const double* out,
+                             double* acc, bool first, hipStream_t s)
 {
-    if (!d.sym || d.sym_units == 0)
+    if (nbatches == 0)
         return hipSuccess;
-    if (!d.sym_unit || !d.sym_out)
+    if (!begin || !end || !off || !base || !out || !acc)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fold_pairs, dim3(static_cast<unsigned>(nbatches)), dim3(256), 0, s, begin,
+                       end, off, base, out, acc, first ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_near_pairs(const DevicePlan& d, int64_t first, int64_t count,
+                             const KernelParams& kp, hipStream_t s)
+{
+    if (!d.sym || count == 0)
+        return hipSuccess;
+    if (!d.sym_unit || !d.sym_out || first < 0 || first + count > d.sym_units)
         return hipErrorInvalidValue;
     const KernelConst kc = kp.kconst();
-    const dim3 grid(static_cast<unsigned>(d.sym_units));
+    const dim3 grid(static_cast<unsigned>(count));
+    const SymUnit* units = d.sym_unit + first;
     const size_t lds = 0;
     if (kp.precision == 1) {
         if (!d.src32 || !d.node_info || !d.batch_info)
             return hipErrorInvalidValue;
         if (kp.kernel == 1)
-            hipLaunchKernelGGL(near_pairs_mixed<1>, grid, dim3(64), lds, s, d.sym_unit, d.src,
+            hipLaunchKernelGGL(near_pairs_mixed<1>, grid, dim3(64), lds, s, units, d.src,
                                d.src32, d.node_info, d.batch_info, d.sym_out, kc);
         else if (kp.kernel == 2)
-            hipLaunchKernelGGL(near_pairs_mixed<2>, grid, dim3(64), lds, s, d.sym_unit, d.src,
+            hipLaunchKernelGGL(near_pairs_mixed<2>, grid, dim3(64), lds, s, units, d.src,
                                d.src32, d.node_info, d.batch_info, d.sym_out, kc);
         else
-            hipLaunchKernelGGL(near_pairs_mixed<0>, grid, dim3(64), lds, s, d.sym_unit, d.src,
+            hipLaunchKernelGGL(near_pairs_mixed<0>, grid, dim3(64), lds, s, units, d.src,
                                d.src32, d.node_info, d.batch_info, d.sym_out, kc);
     } else {
         if (kp.kernel == 1)
-            hipLaunchKernelGGL(near_pairs_f64<1>, grid, dim3(64), lds, s, d.sym_unit, d.src,
+            hipLaunchKernelGGL(near_pairs_f64<1>, grid, dim3(64), lds, s, units, d.src,
                                d.sym_out, kc);
         else if (kp.kernel == 2)
-            hipLaunchKernelGGL(near_pairs_f64<2>, grid, dim3(64), lds, s, d.sym_unit, d.src,
+            hipLaunchKernelGGL(near_pairs_f64<2>, grid, dim3(64), lds, s, units, d.src,
                                d.sym_out, kc);
         else
-            hipLaunchKernelGGL(near_pairs_f64<0>, grid, dim3(64), lds, s, d.sym_unit, d.src,
+            hipLaunchKernelGGL(near_pairs_f64<0>, grid, dim3(64), lds, s, units, d.src,
                                d.sym_out, kc);
     }
     return hipGetLastError();

@@ -507,7 +507,8 @@ void plan_schedule(HostPlan& hp)
                    hp.group_batch, hp.group_first);
 }
 
-bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, SymPlan& sp)
+bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, int64_t max_unit,
+                    SymPlan& sp)
 {
     if (sub < 1)
         return false;
@@ -565,7 +566,8 @@ bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, SymPlan
     for (const auto& u : units) {
         const int64_t nbk = batch_count[u.first], nck = batch_count[u.second];
         const int64_t ns = (nbk + sub - 1) / sub;
-        if (off + nbk + ns * nck > max_out)
+        const int64_t size = nbk + ns * nck;
+        if (size > max_unit || off + size > max_out)
             continue;
         unit_of[key(u.first, u.second)] = static_cast<int64_t>(out.ub.size());
         out.ub.push_back(u.first);
@@ -610,6 +612,26 @@ bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, SymPlan
         out.pc_off[b + 1] = static_cast<int32_t>(out.pc_base.size());
     }
     sp = std::move(out);
+    return true;
+}
+
+bool plan_pair_rounds(const SymPlan& sp, int64_t cap, std::vector<int32_t>& unit_begin,
+                      std::vector<int64_t>& base)
+{
+    unit_begin.assign(1, 0);
+    base.assign(1, 0);
+    const int64_t nu = static_cast<int64_t>(sp.ub.size());
+    for (int64_t u = 0; u < nu; ++u) {
+        const int64_t end = u + 1 < nu ? sp.roff[u + 1] : sp.out_size;   // offsets are ascending
+        if (end - sp.roff[u] > cap)
+            return false;
+        if (end - base.back() > cap) {
+            unit_begin.push_back(static_cast<int32_t>(u));
+            base.push_back(sp.roff[u]);
+        }
+    }
+    unit_begin.push_back(static_cast<int32_t>(nu));
+    base.push_back(sp.out_size);
     return true;
 }
 

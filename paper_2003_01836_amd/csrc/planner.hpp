@@ -140,10 +140,20 @@ struct DirectLists {
 };
 
 // Builds sp from the direct lists with sub-units of `sub` targets; the units
-// are taken heaviest first while out_size stays within max_out values (the
-// mutual pairs left over stay in the lists).  Returns false (sp untouched)
-// when no unit is taken or a direct entry is not a batch's leaf.
-bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, SymPlan& sp);
+// are taken heaviest first while out_size stays within max_out values, each
+// with at most max_unit result values (the mutual pairs left over stay in the
+// lists).  Returns false (sp untouched) when no unit is taken or a direct
+// entry is not a batch's leaf.
+bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, int64_t max_unit,
+                    SymPlan& sp);
+
+// Rounds of the mutual-pair results through a workspace of `cap` values: the
+// units of sp in their offset order (heaviest first), cut into runs whose
+// results fit in cap; round r holds units [unit_begin[r], unit_begin[r + 1])
+// and result offsets [base[r], base[r + 1]).  Returns false when one unit
+// alone needs more than cap values.
+bool plan_pair_rounds(const SymPlan& sp, int64_t cap, std::vector<int32_t>& unit_begin,
+                      std::vector<int64_t>& base);
 
 // Builds the tree with leaf capacity `cap` (readings of the tree rules are
 // documented in planner.cpp).

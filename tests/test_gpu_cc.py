@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.conftest import KERNEL_CASES, kernel_kwargs
+from tests.conftest import KERNEL_CASES, assert_mixed, kernel_kwargs
 from paper_2003_01836_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -150,7 +150,7 @@ def test_cc_mixed_matches_oracle(dev, kernel, kappa):
     ref = oracle.ClusterCluster(pos, pos, 0.7, 6, 400, 400).potential(q[0], kernel=kern,
                                                                         kappa=kappa)
     assert np.all(np.isfinite(phi))
-    assert oracle.rel_l2(ref, phi) <= MIXED_L2
+    assert_mixed(ref, phi, pos, pos, q[0], kern, kappa, what=f"cc {kernel}")
 
 
 def test_cc_full_size_sampled(dev):
@@ -164,7 +164,7 @@ def test_cc_full_size_sampled(dev):
         if precision == "fp64":
             _close(ref, phi[smp])
         else:
-            assert oracle.rel_l2(ref, phi[smp]) <= MIXED_L2
+            assert_mixed(ref, phi[smp], pos, pos, q[0], idx=smp, what="cc 1M sampled")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
@@ -193,7 +193,7 @@ def test_cc_edge_cases(dev, precision):
         if precision == "fp64":
             _close(ref, phi)
         else:
-            assert oracle.rel_l2(ref, phi) <= MIXED_L2
+            assert_mixed(ref, phi, tgt, src, q, what=f"cc edge n={n} leaf={leaf}")
 
 
 def test_cc_rejects_unsupported(dev):

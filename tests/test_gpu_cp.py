@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.conftest import KERNEL_CASES, kernel_kwargs
+from tests.conftest import KERNEL_CASES, assert_mixed, kernel_kwargs
 from paper_2003_01836_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -122,7 +122,7 @@ def test_cp_proxy_potentials_every_variant(dev, kernel, kappa, precision, theta,
     if precision == "fp64":
         _close(ref, phi)
     else:
-        assert oracle.rel_l2(ref, phi) <= MIXED_L2
+        assert_mixed(ref, phi, pos, pos, q[0], kern, kpar, what=f"cp {kernel} n={degree}")
 
 
 @pytest.mark.parametrize("degree,n,leaf", [(1, 12000, 64), (2, 12000, 64), (7, 12000, 256),
@@ -187,7 +187,7 @@ def test_cp_mixed_matches_oracle(dev, kernel, kappa):
     ref = oracle.ClusterParticle(pos, pos, 0.7, 6, 400, 400).potential(q[0], kernel=kern,
                                                                         kappa=kappa)
     assert np.all(np.isfinite(phi))
-    assert oracle.rel_l2(ref, phi) <= MIXED_L2
+    assert_mixed(ref, phi, pos, pos, q[0], kern, kappa, what=f"cp {kernel}")
 
 
 def test_cp_full_size_sampled(dev):
@@ -201,7 +201,7 @@ def test_cp_full_size_sampled(dev):
         if precision == "fp64":
             _close(ref, phi[smp])
         else:
-            assert oracle.rel_l2(ref, phi[smp]) <= MIXED_L2
+            assert_mixed(ref, phi[smp], pos, pos, q[0], idx=smp, what="cp 1M sampled")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
@@ -230,7 +230,7 @@ def test_cp_edge_cases(dev, precision):
         if precision == "fp64":
             _close(ref, phi)
         else:
-            assert oracle.rel_l2(ref, phi) <= MIXED_L2
+            assert_mixed(ref, phi, tgt, src, q, what=f"cp edge n={n} leaf={leaf}")
 
 
 def test_cp_rejects_unsupported(dev):

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.conftest import KERNEL_CASES, kernel_kwargs
+from tests.conftest import KERNEL_CASES, assert_mixed, kernel_kwargs
 from paper_2003_01836_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -221,7 +221,7 @@ def test_hermite_mixed_matches_oracle(dev, kernel, kappa, degree, n, leaf, batch
     oc = oracle.Treecode(pos, pos, 0.7, degree, leaf, batch, hermite=True)
     ref = oc.potential(q[0], kernel=kern, kappa=kpar)
     assert np.all(np.isfinite(phi))
-    assert oracle.rel_l2(ref, phi) <= MIXED_L2
+    assert_mixed(ref, phi, pos, pos, q[0], kern, kpar, what=f"hermite {kernel} n={degree}")
 
 
 @pytest.mark.parametrize("scale", [1e-7, 1e6])
@@ -235,7 +235,7 @@ def test_hermite_mixed_any_length_scale(dev, scale):
     assert plan.stats()["approx_pairs"] > 0
     ref = oracle.Treecode(pos, pos, 0.7, 4, 700, 700, hermite=True).potential(q[0])
     assert np.all(np.isfinite(phi))
-    assert oracle.rel_l2(ref, phi) <= MIXED_L2
+    assert_mixed(ref, phi, pos, pos, q[0], what=f"hermite scale {scale}")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])

@@ -37,12 +37,39 @@ def _soa(pos):
 
 @pytest.mark.parametrize("bad", [
     dict(theta=1.0), dict(theta=-0.1), dict(degree=0), dict(degree=17), dict(leaf_size=0),
-    dict(batch_size=0), dict(kappa=-1.0), dict(kernel=5), dict(precision=7),
+    dict(batch_size=0), dict(leaf_size=-1, batch_size=-1), dict(kappa=-1.0), dict(kernel=5),
+    dict(precision=7), dict(threads_per_target=3), dict(workspace_limit=-1),
 ])
 def test_invalid_parameters_are_rejected(bad):
     pos, _ = inputs.uniform_cube(100, 1)
     with pytest.raises(bltc.InvalidArgument):
         bltc.Plan(_soa(pos), _soa(pos), host=True, **bad)
+
+
+def test_zero_sizes_and_threads_on_host_plans():
+    # leaf_size = batch_size = 0 asks the tuner, which times plans on the device:
+    # a host plan cannot, and says so; threads_per_target = 0 is one lane there
+    pos, _ = inputs.uniform_cube(3000, 5)
+    with pytest.raises(bltc.BLTCError) as ei:
+        bltc.Plan(_soa(pos), _soa(pos), host=True, leaf_size=0, batch_size=0)
+    assert ei.value.code == _capi.BLTC_EUNSUPPORTED
+    assert "device coordinates" in str(ei.value)
+    p = bltc.Plan(_soa(pos), _soa(pos), host=True, leaf_size=300, batch_size=300,
+                  threads_per_target=0)
+    st = p.stats()
+    assert st["threads_per_target"] == 1 and st["leaf_size"] == 300
+    # the C defaults: one lane, no workspace limit
+    d = _capi.Params()
+    _capi.load().bltc_params_default(ctypes.byref(d))
+    assert d.threads_per_target == 1 and d.workspace_limit == 0 and d.leaf_size == 2000
+
+
+def test_workspace_is_not_held_by_host_plans():
+    pos, _ = inputs.uniform_cube(3000, 6)
+    st = bltc.Plan(_soa(pos), _soa(pos), host=True, leaf_size=200, batch_size=200,
+                   workspace_limit=1 << 20).stats()
+    # no device side yet: nothing held, no pair rounds planned
+    assert st["workspace_bytes"] == 0 and st["pair_rounds"] == 0
 
 
 def test_nonfinite_coordinates_are_rejected():
