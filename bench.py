@@ -26,20 +26,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X: 256 CU x 64 lanes x 2 flops x 2.4 GHz
-FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak
-# flop convention per kernel evaluation (one target, one source or proxy point):
-# 3 differences, 3 squares and 2 sums, 1 reciprocal square root, 1 multiply-add (2)
-FLOPS_COULOMB = 11
-FLOPS_YUKAWA = 15                   # + r = r^2 * (1/r), -kappa r, exp, product
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published FP32 vector peak (packed FP32)
+# Flop convention per kernel value (one target, one source or proxy point):
+# Coulomb 9 flops + 1 reciprocal square root = 10; Yukawa adds 1 exponential and
+# 2 flops = 13.  A mutual direct pair (targets = sources) forms one kernel value
+# that serves the row and the column term: + 1 multiply-add (2).
+FLOPS_COULOMB = 10
+FLOPS_YUKAWA = 13
+FLOPS_PAIR_EXTRA = 2
 # Hermite approximation, per grid point and target (Coulomb): distance 8, reciprocal
 # square root 1, g1..g3 from 1/r 6, d1 d2 and d1 d2 d3 2, first-order sum 5,
 # second-order sum 6, third-order product 1, combination with g0..g3 7, accumulate 1
 FLOPS_HERMITE_POINT = 37
-
-
-# a mutual direct pair (targets = sources): one kernel value (11) serving the
-# row term and the column term (+ 1 multiply-add, 2)
-FLOPS_MUTUAL_PAIR = 13
+FLOPS_MUTUAL_PAIR = FLOPS_COULOMB + FLOPS_PAIR_EXTRA
 
 MFMA_F64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 matrix peak
 KERNEL_SOURCES = {
@@ -51,12 +50,15 @@ KERNEL_SOURCES = {
 }
 
 
-# Issue-rate model of the FP32-mixed kernels: SIMD-cycles per wave instruction
-# (64 lanes) measured on the box by a dependency-free probe (8 independent
-# chains per lane) at the nominal clock: FP32 FMA-class instructions, and the
-# transcendental unit (v_rsq_f32, v_exp_f32), whose issue does not overlap.
-CYCLES_FMA32 = 2.86
-CYCLES_TRANS32 = 9.1
+# Issue-rate model of the interaction kernels: SIMD-cycles per wave instruction
+# (64 lanes), measured on the box by a dependency-free probe (8 independent
+# chains per lane, 16 waves per SIMD, at the nominal clock): FP32 FMA-class and
+# other 32-bit instructions, the FP32 transcendentals (v_rsq_f32, v_exp_f32),
+# FP64 add / multiply / FMA, and v_rsq_f64.  Their issue does not overlap.
+CYCLES_FMA32 = 2.66
+CYCLES_TRANS32 = 8.85
+CYCLES_F64 = 4.7
+CYCLES_TRANS64 = 17.1
 SIMDS = 1024                        # 256 CU x 4 SIMD
 CLOCK_HZ = 2.4e9
 
@@ -104,21 +106,31 @@ def counter_traffic(kernel, degree, ker_id, tpt=1):
 
 def issue_model(kernel, degree, ker_id, trans_per_eval, evals, ms, tpt=1):
     """Shortest time at which the SIMDs could issue the VALU instructions that the
-    kernel issues per launch (SQ_INSTS_VALU of the committed counter summary: one
-    transcendental per kernel value, or two for Yukawa, the rest FMA-class), and its
-    ratio to the measured launch time; None where no counters fit the kernel."""
-    valu = counter_value("valu_insts", "interact_uniform-1M_valu_counters.md", kernel, degree,
-                         ker_id, tpt)
-    if valu is None or not kernel.endswith("mixed"):
+    kernel issues per launch, from the committed counter summary (SQ_INSTS_VALU; for
+    the FP32-mixed kernels the FP32 transcendentals, one per kernel value or two for
+    Yukawa where no counter run took them; for the FP64 kernels the FP64 add, multiply
+    and FMA instructions and v_rsq_f64), each class at its probed issue cost, the rest
+    at the 32-bit rate; and its ratio to the measured launch time.  None where no
+    counters fit the kernel."""
+    prof = "interact_uniform-1M_valu_counters.md"
+    valu = counter_value("valu_insts", prof, kernel, degree, ker_id, tpt)
+    if valu is None:
         return None
-    # the counted transcendental instructions where a run took them, else the model
-    trans = counter_value("trans_insts", "interact_uniform-1M_valu_counters.md", kernel, degree,
-                          ker_id, tpt)
-    if trans is None:
-        trans = trans_per_eval * evals / 64.0
-    cycles = (valu - trans) * CYCLES_FMA32 + trans * CYCLES_TRANS32
+    if kernel.endswith("mixed"):
+        trans = counter_value("trans_insts", prof, kernel, degree, ker_id, tpt)
+        if trans is None:
+            trans = trans_per_eval * evals / 64.0
+        cycles = (valu - trans) * CYCLES_FMA32 + trans * CYCLES_TRANS32
+        parts = {"trans_insts": trans}
+    else:
+        f64 = counter_value("f64_insts", prof, kernel, degree, ker_id, tpt)
+        trans = counter_value("trans64_insts", prof, kernel, degree, ker_id, tpt)
+        if f64 is None or trans is None:
+            return None
+        cycles = f64 * CYCLES_F64 + trans * CYCLES_TRANS64 + (valu - f64 - trans) * CYCLES_FMA32
+        parts = {"f64_insts": f64, "trans64_insts": trans}
     t_min = cycles / SIMDS / CLOCK_HZ * 1e3
-    return {"valu_insts": valu, "trans_insts": trans, "t_min_ms": t_min, "frac": t_min / ms}
+    return {"valu_insts": valu, **parts, "t_min_ms": t_min, "frac": t_min / ms}
 
 
 def upward_roofline(degree, macs, ms):
@@ -247,6 +259,11 @@ def run_sweep(args, dev):
     t = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
     qd = torch.from_numpy(q[0]).to(dev)
     smp = inputs.sample_indices(n, 1000, inputs.sample_seed(2))
+    ds = None
+    if not args.no_cpu:
+        import oracle
+        log("sweep: oracle direct sum on the 1000 sampled targets")
+        ds = oracle.direct(pos[smp], pos, q[0], kernel=oracle.YUKAWA, kappa=0.5)
     rows = []
     for theta in (0.5, 0.7, 0.8):
         for deg in (4, 6, 8, 10):
@@ -272,10 +289,90 @@ def run_sweep(args, dev):
                 row = {"theta": theta, "n": deg, "precision": prec, "ms": ms,
                        "targets_per_s": n / (ms * 1e-3), "threads_per_target": tpt}
                 if ref is not None:
-                    row["E_par"] = rel_l2(ref, phi.cpu().numpy()[smp])
+                    got = phi.cpu().numpy()[smp]
+                    row["E_par"] = rel_l2(ref, got)
+                    row["E_tc"] = rel_l2(ds, got)
+                    row["oracle_E_tc"] = rel_l2(ds, ref)
                 rows.append(row)
                 log(f"sweep {row}")
     return {"workload": "yukawa-plummer-2M sweep", "rows": rows}
+
+
+def matched_accuracy(rows, slack=1.1):
+    """Time against error (eq. 16) of both paths: for every FP64 cell on the FP64
+    frontier (no faster FP64 cell with a smaller E_tc), the fastest FP32-mixed cell
+    whose E_tc is at most `slack` times that cell's, and the time ratio."""
+    f64 = sorted((r for r in rows if r["precision"] == "fp64"), key=lambda r: r["ms"])
+    mixed = [r for r in rows if r["precision"] == "fp32_mixed"]
+    frontier, best = [], float("inf")
+    for r in f64:
+        if r["E_tc"] < best:
+            frontier.append(r)
+            best = r["E_tc"]
+    out = []
+    for r in frontier:
+        cand = [m for m in mixed if m["E_tc"] <= slack * r["E_tc"] and m["E_par"] <= 1e-6]
+        m = min(cand, key=lambda x: x["ms"], default=None)
+        out.append({"E_tc_fp64": r["E_tc"], "fp64": (r["theta"], r["n"]), "fp64_ms": r["ms"],
+                    "fp32_mixed": None if m is None else (m["theta"], m["n"]),
+                    "mixed_ms": None if m is None else m["ms"],
+                    "E_tc_mixed": None if m is None else m["E_tc"],
+                    "speedup": None if m is None else r["ms"] / m["ms"]})
+    return out
+
+
+def run_accuracy(args, dev):
+    """Time against error on the headline geometry (10^6 uniform, Coulomb,
+    N_L = N_B = 2000): theta in {0.5, 0.7, 0.8, 0.9} x n in 3..10, both paths, threads
+    per target from the library's autotuner; E_tc against the oracle's direct sum
+    and E_par against the oracle treecode on the 1000 sampled targets (Sec. IV,
+    Fig. 4); then the matched-accuracy comparison of the two paths."""
+    import numpy as np
+    import torch
+
+    import paper_2003_01836_amd as bltc
+    from paper_2003_01836_amd import inputs
+
+    w = WORKLOADS["uniform-1M"]
+    n = w["n"]
+    pos, q = inputs.uniform_cube(n, inputs.config_seed(w["cfg"]))
+    t = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
+    qd = torch.from_numpy(q[0]).to(dev)
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    smp = inputs.sample_indices(n, w["samples"], inputs.sample_seed(w["cfg"]))
+    import oracle
+    log("accuracy: oracle direct sum on the 1000 sampled targets")
+    ds = oracle.direct(pos[smp], pos, q[0])
+    rows = []
+    for theta in args.thetas:
+        for deg in args.degrees:
+            oc = oracle.Treecode(pos, pos, theta, deg, w["leaf"], w["batch"])
+            ref = oc.potential(q[0], sample=smp)
+            del oc
+            for prec in ("fp64", "fp32_mixed"):
+                _, tpt, _ = bltc.autotune(t, t, candidates=(w["leaf"],), use_cache=False, full=True,
+                                          theta=theta, degree=deg, precision=prec)
+                plan = bltc.Plan(t, t, theta=theta, degree=deg, leaf_size=w["leaf"],
+                                 batch_size=w["batch"], precision=prec, threads_per_target=tpt)
+                for _ in range(max(1, args.warmup)):
+                    plan.execute(qd, out=phi)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    plan.execute(qd, out=phi)
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0) / args.steps
+                got = phi.cpu().numpy()[smp]
+                row = {"theta": theta, "n": deg, "precision": prec, "ms": ms,
+                       "targets_per_s": n / (ms * 1e-3), "threads_per_target": tpt,
+                       "E_par": rel_l2(ref, got), "E_tc": rel_l2(ds, got),
+                       "oracle_E_tc": rel_l2(ds, ref)}
+                rows.append(row)
+                del plan
+                log(f"accuracy {row}")
+    return {"workload": f"uniform-1M accuracy sweep: N={n} uniform [-1,1]^3, coulomb, "
+                        f"N_L=N_B={w['leaf']}, 1000 sampled targets",
+            "rows": rows, "matched": matched_accuracy(rows)}
 
 
 def run_large(args, dev):
@@ -307,7 +404,11 @@ def run_large(args, dev):
         ph = plan.phase_times()
         res[prec] = {"plan_s": t_plan, "phases_ms": ph, "targets_per_s": n / (ph["total"] * 1e-3),
                      "end_to_end_targets_per_s": n / (t_plan + ph["total"] * 1e-3),
-                     "far_evals": st["far_evals"], "near_evals": st["near_evals"]}
+                     "far_evals": st["far_evals"], "near_evals": st["near_evals"],
+                     "mutual_pairs": st["mutual_pairs"], "mutual_pair_evals": st["mutual_pair_evals"],
+                     "pair_rounds": st["pair_rounds"],
+                     "pair_workspace_bytes": st["pair_workspace_bytes"],
+                     "workspace_bytes": st["workspace_bytes"]}
         log(f"large {prec}: {ph}")
         if prec == "fp64":
             phi64 = phi.clone()
@@ -344,6 +445,19 @@ def run_large(args, dev):
         res["E_tc_oracle_300"] = {"fp64": rel_l2(od, g64[:300]), "fp32_mixed": rel_l2(od, gm[:300])}
         res["oracle_threads"] = oracle.max_threads()
         log(f"large: oracle cross-check {res['gpu_direct_vs_oracle_direct_300']:.3e}")
+        # E_par: the oracle treecode (host tree and lists of the whole set; modified
+        # charges of the clusters the sampled batches need) on the 10,000 targets
+        log("large: oracle treecode: building the trees and lists on the host")
+        oc = oracle.Treecode(post, post, 0.7, 8, 4000, 4000)
+        log(f"large: oracle treecode: {oc.n_batches} batches, {oc.n_clusters} clusters "
+            f"({oc.t_setup:.1f}s); modified charges and the sampled potentials")
+        ref, times = oc.potential(q, sample=smp, return_times=True)
+        del oc
+        res["E_par_10000"] = {"fp64": rel_l2(ref, g64), "fp32_mixed": rel_l2(ref, gm)}
+        res["oracle_E_tc_10000"] = rel_l2(ds, ref)
+        res["oracle_treecode_s"] = times
+        log(f"large: E_par on 10,000 targets {res['E_par_10000']}; oracle E_tc "
+            f"{res['oracle_E_tc_10000']:.3e}")
     return res
 
 
@@ -569,7 +683,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="uniform-1M",
                     choices=sorted(WORKLOADS) + ["batched-64x16", "yukawa-plummer-sweep", "uniform-large",
-                                                 "setup", "cp", "cc", "hermite"])
+                                                 "setup", "cp", "cc", "hermite", "accuracy-sweep"])
+    ap.add_argument("--thetas", type=float, nargs="+", default=[0.5, 0.7, 0.8, 0.9],
+                    help="accuracy-sweep workload: MAC parameters")
+    ap.add_argument("--degrees", type=int, nargs="+", default=[3, 4, 5, 6, 7, 8, 9, 10],
+                    help="accuracy-sweep workload: interpolation degrees")
     ap.add_argument("--large-n", type=int, default=128_000_000)
     ap.add_argument("--large-method", default="bltc", choices=["bltc", "cp", "cc"],
                     help="uniform-large workload: treecode variant")
@@ -604,10 +722,11 @@ def main():
         return 1
     dev = torch.device("cuda:0")
     if args.workload in ("batched-64x16", "yukawa-plummer-sweep", "uniform-large", "setup", "cp",
-                         "cc", "hermite"):
+                         "cc", "hermite", "accuracy-sweep"):
         fn = {"batched-64x16": run_batched, "yukawa-plummer-sweep": run_sweep,
               "uniform-large": run_large, "setup": run_setup, "cp": run_variant,
-              "cc": run_variant, "hermite": run_hermite}[args.workload]
+              "cc": run_variant, "hermite": run_hermite,
+              "accuracy-sweep": run_accuracy}[args.workload]
         print(json.dumps(fn(args, dev)), flush=True)
         return 0
     w = WORKLOADS[args.workload]
@@ -652,21 +771,19 @@ def main():
             plan.execute(qd, out=phi)
         torch.cuda.synchronize()
         log(f"{prec}: warmup done; timing {args.steps} steps")
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            plan.execute(qd, out=phi)
-        torch.cuda.synchronize()
-        t_total = time.perf_counter() - t0
-        ms_step = 1e3 * t_total / args.steps
-        # per-phase device times (HIP events on the execution stream), separate pass
+        # the timed steps record HIP events between the phases on the plan's
+        # stream (bltc_plan_set_timing); each step's phase times are read after it
         plan.set_timing(True)
         ph = {"gather": 0.0, "upward": 0.0, "interact": 0.0, "total": 0.0, "mutual_pairs": 0.0}
+        t0 = time.perf_counter()
         for _ in range(args.steps):
             plan.execute(qd, out=phi)
             for k, v in plan.phase_times().items():
                 ph[k] += v / args.steps
-        plan.set_timing(False)
         torch.cuda.synchronize()
+        t_total = time.perf_counter() - t0
+        plan.set_timing(False)
+        ms_step = 1e3 * t_total / args.steps
         got = phi.cpu().numpy()
         log(f"{prec}: {ms_step:.3f} ms/step; phases {ph}")
         results[prec] = dict(plan=plan, stats=st, ms=ms_step, phases=ph, phi=got, t_plan=t_plan,
@@ -698,47 +815,77 @@ def main():
                           f"batches need ({ctimes['upward']:.2f}s) + evaluation ({ctimes['eval']:.2f}s)")}
         log(f"oracle: {cpu['value']:.1f} targets/s on {cpu['cores']} threads")
 
-    # headline value: the fastest path that meets rel-L2 <= 1e-6 against the FP64 oracle
-    def ok(prec):
-        return (prec not in errors) or errors[prec]["E_par"] <= 1e-6
-    best = min((p for p in results if ok(p)), key=lambda p: results[p]["ms"], default="fp64")
-    r = results[best]
+    # headline: the FP64 path, the paper's precision (Sec. IV); the FP32-mixed path
+    # is reported beside it with its own roofline and the equal-accuracy test
+    head = "fp64" if "fp64" in results else precisions[0]
+    r = results[head]
     st = r["stats"]
-    flops_eval = FLOPS_YUKAWA if w["kernel"] == "yukawa" else FLOPS_COULOMB
-    flops_pair = flops_eval + 2
-    evals = st["far_evals"] + st["near_evals"]
     ker_id = 1 if w["kernel"] == "yukawa" else 0
-    peak = FP64_VECTOR_PEAK_TFLOPS if best == "fp64" else FP32_VECTOR_PEAK_TFLOPS
-    suffix = "f64" if best == "fp64" else "mixed"
-    # the interaction phase is two launches when mutual direct pairs are evaluated
-    # once: the pair kernel (kernel values = mutual_pair_evals, each serving two
-    # direct terms) and the batch kernel (far field, the other direct terms)
-    mutual = st.get("mutual_pair_evals", 0)
-    t_pairs = r["phases"].get("mutual_pairs", 0.0)
-    t_batch = r["phases"]["interact"] - t_pairs
-    kernels = {
-        f"interact_{suffix}": {"evals": evals - 2 * mutual, "flops_per_eval": flops_eval,
-                               "ms_per_launch": t_batch},
-    }
-    if mutual:
-        kernels[f"near_pairs_{suffix}"] = {"evals": mutual, "flops_per_eval": flops_pair,
-                                           "ms_per_launch": t_pairs}
     trans_per_eval = 2 if w["kernel"] == "yukawa" else 1
-    for kn, kv in kernels.items():
-        kv["achieved"] = kv["evals"] * kv["flops_per_eval"] / (kv["ms_per_launch"] * 1e-3) / 1e12
-        kv["frac"] = kv["achieved"] / peak
-        # the pair kernel does not depend on the threads per target
-        kt = r["tpt"] if kn.startswith("interact") else 1
-        kv["traffic"] = counter_traffic(kn, w["degree"], ker_id, kt)
-        kv["issue"] = issue_model(kn, w["degree"], ker_id, trans_per_eval, kv["evals"],
-                                  kv["ms_per_launch"], kt)
-    kname = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])
-    kd = kernels[kname]
-    phase_flops = sum(v["evals"] * v["flops_per_eval"] for v in kernels.values())
-    phase_achieved = phase_flops / (r["phases"]["interact"] * 1e-3) / 1e12
+    flops_eval = FLOPS_YUKAWA if w["kernel"] == "yukawa" else FLOPS_COULOMB
+
+    def path_roofline(prec, v):
+        """Roofline of one path's interaction launches: the pair kernel (kernel values
+        = mutual_pair_evals, each serving two direct terms) and the batch kernel (far
+        field, the other direct terms), each from its HIP-event time in the timed steps."""
+        sv = v["stats"]
+        evals = sv["far_evals"] + sv["near_evals"]
+        mutual = sv.get("mutual_pair_evals", 0)
+        t_pairs = v["phases"].get("mutual_pairs", 0.0)
+        t_batch = v["phases"]["interact"] - t_pairs
+        suffix = "f64" if prec == "fp64" else "mixed"
+        peak = FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+        kernels = {f"interact_{suffix}": {"evals": evals - 2 * mutual, "flops_per_eval": flops_eval,
+                                          "ms_per_launch": t_batch}}
+        if mutual:
+            kernels[f"near_pairs_{suffix}"] = {"evals": mutual,
+                                               "flops_per_eval": flops_eval + FLOPS_PAIR_EXTRA,
+                                               "ms_per_launch": t_pairs}
+        for kn, kv in kernels.items():
+            kv["achieved"] = kv["evals"] * kv["flops_per_eval"] / (kv["ms_per_launch"] * 1e-3) / 1e12
+            kv["frac"] = kv["achieved"] / peak
+            # the pair kernel does not depend on the threads per target
+            kt = v["tpt"] if kn.startswith("interact") else 1
+            kv["traffic"] = counter_traffic(kn, w["degree"], ker_id, kt)
+            kv["issue"] = issue_model(kn, w["degree"], ker_id, trans_per_eval, kv["evals"],
+                                      kv["ms_per_launch"], kt)
+        kname = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])
+        kd = kernels[kname]
+        phase_flops = sum(x["evals"] * x["flops_per_eval"] for x in kernels.values())
+        phase_achieved = phase_flops / (v["phases"]["interact"] * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": kd["achieved"], "peak": peak, "unit": "TFLOP/s",
+                "frac": kd["frac"], "traffic": kd["traffic"],
+                "kernel": kname, "flops_per_eval": kd["flops_per_eval"],
+                "evals_per_launch": kd["evals"], "ms_per_launch": kd["ms_per_launch"],
+                "issue": kd["issue"],
+                "interaction_kernels": kernels,
+                "interaction_phase": {"achieved": phase_achieved, "frac": phase_achieved / peak,
+                                      "ms": v["phases"]["interact"]},
+                "upward": upward_roofline(w["degree"], sv["upward_terms"], v["phases"]["upward"])}
+
+    paths = {}
+    for p, v in results.items():
+        ev = v["stats"]["far_evals"] + v["stats"]["near_evals"]
+        paths[p] = {"targets_per_s": n / (v["ms"] * 1e-3), "ms_per_step": v["ms"],
+                    "threads_per_target": v["tpt"], "phases_ms": v["phases"], "plan_s": v["t_plan"],
+                    "end_to_end_targets_per_s": n / (v["t_plan"] + v["ms"] * 1e-3),
+                    "terms_per_s": ev / (v["phases"]["interact"] * 1e-3),
+                    **errors.get(p, {})}
+        if p != head:
+            paths[p]["roofline"] = path_roofline(p, v)
+    if "fp64" in errors and "fp32_mixed" in errors:
+        e64, emx = errors["fp64"], errors["fp32_mixed"]
+        ratio = emx["E_tc"] / e64["E_tc"]
+        paths["fp32_mixed"]["E_tc_ratio_to_fp64"] = ratio
+        # equal accuracy: both paths within 1e-6 of the oracle treecode, and the
+        # mixed path's error against the direct sum at most 1.1 x the FP64 path's
+        paths["fp32_mixed"]["equal_accuracy"] = bool(e64["E_par"] <= 1e-6 and emx["E_par"] <= 1e-6
+                                                     and ratio <= 1.1)
+        paths["fp32_mixed"]["speedup_vs_fp64"] = results["fp64"]["ms"] / results["fp32_mixed"]["ms"]
+    valid = head not in errors or errors[head]["E_par"] <= 1e-6
     line = {
         "metric": "targets/s at rel-L2 err <=1e-6 (BLTC evaluation phase)",
-        "value": n / (r["ms"] * 1e-3),
+        "value": n / (r["ms"] * 1e-3) if valid else None,
         "unit": "targets/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -747,29 +894,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if best == "fp64" else "f32-mixed",
+        "dtype": "f64" if head == "fp64" else "f32-mixed",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: N={n} uniform [-1,1]^3, charges U[-1,1], "
                                f"{w['kernel']}, theta={w['theta']}, n={w['degree']}, "
-                               f"N_L=N_B={w['leaf']}", "path": best,
+                               f"N_L=N_B={w['leaf']}", "path": head,
                    "threads_per_target": r["tpt"]},
-        "roofline": {"bound": "alu", "achieved": kd["achieved"], "peak": peak, "unit": "TFLOP/s",
-                     "frac": kd["frac"], "traffic": kd["traffic"],
-                     "kernel": kname, "flops_per_eval": kd["flops_per_eval"],
-                     "evals_per_launch": kd["evals"], "ms_per_launch": kd["ms_per_launch"],
-                     "issue": kd["issue"],
-                     "interaction_kernels": kernels,
-                     "interaction_phase": {"achieved": phase_achieved, "frac": phase_achieved / peak,
-                                           "ms": r["phases"]["interact"]},
-                     "upward": upward_roofline(w["degree"], st["upward_terms"],
-                                               r["phases"]["upward"])},
+        "roofline": path_roofline(head, r),
         "cpu_baseline": cpu,
-        "paths": {p: {"targets_per_s": n / (v["ms"] * 1e-3), "ms_per_step": v["ms"],
-                      "threads_per_target": v["tpt"],
-                      "phases_ms": v["phases"], "plan_s": v["t_plan"],
-                      "end_to_end_targets_per_s": n / (v["t_plan"] + v["ms"] * 1e-3),
-                      "terms_per_s": evals / (v["phases"]["interact"] * 1e-3),
-                      **errors.get(p, {})} for p, v in results.items()},
+        "paths": paths,
         "oracle_E_tc": errors.get("oracle", {}).get("E_tc"),
         "stats": {k: st[k] for k in ("clusters", "batches", "approx_pairs", "direct_pairs",
                                      "far_evals", "near_evals", "upward_terms", "depth",

@@ -67,7 +67,13 @@ typedef enum {
  *  BLTC_FP32_MIXED  kernel evaluations in FP32 on local coordinates, partial
  *                   sums over at most one cluster in FP32, accumulated per target
  *                   in FP64; barycentric factors, the coincidence branch and
- *                   pairs closer than a fixed cut-off stay FP64. */
+ *                   pairs closer than a fixed cut-off stay FP64.  All points
+ *                   must lie in a box of side at most 2^60 (squared FP32
+ *                   distances stay finite); plan creation returns
+ *                   BLTC_EUNSUPPORTED otherwise.  A target closer than about
+ *                   1e-19 to a Chebyshev point of an approximated cluster
+ *                   (possible only for clusters of coincident points) loses
+ *                   that term: use BLTC_FP64 for such data. */
 typedef enum { BLTC_FP64 = 0, BLTC_FP32_MIXED = 1 } bltc_precision;
 
 /* Which side is interpolated.

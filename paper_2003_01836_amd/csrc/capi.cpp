@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -466,9 +467,69 @@ int upload_particle_cluster(bltc_plan* plan, hipStream_t s)
 
 }  // namespace
 
+namespace {
+
+// Side of the smallest cube-aligned box around every point of the plan's trees.
+double plan_extent(const bltc_plan* plan)
+{
+    double lo[3], hi[3];
+    for (int l = 0; l < 3; ++l) {
+        lo[l] = std::numeric_limits<double>::infinity();
+        hi[l] = -std::numeric_limits<double>::infinity();
+    }
+    auto take = [&](const bltc::Tree& t) {
+        if (t.nodes() == 0)
+            return;
+        for (int l = 0; l < 3; ++l) {   // node 0 is the root
+            lo[l] = std::min(lo[l], t.lo[l]);
+            hi[l] = std::max(hi[l], t.hi[l]);
+        }
+    };
+    if (plan->cp) {
+        take(plan->cpp.tgt);
+        take(plan->cpp.src);
+    } else if (plan->cc) {
+        take(plan->ccp.tgt);
+        take(plan->ccp.src);
+    } else {
+        take(plan->hp.src);
+        take(plan->hp.tgt);
+        const size_t nb = plan->hp.batch_lo.size() / 3;
+        for (size_t b = 0; b < nb; ++b)
+            for (int l = 0; l < 3; ++l) {
+                lo[l] = std::min(lo[l], plan->hp.batch_lo[3 * b + l]);
+                hi[l] = std::max(hi[l], plan->hp.batch_hi[3 * b + l]);
+            }
+    }
+    double ext = 0.0;
+    for (int l = 0; l < 3; ++l)
+        if (hi[l] >= lo[l])
+            ext = std::max(ext, hi[l] - lo[l]);
+    return ext;
+}
+
+}  // namespace
+
+// FP32-mixed kernels square coordinate differences in FP32: every distance
+// between two points of the plan must keep its square finite there.
+int bltc_internal_check_mixed_extent(const bltc_plan* plan)
+{
+    if (plan->prm.precision != BLTC_FP32_MIXED)
+        return BLTC_OK;
+    const double ext = plan_extent(plan);
+    if (ext <= bltc::kMixedMaxExtent)
+        return BLTC_OK;
+    return fail(BLTC_EUNSUPPORTED,
+                "FP32-mixed plans take points within a box of side at most 2^60 (%.3e here): "
+                "FP32 squared distances would overflow; use BLTC_FP64",
+                ext);
+}
+
 int bltc_internal_upload_plan(bltc_plan* plan, hipStream_t s)
 {
-    int rc = BLTC_OK;
+    int rc = plan->uploaded ? BLTC_OK : bltc_internal_check_mixed_extent(plan);
+    if (rc != BLTC_OK)
+        return rc;
     if (!plan->uploaded)
         rc = plan->cp ? bltc_cp::upload(plan, s)
            : plan->cc ? bltc_cc::upload(plan, s)
@@ -644,6 +705,8 @@ int create_from_host(bltc_plan** out, const bltc_params* p, int64_t nt, const do
             rc = bltc_cc::create_host(plan, plan_params(plan, p), nt, tx, ty, tz, ns, sx, sy, sz);
         else
             rc = make_host_plan(plan, p, nt, tx, ty, tz, ns, sx, sy, sz);
+        if (rc == BLTC_OK)
+            rc = bltc_internal_check_mixed_extent(plan);
     } catch (const std::bad_alloc&) {
         rc = fail(BLTC_ENOMEM, "host allocation failed while planning");
     } catch (const std::exception& ex) {
@@ -725,7 +788,9 @@ int bltc_internal_finish_pairs(bltc_plan* plan, hipStream_t s)
         for (int64_t b = 0; b < nb; ++b)
             ntgt = std::max(ntgt, pr.batch_begin[b] + pr.batch_count[b]);
         const int64_t npc = nb > 0 ? sp.pc_off[nb] : 0;
-        const int64_t fixed = units_bytes + ntgt * 8 + nb * 8 + npc * 8 + (nb + 1) * 4;
+        // pieces of several lanes per target read the sums through their own table
+        const int64_t piece_bytes = (&d == &plan->d && plan->tpt > 1) ? (nb * plan->tpt + 1) * 4 : 0;
+        const int64_t fixed = units_bytes + ntgt * 8 + nb * 8 + npc * 8 + (nb + 1) * 4 + piece_bytes;
         int64_t rounds = 1;
         for (int it = 0;; ++it) {
             const int64_t room = std::min<int64_t>(kPairWorkspaceBytes,
@@ -768,6 +833,8 @@ int bltc_internal_finish_pairs(bltc_plan* plan, hipStream_t s)
                 su.nc = static_cast<int32_t>(pr.batch_count[c]);
                 su.batch = b;
                 su.leaf = pr.batch_node[c];
+                su.apart = sp.apart[k];
+                su.pad = 0;
                 units.push_back(su);
             }
         }
@@ -862,6 +929,27 @@ int bltc_internal_pairs(bltc_plan* plan, const bltc::DevicePlan& d, const bltc::
         HIP_TRY(bltc::launch_fold_pairs(nb, d.batch_begin, pr.batch_end, pr.fold_off + r * (nb + 1),
                                         pr.fold_base, d.sym_out, d.sym_acc, r == 0, s));
     }
+    return BLTC_OK;
+}
+
+int bltc_internal_check_direct(const bltc_params* p, int64_t nt, const double* tx,
+                               const double* ty, const double* tz, int64_t ns, const double* sx,
+                               const double* sy, const double* sz, const double* q, int32_t num_q,
+                               const double* phi)
+{
+    int rc = check_params(p);
+    if (rc != BLTC_OK)
+        return rc;
+    if ((rc = check_coords(nt, tx, ty, tz, "target")) != BLTC_OK)
+        return rc;
+    if ((rc = check_coords(ns, sx, sy, sz, "source")) != BLTC_OK)
+        return rc;
+    if (num_q < 1)
+        return fail(BLTC_EINVAL, "num_q must be >= 1");
+    if (nt > 0 && !phi)
+        return fail(BLTC_EINVAL, "phi is NULL");
+    if (nt > 0 && ns > 0 && !q)
+        return fail(BLTC_EINVAL, "q is NULL");
     return BLTC_OK;
 }
 
@@ -1189,24 +1277,14 @@ int bltc_direct(const bltc_params* p, int64_t nt, const double* tx, const double
                 const double* q, int32_t num_q, int64_t q_ld, double* phi, int64_t phi_ld,
                 void* stream)
 {
-    int rc = check_params(p);
+    int rc = bltc_internal_check_direct(p, nt, tx, ty, tz, ns, sx, sy, sz, q, num_q, phi);
     if (rc != BLTC_OK)
         return rc;
-    if ((rc = check_coords(nt, tx, ty, tz, "target")) != BLTC_OK)
-        return rc;
-    if ((rc = check_coords(ns, sx, sy, sz, "source")) != BLTC_OK)
-        return rc;
-    if (num_q < 1)
-        return fail(BLTC_EINVAL, "num_q must be >= 1");
     if (nt == 0)
         return BLTC_OK;
-    if (!phi)
-        return fail(BLTC_EINVAL, "phi is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (ns == 0)
         return zero_phi(nt, num_q, phi, phi_ld, s);
-    if (!q)
-        return fail(BLTC_EINVAL, "q is NULL");
     double4* packed = nullptr;
     HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&packed), ns * sizeof(double4), s));
     bltc::KernelParams kp;

@@ -11,45 +11,39 @@ namespace bltc {
 namespace dev {
 
 // ---------------------------------------------------------------------------
-// FP64 reciprocal square root from the hardware estimate y0 (v_rsq_f64,
-// relative error about 2^-24), refined with e = 1 - r2*y0^2:
-//  * third-order Householder step y = y0 (1 + e/2 + 3e^2/8): truncation term
-//    5e^3/16, so the result is correct to rounding (direct sums, eq. 9);
-//  * second-order (Newton) step y = y0 (1 + e/2): truncation term 3e^2/8,
-//    a few 1e-15 relative, used for the proxy-point sums of eq. 11 whose own
-//    approximation error is many orders larger.
+// FP64 reciprocal square root from the hardware estimate y0 = v_rsq_f64(r2)
+// (relative error below 2^-22 on this device) and one Newton step in the form
+//   2/sqrt(r2) ~ y0 (3 - r2 y0^2),
+// three instructions (r2 y0, the fused 3 - (r2 y0) y0, the product with y0).
+// The step's truncation error is -(3/8) e^2 relative with e = 1 - r2 y0^2, at
+// most a few 1e-15 and of one sign; the interaction kernels accumulate the
+// doubled values and halve each sum once.  rsqrt2_f64_or_zero returns +0 for
+// r2 == 0: the estimate of 0 is +inf, whose low word is zero, so clearing its
+// high word gives y0 = +0 and then 0 (pairs at zero distance contribute
+// nothing, eq. 9).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double rsqrt_refine3(double r2, double y)
+__device__ __forceinline__ double newton2(double r2, double y)
 {
-    const double t = r2 * y;
-    const double e = __fma_rn(-t, y, 1.0);
-    const double p = __fma_rn(0.375, e, 0.5);
-    const double s = y * e;
-    return __fma_rn(s, p, y);
+    const double u = r2 * y;
+    return y * __fma_rn(-u, y, 3.0);
 }
 
-__device__ __forceinline__ double rsqrt_f64(double r2)
+__device__ __forceinline__ double rsqrt2_f64(double r2)
 {
-    return rsqrt_refine3(r2, __builtin_amdgcn_rsq(r2));
+    return newton2(r2, __builtin_amdgcn_rsq(r2));
 }
 
-__device__ __forceinline__ double rsqrt_f64_newton(double r2)
-{
-    const double y = __builtin_amdgcn_rsq(r2);
-    const double t = r2 * y;
-    const double e = __fma_rn(-t, y, 1.0);
-    return __fma_rn(y * e, 0.5, y);
-}
-
-// Estimate of 1/sqrt(r2) that is exactly +0 when r2 == 0: the estimate of 0 is
-// +inf, whose low word is zero, so clearing the high word yields +0 and the
-// refinement then returns 0.  Pairs at zero distance thus contribute nothing.
-__device__ __forceinline__ double rsqrt_f64_or_zero(double r2)
+__device__ __forceinline__ double rsqrt2_f64_or_zero(double r2)
 {
     const double y = __builtin_amdgcn_rsq(r2);
     const int lo = __double2loint(y);
     const int hi = r2 > 0.0 ? __double2hiint(y) : 0;
-    return rsqrt_refine3(r2, __hiloint2double(hi, lo));
+    return newton2(r2, __hiloint2double(hi, lo));
+}
+
+__device__ __forceinline__ double rsqrt_f64_newton(double r2)
+{
+    return 0.5 * rsqrt2_f64(r2);
 }
 
 // ---------------------------------------------------------------------------
@@ -92,34 +86,48 @@ __device__ __forceinline__ double exp_f64(double x, const double* __restrict__ t
 }
 
 // G as a function of r^2 (eq. 2; KER 0 Coulomb 1/r, 1 Yukawa exp(-kappa r)/r,
-// 2 regularized Coulomb (r^2 + delta^2)^(-1/2)).  green_far_f64: well-separated
-// points (r > 0), 1/sqrt by one Newton step; green_near_f64: any pair, zero at
-// r = 0 (pairs at zero distance are skipped).
+// 2 regularized Coulomb (r^2 + delta^2)^(-1/2)), doubled: green_far2_f64 for
+// well-separated points (r > 0), green_near2_f64 for any pair, zero at r = 0
+// (pairs at zero distance are skipped).  With h = 2/r from rsqrt2, Yukawa's
+// exponent -kappa r is -(kappa / 2) r^2 h.  green_far_f64 / green_near_f64 are
+// the plain values.
+template <int KER>
+__device__ __forceinline__ double green_far2_f64(double r2, const KernelArg& ka)
+{
+    if constexpr (KER == 0) {
+        return rsqrt2_f64(r2);
+    } else if constexpr (KER == 1) {
+        const double h = rsqrt2_f64(r2);
+        return exp_f64(-0.5 * ka.kappa * (r2 * h), ka.tab) * h;
+    } else {
+        return rsqrt2_f64(r2 + ka.delta2);
+    }
+}
+
+template <int KER>
+__device__ __forceinline__ double green_near2_f64(double r2, const KernelArg& ka)
+{
+    if constexpr (KER == 0) {
+        return rsqrt2_f64_or_zero(r2);
+    } else if constexpr (KER == 1) {
+        const double h = rsqrt2_f64_or_zero(r2);
+        return exp_f64(-0.5 * ka.kappa * (r2 * h), ka.tab) * h;
+    } else {
+        const double g = rsqrt2_f64(r2 + ka.delta2);
+        return r2 == 0.0 ? 0.0 : g;
+    }
+}
+
 template <int KER>
 __device__ __forceinline__ double green_far_f64(double r2, const KernelArg& ka)
 {
-    if constexpr (KER == 0) {
-        return rsqrt_f64_newton(r2);
-    } else if constexpr (KER == 1) {
-        const double rinv = rsqrt_f64_newton(r2);
-        return exp_f64(-ka.kappa * (r2 * rinv), ka.tab) * rinv;
-    } else {
-        return rsqrt_f64_newton(r2 + ka.delta2);
-    }
+    return 0.5 * green_far2_f64<KER>(r2, ka);
 }
 
 template <int KER>
 __device__ __forceinline__ double green_near_f64(double r2, const KernelArg& ka)
 {
-    if constexpr (KER == 0) {
-        return rsqrt_f64_or_zero(r2);
-    } else if constexpr (KER == 1) {
-        const double rinv = rsqrt_f64_or_zero(r2);
-        return exp_f64(-ka.kappa * (r2 * rinv), ka.tab) * rinv;
-    } else {
-        const double g = rsqrt_f64(r2 + ka.delta2);
-        return r2 == 0.0 ? 0.0 : g;
-    }
+    return 0.5 * green_near2_f64<KER>(r2, ka);
 }
 
 // FP32 kernel values (FP32-mixed path): nk = -kappa log2(e); r^2 > 0 (pairs at
@@ -149,17 +157,25 @@ __device__ __forceinline__ float green_f32(float r2, const KernelArg32& ka)
 
 // ---------------------------------------------------------------------------
 // Direct batch/cluster sum over a contiguous source range (eq. 9), pairs at
-// zero distance skipped.  `s` is wave-uniform.
+// zero distance skipped.  `s` is wave-uniform.  The four partial sums hold
+// doubled terms and are halved once.
 // ---------------------------------------------------------------------------
 template <int KER>
-__device__ __forceinline__ double near_term_f64(double x, double y, double z, const double4 p,
-                                                const KernelArg& kappa)
+__device__ __forceinline__ double near_term2_f64(double x, double y, double z, const double4 p,
+                                                 const KernelArg& kappa)
 {
     const double dx = x - p.x;
     const double dy = y - p.y;
     const double dz = z - p.z;
     const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-    return green_near_f64<KER>(r2, kappa) * p.w;
+    return green_near2_f64<KER>(r2, kappa) * p.w;
+}
+
+template <int KER>
+__device__ __forceinline__ double near_term_f64(double x, double y, double z, const double4 p,
+                                                const KernelArg& kappa)
+{
+    return 0.5 * near_term2_f64<KER>(x, y, z, p, kappa);
 }
 
 template <int KER>
@@ -170,14 +186,14 @@ __device__ __forceinline__ double near_sum_f64(double x, double y, double z,
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int32_t j = 0;
     for (; j + 4 <= cnt; j += 4) {
-        a0 += near_term_f64<KER>(x, y, z, s[j], kappa);
-        a1 += near_term_f64<KER>(x, y, z, s[j + 1], kappa);
-        a2 += near_term_f64<KER>(x, y, z, s[j + 2], kappa);
-        a3 += near_term_f64<KER>(x, y, z, s[j + 3], kappa);
+        a0 += near_term2_f64<KER>(x, y, z, s[j], kappa);
+        a1 += near_term2_f64<KER>(x, y, z, s[j + 1], kappa);
+        a2 += near_term2_f64<KER>(x, y, z, s[j + 2], kappa);
+        a3 += near_term2_f64<KER>(x, y, z, s[j + 3], kappa);
     }
     for (; j < cnt; ++j)
-        a0 += near_term_f64<KER>(x, y, z, s[j], kappa);
-    return (a0 + a1) + (a2 + a3);
+        a0 += near_term2_f64<KER>(x, y, z, s[j], kappa);
+    return 0.5 * ((a0 + a1) + (a2 + a3));
 }
 
 }  // namespace dev

@@ -232,6 +232,16 @@ int bltc_internal_tune(const bltc_params* p, int64_t nt, const double* tx, const
                        const double* tz, int64_t ns, const double* sx, const double* sy,
                        const double* sz, int32_t max_q, bltc_params* out, void* stream);
 
+// BLTC_EUNSUPPORTED for an FP32-mixed plan whose points do not fit in a box of
+// side kMixedMaxExtent (capi.cpp); BLTC_OK otherwise.
+int bltc_internal_check_mixed_extent(const bltc_plan* plan);
+
+// Argument checks of bltc_direct and bltc_direct_noalloc (capi.cpp).
+int bltc_internal_check_direct(const bltc_params* p, int64_t nt, const double* tx,
+                               const double* ty, const double* tz, int64_t ns, const double* sx,
+                               const double* sy, const double* sz, const double* q, int32_t num_q,
+                               const double* phi);
+
 // cluster-particle plans (cp.cpp)
 namespace bltc_cp {
 int create_host(bltc_plan* plan, const bltc::PlanParams& pp, int64_t nt, const double* tx,

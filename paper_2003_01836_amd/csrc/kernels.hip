@@ -49,7 +49,7 @@ __device__ __forceinline__ double far_sum_f64(double x, double y, double z,
 #pragma unroll
             for (int k3 = 0; k3 < NP; ++k3) {
                 const double r2 = ab + c2[k3];
-                const double g = green_far_f64<KER>(r2, kappa);
+                const double g = green_far2_f64<KER>(r2, kappa);
                 if ((k2 + k3) & 1)
                     acc1 = __fma_rn(g, q1[k2 * NP + k3], acc1);
                 else
@@ -57,7 +57,7 @@ __device__ __forceinline__ double far_sum_f64(double x, double y, double z,
             }
         }
     }
-    return acc0 + acc1;
+    return 0.5 * (acc0 + acc1);   // the terms are doubled (green_far2_f64)
 }
 
 // ---------------------------------------------------------------------------

@@ -36,6 +36,8 @@ struct SymUnit {
     int32_t nb, nc;
     int32_t batch;    // B's batch (batch_info)
     int32_t leaf;     // C's node (node_info)
+    int32_t apart;    // 1: no pair of the unit is at zero distance (SymPlan::apart)
+    int32_t pad;
 };
 
 // Device-side view of a plan (all device pointers).
@@ -212,10 +214,13 @@ hipError_t launch_fold_pairs(int64_t nbatches, const int64_t* begin, const int64
 // B targets per sub-unit of launch_near_pairs (one wave holds them all in
 // registers, 64 per chunk): FP32-mixed and FP64
 constexpr int64_t kSymTargetsMixed = 512;
-constexpr int64_t kSymTargetsF64 = 256;
+constexpr int64_t kSymTargetsF64 = 512;
 // the FP32-mixed path computes the kernel values of pairs closer than
 // kMixedTauRel * (distance of the box centers + r_B + 2 r_C) from FP64 coordinates
 constexpr double kMixedTauRel = 2.4e-2;
+// side of the largest box of points the FP32-mixed path takes: squared FP32
+// distances stay below 3 * 2^120, finite
+constexpr double kMixedMaxExtent = 0x1p60;
 // batch/cluster interactions: eqs. 9 and 11, phi written in caller order
 hipError_t launch_interact(const DevicePlan& d, const KernelParams& kp, double* phi,
                            hipStream_t s);

@@ -14,6 +14,16 @@
 // sub-unit's targets of column l mod kBlk, which lanes 0..kBlk-1 store; the
 // butterfly's cost is shared by the kChunks targets of a lane.  Every sum has
 // a fixed order, so the results are deterministic.
+//
+// FP32-mixed rounding: a column sum covers up to 512 target terms, but as 64
+// lane sums of at most kChunks = 8 terms combined by the butterfly's 6 levels
+// of pairwise additions, so its rounding error is at most (8 + 6) eps32 times
+// the sum of the magnitudes of its terms -- that of a 14-term sequential sum,
+// below the row sums' (at most kFlushEvery = 128 FP32 terms, then FP64).  A
+// close pair's kernel value comes from the FP64 coordinates and is rounded
+// once to FP32 like every other value: the FP64 branch removes the coordinate
+// rounding that 1/r amplifies for close pairs, and what is left is one FP32
+// rounding of the value and one of its product with the charge.
 #include "kernels.hpp"
 #include "device_common.hpp"
 
@@ -24,7 +34,7 @@ using namespace dev;
 
 constexpr int kBlk = 8;           // sources per butterfly block
 constexpr int kChunks = 8;        // 64-target chunks held in registers (FP32-mixed)
-constexpr int kChunks64 = 4;      // the same for the FP64 kernel (twice the registers)
+constexpr int kChunks64 = 8;      // the same for the FP64 kernel
 static_assert(kSymTargetsMixed == 64 * kChunks && kSymTargetsF64 == 64 * kChunks64,
               "sub-unit sizes");
 
@@ -56,16 +66,28 @@ __device__ __forceinline__ T column_sums(T (&v)[kBlk], int lane)
 // ---------------------------------------------------------------------------
 // FP64
 // ---------------------------------------------------------------------------
-template <int KER>
-__global__ __launch_bounds__(64) void near_pairs_f64(const SymUnit* __restrict__ units,
-                                                     const double4* __restrict__ src,
-                                                     double* __restrict__ out, KernelConst kc)
+// One mutual pair: the doubled kernel value serves the row term (into the
+// target's sum `row`) and the column term (into the source's column `col`).
+// CHECK = false: the unit's leaves are apart (r^2 > 0 for every pair), so the
+// zero-distance test of green_near2_f64 is left out.
+template <int KER, bool CHECK>
+__device__ __forceinline__ void pair_term_f64(double tx, double ty, double tz, double tq,
+                                              const double4 p, const KernelArg& ka, double& row,
+                                              double& col)
 {
-    __shared__ double exp_tab[64];
-    if constexpr (KER == 1)
-        fill_exp2_table(exp_tab);
-    const KernelArg ka{kc.kappa, kc.delta2, exp_tab};
-    const SymUnit u = units[blockIdx.x];
+    const double dx = tx - p.x;
+    const double dy = ty - p.y;
+    const double dz = tz - p.z;
+    const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
+    const double g = CHECK ? green_near2_f64<KER>(r2, ka) : green_far2_f64<KER>(r2, ka);  // 2 G
+    row = __fma_rn(g, p.w, row);
+    col = __fma_rn(g, tq, col);
+}
+
+template <int KER, bool CHECK>
+__device__ __forceinline__ void pairs_unit_f64(const SymUnit& u, const double4* __restrict__ src,
+                                               double* __restrict__ out, const KernelArg& ka)
+{
     const int lane = threadIdx.x;
     const double4* __restrict__ S = src + u.sb;
     const int nch = (u.nb + 63) / 64;   // uniform, <= kChunks64 by construction
@@ -82,8 +104,33 @@ __global__ __launch_bounds__(64) void near_pairs_f64(const SymUnit* __restrict__
         a0[k] = 0.0;
         a1[k] = 0.0;
     }
-    for (int s0 = 0; s0 < u.nc; s0 += kBlk) {
-        const int cnt = min(kBlk, u.nc - s0);   // uniform
+    // full blocks: the kBlk sources are loaded once (wave-uniform, into SGPRs)
+    // and serve every chunk of targets
+    int s0 = 0;
+    for (; s0 + kBlk <= u.nc; s0 += kBlk) {
+        double4 p[kBlk];
+#pragma unroll
+        for (int m = 0; m < kBlk; ++m)
+            p[m] = S[s0 + m];
+        double v[kBlk];
+#pragma unroll
+        for (int m = 0; m < kBlk; ++m)
+            v[m] = 0.0;
+#pragma unroll
+        for (int k = 0; k < kChunks64; ++k) {
+            if (k >= nch)
+                break;
+#pragma unroll
+            for (int m = 0; m < kBlk; ++m)
+                pair_term_f64<KER, CHECK>(tx[k], ty[k], tz[k], tq[k], p[m], ka,
+                                          (m & 1) ? a1[k] : a0[k], v[m]);
+        }
+        const double cs = column_sums(v, lane);
+        out[u.coff + s0 + (lane & (kBlk - 1))] = 0.5 * cs;   // lanes l, l + kBlk, ... agree
+    }
+    if (s0 < u.nc) {
+        // the last, partial block
+        const int cnt = u.nc - s0;   // uniform, < kBlk
         double v[kBlk];
 #pragma unroll
         for (int m = 0; m < kBlk; ++m)
@@ -96,29 +143,40 @@ __global__ __launch_bounds__(64) void near_pairs_f64(const SymUnit* __restrict__
             for (int m = 0; m < kBlk; ++m) {
                 if (m >= cnt)
                     break;
-                const double4 p = S[s0 + m];
-                const double dx = tx[k] - p.x;
-                const double dy = ty[k] - p.y;
-                const double dz = tz[k] - p.z;
-                const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-                const double g = green_near_f64<KER>(r2, ka);
-                if (m & 1)
-                    a1[k] = __fma_rn(g, p.w, a1[k]);
-                else
-                    a0[k] = __fma_rn(g, p.w, a0[k]);
-                v[m] = __fma_rn(g, tq[k], v[m]);
+                pair_term_f64<KER, CHECK>(tx[k], ty[k], tz[k], tq[k], S[s0 + m], ka,
+                                          (m & 1) ? a1[k] : a0[k], v[m]);
             }
         }
         const double cs = column_sums(v, lane);
         if (lane < cnt)
-            out[u.coff + s0 + lane] = cs;
+            out[u.coff + s0 + lane] = 0.5 * cs;
     }
 #pragma unroll
     for (int k = 0; k < kChunks64; ++k) {
         const int i = 64 * k + lane;
         if (k < nch && i < u.nb)
-            out[u.roff + i] = a0[k] + a1[k];
+            out[u.roff + i] = 0.5 * (a0[k] + a1[k]);
     }
+}
+
+// Two waves per SIMD: 8 chunks of targets and a source block in flight take
+// about 250 VGPRs (one wave per SIMD when left to the compiler, or spills at
+// three); measured on 10^6 particles, 19.2 ms against 24.9 ms (one wave) and
+// 20.5 ms (4 chunks, three waves).
+template <int KER>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void near_pairs_f64(
+    const SymUnit* __restrict__ units, const double4* __restrict__ src, double* __restrict__ out,
+    KernelConst kc)
+{
+    __shared__ double exp_tab[64];
+    if constexpr (KER == 1)
+        fill_exp2_table(exp_tab);
+    const KernelArg ka{kc.kappa, kc.delta2, exp_tab};
+    const SymUnit u = units[blockIdx.x];
+    if (u.apart)
+        pairs_unit_f64<KER, false>(u, src, out, ka);
+    else
+        pairs_unit_f64<KER, true>(u, src, out, ka);
 }
 
 // ---------------------------------------------------------------------------

@@ -17,6 +17,7 @@
 #include "planner.hpp"
 
 #include <algorithm>
+#include <limits>
 #include <map>
 #include <unordered_map>
 #include <atomic>
@@ -573,6 +574,15 @@ bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, int64_t
         out.ub.push_back(u.first);
         out.uc.push_back(u.second);
         out.nsub.push_back(static_cast<int32_t>(ns));
+        // separation of the two leaves' boxes (points with equal coordinates
+        // always share a leaf, so distinct leaves have a positive gap; the
+        // test guards against squares that would underflow)
+        const int64_t bn = batch_node[u.first], cn = batch_node[u.second];
+        double gap = -std::numeric_limits<double>::infinity();
+        for (int l = 0; l < 3; ++l)
+            gap = std::max(gap, std::max(S.lo[3 * cn + l] - S.hi[3 * bn + l],
+                                         S.lo[3 * bn + l] - S.hi[3 * cn + l]));
+        out.apart.push_back(gap >= 0x1p-500 ? 1 : 0);
         out.roff.push_back(off);
         out.coff.push_back(off + nbk);
         off += nbk + ns * nck;

@@ -111,6 +111,9 @@ struct SymPlan {
     std::vector<int32_t> ub, uc;        // batches of a unit, ub < uc; heaviest unit first
     std::vector<int64_t> roff, coff;    // out offsets of a unit's rows and first column block
     std::vector<int32_t> nsub;          // sub-units of a unit: ceil(|B| / sub)
+    // 1 when the two leaves' boxes are at least 2^-500 apart in some dimension:
+    // every pair of the unit then has r^2 >= 2^-1000 > 0 (no zero-distance test)
+    std::vector<uint8_t> apart;
     int64_t sub = 0;                    // B targets per sub-unit
     int64_t out_size = 0;
     int64_t pair_evals = 0;             // sum over units of |B| |C|

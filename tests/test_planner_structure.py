@@ -72,6 +72,28 @@ def test_workspace_is_not_held_by_host_plans():
     assert st["workspace_bytes"] == 0 and st["pair_rounds"] == 0
 
 
+@pytest.mark.parametrize("method", ["bltc", "cp", "cc", "hermite"])
+def test_fp32_mixed_coordinate_range(method):
+    # FP32-mixed kernels square coordinate differences in FP32: points spread
+    # over more than 2^60 are refused (FP64 takes them), up to 2^60 accepted
+    pos, _ = inputs.uniform_cube(2000, 7)
+    deg = 2 if method == "hermite" else 4
+    kw = dict(host=True, method=method, leaf_size=200, batch_size=200, degree=deg)
+    wide = pos * 2.0 ** 60          # side 2^61
+    with pytest.raises(bltc.BLTCError) as ei:
+        bltc.Plan(_soa(wide), _soa(wide), precision="fp32_mixed", **kw)
+    assert ei.value.code == _capi.BLTC_EUNSUPPORTED and "2^60" in str(ei.value)
+    bltc.Plan(_soa(wide), _soa(wide), precision="fp64", **kw)
+    ok = pos * 2.0 ** 58            # side 2^59
+    bltc.Plan(_soa(ok), _soa(ok), precision="fp32_mixed", **kw)
+    # targets and sources apart: the box around both counts
+    far = pos.copy()
+    far[:, 0] += 2.0 ** 61
+    with pytest.raises(bltc.BLTCError) as ei:
+        bltc.Plan(_soa(far), _soa(pos), precision="fp32_mixed", **kw)
+    assert ei.value.code == _capi.BLTC_EUNSUPPORTED
+
+
 def test_nonfinite_coordinates_are_rejected():
     pos, _ = inputs.uniform_cube(100, 1)
     pos[17, 1] = np.nan
