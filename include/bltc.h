@@ -387,6 +387,23 @@ int bltc_direct(const bltc_params* p,
                 const double* q, int32_t num_q, int64_t q_ld,
                 double* phi, int64_t phi_ld, void* stream);
 
+/* bltc_direct without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, checks and results as bltc_direct; the
+ * per-vector staging of the sources (x, y, z, q records, 32 B per source)
+ * goes to a fixed array of 2^20 records (32 MiB) in device memory, one per GPU,
+ * that the library holds until the process ends.  ns > 2^20 returns
+ * BLTC_EUNSUPPORTED (use bltc_direct).  Calls no hipMalloc/hipFree; the first
+ * call on a device looks up that device's address of the array.  All calls on
+ * one GPU share its array: calls that overlap in time on one GPU (different
+ * streams, or host threads) race and must be serialised by the caller.
+ * Enqueued on `stream`. */
+int bltc_direct_noalloc(const bltc_params* p,
+                        int64_t nt, const double* tx, const double* ty, const double* tz,
+                        int64_t ns, const double* sx, const double* sy, const double* sz,
+                        const double* q, int32_t num_q, int64_t q_ld,
+                        double* phi, int64_t phi_ld, void* stream);
+
 const char* bltc_status_string(int code);
 const char* bltc_last_error(void);     /* message of the calling thread's last failure */
 const char* bltc_version(void);

@@ -338,8 +338,10 @@ def potential(targets, sources, charges, *, stream=None, out=None, **kw):
 
 
 def direct(targets, sources, charges, *, stream=None, out=None, kernel="coulomb", kappa=0.0,
-           delta=0.0):
-    """GPU FP64 direct sum of eq. (1) (`bltc_direct`)."""
+           delta=0.0, noalloc=False):
+    """GPU FP64 direct sum of eq. (1) (`bltc_direct`); with noalloc=True the variant
+    that allocates no device memory (`bltc_direct_noalloc`, at most 2^20 sources;
+    pass `out` to keep the call free of allocations here too)."""
     torch = _torch()
     lib = _capi.load()
     p = params(kernel=kernel, kappa=kappa, delta=delta)
@@ -350,8 +352,9 @@ def direct(targets, sources, charges, *, stream=None, out=None, kernel="coulomb"
     if out is None:
         out = torch.empty((m, nt), dtype=torch.float64, device=q2.device)
     o2 = out.unsqueeze(0) if out.dim() == 1 else out
-    rc = lib.bltc_direct(ctypes.byref(p), nt, *tp, ns, *sp, ctypes.c_void_p(q2.data_ptr()), m,
-                         q2.stride(0) if m > 1 else ns, ctypes.c_void_p(o2.data_ptr()),
-                         o2.stride(0) if m > 1 else nt, _stream_handle(stream))
+    fn = lib.bltc_direct_noalloc if noalloc else lib.bltc_direct
+    rc = fn(ctypes.byref(p), nt, *tp, ns, *sp, ctypes.c_void_p(q2.data_ptr()), m,
+            q2.stride(0) if m > 1 else ns, ctypes.c_void_p(o2.data_ptr()),
+            o2.stride(0) if m > 1 else nt, _stream_handle(stream))
     _capi.check(rc)
     return out[0] if (one and out.dim() == 2) else out

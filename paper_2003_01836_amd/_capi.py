@@ -31,7 +31,7 @@ EXPORTS = (
     "bltc_plan_set_timing", "bltc_plan_phase_times", "bltc_plan_destroy", "bltc_direct",
     "bltc_batch_create", "bltc_batch_execute", "bltc_batch_set_graph", "bltc_batch_info_get",
     "bltc_batch_destroy", "bltc_batch_potential", "bltc_autotune", "bltc_status_string",
-    "bltc_last_error", "bltc_version",
+    "bltc_last_error", "bltc_version", "bltc_direct_noalloc",
 )
 
 
@@ -136,6 +136,7 @@ def load():
     lib.bltc_plan_destroy.argtypes = [vp]
     lib.bltc_plan_destroy.restype = None
     lib.bltc_direct.argtypes = [PP, i64, vp, vp, vp, i64, vp, vp, vp, vp, i32, i64, vp, i64, vp]
+    lib.bltc_direct_noalloc.argtypes = lib.bltc_direct.argtypes
     lib.bltc_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
     lib.bltc_batch_execute.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(i32),
                                        ctypes.POINTER(i64), ctypes.POINTER(vp), ctypes.POINTER(i64), vp]
@@ -156,7 +157,7 @@ def load():
                  "bltc_plan_modified_charges", "bltc_plan_stats", "bltc_plan_view_get", "bltc_direct",
                  "bltc_plan_set_timing", "bltc_plan_phase_times", "bltc_batch_create",
                  "bltc_batch_execute", "bltc_batch_set_graph", "bltc_batch_info_get",
-                 "bltc_batch_potential", "bltc_autotune"):
+                 "bltc_batch_potential", "bltc_autotune", "bltc_direct_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -74,6 +74,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
         "kernels_hermite": os.path.join(build_dir, "kernels_hermite.o"),
         "kernels_sym": os.path.join(build_dir, "kernels_sym.o"),
         "kernels_split": os.path.join(build_dir, "kernels_split.o"),
+        "noalloc": os.path.join(build_dir, "noalloc.o"),
     }
     cmds = [
         ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "planner.cpp"), "-o", objs["planner"]],
@@ -98,6 +99,7 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
                                objs["kernels_sym"]],
         [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "kernels_split.hip"), "-o",
                                objs["kernels_split"]],
+        [hipcc] + hip_flags + ["-c", os.path.join(CSRC, "noalloc.hip"), "-o", objs["noalloc"]],
     ]
     if verbose:
         for c in cmds:
