@@ -50,17 +50,18 @@ KERNEL_SOURCES = {
 }
 
 
-# Issue-rate model of the interaction kernels: SIMD-cycles per wave instruction
-# (64 lanes), measured on the box by a dependency-free probe (8 independent
-# chains per lane, 16 waves per SIMD, at the nominal clock): FP32 FMA-class and
-# other 32-bit instructions, the FP32 transcendentals (v_rsq_f32, v_exp_f32),
-# FP64 add / multiply / FMA, and v_rsq_f64.  Their issue does not overlap.
-CYCLES_FMA32 = 2.66
-CYCLES_TRANS32 = 8.85
-CYCLES_F64 = 4.7
-CYCLES_TRANS64 = 17.1
+# Issue-rate model of the interaction kernels: core cycles per wave instruction
+# (64 lanes) from paper_2003_01836_amd/microbench (8 independent chains per
+# lane, 16 waves per SIMD; its wall time times the clock that GRBM_GUI_ACTIVE
+# reports for the same dispatch, profiles/issue_rates_microbench.md): FP32
+# FMA-class and other 32-bit instructions, the FP32 transcendentals (v_rsq_f32,
+# v_exp_f32), FP64 add / multiply / FMA, and v_rsq_f64.  Their issue adds up.
+CYCLES_FMA32 = 2.54
+CYCLES_TRANS32 = 8.8
+CYCLES_F64 = 4.4
+CYCLES_TRANS64 = 16.6
 SIMDS = 1024                        # 256 CU x 4 SIMD
-CLOCK_HZ = 2.4e9
+CLOCK_HZ = 2.4e9                    # nominal; the model takes the kernel's measured clock
 
 
 def counter_value(prefix, profile, kernel, degree, ker_id, tpt=1):
@@ -78,7 +79,8 @@ def counter_value(prefix, profile, kernel, degree, ker_id, tpt=1):
         with open(os.path.join(ROOT, "paper_2003_01836_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if kernel == "upward_single":
-        want = f"{prefix} {kernel}<{degree + 1}, false> "
+        # ker_id 1: the FP32-product instantiation of the FP32-mixed path
+        want = f"{prefix} {kernel}<{degree + 1}, false, {'true' if ker_id else 'false'}> "
     elif kernel.startswith("interact"):
         want = f"{prefix} {kernel}<{degree}, {ker_id}> "
     else:
@@ -110,8 +112,9 @@ def issue_model(kernel, degree, ker_id, trans_per_eval, evals, ms, tpt=1):
     the FP32-mixed kernels the FP32 transcendentals, one per kernel value or two for
     Yukawa where no counter run took them; for the FP64 kernels the FP64 add, multiply
     and FMA instructions and v_rsq_f64), each class at its probed issue cost, the rest
-    at the 32-bit rate; and its ratio to the measured launch time.  None where no
-    counters fit the kernel."""
+    at the 32-bit rate, at the kernel's clock from the same summary (GRBM_GUI_ACTIVE
+    over its time; nominal 2.4 GHz where none was taken); and its ratio to the
+    measured launch time.  None where no counters fit the kernel."""
     prof = "interact_uniform-1M_valu_counters.md"
     valu = counter_value("valu_insts", prof, kernel, degree, ker_id, tpt)
     if valu is None:
@@ -129,21 +132,25 @@ def issue_model(kernel, degree, ker_id, trans_per_eval, evals, ms, tpt=1):
             return None
         cycles = f64 * CYCLES_F64 + trans * CYCLES_TRANS64 + (valu - f64 - trans) * CYCLES_FMA32
         parts = {"f64_insts": f64, "trans64_insts": trans}
-    t_min = cycles / SIMDS / CLOCK_HZ * 1e3
-    return {"valu_insts": valu, **parts, "t_min_ms": t_min, "frac": t_min / ms}
+    clock = counter_value("clock_hz", prof, kernel, degree, ker_id, tpt) or CLOCK_HZ
+    t_min = cycles / SIMDS / clock * 1e3
+    return {"valu_insts": valu, **parts, "clock_hz": clock, "t_min_ms": t_min, "frac": t_min / ms}
 
 
-def upward_roofline(degree, macs, ms):
-    """The upward pass of one charge vector against the FP64 matrix-core peak:
-    algorithmic flops 2 * sum_C N_C (n+1)^3 over the phase time (the kernel and
-    the chunk-sum reduction), and the matrix-core busy time per SIMD from the
-    committed counter summary (None when the kernel changed since)."""
+def upward_roofline(degree, macs, ms, prec="fp64"):
+    """The upward pass of one charge vector against the matrix-core peak of its
+    products (FP64 for the FP64 path, FP32 for the FP32-mixed one): algorithmic flops
+    2 * sum_C N_C (n+1)^3 over the phase time (the kernel and the chunk-sum
+    reduction), and the matrix-core busy time per SIMD from the committed counter
+    summary (None when the kernel changed since)."""
+    f32 = prec != "fp64"
+    peak = FP32_VECTOR_PEAK_TFLOPS if f32 else MFMA_F64_PEAK_TFLOPS
     achieved = 2.0 * macs / (ms * 1e-3) / 1e12
     busy = counter_value("mfma_busy_cycles", "upward_uniform-1M_mfma_counters.md",
-                         "upward_single", degree, 0)
-    return {"kernel": f"upward_single<{degree + 1}, false>", "bound": "mfma",
-            "macs": macs, "ms": ms, "achieved": achieved, "peak": MFMA_F64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / MFMA_F64_PEAK_TFLOPS,
+                         "upward_single", degree, 1 if f32 else 0)
+    return {"kernel": f"upward_single<{degree + 1}, false, {'true' if f32 else 'false'}>",
+            "bound": "mfma", "macs": macs, "ms": ms, "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak,
             "mfma_busy_frac": None if busy is None else busy / SIMDS / (ms * 1e-3 * CLOCK_HZ)}
 
 
@@ -861,7 +868,8 @@ def main():
                 "interaction_kernels": kernels,
                 "interaction_phase": {"achieved": phase_achieved, "frac": phase_achieved / peak,
                                       "ms": v["phases"]["interact"]},
-                "upward": upward_roofline(w["degree"], sv["upward_terms"], v["phases"]["upward"])}
+                "upward": upward_roofline(w["degree"], sv["upward_terms"], v["phases"]["upward"],
+                                          prec)}
 
     paths = {}
     for p, v in results.items():

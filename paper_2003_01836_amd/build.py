@@ -19,6 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbltc.so")
+MICROBENCH = os.path.join(PKG, "microbench")
 
 ARCH = "gfx950"
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
@@ -109,7 +110,20 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB, build_dir: str
     link = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + list(objs.values()) + ["-lpthread"]
     _run_all([link])
     os.replace(tmp, lib_path)
+    build_microbench()
     return lib_path
+
+
+def build_microbench(exe_path: str = MICROBENCH) -> str:
+    """Compiles the instruction-cost probes (csrc/microbench.hip) into a standalone
+    program; bench.py's issue-rate model takes its constants from their output."""
+    tmp = exe_path + ".tmp"
+    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Wno-unused-command-line-argument", "-o", tmp, os.path.join(CSRC, "microbench.hip")]
+    _run_all([cmd])
+    os.replace(tmp, exe_path)
+    return exe_path
 
 
 if __name__ == "__main__":

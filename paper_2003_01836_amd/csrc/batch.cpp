@@ -28,6 +28,9 @@ struct bltc_batch {
     int32_t nupunits = 0;
     int32_t passes = 1;
     size_t lds = 0;
+    // every system of one degree n <= 8: the 16-vector Lagrange upward kernel
+    // (FP32 products for FP32-mixed batches) instead of the general one
+    int32_t multi_np = 0;
     int32_t* d_counter = nullptr;
     int32_t workgroups = 0;
     // graph of the last set of caller buffers
@@ -62,8 +65,12 @@ int enqueue(bltc_batch* b, const double* const* q, const int32_t* num_q, const i
         const bltc::DevicePlan& d = b->plans[i]->d;
         HIP_TRY(bltc::launch_gather_charges16(d, q[i], q_ld[i], num_q[i], s));
     }
-    HIP_TRY(bltc::launch_upward_many(b->d_updescs, b->d_upunits, b->nupunits, b->mw, b->passes,
-                                     b->lds, s));
+    if (b->multi_np > 0)
+        HIP_TRY(bltc::launch_upward_many_multi(b->d_updescs, b->d_upunits, b->nupunits,
+                                               b->multi_np, b->kp.precision == 1, s));
+    else
+        HIP_TRY(bltc::launch_upward_many(b->d_updescs, b->d_upunits, b->nupunits, b->mw,
+                                         b->passes, b->lds, s));
     for (int32_t i = 0; i < count; ++i) {
         const bltc::DevicePlan& d = b->plans[i]->d;
         HIP_TRY(bltc::launch_upward_reduce(d, b->mw, d.qhat16, d.qhat16f, s));
@@ -116,8 +123,10 @@ int bltc_batch_create(bltc_batch** out, bltc_plan* const* plans, int32_t count, 
     std::vector<Unit> units;
     std::vector<Unit> up;
     int32_t max_np = 1;
+    bool one_np = true;
     for (int32_t i = 0; i < count; ++i) {
         const bltc::HostPlan& hp = plans[i]->hp;
+        one_np = one_np && hp.np == plans[0]->hp.np && !plans[i]->d.hermite;
         for (size_t g = 0; g < hp.group_batch.size(); ++g) {
             const int32_t bt = hp.group_batch[g];
             if (bt >= 0)
@@ -140,11 +149,13 @@ int bltc_batch_create(bltc_batch** out, bltc_plan* const* plans, int32_t count, 
     b->nupunits = static_cast<int32_t>(hup.size());
     b->passes = bltc::upward_passes(max_np, b->mw);
     b->lds = bltc::upward_lds_bytes(max_np, b->mw, max_np);
+    if (one_np && bltc::upward_many_multi(max_np, b->mw))
+        b->multi_np = max_np;
 
     std::vector<bltc::UpwardDesc> ud(count);
     for (int32_t i = 0; i < count; ++i) {
         const bltc::DevicePlan& d = plans[i]->d;
-        ud[i] = bltc::UpwardDesc{d.src, d.qm, d.chunk_slot, d.chunk_begin, d.chunk_count,
+        ud[i] = bltc::UpwardDesc{d.src, d.qm, d.qm32, d.chunk_slot, d.chunk_begin, d.chunk_count,
                                  d.chunk_dst, d.slot_nodes, d.qhat16, d.degree + 1};
     }
     int rc = BLTC_OK;

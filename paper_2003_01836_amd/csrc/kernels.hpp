@@ -167,6 +167,7 @@ hipError_t launch_upward_mfma(const DevicePlan& d, int32_t mw, double* buf, floa
 struct UpwardDesc {
     const double4* src;
     const double* qm;
+    const float* qm32;                // FP32 copies of the charges (FP32-mixed plans)
     const int32_t* chunk_slot;
     const int64_t* chunk_begin;
     const int64_t* chunk_count;
@@ -181,6 +182,11 @@ int32_t upward_passes(int32_t nf, int32_t mw);
 hipError_t upward_prepare(size_t lds);
 hipError_t launch_upward_many(const UpwardDesc* descs, const int2* units, int32_t nunits,
                               int32_t mw, int32_t passes, size_t lds, hipStream_t s);
+// the 16-vector Lagrange kernel of n + 1 = np <= 9 for systems of one degree:
+// whether it applies, and its launch (FP32 matrix-core products when f32)
+bool upward_many_multi(int32_t np, int32_t mw);
+hipError_t launch_upward_many_multi(const UpwardDesc* descs, const int2* units, int32_t nunits,
+                                    int32_t np, bool f32, hipStream_t s);
 hipError_t launch_upward_reduce(const DevicePlan& d, int32_t mw, double* buf, float* qhat32,
                                 hipStream_t s);
 // (with d.hermite the upward pass forms 8 (n+1)^3 charges per slot and the

@@ -20,10 +20,13 @@
 
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace bltc {
 namespace {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 128;          // sources staged in LDS at a time
 constexpr int kTilesPerWave = 8;    // 16x16 output tiles accumulated per wave
@@ -326,6 +329,45 @@ __device__ __forceinline__ void hermite_row(double yv, const double* __restrict_
     }
 }
 
+// FP32-mixed rows of one source: the factors are formed in FP64 as above and
+// normalized per dimension before rounding -- L_k = a_k / D_l (eq. 4), or
+// A_k, B_k -- so that every stored value is O(1) and the charge multiplies
+// the x row: r1 = q L1, r2 = L2, r3 = L3.  A coordinate on a node gives the
+// one-hot row of eq. 5.
+template <int NP, bool HERM>
+__device__ __forceinline__ void rows_f32(const double4 p, bool live, const double* __restrict__ sn,
+                                         const double* __restrict__ sc, float* __restrict__ r1,
+                                         float* __restrict__ r2, float* __restrict__ r3)
+{
+    constexpr int NF = HERM ? 2 * NP : NP;
+    const double q = live ? p.w : 0.0;
+    const double yv[3] = {p.x, p.y, p.z};
+    float* const rows[3] = {r1, r2, r3};
+#pragma unroll
+    for (int l = 2; l >= 0; --l) {
+        double a[NF];
+        const double scale = l == 0 ? q : 1.0;
+        if constexpr (HERM) {
+            hermite_row<NP>(yv[l], sn + l * NP, sc + l * NP, scale, a);
+        } else {
+            bool tiny;
+            const double D = factors_np<NP>(yv[l], sn + l * NP, a, tiny);
+            if (tiny) {
+                one_hot_row<NP>(yv[l], sn + l * NP, scale, a);
+            } else {
+                const double f = scale / D;
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    a[k] *= f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NF; ++k)
+            rows[l][k] = static_cast<float>(a[k]);
+        rows[l][NF] = 0.0f;
+    }
+}
+
 // NF factors per dimension: NP Lagrange factors or 2 NP Hermite factors
 template <int NP, bool HERM>
 constexpr int single_nf()
@@ -347,7 +389,12 @@ constexpr int single_lds_doubles()
 // HERM: the Hermite charges (8 (n+1)^3 per cluster, blocked layout
 // (f1 NF + f2) NF + f3 with f = a (n+1) + k): rows f1 = 2 NP <= 16, columns
 // (f2, f3), factors normalized (q instead of q~).
-template <int NP, bool HERM>
+//
+// F32 (FP32-mixed plans): the rows are rounded to FP32 after their FP64
+// formation (rows_f32), the products run on v_mfma_f32_16x16x4f32, and each
+// wave's FP32 partial tiles -- at most 32 sources of one 128-source tile --
+// are added to its FP64 tiles after every tile; outputs stay FP64.
+template <int NP, bool HERM, bool F32>
 __global__ __launch_bounds__(256) void upward_single(
     const double4* __restrict__ src, const int32_t* __restrict__ chunk_slot,
     const int64_t* __restrict__ chunk_begin, const int64_t* __restrict__ chunk_count,
@@ -359,11 +406,12 @@ __global__ __launch_bounds__(256) void upward_single(
     constexpr int CT = (NF2 + 15) / 16;
     constexpr int SP = NF + 1;                      // row stride: NF factors and a zero
     static_assert(NF <= 16, "one row tile");
+    using R = typename std::conditional<F32, float, double>::type;
     __shared__ double lds[single_lds_doubles<NP, HERM>()];
-    double* __restrict__ A1 = lds;                  // [kTile][SP]  x factors times q~ (q)
-    double* __restrict__ A2 = A1 + kTile * SP;      // [kTile][SP]
-    double* __restrict__ A3 = A2 + kTile * SP;      // [kTile][SP]
-    double* __restrict__ SC = A3 + kTile * SP;      // [3][NP] c_k (Hermite)
+    R* __restrict__ A1 = reinterpret_cast<R*>(lds); // [kTile][SP]  x factors times q~ (q)
+    R* __restrict__ A2 = A1 + kTile * SP;           // [kTile][SP]
+    R* __restrict__ A3 = A2 + kTile * SP;           // [kTile][SP]
+    double* __restrict__ SC = lds + 3 * kTile * SP; // [3][NP] c_k (Hermite)
 
     const int c = blockIdx.x;
     const int64_t slot = chunk_slot[c];
@@ -399,9 +447,12 @@ __global__ __launch_bounds__(256) void upward_single(
         off3[ct] = (lane >> 4) * SP + (cc < NF2 ? cc - (cc / NF) * NF : NF);
     }
     d4v acc[CT];
+    f4v acc32[CT];
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
+    for (int ct = 0; ct < CT; ++ct) {
         acc[ct] = d4v{0.0, 0.0, 0.0, 0.0};
+        acc32[ct] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    }
 
     for (int64_t t0 = 0; t0 < count; t0 += kTile) {
         const int tn = static_cast<int>(count - t0 < kTile ? count - t0 : kTile);
@@ -413,7 +464,11 @@ __global__ __launch_bounds__(256) void upward_single(
             const bool live = ft < tn;
             if (live)
                 p = src[begin + t0 + ft];
-            if constexpr (HERM) {
+            if constexpr (F32) {
+                rows_f32<NP, HERM>(p, live, sn, SC, reinterpret_cast<float*>(A1) + ft * SP,
+                                   reinterpret_cast<float*>(A2) + ft * SP,
+                                   reinterpret_cast<float*>(A3) + ft * SP);
+            } else if constexpr (HERM) {
                 hermite_row<NP>(p.z, sn + 2 * NP, SC + 2 * NP, 1.0, A3 + ft * SP);
                 hermite_row<NP>(p.y, sn + NP, SC + NP, 1.0, A2 + ft * SP);
                 hermite_row<NP>(p.x, sn, SC, live ? p.w : 0.0, A1 + ft * SP);
@@ -456,17 +511,30 @@ __global__ __launch_bounds__(256) void upward_single(
         const int steps = (tn + 3) / 4;
         for (int st = wave; st < steps; st += 4) {
             const int jb = 4 * st * SP;
-            const double av = A1[jb + off1];
+            const R av = A1[jb + off1];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-                const double bv = A2[jb + off2[ct]] * A3[jb + off3[ct]];
-                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+                const R bv = A2[jb + off2[ct]] * A3[jb + off3[ct]];
+                if constexpr (F32)
+                    acc32[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc32[ct], 0, 0, 0);
+                else
+                    acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+            }
+        }
+        if constexpr (F32) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[ct][r] += static_cast<double>(acc32[ct][r]);
+                acc32[ct] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
             }
         }
         __syncthreads();
     }
 
     // (w0 + w2) + (w1 + w3) through LDS; lane l, register r holds D[4r + l/16][l % 16]
+    // (f64 MFMA) or D[4 (l/16) + r][l % 16] (f32 MFMA)
     if (wave >= 2) {
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
@@ -498,7 +566,7 @@ __global__ __launch_bounds__(256) void upward_single(
             const int cc = ct * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = 4 * r + (lane >> 4);
+                const int row = F32 ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
                 if (row < NF && cc < NF2)
                     dst[row * NF2 + cc] = acc[ct][r] + lds[(ct * 4 + r) * 64 + lane];
             }
@@ -509,9 +577,15 @@ __global__ __launch_bounds__(256) void upward_single(
 template <int NP, bool HERM = false>
 hipError_t launch_single_np(const DevicePlan& d, double* buf, hipStream_t s)
 {
-    hipLaunchKernelGGL((upward_single<NP, HERM>), dim3(static_cast<unsigned>(d.nchunks)), dim3(256),
-                       0, s, d.src, d.chunk_slot, d.chunk_begin, d.chunk_count, d.chunk_dst,
-                       d.slot_nodes, buf);
+    // FP32-mixed plans (they hold FP32 source copies): FP32 matrix-core products
+    if (d.src32)
+        hipLaunchKernelGGL((upward_single<NP, HERM, true>), dim3(static_cast<unsigned>(d.nchunks)),
+                           dim3(256), 0, s, d.src, d.chunk_slot, d.chunk_begin, d.chunk_count,
+                           d.chunk_dst, d.slot_nodes, buf);
+    else
+        hipLaunchKernelGGL((upward_single<NP, HERM, false>), dim3(static_cast<unsigned>(d.nchunks)),
+                           dim3(256), 0, s, d.src, d.chunk_slot, d.chunk_begin, d.chunk_count,
+                           d.chunk_dst, d.slot_nodes, buf);
     return hipGetLastError();
 }
 
@@ -548,6 +622,212 @@ bool launch_single(const DevicePlan& d, double* buf, hipStream_t s, hipError_t* 
     case 15: *err = launch_single_np<15>(d, buf, s); return true;
     case 16: *err = launch_single_np<16>(d, buf, s); return true;
     default: return false;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 16 charge vectors, Lagrange factors, n + 1 = NP <= 9 nodes per dimension.
+// Output tile (k1, ct) is Qhat[k1][m][(k2, k3)] for the 16 vectors m (rows)
+// and the 16 columns ct*16 .. ct*16 + 15 of (k2, k3): A[m][j] = L1[j][k1]
+// q[j][m] and B[j][(k2, k3)] = L2[j][k2] L3[j][k3], with the factors
+// normalized per dimension (L_l = a_l / D_l, eq. 4, so q~ of eq. 14 is the
+// charge itself).  The NP * ceil(NP^2 / 16) tiles of a chunk are dealt
+// round-robin to the 8 waves of a workgroup and each wave runs over all of
+// the chunk's sources, so the factors are formed once per chunk, 256 sources
+// at a time (threads t and t + 256 share source t: x and y, z), with the
+// degree known at compile time.  The
+// charges come straight from memory (lane l reads vector l % 16 of source
+// 4 st + l / 16: 512 contiguous bytes per step).  F32: the rows are rounded to
+// FP32 after their FP64 formation, the products run on
+// v_mfma_f32_16x16x4f32, and every wave adds its FP32 tiles -- 256 sources --
+// to FP64 tiles after each round of factors.
+// ---------------------------------------------------------------------------
+constexpr int kMultiTile = 256;
+constexpr int kMultiWaves = 8;
+constexpr int kMultiMaxNP = 9;
+
+template <int NP>
+constexpr int multi_tiles_per_wave()
+{
+    return (NP * ((NP * NP + 15) / 16) + kMultiWaves - 1) / kMultiWaves;
+}
+
+template <int NP, bool F32>
+__device__ __forceinline__ void multi_chunk(const double4* __restrict__ src,
+                                            const double* __restrict__ qm,
+                                            const float* __restrict__ qm32,
+                                            const int32_t* __restrict__ chunk_slot,
+                                            const int64_t* __restrict__ chunk_begin,
+                                            const int64_t* __restrict__ chunk_count,
+                                            const int64_t* __restrict__ chunk_dst,
+                                            const double* __restrict__ slot_nodes,
+                                            double* __restrict__ out, int c, double* lds)
+{
+    constexpr int NP2 = NP * NP;
+    constexpr int CT = (NP2 + 15) / 16;
+    constexpr int T = NP * CT;
+    constexpr int TW = multi_tiles_per_wave<NP>();
+    constexpr int SP = NP + 1;                      // row stride: NP factors and a zero
+    using R = typename std::conditional<F32, float, double>::type;
+    R* __restrict__ L1 = reinterpret_cast<R*>(lds);
+    R* __restrict__ L2 = L1 + kMultiTile * SP;
+    R* __restrict__ L3 = L2 + kMultiTile * SP;
+
+    const int64_t slot = chunk_slot[c];
+    const int64_t begin = chunk_begin[c];
+    const int64_t count = chunk_count[c];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double* __restrict__ sn = slot_nodes + slot * 3 * NP;   // wave-uniform
+
+    // this wave's tiles t = wave + 8u: row tile k1 = t / CT, column tile t % CT;
+    // columns past NP^2 read the zero entry of the rows
+    int ok1[TW], ok2[TW], ok3[TW];
+    d4v acc[TW];
+    f4v acc32[TW];
+#pragma unroll
+    for (int u = 0; u < TW; ++u) {
+        const int t = wave + kMultiWaves * u;
+        const bool live = t < T;
+        const int k1 = live ? t / CT : 0;
+        const int cc = (live ? t - (t / CT) * CT : 0) * 16 + (lane & 15);
+        ok1[u] = k1;
+        ok2[u] = cc < NP2 ? cc / NP : NP;
+        ok3[u] = cc < NP2 ? cc - (cc / NP) * NP : NP;
+        acc[u] = d4v{0.0, 0.0, 0.0, 0.0};
+        acc32[u] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    const int m = lane & 15;
+    const int jl = lane >> 4;
+
+    for (int64_t t0 = 0; t0 < count; t0 += kMultiTile) {
+        const int tn = static_cast<int>(count - t0 < kMultiTile ? count - t0 : kMultiTile);
+        {
+            // source js: dimensions x and y (threads below 256) or z; rows past
+            // the chunk's end are zero
+            const int js = tid & (kMultiTile - 1);
+            const int l0 = tid < kMultiTile ? 0 : 2, l1 = tid < kMultiTile ? 2 : 3;
+            const bool on = js < tn;
+            const double4 p = on ? src[begin + t0 + js] : double4{0.0, 0.0, 0.0, 0.0};
+            const double yv[3] = {p.x, p.y, p.z};
+            R* const rows[3] = {L1 + js * SP, L2 + js * SP, L3 + js * SP};
+            for (int l = l0; l < l1; ++l) {
+                double a[NP];
+                bool tiny;
+                const double D = factors_np<NP>(yv[l], sn + l * NP, a, tiny);
+                const double f = on ? 1.0 : 0.0;
+                if (tiny) {
+                    one_hot_row<NP>(yv[l], sn + l * NP, f, a);
+                } else {
+                    const double g = f / D;
+#pragma unroll
+                    for (int k = 0; k < NP; ++k)
+                        a[k] *= g;
+                }
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    rows[l][k] = static_cast<R>(a[k]);
+                rows[l][NP] = R(0);
+            }
+        }
+        __syncthreads();
+        const int steps = (tn + 3) / 4;
+        for (int st = 0; st < steps; ++st) {
+            const int j = 4 * st + jl;
+            const int64_t jq = begin + t0 + (j < tn ? j : tn - 1);   // rows past tn are zero
+            R qv;
+            if constexpr (F32)
+                qv = qm32[jq * 16 + m];
+            else
+                qv = qm[jq * 16 + m];
+            const int jb = j * SP;
+#pragma unroll
+            for (int u = 0; u < TW; ++u) {
+                if (wave + kMultiWaves * u >= T)   // uniform: past this wave's last tile
+                    continue;
+                const R av = L1[jb + ok1[u]] * qv;
+                const R bv = L2[jb + ok2[u]] * L3[jb + ok3[u]];
+                if constexpr (F32)
+                    acc32[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc32[u], 0, 0, 0);
+                else
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+            }
+        }
+        if constexpr (F32) {
+#pragma unroll
+            for (int u = 0; u < TW; ++u) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc[u][r] += static_cast<double>(acc32[u][r]);
+                acc32[u] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+        }
+        __syncthreads();
+    }
+
+    // lane l, register r: row m = 4r + l/16 (f64) or 4 (l/16) + r (f32), column l % 16
+    double* __restrict__ dst = out + chunk_dst[c] * static_cast<int64_t>(NP2) * NP * 16;
+#pragma unroll
+    for (int u = 0; u < TW; ++u) {
+        if (wave + kMultiWaves * u >= T || ok2[u] == NP)
+            continue;
+        const int64_t kb = static_cast<int64_t>((ok1[u] * NP + ok2[u]) * NP + ok3[u]) * 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int mo = F32 ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
+            dst[kb + mo] = acc[u][r];
+        }
+    }
+}
+
+template <int NP, bool F32>
+__global__ __launch_bounds__(64 * kMultiWaves) void upward_multi(
+    const double4* __restrict__ src, const double* __restrict__ qm, const float* __restrict__ qm32,
+    const int32_t* __restrict__ chunk_slot, const int64_t* __restrict__ chunk_begin,
+    const int64_t* __restrict__ chunk_count, const int64_t* __restrict__ chunk_dst,
+    const double* __restrict__ slot_nodes, double* __restrict__ out)
+{
+    __shared__ double lds[3 * kMultiTile * (kMultiMaxNP + 1)];
+    multi_chunk<NP, F32>(src, qm, qm32, chunk_slot, chunk_begin, chunk_count, chunk_dst,
+                         slot_nodes, out, blockIdx.x, lds);
+}
+
+// the chunks of many systems (all of degree NP - 1) in one launch
+template <int NP, bool F32>
+__global__ __launch_bounds__(64 * kMultiWaves) void upward_multi_many(
+    const UpwardDesc* __restrict__ descs, const int2* __restrict__ units)
+{
+    __shared__ double lds[3 * kMultiTile * (kMultiMaxNP + 1)];
+    const int2 w = units[blockIdx.x];
+    const UpwardDesc& d = descs[__builtin_amdgcn_readfirstlane(w.x)];
+    multi_chunk<NP, F32>(d.src, d.qm, d.qm32, d.chunk_slot, d.chunk_begin, d.chunk_count,
+                         d.chunk_dst, d.slot_nodes, d.buf, __builtin_amdgcn_readfirstlane(w.y),
+                         lds);
+}
+
+#define BLTC_MULTI_NP(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9)
+
+// 16-vector Lagrange upward pass of one plan (n + 1 <= 9); false for other degrees
+bool launch_multi(const DevicePlan& d, double* buf, bool f32, hipStream_t s, hipError_t* err)
+{
+    switch (d.degree + 1) {
+#define X(np)                                                                                  \
+    case np:                                                                                   \
+        if (f32)                                                                               \
+            hipLaunchKernelGGL((upward_multi<np, true>), dim3(static_cast<unsigned>(d.nchunks)), \
+                               dim3(64 * kMultiWaves), 0, s, d.src, d.qm, d.qm32, d.chunk_slot, d.chunk_begin, \
+                               d.chunk_count, d.chunk_dst, d.slot_nodes, buf);                 \
+        else                                                                                   \
+            hipLaunchKernelGGL((upward_multi<np, false>), dim3(static_cast<unsigned>(d.nchunks)), \
+                               dim3(64 * kMultiWaves), 0, s, d.src, d.qm, d.qm32, d.chunk_slot, d.chunk_begin, \
+                               d.chunk_count, d.chunk_dst, d.slot_nodes, buf);                 \
+        *err = hipGetLastError();                                                              \
+        return true;
+        BLTC_MULTI_NP(X)
+#undef X
+    default:
+        return false;
     }
 }
 
@@ -696,6 +976,11 @@ hipError_t launch_upward_mfma(const DevicePlan& d, int32_t mw, double* buf, floa
             return e;
         return launch_upward_reduce(d, mw, buf, qhat32, s);
     }
+    if (mw == 16 && !d.hermite && launch_multi(d, buf, d.src32 != nullptr, s, &e)) {
+        if (e != hipSuccess)
+            return e;
+        return launch_upward_reduce(d, mw, buf, qhat32, s);
+    }
     const int32_t np = d.degree + 1;
     const int32_t nf = d.hermite ? 2 * np : np;
     const size_t lds = upward_lds_bytes(np, mw, nf);
@@ -709,6 +994,33 @@ hipError_t launch_upward_mfma(const DevicePlan& d, int32_t mw, double* buf, floa
     if (e != hipSuccess)
         return e;
     return launch_upward_reduce(d, mw, buf, qhat32, s);
+}
+
+bool upward_many_multi(int32_t np, int32_t mw)
+{
+    return mw == 16 && np >= 2 && np <= kMultiMaxNP;
+}
+
+hipError_t launch_upward_many_multi(const UpwardDesc* descs, const int2* units, int32_t nunits,
+                                    int32_t np, bool f32, hipStream_t s)
+{
+    if (nunits == 0)
+        return hipSuccess;
+    switch (np) {
+#define X(n)                                                                                   \
+    case n:                                                                                    \
+        if (f32)                                                                               \
+            hipLaunchKernelGGL((upward_multi_many<n, true>), dim3(static_cast<unsigned>(nunits)), \
+                               dim3(64 * kMultiWaves), 0, s, descs, units);                                 \
+        else                                                                                   \
+            hipLaunchKernelGGL((upward_multi_many<n, false>), dim3(static_cast<unsigned>(nunits)), \
+                               dim3(64 * kMultiWaves), 0, s, descs, units);                                 \
+        return hipGetLastError();
+        BLTC_MULTI_NP(X)
+#undef X
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_upward_many(const UpwardDesc* descs, const int2* units, int32_t nunits,

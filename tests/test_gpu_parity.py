@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.conftest import KERNEL_CASES, assert_mixed, kernel_kwargs
+from tests.conftest import EPS32, KERNEL_CASES, assert_mixed, kernel_kwargs
 from paper_2003_01836_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -467,6 +467,57 @@ def test_modified_charges_multi_chunk_clusters(dev, m):
         for qi in ([0] if m == 1 else [0, 7, 15]):
             got = plan.modified_charges(c, qi)
             assert np.max(np.abs(ref[qi] - got)) <= 1e-12 * np.max(np.abs(ref[qi])), (c, qi)
+
+
+def _abs_moments(oc, c, q, degree):
+    """sum_j |q_jm| |L1_k1(y_j)| |L2_k2(y_j)| |L3_k3(y_j)| of oracle cluster c (eq. 12
+    with every term taken by magnitude): the scale of the FP32 rounding of q-hat."""
+    info = oc.cluster(c)
+    members = oc.cluster_members(c)
+    q2 = np.atleast_2d(q)[:, members]
+    pos = oc._s[members]
+    L = []
+    for l in range(3):
+        nodes, w = oracle.chebyshev(degree, info["lo"][l], info["hi"][l])
+        L.append(np.abs(np.array([oracle.lagrange(degree, nodes, w, x) for x in pos[:, l]])))
+    return np.einsum("mj,ja,jb,jc->mabc", np.abs(q2), L[0], L[1], L[2])
+
+
+@pytest.mark.parametrize("m", [1, 16])
+def test_mixed_modified_charges_fp32_products(dev, m):
+    # FP32-mixed plans form the factors in FP64 and run the upward products on
+    # FP32 matrix cores (partial tiles of at most 256 sources, summed in FP64):
+    # every q-hat entry within 16 eps32 of the sum of its terms' magnitudes, on
+    # clusters that span several upward chunks and on leaves
+    pos, q = inputs.uniform_cube(40000, 160 + m, m=m)
+    g = np.random.default_rng(160 + m)
+    tgt = np.concatenate([g.uniform(-1, 1, (3000, 3)), g.uniform(-1, 1, (3000, 3)) + [8.0, 1.0, 0.0]])
+    plan, _ = _run_plan(dev, tgt, pos, q if m > 1 else q[0], theta=0.9, degree=4, leaf_size=2000,
+                        batch_size=2000, precision="fp32_mixed")
+    oc = oracle.Treecode(tgt, pos, 0.9, 4, 2000, 2000)
+    v = plan.view()
+    oorder = oc.source_order()
+    okey = {}
+    for c in range(oc.n_clusters):
+        info = oc.cluster(c)
+        okey[tuple(np.sort(oorder[info["begin"]:info["begin"] + info["count"]]))] = c
+    approx = np.unique(v["item_cluster"][v["item_kind"] == 0])
+    big = [c for c in approx if v["cluster_count"][c] > 8192]
+    assert big, "the test needs clusters that span several chunks"
+    worst = 0.0
+    for c in list(big) + list(approx[:4]):
+        key = tuple(np.sort(v["source_order"][v["cluster_begin"][c]:v["cluster_begin"][c] + v["cluster_count"][c]]))
+        oc_c = okey[key]
+        ref = oc.modified_charges(oc_c, q)       # (m, 5, 5, 5), or (5, 5, 5) for one vector
+        scale = _abs_moments(oc, oc_c, q, 4)     # (m, 5, 5, 5)
+        if m == 1:
+            ref = ref[None]
+        for qi in ([0] if m == 1 else [0, 7, 15]):
+            got = plan.modified_charges(c, qi)
+            ratio = np.max(np.abs(ref[qi] - got) / (EPS32 * scale[qi]))
+            worst = max(worst, float(ratio))
+            assert ratio <= 16.0, (c, qi, ratio)
+    print(f"[qhat fp32] worst {worst:.2f} eps32 sum|terms|", flush=True)
 
 
 @pytest.mark.parametrize("degree", list(range(1, 17)))
