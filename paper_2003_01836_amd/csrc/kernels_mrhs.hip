@@ -8,8 +8,10 @@
 // lane l evaluates G for target row (l % 16) of each tile and source column
 // (l / 16) on the VALU -- exactly the MFMA A-operand layout -- and loads
 // Q[source l/16][rhs l%16] -- the B-operand layout -- so the G tile goes
-// straight from the VALU into v_mfma_*_16x16x4 without any shuffle.  The
-// matrix core runs concurrently with the VALU work of other waves.
+// straight from the VALU into v_mfma_*_16x16x4 without any shuffle.  On
+// gfx950 the matrix core and the VALU of a SIMD do not issue at the same time
+// (measured: their costs add, within a wave and across waves), so a step costs
+// its VALU work plus its MFMAs.
 //
 // Result layouts of the 16x16x4 MFMAs on gfx950 (checked on the device):
 //   f64: lane l, register r holds D[4r + l/16][l % 16]

@@ -633,18 +633,19 @@ bool launch_single(const DevicePlan& d, double* buf, hipStream_t s, hipError_t* 
 // normalized per dimension (L_l = a_l / D_l, eq. 4, so q~ of eq. 14 is the
 // charge itself).  The NP * ceil(NP^2 / 16) tiles of a chunk are dealt
 // round-robin to the 8 waves of a workgroup and each wave runs over all of
-// the chunk's sources, so the factors are formed once per chunk, 256 sources
-// at a time (threads t and t + 256 share source t: x and y, z), with the
-// degree known at compile time.  The
-// charges come straight from memory (lane l reads vector l % 16 of source
-// 4 st + l / 16: 512 contiguous bytes per step).  F32: the rows are rounded to
-// FP32 after their FP64 formation, the products run on
-// v_mfma_f32_16x16x4f32, and every wave adds its FP32 tiles -- 256 sources --
-// to FP64 tiles after each round of factors.
+// the chunk's sources, so the factors are formed once per chunk, 128 sources
+// at a time: the four quarters of the workgroup take the x, y and z factors
+// and the charges (16 per source) of the same 128 sources into LDS, with the
+// degree known at compile time.  F32: the rows and charges are rounded to
+// FP32 after their FP64 formation, the products run on v_mfma_f32_16x16x4f32,
+// and every wave adds its FP32 tiles -- 128 sources -- to FP64 tiles after
+// each round.
 // ---------------------------------------------------------------------------
-constexpr int kMultiTile = 256;
+constexpr int kMultiTile = 128;
 constexpr int kMultiWaves = 8;
 constexpr int kMultiMaxNP = 9;
+// LDS of one round: three factor rows of kMultiMaxNP + 1 and 16 charges per source
+constexpr int kMultiLds = kMultiTile * (3 * (kMultiMaxNP + 1) + 16);
 
 template <int NP>
 constexpr int multi_tiles_per_wave()
@@ -672,6 +673,7 @@ __device__ __forceinline__ void multi_chunk(const double4* __restrict__ src,
     R* __restrict__ L1 = reinterpret_cast<R*>(lds);
     R* __restrict__ L2 = L1 + kMultiTile * SP;
     R* __restrict__ L3 = L2 + kMultiTile * SP;
+    R* __restrict__ SQ = L3 + kMultiTile * SP;      // [kMultiTile][16] charges
 
     const int64_t slot = chunk_slot[c];
     const int64_t begin = chunk_begin[c];
@@ -700,47 +702,52 @@ __device__ __forceinline__ void multi_chunk(const double4* __restrict__ src,
     }
     const int m = lane & 15;
     const int jl = lane >> 4;
+    const int js = tid & (kMultiTile - 1);          // this thread's source of a round
+    const int role = tid / kMultiTile;              // 0, 1, 2: x, y, z factors; 3: charges
 
     for (int64_t t0 = 0; t0 < count; t0 += kMultiTile) {
         const int tn = static_cast<int>(count - t0 < kMultiTile ? count - t0 : kMultiTile);
         {
-            // source js: dimensions x and y (threads below 256) or z; rows past
-            // the chunk's end are zero
-            const int js = tid & (kMultiTile - 1);
-            const int l0 = tid < kMultiTile ? 0 : 2, l1 = tid < kMultiTile ? 2 : 3;
+            // rows and charges past the chunk's end are zero
             const bool on = js < tn;
-            const double4 p = on ? src[begin + t0 + js] : double4{0.0, 0.0, 0.0, 0.0};
-            const double yv[3] = {p.x, p.y, p.z};
-            R* const rows[3] = {L1 + js * SP, L2 + js * SP, L3 + js * SP};
-            for (int l = l0; l < l1; ++l) {
+            const int64_t j = begin + t0 + (on ? js : 0);
+            if (role < 3) {
+                const double4 p = src[j];
+                const double yv = role == 0 ? p.x : role == 1 ? p.y : p.z;
                 double a[NP];
                 bool tiny;
-                const double D = factors_np<NP>(yv[l], sn + l * NP, a, tiny);
+                const double D = factors_np<NP>(yv, sn + role * NP, a, tiny);
                 const double f = on ? 1.0 : 0.0;
                 if (tiny) {
-                    one_hot_row<NP>(yv[l], sn + l * NP, f, a);
+                    one_hot_row<NP>(yv, sn + role * NP, f, a);
                 } else {
                     const double g = f / D;
 #pragma unroll
                     for (int k = 0; k < NP; ++k)
                         a[k] *= g;
                 }
+                R* __restrict__ row = (role == 0 ? L1 : role == 1 ? L2 : L3) + js * SP;
 #pragma unroll
                 for (int k = 0; k < NP; ++k)
-                    rows[l][k] = static_cast<R>(a[k]);
-                rows[l][NP] = R(0);
+                    row[k] = static_cast<R>(a[k]);
+                row[NP] = R(0);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    R qv;
+                    if constexpr (F32)
+                        qv = on ? qm32[j * 16 + v] : 0.0f;
+                    else
+                        qv = on ? qm[j * 16 + v] : 0.0;
+                    SQ[js * 16 + v] = qv;
+                }
             }
         }
         __syncthreads();
         const int steps = (tn + 3) / 4;
         for (int st = 0; st < steps; ++st) {
             const int j = 4 * st + jl;
-            const int64_t jq = begin + t0 + (j < tn ? j : tn - 1);   // rows past tn are zero
-            R qv;
-            if constexpr (F32)
-                qv = qm32[jq * 16 + m];
-            else
-                qv = qm[jq * 16 + m];
+            const R qv = SQ[j * 16 + m];
             const int jb = j * SP;
 #pragma unroll
             for (int u = 0; u < TW; ++u) {
@@ -788,7 +795,7 @@ __global__ __launch_bounds__(64 * kMultiWaves) void upward_multi(
     const int64_t* __restrict__ chunk_count, const int64_t* __restrict__ chunk_dst,
     const double* __restrict__ slot_nodes, double* __restrict__ out)
 {
-    __shared__ double lds[3 * kMultiTile * (kMultiMaxNP + 1)];
+    __shared__ double lds[kMultiLds];
     multi_chunk<NP, F32>(src, qm, qm32, chunk_slot, chunk_begin, chunk_count, chunk_dst,
                          slot_nodes, out, blockIdx.x, lds);
 }
@@ -798,7 +805,7 @@ template <int NP, bool F32>
 __global__ __launch_bounds__(64 * kMultiWaves) void upward_multi_many(
     const UpwardDesc* __restrict__ descs, const int2* __restrict__ units)
 {
-    __shared__ double lds[3 * kMultiTile * (kMultiMaxNP + 1)];
+    __shared__ double lds[kMultiLds];
     const int2 w = units[blockIdx.x];
     const UpwardDesc& d = descs[__builtin_amdgcn_readfirstlane(w.x)];
     multi_chunk<NP, F32>(d.src, d.qm, d.qm32, d.chunk_slot, d.chunk_begin, d.chunk_count,
