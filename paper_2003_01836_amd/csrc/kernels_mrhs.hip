@@ -85,6 +85,35 @@ __device__ __forceinline__ void gstore(T* p, T v)
     *(__attribute__((address_space(1))) T*)(p) = v;
 }
 
+// Order of the far-field steps over a cluster's (n+1)^3 proxy points: the
+// grid's (n+1)^2 lines (k1, k2) go to the four source columns of a step in
+// rounds -- line 4R + c to column c in round R -- and a round takes n + 1
+// steps, k3 = 0..n.  A lane thus keeps one line for n + 1 steps: the x- and
+// y-part of its targets' squared distances is formed once per round, and a
+// step forms one difference and one FMA per value (the separable grid of
+// eq. 11).  Columns past the last line carry zero charges.  The cursor is
+// the same in every lane (uniform).
+struct GridWalk {
+    int np, lines;   // n + 1, (n + 1)^2
+    int round, k3;
+    __device__ __forceinline__ GridWalk(int n1) : np(n1), lines(n1 * n1), round(0), k3(0) {}
+    __device__ __forceinline__ void advance()
+    {
+        if (++k3 == np) {
+            k3 = 0;
+            ++round;
+        }
+    }
+    __device__ __forceinline__ bool live(int col) const { return 4 * round + col < lines; }
+    // proxy index of column col (the last point for columns past the end)
+    __device__ __forceinline__ uint32_t point(int col) const
+    {
+        const int line = 4 * round + col;
+        return static_cast<uint32_t>(line < lines ? line * np + k3 : lines * np - 1);
+    }
+    __device__ __forceinline__ int steps() const { return ((lines + 3) / 4) * np; }
+};
+
 // ---------------------------------------------------------------------------
 // FP64: G in FP64 on the VALU, contraction on v_mfma_f64_16x16x4f64.
 // ---------------------------------------------------------------------------
@@ -144,32 +173,43 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
         // are in flight; ring slot u serves steps u, u + kAheadF64, ... and is
         // reloaded once its step is evaluated.  Whole rounds of steps are
         // evaluated; steps past the end carry zero charges.
+        GridWalk ld(np), ev(np);   // next step to load, next step to evaluate
         d3v pn[kAheadF64];
         double qn[kAheadF64];
 #pragma unroll
         for (int a = 0; a < kAheadF64; ++a) {
-            const int kk = 4 * a + col < P ? 4 * a + col : P - 1;
-            pn[a] = gload_at<d3v>(px, static_cast<uint32_t>(kk) * 32u);
-            qn[a] = gload_at<double>(qh, (static_cast<uint32_t>(kk) * kRhs + row) * 8u);
+            const uint32_t kk = ld.point(col);
+            pn[a] = gload_at<d3v>(px, kk * 32u);
+            qn[a] = gload_at<double>(qh, (kk * kRhs + row) * 8u);
+            ld.advance();
             // slot 0 first: the loop's first wait then leaves the other slots in flight
             __builtin_amdgcn_sched_barrier(0);
         }
-        for (int k1 = 0; k1 < P; k1 += 4 * kAheadF64) {
+        double ab[4];   // (x - x_k1)^2 + (y - y_k2)^2 of the lane's line
+        const int steps = ev.steps();
+        for (int s1 = 0; s1 < steps; s1 += kAheadF64) {
 #pragma unroll
             for (int u = 0; u < kAheadF64; ++u) {
-                const int k0 = k1 + 4 * u;
-                const double bq = (k0 + col < P) ? qn[u] : 0.0;
+                const double bq = ev.live(col) ? qn[u] : 0.0;
+                if (ev.k3 == 0) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const double dx = tx[t] - pn[u].x, dy = ty[t] - pn[u].y;
+                        ab[t] = __fma_rn(dy, dy, dx * dx);
+                    }
+                }
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const double dx = tx[t] - pn[u].x, dy = ty[t] - pn[u].y, dz = tz[t] - pn[u].z;
-                    const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-                    const double gv = green_far_f64<KER>(r2, kappa);
+                    const double dz = tz[t] - pn[u].z;
+                    const double r2 = __fma_rn(dz, dz, ab[t]);
+                    const double gv = green_far2_f64<KER>(r2, kappa);   // 2 G
                     acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
                 }
-                int kk = k0 + 4 * kAheadF64 + col;
-                kk = kk < P ? kk : P - 1;
-                pn[u] = gload_at<d3v>(px, static_cast<uint32_t>(kk) * 32u);
-                qn[u] = gload_at<double>(qh, (static_cast<uint32_t>(kk) * kRhs + row) * 8u);
+                ev.advance();
+                const uint32_t kk = ld.point(col);
+                pn[u] = gload_at<d3v>(px, kk * 32u);
+                qn[u] = gload_at<double>(qh, (kk * kRhs + row) * 8u);
+                ld.advance();
                 // keep the step's order: its reload is issued after its MFMAs
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -200,7 +240,7 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
                 for (int t = 0; t < 4; ++t) {
                     const double dx = tx[t] - pn[u].x, dy = ty[t] - pn[u].y, dz = tz[t] - pn[u].z;
                     const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
-                    const double gv = green_near_f64<KER>(r2, kappa);
+                    const double gv = green_near2_f64<KER>(r2, kappa);   // 2 G
                     acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv, bq, acc[t], 0, 0, 0);
                 }
                 const int32_t jn = j0 + 4 * kAheadF64 + col;
@@ -218,8 +258,8 @@ __device__ __forceinline__ void group_mrhs_f64(const MrhsDesc& d, int g, const d
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = wave_first + 16 * t + 4 * r + col;
-                if (i < end)
-                    gstore(phi + row * phi_ld + gload<int64_t>(tgt_orig + i), acc[t][r]);
+                if (i < end)   // the kernel values were doubled (green_*2_f64)
+                    gstore(phi + row * phi_ld + gload<int64_t>(tgt_orig + i), 0.5 * acc[t][r]);
             }
     }
 }
@@ -241,7 +281,8 @@ __device__ __forceinline__ void flush_f32(f4v (&part)[4], double (&acc)[4][4])
 }
 
 template <int KER>
-__device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const double* exp_tab)
+__device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const double* exp_tab,
+                                                 double* __restrict__ tl)
 {
     const double4* __restrict__ tgt = d.tgt;
     const int64_t* __restrict__ tgt_orig = d.tgt_orig;
@@ -277,15 +318,23 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
     const int col = lane >> 4;
     const KernelArg32 nk = kernel_arg32(d.kc.kappa, d.kc.delta2);
 
-    double tx[4], ty[4], tz[4];
+    // The targets' FP64 coordinates wait in LDS, in slots of this lane only
+    // (no barrier): held in registers they would take 24 VGPRs for the whole
+    // group and keep the kernel from four waves per SIMD.  The accesses are
+    // volatile, or the compiler forwards the stored values and keeps them in
+    // registers after all.
+    volatile double* tl_lane = tl + threadIdx.x;
+    auto tc = [tl_lane](int t, int l) -> volatile double& {
+        return tl_lane[(3 * t + l) * kGroupSize];
+    };
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         int64_t i = wave_first + 16 * t + row;
         i = i < end ? i : end - 1;
         const d3v v = gload<d3v>(tgt + i);
-        tx[t] = v.x;
-        ty[t] = v.y;
-        tz[t] = v.z;
+        tc(t, 0) = v.x;
+        tc(t, 1) = v.y;
+        tc(t, 2) = v.z;
     }
     double acc[4][4];
     f4v part[4];
@@ -306,39 +355,50 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
         float ux[4], uy[4], uz[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            ux[t] = static_cast<float>(tx[t] - ci.x);
-            uy[t] = static_cast<float>(ty[t] - ci.y);
-            uz[t] = static_cast<float>(tz[t] - ci.z);
+            ux[t] = static_cast<float>(tc(t, 0) - ci.x);
+            uy[t] = static_cast<float>(tc(t, 1) - ci.y);
+            uz[t] = static_cast<float>(tc(t, 2) - ci.z);
         }
         const float4* __restrict__ px = proxies32 + slot * P;
         const float* __restrict__ qh = qhat16 + slot * static_cast<int64_t>(P) * kRhs;
+        GridWalk ld(np), ev(np);   // next step to load, next step to evaluate
         f3v pn[kAheadMixed];
         float qn[kAheadMixed];
 #pragma unroll
         for (int a = 0; a < kAheadMixed; ++a) {
-            const int kk = 4 * a + col < P ? 4 * a + col : P - 1;
-            pn[a] = gload_at<f3v>(px, static_cast<uint32_t>(kk) * 16u);
-            qn[a] = gload_at<float>(qh, (static_cast<uint32_t>(kk) * kRhs + row) * 4u);
+            const uint32_t kk = ld.point(col);
+            pn[a] = gload_at<f3v>(px, kk * 16u);
+            qn[a] = gload_at<float>(qh, (kk * kRhs + row) * 4u);
+            ld.advance();
             // slot 0 first: the loop's first wait then leaves the other slots in flight
             __builtin_amdgcn_sched_barrier(0);
         }
+        float ab[4];   // (x - x_k1)^2 + (y - y_k2)^2 of the lane's line
         int rounds = 0;
-        for (int k1 = 0; k1 < P; k1 += 4 * kAheadMixed) {
+        const int steps = ev.steps();
+        for (int s1 = 0; s1 < steps; s1 += kAheadMixed) {
 #pragma unroll
             for (int u = 0; u < kAheadMixed; ++u) {
-                const int k0 = k1 + 4 * u;
-                const float bq = (k0 + col < P) ? qn[u] : 0.0f;
+                const float bq = ev.live(col) ? qn[u] : 0.0f;
+                if (ev.k3 == 0) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float dx = ux[t] - pn[u].x, dy = uy[t] - pn[u].y;
+                        ab[t] = __fmaf_rn(dy, dy, dx * dx);
+                    }
+                }
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const float dx = ux[t] - pn[u].x, dy = uy[t] - pn[u].y, dz = uz[t] - pn[u].z;
-                    const float r2 = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+                    const float dz = uz[t] - pn[u].z;
+                    const float r2 = __fmaf_rn(dz, dz, ab[t]);
                     const float gv = green_f32<KER>(r2, nk);
                     part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, bq, part[t], 0, 0, 0);
                 }
-                int kk = k0 + 4 * kAheadMixed + col;
-                kk = kk < P ? kk : P - 1;
-                pn[u] = gload_at<f3v>(px, static_cast<uint32_t>(kk) * 16u);
-                qn[u] = gload_at<float>(qh, (static_cast<uint32_t>(kk) * kRhs + row) * 4u);
+                ev.advance();
+                const uint32_t kk = ld.point(col);
+                pn[u] = gload_at<f3v>(px, kk * 16u);
+                qn[u] = gload_at<float>(qh, (kk * kRhs + row) * 4u);
+                ld.advance();
                 // keep the step's order: its reload is issued after its MFMAs
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -361,9 +421,9 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
         float ux[4], uy[4], uz[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            ux[t] = static_cast<float>(tx[t] - li.x);
-            uy[t] = static_cast<float>(ty[t] - li.y);
-            uz[t] = static_cast<float>(tz[t] - li.z);
+            ux[t] = static_cast<float>(tc(t, 0) - li.x);
+            uy[t] = static_cast<float>(tc(t, 1) - li.y);
+            uz[t] = static_cast<float>(tc(t, 2) - li.z);
         }
         const int64_t nb = uniform64(gload<int64_t>(near_begin + e));
         const int32_t cnt = uniform32(static_cast<int32_t>(gload<int64_t>(near_count + e)));
@@ -398,7 +458,9 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
                         if (r2v[t] <= tau2) {
-                            const double dx = tx[t] - p64.x, dy = ty[t] - p64.y, dz = tz[t] - p64.z;
+                            const double dx = tc(t, 0) - p64.x;
+                            const double dy = tc(t, 1) - p64.y;
+                            const double dz = tc(t, 2) - p64.z;
                             const double r2 = __fma_rn(dz, dz, __fma_rn(dy, dy, dx * dx));
                             gv[t] = static_cast<float>(green_near_f64<KER>(r2, kappa));
                         }
@@ -436,25 +498,29 @@ template <int KER, int PREC>
 __global__ __launch_bounds__(kGroupSize) void interact_mrhs(MrhsDesc d)
 {
     __shared__ double exp_tab[64];
+    __shared__ double tlds[PREC == 0 ? 1 : 12 * kGroupSize];
     if constexpr (KER == 1)
         fill_exp2_table(exp_tab);
     if constexpr (PREC == 0)
         group_mrhs_f64<KER>(d, blockIdx.x, exp_tab);
     else
-        group_mrhs_mixed<KER>(d, blockIdx.x, exp_tab);
+        group_mrhs_mixed<KER>(d, blockIdx.x, exp_tab, tlds);
 }
 
 // Persistent work queue over the groups of many systems: every workgroup
 // repeatedly takes the next unit (system, group) -- heaviest first -- until
 // the queue is empty.  The counter is reset by reset_counter before a launch.
 template <int KER, int PREC>
-__global__ __launch_bounds__(kGroupSize) void interact_queue(const MrhsDesc* __restrict__ descs,
-                                                             const int2* __restrict__ units,
-                                                             int32_t nunits,
-                                                             int32_t* __restrict__ counter)
+// The FP32-mixed form is held to four waves per SIMD (the compiler then keeps
+// 128 VGPRs and spills a few to scratch; measured faster than three waves
+// without spills).
+__global__ __launch_bounds__(kGroupSize) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 4 : 1)))
+void interact_queue(const MrhsDesc* __restrict__ descs, const int2* __restrict__ units,
+                    int32_t nunits, int32_t* __restrict__ counter)
 {
     __shared__ int32_t next;
     __shared__ double exp_tab[64];
+    __shared__ double tlds[PREC == 0 ? 1 : 12 * kGroupSize];
     if constexpr (KER == 1)
         fill_exp2_table(exp_tab);
     for (;;) {
@@ -471,7 +537,7 @@ __global__ __launch_bounds__(kGroupSize) void interact_queue(const MrhsDesc* __r
         if constexpr (PREC == 0)
             group_mrhs_f64<KER>(descs[sys], g, exp_tab);
         else
-            group_mrhs_mixed<KER>(descs[sys], g, exp_tab);
+            group_mrhs_mixed<KER>(descs[sys], g, exp_tab, tlds);
     }
 }
 
