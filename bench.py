@@ -238,7 +238,9 @@ def run_batched(args, dev):
     info = batch.info()
     # a kernel value G(x, y) (VALU, 11 flops) serves the 16 vectors through the
     # matrix cores (16 multiply-adds); priced over the whole step
-    values = sum(p.stats()["far_evals"] + p.stats()["near_evals"] for p in plans)
+    far_values = sum(p.stats()["far_evals"] for p in plans)
+    near_values = sum(p.stats()["near_evals"] for p in plans)
+    values = far_values + near_values
     t_s = ms * 1e-3
     peak = FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS
     mpeak = MFMA_F64_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS
@@ -250,7 +252,8 @@ def run_batched(args, dev):
     return {"workload": "batched-64x16", "precision": prec, "systems": 64, "particles": total,
             "vectors": 16, "ms_per_step": ms, "targets_per_s": total / (ms * 1e-3),
             "target_vectors_per_s": 16 * total / (ms * 1e-3), "autotune_s": t_tune,
-            "leaf_sizes": sorted(set(leaves)), "units": info["units"],
+            "leaf_sizes": sorted(set(leaves)), "far_values": far_values,
+            "near_values": near_values, "units": info["units"],
             "workgroups": info["workgroups"], "graph_captures": info["graph_captures"],
             "roofline": roof, "E_par_max_sampled": max(errs) if errs else None,
             "E_par_sample": "systems 0, 4, ..., 60; vectors 0, 5, 10, 15; 200 targets each"}
