@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "parallel.hpp"
 #include "kernels_split.hpp"
 #include "setup_gpu.hpp"
 
@@ -815,16 +816,21 @@ int bltc_internal_finish_pairs(bltc_plan* plan, hipStream_t s)
     }
     const int32_t R = static_cast<int32_t>(round_unit.size()) - 1;
     // sub-units round by round, each round heaviest first, offsets relative
-    // to the round's base
-    std::vector<bltc::SymUnit> units;
-    units.reserve(static_cast<size_t>(nsubunits));
+    // to the round's base; the rounds are built and sorted on host threads
     std::vector<int32_t> round_sub(static_cast<size_t>(R) + 1, 0);
     for (int32_t r = 0; r < R; ++r) {
-        const size_t first = units.size();
+        int64_t n = 0;
+        for (int32_t k = round_unit[r]; k < round_unit[r + 1]; ++k)
+            n += sp.nsub[k];
+        round_sub[r + 1] = static_cast<int32_t>(round_sub[r] + n);
+    }
+    std::vector<bltc::SymUnit> units(static_cast<size_t>(nsubunits));
+    bltc::parallel_each(R, [&](int64_t r) {
+        size_t pos = static_cast<size_t>(round_sub[r]);
         for (int32_t k = round_unit[r]; k < round_unit[r + 1]; ++k) {
             const int32_t b = sp.ub[k], c = sp.uc[k];
             for (int32_t q = 0; q < sp.nsub[k]; ++q) {
-                bltc::SymUnit su;
+                bltc::SymUnit& su = units[pos++];
                 su.tb = pr.batch_begin[b] + q * sub;
                 su.sb = pr.batch_begin[c];
                 su.roff = sp.roff[k] - base[r] + q * sub;
@@ -835,34 +841,51 @@ int bltc_internal_finish_pairs(bltc_plan* plan, hipStream_t s)
                 su.leaf = pr.batch_node[c];
                 su.apart = sp.apart[k];
                 su.pad = 0;
-                units.push_back(su);
             }
         }
         // heaviest sub-unit first (one wave each)
-        std::stable_sort(units.begin() + static_cast<std::ptrdiff_t>(first), units.end(),
+        std::stable_sort(units.begin() + round_sub[r], units.begin() + round_sub[r + 1],
                          [](const bltc::SymUnit& a, const bltc::SymUnit& c) {
                              return static_cast<int64_t>(a.nb) * a.nc >
                                     static_cast<int64_t>(c.nb) * c.nc;
                          });
-        round_sub[r + 1] = static_cast<int32_t>(units.size());
-    }
+    });
     const int64_t held = plan->bytes;
     HIP_TRY(plan->put(&d.sym_unit, units, s));
     HIP_TRY(plan->alloc(&d.sym_out, static_cast<size_t>(ws_values)));
     d.sym_units = static_cast<int64_t>(units.size());
     if (R > 1) {
-        // fold tables: per round and batch, the batch's result entries of that round
+        // fold tables: per round and batch, the batch's result entries of that
+        // round, rounds in order, batches in order, entries in list order
+        // (counted and filled per batch on host threads)
         std::vector<int32_t> off(static_cast<size_t>(R) * (nb + 1), 0);
-        std::vector<int64_t> fbase;
+        auto round_of = [&](int64_t v) {
+            return static_cast<int32_t>(std::upper_bound(base.begin(), base.end(), v) -
+                                        base.begin()) - 1;
+        };
+        bltc::parallel_for(nb, [&](int64_t b) {
+            for (int32_t e = sp.pc_off[b]; e < sp.pc_off[b + 1]; ++e)
+                ++off[round_of(sp.pc_base[e]) * (nb + 1) + b];
+        });
+        int32_t total = 0;
         for (int32_t r = 0; r < R; ++r) {
             for (int64_t b = 0; b < nb; ++b) {
-                off[r * (nb + 1) + b] = static_cast<int32_t>(fbase.size());
-                for (int32_t e = sp.pc_off[b]; e < sp.pc_off[b + 1]; ++e)
-                    if (sp.pc_base[e] >= base[r] && sp.pc_base[e] < base[r + 1])
-                        fbase.push_back(sp.pc_base[e] - base[r]);
+                const int32_t c = off[r * (nb + 1) + b];
+                off[r * (nb + 1) + b] = total;
+                total += c;
             }
-            off[r * (nb + 1) + nb] = static_cast<int32_t>(fbase.size());
+            off[r * (nb + 1) + nb] = total;
         }
+        std::vector<int64_t> fbase(static_cast<size_t>(total));
+        bltc::parallel_for(nb, [&](int64_t b) {
+            std::vector<int32_t> next(static_cast<size_t>(R));
+            for (int32_t r = 0; r < R; ++r)
+                next[r] = off[r * (nb + 1) + b];
+            for (int32_t e = sp.pc_off[b]; e < sp.pc_off[b + 1]; ++e) {
+                const int32_t r = round_of(sp.pc_base[e]);
+                fbase[next[r]++] = sp.pc_base[e] - base[r];
+            }
+        });
         std::vector<int64_t> bend(static_cast<size_t>(nb));
         int64_t ntgt = 0;
         for (int64_t b = 0; b < nb; ++b) {

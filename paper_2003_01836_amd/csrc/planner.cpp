@@ -15,11 +15,11 @@
 // non-leaf cluster (direct sum at a leaf); a size-only failure is a direct sum
 // over the whole cluster.
 #include "planner.hpp"
+#include "parallel.hpp"
 
 #include <algorithm>
 #include <limits>
 #include <map>
-#include <unordered_map>
 #include <atomic>
 #include <chrono>
 #include <climits>
@@ -29,36 +29,6 @@
 #include <thread>
 
 namespace bltc {
-namespace {
-
-template <class F>
-void parallel_for(int64_t n, F&& f)
-{
-    unsigned hw = std::thread::hardware_concurrency();
-    int64_t nthr = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 1, 16));
-    if (n < 64 || nthr == 1) {
-        for (int64_t i = 0; i < n; ++i)
-            f(i);
-        return;
-    }
-    std::vector<std::thread> th;
-    std::atomic_int64_t next{0};
-    for (int64_t t = 0; t < nthr; ++t)
-        th.emplace_back([&]() {
-            for (;;) {
-                int64_t i = next.fetch_add(16);
-                if (i >= n)
-                    break;
-                int64_t e = std::min<int64_t>(n, i + 16);
-                for (; i < e; ++i)
-                    f(i);
-            }
-        });
-    for (auto& t : th)
-        t.join();
-}
-
-}  // namespace
 
 int32_t Tree::add_node(int64_t b, int64_t c, int32_t lev, int32_t par)
 {
@@ -525,102 +495,156 @@ bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, int64_t
     std::vector<int32_t> batch_of_node(S.nodes(), -1);
     for (int64_t b = 0; b < nb; ++b)
         batch_of_node[batch_node[b]] = static_cast<int32_t>(b);
-    // sorted direct partners (as batches) of every batch, for membership tests
-    std::vector<std::vector<int32_t>> partners(nb);
-    for (int64_t b = 0; b < nb; ++b) {
+    // direct partners (as batches) of every batch, sorted within the batch's
+    // segment [near_off[b], near_off[b + 1]), for membership tests
+    const int64_t ne = nb > 0 ? near_off[nb] : 0;
+    std::vector<int32_t> part(static_cast<size_t>(ne));
+    std::atomic<bool> not_leaf{false};
+    parallel_for(nb, [&](int64_t b) {
         for (int32_t e = near_off[b]; e < near_off[b + 1]; ++e) {
             const int32_t c = batch_of_node[near_leaf[e]];
             if (c < 0)
-                return false;   // a direct entry that is not a leaf
-            partners[b].push_back(c);
+                not_leaf = true;
+            part[e] = c;
         }
-        std::sort(partners[b].begin(), partners[b].end());
-    }
-    auto has = [&](int64_t b, int32_t c) {
-        return std::binary_search(partners[b].begin(), partners[b].end(), c);
+        std::sort(part.begin() + near_off[b], part.begin() + near_off[b + 1]);
+    });
+    if (not_leaf)
+        return false;   // a direct entry that is not a leaf
+    // position of c in b's sorted partners, or -1
+    auto find = [&](int64_t b, int32_t c) -> int64_t {
+        const auto first = part.begin() + near_off[b], last = part.begin() + near_off[b + 1];
+        const auto it = std::lower_bound(first, last, c);
+        return it != last && *it == c ? it - part.begin() : -1;
     };
-    // units: every mutual pair once, from its lower batch
-    std::vector<std::pair<int32_t, int32_t>> units;
+    // units: every mutual pair once, from its lower batch, in batch order and
+    // partner order (per batch on host threads: count, then fill)
+    std::vector<int64_t> uoff(static_cast<size_t>(nb) + 1, 0);
+    parallel_for(nb, [&](int64_t b) {
+        int64_t m = 0;
+        for (int32_t e = near_off[b]; e < near_off[b + 1]; ++e)
+            m += part[e] > b && find(part[e], static_cast<int32_t>(b)) >= 0;
+        uoff[b + 1] = m;
+    });
     for (int64_t b = 0; b < nb; ++b)
-        for (int32_t c : partners[b])
-            if (c > b && has(c, static_cast<int32_t>(b)))
-                units.emplace_back(static_cast<int32_t>(b), c);
+        uoff[b + 1] += uoff[b];
+    // (pair evaluations, lower batch, upper batch)
+    struct Cand {
+        int64_t evals;
+        int32_t b, c;
+    };
+    std::vector<Cand> units(static_cast<size_t>(uoff[nb]));
     if (units.empty())
         return false;
-    auto evals = [&](const std::pair<int32_t, int32_t>& u) {
-        return batch_count[u.first] * batch_count[u.second];
-    };
-    std::stable_sort(units.begin(), units.end(),
-                     [&](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& c) {
-                         return evals(a) > evals(c);
-                     });
+    parallel_for(nb, [&](int64_t b) {
+        int64_t k = uoff[b];
+        for (int32_t e = near_off[b]; e < near_off[b + 1]; ++e) {
+            const int32_t c = part[e];
+            if (c > b && find(c, static_cast<int32_t>(b)) >= 0)
+                units[k++] = Cand{batch_count[b] * batch_count[c], static_cast<int32_t>(b), c};
+        }
+    });
+    // heaviest first; equal weights keep the batch and partner order
+    parallel_sort(units.begin(), units.end(), [](const Cand& a, const Cand& c) {
+        if (a.evals != c.evals)
+            return a.evals > c.evals;
+        return a.b != c.b ? a.b < c.b : a.c < c.c;
+    });
     // heaviest first while the results fit in max_out values; the mutual pairs
     // left over stay in the lists
     SymPlan out;
     out.sub = sub;
+    std::vector<int64_t> taken;
     int64_t off = 0;
-    std::unordered_map<int64_t, int64_t> unit_of;
-    unit_of.reserve(units.size());
-    auto key = [](int32_t lo, int32_t hi) {
-        return (static_cast<int64_t>(lo) << 32) | static_cast<uint32_t>(hi);
-    };
-    for (const auto& u : units) {
-        const int64_t nbk = batch_count[u.first], nck = batch_count[u.second];
+    for (int64_t k = 0; k < static_cast<int64_t>(units.size()); ++k) {
+        const int64_t nbk = batch_count[units[k].b], nck = batch_count[units[k].c];
         const int64_t ns = (nbk + sub - 1) / sub;
         const int64_t size = nbk + ns * nck;
         if (size > max_unit || off + size > max_out)
             continue;
-        unit_of[key(u.first, u.second)] = static_cast<int64_t>(out.ub.size());
-        out.ub.push_back(u.first);
-        out.uc.push_back(u.second);
-        out.nsub.push_back(static_cast<int32_t>(ns));
+        taken.push_back(k);
+        out.roff.push_back(off);
+        out.coff.push_back(off + nbk);
+        off += size;
+        out.pair_evals += units[k].evals;
+    }
+    out.out_size = off;
+    if (taken.empty())
+        return false;
+    // the taken units' fields; unit_at[e]: the unit of sorted partner entry e
+    // (in both batches' segments), or -1
+    const int64_t nu = static_cast<int64_t>(taken.size());
+    out.ub.resize(nu);
+    out.uc.resize(nu);
+    out.nsub.resize(nu);
+    out.apart.resize(nu);
+    std::vector<int32_t> unit_at(static_cast<size_t>(ne), -1);
+    parallel_for(nu, [&](int64_t id) {
+        const Cand& u = units[taken[id]];
+        out.ub[id] = u.b;
+        out.uc[id] = u.c;
+        out.nsub[id] = static_cast<int32_t>((batch_count[u.b] + sub - 1) / sub);
+        unit_at[find(u.b, u.c)] = static_cast<int32_t>(id);
+        unit_at[find(u.c, u.b)] = static_cast<int32_t>(id);
         // separation of the two leaves' boxes (points with equal coordinates
         // always share a leaf, so distinct leaves have a positive gap; the
         // test guards against squares that would underflow)
-        const int64_t bn = batch_node[u.first], cn = batch_node[u.second];
+        const int64_t bn = batch_node[u.b], cn = batch_node[u.c];
         double gap = -std::numeric_limits<double>::infinity();
         for (int l = 0; l < 3; ++l)
             gap = std::max(gap, std::max(S.lo[3 * cn + l] - S.hi[3 * bn + l],
                                          S.lo[3 * bn + l] - S.hi[3 * cn + l]));
-        out.apart.push_back(gap >= 0x1p-500 ? 1 : 0);
-        out.roff.push_back(off);
-        out.coff.push_back(off + nbk);
-        off += nbk + ns * nck;
-        out.pair_evals += evals(u);
-    }
-    out.out_size = off;
-    if (out.ub.empty())
-        return false;
-    // reduced lists in the original list order, and the costs left to the batches
+        out.apart[id] = gap >= 0x1p-500 ? 1 : 0;
+    });
+    // reduced lists in the original list order, and the costs left to the
+    // batches (per batch on host threads: count, then fill)
     out.near_off.assign(nb + 1, 0);
     out.pc_off.assign(nb + 1, 0);
     out.batch_cost = (*dl.batch_cost);
+    auto unit_of_entry = [&](int64_t b, int32_t e) -> int64_t {
+        const int32_t c = batch_of_node[near_leaf[e]];
+        return c != b ? unit_at[find(b, c)] : -1;
+    };
+    parallel_for(nb, [&](int64_t b) {
+        int32_t nl = 0, npc = 0;
+        for (int32_t e = near_off[b]; e < near_off[b + 1]; ++e) {
+            const int64_t u = unit_of_entry(b, e);
+            if (u < 0)
+                ++nl;
+            else
+                npc += b < out.uc[u] ? 1 : out.nsub[u];
+        }
+        out.near_off[b + 1] = nl;
+        out.pc_off[b + 1] = npc;
+    });
     for (int64_t b = 0; b < nb; ++b) {
+        out.near_off[b + 1] += out.near_off[b];
+        out.pc_off[b + 1] += out.pc_off[b];
+    }
+    out.near_leaf.resize(out.near_off[nb]);
+    out.near_begin.resize(out.near_off[nb]);
+    out.near_count.resize(out.near_off[nb]);
+    out.pc_base.resize(out.pc_off[nb]);
+    parallel_for(nb, [&](int64_t b) {
+        int32_t kl = out.near_off[b], kp = out.pc_off[b];
         for (int32_t e = near_off[b]; e < near_off[b + 1]; ++e) {
             const int32_t leaf = near_leaf[e];
-            const int32_t c = batch_of_node[leaf];
-            const int32_t lo = std::min<int32_t>(static_cast<int32_t>(b), c);
-            const int32_t hi = std::max<int32_t>(static_cast<int32_t>(b), c);
-            const auto it = c != b ? unit_of.find(key(lo, hi)) : unit_of.end();
-            if (it == unit_of.end()) {
-                out.near_leaf.push_back(leaf);
-                out.near_begin.push_back(S.begin[leaf]);
-                out.near_count.push_back(S.count[leaf]);
-                continue;
-            }
-            const int64_t u = it->second;
-            if (b == lo) {
-                out.pc_base.push_back(out.roff[u]);
+            const int64_t u = unit_of_entry(b, e);
+            if (u < 0) {
+                out.near_leaf[kl] = leaf;
+                out.near_begin[kl] = S.begin[leaf];
+                out.near_count[kl] = S.count[leaf];
+                ++kl;
+            } else if (b < out.uc[u]) {
+                out.pc_base[kp++] = out.roff[u];
                 out.batch_cost[b] -= S.count[leaf] - 1;   // one read instead of |C| evaluations
             } else {
                 for (int32_t q = 0; q < out.nsub[u]; ++q)
-                    out.pc_base.push_back(out.coff[u] + q * batch_count[b]);
+                    out.pc_base[kp++] = out.coff[u] + q * batch_count[b];
                 out.batch_cost[b] -= S.count[leaf] - out.nsub[u];
             }
         }
-        out.near_off[b + 1] = static_cast<int32_t>(out.near_leaf.size());
-        out.pc_off[b + 1] = static_cast<int32_t>(out.pc_base.size());
-    }
+    });
     sp = std::move(out);
     return true;
 }
