@@ -228,7 +228,12 @@ __global__ __launch_bounds__(64) void proxy_potentials(
 #pragma unroll
                 for (int u = 0; u < kProxyK1; ++u) {
                     const double d1 = t1[u] - p.x;
-                    acc[u] = __fma_rn(green_far_f64<KER>(__fma_rn(d1, d1, bc), ka), p.w, acc[u]);
+                    const double r2 = __fma_rn(d1, d1, bc);
+                    // FP64 plans sum 2 G (the Newton step's factor, halved at
+                    // the store: the same sums exactly); here the FP32-mixed
+                    // plans' FP64 terms are added to FP32 partial sums
+                    const double gv = MIXED ? green_far_f64<KER>(r2, ka) : green_far2_f64<KER>(r2, ka);
+                    acc[u] = __fma_rn(gv, p.w, acc[u]);
                 }
             }
         }
@@ -238,7 +243,7 @@ __global__ __launch_bounds__(64) void proxy_potentials(
 #pragma unroll
         for (int u = 0; u < kProxyK1; ++u)
             if (kProxyK1 * g + u < NP)
-                dst[(kProxyK1 * g + u) * NP2] = acc[u];
+                dst[(kProxyK1 * g + u) * NP2] = MIXED ? acc[u] : 0.5 * acc[u];
     }
 }
 
