@@ -475,6 +475,71 @@ def run_large(args, dev):
     return res
 
 
+def run_multi(args, dev):
+    """The headline points (10^6 uniform, Coulomb, theta 0.7, n 8, N_L = N_B = 2000)
+    with 16 charge vectors through one multi-vector plan (kernel values shared,
+    contraction on the matrix cores), FP64 and FP32-mixed, beside the one-vector
+    FP64 plan on the first vector: per-vector throughput at the same accuracy.
+    Errors against the oracle's treecode on the sampled targets, vectors 0 and 15."""
+    import numpy as np
+    import torch
+
+    import paper_2003_01836_amd as bltc
+    from paper_2003_01836_amd import inputs
+
+    w = WORKLOADS["uniform-1M"]
+    n, m = w["n"], 16
+    log(f"multi: generating {n} particles, {m} charge vectors")
+    pos, q = inputs.uniform_cube(n, inputs.config_seed(w["cfg"]), m=m)
+    t = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
+    qd = torch.from_numpy(np.ascontiguousarray(q)).to(dev)
+    phi = torch.empty((m, n), dtype=torch.float64, device=dev)
+    smp = inputs.sample_indices(n, w["samples"], inputs.sample_seed(w["cfg"]))
+    kw = dict(theta=w["theta"], degree=w["degree"], leaf_size=w["leaf"], batch_size=w["batch"])
+    res = {"workload": f"multi uniform-1M x{m}: N={n}, {m} charge vectors, coulomb, "
+                       f"theta={w['theta']}, n={w['degree']}, N_L=N_B={w['leaf']}", "paths": {}}
+
+    def timed(plan, qv, out):
+        for _ in range(args.warmup):
+            plan.execute(qv, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.execute(qv, out=out)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / args.steps
+
+    # the plain FP64 path: one vector per evaluation, its own autotuned lanes per target
+    _, tpt, _ = bltc.autotune(t, t, candidates=(w["leaf"],), use_cache=False, full=True,
+                              precision="fp64", **{k: v for k, v in kw.items()
+                                                   if k in ("theta", "degree")})
+    one = bltc.Plan(t, t, precision="fp64", threads_per_target=max(1, tpt), **kw)
+    ms1 = timed(one, qd[0].contiguous(), phi[0])
+    del one
+    res["one_vector_fp64"] = {"ms_per_vector": ms1, "targets_per_s": n / (ms1 * 1e-3),
+                              "threads_per_target": max(1, tpt)}
+    log(f"multi: one-vector FP64 {ms1:.2f} ms per vector")
+    got = {}
+    for prec in ("fp64", "fp32_mixed"):
+        plan = bltc.Plan(t, t, precision=prec, max_q=m, **kw)
+        ms = timed(plan, qd, phi)
+        got[prec] = phi[[0, m - 1]].cpu().numpy()
+        res["paths"][prec] = {"ms_per_step": ms, "ms_per_vector": ms / m,
+                              "target_vectors_per_s": m * n / (ms * 1e-3),
+                              "speedup_per_vector_vs_one_vector_fp64": ms1 / (ms / m)}
+        log(f"multi {prec}: {ms:.1f} ms for {m} vectors ({ms / m:.2f} ms per vector, "
+            f"{ms1 / (ms / m):.2f}x the one-vector FP64 path)")
+        del plan
+    if not args.no_cpu:
+        import oracle
+        oc = oracle.Treecode(pos, pos, w["theta"], w["degree"], w["leaf"], w["batch"])
+        ref = oc.potential(q[[0, m - 1]], sample=smp)
+        for prec in got:
+            res["paths"][prec]["E_par"] = max(rel_l2(ref[i], got[prec][i][smp]) for i in range(2))
+            log(f"multi {prec}: E_par {res['paths'][prec]['E_par']:.2e} (vectors 0 and {m - 1})")
+    return res
+
+
 def run_variant(args, dev):
     """Cluster-particle (targets interpolated) or cluster-cluster (both sides)
     treecode on the headline workload: 10^6 uniform, Coulomb, theta 0.7, n 8,
@@ -697,7 +762,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="uniform-1M",
                     choices=sorted(WORKLOADS) + ["batched-64x16", "yukawa-plummer-sweep", "uniform-large",
-                                                 "setup", "cp", "cc", "hermite", "accuracy-sweep"])
+                                                 "setup", "cp", "cc", "hermite", "accuracy-sweep",
+                                                 "multi-1M"])
     ap.add_argument("--thetas", type=float, nargs="+", default=[0.5, 0.7, 0.8, 0.9],
                     help="accuracy-sweep workload: MAC parameters")
     ap.add_argument("--degrees", type=int, nargs="+", default=[3, 4, 5, 6, 7, 8, 9, 10],
@@ -736,11 +802,11 @@ def main():
         return 1
     dev = torch.device("cuda:0")
     if args.workload in ("batched-64x16", "yukawa-plummer-sweep", "uniform-large", "setup", "cp",
-                         "cc", "hermite", "accuracy-sweep"):
+                         "cc", "hermite", "accuracy-sweep", "multi-1M"):
         fn = {"batched-64x16": run_batched, "yukawa-plummer-sweep": run_sweep,
               "uniform-large": run_large, "setup": run_setup, "cp": run_variant,
               "cc": run_variant, "hermite": run_hermite,
-              "accuracy-sweep": run_accuracy}[args.workload]
+              "accuracy-sweep": run_accuracy, "multi-1M": run_multi}[args.workload]
         print(json.dumps(fn(args, dev)), flush=True)
         return 0
     w = WORKLOADS[args.workload]

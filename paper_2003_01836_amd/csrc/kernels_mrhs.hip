@@ -494,8 +494,10 @@ __device__ __forceinline__ void group_mrhs_mixed(const MrhsDesc& d, int g, const
     }
 }
 
+// four waves per SIMD on the FP32-mixed form, as for the work queue below
 template <int KER, int PREC>
-__global__ __launch_bounds__(kGroupSize) void interact_mrhs(MrhsDesc d)
+__global__ __launch_bounds__(kGroupSize) __attribute__((amdgpu_waves_per_eu(PREC == 1 ? 4 : 1)))
+void interact_mrhs(MrhsDesc d)
 {
     __shared__ double exp_tab[64];
     __shared__ double tlds[PREC == 0 ? 1 : 12 * kGroupSize];
