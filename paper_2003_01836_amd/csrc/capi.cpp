@@ -272,23 +272,14 @@ int upload_split(bltc_plan* plan, hipStream_t s)
     } else {
         HIP_TRY(plan->put(&t.near_off, split(hp.near_off), s));
     }
-    // T copies of the targets; copy p writes p nt + caller index
-    std::vector<int64_t> orig(static_cast<size_t>(nt));
-    if (plan->device_particles) {
-        if (nt > 0)
-            HIP_TRY(hipMemcpy(orig.data(), d.tgt_orig, nt * sizeof(int64_t), hipMemcpyDeviceToHost));
-    } else {
-        orig = hp.tgt.order;
-    }
-    std::vector<int64_t> orig_t(static_cast<size_t>(T * nt)), end_t(static_cast<size_t>(nb * T));
-    for (int32_t p = 0; p < T; ++p)
-        for (int64_t i = 0; i < nt; ++i)
-            orig_t[p * nt + i] = p * nt + orig[i];
+    // T copies of the targets, written on the device; copy p writes p nt +
+    // caller index
     HIP_TRY(plan->alloc(&t.tgt, static_cast<size_t>(T * nt)));
-    for (int32_t p = 0; p < T; ++p)
-        HIP_TRY(hipMemcpyAsync(t.tgt + p * nt, d.tgt, nt * sizeof(double4),
-                               hipMemcpyDeviceToDevice, s));
-    HIP_TRY(plan->put(&t.tgt_orig, orig_t, s));
+    int64_t* orig_t = nullptr;
+    HIP_TRY(plan->alloc(&orig_t, static_cast<size_t>(T * nt)));
+    t.tgt_orig = orig_t;
+    HIP_TRY(bltc::launch_replicate_targets(t.tgt, orig_t, d.tgt, d.tgt_orig, nt, T, s));
+    std::vector<int64_t> end_t(static_cast<size_t>(nb * T));
     // batches, their boxes (FP32-mixed) and the workgroup schedule, each
     // piece with 1/T of its batch's work
     std::vector<int64_t> begin_t(static_cast<size_t>(nb * T)), count_t(begin_t.size()),
