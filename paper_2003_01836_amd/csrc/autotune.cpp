@@ -17,7 +17,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <fstream>
+#include <new>
 #include <sstream>
 #include <string>
 
@@ -223,8 +225,14 @@ extern "C" int bltc_autotune(const bltc_params* p, int64_t nt, const double* tx,
     for (int32_t c = 0; c < ncand; ++c)
         if (candidates[c] < 1)
             return fail(BLTC_EINVAL, "candidate sizes must be >= 1");
-    return autotune_impl(p, nt, tx, ty, tz, ns, sx, sy, sz, num_q, candidates, ncand, use_cache,
-                         out, best_ms, stream);
+    try {
+        return autotune_impl(p, nt, tx, ty, tz, ns, sx, sy, sz, num_q, candidates, ncand,
+                             use_cache, out, best_ms, stream);
+    } catch (const std::bad_alloc&) {
+        return fail(BLTC_ENOMEM, "host allocation failed while tuning");
+    } catch (const std::exception& ex) {
+        return fail(BLTC_EINTERNAL, "tuning failed: %s", ex.what());
+    }
 }
 
 int bltc_internal_tune(const bltc_params* p, int64_t nt, const double* tx, const double* ty,

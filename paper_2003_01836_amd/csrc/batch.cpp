@@ -10,6 +10,8 @@
 // sequence is captured once into a hipGraph per set of caller buffers and
 // replayed afterwards.
 #include <cstring>
+#include <exception>
+#include <new>
 
 #include "internal.hpp"
 
@@ -81,11 +83,7 @@ int enqueue(bltc_batch* b, const double* const* q, const int32_t* num_q, const i
     return BLTC_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int bltc_batch_create(bltc_batch** out, bltc_plan* const* plans, int32_t count, void* stream)
+int batch_create(bltc_batch** out, bltc_plan* const* plans, int32_t count, void* stream)
 {
     if (!out)
         return fail(BLTC_EINVAL, "out is NULL");
@@ -195,9 +193,8 @@ int bltc_batch_create(bltc_batch** out, bltc_plan* const* plans, int32_t count, 
     return BLTC_OK;
 }
 
-int bltc_batch_execute(bltc_batch* b, const double* const* q, const int32_t* num_q,
-                       const int64_t* q_ld, double* const* phi, const int64_t* phi_ld,
-                       void* stream)
+int batch_execute(bltc_batch* b, const double* const* q, const int32_t* num_q,
+                  const int64_t* q_ld, double* const* phi, const int64_t* phi_ld, void* stream)
 {
     if (!b || !q || !num_q || !q_ld || !phi || !phi_ld)
         return fail(BLTC_EINVAL, "NULL argument");
@@ -269,6 +266,36 @@ int bltc_batch_execute(bltc_batch* b, const double* const* q, const int32_t* num
     HIP_TRY(hipGraphLaunch(b->exec, s));
     ++b->launches;
     return BLTC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+// host allocations of the planner and the batch tables may throw: no
+// exception leaves the C ABI
+int bltc_batch_create(bltc_batch** out, bltc_plan* const* plans, int32_t count, void* stream)
+{
+    try {
+        return batch_create(out, plans, count, stream);
+    } catch (const std::bad_alloc&) {
+        return fail(BLTC_ENOMEM, "host allocation failed while building the batch");
+    } catch (const std::exception& ex) {
+        return fail(BLTC_EINTERNAL, "batch creation failed: %s", ex.what());
+    }
+}
+
+int bltc_batch_execute(bltc_batch* b, const double* const* q, const int32_t* num_q,
+                       const int64_t* q_ld, double* const* phi, const int64_t* phi_ld,
+                       void* stream)
+{
+    try {
+        return batch_execute(b, q, num_q, q_ld, phi, phi_ld, stream);
+    } catch (const std::bad_alloc&) {
+        return fail(BLTC_ENOMEM, "host allocation failed");
+    } catch (const std::exception& ex) {
+        return fail(BLTC_EINTERNAL, "%s", ex.what());
+    }
 }
 
 int bltc_batch_set_graph(bltc_batch* b, int32_t enable)

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
+#include <exception>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -18,7 +20,8 @@ inline int64_t planner_threads()
 }
 
 // f(i) for i in [0, n), indices handed out `grain` at a time; serial below
-// `serial_below` items.  f must not throw.
+// `serial_below` items.  An exception thrown by f (say std::bad_alloc) stops
+// the hand-out and is rethrown to the caller once every thread has joined.
 template <class F>
 void parallel_for(int64_t n, F&& f, int64_t grain = 16, int64_t serial_below = 64)
 {
@@ -30,19 +33,30 @@ void parallel_for(int64_t n, F&& f, int64_t grain = 16, int64_t serial_below = 6
     }
     std::vector<std::thread> th;
     std::atomic<int64_t> next{0};
+    std::mutex err_mu;
+    std::exception_ptr err;
     for (int64_t t = 0; t < nthr; ++t)
         th.emplace_back([&]() {
-            for (;;) {
-                int64_t i = next.fetch_add(grain);
-                if (i >= n)
-                    break;
-                const int64_t e = std::min<int64_t>(n, i + grain);
-                for (; i < e; ++i)
-                    f(i);
+            try {
+                for (;;) {
+                    int64_t i = next.fetch_add(grain);
+                    if (i >= n)
+                        break;
+                    const int64_t e = std::min<int64_t>(n, i + grain);
+                    for (; i < e; ++i)
+                        f(i);
+                }
+            } catch (...) {
+                next = n;   // no more work for anyone
+                std::lock_guard<std::mutex> lock(err_mu);
+                if (!err)
+                    err = std::current_exception();
             }
         });
     for (auto& t : th)
         t.join();
+    if (err)
+        std::rethrow_exception(err);
 }
 
 // the same for a few heavy items: one index at a time, threads from 2 items on
