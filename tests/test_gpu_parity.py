@@ -284,6 +284,30 @@ def test_benchmark_plan_four_threads_per_target(dev, uniform_1m, precision):
         assert_mixed(ref, phi[smp], pos, pos, q[0], idx=smp, what="1M 4 lanes per target")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_benchmark_points_sixteen_vectors(dev, precision):
+    # the multi-vector plan of the multi-1M benchmark: the headline points with
+    # 16 charge vectors; the oracle's treecode on the sampled targets, vectors
+    # 0, 7 and 15 (vector 0 is the headline's charge vector)
+    import paper_2003_01836_amd as bltc
+    n, m = 1_000_000, 16
+    pos, q = inputs.uniform_cube(n, inputs.config_seed(1), m=m)
+    smp = inputs.sample_indices(n, 1000, inputs.sample_seed(1))
+    vec = [0, 7, 15]
+    ref = oracle.Treecode(pos, pos, 0.7, 8, 2000, 2000).potential(q[vec], sample=smp)
+    t = _dev_soa(pos, dev)
+    plan = bltc.Plan(t, t, theta=0.7, degree=8, leaf_size=2000, batch_size=2000, max_q=m,
+                     precision=precision)
+    phi = plan.execute(torch.from_numpy(np.ascontiguousarray(q)).to(dev))
+    torch.cuda.synchronize()
+    got = phi.cpu().numpy()
+    for i, v in enumerate(vec):
+        if precision == "fp64":
+            _close(ref[i], got[v][smp])
+        else:
+            assert_mixed(ref[i], got[v][smp], pos, pos, q[v], idx=smp, what=f"1M vector {v}")
+
+
 # --------------------------------------------------------------------------
 # FP32-mixed path against the FP64 oracle: relative 2-norm <= 1e-6, largest
 # difference <= 1e-5 of the largest potential, and per target at most a stated
