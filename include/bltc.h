@@ -327,7 +327,8 @@ void bltc_plan_destroy(bltc_plan* plan);
  * buffers/counts is seen and replayed afterwards (a new set of buffers is
  * re-captured; that call synchronises `stream`).  Enqueued on `stream`.
  * Calls on one batch must not overlap.  BLTC_EINVAL on mismatched plans,
- * counts or NULL buffers. */
+ * counts or NULL buffers; BLTC_ENOMEM when a host or device allocation of the
+ * batch tables fails (no C++ exception leaves any bltc_* call). */
 typedef struct bltc_batch bltc_batch;
 
 typedef struct {
