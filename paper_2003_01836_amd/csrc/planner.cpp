@@ -544,12 +544,22 @@ bool plan_symmetric(const DirectLists& dl, int64_t sub, int64_t max_out, int64_t
                 units[k++] = Cand{batch_count[b] * batch_count[c], static_cast<int32_t>(b), c};
         }
     });
-    // heaviest first; equal weights keep the batch and partner order
-    parallel_sort(units.begin(), units.end(), [](const Cand& a, const Cand& c) {
-        if (a.evals != c.evals)
-            return a.evals > c.evals;
-        return a.b != c.b ? a.b < c.b : a.c < c.c;
-    });
+    // heaviest first (equal weights keep the batch and partner order) when the
+    // caps below leave some unit out; when every unit fits, the batch order
+    // serves as well (it only places the units' results)
+    int64_t total = 0, largest = 0;
+    for (const Cand& u : units) {
+        const int64_t nbk = batch_count[u.b], nck = batch_count[u.c];
+        const int64_t size = nbk + ((nbk + sub - 1) / sub) * nck;
+        total += size;
+        largest = std::max(largest, size);
+    }
+    if (total > max_out || largest > max_unit)
+        parallel_sort(units.begin(), units.end(), [](const Cand& a, const Cand& c) {
+            if (a.evals != c.evals)
+                return a.evals > c.evals;
+            return a.b != c.b ? a.b < c.b : a.c < c.c;
+        });
     // heaviest first while the results fit in max_out values; the mutual pairs
     // left over stay in the lists
     SymPlan out;

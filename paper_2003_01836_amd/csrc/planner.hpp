@@ -108,7 +108,8 @@ struct HostPlan {
 // sources) to out[roff + s sub ..] and its column sums (at C's targets from
 // its B sources) to out[coff + s |C| .. + |C|).
 struct SymPlan {
-    std::vector<int32_t> ub, uc;        // batches of a unit, ub < uc; heaviest unit first
+    std::vector<int32_t> ub, uc;        // batches of a unit, ub < uc; heaviest unit first when
+                                        // the caps leave some out, else in batch order
     std::vector<int64_t> roff, coff;    // out offsets of a unit's rows and first column block
     std::vector<int32_t> nsub;          // sub-units of a unit: ceil(|B| / sub)
     // 1 when the two leaves' boxes are at least 2^-500 apart in some dimension:
