@@ -55,3 +55,28 @@ def test_issue_model_from_the_committed_counters(tmp_path, monkeypatch):
     cycles = (1e9 - 1e8) * bench.CYCLES_FMA32 + 1e8 * bench.CYCLES_TRANS32
     assert abs(m["t_min_ms"] - cycles / bench.SIMDS / bench.CLOCK_HZ * 1e3) < 1e-9
     assert abs(m["frac"] - m["t_min_ms"] / 2.0) < 1e-12
+
+
+def test_committed_profiles_cover_the_headline_kernels():
+    """The counters the bench line reads (HBM traffic, instruction counts, clocks)
+    exist for the headline kernels as they are now: every interaction kernel at
+    2 and 4 threads per target, the pair kernels, both upward instantiations.
+    A kernel source edited after the counters were taken fails here."""
+    sys.path.insert(0, ROOT)
+    import bench
+    for kernel in ("interact_f64", "interact_mixed"):
+        for tpt in (2, 4):
+            assert bench.counter_value("traffic_bytes", "interact_uniform-1M_counters.md",
+                                       kernel, 8, 0, tpt) is not None, (kernel, tpt)
+            assert bench.counter_value("valu_insts", "interact_uniform-1M_valu_counters.md",
+                                       kernel, 8, 0, tpt) is not None, (kernel, tpt)
+            assert bench.counter_value("clock_hz", "interact_uniform-1M_valu_counters.md",
+                                       kernel, 8, 0, tpt) is not None, (kernel, tpt)
+    for kernel in ("near_pairs_f64", "near_pairs_mixed"):
+        assert bench.counter_value("traffic_bytes", "interact_uniform-1M_counters.md",
+                                   kernel, 8, 0) is not None, kernel
+        assert bench.counter_value("valu_insts", "interact_uniform-1M_valu_counters.md",
+                                   kernel, 8, 0) is not None, kernel
+    for ker_id in (0, 1):
+        assert bench.counter_value("mfma_busy_cycles", "upward_uniform-1M_mfma_counters.md",
+                                   "upward_single", 8, ker_id) is not None, ker_id
