@@ -241,6 +241,14 @@ __device__ __forceinline__ double far_sum_hermite_f32(double x, double y, double
     return acc;
 }
 
+// LDS staging of the FP32 modified charges at n = 4 (1000 values, 4 KB per
+// one-wave workgroup): 4% faster there; at n = 2 and 3 the two barriers per
+// cluster cost more than the scalar loads save, and at n = 6 the LDS size
+// costs occupancy, so the other degrees read the charges through the scalar
+// cache
+template <int N>
+constexpr bool kStageHermite = N == 4;
+
 template <int N, int KER>
 __global__ __launch_bounds__(kGroupSize) void interact_hermite_mixed(
     const double4* __restrict__ tgt, const int64_t* __restrict__ tgt_orig,
@@ -270,8 +278,9 @@ __global__ __launch_bounds__(kGroupSize) void interact_hermite_mixed(
         return;  // empty slot of the per-die schedule
     const int64_t first = group_first[g];
     const int64_t end = batch_end[b];
-    if (first + (threadIdx.x & ~63) >= end)
-        return;  // the whole wave lies past the batch end
+    // (one-vector plans launch one wave per workgroup, so every wave of a
+    // workgroup reaches the barriers of the far-field loop below; a wave
+    // past the batch end evaluates its clamped targets and stores nothing)
     int64_t i = first + threadIdx.x;
     const bool valid = i < end;
     if (!valid)
@@ -279,10 +288,26 @@ __global__ __launch_bounds__(kGroupSize) void interact_hermite_mixed(
     const double4 t = tgt[i];
     double acc = 0.0;
     const int f_end = far_off[b + 1];
-    for (int f = far_off[b]; f < f_end; ++f) {
-        const int64_t slot = far_slot[f];
-        acc += far_sum_hermite_f32<N, KER>(t.x, t.y, t.z, slot_nodes + slot * 3 * NP,
-                                           qh32 + slot * P8, nk, kf);
+    if constexpr (kStageHermite<N>) {
+        // the cluster's 8 (n+1)^3 modified charges staged in LDS, as in the
+        // FP32-mixed BLTC kernel
+        extern __shared__ float qs[];
+        for (int f = far_off[b]; f < f_end; ++f) {
+            const int64_t slot = far_slot[f];
+            const float* __restrict__ qg = qh32 + slot * P8;
+            __syncthreads();   // the previous cluster's charges are read
+            for (int k = threadIdx.x; k < P8; k += blockDim.x)
+                qs[k] = qg[k];
+            __syncthreads();
+            acc += far_sum_hermite_f32<N, KER>(t.x, t.y, t.z, slot_nodes + slot * 3 * NP, qs,
+                                               nk, kf);
+        }
+    } else {
+        for (int f = far_off[b]; f < f_end; ++f) {
+            const int64_t slot = far_slot[f];
+            acc += far_sum_hermite_f32<N, KER>(t.x, t.y, t.z, slot_nodes + slot * 3 * NP,
+                                               qh32 + slot * P8, nk, kf);
+        }
     }
     const double4 bi = batch_info[b];
     const int n_end = near_off[b + 1];
@@ -309,8 +334,9 @@ hipError_t run_interact_hermite_mixed(const DevicePlan& d, double* phi, KernelCo
     if (d.ngroups == 0)
         return hipSuccess;
     const NearLists nl = near_lists(d);
+    const size_t lds = kStageHermite<N> ? sizeof(float) * 8 * (N + 1) * (N + 1) * (N + 1) : 0;
     hipLaunchKernelGGL((interact_hermite_mixed<N, KER>), dim3(static_cast<unsigned>(d.ngroups)),
-                       dim3(d.group_threads), 0, s, d.tgt, d.tgt_orig, d.src, d.src32,
+                       dim3(d.group_threads), lds, s, d.tgt, d.tgt_orig, d.src, d.src32,
                        d.node_info, d.batch_info, d.group_batch, d.group_first, d.batch_end,
                        d.far_off, d.far_slot, nl.off, nl.begin, nl.count, nl.leaf, d.slot_nodes,
                        d.qhat32, nl.pc_off, nl.pc_base, nl.pair_out, nl.batch_begin, phi, kc);

@@ -207,7 +207,8 @@ def test_hermite_rejects_unsupported(dev):
 
 
 @pytest.mark.parametrize("kernel,kappa", KERNEL_CASES)
-@pytest.mark.parametrize("degree,n,leaf,batch", [(3, 30000, 1000, 500), (5, 60000, 2000, 2000)])
+@pytest.mark.parametrize("degree,n,leaf,batch", [(3, 30000, 1000, 500), (4, 40000, 1200, 600),
+                                                  (5, 60000, 2000, 2000)])
 def test_hermite_mixed_matches_oracle(dev, kernel, kappa, degree, n, leaf, batch):
     # leaf == batch: the mutual direct pairs run too
     pos, q = inputs.uniform_cube(n, 191 + degree)
